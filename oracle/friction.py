@@ -1,0 +1,57 @@
+"""Rate-and-state friction and the equilibrium solve (oracle).
+
+* strength tau = sigma_n [f_* + a ln(V/V_*) + b ln(V_* theta / D_c)]
+  (Section 2.2, eq. "R&S_friction"; the printed form has b ln(V theta / D_c),
+  read as b ln(V_* theta / D_c));
+* intermediate state law dtheta/dt = (1/eps)[(V theta/D_c)^(-eps) - 1] V theta / D_c,
+  eps = 1 giving the aging law dtheta/dt = 1 - V theta / D_c (eq. "state_evolution_law");
+* equilibrium on every element (eq. "force_balance" with the traction split of
+  eq. "superimposition2"):  tau0 + f - mu/(2 cs) V = strength(V, theta),
+  solved for V by Newton-Raphson (Section 2.4, step 2).
+
+The unknown is x = ln V.  g(x) = A - eta e^x - sigma_n [f_* + a (x - ln V_*) +
+b ln(V_* theta/D_c)] is strictly decreasing and concave, so the root is unique;
+iterates are clamped to |dx| <= 5 and stopped when |dx| <= tol max(1, |x|).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def strength(V, theta, a, b, Dc, sigma_n, V0, f0):
+    return sigma_n * (f0 + a * np.log(V / V0) + b * np.log(V0 * theta / Dc))
+
+
+def state_rate(V, theta, Dc, eps=1.0):
+    r = V * theta / Dc
+    if np.all(np.asarray(eps) == 1.0):
+        return 1.0 - r
+    return (1.0 / eps) * (r ** (-eps) - 1.0) * r
+
+
+class NotConverged(RuntimeError):
+    pass
+
+
+def solve_velocity(A, theta, eta, a, b, Dc, sigma_n, V0, f0, x0, tol=1e-14, max_iter=50):
+    """Vectorised Newton on x = ln V for  A - eta V = strength(V, theta).
+
+    Every element iterates independently (a converged element is frozen), so the
+    result equals a scalar Newton run element by element."""
+    A = np.asarray(A, float)
+    x = np.array(x0, dtype=float, copy=True) * np.ones_like(A)
+    c = sigma_n * (f0 - a * np.log(V0) + b * np.log(V0 * theta / Dc))
+    active = np.ones(A.shape, bool)
+    for _ in range(max_iter):
+        if not active.any():
+            break
+        ex = np.exp(x)
+        g = A - eta * ex - c - sigma_n * a * x
+        dg = -eta * ex - sigma_n * a
+        dx = np.clip(-g / dg, -5.0, 5.0)
+        dx = np.where(active, dx, 0.0)
+        x = x + dx
+        active = active & (np.abs(dx) > tol * np.maximum(1.0, np.abs(x)))
+    if active.any():
+        raise NotConverged(f"{int(active.sum())} elements did not converge")
+    return np.exp(x)

@@ -1,0 +1,161 @@
+"""Prescribed-history stress evaluation and the SEAS predictor-corrector (oracle).
+
+The stress transfer is the history functional f of eq. "superimposition2"
+(radiation damping excluded), split as in eq. "traction_decomposition" into the
+spectral self term of each fault and the fault-to-fault space-time term.
+
+Time indexing (Section 2.3.2 and Section 2.4; see the design doc for the reading):
+V^m is the slip rate held over [t_m, t_{m+1}]; the interaction stress at t_{h+1}
+is sum_T K^T V^{h-T}; the self term at t_s uses D^{s-T}, T = 0..W_n, where D^s is
+the transform of the slip at t_s.
+
+* prescribed mode (stress evaluation of a given rate history): for n = 1..n_steps,
+  delta^n = delta^{n-1} + dt V^{n-1}, f^n = f_self(D^n, D^{n-1}, ...) +
+  f_int(V^{n-1}, V^{n-2}, ...);
+* SEAS mode, one step t_n -> t_{n+1} (Section 2.4 steps 2 and 3): predictor with
+  delta* = delta^n + dt V^n, theta* = theta^n + dt thetadot^n, D* = DFT(delta*),
+  Newton for V*; corrector with the averages of V and thetadot, in which only the
+  lag-0 terms change; V** and D** are appended to the histories.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import friction, geometry, interaction, selfterm
+
+
+class Problem:
+    def __init__(self, faults, params, n_hist_max=None, use_c=True):
+        p = dict(params)
+        self.p = p
+        self.geo = geometry.discretize(faults)
+        self.off = geometry.offsets(self.geo)
+        self.N = self.off[-1]
+        self.mu, self.cs = float(p["mu"]), float(p["cs"])
+        self.eta = self.mu / (2 * self.cs)
+        self.dt = geometry.time_step(self.geo, self.cs, float(p.get("beta", 0.5)))
+        self.with_tail = bool(p.get("int_tail", 1))
+        self.inter = interaction.DenseInteraction(
+            self.geo, self.mu, self.cs, self.dt, float(p.get("eta_tmin", 0.01)),
+            float(p.get("eta_tmax", 0.01)), windowed=True, max_lag=n_hist_max,
+            with_tail=self.with_tail)
+        self.selfs = []
+        cache = {}
+        for f in self.geo:
+            key = (f.Np, f.L)
+            if key not in cache:
+                cache[key] = selfterm.SelfTerm(f.Np, f.L, self.mu, self.cs, self.dt,
+                                               float(p.get("eta_w", 1.5)), int(p.get("q_w", 0)),
+                                               int(p.get("mode_cap", 0)), use_c=use_c)
+            self.selfs.append(cache[key])
+
+    # ------------------------------------------------------------------ helpers
+    def dfts(self, delta):
+        return [self.selfs[k].dft(delta[self.off[k]:self.off[k + 1]]) for k in range(len(self.geo))]
+
+    def self_stress(self, Dh, t, first, D_now=None):
+        f = np.zeros(self.N)
+        for k in range(len(self.geo)):
+            now = None if D_now is None else D_now[k]
+            f[self.off[k]:self.off[k + 1]] = self.selfs[k].stress(Dh[k], t, first, now)
+        return f
+
+    def expired(self, Vh, head, first):
+        return self.inter.expired_slip(Vh, head, first, self.dt) if self.with_tail else None
+
+
+def prescribed(prob, V, prior_V=None, delta0=None):
+    """Stress history f^n, n = 1..n_steps, for the slip rates V[m], m = 0..n_steps-1.
+
+    ``prior_V`` (H x N, oldest first) are the rates of steps -H..-1; slip before
+    t = 0 follows from delta^{m+1} = delta^m + dt V^m with delta^0 = ``delta0``."""
+    V = np.asarray(V, float)
+    n_steps, N = V.shape
+    H = 0 if prior_V is None else len(prior_V)
+    Vall = V if H == 0 else np.concatenate([prior_V, V])
+    first = -H
+    d0 = np.zeros(N) if delta0 is None else np.asarray(delta0, float)
+    # slip at t_m for m = -H..n_steps
+    delta = np.empty((H + n_steps + 1, N))
+    delta[H] = d0
+    for m in range(-1, -H - 1, -1):
+        delta[m + H] = delta[m + 1 + H] - prob.dt * Vall[m + H]
+    for m in range(0, n_steps):
+        delta[m + 1 + H] = delta[m + H] + prob.dt * Vall[m + H]
+    nf = len(prob.geo)
+    Dh = [np.array([prob.selfs[k].dft(delta[i, prob.off[k]:prob.off[k + 1]])
+                    for i in range(len(delta))]) for k in range(nf)]
+    out = np.zeros((n_steps, N))
+    for n in range(1, n_steps + 1):
+        head = n - 1
+        f_int = prob.inter.stress(Vall, head, first, expired=prob.expired(Vall, head, first))
+        f_self = prob.self_stress(Dh, n, first)
+        out[n - 1] = f_self + f_int
+    return out
+
+
+class SeasState:
+    def __init__(self, prob, fric, V0, theta0, tau0, tau0_rate=None, delta0=None,
+                 prior_V=None, eps=1.0):
+        self.prob = prob
+        self.fric = {k: np.asarray(v, float) for k, v in fric.items()}
+        self.eps = eps
+        N = prob.N
+        H = 0 if prior_V is None else len(prior_V)
+        self.first = -H
+        self.n = 0
+        self.V = np.asarray(V0, float).copy()
+        self.theta = np.asarray(theta0, float).copy()
+        self.tau0 = np.asarray(tau0, float).copy()
+        self.tau0_rate = np.zeros(N) if tau0_rate is None else np.asarray(tau0_rate, float)
+        self.delta = np.zeros(N) if delta0 is None else np.asarray(delta0, float).copy()
+        self.thetadot = friction.state_rate(self.V, self.theta, self.fric["Dc"], eps)
+        Vh = [] if prior_V is None else list(np.asarray(prior_V, float))
+        Vh.append(self.V.copy())
+        self.Vh = Vh                               # rows m = first..n
+        dl = [self.delta.copy()]
+        for m in range(-1, -H - 1, -1):
+            dl.insert(0, dl[0] - prob.dt * Vh[m + H])
+        self.Dh = [[prob.selfs[k].dft(d[prob.off[k]:prob.off[k + 1]]) for d in dl]
+                   for k in range(len(prob.geo))]
+        self.last = {}
+
+    def _solve(self, A, theta, x0):
+        F = self.fric
+        return friction.solve_velocity(A, theta, self.prob.eta, F["a"], F["b"], F["Dc"],
+                                       F["sigma_n"], F["V0"], F["f0"], x0)
+
+    def step(self):
+        """Advance one predictor-corrector step t_n -> t_{n+1}."""
+        P = self.prob
+        dt, n = P.dt, self.n
+        Vh = np.array(self.Vh)
+        Dh = [np.array(d) for d in self.Dh]
+        # interaction history part (lags >= 1) and the static tail
+        f_hist = P.inter.stress(Vh, n, self.first, min_lag=1, expired=P.expired(Vh, n, self.first))
+        # ---- predictor
+        d_star = self.delta + dt * self.V
+        th_star = self.theta + dt * self.thetadot
+        D_star = P.dfts(d_star)
+        fs_star = P.self_stress(Dh, n + 1, self.first, D_now=D_star)
+        fi_star = f_hist + P.inter.lag0_apply(self.V)
+        tau0 = self.tau0 + self.tau0_rate * (n + 1) * dt
+        V_star = self._solve(tau0 + fs_star + fi_star, th_star, np.log(self.V))
+        thd_star = friction.state_rate(V_star, th_star, self.fric["Dc"], self.eps)
+        # ---- corrector
+        Vbar = 0.5 * (self.V + V_star)
+        thd_bar = 0.5 * (self.thetadot + thd_star)
+        d_2 = self.delta + dt * Vbar
+        th_2 = self.theta + dt * thd_bar
+        D_2 = P.dfts(d_2)
+        fs_2 = P.self_stress(Dh, n + 1, self.first, D_now=D_2)
+        fi_2 = f_hist + P.inter.lag0_apply(Vbar)
+        V_2 = self._solve(tau0 + fs_2 + fi_2, th_2, np.log(V_star))
+        thd_2 = friction.state_rate(V_2, th_2, self.fric["Dc"], self.eps)
+        self.last = dict(f_hist=f_hist, f_self=fs_2, f_int=fi_2, V_star=V_star)
+        # ---- commit and append
+        self.delta, self.theta, self.V, self.thetadot = d_2, th_2, V_2, thd_2
+        self.Vh.append(V_2.copy())
+        for k in range(len(P.geo)):
+            self.Dh[k].append(D_2[k])
+        self.n = n + 1
