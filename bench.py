@@ -1,0 +1,161 @@
+#!/usr/bin/env python3
+"""Throughput of the SEAS step loop on one MI355X.
+
+Workload (default): five seeded 30 km faults of 600 elements (N = 3000, dx = 50 m)
+in a 40 x 20 km box, strikes U(0, 40) degrees; H-matrix with eta_H = 2, leaf 50,
+ACA tolerance 1e-6; FP32 factors, FP64 state and friction; aging law with the
+velocity-weakening central patch; a seeded slip-rate history as long as the
+longest causality window is loaded first, so every timed step evaluates full
+windows.  A step is one predictor-corrector step: history push, interaction
+convolution over the H-stack with its static tail and lag-0 terms, spectral self
+term, two Newton solves and the state update.
+
+Prints one JSON line: element-steps/s (N x steps / wall time), the roofline of
+the dominant kernel (the H-matrix apply, timed with HIP events on its launch
+stream) and the oracle's CPU rate on a bounded sample of receivers.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "element-steps/s (stress eval) vs plain at rel err≤1e-4; p50/p99 window latency"
+
+
+def cpu_baseline(faults, params, prior, budget_s=12.0):
+    """The oracle (numpy, one thread) on a bounded sample: interaction rows of a
+    few receivers plus the full self term of their fault, at a saturated step."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import interaction as OI
+    from oracle import seas as OS
+    prob = OS.Problem(faults, params, dense=False)
+    first = -len(prior)
+    head = -1
+    p = prob.p
+    Np = prob.geo[0].Np
+    rows_all = list(np.linspace(0, Np - 1, 64).astype(int))
+    with threadpool_limits(limits=1):
+        t_int, done = 0.0, 0
+        while done < len(rows_all) and (t_int < budget_s or done < 4):
+            t0 = time.perf_counter()
+            OI.stress_rows(prob.geo, [rows_all[done]], prior, head, first, prob.mu, prob.cs, prob.dt,
+                           p["eta_tmin"], p["eta_tmax"], with_tail=prob.with_tail)
+            t_int += time.perf_counter() - t0
+            done += 1
+        t0 = time.perf_counter()
+        OS.prescribed_rows(prob, prior, first, 0, [], delta0=None)     # warm the DFT matrix
+        st = prob.selfs[0]
+        delta = np.vstack([np.zeros((1, prob.N)), np.cumsum(prior, axis=0) * prob.dt])
+        delta = delta - delta[-1][None, :]
+        W = int(st.W.max())
+        t0 = time.perf_counter()
+        Dh = st.dft(delta[-W - 1:, :Np])
+        st.stress(Dh, 0, -W)
+        t_self = time.perf_counter() - t0
+    per_elem = t_int / done + t_self / Np
+    return {"value": 1.0 / per_elem, "unit": "element-steps/s", "cores": 1, "kind": "oracle",
+            "sample": (f"{done} receivers' interaction rows (all lags of all pair windows, kernel "
+                       f"evaluated on the fly) + the full self term of one {Np}-element fault, at a "
+                       f"saturated step of the same workload; {t_int + t_self:.1f} s of CPU work")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--aca", type=float, default=1e-6)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU; --gpus N > 1 is not supported "
+              "(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2603_00383_amd as P
+    import seas_inputs as SI
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    torch.cuda.set_device(0)
+    faults = SI.five_fault_network(seed=args.seed)
+    params = SI.default_params(factor_dtype=args.dtype, aca_tol=args.aca, eta_H=2.0, leaf=50)
+    os.environ.setdefault("SEAS_VERBOSE", "1")
+    print("[bench] building the operator", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    op = P.Operator(faults, params)
+    build_s = time.perf_counter() - t0
+    info = op.info
+    N = op.N
+    print(f"[bench] operator built in {build_s:.1f} s: N={N} items={info['n_items']} "
+          f"stored/dense={info['stored_entries'] / info['dense_entries']:.3f} max_lag={info['max_lag']}",
+          file=sys.stderr, flush=True)
+    fric = SI.rate_state_fields(faults)
+    # a mild overstress keeps the explicit aging-law update away from its stiff limit
+    ini = SI.near_nucleation_state(faults, fric, seed=args.seed, bump_amp=0.05)
+    prior = SI.saturated_history(faults, info["max_lag"] + 2, args.seed)
+    stream = torch.cuda.current_stream()
+    s = stream.cuda_stream
+    st = P.State(op, fric, ini["V"], ini["theta"], ini["tau0"], ini["tau0_rate"], stream=s)
+    st.load_history(prior, stream=s)
+    print(f"[bench] history loaded ({len(prior)} steps), warmup {args.warmup}", file=sys.stderr, flush=True)
+    st.step(args.warmup, stream=s)
+    st.check(stream=s)
+    st.set_timing(True)
+    st.read_timing(stream=s)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    e0.record(stream)
+    st.step(args.steps, stream=s)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms_hmat, n_launch = st.read_timing(stream=s)
+    st.check(stream=s)
+    ev_ms = e0.elapsed_time(e1)
+    elem_bytes = 4 if args.dtype == "f32" else 8
+    hmat_bytes = info["stored_entries"] * elem_bytes
+    avg_ms = ms_hmat / max(n_launch, 1)
+    achieved = hmat_bytes / (avg_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": N * args.steps / wall,
+        "unit": "element-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": "five-fault SEAS step loop, 5 x 600 elements (N=3000, dx=50 m), "
+                               f"{args.dtype.upper()} factors, FP64 state, ACA {args.aca:g}, eta_H 2, leaf 50, "
+                               "saturated history windows",
+                   "seed": args.seed, "N": N, "max_lag": info["max_lag"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_hmat", "kernel_avg_ms": avg_ms, "algorithmic_bytes": hmat_bytes},
+        "gpu_event_ms_per_step": ev_ms / args.steps,
+        "build_s": build_s,
+        "stored_over_dense": info["stored_entries"] / info["dense_entries"],
+    }
+    print(f"[bench] timed {args.steps} steps: {wall:.3f} s", file=sys.stderr, flush=True)
+    if not args.no_cpu_baseline:
+        print("[bench] oracle CPU baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(faults, params, prior)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

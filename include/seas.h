@@ -1,0 +1,226 @@
+/*
+ * seas.h -- C ABI of the MI355X stress-transfer library for 2-D antiplane
+ * fault networks (Ciardo & Romanet, "A divide-and-conquer strategy for fast
+ * elastodynamic simulation of earthquakes and aseismic slip on fault networks").
+ *
+ * The library evaluates, every time step, the history functional f of the
+ * elastic traction (the part of tau_el that is not radiation damping, Section
+ * 2.3, eq. "superimposition2") on every element of a network of straight
+ * faults, as the sum of
+ *   - a non-replicating spectral self term per fault (Section 2.3.1, eqs.
+ *     "functional_no_replication", "non_replicant_kernel",
+ *     "funcational_discretized_form", "mode_dependent_truncation"), and
+ *   - a fault-to-fault space-time convolution over a selective H-matrix, one
+ *     binary cluster tree per fault, low-rank admissible blocks, dense
+ *     near-field blocks, causality-truncated lag windows (Section 2.3.2, eqs.
+ *     "fault-to-fault_interactions_discretized", "kernel_interactions",
+ *     "primitives", "early_time", "admissibility_condition"),
+ * and advances rate-and-state friction with the predictor-corrector of
+ * Section 2.4 (eqs. "R&S_friction", "state_evolution_law", "force_balance").
+ *
+ * Conventions
+ *   - Status codes: every call returns SEAS_OK (0) or a negative code; the
+ *     message of the last failure on the calling thread is seas_last_error().
+ *     No C++ exception crosses this boundary.
+ *   - Units are SI. Element arrays are in fault order, element j of fault k at
+ *     global index off_k + j (off_k = sum of earlier faults' n_elem).
+ *   - Host pointers are read during the call only (copied). Device pointers
+ *     (named *_dev) must stay valid until the work queued on `stream` is done.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Every call that takes a stream only enqueues work on it, except where
+ *     stated; the library synchronises nothing else.
+ *   - Objects: an operator is immutable after build and may be shared by
+ *     several states; a state must be used from one stream at a time.
+ *     The library owns the device memory of operators and states.
+ */
+#ifndef SEAS_H
+#define SEAS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t seas_status;
+#define SEAS_OK 0
+#define SEAS_ERR_INVALID_ARG (-1)   /* bad size, pointer, geometry or parameter */
+#define SEAS_ERR_OOM (-2)           /* device or host allocation failed */
+#define SEAS_ERR_HIP (-3)           /* a HIP runtime call failed */
+#define SEAS_ERR_NOT_CONVERGED (-4) /* Newton did not converge (see seas_state_check) */
+#define SEAS_ERR_MISMATCH (-5)      /* object used in the wrong mode or with another operator */
+#define SEAS_ERR_INTERNAL (-6)
+
+/* Storage/compute precision of the interaction factors. F64: factors, history
+ * operand and accumulation in FP64. F32: factors and history operand in FP32,
+ * FP32 accumulation within a work item, FP64 across items. State, self term,
+ * friction and time integration are FP64 in every mode. */
+#define SEAS_F64 0
+#define SEAS_F32 1
+
+const char* seas_last_error(void);
+const char* seas_version(void);
+
+/* One straight fault: centroid (cx, cy), unit normal (nx, ny) = e2' of its
+ * local frame, tangent e1' = e3 x e2' = (-ny, nx) (Section 3.1), length and
+ * number of equal piecewise-constant elements (collocated at midpoints,
+ * Section 2.3.1). */
+typedef struct {
+  double cx, cy, nx, ny, length;
+  int32_t n_elem;
+  int32_t reserved;
+} seas_fault_t;
+
+typedef struct {
+  double mu;        /* shear modulus [Pa] */
+  double cs;        /* shear-wave speed [m/s] */
+  double beta;      /* dt = beta * min(dx) / cs, beta <= 1/2 (Section 2.3.1) */
+  double eta_H;     /* admissibility factor (eq. "admissibility_condition") */
+  double aca_tol;   /* relative Frobenius tolerance of the low-rank factors */
+  double eta_tmin;  /* causality window safety factors (Section 2.3.2) */
+  double eta_tmax;
+  double eta_w;     /* lowest-mode self window factor, T_end(1) = eta_w L / cs */
+  int32_t leaf;     /* eta_leaf: maximum elements in a leaf cluster */
+  int32_t compress; /* 0: every block stored dense (uncompressed operator) */
+  int32_t int_tail; /* 1: static stress of slip older than the pair window is kept; 0: dropped */
+  int32_t q_w;      /* window modulation integer, 0 = round(N_p / 5) per fault */
+  int32_t mode_cap; /* 0 = all N_p modes of the 2 N_p padded transform; else keep n <= mode_cap */
+  int32_t factor_dtype; /* SEAS_F64 or SEAS_F32 */
+  int32_t n_threads;    /* host threads for the build (0 = all) */
+  int32_t host_only;    /* 1: build on the host only (no device memory; for inspecting the
+                           partition, windows, tables and factors); evaluation and state calls
+                           then fail with MISMATCH */
+} seas_params_t;
+
+typedef struct seas_op seas_op_t;
+typedef struct seas_state seas_state_t;
+
+/* Build the operator (host geometry, H-matrix partition, per-lag ACA
+ * compression, self-kernel tables) and upload it to the current HIP device.
+ * Blocking. Errors: INVALID_ARG for degenerate faults (length <= 0, n_elem < 2,
+ * zero normal, a collocation point on another fault's element edge), OOM, HIP. */
+seas_status seas_build_operator(const seas_fault_t* faults, int32_t n_faults,
+                                const seas_params_t* params, seas_op_t** out);
+void seas_operator_destroy(seas_op_t* op);
+
+typedef struct {
+  int32_t n_faults, n_elem;   /* faults, total elements N */
+  double dt;                  /* time step [s] */
+  int32_t max_lag;            /* largest interaction lag T_end over pairs */
+  int32_t max_self_window;    /* largest self window W_n over faults and modes */
+  int64_t n_blocks;           /* H-matrix blocks over all ordered pairs */
+  int64_t n_items;            /* work items of the per-step evaluation */
+  int64_t dense_entries;      /* entries of the uncompressed kernel in the pair windows */
+  int64_t stored_entries;     /* stored factor entries (low rank + dense), lags >= 1 and tail */
+  int64_t lag0_nnz;           /* nonzeros of the lag-0 interaction (pairs with T_init = 0) */
+  int64_t self_entries;       /* sum over faults and modes of (W_n + 1) */
+  double bytes_per_step;      /* algorithmic HBM bytes of one stress evaluation */
+  double flops_per_step;      /* 2 x stored entries + self term MACs */
+  double build_seconds;
+  int32_t factor_dtype;
+  int32_t reserved;
+} seas_op_info_t;
+
+seas_status seas_operator_info(const seas_op_t* op, seas_op_info_t* out);
+
+/* Causality window [T_init, T_end] (in lags) of every ordered pair (a, b),
+ * a != b, row-major over a then b with the diagonal skipped:
+ * n_faults * (n_faults - 1) entries each. */
+seas_status seas_operator_windows(const seas_op_t* op, int32_t* T_init, int32_t* T_end);
+
+/* Block partition of the ordered pair (a, b): count (blocks == NULL) or copy
+ * rows of 5 int32: r0, r1, s0, s1 (element ranges local to the faults) and
+ * 1 for admissible / 0 for near-field, in depth-first traversal order. */
+seas_status seas_operator_blocks(const seas_op_t* op, int32_t a, int32_t b,
+                                 int32_t* blocks, int64_t* count);
+
+/* Self-kernel table K_n^T of fault k, mode n (1..), T = 0..W_n, and W_n.
+ * Host copy of the values the device uses. */
+seas_status seas_operator_self_table(const seas_op_t* op, int32_t k, int32_t n,
+                                     double* out, int32_t capacity, int32_t* W_n);
+
+/* Reconstruct the kernel matrix of the ordered pair (a, b) at lag T (T >= 0; T = -1
+ * for the static-tail matrix, stored as -G/eta with G the static stress per unit
+ * slip) from the stored factors: out is n_elem(a) x n_elem(b), row-major, host.
+ * Only for operators built with host_only = 1 (the factors are on the host). */
+seas_status seas_operator_lag_matrix(const seas_op_t* op, int32_t a, int32_t b, int32_t T, double* out);
+
+/* Rate-and-state parameters, one value per element (host arrays of N):
+ * strength sigma_n [f0 + a ln(V/V0) + b ln(V0 theta / Dc)], state law with
+ * exponent eps (1 = aging law). */
+typedef struct {
+  const double *a, *b, *Dc, *sigma_n, *V0, *f0, *eps;  /* eps may be NULL (aging law) */
+} seas_friction_t;
+
+/* Device bytes a state of `n_variants` variants needs (admission control). */
+size_t seas_state_bytes(const seas_op_t* op, int32_t n_variants);
+
+/* Create a state at t = 0: slip rate V_init, state theta_init, background
+ * shear stress tau0 and its rate (may be NULL), slip delta_init (may be NULL
+ * = 0). Host arrays of N. Histories before t = 0 are zero (no prior slip)
+ * unless seas_state_load_history is called next. n_variants must be 1. */
+seas_status seas_state_create(seas_op_t* op, int32_t n_variants, const seas_friction_t* fric,
+                              const double* V_init, const double* theta_init,
+                              const double* tau0, const double* tau0_rate,
+                              const double* delta_init, void* stream, seas_state_t** out);
+void seas_state_destroy(seas_state_t* st);
+
+/* Prior slip-rate history V[m][N] for the n_hist steps before t = 0 (host,
+ * oldest first): fills both histories (slip before t = 0 follows from
+ * delta^{m+1} = delta^m + dt V^m) and the expired-slip accumulators. Must be
+ * called right after seas_state_create. */
+seas_status seas_state_load_history(seas_state_t* st, const double* V_hist, int32_t n_hist,
+                                    void* stream);
+
+/* Stress evaluation of a prescribed slip-rate history (no friction): for
+ * n = 1..n_steps, with V^m = V_dev[(m)*N ...] (device, FP64, n_steps x N):
+ *   delta^n = delta^{n-1} + dt V^{n-1}
+ *   f^n = f_self(D^n, D^{n-1}, ...) + f_int(V^{n-1}, V^{n-2}, ...)
+ * written to f_dev[(n-1)*N ...] (device, FP64). Consecutive calls continue the
+ * same history. MISMATCH if the state has taken SEAS steps. */
+seas_status seas_eval_prescribed(seas_op_t* op, seas_state_t* st, const double* V_dev,
+                                 int32_t n_steps, double* f_dev, void* stream);
+
+/* Advance n_steps predictor-corrector steps (Section 2.4). Enqueue only; the
+ * Newton convergence flag is read by seas_state_check. */
+seas_status seas_step(seas_op_t* op, seas_state_t* st, int32_t n_steps, void* stream);
+
+/* Synchronise `stream` and report NOT_CONVERGED if any Newton solve since the
+ * last check exceeded 50 iterations (the flag is then cleared). */
+seas_status seas_state_check(seas_state_t* st, void* stream);
+
+#define SEAS_FIELD_V 0          /* slip rate at the current step */
+#define SEAS_FIELD_THETA 1
+#define SEAS_FIELD_DELTA 2      /* slip */
+#define SEAS_FIELD_THETADOT 3
+#define SEAS_FIELD_F_HIST 4     /* interaction history part (lags >= 1 + tail) of the last step */
+#define SEAS_FIELD_F_SELF 5     /* self term of the last corrector */
+#define SEAS_FIELD_F_INT 6      /* interaction stress of the last corrector (with lag 0) */
+#define SEAS_FIELD_TAU0 7
+
+/* Copy N values of a field to dst (device if dst_is_device, else host; a host
+ * copy synchronises the stream). */
+seas_status seas_read_state(const seas_state_t* st, int32_t field, int32_t variant, double* dst,
+                            size_t count, int32_t dst_is_device, void* stream);
+/* Device time of the interaction-evaluation kernel: when enabled, every launch of
+ * it inside seas_step / seas_eval_prescribed is bracketed by HIP events recorded
+ * on the launch stream. read_timing synchronises `stream`, returns the summed
+ * milliseconds and the number of launches since the last read, and resets them. */
+seas_status seas_state_set_timing(seas_state_t* st, int32_t enable);
+seas_status seas_state_read_timing(seas_state_t* st, void* stream, double* ms_total, int64_t* launches);
+
+/* Current step index (number of steps taken, or prescribed steps evaluated). */
+int64_t seas_state_step_index(const seas_state_t* st);
+
+/* Checkpoint: size in bytes, save to / restore from a host buffer (synchronises
+ * the stream). Restoring into a state of the same operator reproduces the
+ * saved state exactly. */
+size_t seas_state_checkpoint_bytes(const seas_state_t* st);
+seas_status seas_state_save(const seas_state_t* st, void* host_buf, size_t bytes, void* stream);
+seas_status seas_state_restore(seas_state_t* st, const void* host_buf, size_t bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SEAS_H */

@@ -229,3 +229,53 @@ class DenseInteraction:
             else:
                 out[(a, b)] = np.zeros(self.geo[b].Np)
         return out
+
+
+# ----------------------------------------------------------------------------
+# Row-sampled evaluation (large networks: kernel rows evaluated on the fly)
+# ----------------------------------------------------------------------------
+def stress_rows(geo, rows, Vh, head, first, mu, cs, dt, eta_tmin=0.01, eta_tmax=0.01,
+                min_lag=0, with_tail=True):
+    """The same sum as ``DenseInteraction.stress`` for the global receiver indices
+    ``rows`` only, with each receiver's kernel row computed lag by lag."""
+    off = [0]
+    for f in geo:
+        off.append(off[-1] + f.Np)
+    eta = mu / (2 * cs)
+    win = {}
+    out = np.zeros(len(rows))
+    for k, r in enumerate(rows):
+        a = int(np.searchsorted(off, r, side="right") - 1)
+        i = r - off[a]
+        acc = 0.0
+        for b in range(len(geo)):
+            if b == a:
+                continue
+            if (a, b) not in win:
+                win[(a, b)] = pair_window_lags(geo, a, b, cs, dt, eta_tmin, eta_tmax)
+            T0, T1 = win[(a, b)]
+            A, B = geo[a], geo[b]
+            d = A.mid[i][None, :] - B.mid
+            r1p = d[:, 0] * B.t[0] + d[:, 1] * B.t[1]
+            r2p = d[:, 0] * B.n[0] + d[:, 1] * B.n[1]
+            n1p, n2p = float(A.n @ B.t), float(A.n @ B.n)
+            lags = np.arange(max(T0, min_lag), T1 + 1)
+            ms = head - lags
+            ok = ms >= first
+            if ok.any():
+                Kr = kernel_from_offsets(r1p[None, :], r2p[None, :], n1p, n2p, B.dx,
+                                         lags[ok][:, None], dt, cs)
+                hv = Vh[ms[ok] - first][:, off[b]:off[b + 1]]
+                acc += -eta * float(np.sum(Kr * hv))
+            if with_tail:
+                last = head - T1 - 1
+                if last >= first:
+                    E = dt * np.sum(Vh[: last - first + 1, off[b]:off[b + 1]], axis=0)
+                    ds = B.dx
+                    rp1, rm1 = r1p + 0.5 * ds, r1p - 0.5 * ds
+                    rp2, rm2 = rp1 * rp1 + r2p * r2p, rm1 * rm1 + r2p * r2p
+                    G = (n1p * mu / (2 * math.pi) * r2p * (1 / rp2 - 1 / rm2)
+                         - n2p * mu / (2 * math.pi) * (rp1 / rp2 - rm1 / rm2))
+                    acc += float(G @ E)
+        out[k] = acc
+    return out

@@ -25,7 +25,7 @@ from . import friction, geometry, interaction, selfterm
 
 
 class Problem:
-    def __init__(self, faults, params, n_hist_max=None, use_c=True):
+    def __init__(self, faults, params, n_hist_max=None, use_c=True, dense=True):
         p = dict(params)
         self.p = p
         self.geo = geometry.discretize(faults)
@@ -35,10 +35,12 @@ class Problem:
         self.eta = self.mu / (2 * self.cs)
         self.dt = geometry.time_step(self.geo, self.cs, float(p.get("beta", 0.5)))
         self.with_tail = bool(p.get("int_tail", 1))
-        self.inter = interaction.DenseInteraction(
-            self.geo, self.mu, self.cs, self.dt, float(p.get("eta_tmin", 0.01)),
-            float(p.get("eta_tmax", 0.01)), windowed=True, max_lag=n_hist_max,
-            with_tail=self.with_tail)
+        self.inter = None
+        if dense:
+            self.inter = interaction.DenseInteraction(
+                self.geo, self.mu, self.cs, self.dt, float(p.get("eta_tmin", 0.01)),
+                float(p.get("eta_tmax", 0.01)), windowed=True, max_lag=n_hist_max,
+                with_tail=self.with_tail)
         self.selfs = []
         cache = {}
         for f in self.geo:
@@ -159,3 +161,33 @@ class SeasState:
         for k in range(len(P.geo)):
             self.Dh[k].append(D_2[k])
         self.n = n + 1
+
+
+def prescribed_rows(prob, V_all, first, n, rows, delta0=None):
+    """f^n at the global receivers ``rows`` for the rate history V_all[m - first]
+    (m = first .. n-1), without building dense operators: interaction rows on the
+    fly, the self term of each fault that holds a sampled receiver in full."""
+    V_all = np.asarray(V_all, float)
+    head = n - 1
+    p = prob.p
+    f_int = interaction.stress_rows(prob.geo, rows, V_all, head, first, prob.mu, prob.cs, prob.dt,
+                                    float(p.get("eta_tmin", 0.01)), float(p.get("eta_tmax", 0.01)),
+                                    with_tail=prob.with_tail)
+    # slip at t_m for m = first .. n, delta^{first} from delta^0 going backwards
+    N = prob.N
+    d0 = np.zeros(N) if delta0 is None else np.asarray(delta0, float)
+    cum = np.cumsum(V_all[: n - first], axis=0) * prob.dt           # sum_{k < m} V^k, m = first+1..n
+    before = np.sum(V_all[: -first], axis=0) * prob.dt if first < 0 else np.zeros(N)
+    delta = np.vstack([np.zeros((1, N)), cum]) + (d0 - before)[None, :]   # rows m = first..n
+    out = np.zeros(len(rows))
+    faults_needed = sorted({int(np.searchsorted(prob.off, r, side="right") - 1) for r in rows})
+    for k in faults_needed:
+        st = prob.selfs[k]
+        Wmax = int(st.W.max())
+        lo = max(first, n - Wmax)
+        Dh = st.dft(delta[lo - first:n - first + 1, prob.off[k]:prob.off[k + 1]])
+        fs = st.stress(Dh, n, lo)
+        for idx, r in enumerate(rows):
+            if prob.off[k] <= r < prob.off[k + 1]:
+                out[idx] = fs[r - prob.off[k]]
+    return out + f_int

@@ -167,11 +167,14 @@ class SelfTerm:
 
     # ---------------------------------------------------------------- transforms
     def dft(self, delta):
-        """D_n = sum_{j<N_p} delta_j exp(-2 pi i n j / M), n = 0..N_p (explicit sum)."""
-        n = np.arange(self.Np + 1)[:, None]
-        j = np.arange(self.Np)[None, :]
-        E = np.exp(-2j * math.pi * ((n * j) % self.M) / self.M)
-        return E @ np.asarray(delta, float)
+        """D_n = sum_{j<N_p} delta_j exp(-2 pi i n j / M), n = 0..N_p (explicit sum);
+        ``delta`` may hold several slip vectors as rows."""
+        if getattr(self, "_E", None) is None:
+            n = np.arange(self.Np + 1)[:, None]
+            j = np.arange(self.Np)[None, :]
+            self._E = np.exp(-2j * math.pi * ((n * j) % self.M) / self.M)
+        d = np.asarray(delta, float)
+        return (self._E @ d.T).T if d.ndim == 2 else self._E @ d
 
     def idft(self, F):
         """f_j = (1/M) [F_0 + 2 Re sum_{n=1}^{N_p-1} F_n e^{2 pi i n j/M} + Re F_{N_p} (-1)^j]."""

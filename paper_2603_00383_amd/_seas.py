@@ -1,0 +1,272 @@
+"""ctypes binding of libseas.so (argument marshalling only).
+
+Every computation of the stress-transfer path runs in the HIP library; this
+module converts Python values to the C structs of include/seas.h, passes device
+pointers (integers, e.g. ``tensor.data_ptr()``) and stream handles (``int``,
+e.g. ``torch.cuda.current_stream().cuda_stream``) through, and raises on any
+non-zero status.  It fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libseas.so")
+
+SEAS_F64, SEAS_F32 = 0, 1
+FIELDS = dict(V=0, theta=1, delta=2, thetadot=3, f_hist=4, f_self=5, f_int=6, tau0=7)
+STATUS = {0: "OK", -1: "INVALID_ARG", -2: "OOM", -3: "HIP", -4: "NOT_CONVERGED", -5: "MISMATCH",
+          -6: "INTERNAL"}
+
+
+class SeasError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Fault(C.Structure):
+    _fields_ = [("cx", C.c_double), ("cy", C.c_double), ("nx", C.c_double), ("ny", C.c_double),
+                ("length", C.c_double), ("n_elem", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Params(C.Structure):
+    _fields_ = [("mu", C.c_double), ("cs", C.c_double), ("beta", C.c_double), ("eta_H", C.c_double),
+                ("aca_tol", C.c_double), ("eta_tmin", C.c_double), ("eta_tmax", C.c_double),
+                ("eta_w", C.c_double), ("leaf", C.c_int32), ("compress", C.c_int32),
+                ("int_tail", C.c_int32), ("q_w", C.c_int32), ("mode_cap", C.c_int32),
+                ("factor_dtype", C.c_int32), ("n_threads", C.c_int32), ("host_only", C.c_int32)]
+
+
+class OpInfo(C.Structure):
+    _fields_ = [("n_faults", C.c_int32), ("n_elem", C.c_int32), ("dt", C.c_double),
+                ("max_lag", C.c_int32), ("max_self_window", C.c_int32), ("n_blocks", C.c_int64),
+                ("n_items", C.c_int64), ("dense_entries", C.c_int64), ("stored_entries", C.c_int64),
+                ("lag0_nnz", C.c_int64), ("self_entries", C.c_int64), ("bytes_per_step", C.c_double),
+                ("flops_per_step", C.c_double), ("build_seconds", C.c_double),
+                ("factor_dtype", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Friction(C.Structure):
+    _fields_ = [(k, C.POINTER(C.c_double)) for k in ("a", "b", "Dc", "sigma_n", "V0", "f0", "eps")]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if libseas.so is missing (no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2603_00383_amd.build` (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
+        sig = {
+            "seas_last_error": (C.c_char_p, []),
+            "seas_version": (C.c_char_p, []),
+            "seas_build_operator": (i32, [C.POINTER(Fault), i32, C.POINTER(Params), C.POINTER(vp)]),
+            "seas_operator_destroy": (None, [vp]),
+            "seas_operator_info": (i32, [vp, C.POINTER(OpInfo)]),
+            "seas_operator_windows": (i32, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+            "seas_operator_blocks": (i32, [vp, i32, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
+            "seas_operator_self_table": (i32, [vp, i32, i32, dp, i32, C.POINTER(C.c_int32)]),
+            "seas_operator_lag_matrix": (i32, [vp, i32, i32, i32, dp]),
+            "seas_state_bytes": (C.c_size_t, [vp, i32]),
+            "seas_state_create": (i32, [vp, i32, C.POINTER(Friction), dp, dp, dp, dp, dp, vp, C.POINTER(vp)]),
+            "seas_state_destroy": (None, [vp]),
+            "seas_state_load_history": (i32, [vp, dp, i32, vp]),
+            "seas_eval_prescribed": (i32, [vp, vp, vp, i32, vp, vp]),
+            "seas_step": (i32, [vp, vp, i32, vp]),
+            "seas_state_check": (i32, [vp, vp]),
+            "seas_read_state": (i32, [vp, i32, i32, vp, C.c_size_t, i32, vp]),
+            "seas_state_step_index": (i64, [vp]),
+            "seas_state_set_timing": (i32, [vp, i32]),
+            "seas_state_read_timing": (i32, [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+            "seas_state_checkpoint_bytes": (C.c_size_t, [vp]),
+            "seas_state_save": (i32, [vp, vp, C.c_size_t, vp]),
+            "seas_state_restore": (i32, [vp, vp, C.c_size_t, vp]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise SeasError(rc, lib().seas_last_error().decode())
+
+
+def _dptr(a):
+    """Host float64 array -> (keepalive, POINTER(c_double))."""
+    if a is None:
+        return None, None
+    arr = np.ascontiguousarray(a, dtype=np.float64)
+    return arr, arr.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ptr(x):
+    """Device pointer / stream from an int or an object with data_ptr()."""
+    if x is None:
+        return None
+    if hasattr(x, "data_ptr"):
+        return C.c_void_p(x.data_ptr())
+    return C.c_void_p(int(x))
+
+
+_DTYPE = {"f64": SEAS_F64, "f32": SEAS_F32, SEAS_F64: SEAS_F64, SEAS_F32: SEAS_F32}
+
+
+def make_params(p):
+    q = Params()
+    q.mu, q.cs, q.beta = p["mu"], p["cs"], p.get("beta", 0.5)
+    q.eta_H, q.aca_tol = p.get("eta_H", 2.0), p.get("aca_tol", 1e-6)
+    q.eta_tmin, q.eta_tmax = p.get("eta_tmin", 0.01), p.get("eta_tmax", 0.01)
+    q.eta_w = p.get("eta_w", 1.5)
+    q.leaf, q.compress = int(p.get("leaf", 50)), int(p.get("compress", 1))
+    q.int_tail, q.q_w, q.mode_cap = int(p.get("int_tail", 1)), int(p.get("q_w", 0)), int(p.get("mode_cap", 0))
+    q.factor_dtype = _DTYPE[p.get("factor_dtype", "f64")]
+    q.n_threads = int(p.get("n_threads", 0))
+    q.host_only = int(p.get("host_only", 0))
+    return q
+
+
+class Operator:
+    def __init__(self, faults, params):
+        arr = (Fault * len(faults))()
+        for i, f in enumerate(faults):
+            arr[i] = Fault(f["cx"], f["cy"], f["nx"], f["ny"], f["length"], int(f["n_elem"]), 0)
+        self._prm = make_params(params)
+        h = C.c_void_p()
+        _check(lib().seas_build_operator(arr, len(faults), C.byref(self._prm), C.byref(h)))
+        self.h = h
+        self.n_faults = len(faults)
+        self.info = self._info()
+        self.N = self.info["n_elem"]
+
+    def _info(self):
+        i = OpInfo()
+        _check(lib().seas_operator_info(self.h, C.byref(i)))
+        return {k: getattr(i, k) for k, _ in OpInfo._fields_ if k != "reserved"}
+
+    def windows(self):
+        n = self.n_faults * (self.n_faults - 1)
+        a, b = (C.c_int32 * n)(), (C.c_int32 * n)()
+        _check(lib().seas_operator_windows(self.h, a, b))
+        out, k = {}, 0
+        for i in range(self.n_faults):
+            for j in range(self.n_faults):
+                if i != j:
+                    out[(i, j)] = (a[k], b[k])
+                    k += 1
+        return out
+
+    def blocks(self, a, b):
+        cnt = C.c_int64(0)
+        _check(lib().seas_operator_blocks(self.h, a, b, None, C.byref(cnt)))
+        buf = (C.c_int32 * (5 * cnt.value))()
+        _check(lib().seas_operator_blocks(self.h, a, b, buf, C.byref(cnt)))
+        v = np.frombuffer(buf, dtype=np.int32).reshape(-1, 5)
+        return [(int(r[0]), int(r[1]), int(r[2]), int(r[3]), bool(r[4])) for r in v]
+
+    def self_table(self, k, n):
+        W = C.c_int32(0)
+        _check(lib().seas_operator_self_table(self.h, k, n, None, 0, C.byref(W)))
+        out = np.zeros(W.value + 1)
+        _check(lib().seas_operator_self_table(self.h, k, n, out.ctypes.data_as(C.POINTER(C.c_double)),
+                                              W.value + 1, C.byref(W)))
+        return out
+
+    def lag_matrix(self, a, b, T, p, q):
+        out = np.zeros((p, q))
+        _check(lib().seas_operator_lag_matrix(self.h, a, b, T, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
+
+    def state_bytes(self, n_variants=1):
+        return int(lib().seas_state_bytes(self.h, n_variants))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().seas_operator_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class State:
+    def __init__(self, op, fric, V, theta, tau0, tau0_rate=None, delta=None, stream=0):
+        self.op = op
+        keep = []
+        fr = Friction()
+        for k in ("a", "b", "Dc", "sigma_n", "V0", "f0", "eps"):
+            arr, p = _dptr(fric.get(k))
+            keep.append(arr)
+            setattr(fr, k, p)
+        args = [_dptr(x) for x in (V, theta, tau0, tau0_rate, delta)]
+        h = C.c_void_p()
+        _check(lib().seas_state_create(op.h, 1, C.byref(fr), *[p for _, p in args], _ptr(stream), C.byref(h)))
+        self.h = h
+
+    def load_history(self, V_hist, stream=0):
+        arr = np.ascontiguousarray(V_hist, dtype=np.float64)
+        _check(lib().seas_state_load_history(self.h, arr.ctypes.data_as(C.POINTER(C.c_double)), arr.shape[0],
+                                             _ptr(stream)))
+
+    def eval_prescribed(self, V_dev, n_steps, f_dev, stream=0):
+        _check(lib().seas_eval_prescribed(self.op.h, self.h, _ptr(V_dev), n_steps, _ptr(f_dev), _ptr(stream)))
+
+    def step(self, n_steps=1, stream=0):
+        _check(lib().seas_step(self.op.h, self.h, n_steps, _ptr(stream)))
+
+    def check(self, stream=0):
+        _check(lib().seas_state_check(self.h, _ptr(stream)))
+
+    def read(self, field, stream=0):
+        out = np.zeros(self.op.N)
+        _check(lib().seas_read_state(self.h, FIELDS[field], 0, C.c_void_p(out.ctypes.data), self.op.N, 0,
+                                     _ptr(stream)))
+        return out
+
+    def set_timing(self, enable=True):
+        _check(lib().seas_state_set_timing(self.h, 1 if enable else 0))
+
+    def read_timing(self, stream=0):
+        ms, n = C.c_double(0), C.c_int64(0)
+        _check(lib().seas_state_read_timing(self.h, _ptr(stream), C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    @property
+    def step_index(self):
+        return int(lib().seas_state_step_index(self.h))
+
+    def save(self, stream=0):
+        n = int(lib().seas_state_checkpoint_bytes(self.h))
+        buf = np.zeros(n, dtype=np.uint8)
+        _check(lib().seas_state_save(self.h, C.c_void_p(buf.ctypes.data), n, _ptr(stream)))
+        return buf
+
+    def restore(self, buf, stream=0):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        _check(lib().seas_state_restore(self.h, C.c_void_p(buf.ctypes.data), buf.nbytes, _ptr(stream)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().seas_state_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,784 @@
+// C ABI of the stress-transfer library: operator upload, state management and
+// the per-step launch sequence. See include/seas.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+using namespace seas;
+
+namespace {
+
+thread_local std::string g_err;
+
+#define HIPCHK(x)                                                                                       \
+  do {                                                                                                  \
+    hipError_t e_ = (x);                                                                                \
+    if (e_ != hipSuccess) throw Error(SEAS_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+template <typename F>
+seas_status guard(F&& f) {
+  try {
+    f();
+    return SEAS_OK;
+  } catch (const Error& e) {
+    g_err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return SEAS_ERR_OOM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return SEAS_ERR_INTERNAL;
+  }
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+void* dalloc(std::vector<DevBuf>& owned, size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error(SEAS_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  owned.push_back({p, bytes});
+  return p;
+}
+
+template <typename T>
+T* upload(std::vector<DevBuf>& owned, const std::vector<T>& v) {
+  T* d = (T*)dalloc(owned, v.size() * sizeof(T));
+  if (!v.empty()) HIPCHK(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return d;
+}
+
+double host_state_rate(double V, double th, double Dc, double eps) {
+  const double r = V * th / Dc;
+  if (eps == 1.0) return 1.0 - r;
+  return (std::pow(r, -eps) - 1.0) * r / eps;
+}
+
+}  // namespace
+
+struct seas_op {
+  HostOp h;
+  int device = 0;
+  std::vector<DevBuf> owned;
+  void* arena = nullptr;
+  Item* items = nullptr;
+  int32_t *lagT = nullptr, *lagCol = nullptr, *lagColOff = nullptr;
+  int32_t *red_ptr = nullptr, *red_idx = nullptr;
+  int32_t *l0_ptr = nullptr, *l0_col = nullptr;
+  double* l0_val = nullptr;
+  SelfMode* modes = nullptr;
+  SelfFaultDev* sf = nullptr;
+  double2* tw = nullptr;
+  double* tab = nullptr;
+  int* fault_of = nullptr;
+  int32_t *src_pairs = nullptr, *src_pairs_ptr = nullptr;
+  std::vector<SelfMode> hmodes;
+  std::vector<SelfFaultDev> hsf;
+  size_t elem_bytes = 8;
+  bool host_only = false;
+  std::vector<std::vector<double>> hb64;  // host factors (host_only)
+  std::vector<std::vector<float>> hb32;
+  std::vector<int64_t> hboff;
+  ~seas_op() {
+    for (auto& b : owned) (void)hipFree(b.p);
+  }
+};
+
+struct seas_state {
+  seas_op* op = nullptr;
+  int mode = 0;  // 0 fresh, 1 prescribed, 2 stepping
+  int64_t step = 0, first = 0;
+  std::vector<DevBuf> owned;
+  std::vector<DevBuf> ckpt;  // buffers that make up the state
+  double *V, *theta, *thdot, *delta, *tau0, *tau0_rate;
+  double *fa, *fb, *fDc, *fsn, *fV0, *ff0, *feps;
+  double *Vstar, *Vbar, *th2, *f_hist, *f_self, *f_int;
+  double* ring64;
+  void* ringop;
+  double* tail_acc;
+  double* partials;
+  double2 *dring, *Fh, *F;
+  int* fail;
+  bool timing = false;
+  std::vector<hipEvent_t> ev;  // start/stop pairs
+  size_t n_ev = 0;             // pairs recorded since the last read
+  ~seas_state() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+    for (auto& b : owned) (void)hipFree(b.p);
+  }
+};
+
+namespace {
+
+template <typename TF>
+StepArgs<TF> make_args(seas_op* op, seas_state* st) {
+  const HostOp& h = op->h;
+  StepArgs<TF> a{};
+  a.N = h.N;
+  a.dt = h.dt;
+  a.eta = h.eta;
+  a.fault_of = op->fault_of;
+  a.sf = op->sf;
+  a.tw = op->tw;
+  a.F = st->F;
+  a.f_hist = st->f_hist;
+  a.l0_ptr = op->l0_ptr;
+  a.l0_col = op->l0_col;
+  a.l0_val = op->l0_val;
+  a.tau0 = st->tau0;
+  a.tau0_rate = st->tau0_rate;
+  a.fric = Friction{st->fa, st->fb, st->fDc, st->fsn, st->fV0, st->ff0, st->feps};
+  a.V = st->V;
+  a.theta = st->theta;
+  a.thdot = st->thdot;
+  a.delta = st->delta;
+  a.Vstar = st->Vstar;
+  a.Vbar = st->Vbar;
+  a.th2 = st->th2;
+  a.f_self_out = st->f_self;
+  a.f_int_out = st->f_int;
+  a.fail = st->fail;
+  a.ring64 = st->ring64;
+  a.ringop = (TF*)st->ringop;
+  a.R = h.ring_len;
+  a.tail_acc = st->tail_acc;
+  a.src_pairs = op->src_pairs;
+  a.src_pairs_ptr = op->src_pairs_ptr;
+  a.first = st->first;
+  a.tail = h.prm.int_tail;
+  return a;
+}
+
+void eval_history(seas_op* op, seas_state* st, int64_t head, hipStream_t s) {
+  const HostOp& h = op->h;
+  if (st->timing) {
+    if (st->ev.size() < 2 * (st->n_ev + 1)) {
+      hipEvent_t a, b;
+      HIPCHK(hipEventCreate(&a));
+      HIPCHK(hipEventCreate(&b));
+      st->ev.push_back(a);
+      st->ev.push_back(b);
+    }
+    HIPCHK(hipEventRecord(st->ev[2 * st->n_ev], s));
+  }
+  launch_hmat(h, op->items, op->lagT, op->lagCol, op->lagColOff, op->arena, st->ringop, head, st->tail_acc,
+              st->partials, s);
+  if (st->timing) {
+    HIPCHK(hipEventRecord(st->ev[2 * st->n_ev + 1], s));
+    st->n_ev++;
+  }
+  launch_reduce(h, st->partials, op->red_ptr, op->red_idx, st->f_hist, s);
+}
+
+template <typename TF>
+void do_steps(seas_op* op, seas_state* st, int n_steps, hipStream_t s) {
+  const HostOp& h = op->h;
+  const int nm = h.n_modes;
+  for (int it = 0; it < n_steps; ++it) {
+    const int64_t n = st->step;
+    eval_history(op, st, n, s);
+    launch_self_hist(nm, op->modes, op->tab, st->dring, n + 1, st->Fh, s);
+    StepArgs<TF> a = make_args<TF>(op, st);
+    a.t_next = (double)(n + 1) * h.dt;
+    a.time_new = n + 1;
+    launch_dft(nm, op->modes, op->sf, st->delta, st->V, h.dt, op->tw, op->tab, st->Fh, nullptr, st->F, st->dring,
+               0, 0, 0, s);
+    launch_stage<TF>(a, 0, s);
+    launch_dft(nm, op->modes, op->sf, st->delta, st->Vbar, h.dt, op->tw, op->tab, st->Fh, nullptr, st->F,
+               st->dring, 1, n + 1, n + 1, s);
+    launch_stage<TF>(a, 1, s);
+    st->step = n + 1;
+  }
+  HIPCHK(hipGetLastError());
+}
+
+template <typename TF>
+void do_prescribed(seas_op* op, seas_state* st, const double* V, int n_steps, double* f, hipStream_t s) {
+  const HostOp& h = op->h;
+  const int nm = h.n_modes;
+  for (int it = 0; it < n_steps; ++it) {
+    const int64_t n = st->step + 1;  // evaluating f^n
+    const int64_t hd = n - 1;        // time of the newest rate, V^{n-1}
+    StepArgs<TF> a = make_args<TF>(op, st);
+    a.time_new = hd;
+    // the accumulators of a new state already cover every time up to -T_end - 1 (the
+    // window of the rate at time 0); re-pushing time 0 must not add that row again
+    if (hd < 1) a.tail = 0;
+    const double* Vrow = V + (size_t)it * h.N;
+    launch_prescribed_push<TF>(a, Vrow, s);
+    eval_history(op, st, hd, s);
+    launch_self_hist(nm, op->modes, op->tab, st->dring, n, st->Fh, s);
+    launch_dft(nm, op->modes, op->sf, st->delta, nullptr, 0.0, op->tw, op->tab, st->Fh, nullptr, st->F, st->dring,
+               1, n, n, s);
+    launch_prescribed_out<TF>(a, Vrow, f + (size_t)it * h.N, s);
+    st->step = n;
+  }
+  HIPCHK(hipGetLastError());
+}
+
+seas_op* checked(seas_op* op) {
+  if (!op) throw Error(SEAS_ERR_INVALID_ARG, "null operator");
+  if (op->host_only) throw Error(SEAS_ERR_MISMATCH, "operator was built with host_only = 1");
+  HIPCHK(hipSetDevice(op->device));
+  return op;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* seas_last_error(void) { return g_err.c_str(); }
+const char* seas_version(void) { return "seas-mi355x 0.1 (gfx950)"; }
+
+seas_status seas_build_operator(const seas_fault_t* faults, int32_t n_faults, const seas_params_t* params,
+                                seas_op_t** out) {
+  return guard([&] {
+    if (!faults || !params || !out) throw Error(SEAS_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    auto op = std::make_unique<seas_op>();
+    op->host_only = params->host_only != 0;
+    if (!op->host_only) HIPCHK(hipGetDevice(&op->device));
+    std::vector<std::vector<double>> b64;
+    std::vector<std::vector<float>> b32;
+    std::vector<int64_t> boff;
+    build_host(faults, n_faults, *params, op->h, b64, b32, boff);
+    HostOp& h = op->h;
+    const bool f32 = h.prm.factor_dtype == SEAS_F32;
+    op->elem_bytes = f32 ? 4 : 8;
+    if (op->host_only) {
+      op->hb64.swap(b64);
+      op->hb32.swap(b32);
+      op->hboff.swap(boff);
+      *out = op.release();
+      return;
+    }
+    // factor arena, block by block
+    op->arena = dalloc(op->owned, (size_t)h.arena_elems * op->elem_bytes);
+    for (size_t bi = 0; bi < boff.size(); ++bi) {
+      const size_t n = f32 ? b32[bi].size() : b64[bi].size();
+      if (n == 0) continue;
+      const void* src = f32 ? (const void*)b32[bi].data() : (const void*)b64[bi].data();
+      HIPCHK(hipMemcpy((char*)op->arena + (size_t)boff[bi] * op->elem_bytes, src, n * op->elem_bytes,
+                       hipMemcpyHostToDevice));
+      std::vector<double>().swap(b64[bi]);
+      std::vector<float>().swap(b32[bi]);
+    }
+    op->items = upload(op->owned, h.items);
+    op->lagT = upload(op->owned, h.lagT);
+    op->lagCol = upload(op->owned, h.lagCol);
+    op->lagColOff = upload(op->owned, h.lagColOff);
+    op->red_ptr = upload(op->owned, h.red_ptr);
+    op->red_idx = upload(op->owned, h.red_idx);
+    op->l0_ptr = upload(op->owned, h.l0_ptr);
+    op->l0_col = upload(op->owned, h.l0_col);
+    op->l0_val = upload(op->owned, h.l0_val);
+    op->tab = upload(op->owned, h.self_tab);
+    // self-term metadata and twiddle tables e^{-2 pi i k / M}
+    std::vector<double2> tw;
+    std::vector<int> fault_of(h.N);
+    for (size_t k = 0; k < h.faults.size(); ++k) {
+      const SelfFault& s = h.self[k];
+      SelfFaultDev d;
+      d.off = h.faults[k].off;
+      d.Np = s.Np;
+      d.M = s.M;
+      d.nm = s.nm;
+      d.mode_off = s.mode_off;
+      d.tw = (int)tw.size();
+      d.cfac = s.cfac;
+      for (int e = 0; e < s.M; ++e) {
+        const double ang = 2.0 * M_PI * (double)e / (double)s.M;
+        tw.push_back(make_double2(std::cos(ang), -std::sin(ang)));
+      }
+      op->hsf.push_back(d);
+      for (int n = 1; n <= s.nm; ++n) {
+        SelfMode m;
+        m.fault = (int)k;
+        m.n = n;
+        m.W = s.W[n - 1];
+        m.pad = 0;
+        m.tab = s.tab_off[n - 1];
+        m.ring = s.ring_off[n - 1];
+        op->hmodes.push_back(m);
+      }
+      for (int j = 0; j < s.Np; ++j) fault_of[d.off + j] = (int)k;
+    }
+    op->sf = upload(op->owned, op->hsf);
+    op->modes = upload(op->owned, op->hmodes);
+    op->tw = upload(op->owned, tw);
+    op->fault_of = upload(op->owned, fault_of);
+    // pairs by source fault (expired-slip updates)
+    std::vector<int32_t> sp, spp(h.faults.size() + 1, 0);
+    for (size_t k = 0; k < h.faults.size(); ++k) {
+      for (size_t pi = 0; pi < h.pairs.size(); ++pi)
+        if (h.pairs[pi].b == (int)k) {
+          sp.push_back(h.tail_off[pi]);
+          sp.push_back(h.pairs[pi].T_end);
+        }
+      spp[k + 1] = (int32_t)(sp.size() / 2);
+    }
+    op->src_pairs = upload(op->owned, sp);
+    op->src_pairs_ptr = upload(op->owned, spp);
+    *out = op.release();
+  });
+}
+
+void seas_operator_destroy(seas_op_t* op) {
+  if (op) {
+    if (!op->host_only) (void)hipSetDevice(op->device);
+    delete op;
+  }
+}
+
+seas_status seas_operator_lag_matrix(const seas_op_t* op, int32_t a, int32_t b, int32_t T, double* out) {
+  return guard([&] {
+    if (!op || !out) throw Error(SEAS_ERR_INVALID_ARG, "null argument");
+    if (!op->host_only) throw Error(SEAS_ERR_MISMATCH, "factors are only kept on the host with host_only = 1");
+    const HostOp& h = op->h;
+    const int nf = (int)h.faults.size();
+    if (a < 0 || b < 0 || a >= nf || b >= nf || a == b || T < -1) throw Error(SEAS_ERR_INVALID_ARG, "bad pair/lag");
+    const Fault &A = h.faults[a], &B = h.faults[b];
+    const int p_all = A.Np, q_all = B.Np;
+    std::fill(out, out + (size_t)p_all * q_all, 0.0);
+    if (T == 0) {
+      for (int i = 0; i < p_all; ++i)
+        for (int k = h.l0_ptr[A.off + i]; k < h.l0_ptr[A.off + i + 1]; ++k) {
+          const int c = h.l0_col[k];
+          if (c >= B.off && c < B.off + q_all) out[(size_t)i * q_all + (c - B.off)] = h.l0_val[k];
+        }
+      return;
+    }
+    // the arena is the concatenation of the per-block buffers: locate an element
+    auto elem = [&](int64_t e) -> double {
+      size_t lo = 0, hi = op->hboff.size();
+      while (hi - lo > 1) {
+        const size_t mid = (lo + hi) / 2;
+        if (op->hboff[mid] <= e) lo = mid;
+        else hi = mid;
+      }
+      const int64_t k = e - op->hboff[lo];
+      return op->elem_bytes == 4 ? (double)op->hb32[lo][k] : op->hb64[lo][k];
+    };
+    for (size_t ii = 0; ii < h.items.size(); ++ii) {
+      const Item& it = h.items[ii];
+      if (it.row0 < A.off || it.row0 >= A.off + p_all || it.col0 < B.off || it.col0 >= B.off + q_all) continue;
+      const int ri = it.row0 - A.off, cj = it.col0 - B.off;
+      const int32_t* cp = &h.lagCol[h.lagColOff[ii]];
+      for (int l = 0; l < it.nlag; ++l) {
+        if (h.lagT[it.lag_off + l] != T) continue;
+        if (it.kind == 0) {
+          const int nc = it.ncol;
+          for (int c = cp[l]; c < cp[l + 1]; ++c)
+            for (int i = 0; i < it.p; ++i) {
+              const double u = elem(it.data + (int64_t)it.q * nc + (int64_t)c * it.p + i);
+              for (int j = 0; j < it.q; ++j)
+                out[(size_t)(ri + i) * q_all + cj + j] += u * elem(it.data + (int64_t)j * nc + c);
+            }
+        } else {
+          for (int j = 0; j < it.q; ++j)
+            for (int i = 0; i < it.p; ++i)
+              out[(size_t)(ri + i) * q_all + cj + j] = elem(it.data + ((int64_t)l * it.q + j) * it.p + i);
+        }
+      }
+    }
+  });
+}
+
+seas_status seas_operator_info(const seas_op_t* op, seas_op_info_t* out) {
+  return guard([&] {
+    if (!op || !out) throw Error(SEAS_ERR_INVALID_ARG, "null argument");
+    const HostOp& h = op->h;
+    std::memset(out, 0, sizeof(*out));
+    out->n_faults = (int32_t)h.faults.size();
+    out->n_elem = h.N;
+    out->dt = h.dt;
+    out->max_lag = h.max_lag;
+    out->max_self_window = h.max_self_W;
+    int64_t nb = 0;
+    for (auto& v : h.blocks) nb += (int64_t)v.size();
+    out->n_blocks = nb;
+    out->n_items = (int64_t)h.items.size();
+    out->dense_entries = h.dense_entries;
+    out->stored_entries = h.stored_entries;
+    out->lag0_nnz = (int64_t)h.l0_val.size();
+    out->self_entries = h.self_entries;
+    out->bytes_per_step = (double)h.stored_entries * (double)op->elem_bytes + (double)h.self_entries * (8.0 + 16.0);
+    out->flops_per_step = 2.0 * (double)h.stored_entries + 4.0 * (double)h.self_entries;
+    out->build_seconds = h.build_seconds;
+    out->factor_dtype = h.prm.factor_dtype;
+  });
+}
+
+seas_status seas_operator_windows(const seas_op_t* op, int32_t* T_init, int32_t* T_end) {
+  return guard([&] {
+    if (!op || !T_init || !T_end) throw Error(SEAS_ERR_INVALID_ARG, "null argument");
+    for (size_t i = 0; i < op->h.pairs.size(); ++i) {
+      T_init[i] = op->h.pairs[i].T_init;
+      T_end[i] = op->h.pairs[i].T_end;
+    }
+  });
+}
+
+seas_status seas_operator_blocks(const seas_op_t* op, int32_t a, int32_t b, int32_t* blocks, int64_t* count) {
+  return guard([&] {
+    if (!op || !count) throw Error(SEAS_ERR_INVALID_ARG, "null argument");
+    const HostOp& h = op->h;
+    const int nf = (int)h.faults.size();
+    if (a < 0 || b < 0 || a >= nf || b >= nf || a == b) throw Error(SEAS_ERR_INVALID_ARG, "bad pair");
+    size_t pi = 0;
+    for (; pi < h.pairs.size(); ++pi)
+      if (h.pairs[pi].a == a && h.pairs[pi].b == b) break;
+    const auto& bl = h.blocks[pi];
+    if (blocks) {
+      if (*count < (int64_t)bl.size()) throw Error(SEAS_ERR_INVALID_ARG, "block buffer too small");
+      for (size_t i = 0; i < bl.size(); ++i) {
+        blocks[5 * i + 0] = bl[i].r0;
+        blocks[5 * i + 1] = bl[i].r1;
+        blocks[5 * i + 2] = bl[i].s0;
+        blocks[5 * i + 3] = bl[i].s1;
+        blocks[5 * i + 4] = bl[i].adm;
+      }
+    }
+    *count = (int64_t)bl.size();
+  });
+}
+
+seas_status seas_operator_self_table(const seas_op_t* op, int32_t k, int32_t n, double* out, int32_t capacity,
+                                     int32_t* W_n) {
+  return guard([&] {
+    if (!op || !W_n) throw Error(SEAS_ERR_INVALID_ARG, "null argument");
+    const HostOp& h = op->h;
+    if (k < 0 || k >= (int)h.self.size() || n < 1 || n > h.self[k].nm) throw Error(SEAS_ERR_INVALID_ARG, "bad mode");
+    const SelfFault& s = h.self[k];
+    *W_n = s.W[n - 1];
+    if (out) {
+      if (capacity < s.W[n - 1] + 1) throw Error(SEAS_ERR_INVALID_ARG, "capacity too small");
+      std::memcpy(out, &h.self_tab[s.tab_off[n - 1]], sizeof(double) * (s.W[n - 1] + 1));
+    }
+  });
+}
+
+size_t seas_state_bytes(const seas_op_t* op, int32_t n_variants) {
+  if (!op || n_variants < 1) return 0;
+  const HostOp& h = op->h;
+  const size_t N = (size_t)h.N * n_variants;
+  size_t b = N * 8 * 19;                                         // per-element state and scratch
+  b += (size_t)h.ring_len * N * 8;                               // FP64 rate history
+  if (op->elem_bytes != 8) b += (size_t)h.ring_len * N * op->elem_bytes;  // operand copy
+  b += (size_t)h.tail_len * 8 * n_variants;
+  b += (size_t)h.n_partials * 8 * n_variants;
+  b += (size_t)h.self_ring_len * 16 * n_variants + (size_t)h.n_modes * 16 * 2 * n_variants;
+  return b;
+}
+
+seas_status seas_state_create(seas_op_t* op, int32_t n_variants, const seas_friction_t* fric, const double* V_init,
+                              const double* theta_init, const double* tau0, const double* tau0_rate,
+                              const double* delta_init, void* stream, seas_state_t** out) {
+  return guard([&] {
+    checked(op);
+    if (!out || !fric || !V_init || !theta_init || !tau0) throw Error(SEAS_ERR_INVALID_ARG, "null argument");
+    if (n_variants != 1) throw Error(SEAS_ERR_INVALID_ARG, "n_variants must be 1");
+    if (!fric->a || !fric->b || !fric->Dc || !fric->sigma_n || !fric->V0 || !fric->f0)
+      throw Error(SEAS_ERR_INVALID_ARG, "null friction array");
+    *out = nullptr;
+    const HostOp& h = op->h;
+    const size_t N = h.N;
+    hipStream_t s = (hipStream_t)stream;
+    auto st = std::make_unique<seas_state>();
+    st->op = op;
+    auto A = [&](size_t bytes, bool ck) {
+      void* p = dalloc(st->owned, bytes);
+      HIPCHK(hipMemsetAsync(p, 0, bytes, s));
+      if (ck) st->ckpt.push_back({p, bytes});
+      return p;
+    };
+    const size_t vb = N * 8;
+    st->V = (double*)A(vb, true);
+    st->theta = (double*)A(vb, true);
+    st->thdot = (double*)A(vb, true);
+    st->delta = (double*)A(vb, true);
+    st->tau0 = (double*)A(vb, true);
+    st->tau0_rate = (double*)A(vb, true);
+    st->fa = (double*)A(vb, true);
+    st->fb = (double*)A(vb, true);
+    st->fDc = (double*)A(vb, true);
+    st->fsn = (double*)A(vb, true);
+    st->fV0 = (double*)A(vb, true);
+    st->ff0 = (double*)A(vb, true);
+    st->feps = (double*)A(vb, true);
+    st->Vstar = (double*)A(vb, false);
+    st->Vbar = (double*)A(vb, false);
+    st->th2 = (double*)A(vb, false);
+    st->f_hist = (double*)A(vb, true);
+    st->f_self = (double*)A(vb, true);
+    st->f_int = (double*)A(vb, true);
+    st->ring64 = (double*)A((size_t)h.ring_len * vb, true);
+    st->ringop = op->elem_bytes == 8 ? (void*)st->ring64 : A((size_t)h.ring_len * N * op->elem_bytes, true);
+    st->tail_acc = (double*)A((size_t)h.tail_len * 8, true);
+    st->partials = (double*)A((size_t)h.n_partials * 8, false);
+    st->dring = (double2*)A((size_t)h.self_ring_len * 16, true);
+    st->Fh = (double2*)A((size_t)h.n_modes * 16, false);
+    st->F = (double2*)A((size_t)h.n_modes * 16, false);
+    st->fail = (int*)A(sizeof(int), false);
+    // host-side initial values
+    std::vector<double> eps(N, 1.0), thd(N), zero(N, 0.0);
+    if (fric->eps) eps.assign(fric->eps, fric->eps + N);
+    for (size_t r = 0; r < N; ++r) {
+      if (!(V_init[r] > 0) || !(theta_init[r] > 0) || !(fric->Dc[r] > 0) || !(fric->V0[r] > 0) ||
+          !(eps[r] > 0 && eps[r] <= 1.0))
+        throw Error(SEAS_ERR_INVALID_ARG, "V, theta, Dc, V0 must be > 0 and 0 < eps <= 1");
+      thd[r] = host_state_rate(V_init[r], theta_init[r], fric->Dc[r], eps[r]);
+    }
+    auto H2D = [&](void* d, const double* src) { HIPCHK(hipMemcpyAsync(d, src, vb, hipMemcpyHostToDevice, s)); };
+    H2D(st->V, V_init);
+    H2D(st->theta, theta_init);
+    H2D(st->thdot, thd.data());
+    H2D(st->delta, delta_init ? delta_init : zero.data());
+    H2D(st->tau0, tau0);
+    H2D(st->tau0_rate, tau0_rate ? tau0_rate : zero.data());
+    H2D(st->fa, fric->a);
+    H2D(st->fb, fric->b);
+    H2D(st->fDc, fric->Dc);
+    H2D(st->fsn, fric->sigma_n);
+    H2D(st->fV0, fric->V0);
+    H2D(st->ff0, fric->f0);
+    H2D(st->feps, eps.data());
+    // histories at t = 0: V^0 and D^0
+    H2D(st->ring64, V_init);  // time 0 -> slot 0
+    if (op->elem_bytes != 8) {
+      std::vector<float> v32(V_init, V_init + N);
+      HIPCHK(hipMemcpyAsync(st->ringop, v32.data(), N * 4, hipMemcpyHostToDevice, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    launch_dft(h.n_modes, op->modes, op->sf, st->delta, nullptr, 0.0, op->tw, op->tab, nullptr, nullptr, st->F,
+               st->dring, 1, 0, 0, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    *out = st.release();
+  });
+}
+
+void seas_state_destroy(seas_state_t* st) {
+  if (st) {
+    (void)hipSetDevice(st->op->device);
+    delete st;
+  }
+}
+
+seas_status seas_state_load_history(seas_state_t* st, const double* V_hist, int32_t n_hist, void* stream) {
+  return guard([&] {
+    if (!st || (!V_hist && n_hist > 0) || n_hist < 0) throw Error(SEAS_ERR_INVALID_ARG, "bad argument");
+    seas_op* op = checked(st->op);
+    if (st->mode != 0 || st->step != 0) throw Error(SEAS_ERR_MISMATCH, "history must be loaded on a fresh state");
+    if (n_hist == 0) return;
+    const HostOp& h = op->h;
+    const size_t N = h.N;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t H = n_hist;
+    // rate rows m = -H..-1 (row H + m of V_hist); only the newest ring_len - 2 can be read
+    const int64_t mlo = std::max<int64_t>(-H, -(int64_t)(h.ring_len - 2));
+    std::vector<float> v32;
+    for (int64_t m = mlo; m <= -1; ++m) {
+      const double* row = V_hist + (size_t)(H + m) * N;
+      const int64_t slot = ((m % h.ring_len) + h.ring_len) % h.ring_len;
+      HIPCHK(hipMemcpyAsync(st->ring64 + slot * N, row, N * 8, hipMemcpyHostToDevice, s));
+      if (op->elem_bytes != 8) {
+        v32.assign(row, row + N);
+        HIPCHK(hipMemcpyAsync((float*)st->ringop + slot * N, v32.data(), N * 4, hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+      }
+    }
+    // slip before t = 0 and its coefficients D^m, m = -1 .. 1 - W_max
+    std::vector<double> d0(N);
+    HIPCHK(hipMemcpyAsync(d0.data(), st->delta, N * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const int64_t dlo = std::max<int64_t>(-H, 1 - (int64_t)std::max(1, h.max_self_W));
+    double* dtmp = (double*)dalloc(st->owned, N * 8);
+    std::vector<double> dm(d0);
+    for (int64_t m = -1; m >= dlo; --m) {
+      const double* row = V_hist + (size_t)(H + m) * N;
+      for (size_t r = 0; r < N; ++r) dm[r] -= h.dt * row[r];
+      HIPCHK(hipMemcpyAsync(dtmp, dm.data(), N * 8, hipMemcpyHostToDevice, s));
+      launch_dft(h.n_modes, op->modes, op->sf, dtmp, nullptr, 0.0, op->tw, op->tab, nullptr, nullptr, st->F,
+                 st->dring, 1, m, 0, s);
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    // expired-slip accumulators: dt sum of V^m, m <= -T_end - 1
+    if (h.prm.int_tail) {
+      std::vector<double> E(h.tail_len, 0.0);
+      for (size_t pi = 0; pi < h.pairs.size(); ++pi) {
+        const Fault& B = h.faults[h.pairs[pi].b];
+        for (int64_t m = -H; m <= -(int64_t)h.pairs[pi].T_end - 1; ++m) {
+          const double* row = V_hist + (size_t)(H + m) * N + B.off;
+          for (int j = 0; j < B.Np; ++j) E[h.tail_off[pi] + j] += h.dt * row[j];
+        }
+      }
+      HIPCHK(hipMemcpyAsync(st->tail_acc, E.data(), E.size() * 8, hipMemcpyHostToDevice, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    st->first = -H;
+  });
+}
+
+seas_status seas_eval_prescribed(seas_op_t* op, seas_state_t* st, const double* V_dev, int32_t n_steps, double* f_dev,
+                                 void* stream) {
+  return guard([&] {
+    checked(op);
+    if (!st || st->op != op) throw Error(SEAS_ERR_MISMATCH, "state belongs to another operator");
+    if (n_steps < 0 || (n_steps > 0 && (!V_dev || !f_dev))) throw Error(SEAS_ERR_INVALID_ARG, "bad arguments");
+    if (st->mode == 2) throw Error(SEAS_ERR_MISMATCH, "state has taken SEAS steps");
+    st->mode = 1;
+    hipStream_t s = (hipStream_t)stream;
+    if (op->elem_bytes == 8) do_prescribed<double>(op, st, V_dev, n_steps, f_dev, s);
+    else do_prescribed<float>(op, st, V_dev, n_steps, f_dev, s);
+  });
+}
+
+seas_status seas_step(seas_op_t* op, seas_state_t* st, int32_t n_steps, void* stream) {
+  return guard([&] {
+    checked(op);
+    if (!st || st->op != op) throw Error(SEAS_ERR_MISMATCH, "state belongs to another operator");
+    if (n_steps < 0) throw Error(SEAS_ERR_INVALID_ARG, "n_steps < 0");
+    if (st->mode == 1) throw Error(SEAS_ERR_MISMATCH, "state is in prescribed-history mode");
+    st->mode = 2;
+    hipStream_t s = (hipStream_t)stream;
+    if (op->elem_bytes == 8) do_steps<double>(op, st, n_steps, s);
+    else do_steps<float>(op, st, n_steps, s);
+  });
+}
+
+seas_status seas_state_check(seas_state_t* st, void* stream) {
+  int bad = 0;
+  seas_status rc = guard([&] {
+    if (!st) throw Error(SEAS_ERR_INVALID_ARG, "null state");
+    checked(st->op);
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipMemcpyAsync(&bad, st->fail, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (bad) HIPCHK(hipMemsetAsync(st->fail, 0, sizeof(int), s));
+    HIPCHK(hipStreamSynchronize(s));
+  });
+  if (rc != SEAS_OK) return rc;
+  if (bad) {
+    g_err = "Newton did not converge within 50 iterations";
+    return SEAS_ERR_NOT_CONVERGED;
+  }
+  return SEAS_OK;
+}
+
+seas_status seas_read_state(const seas_state_t* st, int32_t field, int32_t variant, double* dst, size_t count,
+                            int32_t dst_is_device, void* stream) {
+  return guard([&] {
+    if (!st || !dst) throw Error(SEAS_ERR_INVALID_ARG, "null argument");
+    checked(st->op);
+    if (variant != 0) throw Error(SEAS_ERR_INVALID_ARG, "variant out of range");
+    const size_t N = st->op->h.N;
+    if (count != N) throw Error(SEAS_ERR_INVALID_ARG, "count must equal the number of elements");
+    const double* src = nullptr;
+    switch (field) {
+      case SEAS_FIELD_V: src = st->V; break;
+      case SEAS_FIELD_THETA: src = st->theta; break;
+      case SEAS_FIELD_DELTA: src = st->delta; break;
+      case SEAS_FIELD_THETADOT: src = st->thdot; break;
+      case SEAS_FIELD_F_HIST: src = st->f_hist; break;
+      case SEAS_FIELD_F_SELF: src = st->f_self; break;
+      case SEAS_FIELD_F_INT: src = st->f_int; break;
+      case SEAS_FIELD_TAU0: src = st->tau0; break;
+      default: throw Error(SEAS_ERR_INVALID_ARG, "unknown field");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipMemcpyAsync(dst, src, N * 8, dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    if (!dst_is_device) HIPCHK(hipStreamSynchronize(s));
+  });
+}
+
+int64_t seas_state_step_index(const seas_state_t* st) { return st ? st->step : -1; }
+
+seas_status seas_state_set_timing(seas_state_t* st, int32_t enable) {
+  return guard([&] {
+    if (!st) throw Error(SEAS_ERR_INVALID_ARG, "null state");
+    st->timing = enable != 0;
+  });
+}
+
+seas_status seas_state_read_timing(seas_state_t* st, void* stream, double* ms_total, int64_t* launches) {
+  return guard([&] {
+    if (!st || !ms_total || !launches) throw Error(SEAS_ERR_INVALID_ARG, "null argument");
+    checked(st->op);
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    double tot = 0.0;
+    for (size_t i = 0; i < st->n_ev; ++i) {
+      float ms = 0.0f;
+      HIPCHK(hipEventElapsedTime(&ms, st->ev[2 * i], st->ev[2 * i + 1]));
+      tot += ms;
+    }
+    *ms_total = tot;
+    *launches = (int64_t)st->n_ev;
+    st->n_ev = 0;
+  });
+}
+
+size_t seas_state_checkpoint_bytes(const seas_state_t* st) {
+  if (!st) return 0;
+  size_t b = 4 * sizeof(int64_t);
+  for (auto& c : st->ckpt) b += c.bytes;
+  return b;
+}
+
+seas_status seas_state_save(const seas_state_t* st, void* host_buf, size_t bytes, void* stream) {
+  return guard([&] {
+    if (!st || !host_buf) throw Error(SEAS_ERR_INVALID_ARG, "null argument");
+    checked(st->op);
+    if (bytes < seas_state_checkpoint_bytes(st)) throw Error(SEAS_ERR_INVALID_ARG, "buffer too small");
+    hipStream_t s = (hipStream_t)stream;
+    char* p = (char*)host_buf;
+    const int64_t hdr[4] = {st->step, st->first, st->mode, (int64_t)st->op->h.N};
+    std::memcpy(p, hdr, sizeof(hdr));
+    p += sizeof(hdr);
+    for (auto& c : st->ckpt) {
+      HIPCHK(hipMemcpyAsync(p, c.p, c.bytes, hipMemcpyDeviceToHost, s));
+      p += c.bytes;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+  });
+}
+
+seas_status seas_state_restore(seas_state_t* st, const void* host_buf, size_t bytes, void* stream) {
+  return guard([&] {
+    if (!st || !host_buf) throw Error(SEAS_ERR_INVALID_ARG, "null argument");
+    checked(st->op);
+    if (bytes < seas_state_checkpoint_bytes(st)) throw Error(SEAS_ERR_INVALID_ARG, "buffer too small");
+    const char* p = (const char*)host_buf;
+    int64_t hdr[4];
+    std::memcpy(hdr, p, sizeof(hdr));
+    if (hdr[3] != st->op->h.N) throw Error(SEAS_ERR_MISMATCH, "checkpoint of another operator");
+    p += sizeof(hdr);
+    hipStream_t s = (hipStream_t)stream;
+    for (auto& c : st->ckpt) {
+      HIPCHK(hipMemcpyAsync(c.p, p, c.bytes, hipMemcpyHostToDevice, s));
+      p += c.bytes;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    st->step = hdr[0];
+    st->first = hdr[1];
+    st->mode = (int)hdr[2];
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,713 @@
+// Host-side operator build: geometry, causality windows, closed-form kernel
+// entries, fault-wise H-matrix partition, per-lag adaptive cross approximation,
+// packing into device work items, spectral self-kernel tables.
+#include <omp.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+#include <numeric>
+
+#include "internal.hpp"
+
+namespace seas {
+
+// ============================================================== primitives
+// Weighted sum n1' I_31 + n2' I_32 of the antiplane primitives (Section 2.3.2,
+// eq. "primitives") at one corner (r1, r2) and ct = cs t. H(0) = 0, sgn(0) = 0.
+// Inside the cone ct > r: sqrt((ct/r)^2 - 1) = Q / r with Q^2 = (ct - r)(ct + r),
+// and arccos(|r1| / sqrt(ct^2 - r2^2)) = atan2(Q, |r1|).
+static inline double corner(double r1, double r2, double ct, double n1, double n2) {
+  const double r = std::hypot(r1, r2);
+  double v = 0.0;
+  if (r1 > 0.0 && ct > std::fabs(r2)) v += n2;  // plane-wave term H(r1) H(t - |r2|/cs)
+  if (ct > r) {
+    const double Q = std::sqrt((ct - r) * (ct + r));
+    const double rr = r * r;
+    v -= n1 * r2 * Q / (M_PI * rr);
+    if (r1 != 0.0) {
+      const double a1 = std::fabs(r1);
+      const double sg = r1 > 0.0 ? 1.0 : -1.0;
+      v += n2 * sg * (a1 * Q / rr - std::atan2(Q, a1)) / M_PI;
+    }
+  }
+  return v;
+}
+
+struct PairFrame {  // receiver a, source b
+  double n1, n2, h;
+};
+
+static inline PairFrame frame(const Fault& A, const Fault& B) {
+  return {A.nx * B.tx + A.ny * B.ty, A.nx * B.nx + A.ny * B.ny, 0.5 * B.dx};
+}
+
+static inline void offsets(const Fault& A, int i, const Fault& B, int j, double& r1, double& r2) {
+  const double dx = A.midx(i) - B.midx(j), dy = A.midy(i) - B.midy(j);
+  r1 = dx * B.tx + dy * B.ty;
+  r2 = dx * B.nx + dy * B.ny;
+}
+
+// K^T of eq. "kernel_interactions": space-time difference over the source element.
+double kernel_entry(const Fault& A, int i, const Fault& B, int j, int T, double dt, double cs) {
+  double r1, r2;
+  offsets(A, i, B, j, r1, r2);
+  const PairFrame fr = frame(A, B);
+  const double c1 = cs * ((T + 1) * dt), c0 = cs * (T * dt);
+  return (corner(r1 + fr.h, r2, c1, fr.n1, fr.n2) - corner(r1 - fr.h, r2, c1, fr.n1, fr.n2)) -
+         (corner(r1 + fr.h, r2, c0, fr.n1, fr.n2) - corner(r1 - fr.h, r2, c0, fr.n1, fr.n2));
+}
+
+// Static stress at receiver i per unit slip of source element j (late-time limit
+// of -mu/(2cs) K^T / dt): two screw dislocations at the element ends.
+double static_stress(const Fault& A, int i, const Fault& B, int j, double mu) {
+  double r1, r2;
+  offsets(A, i, B, j, r1, r2);
+  const PairFrame fr = frame(A, B);
+  const double p1 = r1 + fr.h, m1 = r1 - fr.h;
+  const double pp = p1 * p1 + r2 * r2, mm = m1 * m1 + r2 * r2;
+  const double c = mu / (2.0 * M_PI);
+  return fr.n1 * c * r2 * (1.0 / pp - 1.0 / mm) - fr.n2 * c * (p1 / pp - m1 / mm);
+}
+
+// ============================================================== self kernel
+// Gauss-Legendre rule on [-1, 1] from the three-term recurrence, by Newton from
+// Tricomi's initial guesses.
+struct GL {
+  std::vector<double> x, w;
+  explicit GL(int n) : x(n), w(n) {
+    for (int i = 0; i < n; ++i) {
+      double z = (1.0 - 1.0 / (8.0 * n * n) + 1.0 / (8.0 * n * n * n)) *
+                 std::cos(M_PI * (4.0 * i + 3.0) / (4.0 * n + 2.0));
+      double dp = 1.0;
+      for (int it = 0; it < 60; ++it) {
+        double p0 = 1.0, p1 = z;
+        for (int k = 2; k <= n; ++k) {
+          const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+          p0 = p1;
+          p1 = p2;
+        }
+        dp = n * (p0 - z * p1) / (1.0 - z * z);
+        const double dz = p1 / dp;
+        z -= dz;
+        if (std::fabs(dz) < 1e-17) break;
+      }
+      x[i] = z;
+      w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+  }
+};
+
+// Integral of K(n, t) over [t0, t1] (eq. "non_replicant_kernel"), with the order
+// of integration exchanged: K is (2/pi) times the integral of cos^2(psi) cos(a t
+// sin psi) over psi in [0, pi/2] restricted to t <= L / (cs sin psi) (this one
+// region covers both branches of the definition, a = n pi cs / L). The t-integral
+// is then elementary, leaving one smooth psi-integral split where the restriction
+// starts to cut the cell: sin psi1 = L/(cs t1), sin psi0 = L/(cs t0).
+void self_cells(int n, int W, double dt, double L, double cs, double* out) {
+  static const GL g(16);
+  const double a = n * M_PI * cs / L;
+  auto piece = [&](double lo, double hi, int panels, const std::function<double(double)>& f) {
+    if (hi <= lo) return 0.0;
+    const double h = (hi - lo) / panels;
+    double s = 0.0;
+    for (int p = 0; p < panels; ++p) {
+      const double m = lo + (p + 0.5) * h;
+      double acc = 0.0;
+      for (size_t k = 0; k < g.x.size(); ++k) acc += g.w[k] * f(m + 0.5 * h * g.x[k]);
+      s += 0.5 * h * acc;
+    }
+    return s;
+  };
+  for (int T = 0; T <= W; ++T) {
+    const double t0 = std::max(0.0, (T - 0.5) * dt), t1 = (T + 0.5) * dt;
+    const double s1 = L / (cs * t1);
+    const double psi1 = s1 >= 1.0 ? 0.5 * M_PI : std::asin(s1);
+    double psi0 = 0.5 * M_PI;
+    if (t0 > 0.0) {
+      const double s0 = L / (cs * t0);
+      psi0 = s0 >= 1.0 ? 0.5 * M_PI : std::asin(s0);
+    }
+    const int pan1 = 4 + (int)std::ceil(a * t1 * std::sin(psi1) / M_PI);
+    const int pan2 = 4 + (int)std::ceil(a * t0 * (std::sin(psi0) - std::sin(psi1)) / M_PI);
+    // full cell: int_t0^t1 cos(a s t) dt = 2 cos(a s (t0+t1)/2) sin(a s (t1-t0)/2) / (a s)
+    const double tm = 0.5 * (t0 + t1), th = 0.5 * (t1 - t0);
+    const double full = piece(0.0, psi1, pan1, [&](double psi) {
+      const double s = std::sin(psi), c = std::cos(psi);
+      const double as = a * s;
+      const double v = as * th < 1e-8 ? 2.0 * th * std::cos(as * tm)
+                                      : 2.0 * std::cos(as * tm) * std::sin(as * th) / as;
+      return c * c * v;
+    });
+    // cut cell: int_t0^{L/(cs s)} cos(a s t) dt = (sin(n pi) - sin(a s t0)) / (a s), sin(n pi) = 0
+    const double cut = piece(psi1, psi0, pan2, [&](double psi) {
+      const double s = std::sin(psi), c = std::cos(psi);
+      return -c * c * std::sin(a * s * t0) / (a * s);
+    });
+    out[T] = 2.0 / M_PI * (full + cut);
+  }
+}
+
+// ============================================================== partition
+struct Node {
+  int lo, hi, kid0 = -1, kid1 = -1;
+  double cx, cy, r;
+};
+
+static void build_tree(const Fault& f, int leaf, std::vector<Node>& nodes) {
+  std::function<int(int, int)> rec = [&](int lo, int hi) -> int {
+    Node nd;
+    nd.lo = lo;
+    nd.hi = hi;
+    const double s = -0.5 * f.L + 0.5 * (lo + hi) * f.dx;  // closed-form bounding circle
+    nd.cx = f.cx + s * f.tx;
+    nd.cy = f.cy + s * f.ty;
+    nd.r = 0.5 * (hi - lo) * f.dx;
+    const int id = (int)nodes.size();
+    nodes.push_back(nd);
+    if (hi - lo > leaf) {
+      const int mid = lo + (hi - lo) / 2;
+      const int k0 = rec(lo, mid);
+      const int k1 = rec(mid, hi);
+      nodes[id].kid0 = k0;
+      nodes[id].kid1 = k1;
+    }
+    return id;
+  };
+  rec(0, f.Np);
+}
+
+static void traverse(const std::vector<Node>& to, const std::vector<Node>& ts, double eta_H, int pair,
+                     int a, int b, std::vector<BlockDesc>& out) {
+  std::function<void(int, int)> rec = [&](int o, int s) {
+    const Node &O = to[o], &S = ts[s];
+    const double d = std::hypot(O.cx - S.cx, O.cy - S.cy);
+    const bool oleaf = O.kid0 < 0, sleaf = S.kid0 < 0;
+    if (d > eta_H * (O.r + S.r)) {
+      out.push_back({pair, a, b, O.lo, O.hi, S.lo, S.hi, 1});
+      return;
+    }
+    if (oleaf && sleaf) {
+      out.push_back({pair, a, b, O.lo, O.hi, S.lo, S.hi, 0});
+      return;
+    }
+    bool split_o;
+    if (O.r > S.r) split_o = !oleaf;
+    else if (S.r > O.r) split_o = sleaf;
+    else split_o = !oleaf;
+    if (split_o) {
+      rec(O.kid0, s);
+      rec(O.kid1, s);
+    } else {
+      rec(o, S.kid0);
+      rec(o, S.kid1);
+    }
+  };
+  rec(0, 0);
+}
+
+// ============================================================== compression
+// Adaptive cross approximation with full pivoting on the evaluated block:
+// A ~= sum_l u_l w_l^T, stopping when the residual's Frobenius norm is at most
+// tol times that of A. Returns the rank, or -1 when the rank reaches
+// kmax (the factors would not be smaller than the block: store it dense).
+static int aca_full(const double* A, int p, int q, double tol, int kmax, std::vector<double>& U,
+                    std::vector<double>& Wf, std::vector<double>& R) {
+  const size_t n = (size_t)p * q;
+  R.assign(A, A + n);
+  double nrm2 = 0.0, amax = 0.0;
+  size_t imax = 0;
+  for (size_t e = 0; e < n; ++e) {
+    nrm2 += R[e] * R[e];
+    if (std::fabs(R[e]) > amax) {
+      amax = std::fabs(R[e]);
+      imax = e;
+    }
+  }
+  U.clear();
+  Wf.clear();
+  if (nrm2 == 0.0) return 0;
+  const double thr2 = tol * tol * nrm2;
+  int k = 0;
+  std::vector<double> u(p), w(q);
+  while (true) {
+    if (k >= kmax) return -1;
+    const int is = (int)(imax / q), js = (int)(imax % q);
+    const double piv = R[imax];
+    if (piv == 0.0) break;
+    for (int i = 0; i < p; ++i) u[i] = R[(size_t)i * q + js];
+    for (int j = 0; j < q; ++j) w[j] = R[(size_t)is * q + j] / piv;
+    U.insert(U.end(), u.begin(), u.end());
+    Wf.insert(Wf.end(), w.begin(), w.end());
+    ++k;
+    double r2 = 0.0;
+    amax = 0.0;
+    imax = 0;
+    for (int i = 0; i < p; ++i) {
+      double* row = &R[(size_t)i * q];
+      const double ui = u[i];
+      for (int j = 0; j < q; ++j) {
+        const double v = row[j] - ui * w[j];
+        row[j] = v;
+        r2 += v * v;
+        if (std::fabs(v) > amax) {
+          amax = std::fabs(v);
+          imax = (size_t)i * q + j;
+        }
+      }
+    }
+    if (r2 <= thr2) break;
+  }
+  if (k >= kmax) return -1;
+  return k;
+}
+
+// ============================================================== per-block build
+struct LagFactor {
+  int T;        // lag (-1 = static tail)
+  int rank;     // > 0 low rank, 0 dense
+  std::vector<double> U, W, D;  // U: k x p (col l = U[l*p..]), W: k x q, D: p x q row-major
+};
+
+struct BlockOut {
+  std::vector<Item> items;
+  std::vector<int32_t> lagT;
+  std::vector<int32_t> lagCol;
+  std::vector<double> d64;
+  std::vector<float> d32;
+  int64_t stored = 0, dense = 0;
+};
+
+static void pack_block(const BlockDesc& bd, const Fault& A, const Fault& B, std::vector<LagFactor>& lags,
+                       bool f32, int tail_off, BlockOut& out) {
+  const int p = bd.r1 - bd.r0, q = bd.s1 - bd.s0;
+  const int64_t target = f32 ? 65536 : 32768;  // elements per item
+  auto push = [&](double v) {
+    if (f32) out.d32.push_back((float)v);
+    else out.d64.push_back(v);
+  };
+  auto cur_size = [&]() -> int64_t { return f32 ? (int64_t)out.d32.size() : (int64_t)out.d64.size(); };
+  size_t i = 0;
+  while (i < lags.size()) {
+    const bool lr = lags[i].rank > 0;
+    const bool tail = lags[i].T < 0;
+    // gather a run of lags of the same kind within the limits
+    size_t j = i;
+    int64_t elems = 0;
+    int ncol = 0;
+    while (j < lags.size() && (lags[j].rank > 0) == lr && (lags[j].T < 0) == tail) {
+      const int nl = (int)(j - i) + 1;
+      const int64_t e = lr ? (int64_t)lags[j].rank * (p + q) : (int64_t)p * q;
+      if (j > i) {
+        if (tail) break;
+        if ((int64_t)nl * q > kHistMax) break;
+        if (lr && ncol + lags[j].rank > kColMax) break;
+        if (elems + e > target) break;
+      }
+      elems += e;
+      if (lr) ncol += lags[j].rank;
+      ++j;
+    }
+    Item it{};
+    it.data = cur_size();  // block-local, rebased later
+    it.kind = lr ? 0 : 1;
+    it.src = tail ? 1 : 0;
+    it.p = p;
+    it.q = q;
+    it.row0 = A.off + bd.r0;
+    it.col0 = B.off + bd.s0;
+    it.nlag = (int)(j - i);
+    it.lag_off = (int)out.lagT.size();
+    it.ncol = ncol;
+    it.tail_off = tail ? tail_off + bd.s0 : 0;
+    for (size_t l = i; l < j; ++l) out.lagT.push_back(lags[l].T);
+    if (lr) {
+      // column prefix
+      int c = 0;
+      out.lagCol.push_back(0);
+      for (size_t l = i; l < j; ++l) {
+        c += lags[l].rank;
+        out.lagCol.push_back(c);
+      }
+      // W panel [q][ncol]
+      for (int jj = 0; jj < q; ++jj)
+        for (size_t l = i; l < j; ++l)
+          for (int r = 0; r < lags[l].rank; ++r) push(lags[l].W[(size_t)r * q + jj]);
+      // U panel [ncol][p]
+      for (size_t l = i; l < j; ++l)
+        for (int r = 0; r < lags[l].rank; ++r)
+          for (int ii = 0; ii < p; ++ii) push(lags[l].U[(size_t)r * p + ii]);
+    } else {
+      for (int l = 0; l < it.nlag; ++l) out.lagCol.push_back(0);
+      out.lagCol.push_back(0);
+      for (size_t l = i; l < j; ++l)
+        for (int jj = 0; jj < q; ++jj)
+          for (int ii = 0; ii < p; ++ii) push(lags[l].D[(size_t)ii * q + jj]);
+    }
+    out.stored += elems;
+    out.items.push_back(it);
+    for (size_t l = i; l < j; ++l) {  // release
+      std::vector<double>().swap(lags[l].U);
+      std::vector<double>().swap(lags[l].W);
+      std::vector<double>().swap(lags[l].D);
+    }
+    i = j;
+  }
+}
+
+static void build_block(const HostOp& op, const BlockDesc& bd, const PairWin& pw, BlockOut& out) {
+  const Fault& A = op.faults[bd.a];
+  const Fault& B = op.faults[bd.b];
+  const int p = bd.r1 - bd.r0, q = bd.s1 - bd.s0;
+  const double cs = op.prm.cs, dt = op.dt;
+  const bool lowrank_ok = op.prm.compress && bd.adm;
+  // ranks above kmax are stored dense; one lag's columns must also fit the
+  // per-item LDS buffer of the device kernel
+  const int kmax = std::min<int>((int)(((int64_t)p * q) / (p + q)), kColMax);
+  if (q > kHistMax) throw Error(SEAS_ERR_INVALID_ARG, "a source cluster exceeds the LDS history capacity");
+  const PairFrame fr = frame(A, B);
+  // receiver offsets in the source frame, per (i, j)
+  std::vector<double> r1((size_t)p * q), r2((size_t)p * q);
+  for (int i = 0; i < p; ++i)
+    for (int j = 0; j < q; ++j) offsets(A, bd.r0 + i, B, bd.s0 + j, r1[(size_t)i * q + j], r2[(size_t)i * q + j]);
+  auto level = [&](int T, std::vector<double>& G) {  // spatial difference at t = T dt
+    const double ct = cs * (T * dt);
+    for (size_t e = 0; e < G.size(); ++e)
+      G[e] = corner(r1[e] + fr.h, r2[e], ct, fr.n1, fr.n2) - corner(r1[e] - fr.h, r2[e], ct, fr.n1, fr.n2);
+  };
+  std::vector<double> G0((size_t)p * q), G1((size_t)p * q), K((size_t)p * q), U, W, R;
+  std::vector<LagFactor> lags;
+  const int T_lo = std::max(1, pw.T_init), T_hi = pw.T_end;
+  out.dense += (int64_t)p * q * (pw.T_end - pw.T_init + 1);
+  if (T_hi >= T_lo) level(T_lo, G0);
+  for (int T = T_lo; T <= T_hi; ++T) {
+    level(T + 1, G1);
+    bool any = false;
+    for (size_t e = 0; e < K.size(); ++e) {
+      K[e] = G1[e] - G0[e];
+      any |= K[e] != 0.0;
+    }
+    std::swap(G0, G1);
+    if (!any) continue;
+    LagFactor lf;
+    lf.T = T;
+    lf.rank = 0;
+    if (lowrank_ok) {
+      const int k = aca_full(K.data(), p, q, op.prm.aca_tol, kmax, U, W, R);
+      if (k > 0) {
+        lf.rank = k;
+        // U is stored as k columns of length p, W as k columns of length q
+        lf.U = U;
+        lf.W = W;
+      }
+    }
+    if (lf.rank == 0) lf.D = K;
+    lags.push_back(std::move(lf));
+  }
+  int toff = 0;
+  if (op.prm.int_tail) {
+    // static tail: stress per unit expired slip, scaled by -1/eta so that the
+    // common -eta factor of the evaluation restores it
+    for (int i = 0; i < p; ++i)
+      for (int j = 0; j < q; ++j)
+        K[(size_t)i * q + j] = -static_stress(A, bd.r0 + i, B, bd.s0 + j, op.prm.mu) / op.eta;
+    LagFactor lf;
+    lf.T = -1;
+    lf.rank = 0;
+    if (lowrank_ok) {
+      const int k = aca_full(K.data(), p, q, op.prm.aca_tol, kmax, U, W, R);
+      if (k > 0) {
+        lf.rank = k;
+        lf.U = U;
+        lf.W = W;
+      }
+    }
+    if (lf.rank == 0) lf.D = K;
+    lags.push_back(std::move(lf));
+    toff = op.tail_off[bd.pair];
+  }
+  pack_block(bd, A, B, lags, op.prm.factor_dtype == SEAS_F32, toff, out);
+}
+
+// ============================================================== driver
+static void check_geometry(const std::vector<Fault>& F) {
+  for (size_t a = 0; a < F.size(); ++a)
+    for (size_t b = 0; b < F.size(); ++b) {
+      if (a == b) continue;
+      const Fault &A = F[a], &B = F[b];
+      for (int i = 0; i < A.Np; ++i)
+        for (int e = 0; e <= B.Np; ++e) {
+          const double s = -0.5 * B.L + e * B.dx;
+          const double d = std::hypot(A.midx(i) - (B.cx + s * B.tx), A.midy(i) - (B.cy + s * B.ty));
+          if (d < 1e-6 * B.dx)
+            throw Error(SEAS_ERR_INVALID_ARG, "a collocation point lies on another fault's element edge");
+        }
+    }
+}
+
+void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostOp& op,
+                std::vector<std::vector<double>>& bd64, std::vector<std::vector<float>>& bd32,
+                std::vector<int64_t>& block_arena_off) {
+  const auto t_start = std::chrono::steady_clock::now();
+  op.prm = prm;
+  if (nf < 1) throw Error(SEAS_ERR_INVALID_ARG, "n_faults must be >= 1");
+  if (!(prm.mu > 0) || !(prm.cs > 0) || !(prm.beta > 0) || prm.beta > 0.5 + 1e-12)
+    throw Error(SEAS_ERR_INVALID_ARG, "mu, cs must be > 0 and 0 < beta <= 1/2");
+  if (prm.leaf < 1 || !(prm.eta_H > 0) || !(prm.aca_tol > 0) || !(prm.eta_w > 0))
+    throw Error(SEAS_ERR_INVALID_ARG, "leaf >= 1, eta_H > 0, aca_tol > 0, eta_w > 0 required");
+  if (prm.factor_dtype != SEAS_F64 && prm.factor_dtype != SEAS_F32)
+    throw Error(SEAS_ERR_INVALID_ARG, "factor_dtype must be SEAS_F64 or SEAS_F32");
+  if (prm.n_threads > 0) omp_set_num_threads(prm.n_threads);
+  // ---- geometry
+  op.faults.clear();
+  int off = 0;
+  double dxmin = 1e300;
+  for (int k = 0; k < nf; ++k) {
+    const seas_fault_t& s = fin[k];
+    const double nn = std::hypot(s.nx, s.ny);
+    if (!(s.length > 0) || s.n_elem < 2 || !(nn > 0) || !std::isfinite(s.cx) || !std::isfinite(s.cy))
+      throw Error(SEAS_ERR_INVALID_ARG, "fault " + std::to_string(k) + ": bad length, n_elem, normal or centre");
+    Fault f;
+    f.cx = s.cx;
+    f.cy = s.cy;
+    f.nx = s.nx / nn;
+    f.ny = s.ny / nn;
+    f.tx = -f.ny;
+    f.ty = f.nx;
+    f.L = s.length;
+    f.Np = s.n_elem;
+    f.dx = f.L / f.Np;
+    f.off = off;
+    off += f.Np;
+    dxmin = std::min(dxmin, f.dx);
+    op.faults.push_back(f);
+  }
+  op.N = off;
+  op.dt = prm.beta * dxmin / prm.cs;
+  op.eta = prm.mu / (2.0 * prm.cs);
+  check_geometry(op.faults);
+  const double cs = prm.cs, dt = op.dt;
+  // ---- causality windows (Section 2.3.2, "Truncation of elastodynamic time-window")
+  op.pairs.clear();
+  op.max_lag = 0;
+  for (int a = 0; a < nf; ++a)
+    for (int b = 0; b < nf; ++b) {
+      if (a == b) continue;
+      const Fault &A = op.faults[a], &B = op.faults[b];
+      double earl = 1e300, dmax = 0.0;
+      for (int i = 0; i < A.Np; ++i)
+        for (int j = 0; j < B.Np; ++j) {
+          double r1, r2;
+          offsets(A, i, B, j, r1, r2);
+          const double r = std::hypot(r1, r2);
+          const double ta = (r1 > 0.0 ? std::min(r, std::fabs(r2)) : r) / cs;
+          earl = std::min(earl, ta);
+        }
+      for (int j = 0; j < B.Np; ++j)
+        for (int e = 0; e < 2; ++e) {
+          const double s = (e == 0 ? -0.5 : 0.5) * A.L;
+          dmax = std::max(dmax, std::hypot(B.midx(j) - (A.cx + s * A.tx), B.midy(j) - (A.cy + s * A.ty)));
+        }
+      PairWin w;
+      w.a = a;
+      w.b = b;
+      w.T_init = (int)std::floor((1.0 - prm.eta_tmin) * earl / dt);
+      w.T_end = (int)std::ceil((1.0 + prm.eta_tmax) * dmax / cs / dt);
+      op.pairs.push_back(w);
+      op.max_lag = std::max(op.max_lag, w.T_end);
+    }
+  op.ring_len = op.max_lag + 3;
+  // ---- partition
+  std::vector<std::vector<Node>> trees(nf);
+  for (int k = 0; k < nf; ++k) build_tree(op.faults[k], prm.leaf, trees[k]);
+  op.blocks.assign(op.pairs.size(), {});
+  std::vector<BlockDesc> all;
+  for (size_t pi = 0; pi < op.pairs.size(); ++pi) {
+    traverse(trees[op.pairs[pi].a], trees[op.pairs[pi].b], prm.eta_H, (int)pi, op.pairs[pi].a, op.pairs[pi].b,
+             op.blocks[pi]);
+    all.insert(all.end(), op.blocks[pi].begin(), op.blocks[pi].end());
+  }
+  // tail accumulators: one per (pair, source element)
+  op.tail_off.assign(op.pairs.size(), 0);
+  op.tail_len = 0;
+  for (size_t pi = 0; pi < op.pairs.size(); ++pi) {
+    op.tail_off[pi] = (int32_t)op.tail_len;
+    op.tail_len += op.faults[op.pairs[pi].b].Np;
+  }
+  // ---- lag-0 CSR (pairs whose window starts at lag 0)
+  {
+    std::vector<std::vector<std::pair<int, double>>> rows(op.N);
+    for (const PairWin& w : op.pairs) {
+      if (w.T_init != 0) continue;
+      const Fault &A = op.faults[w.a], &B = op.faults[w.b];
+      for (int i = 0; i < A.Np; ++i)
+        for (int j = 0; j < B.Np; ++j) {
+          const double k0 = kernel_entry(A, i, B, j, 0, dt, cs);
+          if (k0 != 0.0) rows[A.off + i].push_back({B.off + j, k0});
+        }
+    }
+    op.l0_ptr.assign(op.N + 1, 0);
+    op.l0_col.clear();
+    op.l0_val.clear();
+    for (int r = 0; r < op.N; ++r) {
+      for (auto& e : rows[r]) {
+        op.l0_col.push_back(e.first);
+        op.l0_val.push_back(e.second);
+      }
+      op.l0_ptr[r + 1] = (int32_t)op.l0_col.size();
+    }
+  }
+  // ---- blocks: evaluate, compress, pack (parallel over blocks, largest first)
+  std::vector<size_t> order(all.size());
+  std::iota(order.begin(), order.end(), 0);
+  auto cost = [&](const BlockDesc& b) {
+    const PairWin& w = op.pairs[b.pair];
+    return (double)(b.r1 - b.r0) * (b.s1 - b.s0) * (w.T_end - w.T_init + 1);
+  };
+  std::sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cost(all[x]) > cost(all[y]); });
+  std::vector<BlockOut> outs(all.size());
+  std::string err;
+  const bool verbose = std::getenv("SEAS_VERBOSE") != nullptr;
+  double total_cost = 0.0, done_cost = 0.0;
+  for (const auto& b : all) total_cost += cost(b);
+  int next_report = 1;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (size_t oi = 0; oi < order.size(); ++oi) {
+    const size_t bi = order[oi];
+    try {
+      build_block(op, all[bi], op.pairs[all[bi].pair], outs[bi]);
+    } catch (const std::exception& e) {
+#pragma omp critical
+      err = e.what();
+    }
+    if (verbose) {
+#pragma omp critical
+      {
+        done_cost += cost(all[bi]);
+        if (done_cost >= 0.1 * next_report * total_cost) {
+          std::fprintf(stderr, "[seas build] %d%% of block work done (%.0f s)\n", 10 * next_report,
+                       std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count());
+          std::fflush(stderr);
+          while (done_cost >= 0.1 * next_report * total_cost) ++next_report;
+        }
+      }
+    }
+  }
+  if (!err.empty()) throw Error(SEAS_ERR_INTERNAL, "block build failed: " + err);
+  // ---- global item list, arena offsets, partial layout
+  op.items.clear();
+  op.lagT.clear();
+  op.lagCol.clear();
+  op.lagColOff.clear();
+  op.arena_elems = 0;
+  op.n_partials = 0;
+  op.stored_entries = 0;
+  op.dense_entries = 0;
+  const bool f32 = prm.factor_dtype == SEAS_F32;
+  bd64.assign(all.size(), {});
+  bd32.assign(all.size(), {});
+  block_arena_off.assign(all.size(), 0);
+  for (size_t bi = 0; bi < all.size(); ++bi) {
+    BlockOut& bo = outs[bi];
+    block_arena_off[bi] = op.arena_elems;
+    const int lag_base = (int)op.lagT.size();
+    const int col_base = (int)op.lagCol.size();
+    // lagCol holds nlag+1 entries per item, in item order
+    int col_cursor = col_base;
+    for (Item it : bo.items) {
+      it.data += op.arena_elems;
+      it.part = (int32_t)op.n_partials;
+      op.n_partials += it.p;
+      op.lagColOff.push_back(col_cursor);
+      col_cursor += it.nlag + 1;
+      it.lag_off += lag_base;
+      op.items.push_back(it);
+    }
+    op.lagT.insert(op.lagT.end(), bo.lagT.begin(), bo.lagT.end());
+    op.lagCol.insert(op.lagCol.end(), bo.lagCol.begin(), bo.lagCol.end());
+    op.arena_elems += f32 ? (int64_t)bo.d32.size() : (int64_t)bo.d64.size();
+    op.stored_entries += bo.stored;
+    op.dense_entries += bo.dense;
+    if (f32) bd32[bi].swap(bo.d32);
+    else bd64[bi].swap(bo.d64);
+  }
+  if (op.n_partials > INT32_MAX || (int64_t)op.lagT.size() > INT32_MAX)
+    throw Error(SEAS_ERR_INTERNAL, "operator too large for 32-bit item offsets");
+  // reduction lists: partial indices per receiver, in item order
+  op.red_ptr.assign(op.N + 1, 0);
+  for (const Item& it : op.items)
+    for (int i = 0; i < it.p; ++i) op.red_ptr[it.row0 + i + 1]++;
+  for (int r = 0; r < op.N; ++r) op.red_ptr[r + 1] += op.red_ptr[r];
+  op.red_idx.assign(op.red_ptr[op.N], 0);
+  {
+    std::vector<int32_t> cur(op.red_ptr.begin(), op.red_ptr.end() - 1);
+    for (const Item& it : op.items)
+      for (int i = 0; i < it.p; ++i) op.red_idx[cur[it.row0 + i]++] = it.part + i;
+  }
+  // ---- self term (Section 2.3.1): windows, tables shared by identical faults
+  op.self.clear();
+  op.self_tab.clear();
+  op.self_ring_len = 0;
+  op.n_modes = 0;
+  op.max_self_W = 0;
+  op.self_entries = 0;
+  struct Key {
+    int Np;
+    double L;
+  };
+  std::vector<std::pair<Key, size_t>> seen;
+  for (int k = 0; k < nf; ++k) {
+    const Fault& f = op.faults[k];
+    SelfFault sf;
+    sf.Np = f.Np;
+    sf.M = 2 * f.Np;
+    sf.nm = prm.mode_cap > 0 ? std::min(prm.mode_cap, f.Np) : f.Np;
+    sf.mode_off = op.n_modes;
+    op.n_modes += sf.nm;
+    sf.cfac = prm.mu * prm.cs * M_PI / (2.0 * f.L);
+    const int qw = prm.q_w > 0 ? prm.q_w : (int)std::lround(f.Np / 5.0);
+    sf.W.resize(sf.nm);
+    for (int n = 1; n <= sf.nm; ++n) {
+      double Ln = 1.0;
+      if (f.Np / 2.0 - 1.0 > 0.0) Ln = 1.0 / n + (qw - 1.0) / (f.Np / 2.0 - 1.0) * (1.0 - 1.0 / n);
+      sf.W[n - 1] = (int)std::floor(prm.eta_w * (f.L / prm.cs) * Ln / dt * (1.0 + 1e-12));
+      op.max_self_W = std::max(op.max_self_W, sf.W[n - 1]);
+      op.self_entries += sf.W[n - 1] + 1;
+    }
+    sf.ring_off.resize(sf.nm);
+    for (int n = 0; n < sf.nm; ++n) {
+      sf.ring_off[n] = op.self_ring_len;
+      op.self_ring_len += sf.W[n];
+    }
+    size_t reuse = SIZE_MAX;
+    for (auto& s : seen)
+      if (s.first.Np == f.Np && s.first.L == f.L) reuse = s.second;
+    if (reuse != SIZE_MAX && op.self[reuse].W == sf.W) {
+      sf.tab_off = op.self[reuse].tab_off;
+    } else {
+      sf.tab_off.resize(sf.nm);
+      int64_t base = (int64_t)op.self_tab.size();
+      for (int n = 0; n < sf.nm; ++n) {
+        sf.tab_off[n] = base;
+        base += sf.W[n] + 1;
+      }
+      op.self_tab.resize(base);
+#pragma omp parallel for schedule(dynamic, 1)
+      for (int n = 1; n <= sf.nm; ++n) {
+        double* o = &op.self_tab[sf.tab_off[n - 1]];
+        self_cells(n, sf.W[n - 1], dt, f.L, prm.cs, o);
+        const double kn = M_PI * n / f.L;
+        for (int T = 0; T <= sf.W[n - 1]; ++T) o[T] *= kn;
+      }
+      seen.push_back({{f.Np, f.L}, op.self.size()});
+    }
+    op.self.push_back(sf);
+  }
+  op.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+}
+
+}  // namespace seas

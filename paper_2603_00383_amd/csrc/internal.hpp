@@ -1,0 +1,117 @@
+// Internal declarations of the stress-transfer library (host and device).
+#pragma once
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "seas.h"
+
+namespace seas {
+
+struct Error : std::runtime_error {
+  seas_status code;
+  Error(seas_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+// ---------------------------------------------------------------- geometry
+struct Fault {
+  double cx, cy, nx, ny;  // centroid, unit normal e2'
+  double tx, ty;          // tangent e1' = e3 x e2' = (-ny, nx)
+  double L, dx;           // length, element size
+  int Np, off;            // elements, global index of the first one
+  double midx(int j) const { return cx + (-0.5 * L + (j + 0.5) * dx) * tx; }
+  double midy(int j) const { return cy + (-0.5 * L + (j + 0.5) * dx) * ty; }
+};
+
+// ---------------------------------------------------------------- device work items
+// One work item of the per-step interaction evaluation: a run of lags of one
+// H-matrix block, all low-rank or all dense, whose factors are contiguous in the
+// factor arena starting at `data`.
+//   low rank (kind 0): W panel [q][ncol] (column fastest), then U panel [ncol][p]
+//   dense    (kind 1): [nlag][q][p] (row fastest)
+// The history row of lag T is the ring slot of time (head - T); src = 1 marks the
+// static-tail item whose single "history row" is the expired-slip accumulator of
+// its pair (at tail_off).
+struct Item {
+  int64_t data;      // element offset in the factor arena
+  int32_t kind;      // 0 low rank, 1 dense
+  int32_t src;       // 0 ring, 1 tail accumulator
+  int32_t p, q;      // block rows (receivers) and columns (sources)
+  int32_t row0;      // global receiver index of the block's first row
+  int32_t col0;      // global source index of the block's first column
+  int32_t nlag;      // lags in this item
+  int32_t lag_off;   // offset in the lag arrays (T values; column prefix for low rank)
+  int32_t ncol;      // total rank columns (low rank)
+  int32_t part;      // offset of this item's p partial sums
+  int32_t tail_off;  // offset of the pair's accumulator (src = 1)
+  int32_t pad;
+};
+static_assert(sizeof(Item) == 56, "Item layout");
+
+constexpr int kItemThreads = 256;
+constexpr int kHistMax = 6144;   // max nlag*q history values staged in LDS per item
+constexpr int kColMax = 1024;    // max low-rank columns per item
+
+// ---------------------------------------------------------------- host operator
+struct PairWin {
+  int a, b, T_init, T_end;
+};
+
+struct BlockDesc {
+  int pair, a, b, r0, r1, s0, s1, adm;
+};
+
+struct SelfFault {          // self-term tables of one fault
+  int Np, M, nm;            // elements, padded length, retained modes
+  int mode_off;             // global offset of this fault's modes (1..nm)
+  std::vector<int> W;       // W_n, n = 1..nm
+  std::vector<int64_t> tab_off;   // offset of K_n^T (T = 0..W_n) in the table
+  std::vector<int64_t> ring_off;  // offset of the D ring of mode n (length W_n)
+  double cfac;              // mu cs pi / (2 L): F_n = -cfac * n * sum K_n^T D
+};
+
+struct HostOp {
+  seas_params_t prm;
+  std::vector<Fault> faults;
+  int N = 0;
+  double dt = 0, eta = 0;
+  std::vector<PairWin> pairs;
+  std::vector<std::vector<BlockDesc>> blocks;  // per pair
+  // work items
+  std::vector<Item> items;
+  std::vector<int32_t> lagT;     // per item: nlag lag values
+  std::vector<int32_t> lagCol;   // per item: nlag+1 column prefix (low rank) (same offset as lagT + item index)
+  std::vector<int32_t> lagColOff;// per item: offset into lagCol
+  int64_t arena_elems = 0;
+  int64_t n_partials = 0;
+  std::vector<int32_t> red_ptr;  // N+1
+  std::vector<int32_t> red_idx;  // partial indices per receiver
+  std::vector<int32_t> tail_off; // per pair: offset of its accumulator; total tail_len
+  int64_t tail_len = 0;
+  // lag-0 CSR (FP64)
+  std::vector<int32_t> l0_ptr, l0_col;
+  std::vector<double> l0_val;
+  // self term
+  std::vector<SelfFault> self;
+  std::vector<double> self_tab;  // K_n^T, all faults
+  int64_t self_ring_len = 0;     // complex entries over all rings
+  int n_modes = 0;               // total modes over faults
+  int max_lag = 0, max_self_W = 0, ring_len = 0;
+  // stats
+  int64_t dense_entries = 0, stored_entries = 0, self_entries = 0;
+  double build_seconds = 0;
+};
+
+// host build (build.cpp)
+void build_host(const seas_fault_t* f, int nf, const seas_params_t& prm, HostOp& op,
+                std::vector<std::vector<double>>& block_data_f64,
+                std::vector<std::vector<float>>& block_data_f32,
+                std::vector<int64_t>& block_arena_off);
+
+double kernel_entry(const Fault& A, int i, const Fault& B, int j, int T, double dt, double cs);
+double static_stress(const Fault& A, int i, const Fault& B, int j, double mu);
+void self_cells(int n, int W, double dt, double L, double cs, double* out);
+
+}  // namespace seas

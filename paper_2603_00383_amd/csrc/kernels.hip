@@ -1,0 +1,373 @@
+// HIP kernels of the per-step stress evaluation and friction update (gfx950).
+//
+// One predictor-corrector step (Section 2.4) on one stream:
+//   k_hmat        interaction history part (lags >= 1 and the static tail): every
+//                 work item (a run of lags of one H-matrix block) streams its
+//                 factors once, with the slip-rate history rows of its lags staged
+//                 in LDS; one partial sum per receiver row
+//   k_reduce      fixed-order sum of each receiver's partials, times -mu/(2cs)
+//   k_self_hist   per-mode time convolution over lags T >= 1 (ragged windows)
+//   k_dft         explicit transform of the predicted / corrected slip, modal stress
+//   k_stage       inverse transform per element, Newton solve in ln V, state
+//                 update; the corrector commits the step and appends the histories
+// Every reduction has a fixed order (no floating-point atomics).
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace seas {
+
+__device__ __forceinline__ int64_t ring_slot(int64_t t, int64_t R) {
+  int64_t s = t % R;
+  return s < 0 ? s + R : s;
+}
+
+// ------------------------------------------------------------------ H-matrix apply
+// y_i = sum_e M[e*p + i] x[e], e in [0, E), for the p rows of an item. The block's
+// threads form G = 256/p groups of p consecutive rows (coalesced row reads); group
+// g takes a contiguous range of e; the G partial rows are added in group order.
+template <typename TF, typename TA>
+__device__ __forceinline__ void rows_accumulate(const TF* __restrict__ M, const TA* __restrict__ x, int E, int p,
+                                                TA* red, double* __restrict__ out) {
+  const int tid = threadIdx.x;
+  if (p <= kItemThreads) {
+    const int G = kItemThreads / p;
+    const int g = tid / p, i = tid - g * p;
+    TA acc = 0;
+    if (g < G) {
+      const int e0 = (int)((int64_t)E * g / G), e1 = (int)((int64_t)E * (g + 1) / G);
+      const TF* m = M + (int64_t)e0 * p + i;
+      int e = e0;
+      TA a1 = 0, a2 = 0, a3 = 0;
+      for (; e + 4 <= e1; e += 4, m += 4 * p) {
+        acc += (TA)m[0] * x[e];
+        a1 += (TA)m[p] * x[e + 1];
+        a2 += (TA)m[2 * p] * x[e + 2];
+        a3 += (TA)m[3 * p] * x[e + 3];
+      }
+      for (; e < e1; ++e, m += p) acc += (TA)m[0] * x[e];
+      acc = (acc + a1) + (a2 + a3);
+    }
+    red[tid] = acc;
+    __syncthreads();
+    if (tid < p) {
+      TA s = 0;
+      for (int gg = 0; gg < G; ++gg) s += red[gg * p + tid];
+      out[tid] = (double)s;
+    }
+  } else {
+    for (int i = tid; i < p; i += kItemThreads) {
+      TA acc = 0;
+      const TF* m = M + i;
+      for (int e = 0; e < E; ++e, m += p) acc += (TA)m[0] * x[e];
+      out[i] = (double)acc;
+    }
+  }
+}
+
+template <typename TF, typename TA>
+__global__ __launch_bounds__(kItemThreads) void k_hmat(const Item* __restrict__ items, const int32_t* __restrict__ lagT,
+                                                       const int32_t* __restrict__ lagCol,
+                                                       const int32_t* __restrict__ lagColOff,
+                                                       const TF* __restrict__ arena, const TF* __restrict__ ring,
+                                                       int64_t head, int64_t R, int N,
+                                                       const double* __restrict__ tail_acc,
+                                                       double* __restrict__ partials) {
+  __shared__ TA h[kHistMax];
+  __shared__ TA z[kColMax];
+  __shared__ int collag[kColMax];
+  __shared__ TA red[kItemThreads];
+  const Item it = items[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int q = it.q, p = it.p, nl = it.nlag;
+  if (it.src == 0) {
+    for (int l = 0; l < nl; ++l) {
+      const int64_t slot = ring_slot(head - lagT[it.lag_off + l], R);
+      const TF* row = ring + slot * N + it.col0;
+      for (int j = tid; j < q; j += kItemThreads) h[l * q + j] = (TA)row[j];
+    }
+  } else {
+    for (int j = tid; j < q; j += kItemThreads) h[j] = (TA)tail_acc[it.tail_off + j];
+  }
+  double* out = partials + it.part;
+  const TF* base = arena + it.data;
+  if (it.kind == 0) {
+    const int nc = it.ncol;
+    const int32_t* cp = lagCol + lagColOff[blockIdx.x];
+    for (int l = 0; l < nl; ++l)
+      for (int c = cp[l] + tid; c < cp[l + 1]; c += kItemThreads) collag[c] = l;
+    __syncthreads();
+    // projection z_c = w_c . h_{lag(c)}; W panel [q][nc], one thread per column
+    for (int c = tid; c < nc; c += kItemThreads) {
+      const TA* hl = h + collag[c] * q;
+      const TF* w = base + c;
+      TA acc = 0, a1 = 0;
+      int j = 0;
+      for (; j + 2 <= q; j += 2) {
+        acc += (TA)w[(int64_t)j * nc] * hl[j];
+        a1 += (TA)w[(int64_t)(j + 1) * nc] * hl[j + 1];
+      }
+      if (j < q) acc += (TA)w[(int64_t)j * nc] * hl[j];
+      z[c] = acc + a1;
+    }
+    __syncthreads();
+    // expansion y = U z; U panel [nc][p]
+    rows_accumulate<TF, TA>(base + (int64_t)q * nc, z, nc, p, red, out);
+  } else {
+    __syncthreads();
+    rows_accumulate<TF, TA>(base, h, nl * q, p, red, out);
+  }
+}
+
+__global__ void k_reduce(const double* __restrict__ partials, const int32_t* __restrict__ ptr,
+                         const int32_t* __restrict__ idx, int N, double neg_eta, double* __restrict__ f) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N) return;
+  double s = 0.0;
+  for (int k = ptr[r]; k < ptr[r + 1]; ++k) s += partials[idx[k]];
+  f[r] = neg_eta * s;
+}
+
+// ------------------------------------------------------------------ self term
+// One 64-lane wave per mode: Fh_n = sum_{T=1}^{W_n} K_n^T D_n^{time0 - T}, where
+// time0 is the time of the coefficient being formed; butterfly sum over lanes.
+__global__ void k_self_hist(const SelfMode* __restrict__ modes, int n_modes, const double* __restrict__ tab,
+                            const double2* __restrict__ dring, int64_t time0, double2* __restrict__ Fh) {
+  const int lane = threadIdx.x & 63;
+  const int gm = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (gm >= n_modes) return;
+  const SelfMode md = modes[gm];
+  double re = 0.0, im = 0.0;
+  for (int T = 1 + lane; T <= md.W; T += 64) {
+    const double k = tab[md.tab + T];
+    const double2 d = dring[md.ring + ring_slot(time0 - T, md.W)];
+    re += k * d.x;
+    im += k * d.y;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    re += __shfl_xor(re, o, 64);
+    im += __shfl_xor(im, o, 64);
+  }
+  if (lane == 0) Fh[gm] = make_double2(re, im);
+}
+
+// D_n = sum_j x_j e^{-2 pi i n j / M}, x = delta + coef * vel (vel may be null);
+// F_n = -cfac n (K_n^0 D_n + Fh_n); optionally D_n is stored in the mode's ring at
+// push_time, which must lie in the window (ring_head - W_n, ring_head] of the
+// ring's newest time ring_head (older times would overwrite newer slots).
+__global__ void k_dft(const SelfMode* __restrict__ modes, int n_modes, const SelfFaultDev* __restrict__ sf,
+                      const double* __restrict__ delta, const double* __restrict__ vel, double coef,
+                      const double2* __restrict__ tw, const double* __restrict__ tab,
+                      const double2* __restrict__ Fh, double2* __restrict__ Dout, double2* __restrict__ Fout,
+                      double2* __restrict__ dring, int push, int64_t push_time, int64_t ring_head) {
+  const int gm = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gm >= n_modes) return;
+  const SelfMode md = modes[gm];
+  const SelfFaultDev f = sf[md.fault];
+  const double2* w = tw + f.tw;
+  double re = 0.0, im = 0.0;
+  int idx = 0;
+  for (int j = 0; j < f.Np; ++j) {
+    const double x = vel ? delta[f.off + j] + coef * vel[f.off + j] : delta[f.off + j];
+    const double2 e = w[idx];
+    re += x * e.x;
+    im += x * e.y;
+    idx += md.n;
+    if (idx >= f.M) idx -= f.M;
+  }
+  const double k0 = tab[md.tab];
+  const double c = -f.cfac * md.n;
+  if (Dout) Dout[gm] = make_double2(re, im);
+  const double2 fh = Fh ? Fh[gm] : make_double2(0.0, 0.0);
+  Fout[gm] = make_double2(c * (k0 * re + fh.x), c * (k0 * im + fh.y));
+  if (push && md.W > 0 && push_time > ring_head - md.W)
+    dring[md.ring + ring_slot(push_time, md.W)] = make_double2(re, im);
+}
+
+// f_j = (1/M) [2 Re sum_{n=1}^{N_p-1} F_n e^{+2 pi i n j/M} + Re F_{N_p} (-1)^j]  (F_0 = 0)
+__device__ __forceinline__ double idft_elem(const SelfFaultDev& f, const double2* __restrict__ F,
+                                            const double2* __restrict__ w, int j) {
+  double s = 0.0;
+  const int ntop = f.nm < f.Np ? f.nm : f.Np - 1;
+  int idx = 0;
+  for (int n = 1; n <= ntop; ++n) {
+    idx += j;
+    if (idx >= f.M) idx -= f.M;
+    const double2 e = w[idx];  // e^{-i...}: Re(F e^{+i...}) = F.x e.x + F.y e.y
+    const double2 Fn = F[n - 1];
+    s += Fn.x * e.x + Fn.y * e.y;
+  }
+  s *= 2.0;
+  if (f.nm >= f.Np) s += F[f.Np - 1].x * ((j & 1) ? -1.0 : 1.0);
+  return s / f.M;
+}
+
+__device__ __forceinline__ double lag0_apply(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                             const double* __restrict__ val, const double* __restrict__ x, int r) {
+  double s = 0.0;
+  for (int k = ptr[r]; k < ptr[r + 1]; ++k) s += val[k] * x[col[k]];
+  return s;
+}
+
+__device__ __forceinline__ double state_rate(double V, double th, double Dc, double eps) {
+  const double r = V * th / Dc;
+  if (eps == 1.0) return 1.0 - r;
+  return (pow(r, -eps) - 1.0) * r / eps;
+}
+
+// Newton on x = ln V for A - eta V = sigma_n [f0 + a (x - ln V0) + b ln(V0 theta / Dc)];
+// steps clamped to |dx| <= 5, stop at |dx| <= 1e-14 max(1, |x|), at most 50 iterations.
+__device__ double newton_lnV(double A, double th, double eta, double a, double b, double Dc, double sn, double V0,
+                             double f0, double x, int* fail) {
+  const double c = sn * (f0 - a * log(V0) + b * log(V0 * th / Dc));
+  for (int it = 0; it < 50; ++it) {
+    const double ex = exp(x);
+    const double g = A - eta * ex - c - sn * a * x;
+    const double dg = -eta * ex - sn * a;
+    double dx = -g / dg;
+    dx = fmin(5.0, fmax(-5.0, dx));
+    x += dx;
+    if (!(fabs(dx) > 1e-14 * fmax(1.0, fabs(x)))) return exp(x);
+  }
+  *fail = 1;
+  return exp(x);
+}
+
+// Expired-slip accumulators of the pairs whose source is element r's fault:
+// E += dt V^{t}, t = time_new - T_end - 1 (the rate that just left the window).
+template <typename TF>
+__device__ __forceinline__ void tail_update(const StepArgs<TF>& a, int r, int k, int j) {
+  for (int e = a.src_pairs_ptr[k]; e < a.src_pairs_ptr[k + 1]; ++e) {
+    const int toff = a.src_pairs[2 * e], Tend = a.src_pairs[2 * e + 1];
+    const int64_t t = a.time_new - Tend - 1;
+    if (t >= a.first) a.tail_acc[toff + j] += a.dt * a.ring64[ring_slot(t, a.R) * a.N + r];
+  }
+}
+
+template <typename TF>
+__global__ void k_stage(StepArgs<TF> a, int stage) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= a.N) return;
+  const int k = a.fault_of[r];
+  const SelfFaultDev f = a.sf[k];
+  const int j = r - f.off;
+  const double fself = idft_elem(f, a.F + f.mode_off, a.tw + f.tw, j);
+  const double tau0 = a.tau0[r] + a.tau0_rate[r] * a.t_next;
+  const Friction& fr = a.fric;
+  if (stage == 0) {  // predictor: delta*, theta* from the current rates
+    const double V = a.V[r];
+    const double th_s = a.theta[r] + a.dt * a.thdot[r];
+    const double fint = a.f_hist[r] - a.eta * lag0_apply(a.l0_ptr, a.l0_col, a.l0_val, a.V, r);
+    const double Vs = newton_lnV(tau0 + fself + fint, th_s, a.eta, fr.a[r], fr.b[r], fr.Dc[r], fr.sn[r], fr.V0[r],
+                                 fr.f0[r], log(V), a.fail);
+    const double tds = state_rate(Vs, th_s, fr.Dc[r], fr.eps[r]);
+    a.Vstar[r] = Vs;
+    a.Vbar[r] = 0.5 * (V + Vs);
+    a.th2[r] = a.theta[r] + a.dt * 0.5 * (a.thdot[r] + tds);
+  } else {  // corrector with the averaged rates; only the lag-0 terms change
+    const double Vb = a.Vbar[r];
+    const double th2 = a.th2[r];
+    const double fint = a.f_hist[r] - a.eta * lag0_apply(a.l0_ptr, a.l0_col, a.l0_val, a.Vbar, r);
+    const double V2 = newton_lnV(tau0 + fself + fint, th2, a.eta, fr.a[r], fr.b[r], fr.Dc[r], fr.sn[r], fr.V0[r],
+                                 fr.f0[r], log(a.Vstar[r]), a.fail);
+    const double td2 = state_rate(V2, th2, fr.Dc[r], fr.eps[r]);
+    // commit: no other element reads V, theta, thdot or delta in this pass
+    a.delta[r] += a.dt * Vb;
+    a.theta[r] = th2;
+    a.thdot[r] = td2;
+    a.V[r] = V2;
+    a.f_self_out[r] = fself;
+    a.f_int_out[r] = fint;
+    const int64_t slot = ring_slot(a.time_new, a.R);
+    a.ring64[slot * a.N + r] = V2;
+    if ((void*)a.ringop != (void*)a.ring64) a.ringop[slot * a.N + r] = (TF)V2;
+    if (a.tail) tail_update(a, r, k, j);
+  }
+}
+
+// Prescribed mode, before the evaluation of step n: append V^{n-1}, advance slip.
+template <typename TF>
+__global__ void k_pre_push(StepArgs<TF> a, const double* __restrict__ Vin) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= a.N) return;
+  const double v = Vin[r];
+  const int64_t slot = ring_slot(a.time_new, a.R);
+  a.ring64[slot * a.N + r] = v;
+  if ((void*)a.ringop != (void*)a.ring64) a.ringop[slot * a.N + r] = (TF)v;
+  a.delta[r] += a.dt * v;
+  if (a.tail) {
+    const int k = a.fault_of[r];
+    tail_update(a, r, k, r - a.sf[k].off);
+  }
+}
+
+// Prescribed mode output: f^n = f_self + f_hist - mu/(2cs) K^0 V^{n-1}.
+template <typename TF>
+__global__ void k_pre_out(StepArgs<TF> a, const double* __restrict__ Vprev, double* __restrict__ fout) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= a.N) return;
+  const int k = a.fault_of[r];
+  const SelfFaultDev f = a.sf[k];
+  const double fself = idft_elem(f, a.F + f.mode_off, a.tw + f.tw, r - f.off);
+  fout[r] = fself + a.f_hist[r] - a.eta * lag0_apply(a.l0_ptr, a.l0_col, a.l0_val, Vprev, r);
+}
+
+// ------------------------------------------------------------------ launchers
+static inline int blocks_for(int64_t n, int t) { return (int)((n + t - 1) / t); }
+
+void launch_hmat(const HostOp& h, const void* items, const int32_t* lagT, const int32_t* lagCol,
+                 const int32_t* lagColOff, const void* arena, const void* ring, int64_t head,
+                 const double* tail_acc, double* partials, hipStream_t s) {
+  const int n = (int)h.items.size();
+  if (n == 0) return;
+  if (h.prm.factor_dtype == SEAS_F64)
+    hipLaunchKernelGGL((k_hmat<double, double>), dim3(n), dim3(kItemThreads), 0, s, (const Item*)items, lagT,
+                       lagCol, lagColOff, (const double*)arena, (const double*)ring, head, (int64_t)h.ring_len, h.N,
+                       tail_acc, partials);
+  else
+    hipLaunchKernelGGL((k_hmat<float, float>), dim3(n), dim3(kItemThreads), 0, s, (const Item*)items, lagT, lagCol,
+                       lagColOff, (const float*)arena, (const float*)ring, head, (int64_t)h.ring_len, h.N, tail_acc,
+                       partials);
+}
+
+void launch_reduce(const HostOp& h, const double* partials, const int32_t* ptr, const int32_t* idx, double* f,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3(blocks_for(h.N, 256)), dim3(256), 0, s, partials, ptr, idx, h.N, -h.eta, f);
+}
+
+void launch_self_hist(int n_modes, const SelfMode* modes, const double* tab, const double2* dring, int64_t time0,
+                      double2* Fh, hipStream_t s) {
+  hipLaunchKernelGGL(k_self_hist, dim3(blocks_for(n_modes, 4)), dim3(256), 0, s, modes, n_modes, tab, dring, time0,
+                     Fh);
+}
+
+void launch_dft(int n_modes, const SelfMode* modes, const SelfFaultDev* sf, const double* delta, const double* vel,
+                double coef, const double2* tw, const double* tab, const double2* Fh, double2* Dout, double2* Fout,
+                double2* dring, int push, int64_t push_time, int64_t ring_head, hipStream_t s) {
+  hipLaunchKernelGGL(k_dft, dim3(blocks_for(n_modes, 64)), dim3(64), 0, s, modes, n_modes, sf, delta, vel, coef, tw,
+                     tab, Fh, Dout, Fout, dring, push, push_time, ring_head);
+}
+
+template <typename TF>
+void launch_stage(const StepArgs<TF>& a, int stage, hipStream_t s) {
+  hipLaunchKernelGGL((k_stage<TF>), dim3(blocks_for(a.N, 128)), dim3(128), 0, s, a, stage);
+}
+
+template <typename TF>
+void launch_prescribed_push(const StepArgs<TF>& a, const double* Vin, hipStream_t s) {
+  hipLaunchKernelGGL((k_pre_push<TF>), dim3(blocks_for(a.N, 256)), dim3(256), 0, s, a, Vin);
+}
+
+template <typename TF>
+void launch_prescribed_out(const StepArgs<TF>& a, const double* Vprev, double* fout, hipStream_t s) {
+  hipLaunchKernelGGL((k_pre_out<TF>), dim3(blocks_for(a.N, 128)), dim3(128), 0, s, a, Vprev, fout);
+}
+
+template void launch_stage<double>(const StepArgs<double>&, int, hipStream_t);
+template void launch_stage<float>(const StepArgs<float>&, int, hipStream_t);
+template void launch_prescribed_push<double>(const StepArgs<double>&, const double*, hipStream_t);
+template void launch_prescribed_push<float>(const StepArgs<float>&, const double*, hipStream_t);
+template void launch_prescribed_out<double>(const StepArgs<double>&, const double*, double*, hipStream_t);
+template void launch_prescribed_out<float>(const StepArgs<float>&, const double*, double*, hipStream_t);
+
+}  // namespace seas

@@ -1,0 +1,75 @@
+// Device-side structures shared by the kernels and their host launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+
+namespace seas {
+
+struct SelfMode {      // one retained mode of one fault
+  int fault, n, W;     // fault index, mode number (1..), window W_n
+  int pad;
+  int64_t tab;         // offset of K_n^T, T = 0..W_n
+  int64_t ring;        // offset of the mode's coefficient ring (W_n entries)
+};
+
+struct SelfFaultDev {
+  int off, Np, M, nm;  // first element, elements, 2 Np, retained modes
+  int mode_off;        // first global mode index
+  int tw;              // offset of the fault's twiddle table (M entries)
+  double cfac;         // mu cs pi / (2 L)
+};
+
+struct Friction {
+  const double *a, *b, *Dc, *sn, *V0, *f0, *eps;
+};
+
+// Arguments of the element kernels (predictor, corrector, prescribed output).
+template <typename TF>
+struct StepArgs {
+  int N;
+  double dt, eta, t_next;
+  const int* fault_of;
+  const SelfFaultDev* sf;
+  const double2* tw;
+  const double2* F;          // modal stress of the current stage
+  const double* f_hist;      // interaction history part
+  const int32_t *l0_ptr, *l0_col;
+  const double* l0_val;
+  const double *tau0, *tau0_rate;
+  Friction fric;
+  double *V, *theta, *thdot, *delta;
+  double *Vstar, *Vbar, *th2;
+  double *f_self_out, *f_int_out;
+  int* fail;
+  // history append (corrector)
+  double* ring64;
+  TF* ringop;               // operand copy (== ring64 for FP64 factors)
+  int64_t R, time_new;      // ring length, time of the appended row
+  // expired-slip accumulators
+  double* tail_acc;
+  const int32_t* src_pairs;     // per fault: list of (pair tail offset, T_end) for pairs with that source
+  const int32_t* src_pairs_ptr; // per fault: range in src_pairs (pairs of 2 ints)
+  int64_t first;            // earliest time held in the histories
+  int tail;                 // static tail on
+};
+
+void launch_hmat(const HostOp& h, const void* items, const int32_t* lagT, const int32_t* lagCol,
+                 const int32_t* lagColOff, const void* arena, const void* ring, int64_t head,
+                 const double* tail_acc, double* partials, hipStream_t s);
+void launch_reduce(const HostOp& h, const double* partials, const int32_t* ptr, const int32_t* idx, double* f,
+                   hipStream_t s);
+void launch_self_hist(int n_modes, const SelfMode* modes, const double* tab, const double2* dring, int64_t time0,
+                      double2* Fh, hipStream_t s);
+void launch_dft(int n_modes, const SelfMode* modes, const SelfFaultDev* sf, const double* delta, const double* vel,
+                double coef, const double2* tw, const double* tab, const double2* Fh, double2* Dout, double2* Fout,
+                double2* dring, int push, int64_t push_time, int64_t ring_head, hipStream_t s);
+template <typename TF>
+void launch_stage(const StepArgs<TF>& a, int stage, hipStream_t s);
+template <typename TF>
+void launch_prescribed_push(const StepArgs<TF>& a, const double* Vin, hipStream_t s);
+template <typename TF>
+void launch_prescribed_out(const StepArgs<TF>& a, const double* Vprev, double* fout, hipStream_t s);
+
+}  // namespace seas

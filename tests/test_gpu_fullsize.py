@@ -1,0 +1,74 @@
+"""Full-size parity at the benchmark's configuration (five 600-element faults,
+FP32 factors, ACA 1e-6, eta_H 2, leaf 50, saturated history windows).
+
+The oracle cannot evaluate all 3000 receivers at every lag in seconds, so it is
+compared on sampled receivers (kernel rows evaluated on the fly) at the same
+steps.  Tolerance: 1e-4 relative (FP32 factors with FP32 accumulation per work
+item; ACA 1e-6)."""
+import numpy as np
+import pytest
+
+import seas_inputs as SI
+from oracle import interaction as OI
+from oracle import seas as OS
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_2603_00383_amd")
+
+ROWS = [0, 37, 301, 599, 600, 899, 1200, 1511, 1799, 1800, 2222, 2400, 2650, 2999]
+
+
+@pytest.fixture(scope="module")
+def fullsize():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    faults = SI.five_fault_network(seed=0)
+    params = SI.default_params(factor_dtype="f32", aca_tol=1e-6, eta_H=2.0, leaf=50)
+    print("[gpu] building the five-fault operator", flush=True)
+    op = P.Operator(faults, params)
+    prior = SI.saturated_history(faults, op.info["max_lag"] + 2, 0)
+    print(f"[gpu] built: items={op.info['n_items']} max_lag={op.info['max_lag']}", flush=True)
+    oracle = OS.Problem(faults, params, dense=False)
+    return faults, params, op, prior, oracle
+
+
+def test_fullsize_prescribed_sampled(fullsize):
+    faults, params, op, prior, oracle = fullsize
+    N = op.N
+    s = torch.cuda.current_stream().cuda_stream
+    fr = SI.rate_state_fields(faults)
+    st = P.State(op, fr, np.full(N, 1e-9), np.full(N, 5e6), np.zeros(N), stream=s)
+    st.load_history(prior, stream=s)
+    V = SI.saturated_history(faults, 3, 1)
+    Vd = torch.from_numpy(V).cuda()
+    fd = torch.empty_like(Vd)
+    st.eval_prescribed(Vd, 3, fd, stream=s)
+    torch.cuda.synchronize()
+    f = fd.cpu().numpy()
+    Vall = np.concatenate([prior, V])
+    first = -len(prior)
+    for n in (1, 3):
+        ref = OS.prescribed_rows(oracle, Vall, first, n, ROWS)
+        e = np.abs(f[n - 1, ROWS] - ref).max() / np.abs(ref).max()
+        print(f"[gpu] full-size prescribed step {n}: sampled rel err {e:.3e}", flush=True)
+        assert e < 1e-4
+
+
+def test_fullsize_seas_step_history_part(fullsize):
+    faults, params, op, prior, oracle = fullsize
+    s = torch.cuda.current_stream().cuda_stream
+    fric = SI.rate_state_fields(faults)
+    ini = SI.near_nucleation_state(faults, fric, seed=0, bump_amp=0.05)
+    st = P.State(op, fric, ini["V"], ini["theta"], ini["tau0"], ini["tau0_rate"], stream=s)
+    st.load_history(prior, stream=s)
+    st.step(1, stream=s)
+    st.check(stream=s)
+    g = st.read("f_hist", stream=s)
+    Vh = np.concatenate([prior, ini["V"][None, :]])
+    ref = OI.stress_rows(oracle.geo, ROWS, Vh, 0, -len(prior), oracle.mu, oracle.cs, oracle.dt,
+                         params["eta_tmin"], params["eta_tmax"], min_lag=1, with_tail=True)
+    e = np.abs(g[ROWS] - ref).max() / np.abs(ref).max()
+    print(f"[gpu] full-size SEAS history part: sampled rel err {e:.3e}", flush=True)
+    assert e < 1e-4

@@ -1,0 +1,133 @@
+"""CPU checks of the C-ABI library (no GPU): it loads, exports every function
+include/seas.h declares, and its host-side build (windows, H-matrix partition,
+self-kernel tables, per-lag factors) agrees with the oracle.  Operators here are
+built with host_only = 1, which keeps everything on the host."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import seas_inputs as SI
+from oracle import geometry, hpartition as HP, interaction as I, selfterm as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+P = pytest.importorskip("paper_2603_00383_amd")
+
+
+def _lib_or_skip():
+    try:
+        return P.lib()
+    except (RuntimeError, OSError) as e:
+        pytest.skip(f"library not built: {e}")
+
+
+def test_exports_every_declared_symbol():
+    L = _lib_or_skip()
+    hdr = open(os.path.join(ROOT, "include", "seas.h")).read()
+    names = set(re.findall(r"\b(seas_[a-z_0-9]+)\s*\(", hdr))
+    assert len(names) >= 20
+    for n in sorted(names):
+        assert hasattr(L, n), n
+
+
+def _op(faults, **kw):
+    _lib_or_skip()
+    p = SI.default_params(host_only=1, **kw)
+    return P.Operator(faults, p)
+
+
+def test_windows_and_partition_match_oracle():
+    faults = SI.two_fault_prescribed_faults()
+    for seed_faults in (faults, SI.five_fault_network(seed=1, n_elem=64)):
+        op = _op(seed_faults, eta_H=2.0, leaf=16)
+        geo = geometry.discretize(seed_faults)
+        dt = geometry.time_step(geo, SI.CS)
+        assert op.info["dt"] == dt
+        win = op.windows()
+        blocks = HP.partition(geo, 2.0, 16)
+        for (a, b), (t0, t1) in win.items():
+            assert (t0, t1) == I.pair_window_lags(geo, a, b, SI.CS, dt, 0.01, 0.01)
+            assert op.blocks(a, b) == blocks[(a, b)]
+
+
+def test_self_tables_match_oracle():
+    faults = SI.two_fault_prescribed_faults()
+    op = _op(faults)
+    geo = geometry.discretize(faults)
+    dt = geometry.time_step(geo, SI.CS)
+    st = S.SelfTerm(128, 12800.0, SI.MU, SI.CS, dt)
+    worst = 0.0
+    for n in (1, 2, 3, 17, 64, 127, 128):
+        lt = op.self_table(0, n)
+        ot = st.table(n - 1)
+        assert len(lt) == len(ot)
+        worst = max(worst, np.abs(lt - ot).max() / np.abs(ot).max())
+    assert worst < 1e-12
+
+
+@pytest.mark.parametrize("compress", [0, 1])
+def test_lag_matrices_match_dense_kernel(compress):
+    faults = SI.two_fault_prescribed_faults(n_elem=64, dx=200.0)
+    tol = 1e-6
+    op = _op(faults, compress=compress, aca_tol=tol, eta_H=1.0, leaf=16)
+    geo = geometry.discretize(faults)
+    dt = geometry.time_step(geo, SI.CS)
+    for (a, b), (t0, t1) in op.windows().items():
+        for T in sorted({0, 1, max(t0, 1), t0 + 3, (t0 + t1) // 2, t1}):
+            if T < t0 or T > t1:
+                continue
+            K = I.pair_kernel(geo, a, b, T, dt, SI.CS)
+            R = op.lag_matrix(a, b, T, 64, 64)
+            nrm = np.linalg.norm(K)
+            if nrm == 0:
+                assert np.all(R == 0)
+                continue
+            err = np.linalg.norm(R - K) / nrm
+            if compress == 0 or T == 0:
+                assert err < 1e-12, (a, b, T, err)
+            else:
+                assert err < 2 * tol, (a, b, T, err)
+        # static tail stored as -G/eta
+        G = I.static_dipole(geo, a, b, SI.MU)
+        R = op.lag_matrix(a, b, -1, 64, 64)
+        eta = SI.MU / (2 * SI.CS)
+        assert np.linalg.norm(R + G / eta) / np.linalg.norm(G / eta) < (1e-12 if compress == 0 else 2 * tol)
+
+
+def test_compression_reduces_storage():
+    faults = SI.five_fault_network(seed=0, n_elem=100)
+    dense = _op(faults, compress=0, eta_H=2.0, leaf=25).info
+    comp = _op(faults, compress=1, eta_H=2.0, leaf=25, aca_tol=1e-6).info
+    assert comp["stored_entries"] < 0.8 * dense["stored_entries"]
+    assert dense["n_blocks"] == comp["n_blocks"]
+
+
+def test_rejects_degenerate_input():
+    _lib_or_skip()
+    bad = [SI.fault(0, 0, 0, 1000.0, 10), dict(cx=0.0, cy=500.0, nx=0.0, ny=0.0, length=1000.0, n_elem=10)]
+    with pytest.raises(P.SeasError) as e:
+        P.Operator(bad, SI.default_params(host_only=1))
+    assert e.value.code == -1
+    with pytest.raises(P.SeasError):
+        P.Operator([SI.fault(0, 0, 0, 1000.0, 1)], SI.default_params(host_only=1))
+    with pytest.raises(P.SeasError):
+        P.Operator([SI.fault(0, 0, 0, 1000.0, 10)], SI.default_params(host_only=1, beta=0.7))
+    # fault 2's element end point at (-450, 0) sits on fault 1's first midpoint
+    f1 = SI.fault(0, 0, 0, 1000.0, 10)
+    f2 = SI.fault(-450.0, 0.0, 90.0, 1000.0, 10)
+    with pytest.raises(P.SeasError) as e:
+        P.Operator([f1, f2], SI.default_params(host_only=1))
+    assert e.value.code == -1
+
+
+def test_host_only_operator_refuses_evaluation():
+    op = _op(SI.two_fault_prescribed_faults(n_elem=16, dx=800.0))
+    n = op.N
+    fr = dict(a=np.full(n, 0.01), b=np.full(n, 0.015), Dc=np.full(n, 5e-3), sigma_n=np.full(n, 5e7),
+              V0=np.full(n, 1e-6), f0=np.full(n, 0.6))
+    with pytest.raises(P.SeasError) as e:
+        P.State(op, fr, np.full(n, 1e-9), np.full(n, 5e6), np.full(n, 3e7))
+    assert e.value.code == -5
