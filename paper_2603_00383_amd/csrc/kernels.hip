@@ -119,13 +119,17 @@ __global__ __launch_bounds__(kItemThreads) void k_hmat(const Item* __restrict__ 
   }
 }
 
+// One 64-lane wave per receiver: lanes stride over the receiver's partial list,
+// then a butterfly sum (fixed order, independent of scheduling).
 __global__ void k_reduce(const double* __restrict__ partials, const int32_t* __restrict__ ptr,
                          const int32_t* __restrict__ idx, int N, double neg_eta, double* __restrict__ f) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (r >= N) return;
   double s = 0.0;
-  for (int k = ptr[r]; k < ptr[r + 1]; ++k) s += partials[idx[k]];
-  f[r] = neg_eta * s;
+  for (int k = ptr[r] + lane; k < ptr[r + 1]; k += 64) s += partials[idx[k]];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) f[r] = neg_eta * s;
 }
 
 // ------------------------------------------------------------------ self term
@@ -332,7 +336,7 @@ void launch_hmat(const HostOp& h, const void* items, const int32_t* lagT, const 
 
 void launch_reduce(const HostOp& h, const double* partials, const int32_t* ptr, const int32_t* idx, double* f,
                    hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3(blocks_for(h.N, 256)), dim3(256), 0, s, partials, ptr, idx, h.N, -h.eta, f);
+  hipLaunchKernelGGL(k_reduce, dim3(blocks_for(h.N, 4)), dim3(256), 0, s, partials, ptr, idx, h.N, -h.eta, f);
 }
 
 void launch_self_hist(int n_modes, const SelfMode* modes, const double* tab, const double2* dring, int64_t time0,
