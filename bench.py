@@ -75,6 +75,9 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--aca", type=float, default=1e-6)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--time-block", type=int, default=8,
+                    help="S: lags >= S applied once per S steps (1 = plain per-step form)")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-form measurement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -92,7 +95,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
     faults = SI.five_fault_network(seed=args.seed)
-    params = SI.default_params(factor_dtype=args.dtype, aca_tol=args.aca, eta_H=2.0, leaf=50)
+    params = SI.default_params(factor_dtype=args.dtype, aca_tol=args.aca, eta_H=2.0, leaf=50,
+                               time_block=args.time_block)
     os.environ.setdefault("SEAS_VERBOSE", "1")
     print("[bench] building the operator", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
@@ -114,23 +118,32 @@ def main():
     print(f"[bench] history loaded ({len(prior)} steps), warmup {args.warmup}", file=sys.stderr, flush=True)
     st.step(args.warmup, stream=s)
     st.check(stream=s)
-    st.set_timing(True)
-    st.read_timing(stream=s)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    w0 = time.perf_counter()
-    e0.record(stream)
-    st.step(args.steps, stream=s)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    ms_hmat, n_launch = st.read_timing(stream=s)
-    st.check(stream=s)
-    ev_ms = e0.elapsed_time(e1)
     elem_bytes = 4 if args.dtype == "f32" else 8
-    hmat_bytes = info["stored_entries"] * elem_bytes
-    avg_ms = ms_hmat / max(n_launch, 1)
-    achieved = hmat_bytes / (avg_ms * 1e-3) / 1e9
+
+    def timed(S):
+        st.set_time_block(S)
+        st.set_timing(True)
+        st.step(2, stream=s)          # enter the form's cadence
+        st.read_timing(stream=s)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        w0 = time.perf_counter()
+        e0.record(stream)
+        st.step(args.steps, stream=s)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        ms, n = st.read_timing(stream=s)
+        st.check(stream=s)
+        avg = ms / max(n, 1)
+        gbs = info["far_entries"] * elem_bytes / (avg * 1e-3) / 1e9
+        return dict(wall=wall, ev_ms=e0.elapsed_time(e1), avg_ms=avg, launches=n, gbs=gbs)
+
+    S = info["time_block"]
+    main_run = timed(S)
+    plain = None if (args.no_plain or S == 1) else timed(1)
+    wall, avg_ms, achieved = main_run["wall"], main_run["avg_ms"], main_run["gbs"]
+    hmat_bytes = info["far_entries"] * elem_bytes
     out = {
         "metric": METRIC,
         "value": N * args.steps / wall,
@@ -142,14 +155,21 @@ def main():
         "config": {"workload": "five-fault SEAS step loop, 5 x 600 elements (N=3000, dx=50 m), "
                                f"{args.dtype.upper()} factors, FP64 state, ACA {args.aca:g}, eta_H 2, leaf 50, "
                                "saturated history windows",
-                   "seed": args.seed, "N": N, "max_lag": info["max_lag"]},
+                   "seed": args.seed, "N": N, "max_lag": info["max_lag"], "time_block": S},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_hmat", "kernel_avg_ms": avg_ms, "algorithmic_bytes": hmat_bytes},
-        "gpu_event_ms_per_step": ev_ms / args.steps,
+                     "kernel": f"k_hmat<float,float,{S}>" if args.dtype == "f32" else f"k_hmat<double,double,{S}>",
+                     "kernel_avg_ms": avg_ms, "algorithmic_bytes": hmat_bytes,
+                     "launches_per_step": main_run["launches"] / args.steps},
+        "gpu_event_ms_per_step": main_run["ev_ms"] / args.steps,
         "build_s": build_s,
         "stored_over_dense": info["stored_entries"] / info["dense_entries"],
     }
+    if plain is not None:
+        out["plain"] = {"value": N * args.steps / plain["wall"], "ms_per_step": plain["wall"] / args.steps * 1e3,
+                        "kernel_avg_ms": plain["avg_ms"], "achieved_GBs": plain["gbs"],
+                        "frac": plain["gbs"] / HBM_PEAK_GBS,
+                        "note": "same operator and state, lags >= S applied every step"}
     print(f"[bench] timed {args.steps} steps: {wall:.3f} s", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] oracle CPU baseline", file=sys.stderr, flush=True)

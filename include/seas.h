@@ -91,6 +91,11 @@ typedef struct {
   int32_t host_only;    /* 1: build on the host only (no device memory; for inspecting the
                            partition, windows, tables and factors); evaluation and state calls
                            then fail with MISMATCH */
+  int32_t time_block;   /* S in {0 (= 1), 1, 2, 4, 8, 16}: lags T >= S are applied once per S
+                           steps to S history windows (a lag-T factor only needs rates at least
+                           T steps old), lags 1..S-1 and the static tail every step; the sum is
+                           the same, only its evaluation order changes */
+  int32_t reserved;
 } seas_params_t;
 
 typedef struct seas_op seas_op_t;
@@ -110,7 +115,7 @@ typedef struct {
   int32_t max_lag;            /* largest interaction lag T_end over pairs */
   int32_t max_self_window;    /* largest self window W_n over faults and modes */
   int64_t n_blocks;           /* H-matrix blocks over all ordered pairs */
-  int64_t n_items;            /* work items of the per-step evaluation */
+  int64_t n_items;            /* work items applied once per time block */
   int64_t dense_entries;      /* entries of the uncompressed kernel in the pair windows */
   int64_t stored_entries;     /* stored factor entries (low rank + dense), lags >= 1 and tail */
   int64_t lag0_nnz;           /* nonzeros of the lag-0 interaction (pairs with T_init = 0) */
@@ -119,7 +124,9 @@ typedef struct {
   double flops_per_step;      /* 2 x stored entries + self term MACs */
   double build_seconds;
   int32_t factor_dtype;
-  int32_t reserved;
+  int32_t time_block;         /* S of the build */
+  int64_t far_entries;        /* stored entries applied once per time block (lags >= S) */
+  int64_t n_items_near;       /* work items applied every step (lags 1..S-1, static tail) */
 } seas_op_info_t;
 
 seas_status seas_operator_info(const seas_op_t* op, seas_op_info_t* out);
@@ -208,6 +215,11 @@ seas_status seas_read_state(const seas_state_t* st, int32_t field, int32_t varia
  * on the launch stream. read_timing synchronises `stream`, returns the summed
  * milliseconds and the number of launches since the last read, and resets them. */
 seas_status seas_state_set_timing(seas_state_t* st, int32_t enable);
+
+/* Evaluation order of a state built with time_block S > 1: S (default) applies the
+ * lags >= S once per S steps; 1 applies them every step (the plain per-step form).
+ * Results agree to rounding; used to compare both forms on one operator. */
+seas_status seas_state_set_time_block(seas_state_t* st, int32_t S);
 seas_status seas_state_read_timing(seas_state_t* st, void* stream, double* ms_total, int64_t* launches);
 
 /* Current step index (number of steps taken, or prescribed steps evaluated). */

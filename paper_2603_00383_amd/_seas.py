@@ -38,7 +38,8 @@ class Params(C.Structure):
                 ("aca_tol", C.c_double), ("eta_tmin", C.c_double), ("eta_tmax", C.c_double),
                 ("eta_w", C.c_double), ("leaf", C.c_int32), ("compress", C.c_int32),
                 ("int_tail", C.c_int32), ("q_w", C.c_int32), ("mode_cap", C.c_int32),
-                ("factor_dtype", C.c_int32), ("n_threads", C.c_int32), ("host_only", C.c_int32)]
+                ("factor_dtype", C.c_int32), ("n_threads", C.c_int32), ("host_only", C.c_int32),
+                ("time_block", C.c_int32), ("reserved", C.c_int32)]
 
 
 class OpInfo(C.Structure):
@@ -47,7 +48,8 @@ class OpInfo(C.Structure):
                 ("n_items", C.c_int64), ("dense_entries", C.c_int64), ("stored_entries", C.c_int64),
                 ("lag0_nnz", C.c_int64), ("self_entries", C.c_int64), ("bytes_per_step", C.c_double),
                 ("flops_per_step", C.c_double), ("build_seconds", C.c_double),
-                ("factor_dtype", C.c_int32), ("reserved", C.c_int32)]
+                ("factor_dtype", C.c_int32), ("time_block", C.c_int32), ("far_entries", C.c_int64),
+                ("n_items_near", C.c_int64)]
 
 
 class Friction(C.Structure):
@@ -86,6 +88,7 @@ def lib():
             "seas_read_state": (i32, [vp, i32, i32, vp, C.c_size_t, i32, vp]),
             "seas_state_step_index": (i64, [vp]),
             "seas_state_set_timing": (i32, [vp, i32]),
+            "seas_state_set_time_block": (i32, [vp, i32]),
             "seas_state_read_timing": (i32, [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
             "seas_state_checkpoint_bytes": (C.c_size_t, [vp]),
             "seas_state_save": (i32, [vp, vp, C.c_size_t, vp]),
@@ -135,6 +138,7 @@ def make_params(p):
     q.factor_dtype = _DTYPE[p.get("factor_dtype", "f64")]
     q.n_threads = int(p.get("n_threads", 0))
     q.host_only = int(p.get("host_only", 0))
+    q.time_block = int(p.get("time_block", 1))
     return q
 
 
@@ -237,6 +241,9 @@ class State:
         _check(lib().seas_read_state(self.h, FIELDS[field], 0, C.c_void_p(out.ctypes.data), self.op.N, 0,
                                      _ptr(stream)))
         return out
+
+    def set_time_block(self, S):
+        _check(lib().seas_state_set_time_block(self.h, int(S)))
 
     def set_timing(self, enable=True):
         _check(lib().seas_state_set_timing(self.h, 1 if enable else 0))

@@ -77,9 +77,9 @@ struct seas_op {
   int device = 0;
   std::vector<DevBuf> owned;
   void* arena = nullptr;
-  Item* items = nullptr;
-  int32_t *lagT = nullptr, *lagCol = nullptr, *lagColOff = nullptr;
-  int32_t *red_ptr = nullptr, *red_idx = nullptr;
+  Item* items[2] = {nullptr, nullptr};
+  int32_t *lagT = nullptr, *lagCol = nullptr, *lagColOff[2] = {nullptr, nullptr};
+  int32_t *red_ptr[2] = {nullptr, nullptr}, *red_idx[2] = {nullptr, nullptr};
   int32_t *l0_ptr = nullptr, *l0_col = nullptr;
   double* l0_val = nullptr;
   SelfMode* modes = nullptr;
@@ -112,7 +112,10 @@ struct seas_state {
   double* ring64;
   void* ringop;
   double* tail_acc;
-  double* partials;
+  double *partials_far, *partials_near;
+  double* f_far;             // far part of the interaction for the S evaluations of a time block
+  int64_t block_head = INT64_MIN / 2;  // head at which f_far was computed
+  int run_S = 0;                        // 1: far list applied every step (plain form); else the build's S
   double2 *dring, *Fh, *F;
   int* fail;
   bool timing = false;
@@ -165,25 +168,60 @@ StepArgs<TF> make_args(seas_op* op, seas_state* st) {
   return a;
 }
 
+void record_start(seas_state* st, hipStream_t s) {
+  if (!st->timing) return;
+  if (st->ev.size() < 2 * (st->n_ev + 1)) {
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    st->ev.push_back(a);
+    st->ev.push_back(b);
+  }
+  HIPCHK(hipEventRecord(st->ev[2 * st->n_ev], s));
+}
+
+void record_stop(seas_state* st, hipStream_t s) {
+  if (!st->timing) return;
+  HIPCHK(hipEventRecord(st->ev[2 * st->n_ev + 1], s));
+  st->n_ev++;
+}
+
+// Interaction history part at `head` into st->f_hist. The far list is applied
+// once per time block (S windows: heads block_head .. block_head + S - 1), the
+// near list (lags 1..S-1 and the static tail) at every head.
 void eval_history(seas_op* op, seas_state* st, int64_t head, hipStream_t s) {
   const HostOp& h = op->h;
-  if (st->timing) {
-    if (st->ev.size() < 2 * (st->n_ev + 1)) {
-      hipEvent_t a, b;
-      HIPCHK(hipEventCreate(&a));
-      HIPCHK(hipEventCreate(&b));
-      st->ev.push_back(a);
-      st->ev.push_back(b);
+  const int S = h.time_block;
+  const int nfar = (int)h.items[0].size(), nnear = (int)h.items[1].size();
+  if (S == 1 || st->run_S == 1) {  // far list every step, one window
+    record_start(st, s);
+    launch_hmat(h, 1, nfar, op->items[0], op->lagT, op->lagCol, op->lagColOff[0], op->arena, st->ringop, head,
+                st->tail_acc, st->partials_far, S, s);
+    record_stop(st, s);
+    if (nnear == 0) {
+      launch_reduce_far(h, 1, st->partials_far, op->red_ptr[0], op->red_idx[0], st->f_hist, s);
+      return;
     }
-    HIPCHK(hipEventRecord(st->ev[2 * st->n_ev], s));
+    launch_reduce_far(h, 1, st->partials_far, op->red_ptr[0], op->red_idx[0], st->f_far, s);
+    st->block_head = INT64_MIN / 2;
+    launch_hmat(h, 1, nnear, op->items[1], op->lagT, op->lagCol, op->lagColOff[1], op->arena, st->ringop, head,
+                st->tail_acc, st->partials_near, 1, s);
+    launch_reduce_near(h, st->partials_near, op->red_ptr[1], op->red_idx[1], st->f_far, st->f_hist, s);
+    return;
   }
-  launch_hmat(h, op->items, op->lagT, op->lagCol, op->lagColOff, op->arena, st->ringop, head, st->tail_acc,
-              st->partials, s);
-  if (st->timing) {
-    HIPCHK(hipEventRecord(st->ev[2 * st->n_ev + 1], s));
-    st->n_ev++;
+  int64_t k = head - st->block_head;
+  if (k < 0 || k >= S) {
+    record_start(st, s);
+    launch_hmat(h, S, nfar, op->items[0], op->lagT, op->lagCol, op->lagColOff[0], op->arena, st->ringop, head,
+                st->tail_acc, st->partials_far, S, s);
+    record_stop(st, s);
+    launch_reduce_far(h, S, st->partials_far, op->red_ptr[0], op->red_idx[0], st->f_far, s);
+    st->block_head = head;
+    k = 0;
   }
-  launch_reduce(h, st->partials, op->red_ptr, op->red_idx, st->f_hist, s);
+  launch_hmat(h, 1, nnear, op->items[1], op->lagT, op->lagCol, op->lagColOff[1], op->arena, st->ringop, head,
+              st->tail_acc, st->partials_near, 1, s);
+  launch_reduce_near(h, st->partials_near, op->red_ptr[1], op->red_idx[1], st->f_far + k * h.N, st->f_hist, s);
 }
 
 template <typename TF>
@@ -279,12 +317,14 @@ seas_status seas_build_operator(const seas_fault_t* faults, int32_t n_faults, co
       std::vector<double>().swap(b64[bi]);
       std::vector<float>().swap(b32[bi]);
     }
-    op->items = upload(op->owned, h.items);
+    for (int L = 0; L < 2; ++L) {
+      op->items[L] = upload(op->owned, h.items[L]);
+      op->lagColOff[L] = upload(op->owned, h.lagColOff[L]);
+      op->red_ptr[L] = upload(op->owned, h.red_ptr[L]);
+      op->red_idx[L] = upload(op->owned, h.red_idx[L]);
+    }
     op->lagT = upload(op->owned, h.lagT);
     op->lagCol = upload(op->owned, h.lagCol);
-    op->lagColOff = upload(op->owned, h.lagColOff);
-    op->red_ptr = upload(op->owned, h.red_ptr);
-    op->red_idx = upload(op->owned, h.red_idx);
     op->l0_ptr = upload(op->owned, h.l0_ptr);
     op->l0_col = upload(op->owned, h.l0_col);
     op->l0_val = upload(op->owned, h.l0_val);
@@ -375,11 +415,12 @@ seas_status seas_operator_lag_matrix(const seas_op_t* op, int32_t a, int32_t b, 
       const int64_t k = e - op->hboff[lo];
       return op->elem_bytes == 4 ? (double)op->hb32[lo][k] : op->hb64[lo][k];
     };
-    for (size_t ii = 0; ii < h.items.size(); ++ii) {
-      const Item& it = h.items[ii];
+    for (int L = 0; L < 2; ++L)
+    for (size_t ii = 0; ii < h.items[L].size(); ++ii) {
+      const Item& it = h.items[L][ii];
       if (it.row0 < A.off || it.row0 >= A.off + p_all || it.col0 < B.off || it.col0 >= B.off + q_all) continue;
       const int ri = it.row0 - A.off, cj = it.col0 - B.off;
-      const int32_t* cp = &h.lagCol[h.lagColOff[ii]];
+      const int32_t* cp = &h.lagCol[h.lagColOff[L][ii]];
       for (int l = 0; l < it.nlag; ++l) {
         if (h.lagT[it.lag_off + l] != T) continue;
         if (it.kind == 0) {
@@ -413,7 +454,13 @@ seas_status seas_operator_info(const seas_op_t* op, seas_op_info_t* out) {
     int64_t nb = 0;
     for (auto& v : h.blocks) nb += (int64_t)v.size();
     out->n_blocks = nb;
-    out->n_items = (int64_t)h.items.size();
+    out->n_items = (int64_t)h.items[0].size();
+    out->n_items_near = (int64_t)h.items[1].size();
+    out->time_block = h.time_block;
+    int64_t far = 0;
+    for (const Item& it : h.items[0])
+      far += it.kind == 0 ? (int64_t)it.ncol * (it.p + it.q) : (int64_t)it.nlag * it.p * it.q;
+    out->far_entries = far;
     out->dense_entries = h.dense_entries;
     out->stored_entries = h.stored_entries;
     out->lag0_nnz = (int64_t)h.l0_val.size();
@@ -482,7 +529,8 @@ size_t seas_state_bytes(const seas_op_t* op, int32_t n_variants) {
   b += (size_t)h.ring_len * N * 8;                               // FP64 rate history
   if (op->elem_bytes != 8) b += (size_t)h.ring_len * N * op->elem_bytes;  // operand copy
   b += (size_t)h.tail_len * 8 * n_variants;
-  b += (size_t)h.n_partials * 8 * n_variants;
+  b += (size_t)(h.n_partials[0] + h.n_partials[1]) * 8 * n_variants;
+  b += (size_t)h.time_block * N * 8;
   b += (size_t)h.self_ring_len * 16 * n_variants + (size_t)h.n_modes * 16 * 2 * n_variants;
   return b;
 }
@@ -531,7 +579,9 @@ seas_status seas_state_create(seas_op_t* op, int32_t n_variants, const seas_fric
     st->ring64 = (double*)A((size_t)h.ring_len * vb, true);
     st->ringop = op->elem_bytes == 8 ? (void*)st->ring64 : A((size_t)h.ring_len * N * op->elem_bytes, true);
     st->tail_acc = (double*)A((size_t)h.tail_len * 8, true);
-    st->partials = (double*)A((size_t)h.n_partials * 8, false);
+    st->partials_far = (double*)A((size_t)h.n_partials[0] * 8, false);
+    st->partials_near = (double*)A((size_t)h.n_partials[1] * 8, false);
+    st->f_far = (double*)A((size_t)h.time_block * vb, true);
     st->dring = (double2*)A((size_t)h.self_ring_len * 16, true);
     st->Fh = (double2*)A((size_t)h.n_modes * 16, false);
     st->F = (double2*)A((size_t)h.n_modes * 16, false);
@@ -717,6 +767,15 @@ seas_status seas_state_set_timing(seas_state_t* st, int32_t enable) {
   });
 }
 
+seas_status seas_state_set_time_block(seas_state_t* st, int32_t S) {
+  return guard([&] {
+    if (!st) throw Error(SEAS_ERR_INVALID_ARG, "null state");
+    if (S != 1 && S != st->op->h.time_block) throw Error(SEAS_ERR_INVALID_ARG, "S must be 1 or the build's time_block");
+    st->run_S = S;
+    st->block_head = INT64_MIN / 2;
+  });
+}
+
 seas_status seas_state_read_timing(seas_state_t* st, void* stream, double* ms_total, int64_t* launches) {
   return guard([&] {
     if (!st || !ms_total || !launches) throw Error(SEAS_ERR_INVALID_ARG, "null argument");
@@ -736,7 +795,7 @@ seas_status seas_state_read_timing(seas_state_t* st, void* stream, double* ms_to
 
 size_t seas_state_checkpoint_bytes(const seas_state_t* st) {
   if (!st) return 0;
-  size_t b = 4 * sizeof(int64_t);
+  size_t b = 5 * sizeof(int64_t);
   for (auto& c : st->ckpt) b += c.bytes;
   return b;
 }
@@ -748,7 +807,7 @@ seas_status seas_state_save(const seas_state_t* st, void* host_buf, size_t bytes
     if (bytes < seas_state_checkpoint_bytes(st)) throw Error(SEAS_ERR_INVALID_ARG, "buffer too small");
     hipStream_t s = (hipStream_t)stream;
     char* p = (char*)host_buf;
-    const int64_t hdr[4] = {st->step, st->first, st->mode, (int64_t)st->op->h.N};
+    const int64_t hdr[5] = {st->step, st->first, st->mode, (int64_t)st->op->h.N, st->block_head};
     std::memcpy(p, hdr, sizeof(hdr));
     p += sizeof(hdr);
     for (auto& c : st->ckpt) {
@@ -765,7 +824,7 @@ seas_status seas_state_restore(seas_state_t* st, const void* host_buf, size_t by
     checked(st->op);
     if (bytes < seas_state_checkpoint_bytes(st)) throw Error(SEAS_ERR_INVALID_ARG, "buffer too small");
     const char* p = (const char*)host_buf;
-    int64_t hdr[4];
+    int64_t hdr[5];
     std::memcpy(hdr, p, sizeof(hdr));
     if (hdr[3] != st->op->h.N) throw Error(SEAS_ERR_MISMATCH, "checkpoint of another operator");
     p += sizeof(hdr);
@@ -778,6 +837,7 @@ seas_status seas_state_restore(seas_state_t* st, const void* host_buf, size_t by
     st->step = hdr[0];
     st->first = hdr[1];
     st->mode = (int)hdr[2];
+    st->block_head = hdr[4];
   });
 }
 

@@ -273,18 +273,25 @@ struct LagFactor {
   std::vector<double> U, W, D;  // U: k x p (col l = U[l*p..]), W: k x q, D: p x q row-major
 };
 
+// Items of one block for the two evaluation passes: list 0 ("far") is applied
+// once per time block of S steps to S history windows at a time; list 1 ("near")
+// holds the lags 1..S-1 and the static tail, applied every step. With S = 1 every
+// lag and the tail are in list 0.
 struct BlockOut {
-  std::vector<Item> items;
-  std::vector<int32_t> lagT;
-  std::vector<int32_t> lagCol;
+  std::vector<Item> items[2];
+  std::vector<int32_t> lagT[2], lagCol[2];
   std::vector<double> d64;
   std::vector<float> d32;
   int64_t stored = 0, dense = 0;
 };
 
-static void pack_block(const BlockDesc& bd, const Fault& A, const Fault& B, std::vector<LagFactor>& lags,
-                       bool f32, int tail_off, BlockOut& out) {
-  const int p = bd.r1 - bd.r0, q = bd.s1 - bd.s0;
+// Pack a run of lag factors of one (sub-)block into items of list `L` whose
+// kernel evaluates S steps: the history span T_last - T_first + S rows of q
+// values, the low-rank columns (times S) and the lag count must fit the LDS
+// buffers of the kernel.
+static void pack_list(int r0, int r1, int s0, int s1, const Fault& A, const Fault& B,
+                      std::vector<LagFactor*>& lags, bool f32, int tail_off, int S, int L, BlockOut& out) {
+  const int p = r1 - r0, q = s1 - s0;
   const int64_t target = f32 ? 65536 : 32768;  // elements per item
   auto push = [&](double v) {
     if (f32) out.d32.push_back((float)v);
@@ -293,23 +300,25 @@ static void pack_block(const BlockDesc& bd, const Fault& A, const Fault& B, std:
   auto cur_size = [&]() -> int64_t { return f32 ? (int64_t)out.d32.size() : (int64_t)out.d64.size(); };
   size_t i = 0;
   while (i < lags.size()) {
-    const bool lr = lags[i].rank > 0;
-    const bool tail = lags[i].T < 0;
-    // gather a run of lags of the same kind within the limits
+    const bool lr = lags[i]->rank > 0;
+    const bool tail = lags[i]->T < 0;
     size_t j = i;
     int64_t elems = 0;
     int ncol = 0;
-    while (j < lags.size() && (lags[j].rank > 0) == lr && (lags[j].T < 0) == tail) {
+    while (j < lags.size() && (lags[j]->rank > 0) == lr && (lags[j]->T < 0) == tail) {
       const int nl = (int)(j - i) + 1;
-      const int64_t e = lr ? (int64_t)lags[j].rank * (p + q) : (int64_t)p * q;
+      const int64_t e = lr ? (int64_t)lags[j]->rank * (p + q) : (int64_t)p * q;
       if (j > i) {
         if (tail) break;
-        if ((int64_t)nl * q > kHistMax) break;
-        if (lr && ncol + lags[j].rank > kColMax) break;
+        if (lags[j]->T != lags[j - 1]->T + 1) break;  // an item's lags are consecutive
+        const int span = lags[j]->T - lags[i]->T + S;
+        if ((int64_t)span * q > kHistMax) break;
+        if (nl > kColMax) break;
+        if (lr && (ncol + lags[j]->rank > kColMax || (int64_t)(ncol + lags[j]->rank) * S > kZMax)) break;
         if (elems + e > target) break;
       }
       elems += e;
-      if (lr) ncol += lags[j].rank;
+      if (lr) ncol += lags[j]->rank;
       ++j;
     }
     Item it{};
@@ -318,62 +327,61 @@ static void pack_block(const BlockDesc& bd, const Fault& A, const Fault& B, std:
     it.src = tail ? 1 : 0;
     it.p = p;
     it.q = q;
-    it.row0 = A.off + bd.r0;
-    it.col0 = B.off + bd.s0;
+    it.row0 = A.off + r0;
+    it.col0 = B.off + s0;
     it.nlag = (int)(j - i);
-    it.lag_off = (int)out.lagT.size();
+    it.lag_off = (int)out.lagT[L].size();
     it.ncol = ncol;
-    it.tail_off = tail ? tail_off + bd.s0 : 0;
-    for (size_t l = i; l < j; ++l) out.lagT.push_back(lags[l].T);
+    it.tail_off = tail ? tail_off + s0 : 0;
+    for (size_t l = i; l < j; ++l) out.lagT[L].push_back(lags[l]->T);
+    out.lagCol[L].push_back(0);
     if (lr) {
-      // column prefix
       int c = 0;
-      out.lagCol.push_back(0);
       for (size_t l = i; l < j; ++l) {
-        c += lags[l].rank;
-        out.lagCol.push_back(c);
+        c += lags[l]->rank;
+        out.lagCol[L].push_back(c);
       }
-      // W panel [q][ncol]
-      for (int jj = 0; jj < q; ++jj)
+      for (int jj = 0; jj < q; ++jj)  // W panel [q][ncol]
         for (size_t l = i; l < j; ++l)
-          for (int r = 0; r < lags[l].rank; ++r) push(lags[l].W[(size_t)r * q + jj]);
-      // U panel [ncol][p]
-      for (size_t l = i; l < j; ++l)
-        for (int r = 0; r < lags[l].rank; ++r)
-          for (int ii = 0; ii < p; ++ii) push(lags[l].U[(size_t)r * p + ii]);
+          for (int r = 0; r < lags[l]->rank; ++r) push(lags[l]->W[(size_t)r * q + jj]);
+      for (size_t l = i; l < j; ++l)  // U panel [ncol][p]
+        for (int r = 0; r < lags[l]->rank; ++r)
+          for (int ii = 0; ii < p; ++ii) push(lags[l]->U[(size_t)r * p + ii]);
     } else {
-      for (int l = 0; l < it.nlag; ++l) out.lagCol.push_back(0);
-      out.lagCol.push_back(0);
-      for (size_t l = i; l < j; ++l)
+      for (int l = 0; l < it.nlag; ++l) out.lagCol[L].push_back(0);
+      for (size_t l = i; l < j; ++l)  // [nlag][q][p]
         for (int jj = 0; jj < q; ++jj)
-          for (int ii = 0; ii < p; ++ii) push(lags[l].D[(size_t)ii * q + jj]);
+          for (int ii = 0; ii < p; ++ii) push(lags[l]->D[(size_t)ii * q + jj]);
     }
     out.stored += elems;
-    out.items.push_back(it);
+    out.items[L].push_back(it);
     for (size_t l = i; l < j; ++l) {  // release
-      std::vector<double>().swap(lags[l].U);
-      std::vector<double>().swap(lags[l].W);
-      std::vector<double>().swap(lags[l].D);
+      std::vector<double>().swap(lags[l]->U);
+      std::vector<double>().swap(lags[l]->W);
+      std::vector<double>().swap(lags[l]->D);
     }
     i = j;
   }
 }
 
-static void build_block(const HostOp& op, const BlockDesc& bd, const PairWin& pw, BlockOut& out) {
+// Evaluate, compress and pack the columns [s0, s1) of block bd over the pair's
+// window (every lag from max(1, T_init) to T_end; lag 0 is applied through the
+// CSR of the lag-0 coupling) and its static tail.
+static void build_subblock(const HostOp& op, const BlockDesc& bd, const PairWin& pw, int s0, int s1,
+                           BlockOut& out) {
   const Fault& A = op.faults[bd.a];
   const Fault& B = op.faults[bd.b];
-  const int p = bd.r1 - bd.r0, q = bd.s1 - bd.s0;
+  const int p = bd.r1 - bd.r0, q = s1 - s0;
   const double cs = op.prm.cs, dt = op.dt;
+  const int S = op.time_block;
   const bool lowrank_ok = op.prm.compress && bd.adm;
-  // ranks above kmax are stored dense; one lag's columns must also fit the
-  // per-item LDS buffer of the device kernel
-  const int kmax = std::min<int>((int)(((int64_t)p * q) / (p + q)), kColMax);
-  if (q > kHistMax) throw Error(SEAS_ERR_INVALID_ARG, "a source cluster exceeds the LDS history capacity");
+  // ranks above kmax are stored dense: the factors would not be smaller, and one
+  // lag's columns must fit the LDS column buffer of the kernel
+  const int kmax = std::min<int>({(int)(((int64_t)p * q) / (p + q)), kColMax, kZMax / S});
   const PairFrame fr = frame(A, B);
-  // receiver offsets in the source frame, per (i, j)
   std::vector<double> r1((size_t)p * q), r2((size_t)p * q);
   for (int i = 0; i < p; ++i)
-    for (int j = 0; j < q; ++j) offsets(A, bd.r0 + i, B, bd.s0 + j, r1[(size_t)i * q + j], r2[(size_t)i * q + j]);
+    for (int j = 0; j < q; ++j) offsets(A, bd.r0 + i, B, s0 + j, r1[(size_t)i * q + j], r2[(size_t)i * q + j]);
   auto level = [&](int T, std::vector<double>& G) {  // spatial difference at t = T dt
     const double ct = cs * (T * dt);
     for (size_t e = 0; e < G.size(); ++e)
@@ -383,6 +391,21 @@ static void build_block(const HostOp& op, const BlockDesc& bd, const PairWin& pw
   std::vector<LagFactor> lags;
   const int T_lo = std::max(1, pw.T_init), T_hi = pw.T_end;
   out.dense += (int64_t)p * q * (pw.T_end - pw.T_init + 1);
+  auto compress = [&](int T) {
+    LagFactor lf;
+    lf.T = T;
+    lf.rank = 0;
+    if (lowrank_ok) {
+      const int k = aca_full(K.data(), p, q, op.prm.aca_tol, kmax, U, W, R);
+      if (k > 0) {
+        lf.rank = k;  // U: k columns of length p, W: k columns of length q
+        lf.U = U;
+        lf.W = W;
+      }
+    }
+    if (lf.rank == 0) lf.D = K;
+    lags.push_back(std::move(lf));
+  };
   if (T_hi >= T_lo) level(T_lo, G0);
   for (int T = T_lo; T <= T_hi; ++T) {
     level(T + 1, G1);
@@ -392,21 +415,7 @@ static void build_block(const HostOp& op, const BlockDesc& bd, const PairWin& pw
       any |= K[e] != 0.0;
     }
     std::swap(G0, G1);
-    if (!any) continue;
-    LagFactor lf;
-    lf.T = T;
-    lf.rank = 0;
-    if (lowrank_ok) {
-      const int k = aca_full(K.data(), p, q, op.prm.aca_tol, kmax, U, W, R);
-      if (k > 0) {
-        lf.rank = k;
-        // U is stored as k columns of length p, W as k columns of length q
-        lf.U = U;
-        lf.W = W;
-      }
-    }
-    if (lf.rank == 0) lf.D = K;
-    lags.push_back(std::move(lf));
+    if (any) compress(T);
   }
   int toff = 0;
   if (op.prm.int_tail) {
@@ -414,23 +423,25 @@ static void build_block(const HostOp& op, const BlockDesc& bd, const PairWin& pw
     // common -eta factor of the evaluation restores it
     for (int i = 0; i < p; ++i)
       for (int j = 0; j < q; ++j)
-        K[(size_t)i * q + j] = -static_stress(A, bd.r0 + i, B, bd.s0 + j, op.prm.mu) / op.eta;
-    LagFactor lf;
-    lf.T = -1;
-    lf.rank = 0;
-    if (lowrank_ok) {
-      const int k = aca_full(K.data(), p, q, op.prm.aca_tol, kmax, U, W, R);
-      if (k > 0) {
-        lf.rank = k;
-        lf.U = U;
-        lf.W = W;
-      }
-    }
-    if (lf.rank == 0) lf.D = K;
-    lags.push_back(std::move(lf));
+        K[(size_t)i * q + j] = -static_stress(A, bd.r0 + i, B, s0 + j, op.prm.mu) / op.eta;
+    compress(-1);
     toff = op.tail_off[bd.pair];
   }
-  pack_block(bd, A, B, lags, op.prm.factor_dtype == SEAS_F32, toff, out);
+  std::vector<LagFactor*> far, near;
+  for (auto& lf : lags) {
+    if (S == 1 || (lf.T >= S)) far.push_back(&lf);
+    else near.push_back(&lf);
+  }
+  const bool f32 = op.prm.factor_dtype == SEAS_F32;
+  pack_list(bd.r0, bd.r1, s0, s1, A, B, far, f32, toff, S, 0, out);
+  pack_list(bd.r0, bd.r1, s0, s1, A, B, near, f32, toff, 1, 1, out);
+}
+
+static void build_block(const HostOp& op, const BlockDesc& bd, const PairWin& pw, BlockOut& out) {
+  // a source cluster wider than the kernel's history buffer holds for S rows is
+  // packed as column slices, each compressed on its own
+  const int qmax = kHistMax / op.time_block;
+  for (int s0 = bd.s0; s0 < bd.s1; s0 += qmax) build_subblock(op, bd, pw, s0, std::min(bd.s1, s0 + qmax), out);
 }
 
 // ============================================================== driver
@@ -461,6 +472,10 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
     throw Error(SEAS_ERR_INVALID_ARG, "leaf >= 1, eta_H > 0, aca_tol > 0, eta_w > 0 required");
   if (prm.factor_dtype != SEAS_F64 && prm.factor_dtype != SEAS_F32)
     throw Error(SEAS_ERR_INVALID_ARG, "factor_dtype must be SEAS_F64 or SEAS_F32");
+  if (prm.time_block < 0 || prm.time_block > kMaxTimeBlock ||
+      (prm.time_block & (prm.time_block - 1)) != 0)
+    throw Error(SEAS_ERR_INVALID_ARG, "time_block must be 0, 1, 2, 4, 8 or 16");
+  op.time_block = prm.time_block > 0 ? prm.time_block : 1;
   if (prm.n_threads > 0) omp_set_num_threads(prm.n_threads);
   // ---- geometry
   op.faults.clear();
@@ -598,55 +613,62 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
     }
   }
   if (!err.empty()) throw Error(SEAS_ERR_INTERNAL, "block build failed: " + err);
-  // ---- global item list, arena offsets, partial layout
-  op.items.clear();
+  // ---- global item lists, arena offsets, partial layouts
+  for (int L = 0; L < 2; ++L) {
+    op.items[L].clear();
+    op.lagColOff[L].clear();
+    op.n_partials[L] = 0;
+  }
   op.lagT.clear();
   op.lagCol.clear();
-  op.lagColOff.clear();
   op.arena_elems = 0;
-  op.n_partials = 0;
   op.stored_entries = 0;
   op.dense_entries = 0;
   const bool f32 = prm.factor_dtype == SEAS_F32;
+  const int S = op.time_block;
   bd64.assign(all.size(), {});
   bd32.assign(all.size(), {});
   block_arena_off.assign(all.size(), 0);
   for (size_t bi = 0; bi < all.size(); ++bi) {
     BlockOut& bo = outs[bi];
     block_arena_off[bi] = op.arena_elems;
-    const int lag_base = (int)op.lagT.size();
-    const int col_base = (int)op.lagCol.size();
-    // lagCol holds nlag+1 entries per item, in item order
-    int col_cursor = col_base;
-    for (Item it : bo.items) {
-      it.data += op.arena_elems;
-      it.part = (int32_t)op.n_partials;
-      op.n_partials += it.p;
-      op.lagColOff.push_back(col_cursor);
-      col_cursor += it.nlag + 1;
-      it.lag_off += lag_base;
-      op.items.push_back(it);
+    for (int L = 0; L < 2; ++L) {
+      const int lag_base = (int)op.lagT.size();
+      int col_cursor = (int)op.lagCol.size();
+      for (Item it : bo.items[L]) {
+        it.data += op.arena_elems;
+        it.part = (int32_t)op.n_partials[L];
+        op.n_partials[L] += (int64_t)it.p * (L == 0 ? S : 1);
+        op.lagColOff[L].push_back(col_cursor);
+        col_cursor += it.nlag + 1;
+        it.lag_off += lag_base;
+        op.items[L].push_back(it);
+      }
+      op.lagT.insert(op.lagT.end(), bo.lagT[L].begin(), bo.lagT[L].end());
+      op.lagCol.insert(op.lagCol.end(), bo.lagCol[L].begin(), bo.lagCol[L].end());
     }
-    op.lagT.insert(op.lagT.end(), bo.lagT.begin(), bo.lagT.end());
-    op.lagCol.insert(op.lagCol.end(), bo.lagCol.begin(), bo.lagCol.end());
     op.arena_elems += f32 ? (int64_t)bo.d32.size() : (int64_t)bo.d64.size();
     op.stored_entries += bo.stored;
     op.dense_entries += bo.dense;
     if (f32) bd32[bi].swap(bo.d32);
     else bd64[bi].swap(bo.d64);
   }
-  if (op.n_partials > INT32_MAX || (int64_t)op.lagT.size() > INT32_MAX)
+  if (op.n_partials[0] > INT32_MAX || op.n_partials[1] > INT32_MAX || (int64_t)op.lagT.size() > INT32_MAX)
     throw Error(SEAS_ERR_INTERNAL, "operator too large for 32-bit item offsets");
-  // reduction lists: partial indices per receiver, in item order
-  op.red_ptr.assign(op.N + 1, 0);
-  for (const Item& it : op.items)
-    for (int i = 0; i < it.p; ++i) op.red_ptr[it.row0 + i + 1]++;
-  for (int r = 0; r < op.N; ++r) op.red_ptr[r + 1] += op.red_ptr[r];
-  op.red_idx.assign(op.red_ptr[op.N], 0);
-  {
-    std::vector<int32_t> cur(op.red_ptr.begin(), op.red_ptr.end() - 1);
-    for (const Item& it : op.items)
-      for (int i = 0; i < it.p; ++i) op.red_idx[cur[it.row0 + i]++] = it.part + i;
+  // reduction lists per receiver, in item order: the base index of the row's
+  // partials (far partials are [p][S], row-major)
+  for (int L = 0; L < 2; ++L) {
+    const int SL = L == 0 ? S : 1;
+    auto& ptr = op.red_ptr[L];
+    auto& idx = op.red_idx[L];
+    ptr.assign(op.N + 1, 0);
+    for (const Item& it : op.items[L])
+      for (int i = 0; i < it.p; ++i) ptr[it.row0 + i + 1]++;
+    for (int r = 0; r < op.N; ++r) ptr[r + 1] += ptr[r];
+    idx.assign(ptr[op.N], 0);
+    std::vector<int32_t> cur(ptr.begin(), ptr.end() - 1);
+    for (const Item& it : op.items[L])
+      for (int i = 0; i < it.p; ++i) idx[cur[it.row0 + i]++] = it.part + i * SL;
   }
   // ---- self term (Section 2.3.1): windows, tables shared by identical faults
   op.self.clear();

@@ -51,8 +51,10 @@ struct Item {
 static_assert(sizeof(Item) == 56, "Item layout");
 
 constexpr int kItemThreads = 256;
-constexpr int kHistMax = 6144;   // max nlag*q history values staged in LDS per item
-constexpr int kColMax = 1024;    // max low-rank columns per item
+constexpr int kHistMax = 6144;   // history values staged in LDS per item: (span of lags + S - 1) * q
+constexpr int kColMax = 1024;    // low-rank columns (and lags) per item
+constexpr int kZMax = 2048;      // low-rank columns times steps per item
+constexpr int kMaxTimeBlock = 16;
 
 // ---------------------------------------------------------------- host operator
 struct PairWin {
@@ -79,15 +81,17 @@ struct HostOp {
   double dt = 0, eta = 0;
   std::vector<PairWin> pairs;
   std::vector<std::vector<BlockDesc>> blocks;  // per pair
-  // work items
-  std::vector<Item> items;
-  std::vector<int32_t> lagT;     // per item: nlag lag values
-  std::vector<int32_t> lagCol;   // per item: nlag+1 column prefix (low rank) (same offset as lagT + item index)
-  std::vector<int32_t> lagColOff;// per item: offset into lagCol
+  // work items: list 0 applied once per block of time_block steps (lags >= S, or
+  // everything when S = 1), list 1 every step (lags 1..S-1 and the static tail)
+  int time_block = 1;
+  std::vector<Item> items[2];
+  std::vector<int32_t> lagT;          // nlag lag values per item (ascending)
+  std::vector<int32_t> lagCol;        // nlag+1 column prefix per item
+  std::vector<int32_t> lagColOff[2];  // per item: offset into lagCol
   int64_t arena_elems = 0;
-  int64_t n_partials = 0;
-  std::vector<int32_t> red_ptr;  // N+1
-  std::vector<int32_t> red_idx;  // partial indices per receiver
+  int64_t n_partials[2] = {0, 0};
+  std::vector<int32_t> red_ptr[2];    // N+1 per list
+  std::vector<int32_t> red_idx[2];    // base partial index of each (receiver, item)
   std::vector<int32_t> tail_off; // per pair: offset of its accumulator; total tail_len
   int64_t tail_len = 0;
   // lag-0 CSR (FP64)

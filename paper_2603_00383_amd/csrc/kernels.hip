@@ -23,70 +23,97 @@ __device__ __forceinline__ int64_t ring_slot(int64_t t, int64_t R) {
 }
 
 // ------------------------------------------------------------------ H-matrix apply
-// y_i = sum_e M[e*p + i] x[e], e in [0, E), for the p rows of an item. The block's
-// threads form G = 256/p groups of p consecutive rows (coalesced row reads); group
-// g takes a contiguous range of e; the G partial rows are added in group order.
-template <typename TF, typename TA>
-__device__ __forceinline__ void rows_accumulate(const TF* __restrict__ M, const TA* __restrict__ x, int E, int p,
-                                                TA* red, double* __restrict__ out) {
+// One work item per workgroup: a run of consecutive lags T_first .. T_first+nl-1
+// of one block (factors contiguous in the arena) applied to S consecutive history
+// windows: window k of lag T reads the rate row of time head + k - T. The item's
+// rows span nl + S - 1 consecutive times and are staged in LDS once, newest
+// first: row rho holds time head + S - 1 - T_first - rho, so lag l, window k is
+// row l + S - 1 - k, and for the dense inner index e = l*q + j the value is
+// h[e + (S-1-k) q].
+//   low rank: z[c][k] = w_c . h(lag(c), k), then y[i][k] = sum_c U[c][i] z[c][k]
+//   dense:    y[i][k] = sum_{l,j} D_l[i][j] h(l, k)[j]
+// Rows are processed by G = 256/p groups of p threads (coalesced factor reads),
+// each over a contiguous range of the inner index; group partials are added in
+// group order. Output: S partial sums per row at out[i * pstride + k].
+
+// acc[k] += sum over e in [e0, e1) of M[e*p + i] * x(e, k)
+template <typename TF, typename TA, int S, typename X>
+__device__ __forceinline__ void accum_rows(const TF* __restrict__ M, int p, int i, int e0, int e1, X x,
+                                           TA (&acc)[S]) {
+  const TF* m = M + (int64_t)e0 * p + i;
+  int e = e0;
+  for (; e + 4 <= e1; e += 4, m += 4 * p) {
+    const TA m0 = (TA)m[0], m1 = (TA)m[p], m2 = (TA)m[2 * p], m3 = (TA)m[3 * p];
+#pragma unroll
+    for (int k = 0; k < S; ++k) acc[k] += m0 * x(e, k) + m1 * x(e + 1, k) + (m2 * x(e + 2, k) + m3 * x(e + 3, k));
+  }
+  for (; e < e1; ++e, m += p) {
+    const TA m0 = (TA)m[0];
+#pragma unroll
+    for (int k = 0; k < S; ++k) acc[k] += m0 * x(e, k);
+  }
+}
+
+template <typename TF, typename TA, int S, typename X>
+__device__ __forceinline__ void rows_apply(const TF* __restrict__ M, int E, int p, X x, TA* red,
+                                           double* __restrict__ out, int pstride) {
   const int tid = threadIdx.x;
   if (p <= kItemThreads) {
     const int G = kItemThreads / p;
     const int g = tid / p, i = tid - g * p;
-    TA acc = 0;
+    TA acc[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) acc[k] = 0;
     if (g < G) {
       const int e0 = (int)((int64_t)E * g / G), e1 = (int)((int64_t)E * (g + 1) / G);
-      const TF* m = M + (int64_t)e0 * p + i;
-      int e = e0;
-      TA a1 = 0, a2 = 0, a3 = 0;
-      for (; e + 4 <= e1; e += 4, m += 4 * p) {
-        acc += (TA)m[0] * x[e];
-        a1 += (TA)m[p] * x[e + 1];
-        a2 += (TA)m[2 * p] * x[e + 2];
-        a3 += (TA)m[3 * p] * x[e + 3];
-      }
-      for (; e < e1; ++e, m += p) acc += (TA)m[0] * x[e];
-      acc = (acc + a1) + (a2 + a3);
+      accum_rows<TF, TA, S>(M, p, i, e0, e1, x, acc);
     }
-    red[tid] = acc;
+    __syncthreads();  // red aliases the staged history
+    if (g < G) {
+#pragma unroll
+      for (int k = 0; k < S; ++k) red[(g * p + i) * S + k] = acc[k];
+    }
     __syncthreads();
-    if (tid < p) {
+    for (int e = tid; e < p * S; e += kItemThreads) {
+      const int ii = e / S, k = e - ii * S;
       TA s = 0;
-      for (int gg = 0; gg < G; ++gg) s += red[gg * p + tid];
-      out[tid] = (double)s;
+      for (int gg = 0; gg < G; ++gg) s += red[(gg * p + ii) * S + k];
+      out[ii * pstride + k] = (double)s;
     }
   } else {
     for (int i = tid; i < p; i += kItemThreads) {
-      TA acc = 0;
-      const TF* m = M + i;
-      for (int e = 0; e < E; ++e, m += p) acc += (TA)m[0] * x[e];
-      out[i] = (double)acc;
+      TA acc[S];
+#pragma unroll
+      for (int k = 0; k < S; ++k) acc[k] = 0;
+      accum_rows<TF, TA, S>(M, p, i, 0, E, x, acc);
+#pragma unroll
+      for (int k = 0; k < S; ++k) out[i * pstride + k] = (double)acc[k];
     }
   }
 }
 
-template <typename TF, typename TA>
+template <typename TF, typename TA, int S>
 __global__ __launch_bounds__(kItemThreads) void k_hmat(const Item* __restrict__ items, const int32_t* __restrict__ lagT,
                                                        const int32_t* __restrict__ lagCol,
                                                        const int32_t* __restrict__ lagColOff,
                                                        const TF* __restrict__ arena, const TF* __restrict__ ring,
                                                        int64_t head, int64_t R, int N,
                                                        const double* __restrict__ tail_acc,
-                                                       double* __restrict__ partials) {
+                                                       double* __restrict__ partials, int pstride) {
   __shared__ TA h[kHistMax];
-  __shared__ TA z[kColMax];
-  __shared__ int collag[kColMax];
-  __shared__ TA red[kItemThreads];
+  __shared__ TA z[kZMax];
+  __shared__ int cl[kColMax];  // lag index of each low-rank column
   const Item it = items[blockIdx.x];
   const int tid = threadIdx.x;
   const int q = it.q, p = it.p, nl = it.nlag;
   if (it.src == 0) {
-    for (int l = 0; l < nl; ++l) {
-      const int64_t slot = ring_slot(head - lagT[it.lag_off + l], R);
-      const TF* row = ring + slot * N + it.col0;
-      for (int j = tid; j < q; j += kItemThreads) h[l * q + j] = (TA)row[j];
+    const int span = nl + S - 1;
+    const int64_t tnew = head + S - 1 - lagT[it.lag_off];
+    for (int e = tid; e < span * q; e += kItemThreads) {
+      const int r = e / q, j = e - r * q;
+      h[e] = (TA)ring[ring_slot(tnew - r, R) * N + it.col0 + j];
     }
-  } else {
+  } else {  // static tail: one row, the pair's expired slip (S = 1)
     for (int j = tid; j < q; j += kItemThreads) h[j] = (TA)tail_acc[it.tail_off + j];
   }
   double* out = partials + it.part;
@@ -95,41 +122,71 @@ __global__ __launch_bounds__(kItemThreads) void k_hmat(const Item* __restrict__ 
     const int nc = it.ncol;
     const int32_t* cp = lagCol + lagColOff[blockIdx.x];
     for (int l = 0; l < nl; ++l)
-      for (int c = cp[l] + tid; c < cp[l + 1]; c += kItemThreads) collag[c] = l;
+      for (int c = cp[l] + tid; c < cp[l + 1]; c += kItemThreads) cl[c] = l;
     __syncthreads();
-    // projection z_c = w_c . h_{lag(c)}; W panel [q][nc], one thread per column
+    // projection, one thread per column; W panel [q][nc]
     for (int c = tid; c < nc; c += kItemThreads) {
-      const TA* hl = h + collag[c] * q;
+      const TA* hc = h + (cl[c] + S - 1) * q;  // window k is hc - k q
       const TF* w = base + c;
-      TA acc = 0, a1 = 0;
-      int j = 0;
-      for (; j + 2 <= q; j += 2) {
-        acc += (TA)w[(int64_t)j * nc] * hl[j];
-        a1 += (TA)w[(int64_t)(j + 1) * nc] * hl[j + 1];
+      TA acc[S];
+#pragma unroll
+      for (int k = 0; k < S; ++k) acc[k] = 0;
+      for (int j = 0; j < q; ++j) {
+        const TA wv = (TA)w[(int64_t)j * nc];
+#pragma unroll
+        for (int k = 0; k < S; ++k) acc[k] += wv * hc[j - k * q];
       }
-      if (j < q) acc += (TA)w[(int64_t)j * nc] * hl[j];
-      z[c] = acc + a1;
+#pragma unroll
+      for (int k = 0; k < S; ++k) z[c * S + k] = acc[k];
     }
     __syncthreads();
     // expansion y = U z; U panel [nc][p]
-    rows_accumulate<TF, TA>(base + (int64_t)q * nc, z, nc, p, red, out);
+    rows_apply<TF, TA, S>(base + (int64_t)q * nc, nc, p, [&](int c, int k) { return z[c * S + k]; }, h, out,
+                          pstride);
   } else {
     __syncthreads();
-    rows_accumulate<TF, TA>(base, h, nl * q, p, red, out);
+    // inner index e = l*q + j over [nlag][q][p]
+    rows_apply<TF, TA, S>(base, nl * q, p, [&](int e, int k) { return h[e + (S - 1 - k) * q]; }, h, out,
+                          pstride);
   }
 }
 
 // One 64-lane wave per receiver: lanes stride over the receiver's partial list,
 // then a butterfly sum (fixed order, independent of scheduling).
-__global__ void k_reduce(const double* __restrict__ partials, const int32_t* __restrict__ ptr,
-                         const int32_t* __restrict__ idx, int N, double neg_eta, double* __restrict__ f) {
+// Far partials: S values per (item, row); f_far[k*N + r] = -eta sum.
+template <int S>
+__global__ void k_reduce_far(const double* __restrict__ partials, const int32_t* __restrict__ ptr,
+                             const int32_t* __restrict__ idx, int N, double neg_eta, double* __restrict__ f) {
+  const int lane = threadIdx.x & 63;
+  const int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (r >= N) return;
+  double s[S];
+#pragma unroll
+  for (int k = 0; k < S; ++k) s[k] = 0.0;
+  for (int e = ptr[r] + lane; e < ptr[r + 1]; e += 64) {
+    const double* pp = partials + idx[e];
+#pragma unroll
+    for (int k = 0; k < S; ++k) s[k] += pp[k];
+  }
+#pragma unroll
+  for (int k = 0; k < S; ++k) {
+    double v = s[k];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) f[(int64_t)k * N + r] = neg_eta * v;
+  }
+}
+
+// Near partials (one per row): f[r] = -eta sum + base[r].
+__global__ void k_reduce_near(const double* __restrict__ partials, const int32_t* __restrict__ ptr,
+                              const int32_t* __restrict__ idx, int N, double neg_eta,
+                              const double* __restrict__ base, double* __restrict__ f) {
   const int lane = threadIdx.x & 63;
   const int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (r >= N) return;
   double s = 0.0;
-  for (int k = ptr[r] + lane; k < ptr[r + 1]; k += 64) s += partials[idx[k]];
+  for (int e = ptr[r] + lane; e < ptr[r + 1]; e += 64) s += partials[idx[e]];
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-  if (lane == 0) f[r] = neg_eta * s;
+  if (lane == 0) f[r] = neg_eta * s + base[r];
 }
 
 // ------------------------------------------------------------------ self term
@@ -319,24 +376,57 @@ __global__ void k_pre_out(StepArgs<TF> a, const double* __restrict__ Vprev, doub
 // ------------------------------------------------------------------ launchers
 static inline int blocks_for(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
-void launch_hmat(const HostOp& h, const void* items, const int32_t* lagT, const int32_t* lagCol,
-                 const int32_t* lagColOff, const void* arena, const void* ring, int64_t head,
-                 const double* tail_acc, double* partials, hipStream_t s) {
-  const int n = (int)h.items.size();
-  if (n == 0) return;
-  if (h.prm.factor_dtype == SEAS_F64)
-    hipLaunchKernelGGL((k_hmat<double, double>), dim3(n), dim3(kItemThreads), 0, s, (const Item*)items, lagT,
-                       lagCol, lagColOff, (const double*)arena, (const double*)ring, head, (int64_t)h.ring_len, h.N,
-                       tail_acc, partials);
-  else
-    hipLaunchKernelGGL((k_hmat<float, float>), dim3(n), dim3(kItemThreads), 0, s, (const Item*)items, lagT, lagCol,
-                       lagColOff, (const float*)arena, (const float*)ring, head, (int64_t)h.ring_len, h.N, tail_acc,
-                       partials);
+template <typename TF, int S>
+static void hmat_s(int n, const void* items, const int32_t* lagT, const int32_t* lagCol, const int32_t* lagColOff,
+                   const void* arena, const void* ring, int64_t head, int64_t R, int N, const double* tail_acc,
+                   double* partials, int pstride, hipStream_t s) {
+  hipLaunchKernelGGL((k_hmat<TF, TF, S>), dim3(n), dim3(kItemThreads), 0, s, (const Item*)items, lagT, lagCol,
+                     lagColOff, (const TF*)arena, (const TF*)ring, head, R, N, tail_acc, partials, pstride);
 }
 
-void launch_reduce(const HostOp& h, const double* partials, const int32_t* ptr, const int32_t* idx, double* f,
-                   hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3(blocks_for(h.N, 4)), dim3(256), 0, s, partials, ptr, idx, h.N, -h.eta, f);
+template <typename TF>
+static void hmat_t(int S, int n, const void* items, const int32_t* lagT, const int32_t* lagCol,
+                   const int32_t* lagColOff, const void* arena, const void* ring, int64_t head, int64_t R, int N,
+                   const double* tail_acc, double* partials, int ps, hipStream_t s) {
+  switch (S) {
+    case 1: hmat_s<TF, 1>(n, items, lagT, lagCol, lagColOff, arena, ring, head, R, N, tail_acc, partials, ps, s); break;
+    case 2: hmat_s<TF, 2>(n, items, lagT, lagCol, lagColOff, arena, ring, head, R, N, tail_acc, partials, ps, s); break;
+    case 4: hmat_s<TF, 4>(n, items, lagT, lagCol, lagColOff, arena, ring, head, R, N, tail_acc, partials, ps, s); break;
+    case 8: hmat_s<TF, 8>(n, items, lagT, lagCol, lagColOff, arena, ring, head, R, N, tail_acc, partials, ps, s); break;
+    case 16: hmat_s<TF, 16>(n, items, lagT, lagCol, lagColOff, arena, ring, head, R, N, tail_acc, partials, ps, s); break;
+    default: break;
+  }
+}
+
+void launch_hmat(const HostOp& h, int S, int n_items, const void* items, const int32_t* lagT, const int32_t* lagCol,
+                 const int32_t* lagColOff, const void* arena, const void* ring, int64_t head,
+                 const double* tail_acc, double* partials, int pstride, hipStream_t s) {
+  if (n_items == 0) return;
+  if (h.prm.factor_dtype == SEAS_F64)
+    hmat_t<double>(S, n_items, items, lagT, lagCol, lagColOff, arena, ring, head, h.ring_len, h.N, tail_acc,
+                   partials, pstride, s);
+  else
+    hmat_t<float>(S, n_items, items, lagT, lagCol, lagColOff, arena, ring, head, h.ring_len, h.N, tail_acc,
+                  partials, pstride, s);
+}
+
+void launch_reduce_far(const HostOp& h, int S, const double* partials, const int32_t* ptr, const int32_t* idx,
+                       double* f, hipStream_t s) {
+  const dim3 g(blocks_for(h.N, 4)), b(256);
+  switch (S) {
+    case 1: hipLaunchKernelGGL(k_reduce_far<1>, g, b, 0, s, partials, ptr, idx, h.N, -h.eta, f); break;
+    case 2: hipLaunchKernelGGL(k_reduce_far<2>, g, b, 0, s, partials, ptr, idx, h.N, -h.eta, f); break;
+    case 4: hipLaunchKernelGGL(k_reduce_far<4>, g, b, 0, s, partials, ptr, idx, h.N, -h.eta, f); break;
+    case 8: hipLaunchKernelGGL(k_reduce_far<8>, g, b, 0, s, partials, ptr, idx, h.N, -h.eta, f); break;
+    case 16: hipLaunchKernelGGL(k_reduce_far<16>, g, b, 0, s, partials, ptr, idx, h.N, -h.eta, f); break;
+    default: break;
+  }
+}
+
+void launch_reduce_near(const HostOp& h, const double* partials, const int32_t* ptr, const int32_t* idx,
+                        const double* base, double* f, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_near, dim3(blocks_for(h.N, 4)), dim3(256), 0, s, partials, ptr, idx, h.N, -h.eta, base,
+                     f);
 }
 
 void launch_self_hist(int n_modes, const SelfMode* modes, const double* tab, const double2* dring, int64_t time0,

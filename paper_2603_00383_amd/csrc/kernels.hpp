@@ -55,11 +55,13 @@ struct StepArgs {
   int tail;                 // static tail on
 };
 
-void launch_hmat(const HostOp& h, const void* items, const int32_t* lagT, const int32_t* lagCol,
+void launch_hmat(const HostOp& h, int S, int n_items, const void* items, const int32_t* lagT, const int32_t* lagCol,
                  const int32_t* lagColOff, const void* arena, const void* ring, int64_t head,
-                 const double* tail_acc, double* partials, hipStream_t s);
-void launch_reduce(const HostOp& h, const double* partials, const int32_t* ptr, const int32_t* idx, double* f,
-                   hipStream_t s);
+                 const double* tail_acc, double* partials, int pstride, hipStream_t s);
+void launch_reduce_far(const HostOp& h, int S, const double* partials, const int32_t* ptr, const int32_t* idx,
+                       double* f, hipStream_t s);
+void launch_reduce_near(const HostOp& h, const double* partials, const int32_t* ptr, const int32_t* idx,
+                        const double* base, double* f, hipStream_t s);
 void launch_self_hist(int n_modes, const SelfMode* modes, const double* tab, const double2* dring, int64_t time0,
                       double2* Fh, hipStream_t s);
 void launch_dft(int n_modes, const SelfMode* modes, const SelfFaultDev* sf, const double* delta, const double* vel,

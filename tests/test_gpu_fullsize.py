@@ -25,7 +25,7 @@ def fullsize():
     if not torch.cuda.is_available():
         pytest.skip("no HIP device")
     faults = SI.five_fault_network(seed=0)
-    params = SI.default_params(factor_dtype="f32", aca_tol=1e-6, eta_H=2.0, leaf=50)
+    params = SI.default_params(factor_dtype="f32", aca_tol=1e-6, eta_H=2.0, leaf=50, time_block=8)
     print("[gpu] building the five-fault operator", flush=True)
     op = P.Operator(faults, params)
     prior = SI.saturated_history(faults, op.info["max_lag"] + 2, 0)
@@ -65,7 +65,7 @@ def test_fullsize_seas_step_history_part(fullsize):
     st.load_history(prior, stream=s)
     st.step(1, stream=s)
     st.check(stream=s)
-    g = st.read("f_hist", stream=s)
+    g = st.read("f_hist", stream=s)      # first step of a time block: far and near parts
     Vh = np.concatenate([prior, ini["V"][None, :]])
     ref = OI.stress_rows(oracle.geo, ROWS, Vh, 0, -len(prior), oracle.mu, oracle.cs, oracle.dt,
                          params["eta_tmin"], params["eta_tmax"], min_lag=1, with_tail=True)

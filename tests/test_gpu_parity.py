@@ -67,10 +67,10 @@ def oracle_prescribed(key, faults, params, V, prior=None):
 C1 = SI.two_fault_prescribed_faults()
 
 
-@pytest.mark.parametrize("seed", [0, 1])
-def test_two_fault_prescribed_fp64_uncompressed(seed):
+@pytest.mark.parametrize("seed,S", [(0, 1), (1, 1), (0, 8)])
+def test_two_fault_prescribed_fp64_uncompressed(seed, S):
     V = SI.prescribed_slip_rate(C1, 256, seed)
-    p = SI.default_params(compress=0)
+    p = SI.default_params(compress=0, time_block=S)
     f, op = gpu_prescribed(C1, p, V)
     ref = oracle_prescribed(("c1", seed), C1, p, V)
     assert op.info["lag0_nnz"] > 0          # the faults intersect: lag-0 coupling exercised
@@ -107,11 +107,11 @@ RAG = [SI.fault(0, 0, 5.0, 1300.0, 13), SI.fault(300.0, 900.0, 70.0, 2900.0, 29)
        SI.fault(-1500.0, 2200.0, 140.0, 2000.0, 40)]
 
 
-@pytest.mark.parametrize("tail", [1, 0])
-def test_ragged_network_with_prior_history(tail):
+@pytest.mark.parametrize("tail,S", [(1, 1), (0, 1), (1, 4), (1, 16)])
+def test_ragged_network_with_prior_history(tail, S):
     # odd sizes, leaf 5 (many tiny blocks), history longer than every window so that
     # slip expires into the static tail; a prior history before t = 0
-    p = SI.default_params(compress=1, aca_tol=1e-13, eta_H=1.5, leaf=5, int_tail=tail)
+    p = SI.default_params(compress=1, aca_tol=1e-13, eta_H=1.5, leaf=5, int_tail=tail, time_block=S)
     n_steps = 140
     V = SI.prescribed_slip_rate(RAG, n_steps, 7, lo_exp=-6, hi_exp=0)
     prior = SI.prescribed_slip_rate(RAG, 90, 8, lo_exp=-6, hi_exp=0)
@@ -119,7 +119,7 @@ def test_ragged_network_with_prior_history(tail):
     assert op.info["max_lag"] < n_steps + len(prior) - 20     # slip expires into the tail
     ref = oracle_prescribed(("rag", tail), RAG, p, V, prior)
     e = rel_err(f, ref)
-    print(f"[gpu] ragged tail={tail}: err {e:.3e}")
+    print(f"[gpu] ragged tail={tail} S={S}: err {e:.3e}")
     assert e < 1e-10
 
 
@@ -162,13 +162,14 @@ def _oracle_seas(faults, params, fric, ini, prior, n_steps):
     return st
 
 
-def test_seas_trajectory_two_faults():
+@pytest.mark.parametrize("S", [1, 8])
+def test_seas_trajectory_two_faults(S):
     faults = SI.two_fault_prescribed_faults(n_elem=24, dx=50.0)
-    p = SI.default_params(compress=0)
+    p = SI.default_params(compress=0, time_block=S)
     fric, ini, _ = _seas_setup(faults, 0, V_init=1e-6, bump=0.1)
     g, _, _ = _gpu_seas(faults, p, fric, ini, None, 120, ("V", "theta", "delta", "f_self", "f_int"))
     o = _oracle_seas(faults, p, fric, ini, None, 120)
-    print("[gpu] seas two-fault 120 steps: " + ", ".join(
+    print(f"[gpu] seas two-fault 120 steps S={S}: " + ", ".join(
         f"{k} {rel_err(g[k], v):.2e}" for k, v in (("V", o.V), ("theta", o.theta), ("delta", o.delta))))
     assert rel_err(g["V"], o.V) < 1e-9
     assert rel_err(g["theta"], o.theta) < 1e-9
@@ -177,13 +178,14 @@ def test_seas_trajectory_two_faults():
     assert rel_err(g["f_int"], o.last["f_int"]) < 1e-9
 
 
-def test_seas_step_from_saturated_history_five_faults():
+@pytest.mark.parametrize("S", [1, 4])
+def test_seas_step_from_saturated_history_five_faults(S):
     faults = SI.five_fault_network(seed=0, n_elem=24)
-    p = SI.default_params(compress=1, aca_tol=1e-13, eta_H=2.0, leaf=6)
+    p = SI.default_params(compress=1, aca_tol=1e-13, eta_H=2.0, leaf=6, time_block=S)
     fric, ini, prior = _seas_setup(faults, 0, prior_len=160)
-    g, _, op = _gpu_seas(faults, p, fric, ini, prior, 3, ("V", "theta", "delta", "f_hist"))
+    g, _, op = _gpu_seas(faults, p, fric, ini, prior, 6, ("V", "theta", "delta", "f_hist"))
     assert op.info["max_lag"] < 160
-    o = _oracle_seas(faults, p, fric, ini, prior, 3)
+    o = _oracle_seas(faults, p, fric, ini, prior, 6)
     print(f"[gpu] seas five-fault saturated: f_hist {rel_err(g['f_hist'], o.last['f_hist']):.2e} "
           f"V {rel_err(g['V'], o.V):.2e}")
     assert rel_err(g["f_hist"], o.last["f_hist"]) < 1e-10
@@ -192,9 +194,11 @@ def test_seas_step_from_saturated_history_five_faults():
     assert rel_err(g["delta"], o.delta) < 1e-10
 
 
-def test_checkpoint_resume_is_bitwise():
+@pytest.mark.parametrize("S", [1, 8])
+def test_checkpoint_resume_is_bitwise(S):
+    # with S = 8 the checkpoint is taken in the middle of a time block
     faults = SI.two_fault_prescribed_faults(n_elem=16, dx=50.0)
-    p = SI.default_params()
+    p = SI.default_params(time_block=S)
     fric, ini, _ = _seas_setup(faults, 1, V_init=1e-6, bump=0.1)
     op = P.Operator(faults, p)
     s = _stream()
@@ -235,3 +239,24 @@ def test_kernel_timing_counts_launches():
     st.step(7, stream=s)
     ms, n = st.read_timing(stream=s)
     assert n == 7 and ms > 0
+
+
+def test_plain_and_blocked_orders_agree():
+    # one operator built with S = 8, evaluated once per step (S = 1) and per block
+    faults = SI.five_fault_network(seed=2, n_elem=32)
+    p = SI.default_params(aca_tol=1e-8, factor_dtype="f32", time_block=8)
+    V = SI.prescribed_slip_rate(faults, 40, 3, lo_exp=-6, hi_exp=0)
+    out = []
+    for S in (1, 8):
+        op = P.Operator(faults, p)
+        N = op.N
+        st = P.State(op, _dummy_friction(N), np.full(N, 1e-9), np.full(N, 5e6), np.zeros(N), stream=_stream())
+        st.set_time_block(S)
+        Vd = torch.from_numpy(V).cuda()
+        fd = torch.empty_like(Vd)
+        st.eval_prescribed(Vd, 40, fd, stream=_stream())
+        torch.cuda.synchronize()
+        out.append(fd.cpu().numpy())
+    e = rel_err(out[1], out[0])
+    print(f"[gpu] plain vs blocked (FP32): {e:.2e}")
+    assert e < 1e-6

@@ -68,11 +68,14 @@ def test_self_tables_match_oracle():
     assert worst < 1e-12
 
 
-@pytest.mark.parametrize("compress", [0, 1])
-def test_lag_matrices_match_dense_kernel(compress):
+@pytest.mark.parametrize("compress,S", [(0, 1), (1, 1), (1, 4), (0, 16)])
+def test_lag_matrices_match_dense_kernel(compress, S):
     faults = SI.two_fault_prescribed_faults(n_elem=64, dx=200.0)
     tol = 1e-6
-    op = _op(faults, compress=compress, aca_tol=tol, eta_H=1.0, leaf=16)
+    op = _op(faults, compress=compress, aca_tol=tol, eta_H=1.0, leaf=16, time_block=S)
+    assert op.info["time_block"] == S
+    if S > 1:
+        assert op.info["n_items_near"] > 0
     geo = geometry.discretize(faults)
     dt = geometry.time_step(geo, SI.CS)
     for (a, b), (t0, t1) in op.windows().items():
@@ -131,3 +134,21 @@ def test_host_only_operator_refuses_evaluation():
     with pytest.raises(P.SeasError) as e:
         P.State(op, fr, np.full(n, 1e-9), np.full(n, 5e6), np.full(n, 3e7))
     assert e.value.code == -5
+
+
+@pytest.mark.slow
+def test_wide_cluster_is_split_into_column_slices():
+    # two parallel 400-element faults whose root clusters are admissible: with
+    # S = 16 the 400-wide source cluster exceeds the kernel's history buffer and is
+    # packed as column slices, each compressed on its own
+    faults = [SI.fault(0, 0, 0, 400.0, 400), SI.fault(0, 100.0, 0, 400.0, 400)]
+    op = _op(faults, compress=1, aca_tol=1e-6, eta_H=0.2, leaf=50, time_block=16)
+    assert op.blocks(0, 1) == [(0, 400, 0, 400, True)]
+    geo = geometry.discretize(faults)
+    dt = geometry.time_step(geo, SI.CS)
+    t0, t1 = op.windows()[(0, 1)]
+    for T in (t0 + 5, t0 + 40, (t0 + t1) // 2):
+        K = I.pair_kernel(geo, 0, 1, T, dt, SI.CS)
+        R = op.lag_matrix(0, 1, T, 400, 400)
+        assert np.linalg.norm(K) > 0
+        assert np.linalg.norm(R - K) / np.linalg.norm(K) < 3e-6
