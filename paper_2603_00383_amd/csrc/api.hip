@@ -199,10 +199,10 @@ void eval_history(seas_op* op, seas_state* st, int64_t head, hipStream_t s) {
                 st->tail_acc, st->partials_far, S, s);
     record_stop(st, s);
     if (nnear == 0) {
-      launch_reduce_far(h, 1, st->partials_far, op->red_ptr[0], op->red_idx[0], st->f_hist, s);
+      launch_reduce_far(h, 1, st->partials_far, false, op->red_ptr[0], op->red_idx[0], st->f_hist, s);
       return;
     }
-    launch_reduce_far(h, 1, st->partials_far, op->red_ptr[0], op->red_idx[0], st->f_far, s);
+    launch_reduce_far(h, 1, st->partials_far, false, op->red_ptr[0], op->red_idx[0], st->f_far, s);
     st->block_head = INT64_MIN / 2;
     launch_hmat(h, 1, nnear, op->items[1], op->lagT, op->lagCol, op->lagColOff[1], op->arena, st->ringop, head,
                 st->tail_acc, st->partials_near, 1, s);
@@ -215,7 +215,7 @@ void eval_history(seas_op* op, seas_state* st, int64_t head, hipStream_t s) {
     launch_hmat(h, S, nfar, op->items[0], op->lagT, op->lagCol, op->lagColOff[0], op->arena, st->ringop, head,
                 st->tail_acc, st->partials_far, S, s);
     record_stop(st, s);
-    launch_reduce_far(h, S, st->partials_far, op->red_ptr[0], op->red_idx[0], st->f_far, s);
+    launch_reduce_far(h, S, st->partials_far, far_partials_f32(h, S), op->red_ptr[0], op->red_idx[0], st->f_far, s);
     st->block_head = head;
     k = 0;
   }

@@ -476,6 +476,7 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
       (prm.time_block & (prm.time_block - 1)) != 0)
     throw Error(SEAS_ERR_INVALID_ARG, "time_block must be 0, 1, 2, 4, 8 or 16");
   op.time_block = prm.time_block > 0 ? prm.time_block : 1;
+  op.use_mfma = std::getenv("SEAS_NO_MFMA") == nullptr;
   if (prm.n_threads > 0) omp_set_num_threads(prm.n_threads);
   // ---- geometry
   op.faults.clear();

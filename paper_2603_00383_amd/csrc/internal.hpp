@@ -84,6 +84,7 @@ struct HostOp {
   // work items: list 0 applied once per block of time_block steps (lags >= S, or
   // everything when S = 1), list 1 every step (lags 1..S-1 and the static tail)
   int time_block = 1;
+  bool use_mfma = true;               // FP32, S = 16 far list on the matrix cores
   std::vector<Item> items[2];
   std::vector<int32_t> lagT;          // nlag lag values per item (ascending)
   std::vector<int32_t> lagCol;        // nlag+1 column prefix per item

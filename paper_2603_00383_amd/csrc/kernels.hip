@@ -36,16 +36,22 @@ __device__ __forceinline__ int64_t ring_slot(int64_t t, int64_t R) {
 // each over a contiguous range of the inner index; group partials are added in
 // group order. Output: S partial sums per row at out[i * pstride + k].
 
-// acc[k] += sum over e in [e0, e1) of M[e*p + i] * x(e, k)
+// acc[k] += sum over e in [e0, e1) of M[e*p + i] * x(e, k); 8 factor loads are
+// issued before their multiply-adds so that enough bytes are in flight per CU.
 template <typename TF, typename TA, int S, typename X>
 __device__ __forceinline__ void accum_rows(const TF* __restrict__ M, int p, int i, int e0, int e1, X x,
                                            TA (&acc)[S]) {
   const TF* m = M + (int64_t)e0 * p + i;
   int e = e0;
-  for (; e + 4 <= e1; e += 4, m += 4 * p) {
-    const TA m0 = (TA)m[0], m1 = (TA)m[p], m2 = (TA)m[2 * p], m3 = (TA)m[3 * p];
+  for (; e + 8 <= e1; e += 8, m += 8 * p) {
+    TA mv[8];
 #pragma unroll
-    for (int k = 0; k < S; ++k) acc[k] += m0 * x(e, k) + m1 * x(e + 1, k) + (m2 * x(e + 2, k) + m3 * x(e + 3, k));
+    for (int u = 0; u < 8; ++u) mv[u] = (TA)m[u * p];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+#pragma unroll
+      for (int k = 0; k < S; ++k) acc[k] += mv[u] * x(e + u, k);
+    }
   }
   for (; e < e1; ++e, m += p) {
     const TA m0 = (TA)m[0];
@@ -151,11 +157,209 @@ __global__ __launch_bounds__(kItemThreads) void k_hmat(const Item* __restrict__ 
   }
 }
 
+// ------------------------------------------------------------------ MFMA form
+// FP32 factors with S = 16 windows: every item is a skinny GEMM with N = 16
+// (the windows), run on the matrix cores with v_mfma_f32_16x16x4_f32. For one
+// 16x16 output tile and 4 consecutive inner indices e:
+//   A operand (16 rows x 4): lane l holds A[row l%16][e + l/16]
+//   B operand (4 x 16):      lane l holds B[e + l/16][window l%16]
+//   accumulator: lane l, register v holds Y[row 4 (l/16) + v][window l%16]
+// so a factor element is read once from HBM and used 16 times, and the history
+// comes from LDS once per 16 multiply-adds.
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
+template <typename FA, typename FB>
+__device__ __forceinline__ mfma_f4 mfma_run(int e0, int e1, FA A, FB B, mfma_f4 acc, int lane) {
+  const int sub = lane >> 4, col = lane & 15;
+  for (int e = e0; e < e1; e += 16) {  // 4 steps of 4, operands loaded first
+    float a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int ee = e + 4 * u + sub;
+      const bool ok = ee < e1;
+      a[u] = ok ? A(ee, col) : 0.0f;
+      b[u] = ok ? B(ee, col) : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b[u], acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// One super-tile of TW consecutive 16-row tiles (rows t0*16 ..) over the inner
+// range [e0, e1): the operands of 4 inner steps (TW factor loads + 1 history load
+// each) are issued before their MFMAs so that enough bytes are in flight.
+template <int TW, typename FB>
+__device__ __forceinline__ void mfma_supertile(const float* __restrict__ M, int p, int t0, int e0, int e1, FB B,
+                                               mfma_f4 (&acc)[TW], int lane) {
+  constexpr int PF = TW <= 4 ? 4 : 2;  // inner steps whose operands are loaded ahead
+  const int sub = lane >> 4, col = lane & 15;
+#pragma unroll
+  for (int u = 0; u < TW; ++u) acc[u] = mfma_f4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int e = e0; e < e1; e += 4 * PF) {
+    float a[PF][TW], b[PF];
+#pragma unroll
+    for (int w4 = 0; w4 < PF; ++w4) {
+      const int ee = e + 4 * w4 + sub;
+      const bool ok = ee < e1;
+      b[w4] = ok ? B(ee, col) : 0.0f;
+      const float* row = M + (int64_t)ee * p + t0 * 16 + col;
+#pragma unroll
+      for (int u = 0; u < TW; ++u) a[w4][u] = (ok && (t0 + u) * 16 + col < p) ? row[u * 16] : 0.0f;
+    }
+#pragma unroll
+    for (int w4 = 0; w4 < PF; ++w4) {
+#pragma unroll
+      for (int u = 0; u < TW; ++u) acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[w4][u], b[w4], acc[u], 0, 0, 0);
+    }
+  }
+}
+
+template <int TW>
+__device__ __forceinline__ void mfma_store(const mfma_f4 (&acc)[TW], int p, int t0, float* __restrict__ out,
+                                           int pstride, int lane) {
+#pragma unroll
+  for (int u = 0; u < TW; ++u) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = (t0 + u) * 16 + 4 * (lane >> 4) + v;
+      if (i < p) out[i * pstride + (lane & 15)] = acc[u][v];
+    }
+  }
+}
+
+// Y (p x 16) = sum_e M[e*p + i] B(e, k), e in [0, E), on the matrix cores.
+// Small blocks (at most 3 row tiles of 16): the 4 waves take a quarter of the
+// inner range each over all row tiles, and their partial tiles are added in wave
+// order through LDS (red, which aliases the staged history, needs 3072 floats).
+// Larger blocks: each wave takes super-tiles of up to 8 consecutive row tiles
+// over the whole inner range, so one B fragment feeds up to 8 MFMAs and the
+// factor loads of consecutive tiles are contiguous.
+template <typename FB>
+__device__ __forceinline__ void mfma_rows(const float* __restrict__ M, int E, int p, FB B, float* red,
+                                          float* __restrict__ out, int pstride) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int RT = (p + 15) >> 4;
+  if (RT <= 3) {
+    const int e0 = ((int)((int64_t)E * wave / 4)) & ~3;
+    const int e1 = wave == 3 ? E : (((int)((int64_t)E * (wave + 1) / 4)) & ~3);
+    float part[3][4] = {};
+    if (RT == 1) {
+      mfma_f4 acc[1];
+      mfma_supertile<1>(M, p, 0, e0, e1, B, acc, lane);
+      for (int v = 0; v < 4; ++v) part[0][v] = acc[0][v];
+    } else if (RT == 2) {
+      mfma_f4 acc[2];
+      mfma_supertile<2>(M, p, 0, e0, e1, B, acc, lane);
+      for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 4; ++v) part[u][v] = acc[u][v];
+    } else {
+      mfma_f4 acc[3];
+      mfma_supertile<3>(M, p, 0, e0, e1, B, acc, lane);
+      for (int u = 0; u < 3; ++u)
+        for (int v = 0; v < 4; ++v) part[u][v] = acc[u][v];
+    }
+    __syncthreads();  // every wave is done with the history that red aliases
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      if (u < RT) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[(wave * 3 + u) * 256 + lane * 4 + v] = part[u][v];
+      }
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < RT * 256; x += kItemThreads) {
+      const int u = x >> 8, w = x & 255, ln = w >> 2, v = w & 3;
+      float sum = 0.0f;
+      for (int wv = 0; wv < 4; ++wv) sum += red[(wv * 3 + u) * 256 + ln * 4 + v];
+      const int i = u * 16 + 4 * (ln >> 4) + v;
+      if (i < p) out[i * pstride + (ln & 15)] = sum;
+    }
+    return;
+  }
+  const int TW = min(8, (RT + 3) / 4);
+  const int NST = (RT + TW - 1) / TW;
+  for (int st = wave; st < NST; st += 4) {
+    const int t0 = st * TW, tw = min(TW, RT - t0);
+#define SEAS_TW_CASE(n)                                      \
+  case n: {                                                  \
+    mfma_f4 acc[n];                                          \
+    mfma_supertile<n>(M, p, t0, 0, E, B, acc, lane);         \
+    mfma_store<n>(acc, p, t0, out, pstride, lane);           \
+  } break;
+    switch (tw) {
+      SEAS_TW_CASE(1)
+      SEAS_TW_CASE(2)
+      SEAS_TW_CASE(3)
+      SEAS_TW_CASE(4)
+      SEAS_TW_CASE(5)
+      SEAS_TW_CASE(6)
+      SEAS_TW_CASE(7)
+      SEAS_TW_CASE(8)
+      default: break;
+    }
+#undef SEAS_TW_CASE
+  }
+}
+
+__global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_hmat_mfma16(const Item* __restrict__ items,
+                                                              const int32_t* __restrict__ lagT,
+                                                              const int32_t* __restrict__ lagCol,
+                                                              const int32_t* __restrict__ lagColOff,
+                                                              const float* __restrict__ arena,
+                                                              const float* __restrict__ ring, int64_t head,
+                                                              int64_t R, int N, float* __restrict__ partials,
+                                                              int pstride) {
+  constexpr int S = 16;
+  __shared__ float h[kHistMax];
+  __shared__ float z[kZMax];
+  const Item it = items[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int q = it.q, p = it.p, nl = it.nlag;
+  {
+    const int span = nl + S - 1;
+    const int64_t tnew = head + S - 1 - lagT[it.lag_off];
+    for (int e = tid; e < span * q; e += kItemThreads) {
+      const int r = e / q, j = e - r * q;
+      h[e] = ring[ring_slot(tnew - r, R) * N + it.col0 + j];
+    }
+  }
+  float* out = partials + it.part;
+  const float* base = arena + it.data;
+  __syncthreads();
+  if (it.kind == 0) {
+    const int nc = it.ncol;
+    const int32_t* cp = lagCol + lagColOff[blockIdx.x];
+    // projection per lag: Z_l (k_l x 16) = W_l^T H_l, column tiles of 16 spread over waves
+    int tile = 0;
+    for (int l = 0; l < nl; ++l) {
+      const int cb = cp[l], ce = cp[l + 1];
+      for (int c0 = cb; c0 < ce; c0 += 16, ++tile) {
+        if ((tile & 3) != wave) continue;
+        const float* hl = h + (l + S - 1) * q;  // window k is hl - k q
+        mfma_f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        acc = mfma_run(0, q,
+                       [&](int j, int c) { const int cc = c0 + c; return cc < ce ? base[(int64_t)j * nc + cc] : 0.0f; },
+                       [&](int j, int k) { return hl[j - k * q]; }, acc, lane);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int cc = c0 + 4 * (lane >> 4) + v;
+          if (cc < ce) z[cc * S + (lane & 15)] = acc[v];
+        }
+      }
+    }
+    __syncthreads();
+    mfma_rows(base + (int64_t)q * nc, nc, p, [&](int c, int k) { return z[c * S + k]; }, h, out, pstride);
+  } else {
+    mfma_rows(base, nl * q, p, [&](int e, int k) { return h[e + (S - 1 - k) * q]; }, h, out, pstride);
+  }
+}
+
 // One 64-lane wave per receiver: lanes stride over the receiver's partial list,
 // then a butterfly sum (fixed order, independent of scheduling).
 // Far partials: S values per (item, row); f_far[k*N + r] = -eta sum.
-template <int S>
-__global__ void k_reduce_far(const double* __restrict__ partials, const int32_t* __restrict__ ptr,
+template <int S, typename TP>
+__global__ void k_reduce_far(const TP* __restrict__ partials, const int32_t* __restrict__ ptr,
                              const int32_t* __restrict__ idx, int N, double neg_eta, double* __restrict__ f) {
   const int lane = threadIdx.x & 63;
   const int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -164,9 +368,9 @@ __global__ void k_reduce_far(const double* __restrict__ partials, const int32_t*
 #pragma unroll
   for (int k = 0; k < S; ++k) s[k] = 0.0;
   for (int e = ptr[r] + lane; e < ptr[r + 1]; e += 64) {
-    const double* pp = partials + idx[e];
+    const TP* pp = partials + idx[e];
 #pragma unroll
-    for (int k = 0; k < S; ++k) s[k] += pp[k];
+    for (int k = 0; k < S; ++k) s[k] += (double)pp[k];
   }
 #pragma unroll
   for (int k = 0; k < S; ++k) {
@@ -212,30 +416,37 @@ __global__ void k_self_hist(const SelfMode* __restrict__ modes, int n_modes, con
   if (lane == 0) Fh[gm] = make_double2(re, im);
 }
 
-// D_n = sum_j x_j e^{-2 pi i n j / M}, x = delta + coef * vel (vel may be null);
-// F_n = -cfac n (K_n^0 D_n + Fh_n); optionally D_n is stored in the mode's ring at
-// push_time, which must lie in the window (ring_head - W_n, ring_head] of the
-// ring's newest time ring_head (older times would overwrite newer slots).
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;  // every lane holds the total (fixed butterfly order)
+}
+
+// One 64-lane wave per mode: D_n = sum_j x_j e^{-2 pi i n j / M}, x = delta + coef
+// vel (vel may be null), lanes strided over j; F_n = -cfac n (K_n^0 D_n + Fh_n).
+// Optionally D_n is stored in the mode's ring at push_time, which must lie in
+// the window (ring_head - W_n, ring_head] of the ring's newest time ring_head
+// (older times would overwrite newer slots).
 __global__ void k_dft(const SelfMode* __restrict__ modes, int n_modes, const SelfFaultDev* __restrict__ sf,
                       const double* __restrict__ delta, const double* __restrict__ vel, double coef,
                       const double2* __restrict__ tw, const double* __restrict__ tab,
                       const double2* __restrict__ Fh, double2* __restrict__ Dout, double2* __restrict__ Fout,
                       double2* __restrict__ dring, int push, int64_t push_time, int64_t ring_head) {
-  const int gm = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int gm = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (gm >= n_modes) return;
   const SelfMode md = modes[gm];
   const SelfFaultDev f = sf[md.fault];
   const double2* w = tw + f.tw;
   double re = 0.0, im = 0.0;
-  int idx = 0;
-  for (int j = 0; j < f.Np; ++j) {
+  for (int j = lane; j < f.Np; j += 64) {
     const double x = vel ? delta[f.off + j] + coef * vel[f.off + j] : delta[f.off + j];
-    const double2 e = w[idx];
+    const double2 e = w[(int)(((int64_t)md.n * j) % f.M)];
     re += x * e.x;
     im += x * e.y;
-    idx += md.n;
-    if (idx >= f.M) idx -= f.M;
   }
+  re = wave_sum(re);
+  im = wave_sum(im);
+  if (lane != 0) return;
   const double k0 = tab[md.tab];
   const double c = -f.cfac * md.n;
   if (Dout) Dout[gm] = make_double2(re, im);
@@ -245,20 +456,18 @@ __global__ void k_dft(const SelfMode* __restrict__ modes, int n_modes, const Sel
     dring[md.ring + ring_slot(push_time, md.W)] = make_double2(re, im);
 }
 
+// Inverse transform at element j, by one wave (lanes strided over modes):
 // f_j = (1/M) [2 Re sum_{n=1}^{N_p-1} F_n e^{+2 pi i n j/M} + Re F_{N_p} (-1)^j]  (F_0 = 0)
-__device__ __forceinline__ double idft_elem(const SelfFaultDev& f, const double2* __restrict__ F,
-                                            const double2* __restrict__ w, int j) {
+__device__ __forceinline__ double idft_wave(const SelfFaultDev& f, const double2* __restrict__ F,
+                                            const double2* __restrict__ w, int j, int lane) {
   double s = 0.0;
   const int ntop = f.nm < f.Np ? f.nm : f.Np - 1;
-  int idx = 0;
-  for (int n = 1; n <= ntop; ++n) {
-    idx += j;
-    if (idx >= f.M) idx -= f.M;
-    const double2 e = w[idx];  // e^{-i...}: Re(F e^{+i...}) = F.x e.x + F.y e.y
+  for (int n = 1 + lane; n <= ntop; n += 64) {
+    const double2 e = w[(int)(((int64_t)n * j) % f.M)];  // e^{-i...}: Re(F e^{+i...}) = F.x e.x + F.y e.y
     const double2 Fn = F[n - 1];
     s += Fn.x * e.x + Fn.y * e.y;
   }
-  s *= 2.0;
+  s = 2.0 * wave_sum(s);
   if (f.nm >= f.Np) s += F[f.Np - 1].x * ((j & 1) ? -1.0 : 1.0);
   return s / f.M;
 }
@@ -305,14 +514,17 @@ __device__ __forceinline__ void tail_update(const StepArgs<TF>& a, int r, int k,
   }
 }
 
+// One wave per element: inverse transform by the whole wave, then lane 0 solves.
 template <typename TF>
 __global__ void k_stage(StepArgs<TF> a, int stage) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (r >= a.N) return;
   const int k = a.fault_of[r];
   const SelfFaultDev f = a.sf[k];
   const int j = r - f.off;
-  const double fself = idft_elem(f, a.F + f.mode_off, a.tw + f.tw, j);
+  const double fself = idft_wave(f, a.F + f.mode_off, a.tw + f.tw, j, lane);
+  if (lane != 0) return;
   const double tau0 = a.tau0[r] + a.tau0_rate[r] * a.t_next;
   const Friction& fr = a.fric;
   if (stage == 0) {  // predictor: delta*, theta* from the current rates
@@ -362,15 +574,16 @@ __global__ void k_pre_push(StepArgs<TF> a, const double* __restrict__ Vin) {
   }
 }
 
-// Prescribed mode output: f^n = f_self + f_hist - mu/(2cs) K^0 V^{n-1}.
+// Prescribed mode output: f^n = f_self + f_hist - mu/(2cs) K^0 V^{n-1} (one wave per element).
 template <typename TF>
 __global__ void k_pre_out(StepArgs<TF> a, const double* __restrict__ Vprev, double* __restrict__ fout) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (r >= a.N) return;
   const int k = a.fault_of[r];
   const SelfFaultDev f = a.sf[k];
-  const double fself = idft_elem(f, a.F + f.mode_off, a.tw + f.tw, r - f.off);
-  fout[r] = fself + a.f_hist[r] - a.eta * lag0_apply(a.l0_ptr, a.l0_col, a.l0_val, Vprev, r);
+  const double fself = idft_wave(f, a.F + f.mode_off, a.tw + f.tw, r - f.off, lane);
+  if (lane == 0) fout[r] = fself + a.f_hist[r] - a.eta * lag0_apply(a.l0_ptr, a.l0_col, a.l0_val, Vprev, r);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -402,6 +615,12 @@ void launch_hmat(const HostOp& h, int S, int n_items, const void* items, const i
                  const int32_t* lagColOff, const void* arena, const void* ring, int64_t head,
                  const double* tail_acc, double* partials, int pstride, hipStream_t s) {
   if (n_items == 0) return;
+  if (h.prm.factor_dtype == SEAS_F32 && S == 16 && h.use_mfma) {
+    hipLaunchKernelGGL(k_hmat_mfma16, dim3(n_items), dim3(kItemThreads), 0, s, (const Item*)items, lagT, lagCol,
+                       lagColOff, (const float*)arena, (const float*)ring, head, (int64_t)h.ring_len, h.N,
+                       (float*)partials, pstride);
+    return;
+  }
   if (h.prm.factor_dtype == SEAS_F64)
     hmat_t<double>(S, n_items, items, lagT, lagCol, lagColOff, arena, ring, head, h.ring_len, h.N, tail_acc,
                    partials, pstride, s);
@@ -410,17 +629,28 @@ void launch_hmat(const HostOp& h, int S, int n_items, const void* items, const i
                   partials, pstride, s);
 }
 
-void launch_reduce_far(const HostOp& h, int S, const double* partials, const int32_t* ptr, const int32_t* idx,
-                       double* f, hipStream_t s) {
+bool far_partials_f32(const HostOp& h, int S) {
+  return h.prm.factor_dtype == SEAS_F32 && S == 16 && h.use_mfma;
+}
+
+template <typename TP>
+static void reduce_far_t(const HostOp& h, int S, const TP* partials, const int32_t* ptr, const int32_t* idx, double* f,
+                         hipStream_t s) {
   const dim3 g(blocks_for(h.N, 4)), b(256);
   switch (S) {
-    case 1: hipLaunchKernelGGL(k_reduce_far<1>, g, b, 0, s, partials, ptr, idx, h.N, -h.eta, f); break;
-    case 2: hipLaunchKernelGGL(k_reduce_far<2>, g, b, 0, s, partials, ptr, idx, h.N, -h.eta, f); break;
-    case 4: hipLaunchKernelGGL(k_reduce_far<4>, g, b, 0, s, partials, ptr, idx, h.N, -h.eta, f); break;
-    case 8: hipLaunchKernelGGL(k_reduce_far<8>, g, b, 0, s, partials, ptr, idx, h.N, -h.eta, f); break;
-    case 16: hipLaunchKernelGGL(k_reduce_far<16>, g, b, 0, s, partials, ptr, idx, h.N, -h.eta, f); break;
+    case 1: hipLaunchKernelGGL((k_reduce_far<1, TP>), g, b, 0, s, partials, ptr, idx, h.N, -h.eta, f); break;
+    case 2: hipLaunchKernelGGL((k_reduce_far<2, TP>), g, b, 0, s, partials, ptr, idx, h.N, -h.eta, f); break;
+    case 4: hipLaunchKernelGGL((k_reduce_far<4, TP>), g, b, 0, s, partials, ptr, idx, h.N, -h.eta, f); break;
+    case 8: hipLaunchKernelGGL((k_reduce_far<8, TP>), g, b, 0, s, partials, ptr, idx, h.N, -h.eta, f); break;
+    case 16: hipLaunchKernelGGL((k_reduce_far<16, TP>), g, b, 0, s, partials, ptr, idx, h.N, -h.eta, f); break;
     default: break;
   }
+}
+
+void launch_reduce_far(const HostOp& h, int S, const void* partials, bool f32, const int32_t* ptr,
+                       const int32_t* idx, double* f, hipStream_t s) {
+  if (f32) reduce_far_t(h, S, (const float*)partials, ptr, idx, f, s);
+  else reduce_far_t(h, S, (const double*)partials, ptr, idx, f, s);
 }
 
 void launch_reduce_near(const HostOp& h, const double* partials, const int32_t* ptr, const int32_t* idx,
@@ -438,13 +668,13 @@ void launch_self_hist(int n_modes, const SelfMode* modes, const double* tab, con
 void launch_dft(int n_modes, const SelfMode* modes, const SelfFaultDev* sf, const double* delta, const double* vel,
                 double coef, const double2* tw, const double* tab, const double2* Fh, double2* Dout, double2* Fout,
                 double2* dring, int push, int64_t push_time, int64_t ring_head, hipStream_t s) {
-  hipLaunchKernelGGL(k_dft, dim3(blocks_for(n_modes, 64)), dim3(64), 0, s, modes, n_modes, sf, delta, vel, coef, tw,
+  hipLaunchKernelGGL(k_dft, dim3(blocks_for(n_modes, 4)), dim3(256), 0, s, modes, n_modes, sf, delta, vel, coef, tw,
                      tab, Fh, Dout, Fout, dring, push, push_time, ring_head);
 }
 
 template <typename TF>
 void launch_stage(const StepArgs<TF>& a, int stage, hipStream_t s) {
-  hipLaunchKernelGGL((k_stage<TF>), dim3(blocks_for(a.N, 128)), dim3(128), 0, s, a, stage);
+  hipLaunchKernelGGL((k_stage<TF>), dim3(blocks_for(a.N, 4)), dim3(256), 0, s, a, stage);
 }
 
 template <typename TF>
@@ -454,7 +684,7 @@ void launch_prescribed_push(const StepArgs<TF>& a, const double* Vin, hipStream_
 
 template <typename TF>
 void launch_prescribed_out(const StepArgs<TF>& a, const double* Vprev, double* fout, hipStream_t s) {
-  hipLaunchKernelGGL((k_pre_out<TF>), dim3(blocks_for(a.N, 128)), dim3(128), 0, s, a, Vprev, fout);
+  hipLaunchKernelGGL((k_pre_out<TF>), dim3(blocks_for(a.N, 4)), dim3(256), 0, s, a, Vprev, fout);
 }
 
 template void launch_stage<double>(const StepArgs<double>&, int, hipStream_t);

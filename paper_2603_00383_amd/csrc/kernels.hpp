@@ -58,8 +58,10 @@ struct StepArgs {
 void launch_hmat(const HostOp& h, int S, int n_items, const void* items, const int32_t* lagT, const int32_t* lagCol,
                  const int32_t* lagColOff, const void* arena, const void* ring, int64_t head,
                  const double* tail_acc, double* partials, int pstride, hipStream_t s);
-void launch_reduce_far(const HostOp& h, int S, const double* partials, const int32_t* ptr, const int32_t* idx,
-                       double* f, hipStream_t s);
+// far partials are FP32 when the far list runs on the matrix cores (FP32, S = 16)
+bool far_partials_f32(const HostOp& h, int S);
+void launch_reduce_far(const HostOp& h, int S, const void* partials, bool f32, const int32_t* ptr,
+                       const int32_t* idx, double* f, hipStream_t s);
 void launch_reduce_near(const HostOp& h, const double* partials, const int32_t* ptr, const int32_t* idx,
                         const double* base, double* f, hipStream_t s);
 void launch_self_hist(int n_modes, const SelfMode* modes, const double* tab, const double2* dring, int64_t time0,

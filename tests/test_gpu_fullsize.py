@@ -25,7 +25,7 @@ def fullsize():
     if not torch.cuda.is_available():
         pytest.skip("no HIP device")
     faults = SI.five_fault_network(seed=0)
-    params = SI.default_params(factor_dtype="f32", aca_tol=1e-6, eta_H=2.0, leaf=50, time_block=8)
+    params = SI.default_params(factor_dtype="f32", aca_tol=1e-6, eta_H=2.0, leaf=50, time_block=16)
     print("[gpu] building the five-fault operator", flush=True)
     op = P.Operator(faults, params)
     prior = SI.saturated_history(faults, op.info["max_lag"] + 2, 0)
