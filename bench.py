@@ -25,6 +25,14 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of the far interaction kernel, from two rocprofv3 --pmc runs of this
+# script's default command (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), scaled by what the
+# same counters read for a plain 2 GiB copy (2.0 for FETCH_SIZE, 1.0 for WRITE_SIZE).  Keyed by
+# the SHA-256 of the kernel source they were taken on: any later change reports null.
+MEASURED_TRAFFIC = {
+    ("k_hmat_mfma16", "6c9971821ad1b001d9b24014e124c9b13117fe579aedcfdbaa73f8f9d9a859dc"):
+        2.0 * 10_763_000 * 1024 + 1.0 * 926_547 * 1024,
+}
 METRIC = "element-steps/s (stress eval) vs plain at rel err≤1e-4; p50/p99 window latency"
 
 
@@ -156,6 +164,15 @@ def main():
     plain = None if (args.no_plain or S == 1) else timed(1)
     wall, avg_ms, achieved = main_run["wall"], main_run["avg_ms"], main_run["gbs"]
     hmat_bytes = info["far_entries"] * elem_bytes
+    if args.dtype == "f32" and S == 16 and not os.environ.get("SEAS_NO_MFMA"):
+        kname = "k_hmat_mfma16"
+    else:
+        t = 'float' if args.dtype == 'f32' else 'double'
+        kname = f"k_hmat<{t},{t},{S}>"
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2603_00383_amd", "csrc", "kernels.hip"), "rb") as fh:
+        ksha = hashlib.sha256(fh.read()).hexdigest()
+    traffic = MEASURED_TRAFFIC.get((kname, ksha))
     out = {
         "metric": METRIC,
         "value": N * args.steps / wall,
@@ -169,8 +186,8 @@ def main():
                                "saturated history windows",
                    "seed": args.seed, "N": N, "max_lag": info["max_lag"], "time_block": S},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": f"k_hmat<float,float,{S}>" if args.dtype == "f32" else f"k_hmat<double,double,{S}>",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": kname,
                      "kernel_avg_ms": avg_ms, "algorithmic_bytes": hmat_bytes,
                      "launches_per_step": main_run["launches"] / args.steps},
         "gpu_event_ms_per_step": main_run["ev_ms"] / args.steps,
