@@ -25,6 +25,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0   # dense matrix-core peak
 # HBM bytes per launch of the far interaction kernel, from two rocprofv3 --pmc runs of this
 # script's default command (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), scaled by what the
 # same counters read for a plain 2 GiB copy (2.0 for FETCH_SIZE, 1.0 for WRITE_SIZE).  Keyed by
@@ -75,12 +76,102 @@ def cpu_baseline(faults, params, prior, budget_s=12.0):
                        f"saturated step of the same workload; {t_int + t_self:.1f} s of CPU work")}
 
 
+def run_ensemble(args):
+    """Ensemble throughput: one geometry, many friction variants stepped together;
+    the interaction sums of all variants are one 16-bit product per work item."""
+    import numpy as np
+    import torch
+
+    import paper_2603_00383_amd as P
+    import seas_inputs as SI
+
+    dtype = args.dtype or "bf16"
+    nv = args.variants
+    faults = SI.ensemble_network(seed=args.seed)
+    params = SI.default_params(factor_dtype=dtype, aca_tol=args.aca, eta_H=2.0, leaf=50, time_block=1,
+                               n_variants=nv)
+    os.environ.setdefault("SEAS_VERBOSE", "1")
+    print("[bench] building the ensemble operator", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    op = P.Operator(faults, params)
+    build_s = time.perf_counter() - t0
+    info = op.info
+    N = op.N
+    print(f"[bench] operator built in {build_s:.1f} s: N={N} items={info['n_items']} segments="
+          f"{info['n_segments']} far bytes={info['far_bytes'] / 1e9:.2f} GB max_lag={info['max_lag']}",
+          file=sys.stderr, flush=True)
+    base = SI.rate_state_fields(faults)
+    var = SI.ensemble_variants(nv, seed=args.seed)
+    fric = {k: np.tile(base[k], nv) for k in ("sigma_n", "V0", "f0")}
+    fric["a"] = np.repeat(var["a"], N)
+    fric["b"] = np.repeat(var["b"], N)
+    fric["Dc"] = np.repeat(var["Dc"], N)
+    V, th, t0_, t0r = [], [], [], []
+    for v in range(nv):
+        fv = {k: fric[k][v * N:(v + 1) * N] for k in ("a", "b", "Dc", "sigma_n", "V0", "f0")}
+        ini = SI.near_nucleation_state(faults, fv, seed=args.seed, bump_amp=0.05)
+        V.append(ini["V"]); th.append(ini["theta"]); t0_.append(ini["tau0"]); t0r.append(ini["tau0_rate"])
+    stream = torch.cuda.current_stream()
+    s = stream.cuda_stream
+    st = P.State(op, fric, np.concatenate(V), np.concatenate(th), np.concatenate(t0_), np.concatenate(t0r),
+                 stream=s)
+    print(f"[bench] state of {nv} variants created, warmup {args.warmup}", file=sys.stderr, flush=True)
+    st.step(args.warmup, stream=s)
+    st.check(stream=s)
+    st.set_timing(True)
+    st.read_timing(stream=s)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    e0.record(stream)
+    st.step(args.steps, stream=s)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms, n = st.read_timing(stream=s)
+    st.check(stream=s)
+    avg = ms / max(n, 1)
+    alg_bytes = info["far_entries"] * 2
+    flops = 2.0 * info["far_entries"] * info["ncols"]
+    achieved = alg_bytes / (avg * 1e-3) / 1e9
+    tflops = flops / (avg * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": N * nv * args.steps / wall,
+        "unit": "element-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": dtype, "data": "synthetic",
+        "config": {"workload": f"ensemble: 8 faults x 750 elements (N=6000, dx=50 m), {nv} friction variants "
+                               f"(a-b, Dc per variant), {dtype.upper()} factors and history operand, FP32 "
+                               "accumulation, FP64 state, ACA 1e-6, eta_H 2, leaf 50",
+                   "seed": args.seed, "N": N, "variants": nv, "max_lag": info["max_lag"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": f"k_hmat_x16<bf16,{info['ncols']} columns>", "kernel_avg_ms": avg,
+                     "algorithmic_bytes": alg_bytes, "launches_per_step": n / args.steps,
+                     "mfma": {"achieved": tflops, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                              "frac": tflops / BF16_PEAK_TFLOPS, "flops_per_launch": flops}},
+        "gpu_event_ms_per_step": e0.elapsed_time(e1) / args.steps,
+        "build_s": build_s,
+        "stored_over_dense": info["stored_entries"] / info["dense_entries"],
+    }
+    print(f"[bench] timed {args.steps} steps: {wall:.3f} s", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--workload", default="seas", choices=["seas", "ensemble"],
+                    help="seas: five-fault step loop (one variant); ensemble: eight faults x 750 elements, "
+                         "64 friction variants in one launch (BF16)")
+    ap.add_argument("--dtype", default=None, choices=["f32", "f64", "bf16", "f16"],
+                    help="factor dtype (default f32; bf16 for the ensemble)")
+    ap.add_argument("--variants", type=int, default=64, help="ensemble: friction variants (16, 32 or 64)")
     ap.add_argument("--aca", type=float, default=1e-6)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--time-block", type=int, default=16,
@@ -103,7 +194,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build runs on one GPU; --gpus N > 1 is not supported "
-              "(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+              "(sharding over GPUs is not built)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -114,6 +205,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
+    if args.workload == "ensemble":
+        return run_ensemble(args)
+    if args.dtype is None:
+        args.dtype = "f32"
     faults = SI.five_fault_network(seed=args.seed)
     params = SI.default_params(factor_dtype=args.dtype, aca_tol=args.aca, eta_H=2.0, leaf=50,
                                time_block=args.time_block)
@@ -138,7 +233,7 @@ def main():
     print(f"[bench] history loaded ({len(prior)} steps), warmup {args.warmup}", file=sys.stderr, flush=True)
     st.step(args.warmup, stream=s)
     st.check(stream=s)
-    elem_bytes = 4 if args.dtype == "f32" else 8
+    elem_bytes = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}[args.dtype]
 
     def timed(S):
         st.set_time_block(S)
@@ -164,7 +259,9 @@ def main():
     plain = None if (args.no_plain or S == 1) else timed(1)
     wall, avg_ms, achieved = main_run["wall"], main_run["avg_ms"], main_run["gbs"]
     hmat_bytes = info["far_entries"] * elem_bytes
-    if args.dtype == "f32" and S == 16 and not os.environ.get("SEAS_NO_MFMA"):
+    if args.dtype in ("bf16", "f16"):
+        kname = f"k_hmat_x16<{'bf16' if args.dtype == 'bf16' else 'f16'},16 columns>"
+    elif args.dtype == "f32" and S == 16 and not os.environ.get("SEAS_NO_MFMA"):
         kname = "k_hmat_mfma16"
     else:
         t = 'float' if args.dtype == 'f32' else 'double'
@@ -182,8 +279,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.dtype, "data": "synthetic",
         "config": {"workload": "five-fault SEAS step loop, 5 x 600 elements (N=3000, dx=50 m), "
-                               f"{args.dtype.upper()} factors, FP64 state, ACA {args.aca:g}, eta_H 2, leaf 50, "
-                               "saturated history windows",
+                               f"{args.dtype.upper()} factors" + (" (lags < 16 in FP32)" if elem_bytes == 2 else "")
+                               + f", FP64 state, ACA {args.aca:g}, eta_H 2, leaf 50, saturated history windows",
                    "seed": args.seed, "N": N, "max_lag": info["max_lag"], "time_block": S},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

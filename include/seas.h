@@ -54,13 +54,25 @@ typedef int32_t seas_status;
 
 /* Storage/compute precision of the interaction factors. F64: factors, history
  * operand and accumulation in FP64. F32: factors and history operand in FP32,
- * FP32 accumulation within a work item, FP64 across items. State, self term,
- * friction and time integration are FP64 in every mode. */
+ * FP32 accumulation within a work item, FP64 across items. BF16 / F16: the lags
+ * applied once per time block (and, for ensembles, every lag and the static
+ * tail) are stored in 16 bits with one power-of-two FP32 scale per work item,
+ * multiplied on the matrix cores against a 16-bit copy of the history with FP32
+ * accumulation; F16 also scales each staged history panel and projected panel
+ * by a power of two so that their values stay in range. With one variant the
+ * lags applied every step are kept in FP32. BF16 ensembles keep a BF16 copy of
+ * the rate history; F16 ensembles an FP32 copy. State, self term, friction and time integration are
+ * FP64 in every mode. */
 #define SEAS_F64 0
 #define SEAS_F32 1
+#define SEAS_BF16 2
+#define SEAS_F16 3
 
 const char* seas_last_error(void);
 const char* seas_version(void);
+/* x rounded to the storage format of factor_dtype (round to nearest even) and
+ * back: the host conversion the build applies to stored factor values. */
+double seas_round_factor(double x, int32_t factor_dtype);
 
 /* One straight fault: centroid (cx, cy), unit normal (nx, ny) = e2' of its
  * local frame, tangent e1' = e3 x e2' = (-ny, nx) (Section 3.1), length and
@@ -86,7 +98,7 @@ typedef struct {
   int32_t int_tail; /* 1: static stress of slip older than the pair window is kept; 0: dropped */
   int32_t q_w;      /* window modulation integer, 0 = round(N_p / 5) per fault */
   int32_t mode_cap; /* 0 = all N_p modes of the 2 N_p padded transform; else keep n <= mode_cap */
-  int32_t factor_dtype; /* SEAS_F64 or SEAS_F32 */
+  int32_t factor_dtype; /* SEAS_F64, SEAS_F32, SEAS_BF16 or SEAS_F16 */
   int32_t n_threads;    /* host threads for the build (0 = all) */
   int32_t host_only;    /* 1: build on the host only (no device memory; for inspecting the
                            partition, windows, tables and factors); evaluation and state calls
@@ -94,8 +106,12 @@ typedef struct {
   int32_t time_block;   /* S in {0 (= 1), 1, 2, 4, 8, 16}: lags T >= S are applied once per S
                            steps to S history windows (a lag-T factor only needs rates at least
                            T steps old), lags 1..S-1 and the static tail every step; the sum is
-                           the same, only its evaluation order changes */
-  int32_t reserved;
+                           the same, only its evaluation order changes. BF16 / F16 operators
+                           with one variant need 16; with several variants, 0 or 1 */
+  int32_t n_variants;   /* 0 or 1: one friction parameter set; 16, 32 or 64: an ensemble of that
+                           many parameter sets on this geometry (BF16 / F16 only), whose
+                           interaction sums are one product of the factors with the
+                           variants' histories side by side */
 } seas_params_t;
 
 typedef struct seas_op seas_op_t;
@@ -127,6 +143,10 @@ typedef struct {
   int32_t time_block;         /* S of the build */
   int64_t far_entries;        /* stored entries applied once per time block (lags >= S) */
   int64_t n_items_near;       /* work items applied every step (lags 1..S-1, static tail) */
+  int32_t n_variants;         /* variants a state of this operator holds */
+  int32_t ncols;              /* columns of the far-list products: time_block x n_variants */
+  int64_t n_segments;         /* BF16 / F16: workgroups of the far list (items with the same rows) */
+  int64_t far_bytes;          /* bytes of the stored far-list factors (with the 16-bit row padding) */
 } seas_op_info_t;
 
 seas_status seas_operator_info(const seas_op_t* op, seas_op_info_t* out);
@@ -153,7 +173,8 @@ seas_status seas_operator_self_table(const seas_op_t* op, int32_t k, int32_t n,
  * Only for operators built with host_only = 1 (the factors are on the host). */
 seas_status seas_operator_lag_matrix(const seas_op_t* op, int32_t a, int32_t b, int32_t T, double* out);
 
-/* Rate-and-state parameters, one value per element (host arrays of N):
+/* Rate-and-state parameters, one value per element and variant (host arrays of
+ * n_variants x N, variant-major):
  * strength sigma_n [f0 + a ln(V/V0) + b ln(V0 theta / Dc)], state law with
  * exponent eps (1 = aging law). */
 typedef struct {
@@ -165,26 +186,29 @@ size_t seas_state_bytes(const seas_op_t* op, int32_t n_variants);
 
 /* Create a state at t = 0: slip rate V_init, state theta_init, background
  * shear stress tau0 and its rate (may be NULL), slip delta_init (may be NULL
- * = 0). Host arrays of N. Histories before t = 0 are zero (no prior slip)
- * unless seas_state_load_history is called next. n_variants must be 1. */
+ * = 0). Host arrays of n_variants x N (variant-major). Histories before t = 0
+ * are zero (no prior slip) unless seas_state_load_history is called next.
+ * n_variants must equal the operator's (seas_op_info_t.n_variants); every
+ * variant evolves on its own, and the variants share the operator's factors. */
 seas_status seas_state_create(seas_op_t* op, int32_t n_variants, const seas_friction_t* fric,
                               const double* V_init, const double* theta_init,
                               const double* tau0, const double* tau0_rate,
                               const double* delta_init, void* stream, seas_state_t** out);
 void seas_state_destroy(seas_state_t* st);
 
-/* Prior slip-rate history V[m][N] for the n_hist steps before t = 0 (host,
- * oldest first): fills both histories (slip before t = 0 follows from
+/* Prior slip-rate history V[m][n_variants][N] for the n_hist steps before t = 0
+ * (host, oldest first): fills both histories (slip before t = 0 follows from
  * delta^{m+1} = delta^m + dt V^m) and the expired-slip accumulators. Must be
  * called right after seas_state_create. */
 seas_status seas_state_load_history(seas_state_t* st, const double* V_hist, int32_t n_hist,
                                     void* stream);
 
 /* Stress evaluation of a prescribed slip-rate history (no friction): for
- * n = 1..n_steps, with V^m = V_dev[(m)*N ...] (device, FP64, n_steps x N):
+ * n = 1..n_steps, with V^m = V_dev[m][variant][element] (device, FP64,
+ * n_steps x n_variants x N):
  *   delta^n = delta^{n-1} + dt V^{n-1}
  *   f^n = f_self(D^n, D^{n-1}, ...) + f_int(V^{n-1}, V^{n-2}, ...)
- * written to f_dev[(n-1)*N ...] (device, FP64). Consecutive calls continue the
+ * written to f_dev[n-1][variant][element] (device, FP64). Consecutive calls continue the
  * same history. MISMATCH if the state has taken SEAS steps. */
 seas_status seas_eval_prescribed(seas_op_t* op, seas_state_t* st, const double* V_dev,
                                  int32_t n_steps, double* f_dev, void* stream);
@@ -206,8 +230,8 @@ seas_status seas_state_check(seas_state_t* st, void* stream);
 #define SEAS_FIELD_F_INT 6      /* interaction stress of the last corrector (with lag 0) */
 #define SEAS_FIELD_TAU0 7
 
-/* Copy N values of a field to dst (device if dst_is_device, else host; a host
- * copy synchronises the stream). */
+/* Copy the N values of a field of one variant to dst (device if dst_is_device,
+ * else host; a host copy synchronises the stream). */
 seas_status seas_read_state(const seas_state_t* st, int32_t field, int32_t variant, double* dst,
                             size_t count, int32_t dst_is_device, void* stream);
 /* Device time of the interaction-evaluation kernel: when enabled, every launch of

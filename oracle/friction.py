@@ -2,7 +2,8 @@
 
 * strength tau = sigma_n [f_* + a ln(V/V_*) + b ln(V_* theta / D_c)]
   (Section 2.2, eq. "R&S_friction"; the printed form has b ln(V theta / D_c),
-  read as b ln(V_* theta / D_c), see DESIGN.md);
+  read as b ln(V_* theta / D_c), the form whose steady state is theta = D_c / V_*
+  as the paper states next to it);
 * intermediate state law dtheta/dt = (1/eps)[(V theta/D_c)^(-eps) - 1] V theta / D_c,
   eps = 1 giving the aging law dtheta/dt = 1 - V theta / D_c (eq. "state_evolution_law");
 * equilibrium on every element (eq. "force_balance" with the traction split of

@@ -12,8 +12,8 @@ Follows Section 2.3.2 of the paper:
 * the causality window [T_init, T_end] of each fault pair ("Truncation of
   elastodynamic time-window" paragraph, eq. "early_time");
 * the static dipole stress used for slip that has left a pair's window (the
-  late-time limit of the same kernel; see the reading of the truncation in
-  DESIGN.md).
+  late-time limit of the same kernel: the 2-D kernel does not decay to zero, so
+  the slip that leaves a window keeps its static stress).
 
 Everything is dense and uncompressed, FP64.
 """

@@ -4,7 +4,7 @@ The stress transfer is the history functional f of eq. "superimposition2"
 (radiation damping excluded), split as in eq. "traction_decomposition" into the
 spectral self term of each fault and the fault-to-fault space-time term.
 
-Time indexing (Section 2.3.2 and Section 2.4; see the design doc for the reading):
+Time indexing (Section 2.3.2 and Section 2.4, as read here):
 V^m is the slip rate held over [t_m, t_{m+1}]; the interaction stress at t_{h+1}
 is sum_T K^T V^{h-T}; the self term at t_s uses D^{s-T}, T = 0..W_n, where D^s is
 the transform of the slip at t_s.

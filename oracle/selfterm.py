@@ -9,7 +9,8 @@ Section 2.3.1 of the paper, followed step by step:
   F_n^t = -(pi mu cs n / (2L)) sum_{T=0}^{W_n} K_n^T D_n^{t-T}
   (eq. "funcational_discretized_form"), where K_n^T = |k_n| times the integral of
   K(n, .) over the centred time cell of lag T (the paper calls the kernel
-  "pre-integrated" without giving the rule; see DESIGN.md);
+  "pre-integrated" without giving the rule; the centred cell is the reading
+  taken here);
 * mode-dependent windows T_end(n) = T_end(1) L(n), T_end(1) = eta_w L / cs
   (eq. "mode_dependent_truncation");
 * the transforms are explicit sums (no FFT): D_n = sum_j delta_j e^{-2 pi i n j / M},

@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libseas.so")
 
-SEAS_F64, SEAS_F32 = 0, 1
+SEAS_F64, SEAS_F32, SEAS_BF16, SEAS_F16 = 0, 1, 2, 3
 FIELDS = dict(V=0, theta=1, delta=2, thetadot=3, f_hist=4, f_self=5, f_int=6, tau0=7)
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "OOM", -3: "HIP", -4: "NOT_CONVERGED", -5: "MISMATCH",
           -6: "INTERNAL"}
@@ -39,7 +39,7 @@ class Params(C.Structure):
                 ("eta_w", C.c_double), ("leaf", C.c_int32), ("compress", C.c_int32),
                 ("int_tail", C.c_int32), ("q_w", C.c_int32), ("mode_cap", C.c_int32),
                 ("factor_dtype", C.c_int32), ("n_threads", C.c_int32), ("host_only", C.c_int32),
-                ("time_block", C.c_int32), ("reserved", C.c_int32)]
+                ("time_block", C.c_int32), ("n_variants", C.c_int32)]
 
 
 class OpInfo(C.Structure):
@@ -49,7 +49,8 @@ class OpInfo(C.Structure):
                 ("lag0_nnz", C.c_int64), ("self_entries", C.c_int64), ("bytes_per_step", C.c_double),
                 ("flops_per_step", C.c_double), ("build_seconds", C.c_double),
                 ("factor_dtype", C.c_int32), ("time_block", C.c_int32), ("far_entries", C.c_int64),
-                ("n_items_near", C.c_int64)]
+                ("n_items_near", C.c_int64), ("n_variants", C.c_int32), ("ncols", C.c_int32),
+                ("n_segments", C.c_int64), ("far_bytes", C.c_int64)]
 
 
 class Friction(C.Structure):
@@ -71,6 +72,7 @@ def lib():
         sig = {
             "seas_last_error": (C.c_char_p, []),
             "seas_version": (C.c_char_p, []),
+            "seas_round_factor": (C.c_double, [C.c_double, i32]),
             "seas_build_operator": (i32, [C.POINTER(Fault), i32, C.POINTER(Params), C.POINTER(vp)]),
             "seas_operator_destroy": (None, [vp]),
             "seas_operator_info": (i32, [vp, C.POINTER(OpInfo)]),
@@ -124,7 +126,8 @@ def _ptr(x):
     return C.c_void_p(int(x))
 
 
-_DTYPE = {"f64": SEAS_F64, "f32": SEAS_F32, SEAS_F64: SEAS_F64, SEAS_F32: SEAS_F32}
+_DTYPE = {"f64": SEAS_F64, "f32": SEAS_F32, "bf16": SEAS_BF16, "f16": SEAS_F16,
+          SEAS_F64: SEAS_F64, SEAS_F32: SEAS_F32, SEAS_BF16: SEAS_BF16, SEAS_F16: SEAS_F16}
 
 
 def make_params(p):
@@ -139,6 +142,7 @@ def make_params(p):
     q.n_threads = int(p.get("n_threads", 0))
     q.host_only = int(p.get("host_only", 0))
     q.time_block = int(p.get("time_block", 1))
+    q.n_variants = int(p.get("n_variants", 1))
     return q
 
 
@@ -209,8 +213,11 @@ class Operator:
 
 
 class State:
+    """Per-element arrays are (n_variants x N), variant-major (plain N for one variant)."""
+
     def __init__(self, op, fric, V, theta, tau0, tau0_rate=None, delta=None, stream=0):
         self.op = op
+        self.nv = int(op.info["n_variants"])
         keep = []
         fr = Friction()
         for k in ("a", "b", "Dc", "sigma_n", "V0", "f0", "eps"):
@@ -219,13 +226,14 @@ class State:
             setattr(fr, k, p)
         args = [_dptr(x) for x in (V, theta, tau0, tau0_rate, delta)]
         h = C.c_void_p()
-        _check(lib().seas_state_create(op.h, 1, C.byref(fr), *[p for _, p in args], _ptr(stream), C.byref(h)))
+        _check(lib().seas_state_create(op.h, self.nv, C.byref(fr), *[p for _, p in args], _ptr(stream),
+                                       C.byref(h)))
         self.h = h
 
     def load_history(self, V_hist, stream=0):
         arr = np.ascontiguousarray(V_hist, dtype=np.float64)
         _check(lib().seas_state_load_history(self.h, arr.ctypes.data_as(C.POINTER(C.c_double)), arr.shape[0],
-                                             _ptr(stream)))
+                                             _ptr(stream)))  # (n_hist, N) or (n_hist, n_variants, N)
 
     def eval_prescribed(self, V_dev, n_steps, f_dev, stream=0):
         _check(lib().seas_eval_prescribed(self.op.h, self.h, _ptr(V_dev), n_steps, _ptr(f_dev), _ptr(stream)))
@@ -236,10 +244,10 @@ class State:
     def check(self, stream=0):
         _check(lib().seas_state_check(self.h, _ptr(stream)))
 
-    def read(self, field, stream=0):
+    def read(self, field, stream=0, variant=0):
         out = np.zeros(self.op.N)
-        _check(lib().seas_read_state(self.h, FIELDS[field], 0, C.c_void_p(out.ctypes.data), self.op.N, 0,
-                                     _ptr(stream)))
+        _check(lib().seas_read_state(self.h, FIELDS[field], int(variant), C.c_void_p(out.ctypes.data), self.op.N,
+                                     0, _ptr(stream)))
         return out
 
     def set_time_block(self, S):

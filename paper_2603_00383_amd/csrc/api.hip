@@ -77,6 +77,8 @@ struct seas_op {
   int device = 0;
   std::vector<DevBuf> owned;
   void* arena = nullptr;
+  float* arena_near = nullptr;  // 16-bit operators: FP32 near-list factors
+  int32_t* seg_ptr = nullptr;   // 16-bit operators: far-list segments
   Item* items[2] = {nullptr, nullptr};
   int32_t *lagT = nullptr, *lagCol = nullptr, *lagColOff[2] = {nullptr, nullptr};
   int32_t *red_ptr[2] = {nullptr, nullptr}, *red_idx[2] = {nullptr, nullptr};
@@ -90,11 +92,10 @@ struct seas_op {
   int32_t *src_pairs = nullptr, *src_pairs_ptr = nullptr;
   std::vector<SelfMode> hmodes;
   std::vector<SelfFaultDev> hsf;
-  size_t elem_bytes = 8;
+  size_t elem_bytes = 8;  // bytes of a stored far-list factor value
+  size_t ring_bytes = 8;  // bytes of a value of the rate history's operand copy (8: the FP64 ring itself)
   bool host_only = false;
-  std::vector<std::vector<double>> hb64;  // host factors (host_only)
-  std::vector<std::vector<float>> hb32;
-  std::vector<int64_t> hboff;
+  HostFactors hf;         // host factors (host_only)
   ~seas_op() {
     for (auto& b : owned) (void)hipFree(b.p);
   }
@@ -102,6 +103,7 @@ struct seas_op {
 
 struct seas_state {
   seas_op* op = nullptr;
+  int nv = 1;    // variants
   int mode = 0;  // 0 fresh, 1 prescribed, 2 stepping
   int64_t step = 0, first = 0;
   std::vector<DevBuf> owned;
@@ -112,7 +114,8 @@ struct seas_state {
   double* ring64;
   void* ringop;
   double* tail_acc;
-  double *partials_far, *partials_near;
+  void* partials_far;      // FP64, or FP32 when the far list runs on the matrix cores
+  double* partials_near;
   double* f_far;             // far part of the interaction for the S evaluations of a time block
   int64_t block_head = INT64_MIN / 2;  // head at which f_far was computed
   int run_S = 0;                        // 1: far list applied every step (plain form); else the build's S
@@ -134,6 +137,10 @@ StepArgs<TF> make_args(seas_op* op, seas_state* st) {
   const HostOp& h = op->h;
   StepArgs<TF> a{};
   a.N = h.N;
+  a.nv = st->nv;
+  a.n_modes = h.n_modes;
+  a.tail_len = h.tail_len;
+  a.dring_len = h.self_ring_len;
   a.dt = h.dt;
   a.eta = h.eta;
   a.fault_of = op->fault_of;
@@ -188,38 +195,34 @@ void record_stop(seas_state* st, hipStream_t s) {
 
 // Interaction history part at `head` into st->f_hist. The far list is applied
 // once per time block (S windows: heads block_head .. block_head + S - 1), the
-// near list (lags 1..S-1 and the static tail) at every head.
+// near list (lags 1..S-1 and the static tail) at every head. In the plain form
+// (S = 1, or run_S = 1) the far list is applied at every head.
 void eval_history(seas_op* op, seas_state* st, int64_t head, hipStream_t s) {
   const HostOp& h = op->h;
   const int S = h.time_block;
   const int nfar = (int)h.items[0].size(), nnear = (int)h.items[1].size();
-  if (S == 1 || st->run_S == 1) {  // far list every step, one window
-    record_start(st, s);
-    launch_hmat(h, 1, nfar, op->items[0], op->lagT, op->lagCol, op->lagColOff[0], op->arena, st->ringop, head,
-                st->tail_acc, st->partials_far, S, s);
-    record_stop(st, s);
-    if (nnear == 0) {
-      launch_reduce_far(h, 1, st->partials_far, false, op->red_ptr[0], op->red_idx[0], st->f_hist, s);
-      return;
-    }
-    launch_reduce_far(h, 1, st->partials_far, false, op->red_ptr[0], op->red_idx[0], st->f_far, s);
-    st->block_head = INT64_MIN / 2;
-    launch_hmat(h, 1, nnear, op->items[1], op->lagT, op->lagCol, op->lagColOff[1], op->arena, st->ringop, head,
-                st->tail_acc, st->partials_near, 1, s);
-    launch_reduce_near(h, st->partials_near, op->red_ptr[1], op->red_idx[1], st->f_far, st->f_hist, s);
-    return;
-  }
+  const bool plain = S == 1 || st->run_S == 1;
   int64_t k = head - st->block_head;
-  if (k < 0 || k >= S) {
+  if (plain || k < 0 || k >= S) {
+    // plain form on a time-blocked build: window 0 of the far list at this head
+    const int Sl = (plain && !h.x16) ? 1 : S;
     record_start(st, s);
-    launch_hmat(h, S, nfar, op->items[0], op->lagT, op->lagCol, op->lagColOff[0], op->arena, st->ringop, head,
-                st->tail_acc, st->partials_far, S, s);
+    if (h.x16)
+      launch_hmat_x16(h, op->items[0], op->seg_ptr, op->lagT, op->lagCol, op->lagColOff[0], op->arena, st->ringop,
+                      head, st->tail_acc, (float*)st->partials_far, s);
+    else
+      launch_hmat(h, Sl, nfar, op->items[0], op->lagT, op->lagCol, op->lagColOff[0], op->arena, st->ringop, head,
+                  st->tail_acc, (double*)st->partials_far, S, s);
     record_stop(st, s);
-    launch_reduce_far(h, S, st->partials_far, far_partials_f32(h, S), op->red_ptr[0], op->red_idx[0], st->f_far, s);
-    st->block_head = head;
+    const bool f32p = far_partials_f32(h, Sl);
+    launch_reduce_far(h, h.x16 ? h.ncols : Sl, st->partials_far, f32p, op->red_ptr[0], op->red_idx[0],
+                      nnear == 0 ? st->f_hist : st->f_far, s);
+    if (nnear == 0) return;
+    st->block_head = plain ? INT64_MIN / 2 : head;
     k = 0;
   }
-  launch_hmat(h, 1, nnear, op->items[1], op->lagT, op->lagCol, op->lagColOff[1], op->arena, st->ringop, head,
+  const void* arena_near = h.x16 ? (const void*)op->arena_near : op->arena;
+  launch_hmat(h, 1, nnear, op->items[1], op->lagT, op->lagCol, op->lagColOff[1], arena_near, st->ringop, head,
               st->tail_acc, st->partials_near, 1, s);
   launch_reduce_near(h, st->partials_near, op->red_ptr[1], op->red_idx[1], st->f_far + k * h.N, st->f_hist, s);
 }
@@ -227,18 +230,19 @@ void eval_history(seas_op* op, seas_state* st, int64_t head, hipStream_t s) {
 template <typename TF>
 void do_steps(seas_op* op, seas_state* st, int n_steps, hipStream_t s) {
   const HostOp& h = op->h;
-  const int nm = h.n_modes;
+  const int nm = h.n_modes, nv = st->nv;
+  const int64_t dl = h.self_ring_len;
   for (int it = 0; it < n_steps; ++it) {
     const int64_t n = st->step;
     eval_history(op, st, n, s);
-    launch_self_hist(nm, op->modes, op->tab, st->dring, n + 1, st->Fh, s);
+    launch_self_hist(nm, nv, dl, op->modes, op->tab, st->dring, n + 1, st->Fh, s);
     StepArgs<TF> a = make_args<TF>(op, st);
     a.t_next = (double)(n + 1) * h.dt;
     a.time_new = n + 1;
-    launch_dft(nm, op->modes, op->sf, st->delta, st->V, h.dt, op->tw, op->tab, st->Fh, nullptr, st->F, st->dring,
-               0, 0, 0, s);
+    launch_dft(nm, nv, h.N, dl, op->modes, op->sf, st->delta, st->V, h.dt, op->tw, op->tab, st->Fh, st->F,
+               st->dring, 0, 0, 0, s);
     launch_stage<TF>(a, 0, s);
-    launch_dft(nm, op->modes, op->sf, st->delta, st->Vbar, h.dt, op->tw, op->tab, st->Fh, nullptr, st->F,
+    launch_dft(nm, nv, h.N, dl, op->modes, op->sf, st->delta, st->Vbar, h.dt, op->tw, op->tab, st->Fh, st->F,
                st->dring, 1, n + 1, n + 1, s);
     launch_stage<TF>(a, 1, s);
     st->step = n + 1;
@@ -249,7 +253,9 @@ void do_steps(seas_op* op, seas_state* st, int n_steps, hipStream_t s) {
 template <typename TF>
 void do_prescribed(seas_op* op, seas_state* st, const double* V, int n_steps, double* f, hipStream_t s) {
   const HostOp& h = op->h;
-  const int nm = h.n_modes;
+  const int nm = h.n_modes, nv = st->nv;
+  const int64_t dl = h.self_ring_len;
+  const size_t row = (size_t)h.N * nv;
   for (int it = 0; it < n_steps; ++it) {
     const int64_t n = st->step + 1;  // evaluating f^n
     const int64_t hd = n - 1;        // time of the newest rate, V^{n-1}
@@ -258,16 +264,32 @@ void do_prescribed(seas_op* op, seas_state* st, const double* V, int n_steps, do
     // the accumulators of a new state already cover every time up to -T_end - 1 (the
     // window of the rate at time 0); re-pushing time 0 must not add that row again
     if (hd < 1) a.tail = 0;
-    const double* Vrow = V + (size_t)it * h.N;
+    const double* Vrow = V + (size_t)it * row;
     launch_prescribed_push<TF>(a, Vrow, s);
     eval_history(op, st, hd, s);
-    launch_self_hist(nm, op->modes, op->tab, st->dring, n, st->Fh, s);
-    launch_dft(nm, op->modes, op->sf, st->delta, nullptr, 0.0, op->tw, op->tab, st->Fh, nullptr, st->F, st->dring,
-               1, n, n, s);
-    launch_prescribed_out<TF>(a, Vrow, f + (size_t)it * h.N, s);
+    launch_self_hist(nm, nv, dl, op->modes, op->tab, st->dring, n, st->Fh, s);
+    launch_dft(nm, nv, h.N, dl, op->modes, op->sf, st->delta, nullptr, 0.0, op->tw, op->tab, st->Fh, st->F,
+               st->dring, 1, n, n, s);
+    launch_prescribed_out<TF>(a, Vrow, f + (size_t)it * row, s);
     st->step = n;
   }
   HIPCHK(hipGetLastError());
+}
+
+// One row (all variants) of the rate history's operand copy, converted on the
+// host; synchronises the stream (the conversion buffer is temporary).
+void upload_op_row(seas_op* op, void* ringop, int64_t slot, const double* row, size_t n, hipStream_t s) {
+  if (op->ring_bytes == 8) return;
+  if (op->ring_bytes == 4) {
+    std::vector<float> v(row, row + n);
+    HIPCHK(hipMemcpyAsync((float*)ringop + slot * n, v.data(), n * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+  } else {
+    std::vector<uint16_t> v(n);
+    for (size_t i = 0; i < n; ++i) v[i] = to_bf16((float)row[i]);
+    HIPCHK(hipMemcpyAsync((uint16_t*)ringop + slot * n, v.data(), n * 2, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
 }
 
 seas_op* checked(seas_op* op) {
@@ -282,7 +304,16 @@ seas_op* checked(seas_op* op) {
 extern "C" {
 
 const char* seas_last_error(void) { return g_err.c_str(); }
-const char* seas_version(void) { return "seas-mi355x 0.1 (gfx950)"; }
+const char* seas_version(void) { return "seas-mi355x 0.2 (gfx950)"; }
+
+double seas_round_factor(double x, int32_t factor_dtype) {
+  switch (factor_dtype) {
+    case SEAS_F32: return (double)(float)x;
+    case SEAS_BF16: return (double)from_bf16(to_bf16((float)x));
+    case SEAS_F16: return (double)from_f16(to_f16((float)x));
+    default: return x;
+  }
+}
 
 seas_status seas_build_operator(const seas_fault_t* faults, int32_t n_faults, const seas_params_t* params,
                                 seas_op_t** out) {
@@ -292,31 +323,36 @@ seas_status seas_build_operator(const seas_fault_t* faults, int32_t n_faults, co
     auto op = std::make_unique<seas_op>();
     op->host_only = params->host_only != 0;
     if (!op->host_only) HIPCHK(hipGetDevice(&op->device));
-    std::vector<std::vector<double>> b64;
-    std::vector<std::vector<float>> b32;
-    std::vector<int64_t> boff;
-    build_host(faults, n_faults, *params, op->h, b64, b32, boff);
+    HostFactors& hf = op->hf;
+    build_host(faults, n_faults, *params, op->h, hf);
     HostOp& h = op->h;
     const bool f32 = h.prm.factor_dtype == SEAS_F32;
-    op->elem_bytes = f32 ? 4 : 8;
+    op->elem_bytes = h.x16 ? 2 : (f32 ? 4 : 8);
+    // rate-history operand: FP32 (F16 stages it with a per-item scale; BF16 with one
+    // variant converts it at staging), BF16 for BF16 ensembles (halves the history reads)
+    op->ring_bytes = h.x16 ? ((h.n_variants > 1 && h.prm.factor_dtype == SEAS_BF16) ? 2 : 4) : op->elem_bytes;
     if (op->host_only) {
-      op->hb64.swap(b64);
-      op->hb32.swap(b32);
-      op->hboff.swap(boff);
       *out = op.release();
       return;
     }
-    // factor arena, block by block
+    // factor arenas, block by block
     op->arena = dalloc(op->owned, (size_t)h.arena_elems * op->elem_bytes);
-    for (size_t bi = 0; bi < boff.size(); ++bi) {
-      const size_t n = f32 ? b32[bi].size() : b64[bi].size();
-      if (n == 0) continue;
-      const void* src = f32 ? (const void*)b32[bi].data() : (const void*)b64[bi].data();
-      HIPCHK(hipMemcpy((char*)op->arena + (size_t)boff[bi] * op->elem_bytes, src, n * op->elem_bytes,
-                       hipMemcpyHostToDevice));
-      std::vector<double>().swap(b64[bi]);
-      std::vector<float>().swap(b32[bi]);
+    if (h.x16) op->arena_near = (float*)dalloc(op->owned, (size_t)h.arena_near_elems * 4);
+    for (size_t bi = 0; bi < hf.off.size(); ++bi) {
+      const size_t n = h.x16 ? hf.f16[bi].size() : (f32 ? hf.f32[bi].size() : hf.f64[bi].size());
+      const void* src = h.x16 ? (const void*)hf.f16[bi].data()
+                              : (f32 ? (const void*)hf.f32[bi].data() : (const void*)hf.f64[bi].data());
+      if (n > 0)
+        HIPCHK(hipMemcpy((char*)op->arena + (size_t)hf.off[bi] * op->elem_bytes, src, n * op->elem_bytes,
+                         hipMemcpyHostToDevice));
+      if (h.x16 && !hf.f32[bi].empty())
+        HIPCHK(hipMemcpy(op->arena_near + hf.off32[bi], hf.f32[bi].data(), hf.f32[bi].size() * 4,
+                         hipMemcpyHostToDevice));
+      std::vector<double>().swap(hf.f64[bi]);
+      std::vector<float>().swap(hf.f32[bi]);
+      std::vector<uint16_t>().swap(hf.f16[bi]);
     }
+    if (h.x16) op->seg_ptr = upload(op->owned, h.seg_ptr);
     for (int L = 0; L < 2; ++L) {
       op->items[L] = upload(op->owned, h.items[L]);
       op->lagColOff[L] = upload(op->owned, h.lagColOff[L]);
@@ -404,16 +440,22 @@ seas_status seas_operator_lag_matrix(const seas_op_t* op, int32_t a, int32_t b, 
         }
       return;
     }
-    // the arena is the concatenation of the per-block buffers: locate an element
-    auto elem = [&](int64_t e) -> double {
-      size_t lo = 0, hi = op->hboff.size();
+    // the arenas are the concatenation of the per-block buffers: locate an element
+    const HostFactors& hf = op->hf;
+    auto elem_in = [&](const std::vector<int64_t>& off, int64_t e, int which) -> double {
+      size_t lo = 0, hi = off.size();
       while (hi - lo > 1) {
         const size_t mid = (lo + hi) / 2;
-        if (op->hboff[mid] <= e) lo = mid;
+        if (off[mid] <= e) lo = mid;
         else hi = mid;
       }
-      const int64_t k = e - op->hboff[lo];
-      return op->elem_bytes == 4 ? (double)op->hb32[lo][k] : op->hb64[lo][k];
+      while (lo + 1 < off.size() && off[lo + 1] == off[lo] &&
+             (which == 2 ? hf.f16[lo].empty() : which == 1 ? hf.f32[lo].empty() : hf.f64[lo].empty()))
+        ++lo;  // skip empty blocks that share the offset
+      const int64_t k = e - off[lo];
+      if (which == 2)
+        return h.prm.factor_dtype == SEAS_BF16 ? (double)from_bf16(hf.f16[lo][k]) : (double)from_f16(hf.f16[lo][k]);
+      return which == 1 ? (double)hf.f32[lo][k] : hf.f64[lo][k];
     };
     for (int L = 0; L < 2; ++L)
     for (size_t ii = 0; ii < h.items[L].size(); ++ii) {
@@ -421,8 +463,30 @@ seas_status seas_operator_lag_matrix(const seas_op_t* op, int32_t a, int32_t b, 
       if (it.row0 < A.off || it.row0 >= A.off + p_all || it.col0 < B.off || it.col0 >= B.off + q_all) continue;
       const int ri = it.row0 - A.off, cj = it.col0 - B.off;
       const int32_t* cp = &h.lagCol[h.lagColOff[L][ii]];
+      const bool x16 = h.x16 && L == 0;
+      const int which = x16 ? 2 : ((h.x16 || h.prm.factor_dtype == SEAS_F32) ? 1 : 0);
+      const std::vector<int64_t>& off = (h.x16 && L == 1) ? hf.off32 : hf.off;
+      auto elem = [&](int64_t e) { return elem_in(off, e, which); };
       for (int l = 0; l < it.nlag; ++l) {
         if (h.lagT[it.lag_off + l] != T) continue;
+        if (x16) {
+          const int q8 = round8(it.q), nc = it.ncol, nc8 = round8(nc);
+          const double sc = it.scale;
+          if (it.kind == 0) {
+            for (int c = cp[l]; c < cp[l + 1]; ++c)
+              for (int i = 0; i < it.p; ++i) {
+                const double u = elem(it.data + (int64_t)nc * q8 + (int64_t)i * nc8 + c);
+                for (int j = 0; j < it.q; ++j)
+                  out[(size_t)(ri + i) * q_all + cj + j] += sc * u * elem(it.data + (int64_t)c * q8 + j);
+              }
+          } else {
+            for (int i = 0; i < it.p; ++i)
+              for (int j = 0; j < it.q; ++j)
+                out[(size_t)(ri + i) * q_all + cj + j] =
+                    sc * elem(it.data + (int64_t)i * it.nlag * q8 + (int64_t)l * q8 + j);
+          }
+          continue;
+        }
         if (it.kind == 0) {
           const int nc = it.ncol;
           for (int c = cp[l]; c < cp[l + 1]; ++c)
@@ -469,6 +533,20 @@ seas_status seas_operator_info(const seas_op_t* op, seas_op_info_t* out) {
     out->flops_per_step = 2.0 * (double)h.stored_entries + 4.0 * (double)h.self_entries;
     out->build_seconds = h.build_seconds;
     out->factor_dtype = h.prm.factor_dtype;
+    out->n_variants = h.n_variants;
+    out->ncols = h.ncols;
+    out->n_segments = h.x16 ? (int64_t)h.seg_ptr.size() - 1 : 0;
+    int64_t fb = 0;
+    for (const Item& it : h.items[0]) {
+      if (h.x16) {
+        const int64_t q8 = round8(it.q);
+        fb += 2 * (it.kind == 0 ? (int64_t)it.ncol * q8 + (int64_t)it.p * round8(it.ncol) : (int64_t)it.nlag * it.p * q8);
+      } else {
+        fb += (int64_t)op->elem_bytes *
+              (it.kind == 0 ? (int64_t)it.ncol * (it.p + it.q) : (int64_t)it.nlag * it.p * it.q);
+      }
+    }
+    out->far_bytes = fb;
   });
 }
 
@@ -527,9 +605,9 @@ size_t seas_state_bytes(const seas_op_t* op, int32_t n_variants) {
   const size_t N = (size_t)h.N * n_variants;
   size_t b = N * 8 * 19;                                         // per-element state and scratch
   b += (size_t)h.ring_len * N * 8;                               // FP64 rate history
-  if (op->elem_bytes != 8) b += (size_t)h.ring_len * N * op->elem_bytes;  // operand copy
+  if (op->ring_bytes != 8) b += (size_t)h.ring_len * N * op->ring_bytes;  // operand copy
   b += (size_t)h.tail_len * 8 * n_variants;
-  b += (size_t)(h.n_partials[0] + h.n_partials[1]) * 8 * n_variants;
+  b += (size_t)h.n_partials[0] * (h.x16 ? 4 : 8) + (size_t)h.n_partials[1] * 8;
   b += (size_t)h.time_block * N * 8;
   b += (size_t)h.self_ring_len * 16 * n_variants + (size_t)h.n_modes * 16 * 2 * n_variants;
   return b;
@@ -541,15 +619,18 @@ seas_status seas_state_create(seas_op_t* op, int32_t n_variants, const seas_fric
   return guard([&] {
     checked(op);
     if (!out || !fric || !V_init || !theta_init || !tau0) throw Error(SEAS_ERR_INVALID_ARG, "null argument");
-    if (n_variants != 1) throw Error(SEAS_ERR_INVALID_ARG, "n_variants must be 1");
+    if (n_variants != op->h.n_variants)
+      throw Error(SEAS_ERR_INVALID_ARG, "n_variants must equal the operator's (" + std::to_string(op->h.n_variants) + ")");
     if (!fric->a || !fric->b || !fric->Dc || !fric->sigma_n || !fric->V0 || !fric->f0)
       throw Error(SEAS_ERR_INVALID_ARG, "null friction array");
     *out = nullptr;
     const HostOp& h = op->h;
-    const size_t N = h.N;
+    const int nv = n_variants;
+    const size_t N = (size_t)h.N * nv;  // values of a per-element array over all variants
     hipStream_t s = (hipStream_t)stream;
     auto st = std::make_unique<seas_state>();
     st->op = op;
+    st->nv = nv;
     auto A = [&](size_t bytes, bool ck) {
       void* p = dalloc(st->owned, bytes);
       HIPCHK(hipMemsetAsync(p, 0, bytes, s));
@@ -577,14 +658,16 @@ seas_status seas_state_create(seas_op_t* op, int32_t n_variants, const seas_fric
     st->f_self = (double*)A(vb, true);
     st->f_int = (double*)A(vb, true);
     st->ring64 = (double*)A((size_t)h.ring_len * vb, true);
-    st->ringop = op->elem_bytes == 8 ? (void*)st->ring64 : A((size_t)h.ring_len * N * op->elem_bytes, true);
-    st->tail_acc = (double*)A((size_t)h.tail_len * 8, true);
-    st->partials_far = (double*)A((size_t)h.n_partials[0] * 8, false);
+    st->ringop = op->ring_bytes == 8 ? (void*)st->ring64 : A((size_t)h.ring_len * N * op->ring_bytes, true);
+    st->tail_acc = (double*)A((size_t)h.tail_len * 8 * nv, true);
+    // FP64 slots even where the far pass writes FP32: the plain form of an FP32
+    // build (seas_state_set_time_block(1)) writes FP64 partials into the same buffer
+    st->partials_far = A((size_t)h.n_partials[0] * (h.x16 ? 4 : 8), false);
     st->partials_near = (double*)A((size_t)h.n_partials[1] * 8, false);
     st->f_far = (double*)A((size_t)h.time_block * vb, true);
-    st->dring = (double2*)A((size_t)h.self_ring_len * 16, true);
-    st->Fh = (double2*)A((size_t)h.n_modes * 16, false);
-    st->F = (double2*)A((size_t)h.n_modes * 16, false);
+    st->dring = (double2*)A((size_t)h.self_ring_len * 16 * nv, true);
+    st->Fh = (double2*)A((size_t)h.n_modes * 16 * nv, false);
+    st->F = (double2*)A((size_t)h.n_modes * 16 * nv, false);
     st->fail = (int*)A(sizeof(int), false);
     // host-side initial values
     std::vector<double> eps(N, 1.0), thd(N), zero(N, 0.0);
@@ -611,13 +694,9 @@ seas_status seas_state_create(seas_op_t* op, int32_t n_variants, const seas_fric
     H2D(st->feps, eps.data());
     // histories at t = 0: V^0 and D^0
     H2D(st->ring64, V_init);  // time 0 -> slot 0
-    if (op->elem_bytes != 8) {
-      std::vector<float> v32(V_init, V_init + N);
-      HIPCHK(hipMemcpyAsync(st->ringop, v32.data(), N * 4, hipMemcpyHostToDevice, s));
-      HIPCHK(hipStreamSynchronize(s));
-    }
-    launch_dft(h.n_modes, op->modes, op->sf, st->delta, nullptr, 0.0, op->tw, op->tab, nullptr, nullptr, st->F,
-               st->dring, 1, 0, 0, s);
+    upload_op_row(op, st->ringop, 0, V_init, N, s);
+    launch_dft(h.n_modes, nv, h.N, h.self_ring_len, op->modes, op->sf, st->delta, nullptr, 0.0, op->tw, op->tab,
+               nullptr, st->F, st->dring, 1, 0, 0, s);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
     *out = st.release();
@@ -638,21 +717,18 @@ seas_status seas_state_load_history(seas_state_t* st, const double* V_hist, int3
     if (st->mode != 0 || st->step != 0) throw Error(SEAS_ERR_MISMATCH, "history must be loaded on a fresh state");
     if (n_hist == 0) return;
     const HostOp& h = op->h;
-    const size_t N = h.N;
+    const int nv = st->nv;
+    const size_t Ne = h.N, N = Ne * nv;
     hipStream_t s = (hipStream_t)stream;
     const int64_t H = n_hist;
-    // rate rows m = -H..-1 (row H + m of V_hist); only the newest ring_len - 2 can be read
+    // rate rows m = -H..-1 (row H + m of V_hist, nv x N values); only the newest
+    // ring_len - 2 can be read
     const int64_t mlo = std::max<int64_t>(-H, -(int64_t)(h.ring_len - 2));
-    std::vector<float> v32;
     for (int64_t m = mlo; m <= -1; ++m) {
       const double* row = V_hist + (size_t)(H + m) * N;
       const int64_t slot = ((m % h.ring_len) + h.ring_len) % h.ring_len;
       HIPCHK(hipMemcpyAsync(st->ring64 + slot * N, row, N * 8, hipMemcpyHostToDevice, s));
-      if (op->elem_bytes != 8) {
-        v32.assign(row, row + N);
-        HIPCHK(hipMemcpyAsync((float*)st->ringop + slot * N, v32.data(), N * 4, hipMemcpyHostToDevice, s));
-        HIPCHK(hipStreamSynchronize(s));
-      }
+      upload_op_row(op, st->ringop, slot, row, N, s);
     }
     // slip before t = 0 and its coefficients D^m, m = -1 .. 1 - W_max
     std::vector<double> d0(N);
@@ -665,20 +741,21 @@ seas_status seas_state_load_history(seas_state_t* st, const double* V_hist, int3
       const double* row = V_hist + (size_t)(H + m) * N;
       for (size_t r = 0; r < N; ++r) dm[r] -= h.dt * row[r];
       HIPCHK(hipMemcpyAsync(dtmp, dm.data(), N * 8, hipMemcpyHostToDevice, s));
-      launch_dft(h.n_modes, op->modes, op->sf, dtmp, nullptr, 0.0, op->tw, op->tab, nullptr, nullptr, st->F,
-                 st->dring, 1, m, 0, s);
+      launch_dft(h.n_modes, nv, h.N, h.self_ring_len, op->modes, op->sf, dtmp, nullptr, 0.0, op->tw, op->tab,
+                 nullptr, st->F, st->dring, 1, m, 0, s);
       HIPCHK(hipStreamSynchronize(s));
     }
     // expired-slip accumulators: dt sum of V^m, m <= -T_end - 1
     if (h.prm.int_tail) {
-      std::vector<double> E(h.tail_len, 0.0);
-      for (size_t pi = 0; pi < h.pairs.size(); ++pi) {
-        const Fault& B = h.faults[h.pairs[pi].b];
-        for (int64_t m = -H; m <= -(int64_t)h.pairs[pi].T_end - 1; ++m) {
-          const double* row = V_hist + (size_t)(H + m) * N + B.off;
-          for (int j = 0; j < B.Np; ++j) E[h.tail_off[pi] + j] += h.dt * row[j];
+      std::vector<double> E((size_t)h.tail_len * nv, 0.0);
+      for (int v = 0; v < nv; ++v)
+        for (size_t pi = 0; pi < h.pairs.size(); ++pi) {
+          const Fault& B = h.faults[h.pairs[pi].b];
+          for (int64_t m = -H; m <= -(int64_t)h.pairs[pi].T_end - 1; ++m) {
+            const double* row = V_hist + (size_t)(H + m) * N + (size_t)v * Ne + B.off;
+            for (int j = 0; j < B.Np; ++j) E[(size_t)v * h.tail_len + h.tail_off[pi] + j] += h.dt * row[j];
+          }
         }
-      }
       HIPCHK(hipMemcpyAsync(st->tail_acc, E.data(), E.size() * 8, hipMemcpyHostToDevice, s));
       HIPCHK(hipStreamSynchronize(s));
     }
@@ -695,8 +772,11 @@ seas_status seas_eval_prescribed(seas_op_t* op, seas_state_t* st, const double* 
     if (st->mode == 2) throw Error(SEAS_ERR_MISMATCH, "state has taken SEAS steps");
     st->mode = 1;
     hipStream_t s = (hipStream_t)stream;
-    if (op->elem_bytes == 8) do_prescribed<double>(op, st, V_dev, n_steps, f_dev, s);
-    else do_prescribed<float>(op, st, V_dev, n_steps, f_dev, s);
+    switch (op->ring_bytes) {
+      case 8: do_prescribed<double>(op, st, V_dev, n_steps, f_dev, s); break;
+      case 4: do_prescribed<float>(op, st, V_dev, n_steps, f_dev, s); break;
+      default: do_prescribed<__bf16>(op, st, V_dev, n_steps, f_dev, s); break;
+    }
   });
 }
 
@@ -708,8 +788,11 @@ seas_status seas_step(seas_op_t* op, seas_state_t* st, int32_t n_steps, void* st
     if (st->mode == 1) throw Error(SEAS_ERR_MISMATCH, "state is in prescribed-history mode");
     st->mode = 2;
     hipStream_t s = (hipStream_t)stream;
-    if (op->elem_bytes == 8) do_steps<double>(op, st, n_steps, s);
-    else do_steps<float>(op, st, n_steps, s);
+    switch (op->ring_bytes) {
+      case 8: do_steps<double>(op, st, n_steps, s); break;
+      case 4: do_steps<float>(op, st, n_steps, s); break;
+      default: do_steps<__bf16>(op, st, n_steps, s); break;
+    }
   });
 }
 
@@ -737,7 +820,7 @@ seas_status seas_read_state(const seas_state_t* st, int32_t field, int32_t varia
   return guard([&] {
     if (!st || !dst) throw Error(SEAS_ERR_INVALID_ARG, "null argument");
     checked(st->op);
-    if (variant != 0) throw Error(SEAS_ERR_INVALID_ARG, "variant out of range");
+    if (variant < 0 || variant >= st->nv) throw Error(SEAS_ERR_INVALID_ARG, "variant out of range");
     const size_t N = st->op->h.N;
     if (count != N) throw Error(SEAS_ERR_INVALID_ARG, "count must equal the number of elements");
     const double* src = nullptr;
@@ -752,6 +835,7 @@ seas_status seas_read_state(const seas_state_t* st, int32_t field, int32_t varia
       case SEAS_FIELD_TAU0: src = st->tau0; break;
       default: throw Error(SEAS_ERR_INVALID_ARG, "unknown field");
     }
+    src += (size_t)variant * N;
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(hipMemcpyAsync(dst, src, N * 8, dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
     if (!dst_is_device) HIPCHK(hipStreamSynchronize(s));

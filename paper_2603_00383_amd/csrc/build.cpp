@@ -266,6 +266,43 @@ static int aca_full(const double* A, int p, int q, double tol, int kmax, std::ve
   return k;
 }
 
+// ============================================================== 16-bit storage
+// Round to nearest even. BF16 keeps the FP32 exponent and 8 significand bits;
+// FP16 is IEEE binary16 (values here are scaled into [-1, 1] first).
+uint16_t to_bf16(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+float from_bf16(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float x;
+  std::memcpy(&x, &u, 4);
+  return x;
+}
+uint16_t to_f16(float x) {
+  const _Float16 h = (_Float16)x;
+  uint16_t b;
+  std::memcpy(&b, &h, 2);
+  return b;
+}
+float from_f16(uint16_t b) {
+  _Float16 h;
+  std::memcpy(&h, &b, 2);
+  return (float)h;
+}
+
+// power of two >= m (1 for m = 0): values divided by it lie in [-1, 1] exactly scaled
+static double pow2_at_least(double m) {
+  if (!(m > 0.0)) return 1.0;
+  int e;
+  const double f = std::frexp(m, &e);  // m = f 2^e, f in [0.5, 1)
+  (void)f;
+  return std::ldexp(1.0, e);
+}
+
 // ============================================================== per-block build
 struct LagFactor {
   int T;        // lag (-1 = static tail)
@@ -282,6 +319,7 @@ struct BlockOut {
   std::vector<int32_t> lagT[2], lagCol[2];
   std::vector<double> d64;
   std::vector<float> d32;
+  std::vector<uint16_t> d16;
   int64_t stored = 0, dense = 0;
 };
 
@@ -364,6 +402,102 @@ static void pack_list(int r0, int r1, int s0, int s1, const Fault& A, const Faul
   }
 }
 
+// Pack a run of lag factors of one (sub-)block into 16-bit items of the far list
+// for the matrix-core kernel, whose products have ncols = S * nv columns (S
+// history windows of nv variants). Layout (rows padded with zeros to q8 / ncol8
+// values so that every 8-value group is one aligned 16-byte load):
+//   dense:    [p][nlag * q8]   row i holds lag 0's q8 values, then lag 1's, ...
+//   low rank: W [ncol][q8]     projection rows, lag after lag
+//             U [p][ncol8]     expansion rows
+// Stored values are the factors divided by a power-of-two item scale (dense: the
+// item's max |D|; low rank: max |W| times max |U|, each panel scaled on its own),
+// so they lie in [-1, 1]. Limits: staged history (span * nv * q8 values), the
+// projected panel (ncol8 * ncols values) and the lag count.
+static void pack_list16(int r0, int r1, int s0, int s1, const Fault& A, const Fault& B,
+                        std::vector<LagFactor*>& lags, bool bf16, int tail_off, int S, int nv, BlockOut& out) {
+  const int p = r1 - r0, q = s1 - s0, q8 = round8(q);
+  const int ncols = S * nv;
+  const int64_t target = 131072;  // stored values per item
+  auto cvt = [&](double v) { return bf16 ? to_bf16((float)v) : to_f16((float)v); };
+  size_t i = 0;
+  while (i < lags.size()) {
+    const bool lr = lags[i]->rank > 0;
+    const bool tail = lags[i]->T < 0;
+    size_t j = i;
+    int64_t elems = 0;
+    int ncol = 0;
+    while (j < lags.size() && (lags[j]->rank > 0) == lr && (lags[j]->T < 0) == tail) {
+      const int nl = (int)(j - i) + 1;
+      const int64_t e = lr ? (int64_t)lags[j]->rank * (p + q) : (int64_t)p * q;
+      if (j > i) {
+        if (tail) break;
+        if (lags[j]->T != lags[j - 1]->T + 1) break;
+        const int span = lags[j]->T - lags[i]->T + S;
+        if ((int64_t)span * nv * q8 > kHist16) break;
+        if (nl > kColMax) break;
+        if (lr && (int64_t)round8(ncol + lags[j]->rank) * ncols > kZ16) break;
+        if (elems + e > target) break;
+      }
+      elems += e;
+      if (lr) ncol += lags[j]->rank;
+      ++j;
+    }
+    Item it{};
+    it.data = (int64_t)out.d16.size();  // block-local, rebased later
+    it.kind = lr ? 0 : 1;
+    it.src = tail ? 1 : 0;
+    it.p = p;
+    it.q = q;
+    it.row0 = A.off + r0;
+    it.col0 = B.off + s0;
+    it.nlag = (int)(j - i);
+    it.lag_off = (int)out.lagT[0].size();
+    it.ncol = ncol;
+    it.tail_off = tail ? tail_off + s0 : 0;
+    for (size_t l = i; l < j; ++l) out.lagT[0].push_back(lags[l]->T);
+    out.lagCol[0].push_back(0);
+    if (lr) {
+      int c = 0;
+      double mw = 0.0, mu = 0.0;
+      for (size_t l = i; l < j; ++l) {
+        c += lags[l]->rank;
+        out.lagCol[0].push_back(c);
+        for (double v : lags[l]->W) mw = std::max(mw, std::fabs(v));
+        for (double v : lags[l]->U) mu = std::max(mu, std::fabs(v));
+      }
+      const double sw = pow2_at_least(mw), su = pow2_at_least(mu);
+      it.scale = (float)(sw * su);
+      const int ncol8 = round8(ncol);
+      for (size_t l = i; l < j; ++l)  // W [ncol][q8]
+        for (int r = 0; r < lags[l]->rank; ++r)
+          for (int jj = 0; jj < q8; ++jj) out.d16.push_back(jj < q ? cvt(lags[l]->W[(size_t)r * q + jj] / sw) : 0);
+      for (int ii = 0; ii < p; ++ii) {  // U [p][ncol8]
+        for (size_t l = i; l < j; ++l)
+          for (int r = 0; r < lags[l]->rank; ++r) out.d16.push_back(cvt(lags[l]->U[(size_t)r * p + ii] / su));
+        for (int cc = ncol; cc < ncol8; ++cc) out.d16.push_back(0);
+      }
+    } else {
+      for (int l = 0; l < it.nlag; ++l) out.lagCol[0].push_back(0);
+      double md = 0.0;
+      for (size_t l = i; l < j; ++l)
+        for (double v : lags[l]->D) md = std::max(md, std::fabs(v));
+      const double sd = pow2_at_least(md);
+      it.scale = (float)sd;
+      for (int ii = 0; ii < p; ++ii)  // [p][nlag * q8]
+        for (size_t l = i; l < j; ++l)
+          for (int jj = 0; jj < q8; ++jj) out.d16.push_back(jj < q ? cvt(lags[l]->D[(size_t)ii * q + jj] / sd) : 0);
+    }
+    out.stored += elems;
+    out.items[0].push_back(it);
+    for (size_t l = i; l < j; ++l) {
+      std::vector<double>().swap(lags[l]->U);
+      std::vector<double>().swap(lags[l]->W);
+      std::vector<double>().swap(lags[l]->D);
+    }
+    i = j;
+  }
+}
+
 // Evaluate, compress and pack the columns [s0, s1) of block bd over the pair's
 // window (every lag from max(1, T_init) to T_end; lag 0 is applied through the
 // CSR of the lag-0 coupling) and its static tail.
@@ -377,7 +511,8 @@ static void build_subblock(const HostOp& op, const BlockDesc& bd, const PairWin&
   const bool lowrank_ok = op.prm.compress && bd.adm;
   // ranks above kmax are stored dense: the factors would not be smaller, and one
   // lag's columns must fit the LDS column buffer of the kernel
-  const int kmax = std::min<int>({(int)(((int64_t)p * q) / (p + q)), kColMax, kZMax / S});
+  int kmax = std::min<int>({(int)(((int64_t)p * q) / (p + q)), kColMax, kZMax / S});
+  if (op.x16) kmax = std::min(kmax, kZ16 / op.ncols);
   const PairFrame fr = frame(A, B);
   std::vector<double> r1((size_t)p * q), r2((size_t)p * q);
   for (int i = 0; i < p; ++i)
@@ -432,6 +567,11 @@ static void build_subblock(const HostOp& op, const BlockDesc& bd, const PairWin&
     if (S == 1 || (lf.T >= S)) far.push_back(&lf);
     else near.push_back(&lf);
   }
+  if (op.x16) {
+    pack_list16(bd.r0, bd.r1, s0, s1, A, B, far, op.prm.factor_dtype == SEAS_BF16, toff, S, op.n_variants, out);
+    pack_list(bd.r0, bd.r1, s0, s1, A, B, near, true, toff, 1, 1, out);
+    return;
+  }
   const bool f32 = op.prm.factor_dtype == SEAS_F32;
   pack_list(bd.r0, bd.r1, s0, s1, A, B, far, f32, toff, S, 0, out);
   pack_list(bd.r0, bd.r1, s0, s1, A, B, near, f32, toff, 1, 1, out);
@@ -440,7 +580,8 @@ static void build_subblock(const HostOp& op, const BlockDesc& bd, const PairWin&
 static void build_block(const HostOp& op, const BlockDesc& bd, const PairWin& pw, BlockOut& out) {
   // a source cluster wider than the kernel's history buffer holds for S rows is
   // packed as column slices, each compressed on its own
-  const int qmax = kHistMax / op.time_block;
+  int qmax = kHistMax / op.time_block;
+  if (op.x16) qmax = std::min(kHistMax, (kHist16 / op.ncols) & ~7);
   for (int s0 = bd.s0; s0 < bd.s1; s0 += qmax) build_subblock(op, bd, pw, s0, std::min(bd.s1, s0 + qmax), out);
 }
 
@@ -460,9 +601,7 @@ static void check_geometry(const std::vector<Fault>& F) {
     }
 }
 
-void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostOp& op,
-                std::vector<std::vector<double>>& bd64, std::vector<std::vector<float>>& bd32,
-                std::vector<int64_t>& block_arena_off) {
+void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostOp& op, HostFactors& hf) {
   const auto t_start = std::chrono::steady_clock::now();
   op.prm = prm;
   if (nf < 1) throw Error(SEAS_ERR_INVALID_ARG, "n_faults must be >= 1");
@@ -470,12 +609,23 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
     throw Error(SEAS_ERR_INVALID_ARG, "mu, cs must be > 0 and 0 < beta <= 1/2");
   if (prm.leaf < 1 || !(prm.eta_H > 0) || !(prm.aca_tol > 0) || !(prm.eta_w > 0))
     throw Error(SEAS_ERR_INVALID_ARG, "leaf >= 1, eta_H > 0, aca_tol > 0, eta_w > 0 required");
-  if (prm.factor_dtype != SEAS_F64 && prm.factor_dtype != SEAS_F32)
-    throw Error(SEAS_ERR_INVALID_ARG, "factor_dtype must be SEAS_F64 or SEAS_F32");
+  if (prm.factor_dtype < SEAS_F64 || prm.factor_dtype > SEAS_F16)
+    throw Error(SEAS_ERR_INVALID_ARG, "factor_dtype must be SEAS_F64, SEAS_F32, SEAS_BF16 or SEAS_F16");
   if (prm.time_block < 0 || prm.time_block > kMaxTimeBlock ||
       (prm.time_block & (prm.time_block - 1)) != 0)
     throw Error(SEAS_ERR_INVALID_ARG, "time_block must be 0, 1, 2, 4, 8 or 16");
   op.time_block = prm.time_block > 0 ? prm.time_block : 1;
+  op.n_variants = prm.n_variants > 0 ? prm.n_variants : 1;
+  op.x16 = prm.factor_dtype == SEAS_BF16 || prm.factor_dtype == SEAS_F16;
+  if (op.n_variants > 1) {
+    if (!op.x16) throw Error(SEAS_ERR_INVALID_ARG, "ensembles (n_variants > 1) need BF16 or F16 factors");
+    if (op.n_variants != 16 && op.n_variants != 32 && op.n_variants != 64)
+      throw Error(SEAS_ERR_INVALID_ARG, "n_variants must be 1, 16, 32 or 64");
+    if (op.time_block != 1) throw Error(SEAS_ERR_INVALID_ARG, "ensembles use time_block 1");
+  } else if (op.x16 && op.time_block != 16) {
+    throw Error(SEAS_ERR_INVALID_ARG, "BF16 / F16 factors with one variant need time_block 16");
+  }
+  op.ncols = op.time_block * op.n_variants;
   op.use_mfma = std::getenv("SEAS_NO_MFMA") == nullptr;
   if (prm.n_threads > 0) omp_set_num_threads(prm.n_threads);
   // ---- geometry
@@ -622,25 +772,32 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
   }
   op.lagT.clear();
   op.lagCol.clear();
+  op.seg_ptr.clear();
   op.arena_elems = 0;
+  op.arena_near_elems = 0;
   op.stored_entries = 0;
   op.dense_entries = 0;
   const bool f32 = prm.factor_dtype == SEAS_F32;
   const int S = op.time_block;
-  bd64.assign(all.size(), {});
-  bd32.assign(all.size(), {});
-  block_arena_off.assign(all.size(), 0);
+  hf.f64.assign(all.size(), {});
+  hf.f32.assign(all.size(), {});
+  hf.f16.assign(all.size(), {});
+  hf.off.assign(all.size(), 0);
+  hf.off32.assign(all.size(), 0);
+  std::vector<int32_t> colOff[2];  // lagCol offset of each item, in build order
   for (size_t bi = 0; bi < all.size(); ++bi) {
     BlockOut& bo = outs[bi];
-    block_arena_off[bi] = op.arena_elems;
+    hf.off[bi] = op.arena_elems;
+    hf.off32[bi] = op.arena_near_elems;
     for (int L = 0; L < 2; ++L) {
       const int lag_base = (int)op.lagT.size();
       int col_cursor = (int)op.lagCol.size();
+      // 16-bit operators: the near list lives in the FP32 arena
+      const int64_t base = (op.x16 && L == 1) ? op.arena_near_elems : op.arena_elems;
       for (Item it : bo.items[L]) {
-        it.data += op.arena_elems;
-        it.part = (int32_t)op.n_partials[L];
-        op.n_partials[L] += (int64_t)it.p * (L == 0 ? S : 1);
-        op.lagColOff[L].push_back(col_cursor);
+        it.data += base;
+        if (!op.x16 || L == 1) it.scale = 1.0f;
+        colOff[L].push_back(col_cursor);
         col_cursor += it.nlag + 1;
         it.lag_off += lag_base;
         op.items[L].push_back(it);
@@ -648,29 +805,121 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
       op.lagT.insert(op.lagT.end(), bo.lagT[L].begin(), bo.lagT[L].end());
       op.lagCol.insert(op.lagCol.end(), bo.lagCol[L].begin(), bo.lagCol[L].end());
     }
-    op.arena_elems += f32 ? (int64_t)bo.d32.size() : (int64_t)bo.d64.size();
+    if (op.x16) {
+      op.arena_elems += (int64_t)bo.d16.size();
+      op.arena_near_elems += (int64_t)bo.d32.size();
+      hf.f16[bi].swap(bo.d16);
+      hf.f32[bi].swap(bo.d32);
+    } else {
+      op.arena_elems += f32 ? (int64_t)bo.d32.size() : (int64_t)bo.d64.size();
+      if (f32) hf.f32[bi].swap(bo.d32);
+      else hf.f64[bi].swap(bo.d64);
+    }
     op.stored_entries += bo.stored;
     op.dense_entries += bo.dense;
-    if (f32) bd32[bi].swap(bo.d32);
-    else bd64[bi].swap(bo.d64);
+  }
+  // 16-bit far list: items with the same receiver rows are ordered next to each
+  // other and grouped into segments, one workgroup each, that keep the sums of
+  // their rows in registers and write one partial set; rows beyond what the
+  // registers hold make single-item segments.
+  if (op.x16) {
+    std::vector<size_t> ord(op.items[0].size());
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) {
+      const Item &a = op.items[0][x], &b = op.items[0][y];
+      return a.row0 != b.row0 ? a.row0 < b.row0 : a.p < b.p;
+    });
+    std::vector<Item> its;
+    std::vector<int32_t> co;
+    for (size_t x : ord) {
+      its.push_back(op.items[0][x]);
+      co.push_back(colOff[0][x]);
+    }
+    op.items[0].swap(its);
+    colOff[0].swap(co);
+    const int rmax = seg_rows_max(op.ncols);
+    auto vals = [](const Item& it) {
+      const int64_t q8 = round8(it.q);
+      return it.kind == 0 ? (int64_t)it.ncol * q8 + (int64_t)it.p * round8(it.ncol) : (int64_t)it.nlag * it.p * q8;
+    };
+    size_t k = 0;
+    while (k < op.items[0].size()) {
+      const Item& f = op.items[0][k];
+      size_t e = k + 1;
+      int64_t v = vals(f);
+      if (f.p <= rmax)
+        while (e < op.items[0].size() && op.items[0][e].row0 == f.row0 && op.items[0][e].p == f.p &&
+               v + vals(op.items[0][e]) <= kSegElems)
+          v += vals(op.items[0][e++]);
+      op.seg_ptr.push_back((int32_t)k);
+      k = e;
+    }
+    op.seg_ptr.push_back((int32_t)op.items[0].size());
+  }
+  // invariants the 16-bit kernel relies on (LDS panel sizes, 16-byte alignment,
+  // one row range per segment, register-held rows of multi-item segments)
+  if (op.x16) {
+    const int rmax = seg_rows_max(op.ncols);
+    for (size_t sg = 0; sg + 1 < op.seg_ptr.size(); ++sg) {
+      const int32_t a = op.seg_ptr[sg], b = op.seg_ptr[sg + 1];
+      if (b <= a) throw Error(SEAS_ERR_INTERNAL, "empty segment");
+      const Item& f = op.items[0][a];
+      if (b - a > 1 && f.p > rmax) throw Error(SEAS_ERR_INTERNAL, "tall block in a multi-item segment");
+      for (int32_t x = a; x < b; ++x) {
+        const Item& it = op.items[0][x];
+        const int q8 = round8(it.q);
+        const int span = it.src == 0 ? it.nlag + S - 1 : 1;
+        if (it.row0 != f.row0 || it.p != f.p || it.p < 1 || it.q < 1 || it.nlag < 1 ||
+            (int64_t)span * op.n_variants * q8 > kHist16 || (it.data & 7) != 0 ||
+            (it.kind == 0 && (int64_t)round8(it.ncol) * op.ncols > kZ16) || (it.src == 1 && op.n_variants == 1) ||
+            it.row0 + it.p > op.N || it.col0 + it.q > op.N)
+          throw Error(SEAS_ERR_INTERNAL, "16-bit item violates the kernel's limits");
+      }
+    }
+  }
+  // partial offsets: per item, or per segment on the 16-bit far list (far
+  // partials are [p][S] or [p][ncols], row-major)
+  for (int L = 0; L < 2; ++L) {
+    const int SL = L == 0 ? op.ncols : 1;
+    auto& its = op.items[L];
+    if (op.x16 && L == 0) {
+      for (size_t sg = 0; sg + 1 < op.seg_ptr.size(); ++sg) {
+        const int32_t part = (int32_t)op.n_partials[0];
+        for (int32_t x = op.seg_ptr[sg]; x < op.seg_ptr[sg + 1]; ++x) its[x].part = part;
+        op.n_partials[0] += (int64_t)its[op.seg_ptr[sg]].p * SL;
+      }
+    } else {
+      for (Item& it : its) {
+        it.part = (int32_t)op.n_partials[L];
+        op.n_partials[L] += (int64_t)it.p * SL;
+      }
+    }
+    op.lagColOff[L] = colOff[L];
   }
   if (op.n_partials[0] > INT32_MAX || op.n_partials[1] > INT32_MAX || (int64_t)op.lagT.size() > INT32_MAX)
     throw Error(SEAS_ERR_INTERNAL, "operator too large for 32-bit item offsets");
-  // reduction lists per receiver, in item order: the base index of the row's
-  // partials (far partials are [p][S], row-major)
+  // reduction lists per receiver, in item (segment) order: the base index of the
+  // row's partials
   for (int L = 0; L < 2; ++L) {
-    const int SL = L == 0 ? S : 1;
+    const int SL = L == 0 ? op.ncols : 1;
     auto& ptr = op.red_ptr[L];
     auto& idx = op.red_idx[L];
+    std::vector<const Item*> heads;
+    if (op.x16 && L == 0) {
+      for (size_t sg = 0; sg + 1 < op.seg_ptr.size(); ++sg) heads.push_back(&op.items[0][op.seg_ptr[sg]]);
+    } else {
+      for (const Item& it : op.items[L]) heads.push_back(&it);
+    }
     ptr.assign(op.N + 1, 0);
-    for (const Item& it : op.items[L])
-      for (int i = 0; i < it.p; ++i) ptr[it.row0 + i + 1]++;
+    for (const Item* it : heads)
+      for (int i = 0; i < it->p; ++i) ptr[it->row0 + i + 1]++;
     for (int r = 0; r < op.N; ++r) ptr[r + 1] += ptr[r];
     idx.assign(ptr[op.N], 0);
     std::vector<int32_t> cur(ptr.begin(), ptr.end() - 1);
-    for (const Item& it : op.items[L])
-      for (int i = 0; i < it.p; ++i) idx[cur[it.row0 + i]++] = it.part + i * SL;
+    for (const Item* it : heads)
+      for (int i = 0; i < it->p; ++i) idx[cur[it->row0 + i]++] = it->part + i * SL;
   }
+  (void)S;
   // ---- self term (Section 2.3.1): windows, tables shared by identical faults
   op.self.clear();
   op.self_tab.clear();

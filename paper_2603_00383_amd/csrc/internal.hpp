@@ -46,7 +46,7 @@ struct Item {
   int32_t ncol;      // total rank columns (low rank)
   int32_t part;      // offset of this item's p partial sums
   int32_t tail_off;  // offset of the pair's accumulator (src = 1)
-  int32_t pad;
+  float scale;       // 16-bit factors: stored values times scale are the factors (1 otherwise)
 };
 static_assert(sizeof(Item) == 56, "Item layout");
 
@@ -55,6 +55,14 @@ constexpr int kHistMax = 6144;   // history values staged in LDS per item: (span
 constexpr int kColMax = 1024;    // low-rank columns (and lags) per item
 constexpr int kZMax = 2048;      // low-rank columns times steps per item
 constexpr int kMaxTimeBlock = 16;
+// 16-bit factors (the matrix-core path): rows padded to 8 values (16 B)
+constexpr int kHist16 = 16384;   // 16-bit history values staged per item: span * variants * q8
+constexpr int kZ16 = 4096;       // 16-bit projected values per low-rank item: ncol8 * columns
+constexpr int kMaxVariants = 64;
+constexpr int64_t kSegElems = 1 << 19;  // factor values per segment (one workgroup)
+inline int round8(int x) { return (x + 7) & ~7; }
+// rows of a multi-item segment: its accumulators stay in registers
+inline int seg_rows_max(int ncols) { return ncols == 16 ? 512 : 256; }
 
 // ---------------------------------------------------------------- host operator
 struct PairWin {
@@ -84,12 +92,17 @@ struct HostOp {
   // work items: list 0 applied once per block of time_block steps (lags >= S, or
   // everything when S = 1), list 1 every step (lags 1..S-1 and the static tail)
   int time_block = 1;
+  int n_variants = 1;                 // friction variants sharing the operator (ensemble columns)
+  int ncols = 1;                      // columns of the far-list products: time_block * n_variants
+  bool x16 = false;                   // far list in BF16/FP16 on the matrix cores, near list in FP32
   bool use_mfma = true;               // FP32, S = 16 far list on the matrix cores
   std::vector<Item> items[2];
   std::vector<int32_t> lagT;          // nlag lag values per item (ascending)
   std::vector<int32_t> lagCol;        // nlag+1 column prefix per item
   std::vector<int32_t> lagColOff[2];  // per item: offset into lagCol
   int64_t arena_elems = 0;
+  int64_t arena_near_elems = 0;       // 16-bit operators: FP32 arena of the near list
+  std::vector<int32_t> seg_ptr;       // 16-bit operators: far items of each segment (workgroup)
   int64_t n_partials[2] = {0, 0};
   std::vector<int32_t> red_ptr[2];    // N+1 per list
   std::vector<int32_t> red_idx[2];    // base partial index of each (receiver, item)
@@ -109,11 +122,23 @@ struct HostOp {
   double build_seconds = 0;
 };
 
+// Factor values per block, in block order, and each block's offsets in the arenas.
+// F64 / F32 operators: one arena (f64 or f32, offsets `off`). 16-bit operators: the
+// far list in f16 (bit patterns of BF16 or FP16, offsets `off`) and the near list
+// in f32 (offsets `off32`).
+struct HostFactors {
+  std::vector<std::vector<double>> f64;
+  std::vector<std::vector<float>> f32;
+  std::vector<std::vector<uint16_t>> f16;
+  std::vector<int64_t> off, off32;
+};
+
 // host build (build.cpp)
-void build_host(const seas_fault_t* f, int nf, const seas_params_t& prm, HostOp& op,
-                std::vector<std::vector<double>>& block_data_f64,
-                std::vector<std::vector<float>>& block_data_f32,
-                std::vector<int64_t>& block_arena_off);
+void build_host(const seas_fault_t* f, int nf, const seas_params_t& prm, HostOp& op, HostFactors& hf);
+uint16_t to_bf16(float x);
+uint16_t to_f16(float x);
+float from_bf16(uint16_t b);
+float from_f16(uint16_t b);
 
 double kernel_entry(const Fault& A, int i, const Fault& B, int j, int T, double dt, double cs);
 double static_stress(const Fault& A, int i, const Fault& B, int j, double mu);

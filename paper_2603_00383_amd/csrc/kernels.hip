@@ -355,6 +355,296 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(4)
   }
 }
 
+// ------------------------------------------------------------------ 16-bit matrix-core form
+// BF16 / FP16 factors (one power-of-two scale per item) times a 16-bit copy of
+// the history, v_mfma_f32_16x16x32_{bf16,f16}, FP32 accumulation. The products
+// have NC = 16 NT columns: S history windows of nv variants, column n = k nv + v.
+// Operand layout of one MFMA (16 rows x 32 inner x 16 columns):
+//   A: lane l holds A[row l%16][8 (l/16) .. +7]      (one 16-byte load)
+//   B: lane l holds B[8 (l/16) .. +7][column l%16]   (one 16-byte LDS read)
+//   D: lane l, register v holds D[row 4 (l/16) + v][column l%16]
+// Factors are stored with the inner index fastest and rows padded to multiples
+// of 8 values, so both operands are aligned 16-byte vectors:
+//   dense    [p][nlag * q8]   inner index e = l q8 + j (lag l, source j)
+//   low rank W [ncol][q8], then U [p][ncol8]
+// The staged history holds, for rows r (time tnew - r, newest first), variants v
+// and sources j, the value at LDS index (r nv + v) q8 + j; B(e, n) for lag l,
+// window k, variant v is row l + S - 1 - k, i.e. index l nv q8 + j + hoff(n) with
+// hoff(n) = ((S - 1 - k) nv + v) q8.
+// A workgroup runs a segment: consecutive items with the same receiver rows.
+// Each wave keeps the sums of its row tiles in registers across the segment
+// (rows up to 4 x RW tiles; larger blocks come as single-item segments whose row
+// tiles are written as they finish) and one partial set of p x NC values is
+// written per segment.
+template <typename T16>
+struct Mx;
+template <>
+struct Mx<__bf16> {
+  typedef __bf16 v8 __attribute__((ext_vector_type(8)));
+  static __device__ __forceinline__ mfma_f4 mma(v8 a, v8 b, mfma_f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ __bf16 cvt(float x) { return (__bf16)x; }
+};
+template <>
+struct Mx<_Float16> {
+  typedef _Float16 v8 __attribute__((ext_vector_type(8)));
+  static __device__ __forceinline__ mfma_f4 mma(v8 a, v8 b, mfma_f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ _Float16 cvt(float x) { return (_Float16)x; }
+};
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// power of two >= m (1 for m = 0)
+__device__ __forceinline__ float pow2_at_least(float m) {
+  if (!(m > 0.0f)) return 1.0f;
+  int e;
+  (void)frexpf(m, &e);
+  return ldexpf(1.0f, e);
+}
+
+// tmp[t] += sum over inner k in [k0, k1) of A(k) B(k, t); k0, k1 multiples of 8.
+// PF inner steps of 32 have their operands loaded before their MFMAs.
+template <typename T16, int NT, int PF, typename FA, typename FB>
+__device__ __forceinline__ void x16_kloop(int k0, int k1, FA A, FB B, mfma_f4 (&tmp)[NT], int g) {
+  typedef typename Mx<T16>::v8 v8;
+  const v8 zero = {};
+  for (int k = k0; k < k1; k += 32 * PF) {
+    v8 a[PF], b[PF][NT];
+#pragma unroll
+    for (int s = 0; s < PF; ++s) {
+      const int kk = k + 32 * s + 8 * g;
+      const bool ok = kk < k1;
+      a[s] = ok ? A(kk) : zero;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) b[s][t] = ok ? B(kk, t) : zero;
+    }
+#pragma unroll
+    for (int s = 0; s < PF; ++s) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) tmp[t] = Mx<T16>::mma(a[s], b[s][t], tmp[t]);
+    }
+  }
+}
+
+template <typename T16, typename TR, bool SCALE, int NT>
+__global__ __launch_bounds__(kItemThreads) void k_hmat_x16(
+    const Item* __restrict__ items, const int32_t* __restrict__ seg_ptr, const int32_t* __restrict__ lagT,
+    const int32_t* __restrict__ lagCol, const int32_t* __restrict__ lagColOff, const T16* __restrict__ arena,
+    const TR* __restrict__ ring, int64_t head, int64_t R, int N, int S, int nv,
+    const double* __restrict__ tail_acc, int64_t tail_len, float* __restrict__ partials) {
+  typedef typename Mx<T16>::v8 v8;
+  constexpr int NC = 16 * NT;
+  constexpr int RW = NT == 1 ? 8 : 4;   // row tiles per wave held across a segment
+  constexpr int PF = NT == 1 ? 8 : 4;   // inner steps loaded ahead
+  __shared__ __attribute__((aligned(16))) T16 h[kHist16];
+  __shared__ __attribute__((aligned(16))) T16 z[kZ16];
+  __shared__ float smax[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, g = lane >> 4;
+  const int x0 = seg_ptr[blockIdx.x], x1 = seg_ptr[blockIdx.x + 1];
+  const int p = items[x0].p;
+  const int RT = (p + 15) >> 4;
+  const bool wide = RT >= 4;
+  const int KS = wide ? 1 : 4 / RT;          // inner-range splits of a narrow block
+  const int rt_n = wide ? 0 : wave % RT;     // a narrow block's row tile of this wave
+  const int ks = wide ? 0 : wave / RT;
+  const bool active = wide || ks < KS;
+  const int my_tiles = wide ? (RT - wave + 3) / 4 : (active ? 1 : 0);
+  const bool held = my_tiles <= RW;          // else a single-item segment, written per row tile
+  float* out = partials + items[x0].part;
+  mfma_f4 acc[RW][NT];
+#pragma unroll
+  for (int u = 0; u < RW; ++u)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[u][t] = mfma_f4{0.0f, 0.0f, 0.0f, 0.0f};
+
+  for (int x = x0; x < x1; ++x) {
+    const Item it = items[x];
+    const int q = it.q, q8 = (q + 7) & ~7, nl = it.nlag;
+    const int span = it.src == 0 ? nl + S - 1 : 1;
+    const int nrow = span * nv;
+    const int64_t tnew = head + S - 1 - lagT[it.lag_off];
+    __syncthreads();  // the previous item is done with h and z
+    // ---- stage the history panel (16-bit, scaled by 1/hs for FP16)
+    float hs = 1.0f;
+    if (SCALE) {
+      float m = 0.0f;
+      for (int rv = wave; rv < nrow; rv += 4) {
+        if (it.src == 0) {
+          const int r = rv / nv, v = rv - r * nv;
+          const TR* src = ring + (ring_slot(tnew - r, R) * nv + v) * (int64_t)N + it.col0;
+          for (int j = lane; j < q; j += 64) m = fmaxf(m, fabsf((float)src[j]));
+        } else {
+          const double* src = tail_acc + (int64_t)rv * tail_len + it.tail_off;
+          for (int j = lane; j < q; j += 64) m = fmaxf(m, fabsf((float)src[j]));
+        }
+      }
+      m = wave_max(m);
+      if (lane == 0) smax[wave] = m;
+      __syncthreads();
+      hs = pow2_at_least(fmaxf(fmaxf(smax[0], smax[1]), fmaxf(smax[2], smax[3])));
+    }
+    const float hsi = 1.0f / hs;
+    for (int rv = wave; rv < nrow; rv += 4) {
+      T16* dst = h + rv * q8;
+      if (it.src == 0) {
+        const int r = rv / nv, v = rv - r * nv;
+        const TR* src = ring + (ring_slot(tnew - r, R) * nv + v) * (int64_t)N + it.col0;
+        for (int j = lane; j < q8; j += 64) dst[j] = j < q ? Mx<T16>::cvt((float)src[j] * hsi) : Mx<T16>::cvt(0.0f);
+      } else {  // static tail (ensembles): the expired-slip accumulators of variant rv
+        const double* src = tail_acc + (int64_t)rv * tail_len + it.tail_off;
+        for (int j = lane; j < q8; j += 64) dst[j] = Mx<T16>::cvt(j < q ? (float)src[j] * hsi : 0.0f);
+      }
+    }
+    // column offsets of this lane's N-tiles
+    int hoff[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int n = t * 16 + l16, k = n / nv, v = n - k * nv;
+      hoff[t] = ((S - 1 - k) * nv + v) * q8;
+    }
+    __syncthreads();
+    const T16* base = arena + it.data;
+    float sc = it.scale * hs;
+    int E, stride;
+    const T16* M;
+    if (it.kind == 0) {
+      // ---- projection Z_l = W_l H_l per lag, column tiles of 16 round robin over waves
+      const int nc = it.ncol, nc8 = (nc + 7) & ~7;
+      const int32_t* cp = lagCol + lagColOff[x];
+      float zs = 1.0f;
+      if (SCALE) {
+        zs = 1.0f / pow2_at_least((float)q8);
+        sc /= zs;
+      }
+      int tile = 0;
+      for (int l = 0; l < nl; ++l) {
+        const int cb = cp[l], ce = cp[l + 1];
+        const int lofs = l * nv * q8;
+        for (int c0 = cb; c0 < ce; c0 += 16, ++tile) {
+          if ((tile & 3) != wave) continue;
+          mfma_f4 tmp[NT];
+#pragma unroll
+          for (int t = 0; t < NT; ++t) tmp[t] = mfma_f4{0.0f, 0.0f, 0.0f, 0.0f};
+          const int c = c0 + l16;
+          const T16* wrow = base + (int64_t)min(c, ce - 1) * q8;
+          x16_kloop<T16, NT, 2>(
+              0, q8, [&](int kk) { return c < ce ? *(const v8*)(wrow + kk) : v8{}; },
+              [&](int kk, int t) { return *(const v8*)(h + lofs + kk + hoff[t]); }, tmp, g);
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int cc = c0 + 4 * g + v;
+              if (cc < ce) z[(t * 16 + l16) * nc8 + cc] = Mx<T16>::cvt(tmp[t][v] * zs);
+            }
+          }
+        }
+      }
+      for (int e = tid; e < NC * (nc8 - nc); e += kItemThreads) {  // zero pad columns
+        const int n = e / (nc8 - nc), c = nc + e - n * (nc8 - nc);
+        z[n * nc8 + c] = Mx<T16>::cvt(0.0f);
+      }
+      __syncthreads();
+      M = base + (int64_t)nc * q8;
+      E = nc8;
+      stride = nc8;
+    } else {
+      M = base;
+      E = nl * q8;
+      stride = nl * q8;
+    }
+    if (!active) continue;
+    // ---- expansion / dense product: Y (p x NC) += sc * M (p x E) B (E x NC)
+    const int k0 = wide ? 0 : ((int)((int64_t)(E / 8) * ks / KS)) * 8;
+    const int k1 = wide ? E : ((int)((int64_t)(E / 8) * (ks + 1) / KS)) * 8;
+    const float inv_q8 = 1.0f / (float)q8;
+    const int lag_stride = (nv - 1) * q8;
+    for (int u = 0; u < my_tiles; ++u) {
+      const int rt = wide ? wave + 4 * u : rt_n;
+      const int i = rt * 16 + l16;
+      const T16* arow = M + (int64_t)min(i, p - 1) * stride;
+      mfma_f4 tmp[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) tmp[t] = mfma_f4{0.0f, 0.0f, 0.0f, 0.0f};
+      auto A = [&](int kk) { return i < p ? *(const v8*)(arow + kk) : v8{}; };
+      if (it.kind == 0) {
+        x16_kloop<T16, NT, PF>(k0, k1, A, [&](int kk, int t) { return *(const v8*)(z + (t * 16 + l16) * (int64_t)E + kk); },
+                               tmp, g);
+      } else if (nv == 1) {
+        x16_kloop<T16, NT, PF>(k0, k1, A, [&](int kk, int t) { return *(const v8*)(h + kk + hoff[t]); }, tmp, g);
+      } else {
+        x16_kloop<T16, NT, PF>(
+            k0, k1, A,
+            [&](int kk, int t) {
+              const int l = (int)(((float)kk + 0.5f) * inv_q8);
+              return *(const v8*)(h + kk + l * lag_stride + hoff[t]);
+            },
+            tmp, g);
+      }
+      if (held) {
+#pragma unroll
+        for (int uu = 0; uu < RW; ++uu) {
+          if (uu == u) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[uu][t] += sc * tmp[t];
+          }
+        }
+      } else {  // single-item segment of a tall block (wide): write this row tile
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int ii = rt * 16 + 4 * g + v;
+            if (ii < p) out[ii * NC + t * 16 + l16] = sc * tmp[t][v];
+          }
+        }
+      }
+    }
+  }
+  if (wide) {
+    if (!held) return;
+#pragma unroll
+    for (int u = 0; u < RW; ++u) {
+      if (u >= my_tiles) break;
+      const int rt = wave + 4 * u;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int ii = rt * 16 + 4 * g + v;
+          if (ii < p) out[ii * NC + t * 16 + l16] = acc[u][t][v];
+        }
+      }
+    }
+    return;
+  }
+  // narrow block: add the inner-range splits in split order through LDS
+  float* red = reinterpret_cast<float*>(h);  // 4 waves x NT x 256 floats <= 32 KB
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[((wave * NT) + t) * 256 + lane * 4 + v] = acc[0][t][v];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < RT * NT * 256; e += kItemThreads) {
+    const int rt = e / (NT * 256), rem = e - rt * NT * 256, t = rem >> 8, w = rem & 255, ln = w >> 2, v = w & 3;
+    float sum = 0.0f;
+    for (int kk = 0; kk < KS; ++kk) sum += red[(((kk * RT + rt) * NT) + t) * 256 + ln * 4 + v];
+    const int ii = rt * 16 + 4 * (ln >> 4) + v;
+    if (ii < p) out[ii * NC + t * 16 + (ln & 15)] = sum;
+  }
+}
+
 // One 64-lane wave per receiver: lanes stride over the receiver's partial list,
 // then a butterfly sum (fixed order, independent of scheduling).
 // Far partials: S values per (item, row); f_far[k*N + r] = -eta sum.
@@ -396,11 +686,15 @@ __global__ void k_reduce_near(const double* __restrict__ partials, const int32_t
 // ------------------------------------------------------------------ self term
 // One 64-lane wave per mode: Fh_n = sum_{T=1}^{W_n} K_n^T D_n^{time0 - T}, where
 // time0 is the time of the coefficient being formed; butterfly sum over lanes.
-__global__ void k_self_hist(const SelfMode* __restrict__ modes, int n_modes, const double* __restrict__ tab,
-                            const double2* __restrict__ dring, int64_t time0, double2* __restrict__ Fh) {
+__global__ void k_self_hist(const SelfMode* __restrict__ modes, int n_modes, int nv, int64_t dring_len,
+                            const double* __restrict__ tab, const double2* __restrict__ dring, int64_t time0,
+                            double2* __restrict__ Fh) {
   const int lane = threadIdx.x & 63;
-  const int gm = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (gm >= n_modes) return;
+  const int gg = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (gg >= n_modes * nv) return;
+  const int v = gg / n_modes, gm = gg - v * n_modes;
+  dring += v * dring_len;
+  Fh += (int64_t)v * n_modes;
   const SelfMode md = modes[gm];
   double re = 0.0, im = 0.0;
   for (int T = 1 + lane; T <= md.W; T += 64) {
@@ -426,14 +720,20 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Optionally D_n is stored in the mode's ring at push_time, which must lie in
 // the window (ring_head - W_n, ring_head] of the ring's newest time ring_head
 // (older times would overwrite newer slots).
-__global__ void k_dft(const SelfMode* __restrict__ modes, int n_modes, const SelfFaultDev* __restrict__ sf,
-                      const double* __restrict__ delta, const double* __restrict__ vel, double coef,
-                      const double2* __restrict__ tw, const double* __restrict__ tab,
-                      const double2* __restrict__ Fh, double2* __restrict__ Dout, double2* __restrict__ Fout,
+__global__ void k_dft(const SelfMode* __restrict__ modes, int n_modes, int nv, int N, int64_t dring_len,
+                      const SelfFaultDev* __restrict__ sf, const double* __restrict__ delta,
+                      const double* __restrict__ vel, double coef, const double2* __restrict__ tw,
+                      const double* __restrict__ tab, const double2* __restrict__ Fh, double2* __restrict__ Fout,
                       double2* __restrict__ dring, int push, int64_t push_time, int64_t ring_head) {
   const int lane = threadIdx.x & 63;
-  const int gm = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (gm >= n_modes) return;
+  const int gg = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (gg >= n_modes * nv) return;
+  const int v = gg / n_modes, gm = gg - v * n_modes;
+  delta += (int64_t)v * N;
+  if (vel) vel += (int64_t)v * N;
+  if (Fh) Fh += (int64_t)v * n_modes;
+  Fout += (int64_t)v * n_modes;
+  dring += v * dring_len;
   const SelfMode md = modes[gm];
   const SelfFaultDev f = sf[md.fault];
   const double2* w = tw + f.tw;
@@ -449,7 +749,6 @@ __global__ void k_dft(const SelfMode* __restrict__ modes, int n_modes, const Sel
   if (lane != 0) return;
   const double k0 = tab[md.tab];
   const double c = -f.cfac * md.n;
-  if (Dout) Dout[gm] = make_double2(re, im);
   const double2 fh = Fh ? Fh[gm] : make_double2(0.0, 0.0);
   Fout[gm] = make_double2(c * (k0 * re + fh.x), c * (k0 * im + fh.y));
   if (push && md.W > 0 && push_time > ring_head - md.W)
@@ -506,84 +805,103 @@ __device__ double newton_lnV(double A, double th, double eta, double a, double b
 // Expired-slip accumulators of the pairs whose source is element r's fault:
 // E += dt V^{t}, t = time_new - T_end - 1 (the rate that just left the window).
 template <typename TF>
-__device__ __forceinline__ void tail_update(const StepArgs<TF>& a, int r, int k, int j) {
+__device__ __forceinline__ void tail_update(const StepArgs<TF>& a, int v, int r, int k, int j) {
+  double* E = a.tail_acc + v * a.tail_len;
   for (int e = a.src_pairs_ptr[k]; e < a.src_pairs_ptr[k + 1]; ++e) {
     const int toff = a.src_pairs[2 * e], Tend = a.src_pairs[2 * e + 1];
     const int64_t t = a.time_new - Tend - 1;
-    if (t >= a.first) a.tail_acc[toff + j] += a.dt * a.ring64[ring_slot(t, a.R) * a.N + r];
+    if (t >= a.first) E[toff + j] += a.dt * a.ring64[(ring_slot(t, a.R) * a.nv + v) * a.N + r];
   }
 }
 
-// One wave per element: inverse transform by the whole wave, then lane 0 solves.
+// operand copy of a rate value
+template <typename TF>
+__device__ __forceinline__ TF to_op(double x) {
+  return (TF)x;
+}
+template <>
+__device__ __forceinline__ __bf16 to_op<__bf16>(double x) {
+  return (__bf16)(float)x;
+}
+
+// One wave per (variant, element): inverse transform by the whole wave, then
+// lane 0 solves.
 template <typename TF>
 __global__ void k_stage(StepArgs<TF> a, int stage) {
   const int lane = threadIdx.x & 63;
-  const int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (r >= a.N) return;
+  const int rg = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (rg >= a.N * a.nv) return;
+  const int v = rg / a.N, r = rg - v * a.N;
+  const int64_t o = (int64_t)v * a.N, e = o + r;
   const int k = a.fault_of[r];
   const SelfFaultDev f = a.sf[k];
   const int j = r - f.off;
-  const double fself = idft_wave(f, a.F + f.mode_off, a.tw + f.tw, j, lane);
+  const double fself = idft_wave(f, a.F + (int64_t)v * a.n_modes + f.mode_off, a.tw + f.tw, j, lane);
   if (lane != 0) return;
-  const double tau0 = a.tau0[r] + a.tau0_rate[r] * a.t_next;
+  const double tau0 = a.tau0[e] + a.tau0_rate[e] * a.t_next;
   const Friction& fr = a.fric;
   if (stage == 0) {  // predictor: delta*, theta* from the current rates
-    const double V = a.V[r];
-    const double th_s = a.theta[r] + a.dt * a.thdot[r];
-    const double fint = a.f_hist[r] - a.eta * lag0_apply(a.l0_ptr, a.l0_col, a.l0_val, a.V, r);
-    const double Vs = newton_lnV(tau0 + fself + fint, th_s, a.eta, fr.a[r], fr.b[r], fr.Dc[r], fr.sn[r], fr.V0[r],
-                                 fr.f0[r], log(V), a.fail);
-    const double tds = state_rate(Vs, th_s, fr.Dc[r], fr.eps[r]);
-    a.Vstar[r] = Vs;
-    a.Vbar[r] = 0.5 * (V + Vs);
-    a.th2[r] = a.theta[r] + a.dt * 0.5 * (a.thdot[r] + tds);
+    const double V = a.V[e];
+    const double th_s = a.theta[e] + a.dt * a.thdot[e];
+    const double fint = a.f_hist[e] - a.eta * lag0_apply(a.l0_ptr, a.l0_col, a.l0_val, a.V + o, r);
+    const double Vs = newton_lnV(tau0 + fself + fint, th_s, a.eta, fr.a[e], fr.b[e], fr.Dc[e], fr.sn[e], fr.V0[e],
+                                 fr.f0[e], log(V), a.fail);
+    const double tds = state_rate(Vs, th_s, fr.Dc[e], fr.eps[e]);
+    a.Vstar[e] = Vs;
+    a.Vbar[e] = 0.5 * (V + Vs);
+    a.th2[e] = a.theta[e] + a.dt * 0.5 * (a.thdot[e] + tds);
   } else {  // corrector with the averaged rates; only the lag-0 terms change
-    const double Vb = a.Vbar[r];
-    const double th2 = a.th2[r];
-    const double fint = a.f_hist[r] - a.eta * lag0_apply(a.l0_ptr, a.l0_col, a.l0_val, a.Vbar, r);
-    const double V2 = newton_lnV(tau0 + fself + fint, th2, a.eta, fr.a[r], fr.b[r], fr.Dc[r], fr.sn[r], fr.V0[r],
-                                 fr.f0[r], log(a.Vstar[r]), a.fail);
-    const double td2 = state_rate(V2, th2, fr.Dc[r], fr.eps[r]);
+    const double Vb = a.Vbar[e];
+    const double th2 = a.th2[e];
+    const double fint = a.f_hist[e] - a.eta * lag0_apply(a.l0_ptr, a.l0_col, a.l0_val, a.Vbar + o, r);
+    const double V2 = newton_lnV(tau0 + fself + fint, th2, a.eta, fr.a[e], fr.b[e], fr.Dc[e], fr.sn[e], fr.V0[e],
+                                 fr.f0[e], log(a.Vstar[e]), a.fail);
+    const double td2 = state_rate(V2, th2, fr.Dc[e], fr.eps[e]);
     // commit: no other element reads V, theta, thdot or delta in this pass
-    a.delta[r] += a.dt * Vb;
-    a.theta[r] = th2;
-    a.thdot[r] = td2;
-    a.V[r] = V2;
-    a.f_self_out[r] = fself;
-    a.f_int_out[r] = fint;
-    const int64_t slot = ring_slot(a.time_new, a.R);
-    a.ring64[slot * a.N + r] = V2;
-    if ((void*)a.ringop != (void*)a.ring64) a.ringop[slot * a.N + r] = (TF)V2;
-    if (a.tail) tail_update(a, r, k, j);
+    a.delta[e] += a.dt * Vb;
+    a.theta[e] = th2;
+    a.thdot[e] = td2;
+    a.V[e] = V2;
+    a.f_self_out[e] = fself;
+    a.f_int_out[e] = fint;
+    const int64_t ri = (ring_slot(a.time_new, a.R) * a.nv + v) * a.N + r;
+    a.ring64[ri] = V2;
+    if ((void*)a.ringop != (void*)a.ring64) a.ringop[ri] = to_op<TF>(V2);
+    if (a.tail) tail_update(a, v, r, k, j);
   }
 }
 
 // Prescribed mode, before the evaluation of step n: append V^{n-1}, advance slip.
+// One thread per (variant, element).
 template <typename TF>
 __global__ void k_pre_push(StepArgs<TF> a, const double* __restrict__ Vin) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= a.N) return;
-  const double v = Vin[r];
-  const int64_t slot = ring_slot(a.time_new, a.R);
-  a.ring64[slot * a.N + r] = v;
-  if ((void*)a.ringop != (void*)a.ring64) a.ringop[slot * a.N + r] = (TF)v;
-  a.delta[r] += a.dt * v;
+  const int rg = blockIdx.x * blockDim.x + threadIdx.x;
+  if (rg >= a.N * a.nv) return;
+  const int v = rg / a.N, r = rg - v * a.N;
+  const double x = Vin[rg];
+  const int64_t ri = (ring_slot(a.time_new, a.R) * a.nv + v) * a.N + r;
+  a.ring64[ri] = x;
+  if ((void*)a.ringop != (void*)a.ring64) a.ringop[ri] = to_op<TF>(x);
+  a.delta[rg] += a.dt * x;
   if (a.tail) {
     const int k = a.fault_of[r];
-    tail_update(a, r, k, r - a.sf[k].off);
+    tail_update(a, v, r, k, r - a.sf[k].off);
   }
 }
 
-// Prescribed mode output: f^n = f_self + f_hist - mu/(2cs) K^0 V^{n-1} (one wave per element).
+// Prescribed mode output: f^n = f_self + f_hist - mu/(2cs) K^0 V^{n-1} (one wave
+// per (variant, element)).
 template <typename TF>
 __global__ void k_pre_out(StepArgs<TF> a, const double* __restrict__ Vprev, double* __restrict__ fout) {
   const int lane = threadIdx.x & 63;
-  const int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (r >= a.N) return;
+  const int rg = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (rg >= a.N * a.nv) return;
+  const int v = rg / a.N, r = rg - v * a.N;
+  const int64_t o = (int64_t)v * a.N;
   const int k = a.fault_of[r];
   const SelfFaultDev f = a.sf[k];
-  const double fself = idft_wave(f, a.F + f.mode_off, a.tw + f.tw, r - f.off, lane);
-  if (lane == 0) fout[r] = fself + a.f_hist[r] - a.eta * lag0_apply(a.l0_ptr, a.l0_col, a.l0_val, Vprev, r);
+  const double fself = idft_wave(f, a.F + (int64_t)v * a.n_modes + f.mode_off, a.tw + f.tw, r - f.off, lane);
+  if (lane == 0) fout[rg] = fself + a.f_hist[rg] - a.eta * lag0_apply(a.l0_ptr, a.l0_col, a.l0_val, Vprev + o, r);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -630,7 +948,42 @@ void launch_hmat(const HostOp& h, int S, int n_items, const void* items, const i
 }
 
 bool far_partials_f32(const HostOp& h, int S) {
-  return h.prm.factor_dtype == SEAS_F32 && S == 16 && h.use_mfma;
+  return h.x16 || (h.prm.factor_dtype == SEAS_F32 && S == 16 && h.use_mfma);
+}
+
+template <typename T16, typename TR, bool SCALE, int NT>
+static void x16_launch(const HostOp& h, const void* items, const int32_t* seg_ptr, const int32_t* lagT,
+                       const int32_t* lagCol, const int32_t* lagColOff, const void* arena, const void* ring,
+                       int64_t head, const double* tail_acc, float* partials, hipStream_t s) {
+  const int nseg = (int)h.seg_ptr.size() - 1;
+  hipLaunchKernelGGL((k_hmat_x16<T16, TR, SCALE, NT>), dim3(nseg), dim3(kItemThreads), 0, s, (const Item*)items,
+                     seg_ptr, lagT, lagCol, lagColOff, (const T16*)arena, (const TR*)ring, head, (int64_t)h.ring_len,
+                     h.N, h.time_block, h.n_variants, tail_acc, (int64_t)h.tail_len, partials);
+}
+
+void launch_hmat_x16(const HostOp& h, const void* items, const int32_t* seg_ptr, const int32_t* lagT,
+                     const int32_t* lagCol, const int32_t* lagColOff, const void* arena, const void* ring,
+                     int64_t head, const double* tail_acc, float* partials, hipStream_t s) {
+  if (h.seg_ptr.size() < 2) return;
+  const bool bf = h.prm.factor_dtype == SEAS_BF16;
+  if (h.n_variants == 1) {
+    if (bf) x16_launch<__bf16, float, false, 1>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head, tail_acc, partials, s);
+    else x16_launch<_Float16, float, true, 1>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head, tail_acc, partials, s);
+    return;
+  }
+  // ensembles: BF16 with a BF16 rate history, or FP16 with an FP32 one scaled per item
+#define SEAS_X16_ENS(NT)                                                                                      \
+  if (bf) x16_launch<__bf16, __bf16, false, NT>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head,   \
+                                                tail_acc, partials, s);                                        \
+  else x16_launch<_Float16, float, true, NT>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head,     \
+                                             tail_acc, partials, s);
+  switch (h.ncols) {
+    case 16: SEAS_X16_ENS(1) break;
+    case 32: SEAS_X16_ENS(2) break;
+    case 64: SEAS_X16_ENS(4) break;
+    default: break;
+  }
+#undef SEAS_X16_ENS
 }
 
 template <typename TP>
@@ -643,6 +996,8 @@ static void reduce_far_t(const HostOp& h, int S, const TP* partials, const int32
     case 4: hipLaunchKernelGGL((k_reduce_far<4, TP>), g, b, 0, s, partials, ptr, idx, h.N, -h.eta, f); break;
     case 8: hipLaunchKernelGGL((k_reduce_far<8, TP>), g, b, 0, s, partials, ptr, idx, h.N, -h.eta, f); break;
     case 16: hipLaunchKernelGGL((k_reduce_far<16, TP>), g, b, 0, s, partials, ptr, idx, h.N, -h.eta, f); break;
+    case 32: hipLaunchKernelGGL((k_reduce_far<32, TP>), g, b, 0, s, partials, ptr, idx, h.N, -h.eta, f); break;
+    case 64: hipLaunchKernelGGL((k_reduce_far<64, TP>), g, b, 0, s, partials, ptr, idx, h.N, -h.eta, f); break;
     default: break;
   }
 }
@@ -659,39 +1014,43 @@ void launch_reduce_near(const HostOp& h, const double* partials, const int32_t* 
                      f);
 }
 
-void launch_self_hist(int n_modes, const SelfMode* modes, const double* tab, const double2* dring, int64_t time0,
-                      double2* Fh, hipStream_t s) {
-  hipLaunchKernelGGL(k_self_hist, dim3(blocks_for(n_modes, 4)), dim3(256), 0, s, modes, n_modes, tab, dring, time0,
-                     Fh);
+void launch_self_hist(int n_modes, int nv, int64_t dring_len, const SelfMode* modes, const double* tab,
+                      const double2* dring, int64_t time0, double2* Fh, hipStream_t s) {
+  hipLaunchKernelGGL(k_self_hist, dim3(blocks_for((int64_t)n_modes * nv, 4)), dim3(256), 0, s, modes, n_modes, nv,
+                     dring_len, tab, dring, time0, Fh);
 }
 
-void launch_dft(int n_modes, const SelfMode* modes, const SelfFaultDev* sf, const double* delta, const double* vel,
-                double coef, const double2* tw, const double* tab, const double2* Fh, double2* Dout, double2* Fout,
-                double2* dring, int push, int64_t push_time, int64_t ring_head, hipStream_t s) {
-  hipLaunchKernelGGL(k_dft, dim3(blocks_for(n_modes, 4)), dim3(256), 0, s, modes, n_modes, sf, delta, vel, coef, tw,
-                     tab, Fh, Dout, Fout, dring, push, push_time, ring_head);
+void launch_dft(int n_modes, int nv, int N, int64_t dring_len, const SelfMode* modes, const SelfFaultDev* sf,
+                const double* delta, const double* vel, double coef, const double2* tw, const double* tab,
+                const double2* Fh, double2* Fout, double2* dring, int push, int64_t push_time, int64_t ring_head,
+                hipStream_t s) {
+  hipLaunchKernelGGL(k_dft, dim3(blocks_for((int64_t)n_modes * nv, 4)), dim3(256), 0, s, modes, n_modes, nv, N,
+                     dring_len, sf, delta, vel, coef, tw, tab, Fh, Fout, dring, push, push_time, ring_head);
 }
 
 template <typename TF>
 void launch_stage(const StepArgs<TF>& a, int stage, hipStream_t s) {
-  hipLaunchKernelGGL((k_stage<TF>), dim3(blocks_for(a.N, 4)), dim3(256), 0, s, a, stage);
+  hipLaunchKernelGGL((k_stage<TF>), dim3(blocks_for((int64_t)a.N * a.nv, 4)), dim3(256), 0, s, a, stage);
 }
 
 template <typename TF>
 void launch_prescribed_push(const StepArgs<TF>& a, const double* Vin, hipStream_t s) {
-  hipLaunchKernelGGL((k_pre_push<TF>), dim3(blocks_for(a.N, 256)), dim3(256), 0, s, a, Vin);
+  hipLaunchKernelGGL((k_pre_push<TF>), dim3(blocks_for((int64_t)a.N * a.nv, 256)), dim3(256), 0, s, a, Vin);
 }
 
 template <typename TF>
 void launch_prescribed_out(const StepArgs<TF>& a, const double* Vprev, double* fout, hipStream_t s) {
-  hipLaunchKernelGGL((k_pre_out<TF>), dim3(blocks_for(a.N, 4)), dim3(256), 0, s, a, Vprev, fout);
+  hipLaunchKernelGGL((k_pre_out<TF>), dim3(blocks_for((int64_t)a.N * a.nv, 4)), dim3(256), 0, s, a, Vprev, fout);
 }
 
 template void launch_stage<double>(const StepArgs<double>&, int, hipStream_t);
 template void launch_stage<float>(const StepArgs<float>&, int, hipStream_t);
+template void launch_stage<__bf16>(const StepArgs<__bf16>&, int, hipStream_t);
 template void launch_prescribed_push<double>(const StepArgs<double>&, const double*, hipStream_t);
 template void launch_prescribed_push<float>(const StepArgs<float>&, const double*, hipStream_t);
+template void launch_prescribed_push<__bf16>(const StepArgs<__bf16>&, const double*, hipStream_t);
 template void launch_prescribed_out<double>(const StepArgs<double>&, const double*, double*, hipStream_t);
 template void launch_prescribed_out<float>(const StepArgs<float>&, const double*, double*, hipStream_t);
+template void launch_prescribed_out<__bf16>(const StepArgs<__bf16>&, const double*, double*, hipStream_t);
 
 }  // namespace seas

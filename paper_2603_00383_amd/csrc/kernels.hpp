@@ -26,9 +26,13 @@ struct Friction {
 };
 
 // Arguments of the element kernels (predictor, corrector, prescribed output).
+// Per-element arrays hold nv variants, variant-major ([nv][N]); the rate rings
+// are [R][nv][N], the modal arrays [nv][n_modes], the coefficient rings
+// [nv][dring_len] and the expired-slip accumulators [nv][tail_len].
 template <typename TF>
 struct StepArgs {
-  int N;
+  int N, nv, n_modes;
+  int64_t tail_len, dring_len;
   double dt, eta, t_next;
   const int* fault_of;
   const SelfFaultDev* sf;
@@ -64,11 +68,17 @@ void launch_reduce_far(const HostOp& h, int S, const void* partials, bool f32, c
                        const int32_t* idx, double* f, hipStream_t s);
 void launch_reduce_near(const HostOp& h, const double* partials, const int32_t* ptr, const int32_t* idx,
                         const double* base, double* f, hipStream_t s);
-void launch_self_hist(int n_modes, const SelfMode* modes, const double* tab, const double2* dring, int64_t time0,
-                      double2* Fh, hipStream_t s);
-void launch_dft(int n_modes, const SelfMode* modes, const SelfFaultDev* sf, const double* delta, const double* vel,
-                double coef, const double2* tw, const double* tab, const double2* Fh, double2* Dout, double2* Fout,
-                double2* dring, int push, int64_t push_time, int64_t ring_head, hipStream_t s);
+// 16-bit far list, one workgroup per segment
+void launch_hmat_x16(const HostOp& h, const void* items, const int32_t* seg_ptr, const int32_t* lagT,
+                     const int32_t* lagCol, const int32_t* lagColOff, const void* arena, const void* ring,
+                     int64_t head, const double* tail_acc, float* partials, hipStream_t s);
+// self term over nv variants: modal arrays [nv][n_modes], rings [nv][dring_len], slip [nv][N]
+void launch_self_hist(int n_modes, int nv, int64_t dring_len, const SelfMode* modes, const double* tab,
+                      const double2* dring, int64_t time0, double2* Fh, hipStream_t s);
+void launch_dft(int n_modes, int nv, int N, int64_t dring_len, const SelfMode* modes, const SelfFaultDev* sf,
+                const double* delta, const double* vel, double coef, const double2* tw, const double* tab,
+                const double2* Fh, double2* Fout, double2* dring, int push, int64_t push_time, int64_t ring_head,
+                hipStream_t s);
 template <typename TF>
 void launch_stage(const StepArgs<TF>& a, int stage, hipStream_t s);
 template <typename TF>

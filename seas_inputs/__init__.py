@@ -58,7 +58,8 @@ def _min_midpoint_node_distance(faults):
 
 
 def default_params(**over):
-    """Parameter set with the unstated values fixed as documented in the design doc."""
+    """Parameter set; the values the paper leaves open (leaf size, window safety
+    factors, self-window factor and modulation) are fixed here."""
     p = dict(mu=MU, cs=CS, beta=0.5,
              eta_H=2.0, aca_tol=1e-6, leaf=50, compress=1,
              eta_tmin=0.01, eta_tmax=0.01, int_tail=1,

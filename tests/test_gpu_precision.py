@@ -1,0 +1,199 @@
+"""GPU parity of the 16-bit matrix-core path (BF16 / FP16 factors with per-item
+power-of-two scales, FP32 accumulation) and of ensembles of friction variants,
+through the C ABI, against the FP64 oracle.
+
+Error measure: e = max_n |f_gpu^n - f_ref^n|_inf / max_n |f_ref^n|_inf (global over
+steps and elements), per variant for ensembles.
+
+Tolerances. FP16 keeps 11 significant bits (a stored value is off by at most
+2^-12 = 2.4e-4 of itself); with the per-item scales the stress meets the 1e-4
+reduced-precision target, which is the tolerance used. BF16 keeps 8 (2^-9 =
+2.0e-3 per value) and cannot meet 1e-4: a receiver's stress is dominated by a
+few near-field terms whose rounding does not average out. Its bound is one
+value's rounding, 2e-3, with one variant (lags below the time block in FP32,
+history in FP32 until staged) and 8e-3 for ensembles, where the factors of
+every lag, the history copy and the projected panel are each rounded once
+(3 x 2^-9 = 5.9e-3, plus the cancellation margin of the sums).
+"""
+import numpy as np
+import pytest
+
+import seas_inputs as SI
+from oracle import seas as OS
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_2603_00383_amd")
+
+TOL = {"bf16": 2e-3, "f16": 1e-4}
+TOL_ENS = {"bf16": 8e-3, "f16": 1e-4}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    torch.cuda.init()
+    yield
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _friction(N, nv=1):
+    f = dict(a=np.full(N, 0.01), b=np.full(N, 0.015), Dc=np.full(N, 5e-3), sigma_n=np.full(N, 50e6),
+             V0=np.full(N, 1e-6), f0=np.full(N, 0.6))
+    return {k: np.tile(v, nv) for k, v in f.items()}
+
+
+def rel_err(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def gpu_prescribed(faults, params, V, prior=None):
+    """V: (steps, N) or (steps, nv, N); returns f of the same shape."""
+    op = P.Operator(faults, params)
+    N, nv = op.N, op.info["n_variants"]
+    s = _stream()
+    st = P.State(op, _friction(N, nv), np.full(N * nv, 1e-9), np.full(N * nv, 5e6), np.zeros(N * nv), stream=s)
+    if prior is not None:
+        st.load_history(prior, stream=s)
+    Vd = torch.from_numpy(np.ascontiguousarray(V)).cuda()
+    fd = torch.empty_like(Vd)
+    print(f"[gpu] prescribed N={N} nv={nv} steps={V.shape[0]} dtype={params['factor_dtype']} "
+          f"segments={op.info['n_segments']}", flush=True)
+    st.eval_prescribed(Vd, V.shape[0], fd, stream=s)
+    torch.cuda.synchronize()
+    return fd.cpu().numpy(), op
+
+
+_REF = {}
+
+
+def oracle_prescribed(key, faults, params, V, prior=None):
+    if key not in _REF:
+        _REF[key] = OS.prescribed(OS.Problem(faults, params), V, prior_V=prior)
+    return _REF[key]
+
+
+# ------------------------------------------------------------ one variant
+C1 = SI.two_fault_prescribed_faults()
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_two_fault_prescribed_16bit(dtype):
+    V = SI.prescribed_slip_rate(C1, 256, 0)
+    p = SI.default_params(factor_dtype=dtype, aca_tol=1e-6, time_block=16)
+    f, op = gpu_prescribed(C1, p, V)
+    ref = oracle_prescribed("c1", C1, SI.default_params(compress=0), V)
+    e = rel_err(f, ref)
+    p32 = SI.default_params(factor_dtype="f32", aca_tol=1e-6, time_block=16)
+    f32, _ = gpu_prescribed(C1, p32, V)
+    e32 = rel_err(f32, ref)
+    print(f"[gpu] two-fault {dtype} S=16: err vs oracle {e:.3e} (fp32 path {e32:.3e}), "
+          f"far bytes {op.info['far_bytes'] / 1e6:.1f} MB", flush=True)
+    assert e < TOL[dtype]
+    assert e > 1e-7  # really 16-bit
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_ragged_network_16bit_with_prior_history(dtype):
+    faults = [SI.fault(0.0, 0.0, 0.0, 6000.0, 60), SI.fault(500.0, 2500.0, 25.0, 4000.0, 37),
+              SI.fault(-3000.0, -1800.0, 50.0, 3000.0, 23)]
+    p = SI.default_params(factor_dtype=dtype, aca_tol=1e-6, leaf=8, time_block=16)
+    prior = SI.saturated_history(faults, 300, 3)
+    V = SI.saturated_history(faults, 40, 4)
+    f, op = gpu_prescribed(faults, p, V, prior)
+    ref = oracle_prescribed(("ragged", 40), faults, SI.default_params(compress=0, leaf=8), V, prior)
+    e = rel_err(f, ref)
+    print(f"[gpu] ragged {dtype}: err {e:.3e} items {op.info['n_items']} segments {op.info['n_segments']}",
+          flush=True)
+    assert e < TOL[dtype]
+
+
+# ------------------------------------------------------------ ensembles
+E2 = SI.two_fault_prescribed_faults(n_elem=64, dx=200.0)
+
+
+def _ensemble_V(nv, steps, seed0=0):
+    return np.stack([SI.prescribed_slip_rate(E2, steps, seed0 + v) for v in range(nv)], axis=1)
+
+
+@pytest.mark.parametrize("dtype,nv", [("bf16", 16), ("bf16", 64), ("f16", 16), ("f16", 64)])
+def test_ensemble_prescribed_matches_oracle_per_variant(dtype, nv):
+    steps = 160
+    V = _ensemble_V(nv, steps)
+    p = SI.default_params(factor_dtype=dtype, aca_tol=1e-6, time_block=1, n_variants=nv)
+    f, op = gpu_prescribed(E2, p, V)
+    worst = 0.0
+    for v in range(0, nv, max(1, nv // 8)):
+        ref = oracle_prescribed(("e2", v), E2, SI.default_params(compress=0), V[:, v, :])
+        worst = max(worst, rel_err(f[:, v, :], ref))
+    print(f"[gpu] ensemble nv={nv} {dtype}: worst per-variant err {worst:.3e}", flush=True)
+    assert worst < TOL_ENS[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_ensemble_variants_do_not_mix(dtype):
+    """Each variant's stress is a function of its own history only: permuting
+    the variants permutes the results bit for bit, and changing the other
+    variants' histories leaves a variant's result bit for bit unchanged (BF16:
+    every column of a product is formed on its own; FP16: the history scale of an
+    item depends on all variants, so only the permutation is bitwise and a
+    variant in another mix agrees to the tolerance)."""
+    nv, steps = 16, 96
+    V = _ensemble_V(nv, steps)
+    p = SI.default_params(factor_dtype=dtype, aca_tol=1e-6, time_block=1, n_variants=nv)
+    f, _ = gpu_prescribed(E2, p, V)
+    perm = np.random.default_rng(5).permutation(nv)
+    fp, _ = gpu_prescribed(E2, p, V[:, perm, :])
+    assert np.array_equal(fp, f[:, perm, :])
+    V2 = V.copy()
+    V2[:, 1:, :] = _ensemble_V(nv - 1, steps, seed0=100)
+    f2, _ = gpu_prescribed(E2, p, V2)
+    if dtype == "bf16":
+        assert np.array_equal(f2[:, 0, :], f[:, 0, :])
+    else:
+        assert rel_err(f2[:, 0, :], f[:, 0, :]) < TOL_ENS[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_ensemble_seas_matches_oracle_per_variant(dtype):
+    """Friction variants (a - b, Dc drawn per variant) stepped together; each
+    variant's trajectory against the oracle stepping that variant alone."""
+    faults = SI.two_fault_prescribed_faults(n_elem=24, dx=50.0)
+    nv, steps = 16, 80
+    N = sum(f["n_elem"] for f in faults)
+    base = SI.rate_state_fields(faults)
+    var = SI.ensemble_variants(nv, seed=1)
+    frs, inis = [], []
+    for v in range(nv):
+        fr = dict(base)
+        fr["a"] = np.full(N, var["a"][v])
+        fr["b"] = np.full(N, var["b"][v])
+        fr["Dc"] = np.full(N, var["Dc"][v])
+        frs.append(fr)
+        inis.append(SI.near_nucleation_state(faults, fr, seed=0, V_init=1e-6, bump_amp=0.1))
+    cat = lambda key, src: np.concatenate([d[key] for d in src])
+    fric = {k: cat(k, frs) for k in ("a", "b", "Dc", "sigma_n", "V0", "f0")}
+    p = SI.default_params(factor_dtype=dtype, aca_tol=1e-6, time_block=1, n_variants=nv, compress=0)
+    op = P.Operator(faults, p)
+    s = _stream()
+    st = P.State(op, fric, cat("V", inis), cat("theta", inis), cat("tau0", inis), cat("tau0_rate", inis), stream=s)
+    print(f"[gpu] ensemble seas {dtype} nv={nv} N={N} steps={steps}", flush=True)
+    st.step(steps, stream=s)
+    st.check(stream=s)
+    worst = {"V": 0.0, "theta": 0.0, "delta": 0.0}
+    for v in range(0, nv, 3):
+        prob = OS.Problem(faults, SI.default_params(compress=0))
+        o = OS.SeasState(prob, frs[v], inis[v]["V"], inis[v]["theta"], inis[v]["tau0"], inis[v]["tau0_rate"])
+        for _ in range(steps):
+            o.step()
+        for k, ref in (("V", o.V), ("theta", o.theta), ("delta", o.delta)):
+            worst[k] = max(worst[k], rel_err(st.read(k, stream=s, variant=v), ref))
+    print("[gpu] ensemble seas worst per-variant err: " + ", ".join(f"{k} {e:.2e}" for k, e in worst.items()),
+          flush=True)
+    for k, e in worst.items():
+        assert e < TOL_ENS[dtype], (k, e)

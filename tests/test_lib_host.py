@@ -100,6 +100,63 @@ def test_lag_matrices_match_dense_kernel(compress, S):
         assert np.linalg.norm(R + G / eta) / np.linalg.norm(G / eta) < (1e-12 if compress == 0 else 2 * tol)
 
 
+@pytest.mark.parametrize("dtype,nv,S", [("bf16", 1, 16), ("f16", 1, 16), ("bf16", 16, 1), ("bf16", 64, 1)])
+def test_16bit_lag_matrices_match_dense_kernel(dtype, nv, S):
+    """16-bit factors with per-item power-of-two scales: the reconstructed lag
+    matrices are the FP64 kernel to the format's rounding (BF16 keeps 8
+    significant bits, FP16 11), plus the ACA tolerance for low-rank blocks. Lags
+    below S stay in FP32 (near list); ensembles put every lag and the static
+    tail in 16 bits."""
+    faults = SI.two_fault_prescribed_faults(n_elem=64, dx=200.0)
+    op = _op(faults, compress=1, aca_tol=1e-6, eta_H=1.0, leaf=16, time_block=S, factor_dtype=dtype,
+             n_variants=nv)
+    info = op.info
+    assert info["n_variants"] == nv and info["ncols"] == S * nv and info["n_segments"] > 0
+    # BF16 keeps 8 significant bits (half-ulp 2^-9), FP16 11 (2^-12); low-rank
+    # lags round both factors
+    rel = {"bf16": 2.0 ** -9, "f16": 2.0 ** -12}[dtype] * 3
+    geo = geometry.discretize(faults)
+    dt = geometry.time_step(geo, SI.CS)
+    seen16 = 0
+    for (a, b), (t0, t1) in op.windows().items():
+        for T in sorted({max(t0, 1), t0 + 3, S, S + 1, (t0 + t1) // 2, t1}):
+            if T < max(t0, 1) or T > t1:
+                continue
+            K = I.pair_kernel(geo, a, b, T, dt, SI.CS)
+            R = op.lag_matrix(a, b, T, 64, 64)
+            nrm = np.linalg.norm(K)
+            if nrm == 0:
+                assert np.all(R == 0)
+                continue
+            err = np.linalg.norm(R - K) / nrm
+            if T < S:
+                assert err < 2e-6, (a, b, T, err)  # FP32 near list
+            else:
+                seen16 += 1
+                assert err < rel + 2e-6, (a, b, T, err)
+                assert err > 1e-9, "16-bit storage expected"
+        G = I.static_dipole(geo, a, b, SI.MU)
+        R = op.lag_matrix(a, b, -1, 64, 64)
+        eta = SI.MU / (2 * SI.CS)
+        e = np.linalg.norm(R + G / eta) / np.linalg.norm(G / eta)
+        assert e < (rel + 2e-6 if nv > 1 else 2e-6), e
+    assert seen16 > 0
+
+
+def test_16bit_rounding_matches_numpy():
+    """The host conversions round to nearest even: FP16 against numpy's float16,
+    BF16 against the top 16 bits of the FP32 pattern rounded to nearest even."""
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.uniform(-1, 1, 4000), rng.uniform(-1e-4, 1e-4, 1000),
+                        [0.0, -0.0, 1.0, -1.0, 2.0 ** -24, 2.0 ** -14, 0.999999]]).astype(np.float32)
+    L = _lib_or_skip()
+    got16 = np.array([L.seas_round_factor(float(v), 3) for v in x], dtype=np.float64)
+    assert np.array_equal(got16, x.astype(np.float16).astype(np.float64))
+    u = x.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint32) << 16
+    assert np.array_equal(np.array([L.seas_round_factor(float(v), 2) for v in x]), r.view(np.float32).astype(np.float64))
+
+
 def test_compression_reduces_storage():
     faults = SI.five_fault_network(seed=0, n_elem=100)
     dense = _op(faults, compress=0, eta_H=2.0, leaf=25).info
