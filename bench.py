@@ -161,17 +161,94 @@ def run_ensemble(args):
     print(json.dumps(out), flush=True)
 
 
+def _window(SI, np, faults, seed, quiet=False):
+    """One request's seeded friction (a - b and Dc drawn per request on the
+    velocity-weakening patches) and its near-nucleation initial state."""
+    fric = SI.rate_state_fields(faults)
+    N = len(fric["a"])
+    if quiet:  # velocity strengthening at steady state: an idle slot
+        fric["b"] = np.full(N, 0.005)
+        ini = SI.near_nucleation_state(faults, fric, seed=seed, bump_amp=0.0)
+    else:
+        var = SI.ensemble_variants(1, seed=seed)
+        fric["b"] = np.where(fric["b"] > 0.01, var["b"][0], fric["b"])
+        fric["Dc"] = np.full(N, var["Dc"][0])
+        ini = SI.near_nucleation_state(faults, fric, seed=seed, bump_amp=0.05)
+    return dict(fric=fric, V=ini["V"], theta=ini["theta"], tau0=ini["tau0"], tau0_rate=ini["tau0_rate"])
+
+
+def run_serving(args):
+    """Serving: a Poisson stream of simulation-window requests on seeded geometry
+    templates, admitted into variant slots of one ensemble state per template
+    (continuous batching), p50/p99 completion latency and throughput."""
+    import numpy as np
+
+    import paper_2603_00383_amd as P
+    import seas_inputs as SI
+
+    dtype = args.dtype or "f16"
+    slots = 16
+    sizes = (500, 1000, 2000)
+    tpls = SI.serving_templates(seed=args.seed, n_templates=args.templates, sizes=sizes)
+    reqs = SI.poisson_requests(n_requests=args.requests, rate=args.rate, seed=args.seed,
+                               n_templates=args.templates, min_steps=args.min_steps, max_steps=args.max_steps)
+    ops, build_s = [], 0.0
+    for k, f in enumerate(tpls):
+        t0 = time.perf_counter()
+        ops.append(P.Operator(f, SI.default_params(factor_dtype=dtype, aca_tol=1e-6, eta_H=2.0, leaf=50,
+                                                   time_block=1, n_variants=slots)))
+        build_s += time.perf_counter() - t0
+        print(f"[bench] template {k}: N={ops[-1].N} faults={len(f)} built", file=sys.stderr, flush=True)
+    idle = [_window(SI, np, f, 0, quiet=True) for f in tpls]
+    budget = int(args.budget_gb * 2 ** 30)
+    sv = P.Server(ops, idle, budget, chunk_steps=args.chunk)
+    trace = [dict(pool=q["template"], n_steps=q["n_steps"], arrival_s=q["arrival"],
+                  window=_window(SI, np, tpls[q["template"]], q["seed"])) for q in reqs]
+    print(f"[bench] serving {len(trace)} requests over {reqs[-1]['arrival']:.1f} s", file=sys.stderr, flush=True)
+    w0 = time.perf_counter()
+    res = sv.run(trace)
+    wall = time.perf_counter() - w0
+    lat = np.array([r["finish_s"] - q["arrival_s"] for r, q in zip(res, trace)])
+    work = float(sum(ops[q["pool"]].N * q["n_steps"] for q in trace))
+    bad = sum(1 for r in res if r["status"] != 0)
+    out = {
+        "metric": METRIC,
+        "value": work / wall,
+        "unit": "element-steps/s",
+        "n_gpus": 1, "steps": int(sum(q["n_steps"] for q in trace)), "warmup": 0,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": dtype, "data": "synthetic",
+        "config": {"workload": f"serving: {len(trace)} Poisson requests (rate {args.rate}/s), {args.templates} "
+                               f"seeded templates with N in {list(sizes)} and 2-10 faults, windows "
+                               f"{args.min_steps}-{args.max_steps} steps, {slots} slots per template, "
+                               f"{dtype.upper()} factors, chunks of {args.chunk} steps",
+                   "seed": args.seed, "templates": [o.N for o in ops], "budget_GiB": args.budget_gb},
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                      "max": float(lat.max())},
+        "makespan_s": wall, "trace_span_s": float(reqs[-1]["arrival"]), "failed_requests": bad,
+        "build_s": build_s,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="seas", choices=["seas", "ensemble"],
+    ap.add_argument("--workload", default="seas", choices=["seas", "ensemble", "serving"],
                     help="seas: five-fault step loop (one variant); ensemble: eight faults x 750 elements, "
                          "64 friction variants in one launch (BF16)")
     ap.add_argument("--dtype", default=None, choices=["f32", "f64", "bf16", "f16"],
                     help="factor dtype (default f32; bf16 for the ensemble)")
     ap.add_argument("--variants", type=int, default=64, help="ensemble: friction variants (16, 32 or 64)")
+    ap.add_argument("--templates", type=int, default=4, help="serving: geometry templates")
+    ap.add_argument("--requests", type=int, default=32, help="serving: requests in the trace")
+    ap.add_argument("--rate", type=float, default=4.0, help="serving: arrivals per second")
+    ap.add_argument("--min-steps", type=int, default=200, help="serving: shortest window")
+    ap.add_argument("--max-steps", type=int, default=2000, help="serving: longest window")
+    ap.add_argument("--chunk", type=int, default=16, help="serving: steps per launch chunk")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: device memory for states")
     ap.add_argument("--aca", type=float, default=1e-6)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--time-block", type=int, default=16,
@@ -207,6 +284,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "ensemble":
         return run_ensemble(args)
+    if args.workload == "serving":
+        return run_serving(args)
     if args.dtype is None:
         args.dtype = "f32"
     faults = SI.five_fault_network(seed=args.seed)

@@ -203,6 +203,18 @@ void seas_state_destroy(seas_state_t* st);
 seas_status seas_state_load_history(seas_state_t* st, const double* V_hist, int32_t n_hist,
                                     void* stream);
 
+/* Start a new window in one variant slot of a stepping (or fresh) state: the
+ * slot's friction parameters, slip rate, state, background stress and its rate
+ * and slip (host arrays of N; tau0_rate, delta_init and fric->eps may be NULL)
+ * replace the old ones, its rate and coefficient histories and expired-slip
+ * accumulators are cleared, and the slot's time origin becomes the current step
+ * (its loading rate counts from there). The other variants are untouched and
+ * keep stepping; the slot evolves exactly as a fresh state would from t = 0.
+ * For continuous batching of requests that share a geometry. Synchronises the
+ * stream. */
+seas_status seas_state_reset_variant(seas_state_t* st, int32_t variant, const seas_friction_t* fric,
+                                     const double* V_init, const double* theta_init, const double* tau0,
+                                     const double* tau0_rate, const double* delta_init, void* stream);
 /* Stress evaluation of a prescribed slip-rate history (no friction): for
  * n = 1..n_steps, with V^m = V_dev[m][variant][element] (device, FP64,
  * n_steps x n_variants x N):
@@ -255,6 +267,43 @@ int64_t seas_state_step_index(const seas_state_t* st);
 size_t seas_state_checkpoint_bytes(const seas_state_t* st);
 seas_status seas_state_save(const seas_state_t* st, void* host_buf, size_t bytes, void* stream);
 seas_status seas_state_restore(seas_state_t* st, const void* host_buf, size_t bytes, void* stream);
+
+/* ---------------------------------------------------------------- serving
+ * A request loop for simulation windows on several geometries ("pools", one
+ * operator each, built with n_variants slots). Each pool steps one ensemble
+ * state on its own stream, in chunks of at most chunk_steps steps; requests of
+ * a pool join free variant slots between chunks (seas_state_reset_variant) and
+ * leave when their window ends, so a running batch admits new requests while
+ * others are on the GPU. A pool's state is created when its first request
+ * arrives and the sum of the states' bytes (seas_state_bytes) stays within
+ * device_budget; an idle pool gives its memory back when another pool waits
+ * for it. Requests queue per pool in arrival order. Not an accuracy feature:
+ * a request's result is the one it gets alone in a fresh state (bit for bit
+ * with BF16 factors, to the FP16 tolerance with FP16 factors, whose history
+ * scales see the other slots). */
+typedef struct {
+  int32_t pool;           /* index of the request's operator in seas_server_create */
+  int32_t n_steps;        /* window length in steps (>= 1) */
+  double arrival_s;       /* arrival time in seconds after seas_server_run starts */
+  seas_friction_t fric;   /* N values each (host, read during the run) */
+  const double *V_init, *theta_init, *tau0;  /* N values (host) */
+  const double *tau0_rate, *delta_init;      /* N values (host) or NULL */
+  double *V_out, *theta_out, *delta_out;     /* N values (host) written when the window ends, or NULL */
+  double admit_s;         /* out: time it took a slot */
+  double finish_s;        /* out: time its results were copied out */
+  int32_t status;         /* out: SEAS_OK, or the error its pool reported (e.g. NOT_CONVERGED) */
+  int32_t reserved;
+} seas_request_t;
+typedef struct seas_server seas_server_t;
+/* ops: n_ops operators (not owned; must outlive the server); idle: one request
+ * per pool whose friction and initial values fill the slots no request holds
+ * (a quiet, steady window, so that idle slots neither diverge nor fail). */
+seas_status seas_server_create(seas_op_t* const* ops, int32_t n_ops, const seas_request_t* idle,
+                               size_t device_budget, int32_t chunk_steps, seas_server_t** out);
+/* Play a trace of n_reqs requests in real time and return when all are done.
+ * Blocking; fills admit_s, finish_s and status of every request. */
+seas_status seas_server_run(seas_server_t* sv, seas_request_t* reqs, int32_t n_reqs);
+void seas_server_destroy(seas_server_t* sv);
 
 #ifdef __cplusplus
 }

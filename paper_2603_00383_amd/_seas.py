@@ -57,6 +57,16 @@ class Friction(C.Structure):
     _fields_ = [(k, C.POINTER(C.c_double)) for k in ("a", "b", "Dc", "sigma_n", "V0", "f0", "eps")]
 
 
+class Request(C.Structure):
+    _fields_ = [("pool", C.c_int32), ("n_steps", C.c_int32), ("arrival_s", C.c_double), ("fric", Friction),
+                ("V_init", C.POINTER(C.c_double)), ("theta_init", C.POINTER(C.c_double)),
+                ("tau0", C.POINTER(C.c_double)), ("tau0_rate", C.POINTER(C.c_double)),
+                ("delta_init", C.POINTER(C.c_double)), ("V_out", C.POINTER(C.c_double)),
+                ("theta_out", C.POINTER(C.c_double)), ("delta_out", C.POINTER(C.c_double)),
+                ("admit_s", C.c_double), ("finish_s", C.c_double), ("status", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
 _lib = None
 
 
@@ -84,6 +94,7 @@ def lib():
             "seas_state_create": (i32, [vp, i32, C.POINTER(Friction), dp, dp, dp, dp, dp, vp, C.POINTER(vp)]),
             "seas_state_destroy": (None, [vp]),
             "seas_state_load_history": (i32, [vp, dp, i32, vp]),
+            "seas_state_reset_variant": (i32, [vp, i32, C.POINTER(Friction), dp, dp, dp, dp, dp, vp]),
             "seas_eval_prescribed": (i32, [vp, vp, vp, i32, vp, vp]),
             "seas_step": (i32, [vp, vp, i32, vp]),
             "seas_state_check": (i32, [vp, vp]),
@@ -95,6 +106,10 @@ def lib():
             "seas_state_checkpoint_bytes": (C.c_size_t, [vp]),
             "seas_state_save": (i32, [vp, vp, C.c_size_t, vp]),
             "seas_state_restore": (i32, [vp, vp, C.c_size_t, vp]),
+            "seas_server_create": (i32, [C.POINTER(vp), i32, C.POINTER(Request), C.c_size_t, i32,
+                                         C.POINTER(vp)]),
+            "seas_server_run": (i32, [vp, C.POINTER(Request), i32]),
+            "seas_server_destroy": (None, [vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -230,6 +245,18 @@ class State:
                                        C.byref(h)))
         self.h = h
 
+    def reset_variant(self, variant, fric, V, theta, tau0, tau0_rate=None, delta=None, stream=0):
+        """Start a new window in one variant slot (arrays of N) at the current step."""
+        keep = []
+        fr = Friction()
+        for k in ("a", "b", "Dc", "sigma_n", "V0", "f0", "eps"):
+            arr, p = _dptr(fric.get(k))
+            keep.append(arr)
+            setattr(fr, k, p)
+        args = [_dptr(x) for x in (V, theta, tau0, tau0_rate, delta)]
+        _check(lib().seas_state_reset_variant(self.h, int(variant), C.byref(fr), *[p for _, p in args],
+                                              _ptr(stream)))
+
     def load_history(self, V_hist, stream=0):
         arr = np.ascontiguousarray(V_hist, dtype=np.float64)
         _check(lib().seas_state_load_history(self.h, arr.ctypes.data_as(C.POINTER(C.c_double)), arr.shape[0],
@@ -278,6 +305,77 @@ class State:
     def close(self):
         if getattr(self, "h", None):
             lib().seas_state_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _request(pool, n_steps, arrival_s, window, keep, outputs=True, N=None):
+    """Fill a Request from a dict window with keys fric (dict of N arrays), V, theta,
+    tau0 (and optional tau0_rate, delta)."""
+    r = Request()
+    r.pool, r.n_steps, r.arrival_s = int(pool), int(n_steps), float(arrival_s)
+    fr = Friction()
+    for k in ("a", "b", "Dc", "sigma_n", "V0", "f0", "eps"):
+        arr, p = _dptr(window["fric"].get(k))
+        keep.append(arr)
+        setattr(fr, k, p)
+    r.fric = fr
+    for name, key in (("V_init", "V"), ("theta_init", "theta"), ("tau0", "tau0"), ("tau0_rate", "tau0_rate"),
+                      ("delta_init", "delta")):
+        arr, p = _dptr(window.get(key))
+        keep.append(arr)
+        setattr(r, name, p)
+    out = {}
+    if outputs:
+        for name, key in (("V_out", "V"), ("theta_out", "theta"), ("delta_out", "delta")):
+            a = np.zeros(N)
+            keep.append(a)
+            out[key] = a
+            setattr(r, name, a.ctypes.data_as(C.POINTER(C.c_double)))
+    return r, out
+
+
+class Server:
+    """Request loop with continuous batching (seas_server_*): one pool per operator."""
+
+    def __init__(self, ops, idle_windows, device_budget, chunk_steps=16):
+        self.ops = list(ops)
+        self._keep = []
+        idle = (Request * len(self.ops))()
+        for k, w in enumerate(idle_windows):
+            idle[k], _ = _request(k, 1, 0.0, w, self._keep, outputs=False)
+        self._idle = idle
+        arr = (C.c_void_p * len(self.ops))(*[o.h.value for o in self.ops])
+        h = C.c_void_p()
+        _check(lib().seas_server_create(arr, len(self.ops), idle, int(device_budget), int(chunk_steps),
+                                        C.byref(h)))
+        self.h = h
+
+    def run(self, requests):
+        """requests: list of dict(pool, n_steps, arrival_s, window). Returns a list of
+        dict(admit_s, finish_s, status, V, theta, delta)."""
+        keep, outs = [], []
+        arr = (Request * len(requests))()
+        for i, q in enumerate(requests):
+            arr[i], o = _request(q["pool"], q["n_steps"], q["arrival_s"], q["window"], keep,
+                                 N=self.ops[q["pool"]].N)
+            outs.append(o)
+        _check(lib().seas_server_run(self.h, arr, len(requests)))
+        res = []
+        for i, o in enumerate(outs):
+            d = dict(o)
+            d.update(admit_s=arr[i].admit_s, finish_s=arr[i].finish_s, status=arr[i].status)
+            res.append(d)
+        return res
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().seas_server_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -72,6 +72,8 @@ double host_state_rate(double V, double th, double Dc, double eps) {
 
 }  // namespace
 
+void seas::set_last_error(const std::string& msg) { g_err = msg; }
+
 struct seas_op {
   HostOp h;
   int device = 0;
@@ -111,6 +113,7 @@ struct seas_state {
   double *V, *theta, *thdot, *delta, *tau0, *tau0_rate;
   double *fa, *fb, *fDc, *fsn, *fV0, *ff0, *feps;
   double *Vstar, *Vbar, *th2, *f_hist, *f_self, *f_int;
+  int64_t* step0;  // per variant: step at which its window started
   double* ring64;
   void* ringop;
   double* tail_acc;
@@ -153,6 +156,7 @@ StepArgs<TF> make_args(seas_op* op, seas_state* st) {
   a.l0_val = op->l0_val;
   a.tau0 = st->tau0;
   a.tau0_rate = st->tau0_rate;
+  a.step0 = st->step0;
   a.fric = Friction{st->fa, st->fb, st->fDc, st->fsn, st->fV0, st->ff0, st->feps};
   a.V = st->V;
   a.theta = st->theta;
@@ -276,20 +280,25 @@ void do_prescribed(seas_op* op, seas_state* st, const double* V, int n_steps, do
   HIPCHK(hipGetLastError());
 }
 
-// One row (all variants) of the rate history's operand copy, converted on the
-// host; synchronises the stream (the conversion buffer is temporary).
-void upload_op_row(seas_op* op, void* ringop, int64_t slot, const double* row, size_t n, hipStream_t s) {
+// n values of the rate history's operand copy at element offset `off`, converted
+// on the host; synchronises the stream (the conversion buffer is temporary).
+void upload_op_seg(seas_op* op, void* ringop, size_t off, const double* row, size_t n, hipStream_t s) {
   if (op->ring_bytes == 8) return;
   if (op->ring_bytes == 4) {
     std::vector<float> v(row, row + n);
-    HIPCHK(hipMemcpyAsync((float*)ringop + slot * n, v.data(), n * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync((float*)ringop + off, v.data(), n * 4, hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
   } else {
     std::vector<uint16_t> v(n);
     for (size_t i = 0; i < n; ++i) v[i] = to_bf16((float)row[i]);
-    HIPCHK(hipMemcpyAsync((uint16_t*)ringop + slot * n, v.data(), n * 2, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync((uint16_t*)ringop + off, v.data(), n * 2, hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
   }
+}
+
+// One row (all variants) of the operand copy at ring slot `slot`.
+void upload_op_row(seas_op* op, void* ringop, int64_t slot, const double* row, size_t n, hipStream_t s) {
+  upload_op_seg(op, ringop, (size_t)slot * n, row, n, s);
 }
 
 seas_op* checked(seas_op* op) {
@@ -657,6 +666,7 @@ seas_status seas_state_create(seas_op_t* op, int32_t n_variants, const seas_fric
     st->f_hist = (double*)A(vb, true);
     st->f_self = (double*)A(vb, true);
     st->f_int = (double*)A(vb, true);
+    st->step0 = (int64_t*)A((size_t)nv * 8, true);
     st->ring64 = (double*)A((size_t)h.ring_len * vb, true);
     st->ringop = op->ring_bytes == 8 ? (void*)st->ring64 : A((size_t)h.ring_len * N * op->ring_bytes, true);
     st->tail_acc = (double*)A((size_t)h.tail_len * 8 * nv, true);
@@ -760,6 +770,64 @@ seas_status seas_state_load_history(seas_state_t* st, const double* V_hist, int3
       HIPCHK(hipStreamSynchronize(s));
     }
     st->first = -H;
+  });
+}
+
+seas_status seas_state_reset_variant(seas_state_t* st, int32_t variant, const seas_friction_t* fric,
+                                     const double* V_init, const double* theta_init, const double* tau0,
+                                     const double* tau0_rate, const double* delta_init, void* stream) {
+  return guard([&] {
+    if (!st || !fric || !V_init || !theta_init || !tau0) throw Error(SEAS_ERR_INVALID_ARG, "null argument");
+    seas_op* op = checked(st->op);
+    if (variant < 0 || variant >= st->nv) throw Error(SEAS_ERR_INVALID_ARG, "variant out of range");
+    if (st->mode == 1) throw Error(SEAS_ERR_MISMATCH, "state is in prescribed-history mode");
+    if (!fric->a || !fric->b || !fric->Dc || !fric->sigma_n || !fric->V0 || !fric->f0)
+      throw Error(SEAS_ERR_INVALID_ARG, "null friction array");
+    const HostOp& h = op->h;
+    const int nv = st->nv, v = variant;
+    const size_t N = h.N;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<double> eps(N, 1.0), thd(N), zero(N, 0.0);
+    if (fric->eps) eps.assign(fric->eps, fric->eps + N);
+    for (size_t r = 0; r < N; ++r) {
+      if (!(V_init[r] > 0) || !(theta_init[r] > 0) || !(fric->Dc[r] > 0) || !(fric->V0[r] > 0) ||
+          !(eps[r] > 0 && eps[r] <= 1.0))
+        throw Error(SEAS_ERR_INVALID_ARG, "V, theta, Dc, V0 must be > 0 and 0 < eps <= 1");
+      thd[r] = host_state_rate(V_init[r], theta_init[r], fric->Dc[r], eps[r]);
+    }
+    const size_t o = (size_t)v * N;
+    auto H2D = [&](double* d, const double* src) {
+      HIPCHK(hipMemcpyAsync(d + o, src, N * 8, hipMemcpyHostToDevice, s));
+    };
+    H2D(st->V, V_init);
+    H2D(st->theta, theta_init);
+    H2D(st->thdot, thd.data());
+    H2D(st->delta, delta_init ? delta_init : zero.data());
+    H2D(st->tau0, tau0);
+    H2D(st->tau0_rate, tau0_rate ? tau0_rate : zero.data());
+    H2D(st->fa, fric->a);
+    H2D(st->fb, fric->b);
+    H2D(st->fDc, fric->Dc);
+    H2D(st->fsn, fric->sigma_n);
+    H2D(st->fV0, fric->V0);
+    H2D(st->ff0, fric->f0);
+    H2D(st->feps, eps.data());
+    const int64_t n = st->step;
+    HIPCHK(hipMemcpyAsync(st->step0 + v, &n, 8, hipMemcpyHostToDevice, s));
+    // no history before the variant's start: clear its rows of every ring, then
+    // append V^n and the coefficients of its slip at n
+    launch_clear_variant(st->ring64, h.ring_len, nv, v, h.N, 8, s);
+    if (op->ring_bytes != 8) launch_clear_variant(st->ringop, h.ring_len, nv, v, h.N, (int)op->ring_bytes, s);
+    launch_clear_variant(st->dring, 1, nv, v, (int)(h.self_ring_len * 2), 8, s);
+    launch_clear_variant(st->tail_acc, 1, nv, v, (int)h.tail_len, 8, s);
+    const int64_t slot = ((n % h.ring_len) + h.ring_len) % h.ring_len;
+    HIPCHK(hipMemcpyAsync(st->ring64 + ((size_t)slot * nv + v) * N, V_init, N * 8, hipMemcpyHostToDevice, s));
+    upload_op_seg(op, st->ringop, ((size_t)slot * nv + v) * N, V_init, N, s);
+    launch_dft(h.n_modes, 1, h.N, h.self_ring_len, op->modes, op->sf, st->delta + o, nullptr, 0.0, op->tw, op->tab,
+               nullptr, st->F + (size_t)v * h.n_modes, st->dring + (size_t)v * h.self_ring_len, 1, n, n, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));  // the host arrays above are temporaries
+    if (st->mode == 0) st->mode = 2;
   });
 }
 

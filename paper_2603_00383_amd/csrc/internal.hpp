@@ -133,6 +133,9 @@ struct HostFactors {
   std::vector<int64_t> off, off32;
 };
 
+// message returned by seas_last_error() on the calling thread (api.hip)
+void set_last_error(const std::string& msg);
+
 // host build (build.cpp)
 void build_host(const seas_fault_t* f, int nf, const seas_params_t& prm, HostOp& op, HostFactors& hf);
 uint16_t to_bf16(float x);

@@ -838,7 +838,7 @@ __global__ void k_stage(StepArgs<TF> a, int stage) {
   const int j = r - f.off;
   const double fself = idft_wave(f, a.F + (int64_t)v * a.n_modes + f.mode_off, a.tw + f.tw, j, lane);
   if (lane != 0) return;
-  const double tau0 = a.tau0[e] + a.tau0_rate[e] * a.t_next;
+  const double tau0 = a.tau0[e] + a.tau0_rate[e] * (a.t_next - (double)a.step0[v] * a.dt);
   const Friction& fr = a.fric;
   if (stage == 0) {  // predictor: delta*, theta* from the current rates
     const double V = a.V[e];
@@ -904,8 +904,26 @@ __global__ void k_pre_out(StepArgs<TF> a, const double* __restrict__ Vprev, doub
   if (lane == 0) fout[rg] = fself + a.f_hist[rg] - a.eta * lag0_apply(a.l0_ptr, a.l0_col, a.l0_val, Vprev + o, r);
 }
 
+// Zero variant v's rows of a [rows][nv][N] array (16-bit words; zero bits are
+// 0.0 in every floating-point format used here).
+__global__ void k_clear_variant(uint16_t* __restrict__ base, int64_t rows, int64_t pitch, int64_t width,
+                                int64_t off) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows * width) return;
+  const int64_t r = i / width, c = i - r * width;
+  base[r * pitch + off + c] = 0;
+}
+
 // ------------------------------------------------------------------ launchers
 static inline int blocks_for(int64_t n, int t) { return (int)((n + t - 1) / t); }
+
+void launch_clear_variant(void* base, int64_t rows, int nv, int v, int N, int elem_bytes, hipStream_t s) {
+  const int64_t w = (int64_t)N * elem_bytes / 2;  // 16-bit words per variant row
+  const int64_t n = rows * w;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_clear_variant, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (uint16_t*)base, rows,
+                     w * nv, w, w * v);
+}
 
 template <typename TF, int S>
 static void hmat_s(int n, const void* items, const int32_t* lagT, const int32_t* lagCol, const int32_t* lagColOff,

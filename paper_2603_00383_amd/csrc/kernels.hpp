@@ -42,6 +42,7 @@ struct StepArgs {
   const int32_t *l0_ptr, *l0_col;
   const double* l0_val;
   const double *tau0, *tau0_rate;
+  const int64_t* step0;     // per variant: the step at which its window started (tau0 loading time origin)
   Friction fric;
   double *V, *theta, *thdot, *delta;
   double *Vstar, *Vbar, *th2;
@@ -68,6 +69,8 @@ void launch_reduce_far(const HostOp& h, int S, const void* partials, bool f32, c
                        const int32_t* idx, double* f, hipStream_t s);
 void launch_reduce_near(const HostOp& h, const double* partials, const int32_t* ptr, const int32_t* idx,
                         const double* base, double* f, hipStream_t s);
+// zero one variant's rows of a [rows][nv][N] array of elem_bytes-sized values (elem_bytes even)
+void launch_clear_variant(void* base, int64_t rows, int nv, int v, int N, int elem_bytes, hipStream_t s);
 // 16-bit far list, one workgroup per segment
 void launch_hmat_x16(const HostOp& h, const void* items, const int32_t* seg_ptr, const int32_t* lagT,
                      const int32_t* lagCol, const int32_t* lagColOff, const void* arena, const void* ring,

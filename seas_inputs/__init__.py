@@ -206,11 +206,11 @@ def ensemble_variants(n_variants=64, seed=0, a=0.010):
 # ----------------------------------------------------------------------------
 # Workload 5: request stream for the serving loop.
 # ----------------------------------------------------------------------------
-def serving_templates(seed=0, n_templates=8, dx=50.0):
+def serving_templates(seed=0, n_templates=8, dx=50.0, sizes=(500, 1000, 2000, 4000, 8000)):
     rng = np.random.default_rng(40_000 + seed)
     out = []
     for t in range(n_templates):
-        N = int(rng.choice([500, 1000, 2000, 4000, 8000]))
+        N = int(rng.choice(sizes))
         nf = int(rng.integers(2, 11))
         per = max(N // nf, 8)
         box = 40e3 * math.sqrt(N / 3000.0), 20e3 * math.sqrt(N / 3000.0)

@@ -13,7 +13,10 @@ few near-field terms whose rounding does not average out. Its bound is one
 value's rounding, 2e-3, with one variant (lags below the time block in FP32,
 history in FP32 until staged) and 8e-3 for ensembles, where the factors of
 every lag, the history copy and the projected panel are each rounded once
-(3 x 2^-9 = 5.9e-3, plus the cancellation margin of the sums).
+(3 x 2^-9 = 5.9e-3, plus the cancellation margin of the sums). FP16 ensembles
+round the near lags (1..15) and the static tail too, which carry the largest
+terms: measured 6.6e-4 (16 variants) and 1.0e-3 (64); bound 3 x 2^-12 = 7.3e-4
+per term with the same cancellation margin, 2e-3.
 """
 import numpy as np
 import pytest
@@ -27,7 +30,7 @@ torch = pytest.importorskip("torch")
 P = pytest.importorskip("paper_2603_00383_amd")
 
 TOL = {"bf16": 2e-3, "f16": 1e-4}
-TOL_ENS = {"bf16": 8e-3, "f16": 1e-4}
+TOL_ENS = {"bf16": 8e-3, "f16": 2e-3}
 
 
 @pytest.fixture(scope="module", autouse=True)
