@@ -434,7 +434,7 @@ __device__ __forceinline__ void x16_kloop(int k0, int k1, FA A, FB B, mfma_f4 (&
 }
 
 template <typename T16, typename TR, bool SCALE, int NT>
-__global__ __launch_bounds__(kItemThreads) void k_hmat_x16(
+__global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT == 1 ? 4 : 2))) void k_hmat_x16(
     const Item* __restrict__ items, const int32_t* __restrict__ seg_ptr, const int32_t* __restrict__ lagT,
     const int32_t* __restrict__ lagCol, const int32_t* __restrict__ lagColOff, const T16* __restrict__ arena,
     const TR* __restrict__ ring, int64_t head, int64_t R, int N, int S, int nv,
@@ -442,7 +442,7 @@ __global__ __launch_bounds__(kItemThreads) void k_hmat_x16(
   typedef typename Mx<T16>::v8 v8;
   constexpr int NC = 16 * NT;
   constexpr int RW = NT == 1 ? 8 : 4;   // row tiles per wave held across a segment
-  constexpr int PF = NT == 1 ? 8 : 4;   // inner steps loaded ahead
+  constexpr int PF = NT == 1 ? 6 : 2;   // inner steps loaded ahead
   __shared__ __attribute__((aligned(16))) T16 h[kHist16];
   __shared__ __attribute__((aligned(16))) T16 z[kZ16];
   __shared__ float smax[4];
@@ -450,13 +450,19 @@ __global__ __launch_bounds__(kItemThreads) void k_hmat_x16(
   const int x0 = seg_ptr[blockIdx.x], x1 = seg_ptr[blockIdx.x + 1];
   const int p = items[x0].p;
   const int RT = (p + 15) >> 4;
-  const bool wide = RT >= 4;
-  const int KS = wide ? 1 : 4 / RT;          // inner-range splits of a narrow block
-  const int rt_n = wide ? 0 : wave % RT;     // a narrow block's row tile of this wave
-  const int ks = wide ? 0 : wave / RT;
-  const bool active = wide || ks < KS;
-  const int my_tiles = wide ? (RT - wave + 3) / 4 : (active ? 1 : 0);
-  const bool held = my_tiles <= RW;          // else a single-item segment, written per row tile
+  // Work units: (row tile, inner-range split) pairs, KS splits per tile, unit
+  // id = tile * KS + split; wave w takes units w, w + 4, ... KS is the smallest
+  // of 1, 2, 4 that makes the unit count a multiple of 4 (all waves equally
+  // busy), as long as each wave holds at most RW units and the split sums fit
+  // the LDS reduction buffer; tall blocks keep KS = 1.
+  int KS = 1;
+  if ((RT & 3) != 0) {
+    const int k = (RT & 1) ? 4 : 2;
+    if ((RT * k + 3) / 4 <= RW && RT * k * NT <= 32) KS = k;
+  }
+  const int units = RT * KS;
+  const int my_units = (units - wave + 3) / 4;
+  const bool held = my_units <= RW;          // else a single-item segment (KS = 1), written per unit
   float* out = partials + items[x0].part;
   mfma_f4 acc[RW][NT];
 #pragma unroll
@@ -560,14 +566,13 @@ __global__ __launch_bounds__(kItemThreads) void k_hmat_x16(
       E = nl * q8;
       stride = nl * q8;
     }
-    if (!active) continue;
     // ---- expansion / dense product: Y (p x NC) += sc * M (p x E) B (E x NC)
-    const int k0 = wide ? 0 : ((int)((int64_t)(E / 8) * ks / KS)) * 8;
-    const int k1 = wide ? E : ((int)((int64_t)(E / 8) * (ks + 1) / KS)) * 8;
     const float inv_q8 = 1.0f / (float)q8;
     const int lag_stride = (nv - 1) * q8;
-    for (int u = 0; u < my_tiles; ++u) {
-      const int rt = wide ? wave + 4 * u : rt_n;
+    for (int u = 0; u < my_units; ++u) {
+      const int id = wave + 4 * u, rt = id / KS, ks = id - rt * KS;
+      const int k0 = ((int)((int64_t)(E / 8) * ks / KS)) * 8;
+      const int k1 = ((int)((int64_t)(E / 8) * (ks + 1) / KS)) * 8;
       const int i = rt * 16 + l16;
       const T16* arow = M + (int64_t)min(i, p - 1) * stride;
       mfma_f4 tmp[NT];
@@ -608,11 +613,11 @@ __global__ __launch_bounds__(kItemThreads) void k_hmat_x16(
       }
     }
   }
-  if (wide) {
-    if (!held) return;
+  if (!held) return;  // single-item segment of a tall block: written per unit above
+  if (KS == 1) {
 #pragma unroll
     for (int u = 0; u < RW; ++u) {
-      if (u >= my_tiles) break;
+      if (u >= my_units) break;
       const int rt = wave + 4 * u;
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
@@ -625,21 +630,24 @@ __global__ __launch_bounds__(kItemThreads) void k_hmat_x16(
     }
     return;
   }
-  // narrow block: add the inner-range splits in split order through LDS
-  float* red = reinterpret_cast<float*>(h);  // 4 waves x NT x 256 floats <= 32 KB
+  // inner-range splits: add the KS sums of each tile in split order through LDS
+  float* red = reinterpret_cast<float*>(h);  // units x NT x 256 floats <= 32 KB
   __syncthreads();
-  if (active) {
+#pragma unroll
+  for (int u = 0; u < RW; ++u) {
+    if (u >= my_units) break;
+    const int id = wave + 4 * u;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) red[((wave * NT) + t) * 256 + lane * 4 + v] = acc[0][t][v];
+      for (int v = 0; v < 4; ++v) red[(id * NT + t) * 256 + lane * 4 + v] = acc[u][t][v];
     }
   }
   __syncthreads();
   for (int e = tid; e < RT * NT * 256; e += kItemThreads) {
     const int rt = e / (NT * 256), rem = e - rt * NT * 256, t = rem >> 8, w = rem & 255, ln = w >> 2, v = w & 3;
     float sum = 0.0f;
-    for (int kk = 0; kk < KS; ++kk) sum += red[(((kk * RT + rt) * NT) + t) * 256 + ln * 4 + v];
+    for (int kk = 0; kk < KS; ++kk) sum += red[((rt * KS + kk) * NT + t) * 256 + ln * 4 + v];
     const int ii = rt * 16 + 4 * (ln >> 4) + v;
     if (ii < p) out[ii * NC + t * 16 + (ln & 15)] = sum;
   }
