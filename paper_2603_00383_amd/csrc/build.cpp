@@ -579,10 +579,20 @@ static void build_subblock(const HostOp& op, const BlockDesc& bd, const PairWin&
 
 static void build_block(const HostOp& op, const BlockDesc& bd, const PairWin& pw, BlockOut& out) {
   // a source cluster wider than the kernel's history buffer holds for S rows is
-  // packed as column slices, each compressed on its own
+  // packed as column slices, each compressed on its own; for ensembles, receiver
+  // clusters taller than a segment's register-held rows are packed as row
+  // slices, so that every item can share a segment (one partial set per
+  // segment instead of one per item)
   int qmax = kHistMax / op.time_block;
   if (op.x16) qmax = std::min(kHistMax, (kHist16 / op.ncols) & ~7);
-  for (int s0 = bd.s0; s0 < bd.s1; s0 += qmax) build_subblock(op, bd, pw, s0, std::min(bd.s1, s0 + qmax), out);
+  const int pmax = (op.x16 && op.n_variants > 1) ? seg_rows_max(op.ncols) : bd.r1 - bd.r0;
+  const int nrs = (bd.r1 - bd.r0 + pmax - 1) / pmax;
+  for (int k = 0; k < nrs; ++k) {
+    BlockDesc rs = bd;  // equal row slices
+    rs.r0 = bd.r0 + (int)((int64_t)(bd.r1 - bd.r0) * k / nrs);
+    rs.r1 = bd.r0 + (int)((int64_t)(bd.r1 - bd.r0) * (k + 1) / nrs);
+    for (int s0 = bd.s0; s0 < bd.s1; s0 += qmax) build_subblock(op, rs, pw, s0, std::min(bd.s1, s0 + qmax), out);
+  }
 }
 
 // ============================================================== driver

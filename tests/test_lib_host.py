@@ -143,6 +143,24 @@ def test_16bit_lag_matrices_match_dense_kernel(dtype, nv, S):
     assert seen16 > 0
 
 
+def test_ensemble_row_slices_reconstruct_the_kernel():
+    """Ensemble builds slice receiver clusters taller than a segment's rows (256
+    for 64 variants) into row slices; the lag matrices they rebuild are still the
+    kernel to BF16 rounding."""
+    faults = SI.two_fault_prescribed_faults(n_elem=320, dx=40.0)
+    op = _op(faults, compress=1, aca_tol=1e-6, eta_H=2.0, leaf=400, time_block=1, factor_dtype="bf16",
+             n_variants=64)
+    blocks = op.blocks(0, 1)
+    assert any(r1 - r0 > 256 for r0, r1, _, _, _ in blocks)  # a tall block exists
+    geo = geometry.discretize(faults)
+    dt = geometry.time_step(geo, SI.CS)
+    (t0, t1) = op.windows()[(0, 1)]
+    for T in (max(t0, 1), (t0 + t1) // 2, t1):
+        K = I.pair_kernel(geo, 0, 1, T, dt, SI.CS)
+        R = op.lag_matrix(0, 1, T, 320, 320)
+        assert np.linalg.norm(R - K) / np.linalg.norm(K) < 3 * 2.0 ** -9, T
+
+
 def test_16bit_rounding_matches_numpy():
     """The host conversions round to nearest even: FP16 against numpy's float16,
     BF16 against the top 16 bits of the FP32 pattern rounded to nearest even."""
