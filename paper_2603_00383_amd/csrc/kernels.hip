@@ -447,6 +447,7 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
   __shared__ __attribute__((aligned(16))) T16 z[kZ16];
   __shared__ float smax[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, g = lane >> 4;
+  const int nv_shift = __builtin_ctz((unsigned)nv);  // nv is a power of two
   const int x0 = seg_ptr[blockIdx.x], x1 = seg_ptr[blockIdx.x + 1];
   const int p = items[x0].p;
   const int RT = (p + 15) >> 4;
@@ -477,19 +478,34 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
     const int nrow = span * nv;
     const int64_t tnew = head + S - 1 - lagT[it.lag_off];
     __syncthreads();  // the previous item is done with h and z
-    // ---- stage the history panel (16-bit, scaled by 1/hs for FP16)
+    // ---- stage the history panel (16-bit, scaled by 1/hs for FP16). Flat over
+    // the nrow x q8 panel: value e is row rv = e / q8 (time tnew - rv / nv,
+    // variant rv % nv), source j = e % q8; each thread issues 8 loads before it
+    // uses them, so a workgroup keeps 2048 loads in flight.
+    const int tot = nrow * q8;
+    const float inv_q8s = 1.0f / (float)q8;
+    const int64_t s0 = ring_slot(tnew, R);
+    auto hval = [&](int e) -> float {
+      const int rv = (int)(((float)e + 0.5f) * inv_q8s), j = e - rv * q8;
+      if (j >= q) return 0.0f;
+      if (it.src != 0) return (float)tail_acc[(int64_t)rv * tail_len + it.tail_off + j];
+      const int r = rv >> nv_shift, v = rv - (r << nv_shift);
+      int64_t sl = s0 - r;
+      if (sl < 0) sl += R;  // r < R
+      return (float)ring[(sl * nv + v) * (int64_t)N + it.col0 + j];
+    };
     float hs = 1.0f;
     if (SCALE) {
       float m = 0.0f;
-      for (int rv = wave; rv < nrow; rv += 4) {
-        if (it.src == 0) {
-          const int r = rv / nv, v = rv - r * nv;
-          const TR* src = ring + (ring_slot(tnew - r, R) * nv + v) * (int64_t)N + it.col0;
-          for (int j = lane; j < q; j += 64) m = fmaxf(m, fabsf((float)src[j]));
-        } else {
-          const double* src = tail_acc + (int64_t)rv * tail_len + it.tail_off;
-          for (int j = lane; j < q; j += 64) m = fmaxf(m, fabsf((float)src[j]));
+      for (int e0 = tid; e0 < tot; e0 += 8 * kItemThreads) {
+        float x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int e = e0 + u * kItemThreads;
+          x[u] = e < tot ? hval(e) : 0.0f;
         }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) m = fmaxf(m, fabsf(x[u]));
       }
       m = wave_max(m);
       if (lane == 0) smax[wave] = m;
@@ -497,15 +513,17 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
       hs = pow2_at_least(fmaxf(fmaxf(smax[0], smax[1]), fmaxf(smax[2], smax[3])));
     }
     const float hsi = 1.0f / hs;
-    for (int rv = wave; rv < nrow; rv += 4) {
-      T16* dst = h + rv * q8;
-      if (it.src == 0) {
-        const int r = rv / nv, v = rv - r * nv;
-        const TR* src = ring + (ring_slot(tnew - r, R) * nv + v) * (int64_t)N + it.col0;
-        for (int j = lane; j < q8; j += 64) dst[j] = j < q ? Mx<T16>::cvt((float)src[j] * hsi) : Mx<T16>::cvt(0.0f);
-      } else {  // static tail (ensembles): the expired-slip accumulators of variant rv
-        const double* src = tail_acc + (int64_t)rv * tail_len + it.tail_off;
-        for (int j = lane; j < q8; j += 64) dst[j] = Mx<T16>::cvt(j < q ? (float)src[j] * hsi : 0.0f);
+    for (int e0 = tid; e0 < tot; e0 += 8 * kItemThreads) {
+      float x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * kItemThreads;
+        x[u] = e < tot ? hval(e) : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * kItemThreads;
+        if (e < tot) h[e] = Mx<T16>::cvt(x[u] * hsi);
       }
     }
     // column offsets of this lane's N-tiles
