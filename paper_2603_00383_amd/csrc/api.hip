@@ -170,6 +170,7 @@ StepArgs<TF> make_args(seas_op* op, seas_state* st) {
   a.fail = st->fail;
   a.ring64 = st->ring64;
   a.ringop = (TF*)st->ringop;
+  a.op_vfast = op->ring_bytes == 2;
   a.R = h.ring_len;
   a.tail_acc = st->tail_acc;
   a.src_pairs = op->src_pairs;
@@ -296,9 +297,29 @@ void upload_op_seg(seas_op* op, void* ringop, size_t off, const double* row, siz
   }
 }
 
-// One row (all variants) of the operand copy at ring slot `slot`.
+// One row (all variants, host layout [nv][N]) of the operand copy at ring slot
+// `slot`; the BF16 ensemble copy is laid out [R][N][nv] (variant fastest).
 void upload_op_row(seas_op* op, void* ringop, int64_t slot, const double* row, size_t n, hipStream_t s) {
-  upload_op_seg(op, ringop, (size_t)slot * n, row, n, s);
+  if (op->ring_bytes != 2) {
+    upload_op_seg(op, ringop, (size_t)slot * n, row, n, s);
+    return;
+  }
+  const size_t N = op->h.N, nv = n / N;
+  std::vector<uint16_t> v(n);
+  for (size_t k = 0; k < nv; ++k)
+    for (size_t r = 0; r < N; ++r) v[r * nv + k] = to_bf16((float)row[k * N + r]);
+  HIPCHK(hipMemcpyAsync((uint16_t*)ringop + (size_t)slot * n, v.data(), n * 2, hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+// Variant v's N values of one ring slot of the BF16 ensemble copy ([R][N][nv]).
+void upload_op_variant(seas_op* op, void* ringop, int64_t slot, int nv, int v, const double* x, hipStream_t s) {
+  const size_t N = op->h.N;
+  std::vector<uint16_t> b(N);
+  for (size_t r = 0; r < N; ++r) b[r] = to_bf16((float)x[r]);
+  HIPCHK(hipMemcpy2DAsync((uint16_t*)ringop + ((size_t)slot * N) * nv + v, (size_t)nv * 2, b.data(), 2, 2, N,
+                          hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
 }
 
 seas_op* checked(seas_op* op) {
@@ -817,12 +838,16 @@ seas_status seas_state_reset_variant(seas_state_t* st, int32_t variant, const se
     // no history before the variant's start: clear its rows of every ring, then
     // append V^n and the coefficients of its slip at n
     launch_clear_variant(st->ring64, h.ring_len, nv, v, h.N, 8, s);
-    if (op->ring_bytes != 8) launch_clear_variant(st->ringop, h.ring_len, nv, v, h.N, (int)op->ring_bytes, s);
+    if (op->ring_bytes == 2)  // [R][N][nv]
+      launch_clear_variant(st->ringop, (int64_t)h.ring_len * h.N, nv, v, 1, 2, s);
+    else if (op->ring_bytes != 8)
+      launch_clear_variant(st->ringop, h.ring_len, nv, v, h.N, (int)op->ring_bytes, s);
     launch_clear_variant(st->dring, 1, nv, v, (int)(h.self_ring_len * 2), 8, s);
     launch_clear_variant(st->tail_acc, 1, nv, v, (int)h.tail_len, 8, s);
     const int64_t slot = ((n % h.ring_len) + h.ring_len) % h.ring_len;
     HIPCHK(hipMemcpyAsync(st->ring64 + ((size_t)slot * nv + v) * N, V_init, N * 8, hipMemcpyHostToDevice, s));
-    upload_op_seg(op, st->ringop, ((size_t)slot * nv + v) * N, V_init, N, s);
+    if (op->ring_bytes == 2) upload_op_variant(op, st->ringop, slot, nv, v, V_init, s);
+    else upload_op_seg(op, st->ringop, ((size_t)slot * nv + v) * N, V_init, N, s);
     launch_dft(h.n_modes, 1, h.N, h.self_ring_len, op->modes, op->sf, st->delta + o, nullptr, 0.0, op->tw, op->tab,
                nullptr, st->F + (size_t)v * h.n_modes, st->dring + (size_t)v * h.self_ring_len, 1, n, n, s);
     HIPCHK(hipGetLastError());

@@ -433,7 +433,7 @@ __device__ __forceinline__ void x16_kloop(int k0, int k1, FA A, FB B, mfma_f4 (&
   }
 }
 
-template <typename T16, typename TR, bool SCALE, int NT>
+template <typename T16, typename TR, bool SCALE, int NT, bool VFAST>
 __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT == 1 ? 4 : 2))) void k_hmat_x16(
     const Item* __restrict__ items, const int32_t* __restrict__ seg_ptr, const int32_t* __restrict__ lagT,
     const int32_t* __restrict__ lagCol, const int32_t* __restrict__ lagColOff, const T16* __restrict__ arena,
@@ -495,6 +495,40 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
       return (float)ring[(sl * nv + v) * (int64_t)N + it.col0 + j];
     };
     float hs = 1.0f;
+    if (VFAST && it.src == 0) {
+      // 16-bit history copy laid out [R][N][nv]: one aligned 16-byte load brings
+      // 8 variants of one (row, source); units u = ((r q8) + j) (nv/8) + vg
+      const int ng = nv >> 3, nu = span * q8 * ng;
+      typedef uint16_t u8v __attribute__((ext_vector_type(8)));
+      for (int u0 = tid; u0 < nu; u0 += 8 * kItemThreads) {
+        u8v x[8];
+#pragma unroll
+        for (int w = 0; w < 8; ++w) {
+          const int u = u0 + w * kItemThreads;
+          x[w] = u8v{};
+          if (u < nu) {
+            const int rj = u >> (nv_shift - 3), vg = u - (rj << (nv_shift - 3));
+            const int r = (int)(((float)rj + 0.5f) * inv_q8s), j = rj - r * q8;
+            if (j < q) {
+              int64_t sl = s0 - r;
+              if (sl < 0) sl += R;
+              x[w] = *(const u8v*)((const uint16_t*)ring + ((sl * N + it.col0 + j) * nv + vg * 8));
+            }
+          }
+        }
+#pragma unroll
+        for (int w = 0; w < 8; ++w) {
+          const int u = u0 + w * kItemThreads;
+          if (u < nu) {
+            const int rj = u >> (nv_shift - 3), vg = u - (rj << (nv_shift - 3));
+            const int r = (int)(((float)rj + 0.5f) * inv_q8s), j = rj - r * q8;
+            uint16_t* d = (uint16_t*)h + ((r * nv + vg * 8) * q8 + j);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) d[k * q8] = x[w][k];
+          }
+        }
+      }
+    } else {
     if (SCALE) {
       float m = 0.0f;
       for (int e0 = tid; e0 < tot; e0 += 8 * kItemThreads) {
@@ -525,6 +559,7 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
         const int e = e0 + u * kItemThreads;
         if (e < tot) h[e] = Mx<T16>::cvt(x[u] * hsi);
       }
+    }
     }
     // column offsets of this lane's N-tiles
     int hoff[NT];
@@ -890,9 +925,10 @@ __global__ void k_stage(StepArgs<TF> a, int stage) {
     a.V[e] = V2;
     a.f_self_out[e] = fself;
     a.f_int_out[e] = fint;
-    const int64_t ri = (ring_slot(a.time_new, a.R) * a.nv + v) * a.N + r;
+    const int64_t sl = ring_slot(a.time_new, a.R), ri = (sl * a.nv + v) * a.N + r;
     a.ring64[ri] = V2;
-    if ((void*)a.ringop != (void*)a.ring64) a.ringop[ri] = to_op<TF>(V2);
+    if ((void*)a.ringop != (void*)a.ring64)
+      a.ringop[a.op_vfast ? (sl * a.N + r) * a.nv + v : ri] = to_op<TF>(V2);
     if (a.tail) tail_update(a, v, r, k, j);
   }
 }
@@ -905,9 +941,9 @@ __global__ void k_pre_push(StepArgs<TF> a, const double* __restrict__ Vin) {
   if (rg >= a.N * a.nv) return;
   const int v = rg / a.N, r = rg - v * a.N;
   const double x = Vin[rg];
-  const int64_t ri = (ring_slot(a.time_new, a.R) * a.nv + v) * a.N + r;
+  const int64_t sl = ring_slot(a.time_new, a.R), ri = (sl * a.nv + v) * a.N + r;
   a.ring64[ri] = x;
-  if ((void*)a.ringop != (void*)a.ring64) a.ringop[ri] = to_op<TF>(x);
+  if ((void*)a.ringop != (void*)a.ring64) a.ringop[a.op_vfast ? (sl * a.N + r) * a.nv + v : ri] = to_op<TF>(x);
   a.delta[rg] += a.dt * x;
   if (a.tail) {
     const int k = a.fault_of[r];
@@ -995,12 +1031,12 @@ bool far_partials_f32(const HostOp& h, int S) {
   return h.x16 || (h.prm.factor_dtype == SEAS_F32 && S == 16 && h.use_mfma);
 }
 
-template <typename T16, typename TR, bool SCALE, int NT>
+template <typename T16, typename TR, bool SCALE, int NT, bool VFAST = false>
 static void x16_launch(const HostOp& h, const void* items, const int32_t* seg_ptr, const int32_t* lagT,
                        const int32_t* lagCol, const int32_t* lagColOff, const void* arena, const void* ring,
                        int64_t head, const double* tail_acc, float* partials, hipStream_t s) {
   const int nseg = (int)h.seg_ptr.size() - 1;
-  hipLaunchKernelGGL((k_hmat_x16<T16, TR, SCALE, NT>), dim3(nseg), dim3(kItemThreads), 0, s, (const Item*)items,
+  hipLaunchKernelGGL((k_hmat_x16<T16, TR, SCALE, NT, VFAST>), dim3(nseg), dim3(kItemThreads), 0, s, (const Item*)items,
                      seg_ptr, lagT, lagCol, lagColOff, (const T16*)arena, (const TR*)ring, head, (int64_t)h.ring_len,
                      h.N, h.time_block, h.n_variants, tail_acc, (int64_t)h.tail_len, partials);
 }
@@ -1017,7 +1053,7 @@ void launch_hmat_x16(const HostOp& h, const void* items, const int32_t* seg_ptr,
   }
   // ensembles: BF16 with a BF16 rate history, or FP16 with an FP32 one scaled per item
 #define SEAS_X16_ENS(NT)                                                                                      \
-  if (bf) x16_launch<__bf16, __bf16, false, NT>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head,   \
+  if (bf) x16_launch<__bf16, __bf16, false, NT, true>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head, \
                                                 tail_acc, partials, s);                                        \
   else x16_launch<_Float16, float, true, NT>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head,     \
                                              tail_acc, partials, s);

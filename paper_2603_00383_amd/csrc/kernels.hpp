@@ -51,6 +51,7 @@ struct StepArgs {
   // history append (corrector)
   double* ring64;
   TF* ringop;               // operand copy (== ring64 for FP64 factors)
+  int op_vfast;             // operand copy laid out [R][N][nv] (variant fastest; BF16 ensembles)
   int64_t R, time_new;      // ring length, time of the appended row
   // expired-slip accumulators
   double* tail_acc;
