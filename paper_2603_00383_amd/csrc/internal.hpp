@@ -57,7 +57,12 @@ constexpr int kZMax = 2048;      // low-rank columns times steps per item
 constexpr int kMaxTimeBlock = 16;
 // 16-bit factors (the matrix-core path): rows padded to 8 values (16 B)
 constexpr int kHist16 = 16384;   // 16-bit history values staged per item: span * variants * q8
+// products of 32 or more columns run two workgroups per CU (registers), so they
+// stage twice the history per item
+inline int hist16_limit(int ncols) { return ncols >= 32 ? 2 * kHist16 : kHist16; }
 constexpr int kZ16 = 4096;       // 16-bit projected values per low-rank item: ncol8 * columns
+// (the last 8 values of the kernel's buffer hold the staging maximum)
+inline int z16_limit(int ncols) { return (ncols >= 32 ? 2 * kZ16 : kZ16) - 8; }
 constexpr int kMaxVariants = 64;
 constexpr int64_t kSegElems = 1 << 19;  // factor values per segment (one workgroup)
 inline int round8(int x) { return (x + 7) & ~7; }

@@ -434,7 +434,7 @@ __device__ __forceinline__ void x16_kloop(int k0, int k1, FA A, FB B, mfma_f4 (&
 }
 
 template <typename T16, typename TR, bool SCALE, int NT, bool VFAST>
-__global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT == 1 && !VFAST ? 4 : 2))) void k_hmat_x16(
+__global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT == 1 && !VFAST ? (SCALE ? 3 : 4) : 2))) void k_hmat_x16(
     const Item* __restrict__ items, const int32_t* __restrict__ seg_ptr, const int32_t* __restrict__ lagT,
     const int32_t* __restrict__ lagCol, const int32_t* __restrict__ lagColOff, const T16* __restrict__ arena,
     const TR* __restrict__ ring, int64_t head, int64_t R, int N, int S, int nv,
@@ -443,9 +443,12 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
   constexpr int NC = 16 * NT;
   constexpr int RW = NT == 1 ? 8 : 4;   // row tiles per wave held across a segment
   constexpr int PF = NT == 1 ? 6 : 2;   // inner steps loaded ahead
-  __shared__ __attribute__((aligned(16))) T16 h[kHist16];
-  __shared__ __attribute__((aligned(16))) T16 z[kZ16];
-  __shared__ float smax[4];
+  constexpr int HL = NT >= 2 ? 2 * kHist16 : kHist16;  // staged history values (hist16_limit)
+  __shared__ __attribute__((aligned(16))) T16 h[HL];
+  constexpr int ZL = NT >= 2 ? 2 * kZ16 : kZ16;  // projected values (z16_limit + 8)
+  __shared__ __attribute__((aligned(16))) T16 z[ZL];
+  // the staging maximum lives in z's last 16 bytes, which projected panels never use
+  float* smax = reinterpret_cast<float*>(z + ZL - 8);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, g = lane >> 4;
   const int nv_shift = __builtin_ctz((unsigned)nv);  // nv is a power of two
   const int x0 = seg_ptr[blockIdx.x], x1 = seg_ptr[blockIdx.x + 1];
@@ -470,48 +473,6 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
   for (int u = 0; u < RW; ++u)
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[u][t] = mfma_f4{0.0f, 0.0f, 0.0f, 0.0f};
-
-  // BF16 ensembles: an item's history panel is at most 8 aligned 16-byte loads
-  // per thread ([R][N][nv] copy, units u = ((r q8) + j) (nv/8) + vg). The panel
-  // of the next item is loaded into registers before the current item's
-  // products run and written to LDS after them, so its latency overlaps them.
-  typedef uint16_t u8v __attribute__((ext_vector_type(8)));
-  u8v pre[8];
-  auto vf_load = [&](const Item& itn) {
-    const int qn = itn.q, q8n = (qn + 7) & ~7, nu = (itn.nlag + S - 1) * q8n * (nv >> 3);
-    const float iq = 1.0f / (float)q8n;
-    const int64_t sn = ring_slot(head + S - 1 - lagT[itn.lag_off], R);
-#pragma unroll
-    for (int w = 0; w < 8; ++w) {
-      const int u = tid + w * kItemThreads;
-      pre[w] = u8v{};
-      if (u < nu) {
-        const int rj = u >> (nv_shift - 3), vg = u - (rj << (nv_shift - 3));
-        const int r = (int)(((float)rj + 0.5f) * iq), j = rj - r * q8n;
-        if (j < qn) {
-          int64_t sl = sn - r;
-          if (sl < 0) sl += R;
-          pre[w] = *(const u8v*)((const uint16_t*)ring + ((sl * N + itn.col0 + j) * nv + vg * 8));
-        }
-      }
-    }
-  };
-  auto vf_store = [&](const Item& itn) {
-    const int q8n = (itn.q + 7) & ~7, nu = (itn.nlag + S - 1) * q8n * (nv >> 3);
-    const float iq = 1.0f / (float)q8n;
-#pragma unroll
-    for (int w = 0; w < 8; ++w) {
-      const int u = tid + w * kItemThreads;
-      if (u < nu) {
-        const int rj = u >> (nv_shift - 3), vg = u - (rj << (nv_shift - 3));
-        const int r = (int)(((float)rj + 0.5f) * iq), j = rj - r * q8n;
-        uint16_t* d = (uint16_t*)h + ((r * nv + vg * 8) * q8n + j);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) d[k * q8n] = pre[w][k];
-      }
-    }
-  };
-  if (VFAST && items[x0].src == 0) vf_load(items[x0]);
 
   for (int x = x0; x < x1; ++x) {
     const Item it = items[x];
@@ -538,7 +499,61 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
     };
     float hs = 1.0f;
     if (VFAST && it.src == 0) {
-      vf_store(it);  // loaded before the previous item's products (or before the loop)
+      // 16-bit history copy laid out [R][N][nv]: one aligned 16-byte load brings
+      // 8 variants of one (row, source); units u = ((r q8) + j) (nv/8) + vg,
+      // 8 loads in flight per thread
+      typedef uint16_t u8v __attribute__((ext_vector_type(8)));
+      const int ng = nv >> 3, nu = span * q8 * ng;
+      for (int u0 = tid; u0 < nu; u0 += 8 * kItemThreads) {
+        u8v xv[8];
+#pragma unroll
+        for (int w = 0; w < 8; ++w) {
+          const int u = u0 + w * kItemThreads;
+          xv[w] = u8v{};
+          if (u < nu) {
+            const int rj = u >> (nv_shift - 3), vg = u - (rj << (nv_shift - 3));
+            const int r = (int)(((float)rj + 0.5f) * inv_q8s), j = rj - r * q8;
+            if (j < q) {
+              int64_t sl = s0 - r;
+              if (sl < 0) sl += R;
+              xv[w] = *(const u8v*)((const uint16_t*)ring + ((sl * N + it.col0 + j) * nv + vg * 8));
+            }
+          }
+        }
+#pragma unroll
+        for (int w = 0; w < 8; ++w) {
+          const int u = u0 + w * kItemThreads;
+          if (u < nu) {
+            const int rj = u >> (nv_shift - 3), vg = u - (rj << (nv_shift - 3));
+            const int r = (int)(((float)rj + 0.5f) * inv_q8s), j = rj - r * q8;
+            uint16_t* d = (uint16_t*)h + ((r * nv + vg * 8) * q8 + j);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) d[k * q8] = xv[w][k];
+          }
+        }
+      }
+    } else if (SCALE && tot <= 16 * kItemThreads) {
+      // FP16, panels of up to 16 values per thread: one pass, values kept in
+      // registers while the panel's maximum is formed
+      float xs[16];
+      float m = 0.0f;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = tid + u * kItemThreads;
+        xs[u] = e < tot ? hval(e) : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) m = fmaxf(m, fabsf(xs[u]));
+      m = wave_max(m);
+      if (lane == 0) smax[wave] = m;
+      __syncthreads();
+      hs = pow2_at_least(fmaxf(fmaxf(smax[0], smax[1]), fmaxf(smax[2], smax[3])));
+      const float hsi = 1.0f / hs;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = tid + u * kItemThreads;
+        if (e < tot) h[e] = Mx<T16>::cvt(xs[u] * hsi);
+      }
     } else {
     if (SCALE) {
       float m = 0.0f;
@@ -580,7 +595,6 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
       hoff[t] = ((S - 1 - k) * nv + v) * q8;
     }
     __syncthreads();
-    if (VFAST && x + 1 < x1 && items[x + 1].src == 0) vf_load(items[x + 1]);
     const T16* base = arena + it.data;
     float sc = it.scale * hs;
     int E, stride;
@@ -696,7 +710,7 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
     return;
   }
   // inner-range splits: add the KS sums of each tile in split order through LDS
-  float* red = reinterpret_cast<float*>(h);  // units x NT x 256 floats <= 32 KB
+  float* red = reinterpret_cast<float*>(h);  // units x NT x 256 floats <= 32 KB <= sizeof h
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < RW; ++u) {
