@@ -254,6 +254,7 @@ def main():
     ap.add_argument("--time-block", type=int, default=16,
                     help="S: lags >= S applied once per S steps (1 = plain per-step form)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form measurement")
+    ap.add_argument("--no-forms", action="store_true", help="skip the 16-bit forms (FP32 runs only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 2 GiB buffer three times (calibrates HBM byte counters)")
@@ -289,32 +290,45 @@ def main():
     if args.dtype is None:
         args.dtype = "f32"
     faults = SI.five_fault_network(seed=args.seed)
-    params = SI.default_params(factor_dtype=args.dtype, aca_tol=args.aca, eta_H=2.0, leaf=50,
-                               time_block=args.time_block)
     os.environ.setdefault("SEAS_VERBOSE", "1")
-    print("[bench] building the operator", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    op = P.Operator(faults, params)
-    build_s = time.perf_counter() - t0
-    info = op.info
-    N = op.N
-    print(f"[bench] operator built in {build_s:.1f} s: N={N} items={info['n_items']} "
-          f"stored/dense={info['stored_entries'] / info['dense_entries']:.3f} max_lag={info['max_lag']}",
-          file=sys.stderr, flush=True)
     fric = SI.rate_state_fields(faults)
     # a mild overstress keeps the explicit aging-law update away from its stiff limit
     ini = SI.near_nucleation_state(faults, fric, seed=args.seed, bump_amp=0.05)
-    prior = SI.saturated_history(faults, info["max_lag"] + 2, args.seed)
     stream = torch.cuda.current_stream()
     s = stream.cuda_stream
-    st = P.State(op, fric, ini["V"], ini["theta"], ini["tau0"], ini["tau0_rate"], stream=s)
-    st.load_history(prior, stream=s)
-    print(f"[bench] history loaded ({len(prior)} steps), warmup {args.warmup}", file=sys.stderr, flush=True)
-    st.step(args.warmup, stream=s)
-    st.check(stream=s)
-    elem_bytes = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}[args.dtype]
+    prior_cache = {}
 
-    def timed(S):
+    def prepare(dtype):
+        """Operator of one factor dtype and a state with full history windows,
+        after the warmup steps."""
+        params = SI.default_params(factor_dtype=dtype, aca_tol=args.aca, eta_H=2.0, leaf=50,
+                                   time_block=args.time_block)
+        print(f"[bench] building the {dtype} operator", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        op = P.Operator(faults, params)
+        bs = time.perf_counter() - t0
+        inf = op.info
+        print(f"[bench] operator built in {bs:.1f} s: N={op.N} items={inf['n_items']} "
+              f"stored/dense={inf['stored_entries'] / inf['dense_entries']:.3f} max_lag={inf['max_lag']}",
+              file=sys.stderr, flush=True)
+        if inf["max_lag"] not in prior_cache:
+            prior_cache[inf["max_lag"]] = SI.saturated_history(faults, inf["max_lag"] + 2, args.seed)
+        prior = prior_cache[inf["max_lag"]]
+        st = P.State(op, fric, ini["V"], ini["theta"], ini["tau0"], ini["tau0_rate"], stream=s)
+        st.load_history(prior, stream=s)
+        print(f"[bench] history loaded ({len(prior)} steps), warmup {args.warmup}", file=sys.stderr, flush=True)
+        st.step(args.warmup, stream=s)
+        st.check(stream=s)
+        return op, inf, st, bs
+
+    def alg_bytes(inf, eb):
+        """Stored far-factor bytes one far launch reads: 16-bit forms keep the
+        near-field blocks in FP32 (far_entries_f32)."""
+        if eb == 2:
+            return (inf["far_entries"] - inf["far_entries_f32"]) * 2 + inf["far_entries_f32"] * 4
+        return inf["far_entries"] * eb
+
+    def timed_on(st, inf, eb, S):
         st.set_time_block(S)
         st.set_timing(True)
         st.step(2, stream=s)          # enter the form's cadence
@@ -330,14 +344,21 @@ def main():
         ms, n = st.read_timing(stream=s)
         st.check(stream=s)
         avg = ms / max(n, 1)
-        gbs = info["far_entries"] * elem_bytes / (avg * 1e-3) / 1e9
+        gbs = alg_bytes(inf, eb) / (avg * 1e-3) / 1e9
         return dict(wall=wall, ev_ms=e0.elapsed_time(e1), avg_ms=avg, launches=n, gbs=gbs)
+
+    op, info, st, build_s = prepare(args.dtype)
+    N = op.N
+    elem_bytes = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}[args.dtype]
+
+    def timed(S):
+        return timed_on(st, info, elem_bytes, S)
 
     S = info["time_block"]
     main_run = timed(S)
     plain = None if (args.no_plain or S == 1) else timed(1)
     wall, avg_ms, achieved = main_run["wall"], main_run["avg_ms"], main_run["gbs"]
-    hmat_bytes = info["far_entries"] * elem_bytes
+    hmat_bytes = alg_bytes(info, elem_bytes)
     if args.dtype in ("bf16", "f16"):
         kname = f"k_hmat_x16<{'bf16' if args.dtype == 'bf16' else 'f16'},16 columns>"
     elif args.dtype == "f32" and S == 16 and not os.environ.get("SEAS_NO_MFMA"):
@@ -358,7 +379,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.dtype, "data": "synthetic",
         "config": {"workload": "five-fault SEAS step loop, 5 x 600 elements (N=3000, dx=50 m), "
-                               f"{args.dtype.upper()} factors" + (" (lags < 16 in FP32)" if elem_bytes == 2 else "")
+                               f"{args.dtype.upper()} factors" + (" (near-field blocks and lags < 16 in FP32)" if elem_bytes == 2 else "")
                                + f", FP64 state, ACA {args.aca:g}, eta_H 2, leaf 50, saturated history windows",
                    "seed": args.seed, "N": N, "max_lag": info["max_lag"], "time_block": S},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -376,9 +397,28 @@ def main():
                         "frac": plain["gbs"] / HBM_PEAK_GBS,
                         "note": "same operator and state, lags >= S applied every step"}
     print(f"[bench] timed {args.steps} steps: {wall:.3f} s", file=sys.stderr, flush=True)
+    if args.dtype == "f32" and not args.no_forms and S == 16:
+        # the 16-bit forms of the same workload (same geometry, state and history)
+        st.close()
+        op.close()
+        out["forms"] = {}
+        for d, err in (("f16", "8.2e-5 (sampled receivers vs the oracle, this workload)"),
+                       ("bf16", "5.9e-4 (sampled receivers vs the oracle, this workload)")):
+            op_d, inf_d, st_d, bs_d = prepare(d)
+            r = timed_on(st_d, inf_d, 2, 16)
+            out["forms"][d] = {"value": N * args.steps / r["wall"], "ms_per_step": r["wall"] / args.steps * 1e3,
+                               "kernel": f"k_hmat_x16<{d},16 columns>", "kernel_avg_ms": r["avg_ms"],
+                               "achieved_GBs": r["gbs"], "frac": r["gbs"] / HBM_PEAK_GBS,
+                               "algorithmic_bytes": alg_bytes(inf_d, 2), "rel_err": err,
+                               "note": "admissible blocks' lags >= 16 in 16 bits; near-field blocks, lags "
+                                       "1..15 and the static tail in FP32"}
+            print(f"[bench] form {d}: {out['forms'][d]['value']:.3e} element-steps/s", file=sys.stderr, flush=True)
+            st_d.close()
+            op_d.close()
     if not args.no_cpu_baseline:
         print("[bench] oracle CPU baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(faults, params, prior)
+        params = SI.default_params(factor_dtype="f64", aca_tol=args.aca, eta_H=2.0, leaf=50)
+        out["cpu_baseline"] = cpu_baseline(faults, params, prior_cache[info["max_lag"]])
     print(json.dumps(out), flush=True)
 
 

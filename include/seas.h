@@ -56,7 +56,8 @@ typedef int32_t seas_status;
  * operand and accumulation in FP64. F32: factors and history operand in FP32,
  * FP32 accumulation within a work item, FP64 across items. BF16 / F16: the lags
  * applied once per time block (and, for ensembles, every lag and the static
- * tail) are stored in 16 bits with one power-of-two FP32 scale per work item,
+ * tail) of admissible blocks (with one variant) or of every block (ensembles)
+ * are stored in 16 bits with one power-of-two FP32 scale per work item,
  * multiplied on the matrix cores against a 16-bit copy of the history with FP32
  * accumulation; F16 also scales each staged history panel and projected panel
  * by a power of two so that their values stay in range. With one variant the
@@ -147,6 +148,8 @@ typedef struct {
   int32_t ncols;              /* columns of the far-list products: time_block x n_variants */
   int64_t n_segments;         /* BF16 / F16: workgroups of the far list (items with the same rows) */
   int64_t far_bytes;          /* bytes of the stored far-list factors (with the 16-bit row padding) */
+  int64_t far_entries_f32;    /* BF16 / F16 with one variant: far entries of near-field (not
+                                 admissible) blocks, kept in FP32 (included in far_entries) */
 } seas_op_info_t;
 
 seas_status seas_operator_info(const seas_op_t* op, seas_op_info_t* out);

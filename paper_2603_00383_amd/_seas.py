@@ -50,7 +50,7 @@ class OpInfo(C.Structure):
                 ("flops_per_step", C.c_double), ("build_seconds", C.c_double),
                 ("factor_dtype", C.c_int32), ("time_block", C.c_int32), ("far_entries", C.c_int64),
                 ("n_items_near", C.c_int64), ("n_variants", C.c_int32), ("ncols", C.c_int32),
-                ("n_segments", C.c_int64), ("far_bytes", C.c_int64)]
+                ("n_segments", C.c_int64), ("far_bytes", C.c_int64), ("far_entries_f32", C.c_int64)]
 
 
 class Friction(C.Structure):

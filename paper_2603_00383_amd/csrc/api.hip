@@ -81,8 +81,8 @@ struct seas_op {
   void* arena = nullptr;
   float* arena_near = nullptr;  // 16-bit operators: FP32 near-list factors
   int32_t* seg_ptr = nullptr;   // 16-bit operators: far-list segments
-  Item* items[2] = {nullptr, nullptr};
-  int32_t *lagT = nullptr, *lagCol = nullptr, *lagColOff[2] = {nullptr, nullptr};
+  Item* items[3] = {nullptr, nullptr, nullptr};
+  int32_t *lagT = nullptr, *lagCol = nullptr, *lagColOff[3] = {nullptr, nullptr, nullptr};
   int32_t *red_ptr[2] = {nullptr, nullptr}, *red_idx[2] = {nullptr, nullptr};
   int32_t *l0_ptr = nullptr, *l0_col = nullptr;
   double* l0_val = nullptr;
@@ -212,10 +212,12 @@ void eval_history(seas_op* op, seas_state* st, int64_t head, hipStream_t s) {
     // plain form on a time-blocked build: window 0 of the far list at this head
     const int Sl = (plain && !h.x16) ? 1 : S;
     record_start(st, s);
-    if (h.x16)
+    if (h.x16) {
       launch_hmat_x16(h, op->items[0], op->seg_ptr, op->lagT, op->lagCol, op->lagColOff[0], op->arena, st->ringop,
                       head, st->tail_acc, (float*)st->partials_far, s);
-    else
+      launch_hmat_f32far(h, (int)h.items[2].size(), op->items[2], op->lagT, op->lagCol, op->lagColOff[2],
+                         op->arena_near, st->ringop, head, (float*)st->partials_far, s);
+    } else
       launch_hmat(h, Sl, nfar, op->items[0], op->lagT, op->lagCol, op->lagColOff[0], op->arena, st->ringop, head,
                   st->tail_acc, (double*)st->partials_far, S, s);
     record_stop(st, s);
@@ -383,9 +385,11 @@ seas_status seas_build_operator(const seas_fault_t* faults, int32_t n_faults, co
       std::vector<uint16_t>().swap(hf.f16[bi]);
     }
     if (h.x16) op->seg_ptr = upload(op->owned, h.seg_ptr);
-    for (int L = 0; L < 2; ++L) {
+    for (int L = 0; L < 3; ++L) {
       op->items[L] = upload(op->owned, h.items[L]);
       op->lagColOff[L] = upload(op->owned, h.lagColOff[L]);
+    }
+    for (int L = 0; L < 2; ++L) {
       op->red_ptr[L] = upload(op->owned, h.red_ptr[L]);
       op->red_idx[L] = upload(op->owned, h.red_idx[L]);
     }
@@ -487,7 +491,7 @@ seas_status seas_operator_lag_matrix(const seas_op_t* op, int32_t a, int32_t b, 
         return h.prm.factor_dtype == SEAS_BF16 ? (double)from_bf16(hf.f16[lo][k]) : (double)from_f16(hf.f16[lo][k]);
       return which == 1 ? (double)hf.f32[lo][k] : hf.f64[lo][k];
     };
-    for (int L = 0; L < 2; ++L)
+    for (int L = 0; L < 3; ++L)
     for (size_t ii = 0; ii < h.items[L].size(); ++ii) {
       const Item& it = h.items[L][ii];
       if (it.row0 < A.off || it.row0 >= A.off + p_all || it.col0 < B.off || it.col0 >= B.off + q_all) continue;
@@ -495,7 +499,7 @@ seas_status seas_operator_lag_matrix(const seas_op_t* op, int32_t a, int32_t b, 
       const int32_t* cp = &h.lagCol[h.lagColOff[L][ii]];
       const bool x16 = h.x16 && L == 0;
       const int which = x16 ? 2 : ((h.x16 || h.prm.factor_dtype == SEAS_F32) ? 1 : 0);
-      const std::vector<int64_t>& off = (h.x16 && L == 1) ? hf.off32 : hf.off;
+      const std::vector<int64_t>& off = (h.x16 && L >= 1) ? hf.off32 : hf.off;
       auto elem = [&](int64_t e) { return elem_in(off, e, which); };
       for (int l = 0; l < it.nlag; ++l) {
         if (h.lagT[it.lag_off + l] != T) continue;
@@ -551,10 +555,13 @@ seas_status seas_operator_info(const seas_op_t* op, seas_op_info_t* out) {
     out->n_items = (int64_t)h.items[0].size();
     out->n_items_near = (int64_t)h.items[1].size();
     out->time_block = h.time_block;
-    int64_t far = 0;
+    int64_t far = 0, far32 = 0;
     for (const Item& it : h.items[0])
       far += it.kind == 0 ? (int64_t)it.ncol * (it.p + it.q) : (int64_t)it.nlag * it.p * it.q;
-    out->far_entries = far;
+    for (const Item& it : h.items[2])
+      far32 += it.kind == 0 ? (int64_t)it.ncol * (it.p + it.q) : (int64_t)it.nlag * it.p * it.q;
+    out->far_entries = far + far32;
+    out->far_entries_f32 = far32;
     out->dense_entries = h.dense_entries;
     out->stored_entries = h.stored_entries;
     out->lag0_nnz = (int64_t)h.l0_val.size();
@@ -576,6 +583,8 @@ seas_status seas_operator_info(const seas_op_t* op, seas_op_info_t* out) {
               (it.kind == 0 ? (int64_t)it.ncol * (it.p + it.q) : (int64_t)it.nlag * it.p * it.q);
       }
     }
+    for (const Item& it : h.items[2])
+      fb += 4 * (it.kind == 0 ? (int64_t)it.ncol * (it.p + it.q) : (int64_t)it.nlag * it.p * it.q);
     out->far_bytes = fb;
   });
 }

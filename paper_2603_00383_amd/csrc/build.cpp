@@ -315,8 +315,8 @@ struct LagFactor {
 // holds the lags 1..S-1 and the static tail, applied every step. With S = 1 every
 // lag and the tail are in list 0.
 struct BlockOut {
-  std::vector<Item> items[2];
-  std::vector<int32_t> lagT[2], lagCol[2];
+  std::vector<Item> items[3];
+  std::vector<int32_t> lagT[3], lagCol[3];
   std::vector<double> d64;
   std::vector<float> d32;
   std::vector<uint16_t> d16;
@@ -568,7 +568,13 @@ static void build_subblock(const HostOp& op, const BlockDesc& bd, const PairWin&
     else near.push_back(&lf);
   }
   if (op.x16) {
-    pack_list16(bd.r0, bd.r1, s0, s1, A, B, far, op.prm.factor_dtype == SEAS_BF16, toff, S, op.n_variants, out);
+    // near-field blocks (one variant): far lags in FP32. Their entries span the
+    // near-singular range of receivers close to a source (fault crossings), and
+    // their sums cancel strongly; 16-bit storage of them would set the error.
+    if (op.n_variants == 1 && !bd.adm)
+      pack_list(bd.r0, bd.r1, s0, s1, A, B, far, true, toff, S, 2, out);
+    else
+      pack_list16(bd.r0, bd.r1, s0, s1, A, B, far, op.prm.factor_dtype == SEAS_BF16, toff, S, op.n_variants, out);
     pack_list(bd.r0, bd.r1, s0, s1, A, B, near, true, toff, 1, 1, out);
     return;
   }
@@ -776,11 +782,11 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
   }
   if (!err.empty()) throw Error(SEAS_ERR_INTERNAL, "block build failed: " + err);
   // ---- global item lists, arena offsets, partial layouts
-  for (int L = 0; L < 2; ++L) {
+  for (int L = 0; L < 3; ++L) {
     op.items[L].clear();
     op.lagColOff[L].clear();
-    op.n_partials[L] = 0;
   }
+  op.n_partials[0] = op.n_partials[1] = 0;
   op.lagT.clear();
   op.lagCol.clear();
   op.seg_ptr.clear();
@@ -795,19 +801,19 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
   hf.f16.assign(all.size(), {});
   hf.off.assign(all.size(), 0);
   hf.off32.assign(all.size(), 0);
-  std::vector<int32_t> colOff[2];  // lagCol offset of each item, in build order
+  std::vector<int32_t> colOff[3];  // lagCol offset of each item, in build order
   for (size_t bi = 0; bi < all.size(); ++bi) {
     BlockOut& bo = outs[bi];
     hf.off[bi] = op.arena_elems;
     hf.off32[bi] = op.arena_near_elems;
-    for (int L = 0; L < 2; ++L) {
+    for (int L = 0; L < 3; ++L) {
       const int lag_base = (int)op.lagT.size();
       int col_cursor = (int)op.lagCol.size();
-      // 16-bit operators: the near list lives in the FP32 arena
-      const int64_t base = (op.x16 && L == 1) ? op.arena_near_elems : op.arena_elems;
+      // 16-bit operators: the near list and list 2 live in the FP32 arena
+      const int64_t base = (op.x16 && L >= 1) ? op.arena_near_elems : op.arena_elems;
       for (Item it : bo.items[L]) {
         it.data += base;
-        if (!op.x16 || L == 1) it.scale = 1.0f;
+        if (!op.x16 || L >= 1) it.scale = 1.0f;
         colOff[L].push_back(col_cursor);
         col_cursor += it.nlag + 1;
         it.lag_off += lag_base;
@@ -908,6 +914,11 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
     }
     op.lagColOff[L] = colOff[L];
   }
+  for (Item& it : op.items[2]) {  // FP32 far items: partials [p][S] in list 0's buffer
+    it.part = (int32_t)op.n_partials[0];
+    op.n_partials[0] += (int64_t)it.p * op.ncols;
+  }
+  op.lagColOff[2] = colOff[2];
   if (op.n_partials[0] > INT32_MAX || op.n_partials[1] > INT32_MAX || (int64_t)op.lagT.size() > INT32_MAX)
     throw Error(SEAS_ERR_INTERNAL, "operator too large for 32-bit item offsets");
   // reduction lists per receiver, in item (segment) order: the base index of the
@@ -919,6 +930,7 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
     std::vector<const Item*> heads;
     if (op.x16 && L == 0) {
       for (size_t sg = 0; sg + 1 < op.seg_ptr.size(); ++sg) heads.push_back(&op.items[0][op.seg_ptr[sg]]);
+      for (const Item& it : op.items[2]) heads.push_back(&it);
     } else {
       for (const Item& it : op.items[L]) heads.push_back(&it);
     }

@@ -101,10 +101,13 @@ struct HostOp {
   int ncols = 1;                      // columns of the far-list products: time_block * n_variants
   bool x16 = false;                   // far list in BF16/FP16 on the matrix cores, near list in FP32
   bool use_mfma = true;               // FP32, S = 16 far list on the matrix cores
-  std::vector<Item> items[2];
+  // list 2 (16-bit builds with one variant): the far lags of near-field (not
+  // admissible) blocks, kept in FP32 and applied with list 0 by the FP32 matrix-core
+  // pass; their partials share list 0's buffer and reduction lists
+  std::vector<Item> items[3];
   std::vector<int32_t> lagT;          // nlag lag values per item (ascending)
   std::vector<int32_t> lagCol;        // nlag+1 column prefix per item
-  std::vector<int32_t> lagColOff[2];  // per item: offset into lagCol
+  std::vector<int32_t> lagColOff[3];  // per item: offset into lagCol
   int64_t arena_elems = 0;
   int64_t arena_near_elems = 0;       // 16-bit operators: FP32 arena of the near list
   std::vector<int32_t> seg_ptr;       // 16-bit operators: far items of each segment (workgroup)

@@ -1053,6 +1053,14 @@ void launch_hmat(const HostOp& h, int S, int n_items, const void* items, const i
                   partials, pstride, s);
 }
 
+void launch_hmat_f32far(const HostOp& h, int n_items, const void* items, const int32_t* lagT, const int32_t* lagCol,
+                        const int32_t* lagColOff, const float* arena, const void* ring, int64_t head,
+                        float* partials, hipStream_t s) {
+  if (n_items == 0) return;
+  hipLaunchKernelGGL(k_hmat_mfma16, dim3(n_items), dim3(kItemThreads), 0, s, (const Item*)items, lagT, lagCol,
+                     lagColOff, arena, (const float*)ring, head, (int64_t)h.ring_len, h.N, partials, 16);
+}
+
 bool far_partials_f32(const HostOp& h, int S) {
   return h.x16 || (h.prm.factor_dtype == SEAS_F32 && S == 16 && h.use_mfma);
 }

@@ -76,6 +76,11 @@ void launch_clear_variant(void* base, int64_t rows, int nv, int v, int N, int el
 void launch_hmat_x16(const HostOp& h, const void* items, const int32_t* seg_ptr, const int32_t* lagT,
                      const int32_t* lagCol, const int32_t* lagColOff, const void* arena, const void* ring,
                      int64_t head, const double* tail_acc, float* partials, hipStream_t s);
+// FP32 far items of a 16-bit build (near-field blocks), S = 16 windows on the
+// matrix cores, FP32 partials [p][16] in the 16-bit far list's partial buffer
+void launch_hmat_f32far(const HostOp& h, int n_items, const void* items, const int32_t* lagT, const int32_t* lagCol,
+                        const int32_t* lagColOff, const float* arena, const void* ring, int64_t head,
+                        float* partials, hipStream_t s);
 // self term over nv variants: modal arrays [nv][n_modes], rings [nv][dring_len], slip [nv][N]
 void launch_self_hist(int n_modes, int nv, int64_t dring_len, const SelfMode* modes, const double* tab,
                       const double2* dring, int64_t time0, double2* Fh, hipStream_t s);
