@@ -29,7 +29,17 @@ BF16_PEAK_TFLOPS = 2500.0   # dense matrix-core peak
 # HBM bytes per launch of the far interaction kernel, from two rocprofv3 --pmc runs of this
 # script's default command (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), scaled by what the
 # same counters read for a plain 2 GiB copy (2.0 for FETCH_SIZE, 1.0 for WRITE_SIZE).  Keyed by
-# the SHA-256 of the kernel source they were taken on: any later change reports null.
+# the SHA-256 of the kernel's source file they were taken on: any later change reports null.
+def measured_traffic(kname):
+    """HBM bytes per launch of a far kernel from the table below, or None when the
+    kernel's source file changed since the counters were taken."""
+    import hashlib
+    src = "kernels_x16.hip" if kname.startswith("k_hmat_x16") else "kernels.hip"
+    with open(os.path.join(ROOT, "paper_2603_00383_amd", "csrc", src), "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()
+    return MEASURED_TRAFFIC.get((kname, sha))
+
+
 MEASURED_TRAFFIC = {
     ("k_hmat_mfma16", "6c9971821ad1b001d9b24014e124c9b13117fe579aedcfdbaa73f8f9d9a859dc"):
         2.0 * 10_763_000 * 1024 + 1.0 * 926_547 * 1024,
@@ -366,10 +376,7 @@ def main():
     else:
         t = 'float' if args.dtype == 'f32' else 'double'
         kname = f"k_hmat<{t},{t},{S}>"
-    import hashlib
-    with open(os.path.join(ROOT, "paper_2603_00383_amd", "csrc", "kernels.hip"), "rb") as fh:
-        ksha = hashlib.sha256(fh.read()).hexdigest()
-    traffic = MEASURED_TRAFFIC.get((kname, ksha))
+    traffic = measured_traffic(kname)
     out = {
         "metric": METRIC,
         "value": N * args.steps / wall,

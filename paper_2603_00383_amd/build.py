@@ -28,8 +28,8 @@ HIP_FLAGS = ["-x", "hip", "--offload-arch=gfx950", "-ffp-contract=fast",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 HOST_FLAGS = ["-x", "c++", "-ffp-contract=off", "-march=x86-64-v2"]
 
-SOURCES = [("build.cpp", HOST_FLAGS), ("kernels.hip", HIP_FLAGS), ("api.hip", HIP_FLAGS),
-           ("server.hip", HIP_FLAGS)]
+SOURCES = [("build.cpp", HOST_FLAGS), ("kernels.hip", HIP_FLAGS), ("kernels_x16.hip", HIP_FLAGS),
+           ("api.hip", HIP_FLAGS), ("server.hip", HIP_FLAGS)]
 
 
 def _run(cmd, verbose):

@@ -4,8 +4,10 @@
 //   k_hmat        interaction history part (lags >= 1 and the static tail): every
 //                 work item (a run of lags of one H-matrix block) streams its
 //                 factors once, with the slip-rate history rows of its lags staged
-//                 in LDS; one partial sum per receiver row
-//   k_reduce      fixed-order sum of each receiver's partials, times -mu/(2cs)
+//                 in LDS; S partial sums per receiver row (S time windows)
+//   k_hmat_mfma16 the same for FP32 factors and S = 16 on the matrix cores
+//                 (16-bit factors: kernels_x16.hip)
+//   k_reduce_*    fixed-order sums of each receiver's partials, times -mu/(2cs)
 //   k_self_hist   per-mode time convolution over lags T >= 1 (ragged windows)
 //   k_dft         explicit transform of the predicted / corrected slip, modal stress
 //   k_stage       inverse transform per element, Newton solve in ln V, state
@@ -13,14 +15,10 @@
 // Every reduction has a fixed order (no floating-point atomics).
 #include <hip/hip_runtime.h>
 
-#include "kernels.hpp"
+#include "device_common.hpp"
 
 namespace seas {
 
-__device__ __forceinline__ int64_t ring_slot(int64_t t, int64_t R) {
-  int64_t s = t % R;
-  return s < 0 ? s + R : s;
-}
 
 // ------------------------------------------------------------------ H-matrix apply
 // One work item per workgroup: a run of consecutive lags T_first .. T_first+nl-1
@@ -166,7 +164,6 @@ __global__ __launch_bounds__(kItemThreads) void k_hmat(const Item* __restrict__ 
 //   accumulator: lane l, register v holds Y[row 4 (l/16) + v][window l%16]
 // so a factor element is read once from HBM and used 16 times, and the history
 // comes from LDS once per 16 multiply-adds.
-typedef float mfma_f4 __attribute__((ext_vector_type(4)));
 
 template <typename FA, typename FB>
 __device__ __forceinline__ mfma_f4 mfma_run(int e0, int e1, FA A, FB B, mfma_f4 acc, int lane) {
@@ -352,383 +349,6 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(4)
     mfma_rows(base + (int64_t)q * nc, nc, p, [&](int c, int k) { return z[c * S + k]; }, h, out, pstride);
   } else {
     mfma_rows(base, nl * q, p, [&](int e, int k) { return h[e + (S - 1 - k) * q]; }, h, out, pstride);
-  }
-}
-
-// ------------------------------------------------------------------ 16-bit matrix-core form
-// BF16 / FP16 factors (one power-of-two scale per item) times a 16-bit copy of
-// the history, v_mfma_f32_16x16x32_{bf16,f16}, FP32 accumulation. The products
-// have NC = 16 NT columns: S history windows of nv variants, column n = k nv + v.
-// Operand layout of one MFMA (16 rows x 32 inner x 16 columns):
-//   A: lane l holds A[row l%16][8 (l/16) .. +7]      (one 16-byte load)
-//   B: lane l holds B[8 (l/16) .. +7][column l%16]   (one 16-byte LDS read)
-//   D: lane l, register v holds D[row 4 (l/16) + v][column l%16]
-// Factors are stored with the inner index fastest and rows padded to multiples
-// of 8 values, so both operands are aligned 16-byte vectors:
-//   dense    [p][nlag * q8]   inner index e = l q8 + j (lag l, source j)
-//   low rank W [ncol][q8], then U [p][ncol8]
-// The staged history holds, for rows r (time tnew - r, newest first), variants v
-// and sources j, the value at LDS index (r nv + v) q8 + j; B(e, n) for lag l,
-// window k, variant v is row l + S - 1 - k, i.e. index l nv q8 + j + hoff(n) with
-// hoff(n) = ((S - 1 - k) nv + v) q8.
-// A workgroup runs a segment: consecutive items with the same receiver rows.
-// Each wave keeps the sums of its row tiles in registers across the segment
-// (rows up to 4 x RW tiles; larger blocks come as single-item segments whose row
-// tiles are written as they finish) and one partial set of p x NC values is
-// written per segment.
-template <typename T16>
-struct Mx;
-template <>
-struct Mx<__bf16> {
-  typedef __bf16 v8 __attribute__((ext_vector_type(8)));
-  static __device__ __forceinline__ mfma_f4 mma(v8 a, v8 b, mfma_f4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ __bf16 cvt(float x) { return (__bf16)x; }
-};
-template <>
-struct Mx<_Float16> {
-  typedef _Float16 v8 __attribute__((ext_vector_type(8)));
-  static __device__ __forceinline__ mfma_f4 mma(v8 a, v8 b, mfma_f4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ _Float16 cvt(float x) { return (_Float16)x; }
-};
-
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
-// power of two >= m (1 for m = 0)
-__device__ __forceinline__ float pow2_at_least(float m) {
-  if (!(m > 0.0f)) return 1.0f;
-  int e;
-  (void)frexpf(m, &e);
-  return ldexpf(1.0f, e);
-}
-
-// tmp[t] += sum over inner k in [k0, k1) of A(k) B(k, t); k0, k1 multiples of 8.
-// PF inner steps of 32 have their operands loaded before their MFMAs.
-template <typename T16, int NT, int PF, typename FA, typename FB>
-__device__ __forceinline__ void x16_kloop(int k0, int k1, FA A, FB B, mfma_f4 (&tmp)[NT], int g) {
-  typedef typename Mx<T16>::v8 v8;
-  const v8 zero = {};
-  for (int k = k0; k < k1; k += 32 * PF) {
-    v8 a[PF], b[PF][NT];
-#pragma unroll
-    for (int s = 0; s < PF; ++s) {
-      const int kk = k + 32 * s + 8 * g;
-      const bool ok = kk < k1;
-      a[s] = ok ? A(kk) : zero;
-#pragma unroll
-      for (int t = 0; t < NT; ++t) b[s][t] = ok ? B(kk, t) : zero;
-    }
-#pragma unroll
-    for (int s = 0; s < PF; ++s) {
-#pragma unroll
-      for (int t = 0; t < NT; ++t) tmp[t] = Mx<T16>::mma(a[s], b[s][t], tmp[t]);
-    }
-  }
-}
-
-template <typename T16, typename TR, bool SCALE, int NT, bool VFAST>
-__global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT == 1 && !VFAST ? (SCALE ? 3 : 4) : 2))) void k_hmat_x16(
-    const Item* __restrict__ items, const int32_t* __restrict__ seg_ptr, const int32_t* __restrict__ lagT,
-    const int32_t* __restrict__ lagCol, const int32_t* __restrict__ lagColOff, const T16* __restrict__ arena,
-    const TR* __restrict__ ring, int64_t head, int64_t R, int N, int S, int nv,
-    const double* __restrict__ tail_acc, int64_t tail_len, float* __restrict__ partials) {
-  typedef typename Mx<T16>::v8 v8;
-  constexpr int NC = 16 * NT;
-  constexpr int RW = NT == 1 ? 8 : 4;   // row tiles per wave held across a segment
-  constexpr int PF = NT == 1 ? 6 : 2;   // inner steps loaded ahead
-  constexpr int HL = NT >= 2 ? 2 * kHist16 : kHist16;  // staged history values (hist16_limit)
-  __shared__ __attribute__((aligned(16))) T16 h[HL];
-  constexpr int ZL = NT >= 2 ? 2 * kZ16 : kZ16;  // projected values (z16_limit + 8)
-  __shared__ __attribute__((aligned(16))) T16 z[ZL];
-  // the staging maximum lives in z's last 16 bytes, which projected panels never use
-  float* smax = reinterpret_cast<float*>(z + ZL - 8);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, g = lane >> 4;
-  const int nv_shift = __builtin_ctz((unsigned)nv);  // nv is a power of two
-  const int x0 = seg_ptr[blockIdx.x], x1 = seg_ptr[blockIdx.x + 1];
-  const int p = items[x0].p;
-  const int RT = (p + 15) >> 4;
-  // Work units: (row tile, inner-range split) pairs, KS splits per tile, unit
-  // id = tile * KS + split; wave w takes units w, w + 4, ... KS is the smallest
-  // of 1, 2, 4 that makes the unit count a multiple of 4 (all waves equally
-  // busy), as long as each wave holds at most RW units and the split sums fit
-  // the LDS reduction buffer; tall blocks keep KS = 1.
-  int KS = 1;
-  if ((RT & 3) != 0) {
-    const int k = (RT & 1) ? 4 : 2;
-    if ((RT * k + 3) / 4 <= RW && RT * k * NT <= 32) KS = k;
-  }
-  const int units = RT * KS;
-  const int my_units = (units - wave + 3) / 4;
-  const bool held = my_units <= RW;          // else a single-item segment (KS = 1), written per unit
-  float* out = partials + items[x0].part;
-  mfma_f4 acc[RW][NT];
-#pragma unroll
-  for (int u = 0; u < RW; ++u)
-#pragma unroll
-    for (int t = 0; t < NT; ++t) acc[u][t] = mfma_f4{0.0f, 0.0f, 0.0f, 0.0f};
-
-  for (int x = x0; x < x1; ++x) {
-    const Item it = items[x];
-    const int q = it.q, q8 = (q + 7) & ~7, nl = it.nlag;
-    const int span = it.src == 0 ? nl + S - 1 : 1;
-    const int nrow = span * nv;
-    const int64_t tnew = head + S - 1 - lagT[it.lag_off];
-    __syncthreads();  // the previous item is done with h and z
-    // ---- stage the history panel (16-bit, scaled by 1/hs for FP16). Flat over
-    // the nrow x q8 panel: value e is row rv = e / q8 (time tnew - rv / nv,
-    // variant rv % nv), source j = e % q8; each thread issues 8 loads before it
-    // uses them, so a workgroup keeps 2048 loads in flight.
-    const int tot = nrow * q8;
-    const float inv_q8s = 1.0f / (float)q8;
-    const int64_t s0 = ring_slot(tnew, R);
-    auto hval = [&](int e) -> float {
-      const int rv = (int)(((float)e + 0.5f) * inv_q8s), j = e - rv * q8;
-      if (j >= q) return 0.0f;
-      if (it.src != 0) return (float)tail_acc[(int64_t)rv * tail_len + it.tail_off + j];
-      const int r = rv >> nv_shift, v = rv - (r << nv_shift);
-      int64_t sl = s0 - r;
-      if (sl < 0) sl += R;  // r < R
-      return (float)ring[(sl * nv + v) * (int64_t)N + it.col0 + j];
-    };
-    float hs = 1.0f;
-    if (VFAST && it.src == 0) {
-      // 16-bit history copy laid out [R][N][nv]: one aligned 16-byte load brings
-      // 8 variants of one (row, source); units u = ((r q8) + j) (nv/8) + vg,
-      // 8 loads in flight per thread
-      typedef uint16_t u8v __attribute__((ext_vector_type(8)));
-      const int ng = nv >> 3, nu = span * q8 * ng;
-      for (int u0 = tid; u0 < nu; u0 += 8 * kItemThreads) {
-        u8v xv[8];
-#pragma unroll
-        for (int w = 0; w < 8; ++w) {
-          const int u = u0 + w * kItemThreads;
-          xv[w] = u8v{};
-          if (u < nu) {
-            const int rj = u >> (nv_shift - 3), vg = u - (rj << (nv_shift - 3));
-            const int r = (int)(((float)rj + 0.5f) * inv_q8s), j = rj - r * q8;
-            if (j < q) {
-              int64_t sl = s0 - r;
-              if (sl < 0) sl += R;
-              xv[w] = *(const u8v*)((const uint16_t*)ring + ((sl * N + it.col0 + j) * nv + vg * 8));
-            }
-          }
-        }
-#pragma unroll
-        for (int w = 0; w < 8; ++w) {
-          const int u = u0 + w * kItemThreads;
-          if (u < nu) {
-            const int rj = u >> (nv_shift - 3), vg = u - (rj << (nv_shift - 3));
-            const int r = (int)(((float)rj + 0.5f) * inv_q8s), j = rj - r * q8;
-            uint16_t* d = (uint16_t*)h + ((r * nv + vg * 8) * q8 + j);
-#pragma unroll
-            for (int k = 0; k < 8; ++k) d[k * q8] = xv[w][k];
-          }
-        }
-      }
-    } else if (SCALE && tot <= 16 * kItemThreads) {
-      // FP16, panels of up to 16 values per thread: one pass, values kept in
-      // registers while the panel's maximum is formed
-      float xs[16];
-      float m = 0.0f;
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int e = tid + u * kItemThreads;
-        xs[u] = e < tot ? hval(e) : 0.0f;
-      }
-#pragma unroll
-      for (int u = 0; u < 16; ++u) m = fmaxf(m, fabsf(xs[u]));
-      m = wave_max(m);
-      if (lane == 0) smax[wave] = m;
-      __syncthreads();
-      hs = pow2_at_least(fmaxf(fmaxf(smax[0], smax[1]), fmaxf(smax[2], smax[3])));
-      const float hsi = 1.0f / hs;
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int e = tid + u * kItemThreads;
-        if (e < tot) h[e] = Mx<T16>::cvt(xs[u] * hsi);
-      }
-    } else {
-    if (SCALE) {
-      float m = 0.0f;
-      for (int e0 = tid; e0 < tot; e0 += 8 * kItemThreads) {
-        float x[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int e = e0 + u * kItemThreads;
-          x[u] = e < tot ? hval(e) : 0.0f;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) m = fmaxf(m, fabsf(x[u]));
-      }
-      m = wave_max(m);
-      if (lane == 0) smax[wave] = m;
-      __syncthreads();
-      hs = pow2_at_least(fmaxf(fmaxf(smax[0], smax[1]), fmaxf(smax[2], smax[3])));
-    }
-    const float hsi = 1.0f / hs;
-    for (int e0 = tid; e0 < tot; e0 += 8 * kItemThreads) {
-      float x[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * kItemThreads;
-        x[u] = e < tot ? hval(e) : 0.0f;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * kItemThreads;
-        if (e < tot) h[e] = Mx<T16>::cvt(x[u] * hsi);
-      }
-    }
-    }
-    // column offsets of this lane's N-tiles
-    int hoff[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const int n = t * 16 + l16, k = n / nv, v = n - k * nv;
-      hoff[t] = ((S - 1 - k) * nv + v) * q8;
-    }
-    __syncthreads();
-    const T16* base = arena + it.data;
-    float sc = it.scale * hs;
-    int E, stride;
-    const T16* M;
-    if (it.kind == 0) {
-      // ---- projection Z_l = W_l H_l per lag, column tiles of 16 round robin over waves
-      const int nc = it.ncol, nc8 = (nc + 7) & ~7;
-      const int32_t* cp = lagCol + lagColOff[x];
-      float zs = 1.0f;
-      if (SCALE) {
-        zs = 1.0f / pow2_at_least((float)q8);
-        sc /= zs;
-      }
-      int tile = 0;
-      for (int l = 0; l < nl; ++l) {
-        const int cb = cp[l], ce = cp[l + 1];
-        const int lofs = l * nv * q8;
-        for (int c0 = cb; c0 < ce; c0 += 16, ++tile) {
-          if ((tile & 3) != wave) continue;
-          mfma_f4 tmp[NT];
-#pragma unroll
-          for (int t = 0; t < NT; ++t) tmp[t] = mfma_f4{0.0f, 0.0f, 0.0f, 0.0f};
-          const int c = c0 + l16;
-          const T16* wrow = base + (int64_t)min(c, ce - 1) * q8;
-          x16_kloop<T16, NT, 2>(
-              0, q8, [&](int kk) { return c < ce ? *(const v8*)(wrow + kk) : v8{}; },
-              [&](int kk, int t) { return *(const v8*)(h + lofs + kk + hoff[t]); }, tmp, g);
-#pragma unroll
-          for (int t = 0; t < NT; ++t) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const int cc = c0 + 4 * g + v;
-              if (cc < ce) z[(t * 16 + l16) * nc8 + cc] = Mx<T16>::cvt(tmp[t][v] * zs);
-            }
-          }
-        }
-      }
-      for (int e = tid; e < NC * (nc8 - nc); e += kItemThreads) {  // zero pad columns
-        const int n = e / (nc8 - nc), c = nc + e - n * (nc8 - nc);
-        z[n * nc8 + c] = Mx<T16>::cvt(0.0f);
-      }
-      __syncthreads();
-      M = base + (int64_t)nc * q8;
-      E = nc8;
-      stride = nc8;
-    } else {
-      M = base;
-      E = nl * q8;
-      stride = nl * q8;
-    }
-    // ---- expansion / dense product: Y (p x NC) += sc * M (p x E) B (E x NC)
-    const float inv_q8 = 1.0f / (float)q8;
-    const int lag_stride = (nv - 1) * q8;
-    for (int u = 0; u < my_units; ++u) {
-      const int id = wave + 4 * u, rt = id / KS, ks = id - rt * KS;
-      const int k0 = ((int)((int64_t)(E / 8) * ks / KS)) * 8;
-      const int k1 = ((int)((int64_t)(E / 8) * (ks + 1) / KS)) * 8;
-      const int i = rt * 16 + l16;
-      const T16* arow = M + (int64_t)min(i, p - 1) * stride;
-      mfma_f4 tmp[NT];
-#pragma unroll
-      for (int t = 0; t < NT; ++t) tmp[t] = mfma_f4{0.0f, 0.0f, 0.0f, 0.0f};
-      auto A = [&](int kk) { return i < p ? *(const v8*)(arow + kk) : v8{}; };
-      if (it.kind == 0) {
-        x16_kloop<T16, NT, PF>(k0, k1, A, [&](int kk, int t) { return *(const v8*)(z + (t * 16 + l16) * (int64_t)E + kk); },
-                               tmp, g);
-      } else if (nv == 1) {
-        x16_kloop<T16, NT, PF>(k0, k1, A, [&](int kk, int t) { return *(const v8*)(h + kk + hoff[t]); }, tmp, g);
-      } else {
-        x16_kloop<T16, NT, PF>(
-            k0, k1, A,
-            [&](int kk, int t) {
-              const int l = (int)(((float)kk + 0.5f) * inv_q8);
-              return *(const v8*)(h + kk + l * lag_stride + hoff[t]);
-            },
-            tmp, g);
-      }
-      if (held) {
-#pragma unroll
-        for (int uu = 0; uu < RW; ++uu) {
-          if (uu == u) {
-#pragma unroll
-            for (int t = 0; t < NT; ++t) acc[uu][t] += sc * tmp[t];
-          }
-        }
-      } else {  // single-item segment of a tall block (wide): write this row tile
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int ii = rt * 16 + 4 * g + v;
-            if (ii < p) out[ii * NC + t * 16 + l16] = sc * tmp[t][v];
-          }
-        }
-      }
-    }
-  }
-  if (!held) return;  // single-item segment of a tall block: written per unit above
-  if (KS == 1) {
-#pragma unroll
-    for (int u = 0; u < RW; ++u) {
-      if (u >= my_units) break;
-      const int rt = wave + 4 * u;
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int ii = rt * 16 + 4 * g + v;
-          if (ii < p) out[ii * NC + t * 16 + l16] = acc[u][t][v];
-        }
-      }
-    }
-    return;
-  }
-  // inner-range splits: add the KS sums of each tile in split order through LDS
-  float* red = reinterpret_cast<float*>(h);  // units x NT x 256 floats <= 32 KB <= sizeof h
-  __syncthreads();
-#pragma unroll
-  for (int u = 0; u < RW; ++u) {
-    if (u >= my_units) break;
-    const int id = wave + 4 * u;
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) red[(id * NT + t) * 256 + lane * 4 + v] = acc[u][t][v];
-    }
-  }
-  __syncthreads();
-  for (int e = tid; e < RT * NT * 256; e += kItemThreads) {
-    const int rt = e / (NT * 256), rem = e - rt * NT * 256, t = rem >> 8, w = rem & 255, ln = w >> 2, v = w & 3;
-    float sum = 0.0f;
-    for (int kk = 0; kk < KS; ++kk) sum += red[((rt * KS + kk) * NT + t) * 256 + ln * 4 + v];
-    const int ii = rt * 16 + 4 * (ln >> 4) + v;
-    if (ii < p) out[ii * NC + t * 16 + (ln & 15)] = sum;
   }
 }
 
@@ -1003,7 +623,6 @@ __global__ void k_clear_variant(uint16_t* __restrict__ base, int64_t rows, int64
 }
 
 // ------------------------------------------------------------------ launchers
-static inline int blocks_for(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
 void launch_clear_variant(void* base, int64_t rows, int nv, int v, int N, int elem_bytes, hipStream_t s) {
   const int64_t w = (int64_t)N * elem_bytes / 2;  // 16-bit words per variant row
@@ -1065,40 +684,6 @@ bool far_partials_f32(const HostOp& h, int S) {
   return h.x16 || (h.prm.factor_dtype == SEAS_F32 && S == 16 && h.use_mfma);
 }
 
-template <typename T16, typename TR, bool SCALE, int NT, bool VFAST = false>
-static void x16_launch(const HostOp& h, const void* items, const int32_t* seg_ptr, const int32_t* lagT,
-                       const int32_t* lagCol, const int32_t* lagColOff, const void* arena, const void* ring,
-                       int64_t head, const double* tail_acc, float* partials, hipStream_t s) {
-  const int nseg = (int)h.seg_ptr.size() - 1;
-  hipLaunchKernelGGL((k_hmat_x16<T16, TR, SCALE, NT, VFAST>), dim3(nseg), dim3(kItemThreads), 0, s, (const Item*)items,
-                     seg_ptr, lagT, lagCol, lagColOff, (const T16*)arena, (const TR*)ring, head, (int64_t)h.ring_len,
-                     h.N, h.time_block, h.n_variants, tail_acc, (int64_t)h.tail_len, partials);
-}
-
-void launch_hmat_x16(const HostOp& h, const void* items, const int32_t* seg_ptr, const int32_t* lagT,
-                     const int32_t* lagCol, const int32_t* lagColOff, const void* arena, const void* ring,
-                     int64_t head, const double* tail_acc, float* partials, hipStream_t s) {
-  if (h.seg_ptr.size() < 2) return;
-  const bool bf = h.prm.factor_dtype == SEAS_BF16;
-  if (h.n_variants == 1) {
-    if (bf) x16_launch<__bf16, float, false, 1>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head, tail_acc, partials, s);
-    else x16_launch<_Float16, float, true, 1>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head, tail_acc, partials, s);
-    return;
-  }
-  // ensembles: BF16 with a BF16 rate history, or FP16 with an FP32 one scaled per item
-#define SEAS_X16_ENS(NT)                                                                                      \
-  if (bf) x16_launch<__bf16, __bf16, false, NT, true>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head, \
-                                                tail_acc, partials, s);                                        \
-  else x16_launch<_Float16, float, true, NT>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head,     \
-                                             tail_acc, partials, s);
-  switch (h.ncols) {
-    case 16: SEAS_X16_ENS(1) break;
-    case 32: SEAS_X16_ENS(2) break;
-    case 64: SEAS_X16_ENS(4) break;
-    default: break;
-  }
-#undef SEAS_X16_ENS
-}
 
 template <typename TP>
 static void reduce_far_t(const HostOp& h, int S, const TP* partials, const int32_t* ptr, const int32_t* idx, double* f,
