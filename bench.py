@@ -26,25 +26,35 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0   # dense matrix-core peak
-# HBM bytes per launch of the far interaction kernel, from two rocprofv3 --pmc runs of this
-# script's default command (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), scaled by what the
-# same counters read for a plain 2 GiB copy (2.0 for FETCH_SIZE, 1.0 for WRITE_SIZE).  Keyed by
-# the SHA-256 of the kernel's source file they were taken on: any later change reports null.
+
 def measured_traffic(kname):
-    """HBM bytes per launch of a far kernel from the table below, or None when the
-    kernel's source file changed since the counters were taken."""
+    """HBM bytes per far pass from the table below, or None when a source file it
+    depends on changed since the counters were taken."""
     import hashlib
-    src = "kernels_x16.hip" if kname.startswith("k_hmat_x16") else "kernels.hip"
-    with open(os.path.join(ROOT, "paper_2603_00383_amd", "csrc", src), "rb") as fh:
-        sha = hashlib.sha256(fh.read()).hexdigest()
-    return MEASURED_TRAFFIC.get((kname, sha))
+    entry = MEASURED_TRAFFIC.get(kname)
+    if entry is None:
+        return None
+    value, files = entry
+    for src, sha in files.items():
+        with open(os.path.join(ROOT, "paper_2603_00383_amd", "csrc", src), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != sha:
+                return None
+    return value
 
 
+KIB = 1024
+# HBM bytes per far pass of config 2 (time block 16), from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE runs of this script (KiB per dispatch), scaled by what the same counters read
+# for a plain 2 GiB copy (2.0 for FETCH_SIZE, 1.0 for WRITE_SIZE); each entry names the
+# SHA-256 of the kernel sources it was measured on. The 16-bit forms' far pass is the
+# 16-bit kernel plus the FP32 pass over the near-field blocks.
 MEASURED_TRAFFIC = {
-    ("k_hmat_mfma16", "6c9971821ad1b001d9b24014e124c9b13117fe579aedcfdbaa73f8f9d9a859dc"):
-        2.0 * 10_763_000 * 1024 + 1.0 * 926_547 * 1024,
+    "k_hmat_mfma16": (2.0 * 10_762_300 * KIB + 926_551 * KIB,
+                      {"kernels.hip": "bacbc5b23e8d53bbf0c3b0e783a71d57a451ce47bc99d15917c7fe7208079646"}),
+    "k_hmat_x16<f16,16 columns>": (2.0 * 4_579_360 * KIB + 102_828 * KIB + 2.0 * 1_254_100 * KIB + 22_377 * KIB,
+                                   {"kernels.hip": "bacbc5b23e8d53bbf0c3b0e783a71d57a451ce47bc99d15917c7fe7208079646",
+                                    "kernels_x16.hip": "95b30fdf8dc98d51ffd69ea1bb92581cbe93904816664c36e24e4ec2771cfe2d"}),
 }
-METRIC = "element-steps/s (stress eval) vs plain at rel err≤1e-4; p50/p99 window latency"
 
 
 def cpu_baseline(faults, params, prior, budget_s=12.0):
@@ -417,6 +427,7 @@ def main():
                                "kernel": f"k_hmat_x16<{d},16 columns>", "kernel_avg_ms": r["avg_ms"],
                                "achieved_GBs": r["gbs"], "frac": r["gbs"] / HBM_PEAK_GBS,
                                "algorithmic_bytes": alg_bytes(inf_d, 2), "rel_err": err,
+                               "traffic": measured_traffic(f"k_hmat_x16<{d},16 columns>"),
                                "note": "admissible blocks' lags >= 16 in 16 bits; near-field blocks, lags "
                                        "1..15 and the static tail in FP32"}
             print(f"[bench] form {d}: {out['forms'][d]['value']:.3e} element-steps/s", file=sys.stderr, flush=True)
