@@ -26,6 +26,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0   # dense matrix-core peak
+METRIC = "element-steps/s (stress eval) vs plain at rel err≤1e-4; p50/p99 window latency"
 
 def measured_traffic(kname):
     """HBM bytes per far pass from the table below, or None when a source file it

@@ -66,19 +66,21 @@ __device__ __forceinline__ void x16_kloop(int k0, int k1, FA A, FB B, mfma_f4 (&
   typedef typename Mx<T16>::v8 v8;
   const v8 zero = {};
   for (int k = k0; k < k1; k += 32 * PF) {
-    v8 a[PF], b[PF][NT];
+    // the global operand of up to PF inner steps is loaded first (one round trip
+    // for most items); the LDS operand is read step by step
+    v8 a[PF];
 #pragma unroll
     for (int s = 0; s < PF; ++s) {
       const int kk = k + 32 * s + 8 * g;
-      const bool ok = kk < k1;
-      a[s] = ok ? A(kk) : zero;
-#pragma unroll
-      for (int t = 0; t < NT; ++t) b[s][t] = ok ? B(kk, t) : zero;
+      a[s] = kk < k1 ? A(kk) : zero;
     }
 #pragma unroll
     for (int s = 0; s < PF; ++s) {
+      if (k + 32 * s >= k1) break;  // the same for every lane of the wave
+      const int kk = k + 32 * s + 8 * g;
+      const bool ok = kk < k1;
 #pragma unroll
-      for (int t = 0; t < NT; ++t) tmp[t] = Mx<T16>::mma(a[s], b[s][t], tmp[t]);
+      for (int t = 0; t < NT; ++t) tmp[t] = Mx<T16>::mma(a[s], ok ? B(kk, t) : zero, tmp[t]);
     }
   }
 }
@@ -92,7 +94,7 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
   typedef typename Mx<T16>::v8 v8;
   constexpr int NC = 16 * NT;
   constexpr int RW = NT == 1 ? 8 : 4;   // row tiles per wave held across a segment
-  constexpr int PF = NT == 1 ? 6 : 2;   // inner steps loaded ahead
+  constexpr int PF = 8;                 // inner steps whose global operand is loaded ahead
   constexpr int HL = NT >= 2 ? 2 * kHist16 : kHist16;  // staged history values (hist16_limit)
   __shared__ __attribute__((aligned(16))) T16 h[HL];
   constexpr int ZL = NT >= 2 ? 2 * kZ16 : kZ16;  // projected values (z16_limit + 8)
@@ -269,7 +271,7 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
           for (int t = 0; t < NT; ++t) tmp[t] = mfma_f4{0.0f, 0.0f, 0.0f, 0.0f};
           const int c = c0 + l16;
           const T16* wrow = base + (int64_t)min(c, ce - 1) * q8;
-          x16_kloop<T16, NT, 2>(
+          x16_kloop<T16, NT, 8>(
               0, q8, [&](int kk) { return c < ce ? *(const v8*)(wrow + kk) : v8{}; },
               [&](int kk, int t) { return *(const v8*)(h + lofs + kk + hoff[t]); }, tmp, g);
 #pragma unroll
