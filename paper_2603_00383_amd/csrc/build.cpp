@@ -433,9 +433,9 @@ static void pack_list16(int r0, int r1, int s0, int s1, const Fault& A, const Fa
         if (tail) break;
         if (lags[j]->T != lags[j - 1]->T + 1) break;
         const int span = lags[j]->T - lags[i]->T + S;
-        if ((int64_t)span * nv * q8 > hist16_limit(ncols)) break;
+        if ((int64_t)span * nv * ld16(q8) > hist16_limit(ncols)) break;
         if (nl > kColMax) break;
-        if (lr && (int64_t)round8(ncol + lags[j]->rank) * ncols > z16_limit(ncols)) break;
+        if (lr && (int64_t)ld16(round8(ncol + lags[j]->rank)) * ncols > z16_limit(ncols)) break;
         if (elems + e > target) break;
       }
       elems += e;
@@ -512,7 +512,7 @@ static void build_subblock(const HostOp& op, const BlockDesc& bd, const PairWin&
   // ranks above kmax are stored dense: the factors would not be smaller, and one
   // lag's columns must fit the LDS column buffer of the kernel
   int kmax = std::min<int>({(int)(((int64_t)p * q) / (p + q)), kColMax, kZMax / S});
-  if (op.x16) kmax = std::min(kmax, (z16_limit(op.ncols) / op.ncols) & ~7);
+  if (op.x16) kmax = std::min(kmax, ((z16_limit(op.ncols) / op.ncols) & ~7) - 8);
   const PairFrame fr = frame(A, B);
   std::vector<double> r1((size_t)p * q), r2((size_t)p * q);
   for (int i = 0; i < p; ++i)
@@ -591,7 +591,7 @@ static void build_block(const HostOp& op, const BlockDesc& bd, const PairWin& pw
   // segment instead of one per item)
   int qmax = kHistMax / op.time_block;
   // (slices as narrow as one default panel: wider slices need ranks above the cap)
-  if (op.x16) qmax = std::min(kHistMax, (kHist16 / op.ncols) & ~7);
+  if (op.x16) qmax = std::min(kHistMax, ((kHist16 / op.ncols) & ~7) - 8);
   const int pmax = (op.x16 && op.n_variants > 1) ? seg_rows_max(op.ncols) : bd.r1 - bd.r0;
   const int nrs = (bd.r1 - bd.r0 + pmax - 1) / pmax;
   for (int k = 0; k < nrs; ++k) {
@@ -887,8 +887,8 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
         const int q8 = round8(it.q);
         const int span = it.src == 0 ? it.nlag + S - 1 : 1;
         if (it.row0 != f.row0 || it.p != f.p || it.p < 1 || it.q < 1 || it.nlag < 1 ||
-            (int64_t)span * op.n_variants * q8 > hist16_limit(op.ncols) || (it.data & 7) != 0 ||
-            (it.kind == 0 && (int64_t)round8(it.ncol) * op.ncols > z16_limit(op.ncols)) ||
+            (int64_t)span * op.n_variants * ld16(q8) > hist16_limit(op.ncols) || (it.data & 7) != 0 ||
+            (it.kind == 0 && (int64_t)ld16(round8(it.ncol)) * op.ncols > z16_limit(op.ncols)) ||
             (it.src == 1 && op.n_variants == 1) ||
             it.row0 + it.p > op.N || it.col0 + it.q > op.N)
           throw Error(SEAS_ERR_INTERNAL, "16-bit item violates the kernel's limits");

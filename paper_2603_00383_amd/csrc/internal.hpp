@@ -66,6 +66,9 @@ inline int z16_limit(int ncols) { return (ncols >= 32 ? 2 * kZ16 : kZ16) - 8; }
 constexpr int kMaxVariants = 64;
 constexpr int64_t kSegElems = 1 << 19;  // factor values per segment (one workgroup)
 inline int round8(int x) { return (x + 7) & ~7; }
+// LDS row stride of a staged 16-bit panel row of q8 values: an odd number of
+// 16-byte groups, so that the 16 rows one MFMA operand reads fall in distinct banks
+inline int ld16(int q8) { return ((q8 >> 3) & 1) ? q8 : q8 + 8; }
 // rows of a multi-item segment: its accumulators stay in registers
 inline int seg_rows_max(int ncols) { return ncols == 16 ? 512 : 256; }
 

@@ -18,9 +18,11 @@ namespace seas {
 //   dense    [p][nlag * q8]   inner index e = l q8 + j (lag l, source j)
 //   low rank W [ncol][q8], then U [p][ncol8]
 // The staged history holds, for rows r (time tnew - r, newest first), variants v
-// and sources j, the value at LDS index (r nv + v) q8 + j; B(e, n) for lag l,
-// window k, variant v is row l + S - 1 - k, i.e. index l nv q8 + j + hoff(n) with
-// hoff(n) = ((S - 1 - k) nv + v) q8.
+// and sources j, the value at LDS index (r nv + v) ldh + j, where the row stride
+// ldh is q8 padded to an odd number of 16-byte groups (the 16 rows an operand
+// reads then fall in distinct banks); B(e, n) for lag l, window k, variant v is
+// row l + S - 1 - k, i.e. index l nv ldh + j + hoff(n) with
+// hoff(n) = ((S - 1 - k) nv + v) ldh.
 // A workgroup runs a segment: consecutive items with the same receiver rows.
 // Each wave keeps the sums of its row tiles in registers across the segment
 // (rows up to 4 x RW tiles; larger blocks come as single-item segments whose row
@@ -129,6 +131,7 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
   for (int x = x0; x < x1; ++x) {
     const Item it = items[x];
     const int q = it.q, q8 = (q + 7) & ~7, nl = it.nlag;
+    const int ldh = ((q8 >> 3) & 1) ? q8 : q8 + 8;  // LDS row stride (ld16)
     const int span = it.src == 0 ? nl + S - 1 : 1;
     const int nrow = span * nv;
     const int64_t tnew = head + S - 1 - lagT[it.lag_off];
@@ -178,9 +181,9 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
           if (u < nu) {
             const int rj = u >> (nv_shift - 3), vg = u - (rj << (nv_shift - 3));
             const int r = (int)(((float)rj + 0.5f) * inv_q8s), j = rj - r * q8;
-            uint16_t* d = (uint16_t*)h + ((r * nv + vg * 8) * q8 + j);
+            uint16_t* d = (uint16_t*)h + ((r * nv + vg * 8) * ldh + j);
 #pragma unroll
-            for (int k = 0; k < 8; ++k) d[k * q8] = xv[w][k];
+            for (int k = 0; k < 8; ++k) d[k * ldh] = xv[w][k];
           }
         }
       }
@@ -204,7 +207,10 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         const int e = tid + u * kItemThreads;
-        if (e < tot) h[e] = Mx<T16>::cvt(xs[u] * hsi);
+        if (e < tot) {
+          const int rv = (int)(((float)e + 0.5f) * inv_q8s);
+          h[e + rv * (ldh - q8)] = Mx<T16>::cvt(xs[u] * hsi);
+        }
       }
     } else {
     if (SCALE) {
@@ -235,7 +241,10 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int e = e0 + u * kItemThreads;
-        if (e < tot) h[e] = Mx<T16>::cvt(x[u] * hsi);
+        if (e < tot) {
+          const int rv = (int)(((float)e + 0.5f) * inv_q8s);
+          h[e + rv * (ldh - q8)] = Mx<T16>::cvt(x[u] * hsi);
+        }
       }
     }
     }
@@ -244,16 +253,17 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int n = t * 16 + l16, k = n / nv, v = n - k * nv;
-      hoff[t] = ((S - 1 - k) * nv + v) * q8;
+      hoff[t] = ((S - 1 - k) * nv + v) * ldh;
     }
     __syncthreads();
     const T16* base = arena + it.data;
     float sc = it.scale * hs;
-    int E, stride;
+    int E, stride, zld = 0;
     const T16* M;
     if (it.kind == 0) {
       // ---- projection Z_l = W_l H_l per lag, column tiles of 16 round robin over waves
       const int nc = it.ncol, nc8 = (nc + 7) & ~7;
+      const int ldz = ((nc8 >> 3) & 1) ? nc8 : nc8 + 8;  // LDS row stride of Z (ld16)
       const int32_t* cp = lagCol + lagColOff[x];
       float zs = 1.0f;
       if (SCALE) {
@@ -263,7 +273,7 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
       int tile = 0;
       for (int l = 0; l < nl; ++l) {
         const int cb = cp[l], ce = cp[l + 1];
-        const int lofs = l * nv * q8;
+        const int lofs = l * nv * ldh;
         for (int c0 = cb; c0 < ce; c0 += 16, ++tile) {
           if ((tile & 3) != wave) continue;
           mfma_f4 tmp[NT];
@@ -279,19 +289,20 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
               const int cc = c0 + 4 * g + v;
-              if (cc < ce) z[(t * 16 + l16) * nc8 + cc] = Mx<T16>::cvt(tmp[t][v] * zs);
+              if (cc < ce) z[(t * 16 + l16) * ldz + cc] = Mx<T16>::cvt(tmp[t][v] * zs);
             }
           }
         }
       }
       for (int e = tid; e < NC * (nc8 - nc); e += kItemThreads) {  // zero pad columns
         const int n = e / (nc8 - nc), c = nc + e - n * (nc8 - nc);
-        z[n * nc8 + c] = Mx<T16>::cvt(0.0f);
+        z[n * ldz + c] = Mx<T16>::cvt(0.0f);
       }
       __syncthreads();
       M = base + (int64_t)nc * q8;
       E = nc8;
       stride = nc8;
+      zld = ldz;
     } else {
       M = base;
       E = nl * q8;
@@ -299,7 +310,7 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
     }
     // ---- expansion / dense product: Y (p x NC) += sc * M (p x E) B (E x NC)
     const float inv_q8 = 1.0f / (float)q8;
-    const int lag_stride = (nv - 1) * q8;
+    const int lag_stride = nv * ldh - q8;  // h index of (lag l, source j): l nv ldh + j = kk + l lag_stride
     for (int u = 0; u < my_units; ++u) {
       const int id = wave + 4 * u, rt = id / KS, ks = id - rt * KS;
       const int k0 = ((int)((int64_t)(E / 8) * ks / KS)) * 8;
@@ -311,9 +322,9 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
       for (int t = 0; t < NT; ++t) tmp[t] = mfma_f4{0.0f, 0.0f, 0.0f, 0.0f};
       auto A = [&](int kk) { return i < p ? *(const v8*)(arow + kk) : v8{}; };
       if (it.kind == 0) {
-        x16_kloop<T16, NT, PF>(k0, k1, A, [&](int kk, int t) { return *(const v8*)(z + (t * 16 + l16) * (int64_t)E + kk); },
+        x16_kloop<T16, NT, PF>(k0, k1, A, [&](int kk, int t) { return *(const v8*)(z + (t * 16 + l16) * zld + kk); },
                                tmp, g);
-      } else if (nv == 1) {
+      } else if (nv == 1 && ldh == q8) {
         x16_kloop<T16, NT, PF>(k0, k1, A, [&](int kk, int t) { return *(const v8*)(h + kk + hoff[t]); }, tmp, g);
       } else {
         x16_kloop<T16, NT, PF>(
