@@ -154,38 +154,30 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
     };
     float hs = 1.0f;
     if (VFAST && it.src == 0) {
-      // 16-bit history copy laid out [R][N][nv]: one aligned 16-byte load brings
-      // 8 variants of one (row, source); units u = ((r q8) + j) (nv/8) + vg,
-      // 8 loads in flight per thread
+      // 16-bit history copy laid out [R][N][nv]. A thread takes a tile of 8
+      // sources x 8 variants: 8 aligned 16-byte loads (one per source, 8 variants
+      // each; the 8 lanes of a group read one 128-byte row segment), a transpose
+      // in registers, and 8 aligned 16-byte LDS stores (one per variant, 8
+      // consecutive sources). Tiles u = ((r nj + jg) ng + vg), nj = q8 / 8.
       typedef uint16_t u8v __attribute__((ext_vector_type(8)));
-      const int ng = nv >> 3, nu = span * q8 * ng;
-      for (int u0 = tid; u0 < nu; u0 += 8 * kItemThreads) {
-        u8v xv[8];
+      const int ng = nv >> 3, nj = q8 >> 3, nt = span * nj * ng;
+      const float inv_nj = 1.0f / (float)nj;
+      for (int u = tid; u < nt; u += kItemThreads) {
+        const int vg = u & (ng - 1), rest = u >> (nv_shift - 3);
+        const int r = (int)(((float)rest + 0.5f) * inv_nj), jg = rest - r * nj;
+        int64_t sl = s0 - r;
+        if (sl < 0) sl += R;
+        const uint16_t* src = (const uint16_t*)ring + ((sl * N + it.col0 + 8 * jg) * nv + vg * 8);
+        u8v xv[8], yv[8];
 #pragma unroll
-        for (int w = 0; w < 8; ++w) {
-          const int u = u0 + w * kItemThreads;
-          xv[w] = u8v{};
-          if (u < nu) {
-            const int rj = u >> (nv_shift - 3), vg = u - (rj << (nv_shift - 3));
-            const int r = (int)(((float)rj + 0.5f) * inv_q8s), j = rj - r * q8;
-            if (j < q) {
-              int64_t sl = s0 - r;
-              if (sl < 0) sl += R;
-              xv[w] = *(const u8v*)((const uint16_t*)ring + ((sl * N + it.col0 + j) * nv + vg * 8));
-            }
-          }
-        }
+        for (int k = 0; k < 8; ++k) xv[k] = (8 * jg + k < q) ? *(const u8v*)(src + (int64_t)k * nv) : u8v{};
 #pragma unroll
-        for (int w = 0; w < 8; ++w) {
-          const int u = u0 + w * kItemThreads;
-          if (u < nu) {
-            const int rj = u >> (nv_shift - 3), vg = u - (rj << (nv_shift - 3));
-            const int r = (int)(((float)rj + 0.5f) * inv_q8s), j = rj - r * q8;
-            uint16_t* d = (uint16_t*)h + ((r * nv + vg * 8) * ldh + j);
+        for (int v = 0; v < 8; ++v)
 #pragma unroll
-            for (int k = 0; k < 8; ++k) d[k * ldh] = xv[w][k];
-          }
-        }
+          for (int k = 0; k < 8; ++k) yv[v][k] = xv[k][v];
+        uint16_t* d = (uint16_t*)h + ((r * nv + vg * 8) * ldh + 8 * jg);
+#pragma unroll
+        for (int v = 0; v < 8; ++v) *(u8v*)(d + v * ldh) = yv[v];
       }
     } else if (SCALE && tot <= 16 * kItemThreads) {
       // FP16, panels of up to 16 values per thread: one pass, values kept in
