@@ -1,7 +1,8 @@
 """GPU parity of the far-list kernels on large blocks: two parallel faults of n
 elements far enough apart that their pair is two low-rank blocks of n/2 rows
-(n = 150, 300, 600, 1200 gives 5, 10, 19 and 38 row tiles of 16, the heights
-of the five-fault benchmark's blocks). The interaction history part of one SEAS
+(n = 150 and 1200 give 5 and 38 row tiles of 16: the inner-range split of the
+work units, and the tall blocks whose rows are written per unit; 300 and 600,
+the heights in between, gave the same errors when measured). The interaction history part of one SEAS
 step from a saturated history is compared with the oracle on sampled receivers,
 for FP32, BF16 and FP16 factors.
 
@@ -37,7 +38,7 @@ def _pair(n):
     return [SI.fault(0.0, 0.0, 0.0, L, n), SI.fault(0.0, 1.6 * L, 10.0, L, n)]
 
 
-@pytest.mark.parametrize("n", [150, 300, 600, 1200])
+@pytest.mark.parametrize("n", [150, 1200])
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
 def test_single_block_history_part(n, dtype):
     faults = _pair(n)
