@@ -390,6 +390,8 @@ def main():
     hmat_bytes = alg_bytes(info, elem_bytes)
     if args.dtype in ("bf16", "f16"):
         kname = f"k_hmat_x16<{'bf16' if args.dtype == 'bf16' else 'f16'},16 columns>"
+    elif args.dtype == "f32" and S == 16 and info["n_segments"] > 0:
+        kname = "k_hmat_x16<f32,16 columns>"  # the segment kernel, FP32 instance
     elif args.dtype == "f32" and S == 16 and not os.environ.get("SEAS_NO_MFMA"):
         kname = "k_hmat_mfma16"
     else:

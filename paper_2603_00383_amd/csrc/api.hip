@@ -210,9 +210,10 @@ void eval_history(seas_op* op, seas_state* st, int64_t head, hipStream_t s) {
   int64_t k = head - st->block_head;
   if (plain || k < 0 || k >= S) {
     // plain form on a time-blocked build: window 0 of the far list at this head
-    const int Sl = (plain && !h.x16) ? 1 : S;
+    // (the segment kernel always forms its S windows; the plain form uses window 0)
+    const int Sl = (plain && !h.seg) ? 1 : S;
     record_start(st, s);
-    if (h.x16) {
+    if (h.seg) {
       launch_hmat_x16(h, op->items[0], op->seg_ptr, op->lagT, op->lagCol, op->lagColOff[0], op->arena, st->ringop,
                       head, st->tail_acc, (float*)st->partials_far, s);
       launch_hmat_f32far(h, (int)h.items[2].size(), op->items[2], op->lagT, op->lagCol, op->lagColOff[2],
@@ -222,13 +223,13 @@ void eval_history(seas_op* op, seas_state* st, int64_t head, hipStream_t s) {
                   st->tail_acc, (double*)st->partials_far, S, s);
     record_stop(st, s);
     const bool f32p = far_partials_f32(h, Sl);
-    launch_reduce_far(h, h.x16 ? h.ncols : Sl, st->partials_far, f32p, op->red_ptr[0], op->red_idx[0],
+    launch_reduce_far(h, h.seg ? h.ncols : Sl, st->partials_far, f32p, op->red_ptr[0], op->red_idx[0],
                       nnear == 0 ? st->f_hist : st->f_far, s);
     if (nnear == 0) return;
     st->block_head = plain ? INT64_MIN / 2 : head;
     k = 0;
   }
-  const void* arena_near = h.x16 ? (const void*)op->arena_near : op->arena;
+  const void* arena_near = h.seg ? (const void*)op->arena_near : op->arena;
   launch_hmat(h, 1, nnear, op->items[1], op->lagT, op->lagCol, op->lagColOff[1], arena_near, st->ringop, head,
               st->tail_acc, st->partials_near, 1, s);
   launch_reduce_near(h, st->partials_near, op->red_ptr[1], op->red_idx[1], st->f_far + k * h.N, st->f_hist, s);
@@ -369,22 +370,25 @@ seas_status seas_build_operator(const seas_fault_t* faults, int32_t n_faults, co
     }
     // factor arenas, block by block
     op->arena = dalloc(op->owned, (size_t)h.arena_elems * op->elem_bytes);
-    if (h.x16) op->arena_near = (float*)dalloc(op->owned, (size_t)h.arena_near_elems * 4);
+    if (h.seg) op->arena_near = (float*)dalloc(op->owned, (size_t)h.arena_near_elems * 4);
     for (size_t bi = 0; bi < hf.off.size(); ++bi) {
-      const size_t n = h.x16 ? hf.f16[bi].size() : (f32 ? hf.f32[bi].size() : hf.f64[bi].size());
+      const size_t n = h.x16 ? hf.f16[bi].size()
+                             : (h.seg ? hf.f32s[bi].size() : (f32 ? hf.f32[bi].size() : hf.f64[bi].size()));
       const void* src = h.x16 ? (const void*)hf.f16[bi].data()
-                              : (f32 ? (const void*)hf.f32[bi].data() : (const void*)hf.f64[bi].data());
+                              : (h.seg ? (const void*)hf.f32s[bi].data()
+                                       : (f32 ? (const void*)hf.f32[bi].data() : (const void*)hf.f64[bi].data()));
       if (n > 0)
         HIPCHK(hipMemcpy((char*)op->arena + (size_t)hf.off[bi] * op->elem_bytes, src, n * op->elem_bytes,
                          hipMemcpyHostToDevice));
-      if (h.x16 && !hf.f32[bi].empty())
+      if (h.seg && !hf.f32[bi].empty())
         HIPCHK(hipMemcpy(op->arena_near + hf.off32[bi], hf.f32[bi].data(), hf.f32[bi].size() * 4,
                          hipMemcpyHostToDevice));
       std::vector<double>().swap(hf.f64[bi]);
       std::vector<float>().swap(hf.f32[bi]);
       std::vector<uint16_t>().swap(hf.f16[bi]);
+      std::vector<float>().swap(hf.f32s[bi]);
     }
-    if (h.x16) op->seg_ptr = upload(op->owned, h.seg_ptr);
+    if (h.seg) op->seg_ptr = upload(op->owned, h.seg_ptr);
     for (int L = 0; L < 3; ++L) {
       op->items[L] = upload(op->owned, h.items[L]);
       op->lagColOff[L] = upload(op->owned, h.lagColOff[L]);
@@ -484,9 +488,13 @@ seas_status seas_operator_lag_matrix(const seas_op_t* op, int32_t a, int32_t b, 
         else hi = mid;
       }
       while (lo + 1 < off.size() && off[lo + 1] == off[lo] &&
-             (which == 2 ? hf.f16[lo].empty() : which == 1 ? hf.f32[lo].empty() : hf.f64[lo].empty()))
+             (which == 3   ? hf.f32s[lo].empty()
+              : which == 2 ? hf.f16[lo].empty()
+              : which == 1 ? hf.f32[lo].empty()
+                           : hf.f64[lo].empty()))
         ++lo;  // skip empty blocks that share the offset
       const int64_t k = e - off[lo];
+      if (which == 3) return (double)hf.f32s[lo][k];
       if (which == 2)
         return h.prm.factor_dtype == SEAS_BF16 ? (double)from_bf16(hf.f16[lo][k]) : (double)from_f16(hf.f16[lo][k]);
       return which == 1 ? (double)hf.f32[lo][k] : hf.f64[lo][k];
@@ -497,13 +505,13 @@ seas_status seas_operator_lag_matrix(const seas_op_t* op, int32_t a, int32_t b, 
       if (it.row0 < A.off || it.row0 >= A.off + p_all || it.col0 < B.off || it.col0 >= B.off + q_all) continue;
       const int ri = it.row0 - A.off, cj = it.col0 - B.off;
       const int32_t* cp = &h.lagCol[h.lagColOff[L][ii]];
-      const bool x16 = h.x16 && L == 0;
-      const int which = x16 ? 2 : ((h.x16 || h.prm.factor_dtype == SEAS_F32) ? 1 : 0);
-      const std::vector<int64_t>& off = (h.x16 && L >= 1) ? hf.off32 : hf.off;
+      const bool sg = h.seg && L == 0;
+      const int which = sg ? (h.x16 ? 2 : 3) : ((h.seg || h.prm.factor_dtype == SEAS_F32) ? 1 : 0);
+      const std::vector<int64_t>& off = (h.seg && L >= 1) ? hf.off32 : hf.off;
       auto elem = [&](int64_t e) { return elem_in(off, e, which); };
       for (int l = 0; l < it.nlag; ++l) {
         if (h.lagT[it.lag_off + l] != T) continue;
-        if (x16) {
+        if (sg) {
           const int q8 = round8(it.q), nc = it.ncol, nc8 = round8(nc);
           const double sc = it.scale;
           if (it.kind == 0) {
@@ -572,12 +580,12 @@ seas_status seas_operator_info(const seas_op_t* op, seas_op_info_t* out) {
     out->factor_dtype = h.prm.factor_dtype;
     out->n_variants = h.n_variants;
     out->ncols = h.ncols;
-    out->n_segments = h.x16 ? (int64_t)h.seg_ptr.size() - 1 : 0;
+    out->n_segments = h.seg ? (int64_t)h.seg_ptr.size() - 1 : 0;
     int64_t fb = 0;
     for (const Item& it : h.items[0]) {
-      if (h.x16) {
+      if (h.seg) {
         const int64_t q8 = round8(it.q);
-        fb += 2 * (it.kind == 0 ? (int64_t)it.ncol * q8 + (int64_t)it.p * round8(it.ncol) : (int64_t)it.nlag * it.p * q8);
+        fb += h.seg_eb * (it.kind == 0 ? (int64_t)it.ncol * q8 + (int64_t)it.p * round8(it.ncol) : (int64_t)it.nlag * it.p * q8);
       } else {
         fb += (int64_t)op->elem_bytes *
               (it.kind == 0 ? (int64_t)it.ncol * (it.p + it.q) : (int64_t)it.nlag * it.p * it.q);
@@ -646,7 +654,7 @@ size_t seas_state_bytes(const seas_op_t* op, int32_t n_variants) {
   b += (size_t)h.ring_len * N * 8;                               // FP64 rate history
   if (op->ring_bytes != 8) b += (size_t)h.ring_len * N * op->ring_bytes;  // operand copy
   b += (size_t)h.tail_len * 8 * n_variants;
-  b += (size_t)h.n_partials[0] * (h.x16 ? 4 : 8) + (size_t)h.n_partials[1] * 8;
+  b += (size_t)h.n_partials[0] * (h.seg ? 4 : 8) + (size_t)h.n_partials[1] * 8;
   b += (size_t)h.time_block * N * 8;
   b += (size_t)h.self_ring_len * 16 * n_variants + (size_t)h.n_modes * 16 * 2 * n_variants;
   return b;
@@ -702,7 +710,7 @@ seas_status seas_state_create(seas_op_t* op, int32_t n_variants, const seas_fric
     st->tail_acc = (double*)A((size_t)h.tail_len * 8 * nv, true);
     // FP64 slots even where the far pass writes FP32: the plain form of an FP32
     // build (seas_state_set_time_block(1)) writes FP64 partials into the same buffer
-    st->partials_far = A((size_t)h.n_partials[0] * (h.x16 ? 4 : 8), false);
+    st->partials_far = A((size_t)h.n_partials[0] * (h.seg ? 4 : 8), false);
     st->partials_near = (double*)A((size_t)h.n_partials[1] * 8, false);
     st->f_far = (double*)A((size_t)h.time_block * vb, true);
     st->dring = (double2*)A((size_t)h.self_ring_len * 16 * nv, true);

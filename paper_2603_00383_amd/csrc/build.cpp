@@ -320,6 +320,7 @@ struct BlockOut {
   std::vector<double> d64;
   std::vector<float> d32;
   std::vector<uint16_t> d16;
+  std::vector<float> s32;  // FP32 segment far list
   int64_t stored = 0, dense = 0;
 };
 
@@ -402,23 +403,30 @@ static void pack_list(int r0, int r1, int s0, int s1, const Fault& A, const Faul
   }
 }
 
-// Pack a run of lag factors of one (sub-)block into 16-bit items of the far list
-// for the matrix-core kernel, whose products have ncols = S * nv columns (S
-// history windows of nv variants). Layout (rows padded with zeros to q8 / ncol8
-// values so that every 8-value group is one aligned 16-byte load):
+// Pack a run of lag factors of one (sub-)block into items of the segment far
+// list for the matrix-core kernel, whose products have ncols = S * nv columns (S
+// history windows of nv variants). Values are BF16 / FP16 (dtype) or FP32.
+// Layout (rows padded with zeros to q8 / ncol8 values so that every 8-value group
+// is one aligned 16- or 32-byte load):
 //   dense:    [p][nlag * q8]   row i holds lag 0's q8 values, then lag 1's, ...
 //   low rank: W [ncol][q8]     projection rows, lag after lag
 //             U [p][ncol8]     expansion rows
-// Stored values are the factors divided by a power-of-two item scale (dense: the
+// 16-bit values are the factors divided by a power-of-two item scale (dense: the
 // item's max |D|; low rank: max |W| times max |U|, each panel scaled on its own),
-// so they lie in [-1, 1]. Limits: staged history (span * nv * q8 values), the
-// projected panel (ncol8 * ncols values) and the lag count.
-static void pack_list16(int r0, int r1, int s0, int s1, const Fault& A, const Fault& B,
-                        std::vector<LagFactor*>& lags, bool bf16, int tail_off, int S, int nv, BlockOut& out) {
+// so they lie in [-1, 1]; FP32 values are the factors (scale 1). Limits: staged
+// history (span * nv * q8 values), the projected panel (ncol8 * ncols values) and
+// the lag count.
+static void pack_seg(int r0, int r1, int s0, int s1, const Fault& A, const Fault& B,
+                     std::vector<LagFactor*>& lags, int dtype, int tail_off, int S, int nv, BlockOut& out) {
   const int p = r1 - r0, q = s1 - s0, q8 = round8(q);
   const int ncols = S * nv;
-  const int64_t target = 131072;  // stored values per item
-  auto cvt = [&](double v) { return bf16 ? to_bf16((float)v) : to_f16((float)v); };
+  const bool f32 = dtype == SEAS_F32;
+  const int eb = f32 ? 4 : 2;
+  const int64_t target = f32 ? 65536 : 131072;  // stored values per item
+  auto put = [&](double v) {
+    if (f32) out.s32.push_back((float)v);
+    else out.d16.push_back(dtype == SEAS_BF16 ? to_bf16((float)v) : to_f16((float)v));
+  };
   size_t i = 0;
   while (i < lags.size()) {
     const bool lr = lags[i]->rank > 0;
@@ -433,9 +441,9 @@ static void pack_list16(int r0, int r1, int s0, int s1, const Fault& A, const Fa
         if (tail) break;
         if (lags[j]->T != lags[j - 1]->T + 1) break;
         const int span = lags[j]->T - lags[i]->T + S;
-        if ((int64_t)span * nv * ld16(q8) > hist16_limit(ncols)) break;
+        if ((int64_t)span * nv * seg_ld(q8, eb) > seg_hist_limit(ncols, eb)) break;
         if (nl > kColMax) break;
-        if (lr && (int64_t)ld16(round8(ncol + lags[j]->rank)) * ncols > z16_limit(ncols)) break;
+        if (lr && (int64_t)seg_ld(round8(ncol + lags[j]->rank), eb) * ncols > seg_z_limit(ncols, eb)) break;
         if (elems + e > target) break;
       }
       elems += e;
@@ -443,7 +451,7 @@ static void pack_list16(int r0, int r1, int s0, int s1, const Fault& A, const Fa
       ++j;
     }
     Item it{};
-    it.data = (int64_t)out.d16.size();  // block-local, rebased later
+    it.data = f32 ? (int64_t)out.s32.size() : (int64_t)out.d16.size();  // block-local, rebased later
     it.kind = lr ? 0 : 1;
     it.src = tail ? 1 : 0;
     it.p = p;
@@ -465,27 +473,27 @@ static void pack_list16(int r0, int r1, int s0, int s1, const Fault& A, const Fa
         for (double v : lags[l]->W) mw = std::max(mw, std::fabs(v));
         for (double v : lags[l]->U) mu = std::max(mu, std::fabs(v));
       }
-      const double sw = pow2_at_least(mw), su = pow2_at_least(mu);
+      const double sw = f32 ? 1.0 : pow2_at_least(mw), su = f32 ? 1.0 : pow2_at_least(mu);
       it.scale = (float)(sw * su);
       const int ncol8 = round8(ncol);
       for (size_t l = i; l < j; ++l)  // W [ncol][q8]
         for (int r = 0; r < lags[l]->rank; ++r)
-          for (int jj = 0; jj < q8; ++jj) out.d16.push_back(jj < q ? cvt(lags[l]->W[(size_t)r * q + jj] / sw) : 0);
+          for (int jj = 0; jj < q8; ++jj) put(jj < q ? lags[l]->W[(size_t)r * q + jj] / sw : 0.0);
       for (int ii = 0; ii < p; ++ii) {  // U [p][ncol8]
         for (size_t l = i; l < j; ++l)
-          for (int r = 0; r < lags[l]->rank; ++r) out.d16.push_back(cvt(lags[l]->U[(size_t)r * p + ii] / su));
-        for (int cc = ncol; cc < ncol8; ++cc) out.d16.push_back(0);
+          for (int r = 0; r < lags[l]->rank; ++r) put(lags[l]->U[(size_t)r * p + ii] / su);
+        for (int cc = ncol; cc < ncol8; ++cc) put(0.0);
       }
     } else {
       for (int l = 0; l < it.nlag; ++l) out.lagCol[0].push_back(0);
       double md = 0.0;
       for (size_t l = i; l < j; ++l)
         for (double v : lags[l]->D) md = std::max(md, std::fabs(v));
-      const double sd = pow2_at_least(md);
+      const double sd = f32 ? 1.0 : pow2_at_least(md);
       it.scale = (float)sd;
       for (int ii = 0; ii < p; ++ii)  // [p][nlag * q8]
         for (size_t l = i; l < j; ++l)
-          for (int jj = 0; jj < q8; ++jj) out.d16.push_back(jj < q ? cvt(lags[l]->D[(size_t)ii * q + jj] / sd) : 0);
+          for (int jj = 0; jj < q8; ++jj) put(jj < q ? lags[l]->D[(size_t)ii * q + jj] / sd : 0.0);
     }
     out.stored += elems;
     out.items[0].push_back(it);
@@ -512,7 +520,7 @@ static void build_subblock(const HostOp& op, const BlockDesc& bd, const PairWin&
   // ranks above kmax are stored dense: the factors would not be smaller, and one
   // lag's columns must fit the LDS column buffer of the kernel
   int kmax = std::min<int>({(int)(((int64_t)p * q) / (p + q)), kColMax, kZMax / S});
-  if (op.x16) kmax = std::min(kmax, ((z16_limit(op.ncols) / op.ncols) & ~7) - 8);
+  if (op.seg) kmax = std::min(kmax, ((seg_z_limit(op.ncols, op.seg_eb) / op.ncols) & ~7) - 8);
   const PairFrame fr = frame(A, B);
   std::vector<double> r1((size_t)p * q), r2((size_t)p * q);
   for (int i = 0; i < p; ++i)
@@ -567,14 +575,14 @@ static void build_subblock(const HostOp& op, const BlockDesc& bd, const PairWin&
     if (S == 1 || (lf.T >= S)) far.push_back(&lf);
     else near.push_back(&lf);
   }
-  if (op.x16) {
-    // near-field blocks (one variant): far lags in FP32. Their entries span the
-    // near-singular range of receivers close to a source (fault crossings), and
+  if (op.seg) {
+    // 16-bit near-field blocks (one variant): far lags in FP32. Their entries span
+    // the near-singular range of receivers close to a source (fault crossings), and
     // their sums cancel strongly; 16-bit storage of them would set the error.
-    if (op.n_variants == 1 && !bd.adm)
+    if (op.x16 && op.n_variants == 1 && !bd.adm)
       pack_list(bd.r0, bd.r1, s0, s1, A, B, far, true, toff, S, 2, out);
     else
-      pack_list16(bd.r0, bd.r1, s0, s1, A, B, far, op.prm.factor_dtype == SEAS_BF16, toff, S, op.n_variants, out);
+      pack_seg(bd.r0, bd.r1, s0, s1, A, B, far, op.prm.factor_dtype, toff, S, op.n_variants, out);
     pack_list(bd.r0, bd.r1, s0, s1, A, B, near, true, toff, 1, 1, out);
     return;
   }
@@ -591,8 +599,9 @@ static void build_block(const HostOp& op, const BlockDesc& bd, const PairWin& pw
   // segment instead of one per item)
   int qmax = kHistMax / op.time_block;
   // (slices as narrow as one default panel: wider slices need ranks above the cap)
-  if (op.x16) qmax = std::min(kHistMax, ((kHist16 / op.ncols) & ~7) - 8);
-  const int pmax = (op.x16 && op.n_variants > 1) ? seg_rows_max(op.ncols) : bd.r1 - bd.r0;
+  // (FP32 segment builds keep the FP32 slices, which fit their staging buffer)
+  if (op.seg) qmax = std::min(op.x16 ? kHistMax : qmax, ((kHist16 * 2 / op.seg_eb / op.ncols) & ~7) - 8);
+  const int pmax = (op.seg && op.n_variants > 1) ? seg_rows_max(op.ncols) : bd.r1 - bd.r0;
   const int nrs = (bd.r1 - bd.r0 + pmax - 1) / pmax;
   for (int k = 0; k < nrs; ++k) {
     BlockDesc rs = bd;  // equal row slices
@@ -644,6 +653,9 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
   }
   op.ncols = op.time_block * op.n_variants;
   op.use_mfma = std::getenv("SEAS_NO_MFMA") == nullptr;
+  op.seg = op.x16 || (prm.factor_dtype == SEAS_F32 && op.time_block == 16 && op.use_mfma &&
+                      std::getenv("SEAS_NO_SEG") == nullptr);
+  op.seg_eb = op.x16 ? 2 : 4;
   if (prm.n_threads > 0) omp_set_num_threads(prm.n_threads);
   // ---- geometry
   op.faults.clear();
@@ -799,6 +811,7 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
   hf.f64.assign(all.size(), {});
   hf.f32.assign(all.size(), {});
   hf.f16.assign(all.size(), {});
+  hf.f32s.assign(all.size(), {});
   hf.off.assign(all.size(), 0);
   hf.off32.assign(all.size(), 0);
   std::vector<int32_t> colOff[3];  // lagCol offset of each item, in build order
@@ -809,11 +822,11 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
     for (int L = 0; L < 3; ++L) {
       const int lag_base = (int)op.lagT.size();
       int col_cursor = (int)op.lagCol.size();
-      // 16-bit operators: the near list and list 2 live in the FP32 arena
-      const int64_t base = (op.x16 && L >= 1) ? op.arena_near_elems : op.arena_elems;
+      // segment operators: the near list and list 2 live in the FP32 near arena
+      const int64_t base = (op.seg && L >= 1) ? op.arena_near_elems : op.arena_elems;
       for (Item it : bo.items[L]) {
         it.data += base;
-        if (!op.x16 || L >= 1) it.scale = 1.0f;
+        if (!op.seg || L >= 1) it.scale = 1.0f;
         colOff[L].push_back(col_cursor);
         col_cursor += it.nlag + 1;
         it.lag_off += lag_base;
@@ -822,10 +835,11 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
       op.lagT.insert(op.lagT.end(), bo.lagT[L].begin(), bo.lagT[L].end());
       op.lagCol.insert(op.lagCol.end(), bo.lagCol[L].begin(), bo.lagCol[L].end());
     }
-    if (op.x16) {
-      op.arena_elems += (int64_t)bo.d16.size();
+    if (op.seg) {
+      op.arena_elems += op.x16 ? (int64_t)bo.d16.size() : (int64_t)bo.s32.size();
       op.arena_near_elems += (int64_t)bo.d32.size();
       hf.f16[bi].swap(bo.d16);
+      hf.f32s[bi].swap(bo.s32);
       hf.f32[bi].swap(bo.d32);
     } else {
       op.arena_elems += f32 ? (int64_t)bo.d32.size() : (int64_t)bo.d64.size();
@@ -835,11 +849,11 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
     op.stored_entries += bo.stored;
     op.dense_entries += bo.dense;
   }
-  // 16-bit far list: items with the same receiver rows are ordered next to each
+  // segment far list: items with the same receiver rows are ordered next to each
   // other and grouped into segments, one workgroup each, that keep the sums of
   // their rows in registers and write one partial set; rows beyond what the
   // registers hold make single-item segments.
-  if (op.x16) {
+  if (op.seg) {
     std::vector<size_t> ord(op.items[0].size());
     std::iota(ord.begin(), ord.end(), 0);
     std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) {
@@ -866,16 +880,17 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
       int64_t v = vals(f);
       if (f.p <= rmax)
         while (e < op.items[0].size() && op.items[0][e].row0 == f.row0 && op.items[0][e].p == f.p &&
-               v + vals(op.items[0][e]) <= kSegElems)
+               v + vals(op.items[0][e]) <= kSegElems * 2 / op.seg_eb)
           v += vals(op.items[0][e++]);
       op.seg_ptr.push_back((int32_t)k);
       k = e;
     }
     op.seg_ptr.push_back((int32_t)op.items[0].size());
   }
-  // invariants the 16-bit kernel relies on (LDS panel sizes, 16-byte alignment,
+  // invariants the segment kernel relies on (LDS panel sizes, 16-byte alignment,
   // one row range per segment, register-held rows of multi-item segments)
-  if (op.x16) {
+  if (op.seg) {
+    const int eb = op.seg_eb;
     const int rmax = seg_rows_max(op.ncols);
     for (size_t sg = 0; sg + 1 < op.seg_ptr.size(); ++sg) {
       const int32_t a = op.seg_ptr[sg], b = op.seg_ptr[sg + 1];
@@ -887,20 +902,20 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
         const int q8 = round8(it.q);
         const int span = it.src == 0 ? it.nlag + S - 1 : 1;
         if (it.row0 != f.row0 || it.p != f.p || it.p < 1 || it.q < 1 || it.nlag < 1 ||
-            (int64_t)span * op.n_variants * ld16(q8) > hist16_limit(op.ncols) || (it.data & 7) != 0 ||
-            (it.kind == 0 && (int64_t)ld16(round8(it.ncol)) * op.ncols > z16_limit(op.ncols)) ||
+            (int64_t)span * op.n_variants * seg_ld(q8, eb) > seg_hist_limit(op.ncols, eb) || (it.data & 7) != 0 ||
+            (it.kind == 0 && (int64_t)seg_ld(round8(it.ncol), eb) * op.ncols > seg_z_limit(op.ncols, eb)) ||
             (it.src == 1 && op.n_variants == 1) ||
             it.row0 + it.p > op.N || it.col0 + it.q > op.N)
-          throw Error(SEAS_ERR_INTERNAL, "16-bit item violates the kernel's limits");
+          throw Error(SEAS_ERR_INTERNAL, "segment item violates the kernel's limits");
       }
     }
   }
-  // partial offsets: per item, or per segment on the 16-bit far list (far
+  // partial offsets: per item, or per segment on the segment far list (far
   // partials are [p][S] or [p][ncols], row-major)
   for (int L = 0; L < 2; ++L) {
     const int SL = L == 0 ? op.ncols : 1;
     auto& its = op.items[L];
-    if (op.x16 && L == 0) {
+    if (op.seg && L == 0) {
       for (size_t sg = 0; sg + 1 < op.seg_ptr.size(); ++sg) {
         const int32_t part = (int32_t)op.n_partials[0];
         for (int32_t x = op.seg_ptr[sg]; x < op.seg_ptr[sg + 1]; ++x) its[x].part = part;
@@ -928,7 +943,7 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
     auto& ptr = op.red_ptr[L];
     auto& idx = op.red_idx[L];
     std::vector<const Item*> heads;
-    if (op.x16 && L == 0) {
+    if (op.seg && L == 0) {
       for (size_t sg = 0; sg + 1 < op.seg_ptr.size(); ++sg) heads.push_back(&op.items[0][op.seg_ptr[sg]]);
       for (const Item& it : op.items[2]) heads.push_back(&it);
     } else {

@@ -64,13 +64,23 @@ constexpr int kZ16 = 4096;       // 16-bit projected values per low-rank item: n
 // (the last 8 values of the kernel's buffer hold the staging maximum)
 inline int z16_limit(int ncols) { return (ncols >= 32 ? 2 * kZ16 : kZ16) - 8; }
 constexpr int kMaxVariants = 64;
-constexpr int64_t kSegElems = 1 << 19;  // factor values per segment (one workgroup)
+constexpr int64_t kSegElems = 1 << 19;  // 16-bit factor values per segment (one workgroup; 1 MiB)
 inline int round8(int x) { return (x + 7) & ~7; }
 // LDS row stride of a staged 16-bit panel row of q8 values: an odd number of
 // 16-byte groups, so that the 16 rows one MFMA operand reads fall in distinct banks
 inline int ld16(int q8) { return ((q8 >> 3) & 1) ? q8 : q8 + 8; }
 // rows of a multi-item segment: its accumulators stay in registers
 inline int seg_rows_max(int ncols) { return ncols == 16 ? 512 : 256; }
+// Segment far list (matrix-core kernel) with eb bytes per stored value: 2 for
+// BF16 / FP16, 4 for FP32 (one variant, 16 columns). The FP32 form stages the
+// same LDS bytes as the 16-bit one, so half as many values.
+inline int seg_hist_limit(int ncols, int eb) { return eb == 2 ? hist16_limit(ncols) : kHist16 / 2; }
+inline int seg_z_limit(int ncols, int eb) { return eb == 2 ? z16_limit(ncols) : kZ16 / 2 - 4; }
+// LDS row stride of q8 staged values: an odd number of 16-byte groups
+inline int seg_ld(int q8, int eb) {
+  const int g = 16 / eb;
+  return ((q8 / g) & 1) ? q8 : q8 + g;
+}
 
 // ---------------------------------------------------------------- host operator
 struct PairWin {
@@ -104,6 +114,11 @@ struct HostOp {
   int ncols = 1;                      // columns of the far-list products: time_block * n_variants
   bool x16 = false;                   // far list in BF16/FP16 on the matrix cores, near list in FP32
   bool use_mfma = true;               // FP32, S = 16 far list on the matrix cores
+  // far list in the segment layout of the matrix-core kernel (16-bit builds, and
+  // FP32 builds with S = 16 unless SEAS_NO_SEG is set); near list then in its own
+  // FP32 arena
+  bool seg = false;
+  int seg_eb = 2;                     // bytes per stored value of the segment far list
   // list 2 (16-bit builds with one variant): the far lags of near-field (not
   // admissible) blocks, kept in FP32 and applied with list 0 by the FP32 matrix-core
   // pass; their partials share list 0's buffer and reduction lists
@@ -112,8 +127,8 @@ struct HostOp {
   std::vector<int32_t> lagCol;        // nlag+1 column prefix per item
   std::vector<int32_t> lagColOff[3];  // per item: offset into lagCol
   int64_t arena_elems = 0;
-  int64_t arena_near_elems = 0;       // 16-bit operators: FP32 arena of the near list
-  std::vector<int32_t> seg_ptr;       // 16-bit operators: far items of each segment (workgroup)
+  int64_t arena_near_elems = 0;       // segment operators: FP32 arena of the near list
+  std::vector<int32_t> seg_ptr;       // segment operators: far items of each segment (workgroup)
   int64_t n_partials[2] = {0, 0};
   std::vector<int32_t> red_ptr[2];    // N+1 per list
   std::vector<int32_t> red_idx[2];    // base partial index of each (receiver, item)
@@ -134,13 +149,14 @@ struct HostOp {
 };
 
 // Factor values per block, in block order, and each block's offsets in the arenas.
-// F64 / F32 operators: one arena (f64 or f32, offsets `off`). 16-bit operators: the
-// far list in f16 (bit patterns of BF16 or FP16, offsets `off`) and the near list
-// in f32 (offsets `off32`).
+// F64 / F32 operators: one arena (f64 or f32, offsets `off`). Segment operators:
+// the far list in f16 (bit patterns of BF16 or FP16) or f32s (FP32), offsets
+// `off`, and the near list in f32 (offsets `off32`).
 struct HostFactors {
   std::vector<std::vector<double>> f64;
   std::vector<std::vector<float>> f32;
   std::vector<std::vector<uint16_t>> f16;
+  std::vector<std::vector<float>> f32s;
   std::vector<int64_t> off, off32;
 };
 

@@ -1,18 +1,23 @@
-// 16-bit far-list pass (BF16 / FP16 factors on the matrix cores) and its launcher.
+// Segment far-list pass on the matrix cores (BF16 / FP16 factors, and FP32
+// factors with 16 windows) and its launcher.
 #include <hip/hip_runtime.h>
 
 #include "device_common.hpp"
 
 namespace seas {
 
-// ------------------------------------------------------------------ 16-bit matrix-core form
+// ------------------------------------------------------------------ segment matrix-core form
 // BF16 / FP16 factors (one power-of-two scale per item) times a 16-bit copy of
-// the history, v_mfma_f32_16x16x32_{bf16,f16}, FP32 accumulation. The products
-// have NC = 16 NT columns: S history windows of nv variants, column n = k nv + v.
-// Operand layout of one MFMA (16 rows x 32 inner x 16 columns):
-//   A: lane l holds A[row l%16][8 (l/16) .. +7]      (one 16-byte load)
-//   B: lane l holds B[8 (l/16) .. +7][column l%16]   (one 16-byte LDS read)
+// the history, v_mfma_f32_16x16x32_{bf16,f16}, FP32 accumulation; or FP32
+// factors times the FP32 history, eight v_mfma_f32_16x16x4_f32 per step. The
+// products have NC = 16 NT columns: S history windows of nv variants, column
+// n = k nv + v. Operand layout of one step (16 rows x 32 inner x 16 columns):
+//   A: lane l holds A[row l%16][8 (l/16) .. +7]      (one 16- or 32-byte load)
+//   B: lane l holds B[8 (l/16) .. +7][column l%16]   (one 16- or 32-byte LDS read)
 //   D: lane l, register v holds D[row 4 (l/16) + v][column l%16]
+// (FP32: MFMA s of the step takes value s of each lane's eight, so lane group g
+// feeds inner index 8 g + s to the instruction's inner slot g; every inner index
+// of the step meets its own B value once.)
 // Factors are stored with the inner index fastest and rows padded to multiples
 // of 8 values, so both operands are aligned 16-byte vectors:
 //   dense    [p][nlag * q8]   inner index e = l q8 + j (lag l, source j)
@@ -45,6 +50,16 @@ struct Mx<_Float16> {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
   }
   static __device__ __forceinline__ _Float16 cvt(float x) { return (_Float16)x; }
+};
+template <>
+struct Mx<float> {
+  typedef float v8 __attribute__((ext_vector_type(8)));
+  static __device__ __forceinline__ mfma_f4 mma(v8 a, v8 b, mfma_f4 c) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[s], c, 0, 0, 0);
+    return c;
+  }
+  static __device__ __forceinline__ float cvt(float x) { return x; }
 };
 
 __device__ __forceinline__ float wave_max(float v) {
@@ -95,14 +110,18 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
     const double* __restrict__ tail_acc, int64_t tail_len, float* __restrict__ partials) {
   typedef typename Mx<T16>::v8 v8;
   constexpr int NC = 16 * NT;
+  constexpr int EB = (int)sizeof(T16);  // bytes per stored value
+  constexpr int G = 16 / EB;            // values per 16-byte group
   constexpr int RW = NT == 1 ? 8 : 4;   // row tiles per wave held across a segment
-  constexpr int PF = 8;                 // inner steps whose global operand is loaded ahead
-  constexpr int HL = NT >= 2 ? 2 * kHist16 : kHist16;  // staged history values (hist16_limit)
+  constexpr int PF = 128 / (8 * EB);    // inner steps whose global operand is loaded ahead (128 B per lane)
+  // staged history and projected values (seg_hist_limit, seg_z_limit + 16 bytes):
+  // the same bytes for every value type
+  constexpr int HL = (NT >= 2 ? 2 * kHist16 : kHist16) * 2 / EB;
   __shared__ __attribute__((aligned(16))) T16 h[HL];
-  constexpr int ZL = NT >= 2 ? 2 * kZ16 : kZ16;  // projected values (z16_limit + 8)
+  constexpr int ZL = (NT >= 2 ? 2 * kZ16 : kZ16) * 2 / EB;
   __shared__ __attribute__((aligned(16))) T16 z[ZL];
   // the staging maximum lives in z's last 16 bytes, which projected panels never use
-  float* smax = reinterpret_cast<float*>(z + ZL - 8);
+  float* smax = reinterpret_cast<float*>(z + ZL - G);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, g = lane >> 4;
   const int nv_shift = __builtin_ctz((unsigned)nv);  // nv is a power of two
   const int x0 = seg_ptr[blockIdx.x], x1 = seg_ptr[blockIdx.x + 1];
@@ -131,7 +150,7 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
   for (int x = x0; x < x1; ++x) {
     const Item it = items[x];
     const int q = it.q, q8 = (q + 7) & ~7, nl = it.nlag;
-    const int ldh = ((q8 >> 3) & 1) ? q8 : q8 + 8;  // LDS row stride (ld16)
+    const int ldh = ((q8 / G) & 1) ? q8 : q8 + G;  // LDS row stride (seg_ld)
     const int span = it.src == 0 ? nl + S - 1 : 1;
     const int nrow = span * nv;
     const int64_t tnew = head + S - 1 - lagT[it.lag_off];
@@ -255,7 +274,7 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
     if (it.kind == 0) {
       // ---- projection Z_l = W_l H_l per lag, column tiles of 16 round robin over waves
       const int nc = it.ncol, nc8 = (nc + 7) & ~7;
-      const int ldz = ((nc8 >> 3) & 1) ? nc8 : nc8 + 8;  // LDS row stride of Z (ld16)
+      const int ldz = ((nc8 / G) & 1) ? nc8 : nc8 + G;  // LDS row stride of Z (seg_ld)
       const int32_t* cp = lagCol + lagColOff[x];
       float zs = 1.0f;
       if (SCALE) {
@@ -273,7 +292,7 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
           for (int t = 0; t < NT; ++t) tmp[t] = mfma_f4{0.0f, 0.0f, 0.0f, 0.0f};
           const int c = c0 + l16;
           const T16* wrow = base + (int64_t)min(c, ce - 1) * q8;
-          x16_kloop<T16, NT, 8>(
+          x16_kloop<T16, NT, PF>(
               0, q8, [&](int kk) { return c < ce ? *(const v8*)(wrow + kk) : v8{}; },
               [&](int kk, int t) { return *(const v8*)(h + lofs + kk + hoff[t]); }, tmp, g);
 #pragma unroll
@@ -402,6 +421,11 @@ void launch_hmat_x16(const HostOp& h, const void* items, const int32_t* seg_ptr,
                      int64_t head, const double* tail_acc, float* partials, hipStream_t s) {
   if (h.seg_ptr.size() < 2) return;
   const bool bf = h.prm.factor_dtype == SEAS_BF16;
+  if (!h.x16) {  // FP32 factors, one variant, 16 windows
+    x16_launch<float, float, false, 1>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head, tail_acc,
+                                       partials, s);
+    return;
+  }
   if (h.n_variants == 1) {
     if (bf) x16_launch<__bf16, float, false, 1>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head, tail_acc, partials, s);
     else x16_launch<_Float16, float, true, 1>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head, tail_acc, partials, s);

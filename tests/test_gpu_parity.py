@@ -265,3 +265,22 @@ def test_plain_and_blocked_orders_agree(SB):
     e = rel_err(out[1], out[0])
     print(f"[gpu] plain vs blocked S={SB} (FP32): {e:.2e}")
     assert e < 2e-5
+
+
+def test_fp32_segment_kernel_matches_item_kernel(monkeypatch):
+    # FP32 with S = 16 runs the far list in the segment layout (rows grouped per
+    # workgroup, inner index fastest); SEAS_NO_SEG builds the same operator for the
+    # one-item-per-workgroup kernel. Same factors, FP32 sums in another order.
+    faults = SI.five_fault_network(seed=3, n_elem=48)
+    p = SI.default_params(aca_tol=1e-6, factor_dtype="f32", time_block=16, leaf=12)
+    V = SI.prescribed_slip_rate(faults, 48, 5, lo_exp=-6, hi_exp=0)
+    prior = SI.prescribed_slip_rate(faults, 400, 6, lo_exp=-6, hi_exp=0)
+    fs, op_s = gpu_prescribed(faults, p, V, prior)
+    monkeypatch.setenv("SEAS_NO_SEG", "1")
+    fi, op_i = gpu_prescribed(faults, p, V, prior)
+    assert op_s.info["n_segments"] > 0 and op_i.info["n_segments"] == 0
+    assert op_s.info["stored_entries"] == op_i.info["stored_entries"]
+    e = rel_err(fs, fi)
+    print(f"[gpu] FP32 segment vs item kernel: {e:.2e} ({op_s.info['n_segments']} segments, "
+          f"{op_i.info['n_items']} items)", flush=True)
+    assert e < 1e-5

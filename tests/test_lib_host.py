@@ -68,14 +68,20 @@ def test_self_tables_match_oracle():
     assert worst < 1e-12
 
 
-@pytest.mark.parametrize("compress,S", [(0, 1), (1, 1), (1, 4), (0, 16)])
-def test_lag_matrices_match_dense_kernel(compress, S):
+@pytest.mark.parametrize("compress,S,dtype", [(0, 1, "f64"), (1, 1, "f64"), (1, 4, "f64"), (0, 16, "f64"),
+                                              (0, 16, "f32"), (1, 16, "f32")])
+def test_lag_matrices_match_dense_kernel(compress, S, dtype):
+    # FP32 with S = 16 packs its far list in the segment layout of the matrix-core
+    # kernel (inner index fastest, rows padded to 8 values, items grouped by rows)
     faults = SI.two_fault_prescribed_faults(n_elem=64, dx=200.0)
     tol = 1e-6
-    op = _op(faults, compress=compress, aca_tol=tol, eta_H=1.0, leaf=16, time_block=S)
+    op = _op(faults, compress=compress, aca_tol=tol, eta_H=1.0, leaf=16, time_block=S, factor_dtype=dtype)
     assert op.info["time_block"] == S
     if S > 1:
         assert op.info["n_items_near"] > 0
+    if dtype == "f32" and S == 16:
+        assert op.info["n_segments"] > 0
+    exact = 1e-12 if dtype == "f64" else 1e-6  # storage rounding
     geo = geometry.discretize(faults)
     dt = geometry.time_step(geo, SI.CS)
     for (a, b), (t0, t1) in op.windows().items():
@@ -89,15 +95,17 @@ def test_lag_matrices_match_dense_kernel(compress, S):
                 assert np.all(R == 0)
                 continue
             err = np.linalg.norm(R - K) / nrm
-            if compress == 0 or T == 0:
+            if T == 0:
                 assert err < 1e-12, (a, b, T, err)
+            elif compress == 0:
+                assert err < exact, (a, b, T, err)
             else:
-                assert err < 2 * tol, (a, b, T, err)
+                assert err < 2 * tol + exact, (a, b, T, err)
         # static tail stored as -G/eta
         G = I.static_dipole(geo, a, b, SI.MU)
         R = op.lag_matrix(a, b, -1, 64, 64)
         eta = SI.MU / (2 * SI.CS)
-        assert np.linalg.norm(R + G / eta) / np.linalg.norm(G / eta) < (1e-12 if compress == 0 else 2 * tol)
+        assert np.linalg.norm(R + G / eta) / np.linalg.norm(G / eta) < (exact if compress == 0 else 2 * tol + exact)
 
 
 @pytest.mark.parametrize("dtype,nv,S", [("bf16", 1, 16), ("f16", 1, 16), ("bf16", 16, 1), ("bf16", 64, 1)])
