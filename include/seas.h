@@ -121,7 +121,12 @@ typedef struct seas_state seas_state_t;
 /* Build the operator (host geometry, H-matrix partition, per-lag ACA
  * compression, self-kernel tables) and upload it to the current HIP device.
  * Blocking. Errors: INVALID_ARG for degenerate faults (length <= 0, n_elem < 2,
- * zero normal, a collocation point on another fault's element edge), OOM, HIP. */
+ * zero normal, a collocation point on another fault's element edge), OOM, HIP.
+ * F32 operators with time_block 16 store the lags >= 16 for the matrix-core
+ * segment kernel (rows grouped per workgroup); two environment variables, read
+ * here, select other kernels for diagnosis: SEAS_NO_SEG=1 the one-item-per-
+ * workgroup matrix-core kernel, SEAS_NO_MFMA=1 the vector-ALU kernel. The sums
+ * agree to FP32 rounding. */
 seas_status seas_build_operator(const seas_fault_t* faults, int32_t n_faults,
                                 const seas_params_t* params, seas_op_t** out);
 void seas_operator_destroy(seas_op_t* op);

@@ -886,6 +886,30 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
       k = e;
     }
     op.seg_ptr.push_back((int32_t)op.items[0].size());
+    // workgroups start in segment order: largest segments first, so that the
+    // small ones fill in at the end of the pass
+    {
+      const size_t ns = op.seg_ptr.size() - 1;
+      std::vector<int64_t> sz(ns, 0);
+      for (size_t g = 0; g < ns; ++g)
+        for (int32_t x = op.seg_ptr[g]; x < op.seg_ptr[g + 1]; ++x) sz[g] += vals(op.items[0][x]);
+      std::vector<size_t> so(ns);
+      std::iota(so.begin(), so.end(), 0);
+      std::stable_sort(so.begin(), so.end(), [&](size_t x, size_t y) { return sz[x] > sz[y]; });
+      std::vector<Item> its2;
+      std::vector<int32_t> co2, sp2;
+      for (size_t g : so) {
+        sp2.push_back((int32_t)its2.size());
+        for (int32_t x = op.seg_ptr[g]; x < op.seg_ptr[g + 1]; ++x) {
+          its2.push_back(op.items[0][x]);
+          co2.push_back(colOff[0][x]);
+        }
+      }
+      sp2.push_back((int32_t)its2.size());
+      op.items[0].swap(its2);
+      colOff[0].swap(co2);
+      op.seg_ptr.swap(sp2);
+    }
   }
   // invariants the segment kernel relies on (LDS panel sizes, 16-byte alignment,
   // one row range per segment, register-held rows of multi-item segments)

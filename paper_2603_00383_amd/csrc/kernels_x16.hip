@@ -77,27 +77,51 @@ __device__ __forceinline__ float pow2_at_least(float m) {
 }
 
 // tmp[t] += sum over inner k in [k0, k1) of A(k) B(k, t); k0, k1 multiples of 8.
-// PF inner steps of 32 have their operands loaded before their MFMAs.
+// 16-bit values: the global operand of PF steps of 32 is loaded before their
+// MFMAs (one round trip for most items). FP32 values: the global operand runs PF
+// steps ahead in a rolling buffer, slot s refilled for the next batch as soon as
+// its step's MFMAs are issued, so a wave keeps about PF steps of loads in flight
+// throughout (the 16-bit instances have no registers to spare for it). The LDS
+// operand is read step by step.
 template <typename T16, int NT, int PF, typename FA, typename FB>
 __device__ __forceinline__ void x16_kloop(int k0, int k1, FA A, FB B, mfma_f4 (&tmp)[NT], int g) {
   typedef typename Mx<T16>::v8 v8;
   const v8 zero = {};
-  for (int k = k0; k < k1; k += 32 * PF) {
-    // the global operand of up to PF inner steps is loaded first (one round trip
-    // for most items); the LDS operand is read step by step
+  if constexpr (sizeof(T16) == 4) {
     v8 a[PF];
 #pragma unroll
     for (int s = 0; s < PF; ++s) {
-      const int kk = k + 32 * s + 8 * g;
+      const int kk = k0 + 32 * s + 8 * g;
       a[s] = kk < k1 ? A(kk) : zero;
     }
+    for (int k = k0; k < k1; k += 32 * PF) {
 #pragma unroll
-    for (int s = 0; s < PF; ++s) {
-      if (k + 32 * s >= k1) break;  // the same for every lane of the wave
-      const int kk = k + 32 * s + 8 * g;
-      const bool ok = kk < k1;
+      for (int s = 0; s < PF; ++s) {
+        if (k + 32 * s >= k1) break;  // the same for every lane of the wave
+        const int kk = k + 32 * s + 8 * g;
+        const bool ok = kk < k1;
 #pragma unroll
-      for (int t = 0; t < NT; ++t) tmp[t] = Mx<T16>::mma(a[s], ok ? B(kk, t) : zero, tmp[t]);
+        for (int t = 0; t < NT; ++t) tmp[t] = Mx<T16>::mma(a[s], ok ? B(kk, t) : zero, tmp[t]);
+        const int kn = kk + 32 * PF;
+        a[s] = kn < k1 ? A(kn) : zero;
+      }
+    }
+  } else {
+    for (int k = k0; k < k1; k += 32 * PF) {
+      v8 a[PF];
+#pragma unroll
+      for (int s = 0; s < PF; ++s) {
+        const int kk = k + 32 * s + 8 * g;
+        a[s] = kk < k1 ? A(kk) : zero;
+      }
+#pragma unroll
+      for (int s = 0; s < PF; ++s) {
+        if (k + 32 * s >= k1) break;  // the same for every lane of the wave
+        const int kk = k + 32 * s + 8 * g;
+        const bool ok = kk < k1;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) tmp[t] = Mx<T16>::mma(a[s], ok ? B(kk, t) : zero, tmp[t]);
+      }
     }
   }
 }
@@ -113,7 +137,7 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
   constexpr int EB = (int)sizeof(T16);  // bytes per stored value
   constexpr int G = 16 / EB;            // values per 16-byte group
   constexpr int RW = NT == 1 ? 8 : 4;   // row tiles per wave held across a segment
-  constexpr int PF = 128 / (8 * EB);    // inner steps whose global operand is loaded ahead (128 B per lane)
+  constexpr int PF = EB == 4 ? 3 : 8;   // inner steps whose global operand is loaded ahead
   // staged history and projected values (seg_hist_limit, seg_z_limit + 16 bytes):
   // the same bytes for every value type
   constexpr int HL = (NT >= 2 ? 2 * kHist16 : kHist16) * 2 / EB;
