@@ -137,7 +137,7 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
   constexpr int EB = (int)sizeof(T16);  // bytes per stored value
   constexpr int G = 16 / EB;            // values per 16-byte group
   constexpr int RW = NT == 1 ? 8 : 4;   // row tiles per wave held across a segment
-  constexpr int PF = EB == 4 ? 3 : 8;   // inner steps whose global operand is loaded ahead
+  constexpr int PF = EB == 4 ? 2 : 8;   // inner steps whose global operand is loaded ahead
   // staged history and projected values (seg_hist_limit, seg_z_limit + 16 bytes):
   // the same bytes for every value type
   constexpr int HL = (NT >= 2 ? 2 * kHist16 : kHist16) * 2 / EB;
@@ -305,29 +305,79 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
         zs = 1.0f / pow2_at_least((float)q8);
         sc /= zs;
       }
-      int tile = 0;
-      for (int l = 0; l < nl; ++l) {
-        const int cb = cp[l], ce = cp[l + 1];
-        const int lofs = l * nv * ldh;
-        for (int c0 = cb; c0 < ce; c0 += 16, ++tile) {
-          if ((tile & 3) != wave) continue;
-          mfma_f4 tmp[NT];
+      // Lag l has ceil(rank_l / 16) tiles of 16 columns; the item's tiles, numbered
+      // lag after lag, are dealt round robin to the waves. A wave runs its tiles as
+      // one stream of fragments (tile, step of 32 inner indices) with the global
+      // operand of PB fragments loaded per round trip, so short tiles (one or two
+      // steps) share their load latency. The lag of a tile comes from a prefix of
+      // the tile counts of up to 63 lags held one per lane.
+      constexpr int PB = EB == 4 ? 4 : 6;
+      const int nst = (q8 + 31) >> 5;  // fragments per tile
+      mfma_f4 tmp[NT];
 #pragma unroll
-          for (int t = 0; t < NT; ++t) tmp[t] = mfma_f4{0.0f, 0.0f, 0.0f, 0.0f};
-          const int c = c0 + l16;
-          const T16* wrow = base + (int64_t)min(c, ce - 1) * q8;
-          x16_kloop<T16, NT, PF>(
-              0, q8, [&](int kk) { return c < ce ? *(const v8*)(wrow + kk) : v8{}; },
-              [&](int kk, int t) { return *(const v8*)(h + lofs + kk + hoff[t]); }, tmp, g);
+      for (int t = 0; t < NT; ++t) tmp[t] = mfma_f4{0.0f, 0.0f, 0.0f, 0.0f};
+      int tiles_before = 0;
+      for (int lc0 = 0; lc0 < nl; lc0 += 63) {
+        const int nlc = min(63, nl - lc0);
+        const int cpa = lane <= nlc ? cp[lc0 + lane] : 0;  // first column of lag lc0 + lane
+        const int cpb = __shfl_down(cpa, 1, 64);            // its end (lanes < nlc)
+        const int nt = lane < nlc ? (cpb - cpa + 15) >> 4 : 0;
+        int incl = nt;
 #pragma unroll
-          for (int t = 0; t < NT; ++t) {
+        for (int o = 1; o < 64; o <<= 1) {
+          const int y = __shfl_up(incl, o, 64);
+          if (lane >= o) incl += y;
+        }
+        const int excl = incl - nt;  // tiles of the chunk before lag lc0 + lane
+        const int T = __shfl(incl, 63, 64);
+        const int first = (wave - tiles_before) & 3;  // this wave's first tile of the chunk
+        const int F = (T > first ? (T - first + 3) / 4 : 0) * nst;
+        for (int f0 = 0; f0 < F; f0 += PB) {
+          v8 a[PB];
+          int dl[PB], dc0[PB], dce[PB];  // tile of each fragment: lag in the chunk, columns
+          int tl = f0 / nst, st = f0 - tl * nst;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const int cc = c0 + 4 * g + v;
-              if (cc < ce) z[(t * 16 + l16) * ldz + cc] = Mx<T16>::cvt(tmp[t][v] * zs);
+          for (int b = 0; b < PB; ++b) {
+            const int tt = first + 4 * tl;
+            const int lr = __popcll(__ballot(lane < nlc && excl <= tt)) - 1;
+            dl[b] = lr;
+            dc0[b] = __builtin_amdgcn_readlane(cpa, lr) + 16 * (tt - __builtin_amdgcn_readlane(excl, lr));
+            dce[b] = __builtin_amdgcn_readlane(cpb, lr);
+            const int c = dc0[b] + l16, kk = 32 * st + 8 * g;
+            a[b] = (f0 + b < F && c < dce[b] && kk < q8) ? *(const v8*)(base + (int64_t)c * q8 + kk) : v8{};
+            if (++st == nst) {
+              st = 0;
+              ++tl;
             }
           }
+          st = f0 - (f0 / nst) * nst;
+#pragma unroll
+          for (int b = 0; b < PB; ++b) {
+            if (f0 + b >= F) break;  // the same for every lane of the wave
+            if (st == 0) {
+#pragma unroll
+              for (int t = 0; t < NT; ++t) tmp[t] = mfma_f4{0.0f, 0.0f, 0.0f, 0.0f};
+            }
+            const int kk = 32 * st + 8 * g;
+            const bool ok = kk < q8;
+            const int lofs = (lc0 + dl[b]) * nv * ldh;
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+              tmp[t] = Mx<T16>::mma(a[b], ok ? *(const v8*)(h + lofs + kk + hoff[t]) : v8{}, tmp[t]);
+            if (st == nst - 1) {
+#pragma unroll
+              for (int t = 0; t < NT; ++t) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                  const int cc = dc0[b] + 4 * g + v;
+                  if (cc < dce[b]) z[(t * 16 + l16) * ldz + cc] = Mx<T16>::cvt(tmp[t][v] * zs);
+                }
+              }
+            }
+            if (++st == nst) st = 0;
+          }
         }
+        tiles_before += T;
       }
       for (int e = tid; e < NC * (nc8 - nc); e += kItemThreads) {  // zero pad columns
         const int n = e / (nc8 - nc), c = nc + e - n * (nc8 - nc);
@@ -348,8 +398,17 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
     const int lag_stride = nv * ldh - q8;  // h index of (lag l, source j): l nv ldh + j = kk + l lag_stride
     for (int u = 0; u < my_units; ++u) {
       const int id = wave + 4 * u, rt = id / KS, ks = id - rt * KS;
-      const int k0 = ((int)((int64_t)(E / 8) * ks / KS)) * 8;
-      const int k1 = ((int)((int64_t)(E / 8) * (ks + 1) / KS)) * 8;
+      int k0 = ((int)((int64_t)(E / 8) * ks / KS)) * 8;
+      int k1 = ((int)((int64_t)(E / 8) * (ks + 1) / KS)) * 8;
+      if (it.kind == 0 && KS > 1) {
+        // low rank: the inner range (ncol8) is short, so a row tile is not split;
+        // its whole range goes to one of its KS units, chosen so that tiles
+        // rt = 0, 1, 2, 3 land on waves 0, 2, 1, 3 (KS = 2) or 0, 1, 2, 3 (KS = 4)
+        const int pick = KS == 4 ? (rt & 3) : ((rt & 3) >> 1);
+        if (ks != pick) continue;  // the same for every lane of the wave
+        k0 = 0;
+        k1 = E;
+      }
       const int i = rt * 16 + l16;
       const T16* arow = M + (int64_t)min(i, p - 1) * stride;
       mfma_f4 tmp[NT];
