@@ -708,8 +708,9 @@ seas_status seas_state_create(seas_op_t* op, int32_t n_variants, const seas_fric
     st->ring64 = (double*)A((size_t)h.ring_len * vb, true);
     st->ringop = op->ring_bytes == 8 ? (void*)st->ring64 : A((size_t)h.ring_len * N * op->ring_bytes, true);
     st->tail_acc = (double*)A((size_t)h.tail_len * 8 * nv, true);
-    // FP64 slots even where the far pass writes FP32: the plain form of an FP32
-    // build (seas_state_set_time_block(1)) writes FP64 partials into the same buffer
+    // item kernels: FP64 slots even where the far pass writes FP32, since the plain
+    // form of an FP32 build (seas_state_set_time_block(1)) writes FP64 partials into
+    // the same buffer; the segment kernel writes FP32 partials in either form
     st->partials_far = A((size_t)h.n_partials[0] * (h.seg ? 4 : 8), false);
     st->partials_near = (double*)A((size_t)h.n_partials[1] * 8, false);
     st->f_far = (double*)A((size_t)h.time_block * vb, true);
