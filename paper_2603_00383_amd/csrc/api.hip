@@ -127,7 +127,15 @@ struct seas_state {
   bool timing = false;
   std::vector<hipEvent_t> ev;  // start/stop pairs
   size_t n_ev = 0;             // pairs recorded since the last read
+  // second stream of a step (default priority): the self history and the
+  // predictor transform run there beside the interaction history part
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   ~seas_state() {
+    if (side) (void)hipStreamSynchronize(side);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side) (void)hipStreamDestroy(side);
     for (auto e : ev) (void)hipEventDestroy(e);
     for (auto& b : owned) (void)hipFree(b.p);
   }
@@ -240,15 +248,28 @@ void do_steps(seas_op* op, seas_state* st, int n_steps, hipStream_t s) {
   const HostOp& h = op->h;
   const int nm = h.n_modes, nv = st->nv;
   const int64_t dl = h.self_ring_len;
+  if (n_steps > 0 && !st->side) {
+    HIPCHK(hipStreamCreateWithFlags(&st->side, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&st->ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&st->ev_join, hipEventDisableTiming));
+  }
   for (int it = 0; it < n_steps; ++it) {
     const int64_t n = st->step;
+    // The self history and the predictor transform read only what the previous
+    // step left (coefficient rings, slip, rate) and write Fh and F, which the
+    // interaction history part neither reads nor writes: they run on the side
+    // stream from the step's start and rejoin before the predictor stage.
+    HIPCHK(hipEventRecord(st->ev_fork, s));
+    HIPCHK(hipStreamWaitEvent(st->side, st->ev_fork, 0));
+    launch_self_hist(nm, nv, dl, op->modes, op->tab, st->dring, n + 1, st->Fh, st->side);
+    launch_dft(nm, nv, h.N, dl, op->modes, op->sf, st->delta, st->V, h.dt, op->tw, op->tab, st->Fh, st->F,
+               st->dring, 0, 0, 0, st->side);
+    HIPCHK(hipEventRecord(st->ev_join, st->side));
     eval_history(op, st, n, s);
-    launch_self_hist(nm, nv, dl, op->modes, op->tab, st->dring, n + 1, st->Fh, s);
+    HIPCHK(hipStreamWaitEvent(s, st->ev_join, 0));
     StepArgs<TF> a = make_args<TF>(op, st);
     a.t_next = (double)(n + 1) * h.dt;
     a.time_new = n + 1;
-    launch_dft(nm, nv, h.N, dl, op->modes, op->sf, st->delta, st->V, h.dt, op->tw, op->tab, st->Fh, st->F,
-               st->dring, 0, 0, 0, s);
     launch_stage<TF>(a, 0, s);
     launch_dft(nm, nv, h.N, dl, op->modes, op->sf, st->delta, st->Vbar, h.dt, op->tw, op->tab, st->Fh, st->F,
                st->dring, 1, n + 1, n + 1, s);
