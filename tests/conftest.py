@@ -19,3 +19,29 @@ def _oracle_helper():
     from oracle import selfterm
     if not os.path.exists(os.path.join(ROOT, "oracle", "_selfkernel.so")):
         selfterm.build_helper()
+
+
+@pytest.fixture(scope="session")
+def loud(pytestconfig):
+    """Context manager for long host builds: the library reports its progress
+    (SEAS_VERBOSE) and pytest's output capture is suspended meanwhile, so a run
+    shows a line every few seconds instead of going quiet for minutes."""
+    import contextlib
+    capman = pytestconfig.pluginmanager.getplugin("capturemanager")
+
+    @contextlib.contextmanager
+    def cm(msg=None):
+        prev = os.environ.get("SEAS_VERBOSE")
+        os.environ["SEAS_VERBOSE"] = "1"
+        ctx = capman.global_and_fixture_disabled() if capman is not None else contextlib.nullcontext()
+        try:
+            with ctx:
+                if msg:
+                    print(msg, flush=True)
+                yield
+        finally:
+            if prev is None:
+                os.environ.pop("SEAS_VERBOSE", None)
+            else:
+                os.environ["SEAS_VERBOSE"] = prev
+    return cm

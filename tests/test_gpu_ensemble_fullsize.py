@@ -24,14 +24,14 @@ TOL = {"bf16": 8e-3, "f16": 2e-3}
 
 
 @pytest.mark.parametrize("dtype", ["bf16"])
-def test_ensemble_fullsize_history_part(dtype):
+def test_ensemble_fullsize_history_part(dtype, loud):
     if not torch.cuda.is_available():
         pytest.skip("no HIP device")
     nv, H = 64, 1200
     faults = SI.ensemble_network(seed=0)
     params = SI.default_params(factor_dtype=dtype, aca_tol=1e-6, eta_H=2.0, leaf=50, time_block=1, n_variants=nv)
-    print(f"[gpu] building the ensemble operator ({dtype})", flush=True)
-    op = P.Operator(faults, params)
+    with loud(f"[gpu] building the ensemble operator ({dtype})"):
+        op = P.Operator(faults, params)
     N = op.N
     fric = SI.rate_state_fields(faults)
     ini = SI.near_nucleation_state(faults, fric, seed=0, bump_amp=0.05)

@@ -26,13 +26,13 @@ TOL = {"f32": 1e-4, "f16": 1e-4, "bf16": 2e-3}
 
 
 @pytest.fixture(scope="module", params=["f32", "f16", "bf16"])
-def fullsize(request):
+def fullsize(request, loud):
     if not torch.cuda.is_available():
         pytest.skip("no HIP device")
     faults = SI.five_fault_network(seed=0)
     params = SI.default_params(factor_dtype=request.param, aca_tol=1e-6, eta_H=2.0, leaf=50, time_block=16)
-    print("[gpu] building the five-fault operator", flush=True)
-    op = P.Operator(faults, params)
+    with loud(f"[gpu] building the five-fault operator ({request.param})"):
+        op = P.Operator(faults, params)
     prior = SI.saturated_history(faults, op.info["max_lag"] + 2, 0)
     print(f"[gpu] built {request.param}: items={op.info['n_items']} max_lag={op.info['max_lag']}", flush=True)
     oracle = OS.Problem(faults, params, dense=False)
