@@ -202,6 +202,9 @@ seas_status seas_state_create(seas_op_t* op, int32_t n_variants, const seas_fric
                               const double* V_init, const double* theta_init,
                               const double* tau0, const double* tau0_rate,
                               const double* delta_init, void* stream, seas_state_t** out);
+/* Free the state's device memory and its second stream (after waiting for that
+ * stream). Work still queued on the caller's streams that uses the state must
+ * have finished: synchronise them first. NULL is ignored. */
 void seas_state_destroy(seas_state_t* st);
 
 /* Prior slip-rate history V[m][n_variants][N] for the n_hist steps before t = 0
@@ -234,7 +237,11 @@ seas_status seas_eval_prescribed(seas_op_t* op, seas_state_t* st, const double* 
                                  int32_t n_steps, double* f_dev, void* stream);
 
 /* Advance n_steps predictor-corrector steps (Section 2.4). Enqueue only; the
- * Newton convergence flag is read by seas_state_check. */
+ * Newton convergence flag is read by seas_state_check. Part of each step (the
+ * self history and the predictor transform) runs on a second stream the state
+ * creates on first use (default priority), forked from and joined back into
+ * `stream` by events within the step: when the call returns, all of its work is
+ * ordered on `stream` like the rest of the library's calls. */
 seas_status seas_step(seas_op_t* op, seas_state_t* st, int32_t n_steps, void* stream);
 
 /* Synchronise `stream` and report NOT_CONVERGED if any Newton solve since the
