@@ -108,6 +108,72 @@ def cpu_baseline(faults, params, prior, budget_s=12.0):
                        f"saturated step of the same workload; {t_int + t_self:.1f} s of CPU work")}
 
 
+def run_precision(args):
+    """Trajectory error of the reduced-precision forms: the five-fault SEAS step loop
+    (5 x 600 elements, time block 16) from one near-nucleation state with no prior
+    slip, stepped 20,000 steps with FP64, FP32, FP16 and BF16 factors; slip, slip rate
+    and stress (f_self + f_int) compared with the FP64 run at 1k, 5k and 20k steps.
+    The FP64 path is the one the parity tests hold to the oracle at 1e-10."""
+    import numpy as np
+    import torch
+
+    import paper_2603_00383_amd as P
+    import seas_inputs as SI
+
+    marks = (1000, 5000, 20000)
+    faults = SI.five_fault_network(seed=args.seed)
+    fric = SI.rate_state_fields(faults)
+    ini = SI.near_nucleation_state(faults, fric, seed=args.seed, bump_amp=0.05)
+    os.environ.setdefault("SEAS_VERBOSE", "1")
+    s = torch.cuda.current_stream().cuda_stream
+    snaps, timing, failed = {}, {}, {}
+    for d in ("f64", "f32", "f16", "bf16"):
+        params = SI.default_params(factor_dtype=d, aca_tol=args.aca, eta_H=2.0, leaf=50, time_block=16)
+        print(f"[bench] building the {d} operator", file=sys.stderr, flush=True)
+        op = P.Operator(faults, params)
+        st = P.State(op, fric, ini["V"], ini["theta"], ini["tau0"], ini["tau0_rate"], stream=s)
+        snaps[d] = {}
+        done, t_run = 0, 0.0
+        try:
+            for m in marks:
+                while done < m:
+                    k = min(1000, m - done)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    st.step(k, stream=s)
+                    st.check(stream=s)
+                    t_run += time.perf_counter() - t0
+                    done += k
+                    print(f"[bench] {d}: {done} steps", file=sys.stderr, flush=True)
+                snaps[d][m] = {"delta": st.read("delta", stream=s), "V": st.read("V", stream=s),
+                               "stress": st.read("f_self", stream=s) + st.read("f_int", stream=s)}
+        except RuntimeError as e:
+            failed[d] = f"step {done}: {e}"
+            print(f"[bench] {d} stopped: {failed[d]}", file=sys.stderr, flush=True)
+        timing[d] = t_run / max(done, 1) * 1e3
+        st.close()
+        op.close()
+    ref = snaps["f64"]
+    errors = {}
+    for d in ("f32", "f16", "bf16"):
+        errors[d] = {}
+        for m in marks:
+            if m not in snaps[d] or m not in ref:
+                continue
+            e = {}
+            for k in ("delta", "V", "stress"):
+                e[k] = float(np.abs(snaps[d][m][k] - ref[m][k]).max() / np.abs(ref[m][k]).max())
+            errors[d][str(m)] = e
+    out = {"metric": "slip, slip-rate and stress error of the reduced-precision forms vs the FP64 path",
+           "data": "synthetic",
+           "config": {"workload": "five-fault SEAS step loop, 5 x 600 elements (N=3000, dx=50 m), time block "
+                                  "16, ACA 1e-6, eta_H 2, leaf 50, near-nucleation state, no prior slip",
+                      "seed": args.seed, "steps": list(marks)},
+           "errors": errors, "ms_per_step": timing, "failed": failed,
+           "note": "max |x - x_f64| / max |x_f64| over all elements at each mark; stress = f_self + f_int"}
+    print(json.dumps(out), flush=True)
+
+
 def run_ensemble(args):
     """Ensemble throughput: one geometry, many friction variants stepped together;
     the interaction sums of all variants are one 16-bit product per work item."""
@@ -269,9 +335,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="seas", choices=["seas", "ensemble", "serving"],
+    ap.add_argument("--workload", default="seas", choices=["seas", "ensemble", "serving", "precision"],
                     help="seas: five-fault step loop (one variant); ensemble: eight faults x 750 elements, "
-                         "64 friction variants in one launch (BF16)")
+                         "64 friction variants in one launch (BF16); precision: 20,000-step trajectories of "
+                         "the reduced-precision forms against FP64")
     ap.add_argument("--dtype", default=None, choices=["f32", "f64", "bf16", "f16"],
                     help="factor dtype (default f32; bf16 for the ensemble)")
     ap.add_argument("--variants", type=int, default=64, help="ensemble: friction variants (16, 32 or 64)")
@@ -320,6 +387,8 @@ def main():
         return run_ensemble(args)
     if args.workload == "serving":
         return run_serving(args)
+    if args.workload == "precision":
+        return run_precision(args)
     if args.dtype is None:
         args.dtype = "f32"
     faults = SI.five_fault_network(seed=args.seed)
