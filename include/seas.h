@@ -316,7 +316,13 @@ typedef struct seas_server seas_server_t;
 seas_status seas_server_create(seas_op_t* const* ops, int32_t n_ops, const seas_request_t* idle,
                                size_t device_budget, int32_t chunk_steps, seas_server_t** out);
 /* Play a trace of n_reqs requests in real time and return when all are done.
- * Blocking; fills admit_s, finish_s and status of every request. */
+ * Blocking; fills admit_s, finish_s and status of every request. A state's
+ * convergence flag covers all its slots: when a chunk of a pool reports an
+ * error (a Newton failure in any slot), every request active in that pool ends
+ * with that status, its outputs hold the state at the end of that chunk, and its
+ * slot returns to the idle window. Errors of the call itself: INVALID_ARG (a
+ * request with a bad pool index or n_steps < 1), HIP, INTERNAL (requests left
+ * that no pool can admit). */
 seas_status seas_server_run(seas_server_t* sv, seas_request_t* reqs, int32_t n_reqs);
 void seas_server_destroy(seas_server_t* sv);
 
