@@ -14,7 +14,6 @@ elastodynamic simulation of earthquakes and aseismic slip on fault networks"):
                     (Section 2.2, Section 2.4)
 * ``hpartition``    per-fault binary cluster trees, bounding circles, admissibility,
                     dual-tree traversal (Section 2.3.2, H-matrix paragraphs)
-* ``compress``      truncated SVD of admissible blocks (Section 2.3.2)
 * ``seas``          prescribed-history evaluation and the predictor-corrector step
                     (Section 2.4)
 

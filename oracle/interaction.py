@@ -138,20 +138,26 @@ def pair_window_lags(geo, a, b, cs, dt, eta_tmin, eta_tmax):
 # ----------------------------------------------------------------------------
 # Static dipole stress (late-time limit of -mu/(2cs) K^T / dt)
 # ----------------------------------------------------------------------------
-def static_dipole(geo, a, b, mu):
-    """Stress at receivers of fault a per unit slip on each element of fault b:
+def static_from_offsets(r1p, r2p, n1p, n2p, ds, mu):
+    """Static stress per unit slip of a source element seen at offsets (r1', r2')
+    in its frame, receiver normal (n1', n2') in the same frame:
 
     sigma_31 = (mu/2pi) r2' (1/r_+^2 - 1/r_-^2)
     sigma_32 = -(mu/2pi) (r1_+/r_+^2 - r1_-/r_-^2),    r1_+- = r1' +- ds/2,
     G = n1' sigma_31 + n2' sigma_32."""
-    r1p, r2p, n1p, n2p = local_offsets(geo, a, b)
-    ds = geo[b].dx
     rp1, rm1 = r1p + 0.5 * ds, r1p - 0.5 * ds
     rp2 = rp1 * rp1 + r2p * r2p
     rm2 = rm1 * rm1 + r2p * r2p
     s31 = mu / (2 * math.pi) * r2p * (1.0 / rp2 - 1.0 / rm2)
     s32 = -mu / (2 * math.pi) * (rp1 / rp2 - rm1 / rm2)
     return n1p * s31 + n2p * s32
+
+
+def static_dipole(geo, a, b, mu):
+    """Stress at receivers of fault a per unit slip on each element of fault b
+    (two screw dislocations at the element's ends), p x q."""
+    r1p, r2p, n1p, n2p = local_offsets(geo, a, b)
+    return static_from_offsets(r1p, r2p, n1p, n2p, geo[b].dx, mu)
 
 
 # ----------------------------------------------------------------------------
@@ -271,11 +277,7 @@ def stress_rows(geo, rows, Vh, head, first, mu, cs, dt, eta_tmin=0.01, eta_tmax=
                 last = head - T1 - 1
                 if last >= first:
                     E = dt * np.sum(Vh[: last - first + 1, off[b]:off[b + 1]], axis=0)
-                    ds = B.dx
-                    rp1, rm1 = r1p + 0.5 * ds, r1p - 0.5 * ds
-                    rp2, rm2 = rp1 * rp1 + r2p * r2p, rm1 * rm1 + r2p * r2p
-                    G = (n1p * mu / (2 * math.pi) * r2p * (1 / rp2 - 1 / rm2)
-                         - n2p * mu / (2 * math.pi) * (rp1 / rp2 - rm1 / rm2))
+                    G = static_from_offsets(r1p, r2p, n1p, n2p, B.dx, mu)
                     acc += float(G @ E)
         out[k] = acc
     return out

@@ -1,0 +1,120 @@
+"""Pins of the oracle's row-sampled sums and of the static tail's window edge (CPU only).
+
+``interaction.stress_rows`` and ``seas.prescribed_rows`` are the references of
+every full-size GPU test (the dense stacks do not fit there); here they are held
+to the dense evaluation (``DenseInteraction.stress`` / ``seas.prescribed``) on a
+ragged three-fault network with a prior history long enough for slip to leave
+every pair window, with and without the static tail.
+
+The impulse test pins the window edge of the static tail (Section 2.3.2,
+truncation of the elastodynamic time window; the tail itself is the reading
+that slip older than a pair's window keeps its static stress): a unit slip-rate
+impulse of one step on one source element must be seen through the dynamic
+kernel for lags T_init..T_end, and from lag T_end + 1 on as exactly dt times the
+static dislocation stress, with no lag counted twice or dropped.
+"""
+import numpy as np
+import pytest
+
+import seas_inputs as SI
+from oracle import geometry, interaction as I, seas as OS
+
+RAG = [SI.fault(0, 0, 5.0, 1300.0, 13), SI.fault(300.0, 900.0, 70.0, 2900.0, 29),
+       SI.fault(-1500.0, 2200.0, 140.0, 2000.0, 40)]
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.fixture(scope="module")
+def rag():
+    p = SI.default_params(eta_H=1.5, leaf=5)
+    prob = OS.Problem(RAG, p)
+    prior = SI.prescribed_slip_rate(RAG, 90, 8, lo_exp=-6, hi_exp=0)
+    V = SI.prescribed_slip_rate(RAG, 140, 7, lo_exp=-6, hi_exp=0)
+    return prob, prior, V
+
+
+@pytest.mark.parametrize("tail", [1, 0])
+@pytest.mark.parametrize("min_lag", [0, 1])
+def test_stress_rows_equals_dense_sum(rag, tail, min_lag):
+    prob, prior, V = rag
+    Vall = np.concatenate([prior, V])
+    first = -len(prior)
+    rows = list(range(prob.N))
+    # slip has left some pair windows at the later heads (and not at the first)
+    assert min(P["T1"] for P in prob.inter.pairs.values()) < 139 + len(prior) - 1
+    for head in (-40, 5, 77, 139):
+        exp = prob.inter.expired_slip(Vall, head, first, prob.dt) if tail else None
+        ref = prob.inter.stress(Vall, head, first, min_lag=min_lag, expired=exp)
+        got = I.stress_rows(prob.geo, rows, Vall, head, first, prob.mu, prob.cs, prob.dt,
+                            min_lag=min_lag, with_tail=bool(tail))
+        assert _rel(got, ref) < 1e-13, (head, _rel(got, ref))
+        if tail and head == 139:
+            # the static tail is a visible part of the sum at these heads
+            plain = prob.inter.stress(Vall, head, first, min_lag=min_lag)
+            assert _rel(plain, ref) > 1e-3
+
+
+def test_prescribed_rows_equals_prescribed(rag):
+    prob, prior, V = rag
+    n_steps = 60
+    ref = OS.prescribed(prob, V[:n_steps], prior_V=prior)
+    Vall = np.concatenate([prior, V[:n_steps]])
+    rows = [0, 6, 12, 13, 27, 41, 42, 60, 81]
+    for n in (1, 2, 17, 60):
+        got = OS.prescribed_rows(prob, Vall, -len(prior), n, rows)
+        assert _rel(got, ref[n - 1][rows]) < 1e-12, n
+
+
+@pytest.mark.parametrize("m0,first", [(0, 0), (-5, -12)])
+def test_tail_impulse_hands_over_at_window_edge(m0, first):
+    # two faults of the prescribed-history geometry (coarse mesh), every pair
+    geo_f = SI.two_fault_prescribed_faults(n_elem=12, dx=400.0)
+    p = SI.default_params()
+    prob = OS.Problem(geo_f, p)
+    eta = prob.mu / (2 * prob.cs)
+    off = prob.off
+    for (a, b), P in prob.inter.pairs.items():
+        T0, T1 = P["T0"], P["T1"]
+        G = I.static_dipole(prob.geo, a, b, prob.mu)
+        for jj in (0, 7):
+            j = off[b] + jj
+            last_head = m0 + T1 + 6
+            Vh = np.zeros((last_head - first + 1, prob.N))
+            Vh[m0 - first, j] = 1.0
+            ra = slice(off[a], off[a + 1])
+            for head in range(m0, last_head + 1):
+                T = head - m0
+                exp = prob.inter.expired_slip(Vh, head, first, prob.dt)
+                f = prob.inter.stress(Vh, head, first, expired=exp)[ra]
+                if T < T0:
+                    assert np.all(f == 0.0), (a, b, T)
+                elif T <= T1:
+                    K = I.pair_kernel(prob.geo, a, b, T, prob.dt, prob.cs)[:, jj]
+                    assert np.allclose(f, -eta * K, rtol=1e-14, atol=0.0), (a, b, T)
+                    assert np.all(exp[(a, b)] == 0.0)
+                else:
+                    # exactly dt of slip has expired, once: the static stress of a
+                    # dislocation of that size
+                    assert exp[(a, b)][jj] == prob.dt and np.count_nonzero(exp[(a, b)]) == 1
+                    assert np.allclose(f, G[:, jj] * prob.dt, rtol=1e-14, atol=0.0), (a, b, T)
+            # the row-sampled sum agrees at the two heads around the edge
+            for head in (m0 + T1, m0 + T1 + 1):
+                exp = prob.inter.expired_slip(Vh, head, first, prob.dt)
+                ref = prob.inter.stress(Vh, head, first, expired=exp)[ra]
+                got = I.stress_rows(prob.geo, list(range(off[a], off[a + 1])), Vh, head, first,
+                                    prob.mu, prob.cs, prob.dt)
+                assert np.allclose(got, ref, rtol=1e-13, atol=1e-30 + 1e-13 * np.abs(ref).max())
+
+
+def test_static_tail_is_the_late_kernel_limit_at_every_receiver():
+    # The tail's stress per unit expired slip is the limit of the dynamic kernel
+    # per unit time: -mu/(2cs) K^T / dt -> G, the O(T^-2) approach of the 2-D kernel.
+    g = geometry.discretize(RAG)
+    dt = geometry.time_step(g, SI.CS)
+    for a, b in ((0, 1), (2, 0), (1, 2)):
+        G = I.static_dipole(g, a, b, SI.MU)
+        K = I.pair_kernel(g, a, b, 20000, dt, SI.CS)
+        assert _rel(-SI.MU / (2 * SI.CS) * K / dt, G) < 1e-3
