@@ -118,9 +118,19 @@ typedef struct {
 typedef struct seas_op seas_op_t;
 typedef struct seas_state seas_state_t;
 
-/* Build the operator (host geometry, H-matrix partition, per-lag ACA
- * compression, self-kernel tables) and upload it to the current HIP device.
- * Blocking. Errors: INVALID_ARG for degenerate faults (length <= 0, n_elem < 2,
+/* Build the operator and upload it to the current HIP device: fault geometry
+ * and the time step dt = beta min(dx) / cs (Section 2.3.1, Section 3.1), the
+ * causality window [T_init, T_end] of every ordered fault pair (Section 2.3.2,
+ * eq. "early_time" and the truncation paragraph), the kernel entries of eq.
+ * "kernel_interactions" from the closed-form primitives of eq. "primitives",
+ * the selective H-matrix of each pair (one binary cluster tree per fault,
+ * bounding circles, eq. "admissibility_condition", dual-tree traversal),
+ * low-rank compression of admissible blocks lag by lag (ACA in place of the
+ * paper's truncated SVD, which Section 4.3 lists as an improvement), and the
+ * self-kernel tables K_n^T with the mode windows W_n of eqs.
+ * "non_replicant_kernel", "funcational_discretized_form" and
+ * "mode_dependent_truncation". Blocking. The operator is owned by the caller
+ * until seas_operator_destroy. Errors: INVALID_ARG for degenerate faults (length <= 0, n_elem < 2,
  * zero normal, a collocation point on another fault's element edge), OOM, HIP.
  * F32 operators with time_block 16 store the lags >= 16 for the matrix-core
  * segment kernel (rows grouped per workgroup); two environment variables, read
@@ -192,9 +202,11 @@ typedef struct {
 /* Device bytes a state of `n_variants` variants needs (admission control). */
 size_t seas_state_bytes(const seas_op_t* op, int32_t n_variants);
 
-/* Create a state at t = 0: slip rate V_init, state theta_init, background
- * shear stress tau0 and its rate (may be NULL), slip delta_init (may be NULL
- * = 0). Host arrays of n_variants x N (variant-major). Histories before t = 0
+/* Create a state at t = 0 (the unknowns of Section 2.4: slip, slip rate,
+ * state variable, with the background stress tau0 of eq. "force_balance"):
+ * slip rate V_init, state theta_init, background shear stress tau0 and its
+ * rate (may be NULL; tectonic loading as in Section 3.2), slip delta_init (may
+ * be NULL = 0). Host arrays of n_variants x N (variant-major). Histories before t = 0
  * are zero (no prior slip) unless seas_state_load_history is called next.
  * n_variants must equal the operator's (seas_op_info_t.n_variants); every
  * variant evolves on its own, and the variants share the operator's factors. */
@@ -226,7 +238,11 @@ seas_status seas_state_load_history(seas_state_t* st, const double* V_hist, int3
 seas_status seas_state_reset_variant(seas_state_t* st, int32_t variant, const seas_friction_t* fric,
                                      const double* V_init, const double* theta_init, const double* tau0,
                                      const double* tau0_rate, const double* delta_init, void* stream);
-/* Stress evaluation of a prescribed slip-rate history (no friction): for
+/* Stress evaluation of a prescribed slip-rate history (no friction): the
+ * history functional f of eq. "superimposition2", split as in eq.
+ * "traction_decomposition" into the spectral self term of each fault (eq.
+ * "funcational_discretized_form") and the fault-to-fault sum of eq.
+ * "fault-to-fault_interactions_discretized". For
  * n = 1..n_steps, with V^m = V_dev[m][variant][element] (device, FP64,
  * n_steps x n_variants x N):
  *   delta^n = delta^{n-1} + dt V^{n-1}
@@ -236,17 +252,34 @@ seas_status seas_state_reset_variant(seas_state_t* st, int32_t variant, const se
 seas_status seas_eval_prescribed(seas_op_t* op, seas_state_t* st, const double* V_dev,
                                  int32_t n_steps, double* f_dev, void* stream);
 
-/* Advance n_steps predictor-corrector steps (Section 2.4). Enqueue only; the
- * Newton convergence flag is read by seas_state_check. Part of each step (the
+/* Advance n_steps predictor-corrector steps (Section 2.4, steps 2 and 3: the
+ * predictor, the Newton solve of the force balance with the friction of eq.
+ * "R&S_friction", the state law of eq. "state_evolution_law", the corrector
+ * with averaged rates, and the history append). Enqueue only.
+ * Newton failure (a solve that needs more than 50 iterations): the variant's
+ * commits stop at the failing step, so its slip, rate, state, histories and
+ * expired-slip accumulators stay at its last good step, and the rest of the
+ * enqueued steps leave it untouched; the other variants keep stepping. The
+ * failure is reported by seas_state_check / seas_state_variant_status. Part of each step (the
  * self history and the predictor transform) runs on a second stream the state
  * creates on first use (default priority), forked from and joined back into
  * `stream` by events within the step: when the call returns, all of its work is
  * ordered on `stream` like the rest of the library's calls. */
 seas_status seas_step(seas_op_t* op, seas_state_t* st, int32_t n_steps, void* stream);
 
-/* Synchronise `stream` and report NOT_CONVERGED if any Newton solve since the
- * last check exceeded 50 iterations (the flag is then cleared). */
+/* Synchronise `stream` and report NOT_CONVERGED if a variant's Newton solve
+ * failed (message: the variants and the steps they are held at). With one
+ * variant the state is then at its last good step: the step index goes back to
+ * it, the flag is cleared and stepping may resume from there (e.g. after
+ * seas_write_state). With several variants the variants share one clock, so a
+ * failed variant stays held (its histories fall behind the others') and keeps
+ * being reported until seas_state_reset_variant starts a new window in its
+ * slot. */
 seas_status seas_state_check(seas_state_t* st, void* stream);
+/* Per-variant convergence (synchronises `stream`): failed[v] = 1 if variant v
+ * is held after a Newton failure, good_step[v] = the step index of its last
+ * committed step (either pointer may be NULL; host arrays of n_variants). */
+seas_status seas_state_variant_status(const seas_state_t* st, int32_t* failed, int64_t* good_step, void* stream);
 
 #define SEAS_FIELD_V 0          /* slip rate at the current step */
 #define SEAS_FIELD_THETA 1
@@ -258,9 +291,23 @@ seas_status seas_state_check(seas_state_t* st, void* stream);
 #define SEAS_FIELD_TAU0 7
 
 /* Copy the N values of a field of one variant to dst (device if dst_is_device,
- * else host; a host copy synchronises the stream). */
+ * else host; a host copy synchronises the stream): the unknowns of the step of
+ * Section 2.4 (slip, slip rate, state, state rate) and the parts of the
+ * traction of eqs. "superimposition2" and "traction_decomposition".
+ * count must equal N (INVALID_ARG otherwise). */
 seas_status seas_read_state(const seas_state_t* st, int32_t field, int32_t variant, double* dst,
                             size_t count, int32_t dst_is_device, void* stream);
+/* Overwrite a field of one variant at the current step, e.g. to resume from
+ * values saved elsewhere or to continue after a Newton failure (Section 2.4
+ * unknowns): SEAS_FIELD_V (> 0; also the newest row of the rate history, which
+ * the next steps read at lag 1), SEAS_FIELD_THETA (> 0), SEAS_FIELD_DELTA (also
+ * the newest row of slip coefficients of the self term) or SEAS_FIELD_TAU0;
+ * writing V or THETA recomputes the state rate. src holds N values (device if
+ * src_is_device, else host); count must equal N. Synchronises the stream.
+ * Errors: INVALID_ARG (other fields, bad count or values), MISMATCH (a
+ * prescribed-history state). */
+seas_status seas_write_state(seas_state_t* st, int32_t field, int32_t variant, const double* src, size_t count,
+                             int32_t src_is_device, void* stream);
 /* Device time of the interaction-evaluation kernel: when enabled, every launch of
  * it inside seas_step / seas_eval_prescribed is bracketed by HIP events recorded
  * on the launch stream. read_timing synchronises `stream`, returns the summed
@@ -292,7 +339,9 @@ seas_status seas_state_restore(seas_state_t* st, const void* host_buf, size_t by
  * others are on the GPU. A pool's state is created when its first request
  * arrives and the sum of the states' bytes (seas_state_bytes) stays within
  * device_budget; an idle pool gives its memory back when another pool waits
- * for it. Requests queue per pool in arrival order. Not an accuracy feature:
+ * for it. Requests queue per pool in arrival order. A slot whose Newton solve
+ * fails ends its request with NOT_CONVERGED and the outputs of its last good
+ * step; the other slots are not affected. Not an accuracy feature:
  * a request's result is the one it gets alone in a fresh state (bit for bit
  * with BF16 factors, to the FP16 tolerance with FP16 factors, whose history
  * scales see the other slots). */
@@ -316,11 +365,10 @@ typedef struct seas_server seas_server_t;
 seas_status seas_server_create(seas_op_t* const* ops, int32_t n_ops, const seas_request_t* idle,
                                size_t device_budget, int32_t chunk_steps, seas_server_t** out);
 /* Play a trace of n_reqs requests in real time and return when all are done.
- * Blocking; fills admit_s, finish_s and status of every request. A state's
- * convergence flag covers all its slots: when a chunk of a pool reports an
- * error (a Newton failure in any slot), every request active in that pool ends
- * with that status, its outputs hold the state at the end of that chunk, and its
- * slot returns to the idle window. Errors of the call itself: INVALID_ARG (a
+ * Blocking; fills admit_s, finish_s and status of every request. A request
+ * whose slot fails a Newton solve ends with NOT_CONVERGED when the chunk that
+ * failed completes; its outputs hold its last good step and its slot returns
+ * to the idle window. Errors of the call itself: INVALID_ARG (a
  * request with a bad pool index or n_steps < 1), HIP, INTERNAL (requests left
  * that no pool can admit). */
 seas_status seas_server_run(seas_server_t* sv, seas_request_t* reqs, int32_t n_reqs);

@@ -98,6 +98,8 @@ def lib():
             "seas_eval_prescribed": (i32, [vp, vp, vp, i32, vp, vp]),
             "seas_step": (i32, [vp, vp, i32, vp]),
             "seas_state_check": (i32, [vp, vp]),
+            "seas_state_variant_status": (i32, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64), vp]),
+            "seas_write_state": (i32, [vp, i32, i32, vp, C.c_size_t, i32, vp]),
             "seas_read_state": (i32, [vp, i32, i32, vp, C.c_size_t, i32, vp]),
             "seas_state_step_index": (i64, [vp]),
             "seas_state_set_timing": (i32, [vp, i32]),
@@ -270,6 +272,19 @@ class State:
 
     def check(self, stream=0):
         _check(lib().seas_state_check(self.h, _ptr(stream)))
+
+    def variant_status(self, stream=0):
+        """(failed[nv] bool array, last good step[nv] int array)."""
+        f = np.zeros(self.nv, dtype=np.int32)
+        g = np.zeros(self.nv, dtype=np.int64)
+        _check(lib().seas_state_variant_status(self.h, f.ctypes.data_as(C.POINTER(C.c_int32)),
+                                               g.ctypes.data_as(C.POINTER(C.c_int64)), _ptr(stream)))
+        return f.astype(bool), g
+
+    def write(self, field, values, stream=0, variant=0):
+        arr = np.ascontiguousarray(values, dtype=np.float64)
+        _check(lib().seas_write_state(self.h, FIELDS[field], int(variant), C.c_void_p(arr.ctypes.data),
+                                      arr.size, 0, _ptr(stream)))
 
     def read(self, field, stream=0, variant=0):
         out = np.zeros(self.op.N)

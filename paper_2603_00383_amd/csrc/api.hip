@@ -123,7 +123,10 @@ struct seas_state {
   int64_t block_head = INT64_MIN / 2;  // head at which f_far was computed
   int run_S = 0;                        // 1: far list applied every step (plain form); else the build's S
   double2 *dring, *Fh, *F;
-  int* fail;
+  int* fail;                 // per variant: a Newton solve failed (state held at its last good step)
+  int64_t* good;             // per variant: step index of the last committed step
+  double *V2, *td2, *fs2, *fi2;  // corrector results awaiting the commit
+  double2* Dnew;             // corrector slip coefficients awaiting the commit
   bool timing = false;
   std::vector<hipEvent_t> ev;  // start/stop pairs
   size_t n_ev = 0;             // pairs recorded since the last read
@@ -176,6 +179,14 @@ StepArgs<TF> make_args(seas_op* op, seas_state* st) {
   a.f_self_out = st->f_self;
   a.f_int_out = st->f_int;
   a.fail = st->fail;
+  a.good = st->good;
+  a.V2 = st->V2;
+  a.td2 = st->td2;
+  a.fs2 = st->fs2;
+  a.fi2 = st->fi2;
+  a.Dnew = st->Dnew;
+  a.dring = st->dring;
+  a.modes = op->modes;
   a.ring64 = st->ring64;
   a.ringop = (TF*)st->ringop;
   a.op_vfast = op->ring_bytes == 2;
@@ -270,10 +281,14 @@ void do_steps(seas_op* op, seas_state* st, int n_steps, hipStream_t s) {
     StepArgs<TF> a = make_args<TF>(op, st);
     a.t_next = (double)(n + 1) * h.dt;
     a.time_new = n + 1;
+    a.self_head = n + 1;
     launch_stage<TF>(a, 0, s);
+    // corrector: D** waits in Dnew; the commit appends it with the rest of the step
+    // unless a solve of the variant failed
     launch_dft(nm, nv, h.N, dl, op->modes, op->sf, st->delta, st->Vbar, h.dt, op->tw, op->tab, st->Fh, st->F,
-               st->dring, 1, n + 1, n + 1, s);
+               st->dring, 0, n + 1, n + 1, s, st->Dnew);
     launch_stage<TF>(a, 1, s);
+    launch_commit<TF>(a, s);
     st->step = n + 1;
   }
   HIPCHK(hipGetLastError());
@@ -671,13 +686,14 @@ size_t seas_state_bytes(const seas_op_t* op, int32_t n_variants) {
   if (!op || n_variants < 1) return 0;
   const HostOp& h = op->h;
   const size_t N = (size_t)h.N * n_variants;
-  size_t b = N * 8 * 19;                                         // per-element state and scratch
+  size_t b = N * 8 * 23;                                         // per-element state and scratch
   b += (size_t)h.ring_len * N * 8;                               // FP64 rate history
   if (op->ring_bytes != 8) b += (size_t)h.ring_len * N * op->ring_bytes;  // operand copy
   b += (size_t)h.tail_len * 8 * n_variants;
   b += (size_t)h.n_partials[0] * (h.seg ? 4 : 8) + (size_t)h.n_partials[1] * 8;
   b += (size_t)h.time_block * N * 8;
-  b += (size_t)h.self_ring_len * 16 * n_variants + (size_t)h.n_modes * 16 * 2 * n_variants;
+  b += (size_t)h.self_ring_len * 16 * n_variants + (size_t)h.n_modes * 16 * 3 * n_variants;
+  b += (size_t)n_variants * (sizeof(int) + sizeof(int64_t));
   return b;
 }
 
@@ -738,7 +754,13 @@ seas_status seas_state_create(seas_op_t* op, int32_t n_variants, const seas_fric
     st->dring = (double2*)A((size_t)h.self_ring_len * 16 * nv, true);
     st->Fh = (double2*)A((size_t)h.n_modes * 16 * nv, false);
     st->F = (double2*)A((size_t)h.n_modes * 16 * nv, false);
-    st->fail = (int*)A(sizeof(int), false);
+    st->fail = (int*)A((size_t)nv * sizeof(int), true);
+    st->good = (int64_t*)A((size_t)nv * sizeof(int64_t), true);
+    st->V2 = (double*)A(vb, false);
+    st->td2 = (double*)A(vb, false);
+    st->fs2 = (double*)A(vb, false);
+    st->fi2 = (double*)A(vb, false);
+    st->Dnew = (double2*)A((size_t)h.n_modes * 16 * nv, false);
     // host-side initial values
     std::vector<double> eps(N, 1.0), thd(N), zero(N, 0.0);
     if (fric->eps) eps.assign(fric->eps, fric->eps + N);
@@ -873,7 +895,10 @@ seas_status seas_state_reset_variant(seas_state_t* st, int32_t variant, const se
     H2D(st->ff0, fric->f0);
     H2D(st->feps, eps.data());
     const int64_t n = st->step;
+    const int zero_flag = 0;
     HIPCHK(hipMemcpyAsync(st->step0 + v, &n, 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(st->good + v, &n, 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(st->fail + v, &zero_flag, sizeof(int), hipMemcpyHostToDevice, s));
     // no history before the variant's start: clear its rows of every ring, then
     // append V^n and the coefficients of its slip at n
     launch_clear_variant(st->ring64, h.ring_len, nv, v, h.N, 8, s);
@@ -929,22 +954,121 @@ seas_status seas_step(seas_op_t* op, seas_state_t* st, int32_t n_steps, void* st
 }
 
 seas_status seas_state_check(seas_state_t* st, void* stream) {
-  int bad = 0;
+  std::vector<int> bad;
+  std::vector<int64_t> good;
   seas_status rc = guard([&] {
     if (!st) throw Error(SEAS_ERR_INVALID_ARG, "null state");
     checked(st->op);
     hipStream_t s = (hipStream_t)stream;
-    HIPCHK(hipMemcpyAsync(&bad, st->fail, sizeof(int), hipMemcpyDeviceToHost, s));
+    bad.assign(st->nv, 0);
+    good.assign(st->nv, 0);
+    HIPCHK(hipMemcpyAsync(bad.data(), st->fail, st->nv * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(good.data(), st->good, st->nv * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (bad) HIPCHK(hipMemsetAsync(st->fail, 0, sizeof(int), s));
-    HIPCHK(hipStreamSynchronize(s));
+    if (st->nv == 1 && bad[0]) {
+      // one variant: the state is back at its last good step, ready to resume
+      st->step = good[0];
+      st->block_head = INT64_MIN / 2;
+      HIPCHK(hipMemsetAsync(st->fail, 0, sizeof(int), s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
   });
   if (rc != SEAS_OK) return rc;
-  if (bad) {
-    g_err = "Newton did not converge within 50 iterations";
+  std::string msg;
+  for (size_t v = 0; v < bad.size(); ++v)
+    if (bad[v]) {
+      if (msg.empty()) msg = "Newton did not converge within 50 iterations: ";
+      else msg += ", ";
+      msg += "variant " + std::to_string(v) + " held at step " + std::to_string(good[v]);
+    }
+  if (!msg.empty()) {
+    g_err = msg;
     return SEAS_ERR_NOT_CONVERGED;
   }
   return SEAS_OK;
+}
+
+seas_status seas_state_variant_status(const seas_state_t* st, int32_t* failed, int64_t* good_step, void* stream) {
+  return guard([&] {
+    if (!st) throw Error(SEAS_ERR_INVALID_ARG, "null state");
+    checked(st->op);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int> bad(st->nv);
+    if (failed) {
+      HIPCHK(hipMemcpyAsync(bad.data(), st->fail, st->nv * sizeof(int), hipMemcpyDeviceToHost, s));
+    }
+    if (good_step) HIPCHK(hipMemcpyAsync(good_step, st->good, st->nv * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (failed)
+      for (int v = 0; v < st->nv; ++v) failed[v] = bad[v];
+  });
+}
+
+seas_status seas_write_state(seas_state_t* st, int32_t field, int32_t variant, const double* src, size_t count,
+                             int32_t src_is_device, void* stream) {
+  return guard([&] {
+    if (!st || !src) throw Error(SEAS_ERR_INVALID_ARG, "null argument");
+    seas_op* op = checked(st->op);
+    if (variant < 0 || variant >= st->nv) throw Error(SEAS_ERR_INVALID_ARG, "variant out of range");
+    const HostOp& h = op->h;
+    const size_t N = h.N;
+    if (count != N) throw Error(SEAS_ERR_INVALID_ARG, "count must equal the number of elements");
+    if (st->mode == 1) throw Error(SEAS_ERR_MISMATCH, "state is in prescribed-history mode");
+    hipStream_t s = (hipStream_t)stream;
+    const int nv = st->nv, v = variant;
+    const size_t o = (size_t)v * N;
+    std::vector<double> x(src_is_device ? N : 0);
+    const double* hx = src;
+    if (src_is_device) {
+      HIPCHK(hipMemcpyAsync(x.data(), src, N * 8, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      hx = x.data();
+    }
+    double* dst = nullptr;
+    switch (field) {
+      case SEAS_FIELD_V:
+        for (size_t r = 0; r < N; ++r)
+          if (!(hx[r] > 0)) throw Error(SEAS_ERR_INVALID_ARG, "V must be > 0");
+        dst = st->V;
+        break;
+      case SEAS_FIELD_THETA:
+        for (size_t r = 0; r < N; ++r)
+          if (!(hx[r] > 0)) throw Error(SEAS_ERR_INVALID_ARG, "theta must be > 0");
+        dst = st->theta;
+        break;
+      case SEAS_FIELD_DELTA: dst = st->delta; break;
+      case SEAS_FIELD_TAU0: dst = st->tau0; break;
+      default: throw Error(SEAS_ERR_INVALID_ARG, "field cannot be written (V, THETA, DELTA or TAU0)");
+    }
+    HIPCHK(hipMemcpyAsync(dst + o, hx, N * 8, hipMemcpyHostToDevice, s));
+    const int64_t n = st->step;
+    if (field == SEAS_FIELD_V) {
+      // V^n is also the newest row of the rate history
+      const int64_t slot = ((n % h.ring_len) + h.ring_len) % h.ring_len;
+      HIPCHK(hipMemcpyAsync(st->ring64 + ((size_t)slot * nv + v) * N, hx, N * 8, hipMemcpyHostToDevice, s));
+      if (op->ring_bytes == 2) upload_op_variant(op, st->ringop, slot, nv, v, hx, s);
+      else upload_op_seg(op, st->ringop, ((size_t)slot * nv + v) * N, hx, N, s);
+    }
+    if (field == SEAS_FIELD_V || field == SEAS_FIELD_THETA) {
+      // the state rate follows from V and theta
+      std::vector<double> V(N), th(N), Dc(N), eps(N), thd(N);
+      HIPCHK(hipMemcpyAsync(V.data(), st->V + o, N * 8, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(th.data(), st->theta + o, N * 8, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(Dc.data(), st->fDc + o, N * 8, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(eps.data(), st->feps + o, N * 8, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      for (size_t r = 0; r < N; ++r) thd[r] = host_state_rate(V[r], th[r], Dc[r], eps[r]);
+      HIPCHK(hipMemcpyAsync(st->thdot + o, thd.data(), N * 8, hipMemcpyHostToDevice, s));
+    }
+    if (field == SEAS_FIELD_DELTA) {
+      // D^n, the transform of the slip at the current step, is the newest coefficient row
+      launch_dft(h.n_modes, 1, h.N, h.self_ring_len, op->modes, op->sf, st->delta + o, nullptr, 0.0, op->tw,
+                 op->tab, nullptr, st->F + (size_t)v * h.n_modes, st->dring + (size_t)v * h.self_ring_len, 1, n, n, s);
+      HIPCHK(hipGetLastError());
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    if (st->mode == 0) st->mode = 2;
+  });
 }
 
 seas_status seas_read_state(const seas_state_t* st, int32_t field, int32_t variant, double* dst, size_t count,

@@ -431,7 +431,8 @@ __global__ void k_dft(const SelfMode* __restrict__ modes, int n_modes, int nv, i
                       const SelfFaultDev* __restrict__ sf, const double* __restrict__ delta,
                       const double* __restrict__ vel, double coef, const double2* __restrict__ tw,
                       const double* __restrict__ tab, const double2* __restrict__ Fh, double2* __restrict__ Fout,
-                      double2* __restrict__ dring, int push, int64_t push_time, int64_t ring_head) {
+                      double2* __restrict__ dring, int push, int64_t push_time, int64_t ring_head,
+                      double2* __restrict__ Dsave) {
   const int lane = threadIdx.x & 63;
   const int gg = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (gg >= n_modes * nv) return;
@@ -460,6 +461,7 @@ __global__ void k_dft(const SelfMode* __restrict__ modes, int n_modes, int nv, i
   Fout[gm] = make_double2(c * (k0 * re + fh.x), c * (k0 * im + fh.y));
   if (push && md.W > 0 && push_time > ring_head - md.W)
     dring[md.ring + ring_slot(push_time, md.W)] = make_double2(re, im);
+  if (Dsave) Dsave[(int64_t)v * n_modes + gm] = make_double2(re, im);
 }
 
 // Inverse transform at element j, by one wave (lanes strided over modes):
@@ -552,7 +554,7 @@ __global__ void k_stage(StepArgs<TF> a, int stage) {
     const double th_s = a.theta[e] + a.dt * a.thdot[e];
     const double fint = a.f_hist[e] - a.eta * lag0_apply(a.l0_ptr, a.l0_col, a.l0_val, a.V + o, r);
     const double Vs = newton_lnV(tau0 + fself + fint, th_s, a.eta, fr.a[e], fr.b[e], fr.Dc[e], fr.sn[e], fr.V0[e],
-                                 fr.f0[e], log(V), a.fail);
+                                 fr.f0[e], log(V), a.fail + v);
     const double tds = state_rate(Vs, th_s, fr.Dc[e], fr.eps[e]);
     a.Vstar[e] = Vs;
     a.Vbar[e] = 0.5 * (V + Vs);
@@ -562,21 +564,53 @@ __global__ void k_stage(StepArgs<TF> a, int stage) {
     const double th2 = a.th2[e];
     const double fint = a.f_hist[e] - a.eta * lag0_apply(a.l0_ptr, a.l0_col, a.l0_val, a.Vbar + o, r);
     const double V2 = newton_lnV(tau0 + fself + fint, th2, a.eta, fr.a[e], fr.b[e], fr.Dc[e], fr.sn[e], fr.V0[e],
-                                 fr.f0[e], log(a.Vstar[e]), a.fail);
-    const double td2 = state_rate(V2, th2, fr.Dc[e], fr.eps[e]);
-    // commit: no other element reads V, theta, thdot or delta in this pass
-    a.delta[e] += a.dt * Vb;
-    a.theta[e] = th2;
-    a.thdot[e] = td2;
+                                 fr.f0[e], log(a.Vstar[e]), a.fail + v);
+    (void)Vb;
+    // the commit (k_commit) takes these once every solve of the variant is known to
+    // have converged
+    a.V2[e] = V2;
+    a.td2[e] = state_rate(V2, th2, fr.Dc[e], fr.eps[e]);
+    a.fs2[e] = fself;
+    a.fi2[e] = fint;
+  }
+}
+
+// Commit of the corrector, after every Newton solve of the step: threads
+// [0, nv N) take one element each, the next nv n_modes one slip coefficient each.
+// A variant whose flag is set (a solve of this or an earlier step failed) is left
+// as it is: its state, histories and accumulators stay at its last good step.
+template <typename TF>
+__global__ void k_commit(StepArgs<TF> a) {
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ne = (int64_t)a.N * a.nv;
+  if (g < ne) {
+    const int v = (int)(g / a.N), r = (int)(g - (int64_t)v * a.N);
+    if (a.fail[v]) return;
+    const int64_t e = g;
+    const double V2 = a.V2[e];
+    a.delta[e] += a.dt * a.Vbar[e];
+    a.theta[e] = a.th2[e];
+    a.thdot[e] = a.td2[e];
     a.V[e] = V2;
-    a.f_self_out[e] = fself;
-    a.f_int_out[e] = fint;
+    a.f_self_out[e] = a.fs2[e];
+    a.f_int_out[e] = a.fi2[e];
     const int64_t sl = ring_slot(a.time_new, a.R), ri = (sl * a.nv + v) * a.N + r;
     a.ring64[ri] = V2;
     if ((void*)a.ringop != (void*)a.ring64)
       a.ringop[a.op_vfast ? (sl * a.N + r) * a.nv + v : ri] = to_op<TF>(V2);
-    if (a.tail) tail_update(a, v, r, k, j);
+    if (a.tail) {
+      const int k = a.fault_of[r];
+      tail_update(a, v, r, k, r - a.sf[k].off);
+    }
+    if (r == 0) a.good[v] = a.time_new;
+    return;
   }
+  g -= ne;
+  if (g >= (int64_t)a.n_modes * a.nv) return;
+  const int v = (int)(g / a.n_modes), gm = (int)(g - (int64_t)v * a.n_modes);
+  if (a.fail[v]) return;
+  const SelfMode md = a.modes[gm];
+  if (md.W > 0) a.dring[v * a.dring_len + md.ring + ring_slot(a.self_head, md.W)] = a.Dnew[g];
 }
 
 // Prescribed mode, before the evaluation of step n: append V^{n-1}, advance slip.
@@ -722,14 +756,20 @@ void launch_self_hist(int n_modes, int nv, int64_t dring_len, const SelfMode* mo
 void launch_dft(int n_modes, int nv, int N, int64_t dring_len, const SelfMode* modes, const SelfFaultDev* sf,
                 const double* delta, const double* vel, double coef, const double2* tw, const double* tab,
                 const double2* Fh, double2* Fout, double2* dring, int push, int64_t push_time, int64_t ring_head,
-                hipStream_t s) {
+                hipStream_t s, double2* Dsave) {
   hipLaunchKernelGGL(k_dft, dim3(blocks_for((int64_t)n_modes * nv, 4)), dim3(256), 0, s, modes, n_modes, nv, N,
-                     dring_len, sf, delta, vel, coef, tw, tab, Fh, Fout, dring, push, push_time, ring_head);
+                     dring_len, sf, delta, vel, coef, tw, tab, Fh, Fout, dring, push, push_time, ring_head, Dsave);
 }
 
 template <typename TF>
 void launch_stage(const StepArgs<TF>& a, int stage, hipStream_t s) {
   hipLaunchKernelGGL((k_stage<TF>), dim3(blocks_for((int64_t)a.N * a.nv, 4)), dim3(256), 0, s, a, stage);
+}
+
+template <typename TF>
+void launch_commit(const StepArgs<TF>& a, hipStream_t s) {
+  const int64_t n = (int64_t)a.N * a.nv + (int64_t)a.n_modes * a.nv;
+  hipLaunchKernelGGL((k_commit<TF>), dim3(blocks_for(n, 256)), dim3(256), 0, s, a);
 }
 
 template <typename TF>
@@ -742,6 +782,9 @@ void launch_prescribed_out(const StepArgs<TF>& a, const double* Vprev, double* f
   hipLaunchKernelGGL((k_pre_out<TF>), dim3(blocks_for((int64_t)a.N * a.nv, 4)), dim3(256), 0, s, a, Vprev, fout);
 }
 
+template void launch_commit<double>(const StepArgs<double>&, hipStream_t);
+template void launch_commit<float>(const StepArgs<float>&, hipStream_t);
+template void launch_commit<__bf16>(const StepArgs<__bf16>&, hipStream_t);
 template void launch_stage<double>(const StepArgs<double>&, int, hipStream_t);
 template void launch_stage<float>(const StepArgs<float>&, int, hipStream_t);
 template void launch_stage<__bf16>(const StepArgs<__bf16>&, int, hipStream_t);

@@ -47,7 +47,16 @@ struct StepArgs {
   double *V, *theta, *thdot, *delta;
   double *Vstar, *Vbar, *th2;
   double *f_self_out, *f_int_out;
+  // per variant: Newton failure flag and the step index of the last committed step;
+  // the corrector's results wait in V2/td2/fs2/fi2 (and the new slip coefficients in
+  // Dnew) until the commit, which skips a failed variant
   int* fail;
+  int64_t* good;
+  double *V2, *td2, *fs2, *fi2;
+  double2* Dnew;
+  double2* dring;           // coefficient rings [nv][dring_len]
+  const SelfMode* modes;
+  int64_t self_head;        // time of the coefficient row the commit appends
   // history append (corrector)
   double* ring64;
   TF* ringop;               // operand copy (== ring64 for FP64 factors)
@@ -84,12 +93,18 @@ void launch_hmat_f32far(const HostOp& h, int n_items, const void* items, const i
 // self term over nv variants: modal arrays [nv][n_modes], rings [nv][dring_len], slip [nv][N]
 void launch_self_hist(int n_modes, int nv, int64_t dring_len, const SelfMode* modes, const double* tab,
                       const double2* dring, int64_t time0, double2* Fh, hipStream_t s);
+// push: 1 stores the coefficients in the mode rings at push_time; Dsave (may be
+// null) receives them instead, [nv][n_modes], for a later conditional push
 void launch_dft(int n_modes, int nv, int N, int64_t dring_len, const SelfMode* modes, const SelfFaultDev* sf,
                 const double* delta, const double* vel, double coef, const double2* tw, const double* tab,
                 const double2* Fh, double2* Fout, double2* dring, int push, int64_t push_time, int64_t ring_head,
-                hipStream_t s);
+                hipStream_t s, double2* Dsave = nullptr);
 template <typename TF>
 void launch_stage(const StepArgs<TF>& a, int stage, hipStream_t s);
+// commit of a corrector: state, histories and outputs of every variant whose
+// Newton solves of the step converged (a failed variant keeps its last good step)
+template <typename TF>
+void launch_commit(const StepArgs<TF>& a, hipStream_t s);
 template <typename TF>
 void launch_prescribed_push(const StepArgs<TF>& a, const double* Vin, hipStream_t s);
 template <typename TF>

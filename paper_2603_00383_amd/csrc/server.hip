@@ -186,14 +186,21 @@ seas_status seas_server_run(seas_server_t* sv, seas_request_t* rq, int32_t n) {
           if (q != hipSuccess) throw Error(SEAS_ERR_HIP, "hipEventQuery failed");
           p.busy = false;
           progress = true;
-          const seas_status cs = seas_state_check(p.st, p.stream);
+          // a slot whose Newton solve failed is held at its last good step; the
+          // others are not affected
+          std::vector<int32_t> failed(p.nv, 0);
+          raise_status(seas_state_variant_status(p.st, failed.data(), nullptr, p.stream),
+                       "seas_state_variant_status");
           for (int s = 0; s < p.nv; ++s) {
             Slot& sl = p.slots[s];
-            if (sl.req < 0) continue;
+            if (sl.req < 0) {
+              if (failed[s]) reset_slot(p, s, p.idle);
+              continue;
+            }
             sl.done += p.K;
             seas_request_t& r = rq[sl.req];
-            if (cs != SEAS_OK) r.status = cs;
-            if (sl.done < r.n_steps && cs == SEAS_OK) continue;
+            if (failed[s]) r.status = SEAS_ERR_NOT_CONVERGED;
+            if (sl.done < r.n_steps && !failed[s]) continue;
             double* outs[3] = {r.V_out, r.theta_out, r.delta_out};
             const int32_t fields[3] = {SEAS_FIELD_V, SEAS_FIELD_THETA, SEAS_FIELD_DELTA};
             for (int k = 0; k < 3; ++k)

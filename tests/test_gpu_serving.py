@@ -109,6 +109,22 @@ def test_server_results_alone_and_in_the_mix():
         alone = sv.run([q])[0]
         for k in ("V", "theta", "delta"):
             assert np.array_equal(alone[k], res[i][k]), (i, k)
+    # a request that cannot converge ends alone, with its last good step; the
+    # others keep the results they get alone
+    bad = dict(reqs[3])
+    bw = dict(bad["window"])
+    bw["V"] = np.full(len(bw["V"]), 1e-300)
+    bad["window"] = bw
+    mixed = list(reqs[:8])
+    mixed[3] = bad
+    resb = sv.run(mixed)
+    assert resb[3]["status"] == -4
+    assert np.array_equal(resb[3]["V"], bw["V"]) and np.array_equal(resb[3]["theta"], bw["theta"])
+    for i in range(8):
+        if i != 3:
+            assert resb[i]["status"] == 0
+            for k in ("V", "theta", "delta"):
+                assert np.array_equal(resb[i][k], res[i][k]), (i, k)
     # memory-bound admission: a budget of one pool's state serialises the pools
     sv1 = P.Server(ops, idle, max(o.state_bytes(16) for o in ops), chunk_steps=8)
     res1 = sv1.run(reqs[:8])
