@@ -22,9 +22,12 @@ namespace seas {
 // Inside the cone ct > r: sqrt((ct/r)^2 - 1) = Q / r with Q^2 = (ct - r)(ct + r),
 // and arccos(|r1| / sqrt(ct^2 - r2^2)) = atan2(Q, |r1|).
 static inline double corner(double r1, double r2, double ct, double n1, double n2) {
-  const double r = std::hypot(r1, r2);
+  const double ar2 = std::fabs(r2);
+  if (!(ct > ar2)) return 0.0;  // before the plane front: both terms vanish (ct <= |r2| <= r)
   double v = 0.0;
-  if (r1 > 0.0 && ct > std::fabs(r2)) v += n2;  // plane-wave term H(r1) H(t - |r2|/cs)
+  if (r1 > 0.0) v += n2;         // plane-wave term H(r1) H(t - |r2|/cs)
+  if (!(ct > std::fabs(r1))) return v;  // ct <= |r1| <= r: outside the cylindrical front
+  const double r = std::hypot(r1, r2);
   if (ct > r) {
     const double Q = std::sqrt((ct - r) * (ct + r));
     const double rr = r * r;
@@ -522,13 +525,28 @@ static void build_subblock(const HostOp& op, const BlockDesc& bd, const PairWin&
   int kmax = std::min<int>({(int)(((int64_t)p * q) / (p + q)), kColMax, kZMax / S});
   if (op.seg) kmax = std::min(kmax, ((seg_z_limit(op.ncols, op.seg_eb) / op.ncols) & ~7) - 8);
   const PairFrame fr = frame(A, B);
-  std::vector<double> r1((size_t)p * q), r2((size_t)p * q);
-  for (int i = 0; i < p; ++i)
-    for (int j = 0; j < q; ++j) offsets(A, bd.r0 + i, B, s0 + j, r1[(size_t)i * q + j], r2[(size_t)i * q + j]);
+  // The corners r1' +- ds/2 of source element j are the offsets of its two edges,
+  // and adjacent elements share an edge: the primitive is evaluated once per edge
+  // (q + 1 per receiver and time level instead of 2 q). Edge e of the slice lies at
+  // s_e = -L/2 + (s0 + e) dx along the source fault; r1' of receiver i from it is
+  // its tangential offset from the source centroid minus s_e, and r2' (its normal
+  // offset) is the same for every source element of a straight fault.
+  const int qe = q + 1;
+  std::vector<double> re((size_t)p * qe), r2i(p), C(qe);
+  for (int i = 0; i < p; ++i) {
+    const double ex = A.midx(bd.r0 + i) - B.cx, ey = A.midy(bd.r0 + i) - B.cy;
+    const double along = ex * B.tx + ey * B.ty;
+    r2i[i] = ex * B.nx + ey * B.ny;
+    for (int e = 0; e < qe; ++e) re[(size_t)i * qe + e] = along - (-0.5 * B.L + (s0 + e) * B.dx);
+  }
   auto level = [&](int T, std::vector<double>& G) {  // spatial difference at t = T dt
     const double ct = cs * (T * dt);
-    for (size_t e = 0; e < G.size(); ++e)
-      G[e] = corner(r1[e] + fr.h, r2[e], ct, fr.n1, fr.n2) - corner(r1[e] - fr.h, r2[e], ct, fr.n1, fr.n2);
+    for (int i = 0; i < p; ++i) {
+      const double* r1e = &re[(size_t)i * qe];
+      for (int e = 0; e < qe; ++e) C[e] = corner(r1e[e], r2i[i], ct, fr.n1, fr.n2);
+      double* g = &G[(size_t)i * q];
+      for (int j = 0; j < q; ++j) g[j] = C[j] - C[j + 1];
+    }
   };
   std::vector<double> G0((size_t)p * q), G1((size_t)p * q), K((size_t)p * q), U, W, R;
   std::vector<LagFactor> lags;
