@@ -69,43 +69,122 @@ MEASURED_TRAFFIC = {
 }
 
 
-def cpu_baseline(faults, params, prior, budget_s=12.0):
-    """The oracle (numpy, one thread) on a bounded sample: interaction rows of a
-    few receivers plus the full self term of their fault, at a saturated step."""
+def cpu_cores():
+    """Host cores the CPU legs use: the process's CPU affinity (what nproc reports),
+    at most 16 (one GPU's share of the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+_W = {}
+
+
+def _rows_init(seed, n_prior):
+    """Worker set-up: the seeded workload and its prior history, generated in the
+    worker (no large arrays cross process boundaries)."""
+    from threadpoolctl import threadpool_limits
+    import seas_inputs as SI
+    from oracle import geometry
+    _W["limit"] = threadpool_limits(limits=1)
+    faults = SI.five_fault_network(seed=seed)
+    _W["geo"] = geometry.discretize(faults)
+    _W["prior"] = SI.saturated_history(faults, n_prior, seed)
+    _W["dt"] = geometry.time_step(_W["geo"], SI.CS)
+
+
+def _rows_work(job):
+    """Oracle interaction history part (lags >= 1 and the static tail) of some
+    receivers at one head, and its wall time."""
+    import seas_inputs as SI
+    from oracle import interaction as OI
+    rows, head = job
+    t0 = time.perf_counter()
+    v = OI.stress_rows(_W["geo"], rows, _W["prior"], head, -len(_W["prior"]), SI.MU, SI.CS, _W["dt"],
+                       0.01, 0.01, min_lag=1, with_tail=True)
+    return rows, head, v, time.perf_counter() - t0
+
+
+def cpu_leg(seed):
+    """The oracle on the host, before the GPU is touched: (a) the five-fault
+    workload's interaction history part on a bounded sample of receivers at five
+    saturated heads (the sampled values also give each GPU form's error), plus
+    the full self term of every fault, as element-steps/s of one step; (b) the
+    two-fault FP64 workload's 256 prescribed steps in full."""
+    import multiprocessing as mp
+
     import numpy as np
     from threadpoolctl import threadpool_limits
 
+    import seas_inputs as SI
     from oracle import interaction as OI
     from oracle import seas as OS
+    cores = cpu_cores()
+    faults = SI.five_fault_network(seed=seed)
+    params = SI.default_params(factor_dtype="f64")
     prob = OS.Problem(faults, params, dense=False)
-    first = -len(prior)
-    head = -1
-    p = prob.p
-    Np = prob.geo[0].Np
-    rows_all = list(np.linspace(0, Np - 1, 64).astype(int))
+    N = prob.N
+    max_lag = max(OI.pair_window_lags(prob.geo, a, b, prob.cs, prob.dt, 0.01, 0.01)[1]
+                  for a in range(len(faults)) for b in range(len(faults)) if a != b)
+    n_prior = max_lag + 8
+    worst, dmin = SI.closest_to_other_faults(faults)
+    rows = sorted(set(worst) | set(int(r) for r in np.linspace(0, N - 1, 96).astype(int)))
+    heads = [0, -1, -2, -3, -4]
+    chunks = [rows[i::cores] for i in range(cores)]
+    jobs = [(c, h) for h in heads for c in chunks if c]
+    t_head = {h: 0.0 for h in heads}
+    ref0 = {}
+    ctx = mp.get_context("spawn")
+    w0 = time.perf_counter()
+    with ctx.Pool(cores, initializer=_rows_init, initargs=(seed, n_prior)) as pool:
+        for rr, h, v, dt_ in pool.imap_unordered(_rows_work, jobs):
+            t_head[h] += dt_
+            if h == 0:
+                ref0.update(zip(rr, v))
+    wall_rows = time.perf_counter() - w0
+    # self term of every fault at a saturated step (faults of one size share tables)
+    prior = SI.saturated_history(faults, n_prior, seed)
     with threadpool_limits(limits=1):
-        t_int, done = 0.0, 0
-        while done < len(rows_all) and (t_int < budget_s or done < 4):
-            t0 = time.perf_counter()
-            OI.stress_rows(prob.geo, [rows_all[done]], prior, head, first, prob.mu, prob.cs, prob.dt,
-                           p["eta_tmin"], p["eta_tmax"], with_tail=prob.with_tail)
-            t_int += time.perf_counter() - t0
-            done += 1
-        t0 = time.perf_counter()
-        OS.prescribed_rows(prob, prior, first, 0, [], delta0=None)     # warm the DFT matrix
-        st = prob.selfs[0]
-        delta = np.vstack([np.zeros((1, prob.N)), np.cumsum(prior, axis=0) * prob.dt])
+        delta = np.vstack([np.zeros((1, N)), np.cumsum(prior, axis=0) * prob.dt])
         delta = delta - delta[-1][None, :]
-        W = int(st.W.max())
         t0 = time.perf_counter()
-        Dh = st.dft(delta[-W - 1:, :Np])
-        st.stress(Dh, 0, -W)
+        for k in range(len(faults)):
+            st = prob.selfs[k]
+            W = int(st.W.max())
+            Dh = st.dft(delta[-W - 1:, prob.off[k]:prob.off[k + 1]])
+            st.stress(Dh, 0, -W)
         t_self = time.perf_counter() - t0
-    per_elem = t_int / done + t_self / Np
-    return {"value": 1.0 / per_elem, "unit": "element-steps/s", "cores": 1, "kind": "oracle",
-            "sample": (f"{done} receivers' interaction rows (all lags of all pair windows, kernel "
-                       f"evaluated on the fly) + the full self term of one {Np}-element fault, at a "
-                       f"saturated step of the same workload; {t_int + t_self:.1f} s of CPU work")}
+    # rows run `cores` at a time: one step's interaction rows take their summed
+    # time / cores of wall time; the self term ran on one core
+    per_step = [t_head[h] / len(rows) * N / cores + t_self for h in heads]
+    med = float(np.median(per_step))
+    # (b) two-fault workload: the dense oracle over all 256 steps
+    f1 = SI.two_fault_prescribed_faults()
+    p1 = SI.default_params(factor_dtype="f64", compress=0)
+    V1 = SI.prescribed_slip_rate(f1, 256, seed)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        prob1 = OS.Problem(f1, p1)
+        t1 = time.perf_counter()
+        ref1 = OS.prescribed(prob1, V1)
+        t2 = time.perf_counter()
+    out = {"value": N / med, "unit": "element-steps/s", "cores": cores, "kind": "oracle",
+           "sample": (f"five-fault workload (N={N}): the oracle's interaction history part (all lags >= 1 "
+                      f"of every pair window, kernel evaluated on the fly, static tail) of {len(rows)} "
+                      f"receivers (96 evenly spaced, {len(worst)} nearest a fault crossing, the closest "
+                      f"{dmin:.1f} m) at 5 saturated steps on {cores} worker processes, plus the full self "
+                      f"term of all {len(faults)} faults on one core; per-step time = summed row time x "
+                      f"N / {len(rows)} / {cores} + self term, median of the 5 steps; "
+                      f"{wall_rows:.1f} s wall for the rows"),
+           "per_step_s": per_step,
+           "two_fault_fp64": {"value": 256 * 256 / (t2 - t1), "unit": "element-steps/s", "cores": 1,
+                              "eval_s": t2 - t1, "setup_s": t1 - t0,
+                              "sample": "all 256 steps of the two-fault prescribed-history workload "
+                                        "(2 x 128 elements), dense FP64 stacks, direct self term"}}
+    return out, dict(rows=rows, worst=worst, ref0=np.array([ref0[r] for r in rows]), n_prior=n_prior,
+                     max_lag=max_lag, ref1=ref1, V1=V1)
 
 
 def run_precision(args):
@@ -276,21 +355,19 @@ def _window(SI, np, faults, seed, quiet=False):
     return dict(fric=fric, V=ini["V"], theta=ini["theta"], tau0=ini["tau0"], tau0_rate=ini["tau0_rate"])
 
 
-def run_serving(args):
+def serving_leg(seed, dtype, templates, sizes, n_requests, rate, min_steps, max_steps, chunk, budget_gb,
+                slots=16):
     """Serving: a Poisson stream of simulation-window requests on seeded geometry
     templates, admitted into variant slots of one ensemble state per template
-    (continuous batching), p50/p99 completion latency and throughput."""
+    (continuous batching); p50/p99 completion latency and throughput."""
     import numpy as np
 
     import paper_2603_00383_amd as P
     import seas_inputs as SI
 
-    dtype = args.dtype or "f16"
-    slots = 16
-    sizes = (500, 1000, 2000)
-    tpls = SI.serving_templates(seed=args.seed, n_templates=args.templates, sizes=sizes)
-    reqs = SI.poisson_requests(n_requests=args.requests, rate=args.rate, seed=args.seed,
-                               n_templates=args.templates, min_steps=args.min_steps, max_steps=args.max_steps)
+    tpls = SI.serving_templates(seed=seed, n_templates=templates, sizes=sizes)
+    reqs = SI.poisson_requests(n_requests=n_requests, rate=rate, seed=seed, n_templates=templates,
+                               min_steps=min_steps, max_steps=max_steps)
     ops, build_s = [], 0.0
     for k, f in enumerate(tpls):
         t0 = time.perf_counter()
@@ -299,8 +376,8 @@ def run_serving(args):
         build_s += time.perf_counter() - t0
         print(f"[bench] template {k}: N={ops[-1].N} faults={len(f)} built", file=sys.stderr, flush=True)
     idle = [_window(SI, np, f, 0, quiet=True) for f in tpls]
-    budget = int(args.budget_gb * 2 ** 30)
-    sv = P.Server(ops, idle, budget, chunk_steps=args.chunk)
+    budget = int(budget_gb * 2 ** 30)
+    sv = P.Server(ops, idle, budget, chunk_steps=chunk)
     trace = [dict(pool=q["template"], n_steps=q["n_steps"], arrival_s=q["arrival"],
                   window=_window(SI, np, tpls[q["template"]], q["seed"])) for q in reqs]
     print(f"[bench] serving {len(trace)} requests over {reqs[-1]['arrival']:.1f} s", file=sys.stderr, flush=True)
@@ -310,30 +387,40 @@ def run_serving(args):
     lat = np.array([r["finish_s"] - q["arrival_s"] for r, q in zip(res, trace)])
     work = float(sum(ops[q["pool"]].N * q["n_steps"] for q in trace))
     bad = sum(1 for r in res if r["status"] != 0)
-    out = {
-        "metric": METRIC,
-        "value": work / wall,
-        "unit": "element-steps/s",
-        "n_gpus": 1, "steps": int(sum(q["n_steps"] for q in trace)), "warmup": 0,
-        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": dtype, "data": "synthetic",
-        "config": {"workload": f"serving: {len(trace)} Poisson requests (rate {args.rate}/s), {args.templates} "
-                               f"seeded templates with N in {list(sizes)} and 2-10 faults, windows "
-                               f"{args.min_steps}-{args.max_steps} steps, {slots} slots per template, "
-                               f"{dtype.upper()} factors, chunks of {args.chunk} steps",
-                   "seed": args.seed, "templates": [o.N for o in ops], "budget_GiB": args.budget_gb},
+    sv.close()
+    for o in ops:
+        o.close()
+    return {
+        "value": work / wall, "unit": "element-steps/s",
+        "workload": f"serving: {len(trace)} Poisson requests (rate {rate}/s), {templates} seeded templates "
+                    f"with N in {list(sizes)} and 2-10 faults, windows {min_steps}-{max_steps} steps, "
+                    f"{slots} slots per template, {dtype.upper()} factors, chunks of {chunk} steps",
+        "templates": [o.N for o in ops], "requests": len(trace),
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                       "max": float(lat.max())},
         "makespan_s": wall, "trace_span_s": float(reqs[-1]["arrival"]), "failed_requests": bad,
-        "build_s": build_s,
+        "build_s": build_s, "budget_GiB": budget_gb,
     }
+
+
+def run_serving(args):
+    dtype = args.dtype or "f16"
+    r = serving_leg(args.seed, dtype, args.templates, (500, 1000, 2000), args.requests, args.rate,
+                    args.min_steps, args.max_steps, args.chunk, args.budget_gb)
+    out = {"metric": METRIC, "value": r["value"], "unit": r["unit"], "n_gpus": 1,
+           "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+           "config": {"workload": r["workload"], "seed": args.seed, "templates": r["templates"],
+                      "budget_GiB": args.budget_gb},
+           "latency_s": r["latency_s"], "makespan_s": r["makespan_s"], "trace_span_s": r["trace_span_s"],
+           "failed_requests": r["failed_requests"], "build_s": r["build_s"]}
     print(json.dumps(out), flush=True)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=160)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="seas", choices=["seas", "ensemble", "serving", "precision"],
                     help="seas: five-fault step loop (one variant); ensemble: eight faults x 750 elements, "
@@ -355,7 +442,10 @@ def main():
                     help="S: lags >= S applied once per S steps (1 = plain per-step form)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form measurement")
     ap.add_argument("--no-forms", action="store_true", help="skip the 16-bit forms (FP32 runs only)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle CPU leg (the forms' errors are then not measured)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the bounded serving leg")
+    ap.add_argument("--no-two-fault", action="store_true", help="skip the two-fault FP64 workload")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 2 GiB buffer three times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -381,6 +471,12 @@ def main():
     import paper_2603_00383_amd as P
     import seas_inputs as SI
 
+    cpu, ref = None, None
+    if args.workload == "seas" and not args.no_cpu_baseline:
+        # the oracle runs first, in worker processes, before anything uses the GPU
+        print(f"[bench] oracle CPU leg on {cpu_cores()} cores", file=sys.stderr, flush=True)
+        cpu, ref = cpu_leg(args.seed)
+        print(f"[bench] oracle: {cpu['value']:.3g} element-steps/s", file=sys.stderr, flush=True)
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
     if args.workload == "ensemble":
@@ -399,10 +495,19 @@ def main():
     stream = torch.cuda.current_stream()
     s = stream.cuda_stream
     prior_cache = {}
+    K, W = args.steps, max(args.warmup, 1)
+
+    def rel_sample(st):
+        """Error of the interaction history part after the first step (head 0) on the
+        oracle's sampled receivers (max abs difference / max abs reference)."""
+        if ref is None:
+            return None
+        f = st.read("f_hist", stream=s)[ref["rows"]]
+        return float(np.abs(f - ref["ref0"]).max() / np.abs(ref["ref0"]).max())
 
     def prepare(dtype):
-        """Operator of one factor dtype and a state with full history windows,
-        after the warmup steps."""
+        """Operator of one factor dtype and a state with full history windows: the
+        first step is compared with the oracle, then the rest of the warmup."""
         params = SI.default_params(factor_dtype=dtype, aca_tol=args.aca, eta_H=2.0, leaf=50,
                                    time_block=args.time_block)
         print(f"[bench] building the {dtype} operator", file=sys.stderr, flush=True)
@@ -413,15 +518,20 @@ def main():
         print(f"[bench] operator built in {bs:.1f} s: N={op.N} items={inf['n_items']} "
               f"stored/dense={inf['stored_entries'] / inf['dense_entries']:.3f} max_lag={inf['max_lag']}",
               file=sys.stderr, flush=True)
-        if inf["max_lag"] not in prior_cache:
-            prior_cache[inf["max_lag"]] = SI.saturated_history(faults, inf["max_lag"] + 2, args.seed)
-        prior = prior_cache[inf["max_lag"]]
+        n_prior = ref["n_prior"] if ref is not None else inf["max_lag"] + 8
+        assert n_prior >= inf["max_lag"] + 8
+        if n_prior not in prior_cache:
+            prior_cache[n_prior] = SI.saturated_history(faults, n_prior, args.seed)
         st = P.State(op, fric, ini["V"], ini["theta"], ini["tau0"], ini["tau0_rate"], stream=s)
-        st.load_history(prior, stream=s)
-        print(f"[bench] history loaded ({len(prior)} steps), warmup {args.warmup}", file=sys.stderr, flush=True)
-        st.step(args.warmup, stream=s)
+        st.load_history(prior_cache[n_prior], stream=s)
+        st.step(1, stream=s)
         st.check(stream=s)
-        return op, inf, st, bs
+        err = rel_sample(st)
+        print(f"[bench] history loaded ({n_prior} steps); sampled error vs oracle {err}, warmup {W}",
+              file=sys.stderr, flush=True)
+        st.step(W - 1, stream=s)
+        st.check(stream=s)
+        return op, inf, st, bs, err
 
     def alg_bytes(inf, eb):
         """Stored far-factor bytes one far launch reads: 16-bit forms keep the
@@ -430,35 +540,39 @@ def main():
             return (inf["far_entries"] - inf["far_entries_f32"]) * 2 + inf["far_entries_f32"] * 4
         return inf["far_entries"] * eb
 
-    def timed_on(st, inf, eb, S):
-        st.set_time_block(S)
+    def timed_on(st, inf, eb, S, n):
+        """n steps timed from the start of a time block: the region holds every far
+        launch its steps need (ceil(n / S)), none run before the timer starts."""
+        st.set_time_block(S)          # the next step starts a new block
         st.set_timing(True)
-        st.step(2, stream=s)          # enter the form's cadence
         st.read_timing(stream=s)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         w0 = time.perf_counter()
         e0.record(stream)
-        st.step(args.steps, stream=s)
+        st.step(n, stream=s)
         e1.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
-        ms, n = st.read_timing(stream=s)
+        ms, launches = st.read_timing(stream=s)
         st.check(stream=s)
-        avg = ms / max(n, 1)
+        want = -(-n // S)
+        assert launches == want, f"{launches} far launches for {n} steps at S = {S} (expected {want})"
+        avg = ms / max(launches, 1)
         gbs = alg_bytes(inf, eb) / (avg * 1e-3) / 1e9
-        return dict(wall=wall, ev_ms=e0.elapsed_time(e1), avg_ms=avg, launches=n, gbs=gbs)
+        return dict(wall=wall, ev_ms=e0.elapsed_time(e1), avg_ms=avg, launches=launches, gbs=gbs,
+                    value=inf_N(inf) * n / wall, ms_per_step=wall / n * 1e3)
 
-    op, info, st, build_s = prepare(args.dtype)
+    def inf_N(inf):
+        return inf["n_elem"]
+
+    op, info, st, build_s, err32 = prepare(args.dtype)
     N = op.N
     elem_bytes = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}[args.dtype]
-
-    def timed(S):
-        return timed_on(st, info, elem_bytes, S)
-
     S = info["time_block"]
-    main_run = timed(S)
-    plain = None if (args.no_plain or S == 1) else timed(1)
+    main_run = timed_on(st, info, elem_bytes, S, K)
+    steady = timed_on(st, info, elem_bytes, S, 10 * S)
+    plain = None if (args.no_plain or S == 1) else timed_on(st, info, elem_bytes, 1, K)
     wall, avg_ms, achieved = main_run["wall"], main_run["avg_ms"], main_run["gbs"]
     hmat_bytes = alg_bytes(info, elem_bytes)
     if args.dtype in ("bf16", "f16"):
@@ -473,54 +587,102 @@ def main():
     traffic = measured_traffic(kname, args)
     out = {
         "metric": METRIC,
-        "value": N * args.steps / wall,
+        "value": N * K / wall,
         "unit": "element-steps/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
+        "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": wall / K * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.dtype, "data": "synthetic",
         "config": {"workload": "five-fault SEAS step loop, 5 x 600 elements (N=3000, dx=50 m), "
                                f"{args.dtype.upper()} factors" + (" (near-field blocks and lags < 16 in FP32)" if elem_bytes == 2 else "")
-                               + f", FP64 state, ACA {args.aca:g}, eta_H 2, leaf 50, saturated history windows",
+                               + f", FP64 state, ACA {args.aca:g}, eta_H 2, leaf 50, saturated history windows, "
+                               f"time block {S}, timed from a block start",
                    "seed": args.seed, "N": N, "max_lag": info["max_lag"], "time_block": S},
+        "rel_err": err32,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kname,
                      "kernel_avg_ms": avg_ms, "algorithmic_bytes": hmat_bytes,
-                     "launches_per_step": main_run["launches"] / args.steps},
-        "gpu_event_ms_per_step": main_run["ev_ms"] / args.steps,
+                     "launches": main_run["launches"],
+                     "launches_per_step": main_run["launches"] / K},
+        "gpu_event_ms_per_step": main_run["ev_ms"] / K,
+        "steady_state": {"value": steady["value"], "ms_per_step": steady["ms_per_step"], "steps": 10 * S,
+                         "launches": steady["launches"], "kernel_avg_ms": steady["avg_ms"],
+                         "frac": steady["gbs"] / HBM_PEAK_GBS,
+                         "note": f"{10 * S} steps from a block start (whole time blocks)"},
         "build_s": build_s,
         "stored_over_dense": info["stored_entries"] / info["dense_entries"],
     }
     if plain is not None:
-        out["plain"] = {"value": N * args.steps / plain["wall"], "ms_per_step": plain["wall"] / args.steps * 1e3,
+        out["plain"] = {"value": plain["value"], "ms_per_step": plain["ms_per_step"],
                         "kernel_avg_ms": plain["avg_ms"], "achieved_GBs": plain["gbs"],
-                        "frac": plain["gbs"] / HBM_PEAK_GBS,
-                        "note": "same operator and state, lags >= S applied every step"}
-    print(f"[bench] timed {args.steps} steps: {wall:.3f} s", file=sys.stderr, flush=True)
+                        "frac": plain["gbs"] / HBM_PEAK_GBS, "rel_err": err32,
+                        "speedup_of_value": (N * K / wall) / plain["value"],
+                        "note": "same operator and state, every lag applied every step (S = 1)"}
+    print(f"[bench] timed {K} steps: {wall:.3f} s", file=sys.stderr, flush=True)
+    st.close()
+    op.close()
     if args.dtype == "f32" and not args.no_forms and S == 16:
-        # the 16-bit forms of the same workload (same geometry, state and history)
-        st.close()
-        op.close()
+        # the other forms of the same workload (same geometry, state and history)
         out["forms"] = {}
-        for d, err in (("f16", "8.2e-5 (sampled receivers vs the oracle, this workload)"),
-                       ("bf16", "5.9e-4 (sampled receivers vs the oracle, this workload)")):
-            op_d, inf_d, st_d, bs_d = prepare(d)
-            r = timed_on(st_d, inf_d, 2, 16)
-            out["forms"][d] = {"value": N * args.steps / r["wall"], "ms_per_step": r["wall"] / args.steps * 1e3,
-                               "kernel": f"k_hmat_x16<{d},16 columns>", "kernel_avg_ms": r["avg_ms"],
+        for d in ("f16", "bf16", "f64"):
+            op_d, inf_d, st_d, bs_d, err_d = prepare(d)
+            eb = {"f16": 2, "bf16": 2, "f64": 8}[d]
+            r = timed_on(st_d, inf_d, eb, 16, K)
+            r_ss = timed_on(st_d, inf_d, eb, 16, 160)
+            kn = f"k_hmat_x16<{d},16 columns>" if eb == 2 else "k_hmat<double,double,16>"
+            out["forms"][d] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
+                               "steady_state_value": r_ss["value"], "kernel": kn, "kernel_avg_ms": r["avg_ms"],
                                "achieved_GBs": r["gbs"], "frac": r["gbs"] / HBM_PEAK_GBS,
-                               "algorithmic_bytes": alg_bytes(inf_d, 2), "rel_err": err,
-                               "traffic": measured_traffic(f"k_hmat_x16<{d},16 columns>", args),
-                               "note": "admissible blocks' lags >= 16 in 16 bits; near-field blocks, lags "
-                                       "1..15 and the static tail in FP32"}
-            print(f"[bench] form {d}: {out['forms'][d]['value']:.3e} element-steps/s", file=sys.stderr, flush=True)
+                               "algorithmic_bytes": alg_bytes(inf_d, eb), "rel_err": err_d,
+                               "within_1e-4": None if err_d is None else bool(err_d <= 1e-4),
+                               "traffic": measured_traffic(kn, args), "build_s": bs_d,
+                               "note": ("admissible blocks' lags >= 16 in 16 bits; near-field blocks, lags "
+                                        "1..15 and the static tail in FP32" if eb == 2 else
+                                        "FP64 factors, history and accumulation (vector ALUs)")}
+            print(f"[bench] form {d}: {r['value']:.3e} element-steps/s, error {err_d}", file=sys.stderr,
+                  flush=True)
             st_d.close()
             op_d.close()
-    if not args.no_cpu_baseline:
-        print("[bench] oracle CPU baseline", file=sys.stderr, flush=True)
-        params = SI.default_params(factor_dtype="f64", aca_tol=args.aca, eta_H=2.0, leaf=50)
-        out["cpu_baseline"] = cpu_baseline(faults, params, prior_cache[info["max_lag"]])
+    if not args.no_two_fault:
+        # two-fault prescribed-history workload: FP64, H-matrix (ACA 1e-12), 256 steps
+        f1 = SI.two_fault_prescribed_faults()
+        p1 = SI.default_params(factor_dtype="f64", aca_tol=1e-12, time_block=16)
+        op1 = P.Operator(f1, p1)
+        V1 = ref["V1"] if ref is not None else SI.prescribed_slip_rate(f1, 256, args.seed)
+        Vd = torch.from_numpy(np.ascontiguousarray(V1)).cuda()
+        fd = torch.empty_like(Vd)
+        N1 = op1.N
+        fr1 = {k: np.full(N1, v) for k, v in (("a", 0.01), ("b", 0.015), ("Dc", 5e-3), ("sigma_n", 50e6),
+                                               ("V0", 1e-6), ("f0", 0.6))}
+        times = []
+        for rep in range(3):
+            st1 = P.State(op1, fr1, np.full(N1, 1e-9), np.full(N1, 5e6), np.zeros(N1), stream=s)
+            torch.cuda.synchronize()
+            w0 = time.perf_counter()
+            st1.eval_prescribed(Vd, 256, fd, stream=s)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - w0)
+            st1.close()
+        e1 = None
+        if ref is not None:
+            f = fd.cpu().numpy()
+            e1 = float(np.abs(f - ref["ref1"]).max() / np.abs(ref["ref1"]).max())
+        out["two_fault_fp64"] = {"value": N1 * 256 / min(times[1:]), "unit": "element-steps/s",
+                                 "ms_per_step": min(times[1:]) / 256 * 1e3, "rel_err": e1,
+                                 "workload": "two 12.8 km faults x 128 elements (N=256), prescribed slip-rate "
+                                             "history, 256 steps, FP64 H-matrix (ACA 1e-12), time block 16; "
+                                             "best of two timed repetitions after one warm one",
+                                 "cpu_oracle": cpu["two_fault_fp64"] if cpu else None}
+        op1.close()
+        print(f"[bench] two-fault FP64: {out['two_fault_fp64']['value']:.3e} element-steps/s, error {e1}",
+              file=sys.stderr, flush=True)
+    if not args.no_serving:
+        out["serving"] = serving_leg(args.seed, "f16", 3, (500, 1000, 2000), 24, 4.0, 200, 1000, 16, 64.0)
+        print(f"[bench] serving p50 {out['serving']['latency_s']['p50']:.2f} s p99 "
+              f"{out['serving']['latency_s']['p99']:.2f} s", file=sys.stderr, flush=True)
+    if cpu is not None:
+        out["cpu_baseline"] = {k: v for k, v in cpu.items() if k != "two_fault_fp64"}
     print(json.dumps(out), flush=True)
 
 

@@ -57,6 +57,26 @@ def _min_midpoint_node_distance(faults):
     return best
 
 
+def closest_to_other_faults(faults, k=8):
+    """Global indices of the k collocation points nearest another fault's segment
+    (point-to-segment distance over the input geometry; near a fault crossing the
+    stress sums of a receiver cancel most), and the smallest such distance."""
+    mids = [fault_midpoints(f) for f in faults]
+    ends = [fault_nodes(f)[[0, -1]] for f in faults]
+    dist = []
+    for a, m in enumerate(mids):
+        d = np.full(len(m), np.inf)
+        for b, e in enumerate(ends):
+            if a == b:
+                continue
+            u = e[1] - e[0]
+            t = np.clip(((m - e[0]) @ u) / (u @ u), 0.0, 1.0)
+            d = np.minimum(d, np.linalg.norm(m - (e[0] + t[:, None] * u[None, :]), axis=1))
+        dist.append(d)
+    d = np.concatenate(dist)
+    return [int(i) for i in np.argsort(d, kind="stable")[:k]], float(d.min())
+
+
 def default_params(**over):
     """Parameter set; the values the paper leaves open (leaf size, window safety
     factors, self-window factor and modulation) are fixed here."""
