@@ -59,11 +59,14 @@ typedef int32_t seas_status;
  * tail) of admissible blocks (with one variant) or of every block (ensembles)
  * are stored in 16 bits with one power-of-two FP32 scale per work item,
  * multiplied on the matrix cores against a 16-bit copy of the history with FP32
- * accumulation; F16 also scales each staged history panel and projected panel
- * by a power of two so that their values stay in range. With one variant the
- * lags applied every step are kept in FP32. BF16 ensembles keep a BF16 copy of
- * the rate history; F16 ensembles an FP32 copy. State, self term, friction and time integration are
- * FP64 in every mode. */
+ * accumulation; F16 also scales each staged history panel (per variant in
+ * ensembles) and projected panel by a power of two so that their values stay in
+ * range. With one variant the lags applied every step and the far lags of
+ * near-field blocks are kept in FP32; ensembles keep the same entries
+ * (near-field blocks, lags below 16, the static tail) in FP32. BF16 ensembles
+ * keep a BF16 copy of the rate history for their 16-bit products (their FP32
+ * entries read the FP64 history); F16 ensembles an FP32 copy. State, self term,
+ * friction and time integration are FP64 in every mode. */
 #define SEAS_F64 0
 #define SEAS_F32 1
 #define SEAS_BF16 2
@@ -342,9 +345,9 @@ seas_status seas_state_restore(seas_state_t* st, const void* host_buf, size_t by
  * for it. Requests queue per pool in arrival order. A slot whose Newton solve
  * fails ends its request with NOT_CONVERGED and the outputs of its last good
  * step; the other slots are not affected. Not an accuracy feature:
- * a request's result is the one it gets alone in a fresh state (bit for bit
- * with BF16 factors, to the FP16 tolerance with FP16 factors, whose history
- * scales see the other slots). */
+ * a request's result is the one it gets alone in a fresh state, bit for bit
+ * (every slot's product column is formed on its own, FP16 history panels with
+ * a power-of-two scale per slot). */
 typedef struct {
   int32_t pool;           /* index of the request's operator in seas_server_create */
   int32_t n_steps;        /* window length in steps (>= 1) */

@@ -81,8 +81,10 @@ struct seas_op {
   void* arena = nullptr;
   float* arena_near = nullptr;  // 16-bit operators: FP32 near-list factors
   int32_t* seg_ptr = nullptr;   // 16-bit operators: far-list segments
-  Item* items[3] = {nullptr, nullptr, nullptr};
-  int32_t *lagT = nullptr, *lagCol = nullptr, *lagColOff[3] = {nullptr, nullptr, nullptr};
+  Item* items[4] = {nullptr, nullptr, nullptr, nullptr};
+  int32_t *lagT = nullptr, *lagCol = nullptr, *lagColOff[4] = {nullptr, nullptr, nullptr, nullptr};
+  float* arena32s = nullptr;    // FP16 ensembles: FP32 segment list (list 3)
+  int32_t* seg_ptr3 = nullptr;
   int32_t *red_ptr[2] = {nullptr, nullptr}, *red_idx[2] = {nullptr, nullptr};
   int32_t *l0_ptr = nullptr, *l0_col = nullptr;
   double* l0_val = nullptr;
@@ -237,6 +239,13 @@ void eval_history(seas_op* op, seas_state* st, int64_t head, hipStream_t s) {
                       head, st->tail_acc, (float*)st->partials_far, s);
       launch_hmat_f32far(h, (int)h.items[2].size(), op->items[2], op->lagT, op->lagCol, op->lagColOff[2],
                          op->arena_near, st->ringop, head, (float*)st->partials_far, s);
+      if (h.ens32) {
+        // BF16 ensembles keep a BF16 history copy: their FP32 list reads the FP64 history
+        const bool r64 = op->ring_bytes == 2;
+        launch_hmat_seg32(h, op->items[3], op->seg_ptr3, op->lagT, op->lagCol, op->lagColOff[3], op->arena32s,
+                          r64 ? (const void*)st->ring64 : (const void*)st->ringop, r64, head, st->tail_acc,
+                          (float*)st->partials_far, s);
+      }
     } else
       launch_hmat(h, Sl, nfar, op->items[0], op->lagT, op->lagCol, op->lagColOff[0], op->arena, st->ringop, head,
                   st->tail_acc, (double*)st->partials_far, S, s);
@@ -407,6 +416,7 @@ seas_status seas_build_operator(const seas_fault_t* faults, int32_t n_faults, co
     // factor arenas, block by block
     op->arena = dalloc(op->owned, (size_t)h.arena_elems * op->elem_bytes);
     if (h.seg) op->arena_near = (float*)dalloc(op->owned, (size_t)h.arena_near_elems * 4);
+    if (h.ens32) op->arena32s = (float*)dalloc(op->owned, (size_t)h.arena32s_elems * 4);
     for (size_t bi = 0; bi < hf.off.size(); ++bi) {
       const size_t n = h.x16 ? hf.f16[bi].size()
                              : (h.seg ? hf.f32s[bi].size() : (f32 ? hf.f32[bi].size() : hf.f64[bi].size()));
@@ -419,13 +429,17 @@ seas_status seas_build_operator(const seas_fault_t* faults, int32_t n_faults, co
       if (h.seg && !hf.f32[bi].empty())
         HIPCHK(hipMemcpy(op->arena_near + hf.off32[bi], hf.f32[bi].data(), hf.f32[bi].size() * 4,
                          hipMemcpyHostToDevice));
+      if (h.ens32 && !hf.f32s[bi].empty())
+        HIPCHK(hipMemcpy(op->arena32s + hf.off3[bi], hf.f32s[bi].data(), hf.f32s[bi].size() * 4,
+                         hipMemcpyHostToDevice));
       std::vector<double>().swap(hf.f64[bi]);
       std::vector<float>().swap(hf.f32[bi]);
       std::vector<uint16_t>().swap(hf.f16[bi]);
       std::vector<float>().swap(hf.f32s[bi]);
     }
     if (h.seg) op->seg_ptr = upload(op->owned, h.seg_ptr);
-    for (int L = 0; L < 3; ++L) {
+    if (h.ens32) op->seg_ptr3 = upload(op->owned, h.seg_ptr3);
+    for (int L = 0; L < 4; ++L) {
       op->items[L] = upload(op->owned, h.items[L]);
       op->lagColOff[L] = upload(op->owned, h.lagColOff[L]);
     }
@@ -535,15 +549,15 @@ seas_status seas_operator_lag_matrix(const seas_op_t* op, int32_t a, int32_t b, 
         return h.prm.factor_dtype == SEAS_BF16 ? (double)from_bf16(hf.f16[lo][k]) : (double)from_f16(hf.f16[lo][k]);
       return which == 1 ? (double)hf.f32[lo][k] : hf.f64[lo][k];
     };
-    for (int L = 0; L < 3; ++L)
+    for (int L = 0; L < 4; ++L)
     for (size_t ii = 0; ii < h.items[L].size(); ++ii) {
       const Item& it = h.items[L][ii];
       if (it.row0 < A.off || it.row0 >= A.off + p_all || it.col0 < B.off || it.col0 >= B.off + q_all) continue;
       const int ri = it.row0 - A.off, cj = it.col0 - B.off;
       const int32_t* cp = &h.lagCol[h.lagColOff[L][ii]];
-      const bool sg = h.seg && L == 0;
-      const int which = sg ? (h.x16 ? 2 : 3) : ((h.seg || h.prm.factor_dtype == SEAS_F32) ? 1 : 0);
-      const std::vector<int64_t>& off = (h.seg && L >= 1) ? hf.off32 : hf.off;
+      const bool sg = h.seg && (L == 0 || L == 3);
+      const int which = sg ? ((h.x16 && L == 0) ? 2 : 3) : ((h.seg || h.prm.factor_dtype == SEAS_F32) ? 1 : 0);
+      const std::vector<int64_t>& off = L == 3 ? hf.off3 : ((h.seg && L >= 1) ? hf.off32 : hf.off);
       auto elem = [&](int64_t e) { return elem_in(off, e, which); };
       for (int l = 0; l < it.nlag; ++l) {
         if (h.lagT[it.lag_off + l] != T) continue;
@@ -602,8 +616,9 @@ seas_status seas_operator_info(const seas_op_t* op, seas_op_info_t* out) {
     int64_t far = 0, far32 = 0;
     for (const Item& it : h.items[0])
       far += it.kind == 0 ? (int64_t)it.ncol * (it.p + it.q) : (int64_t)it.nlag * it.p * it.q;
-    for (const Item& it : h.items[2])
-      far32 += it.kind == 0 ? (int64_t)it.ncol * (it.p + it.q) : (int64_t)it.nlag * it.p * it.q;
+    for (int L = 2; L < 4; ++L)
+      for (const Item& it : h.items[L])
+        far32 += it.kind == 0 ? (int64_t)it.ncol * (it.p + it.q) : (int64_t)it.nlag * it.p * it.q;
     out->far_entries = far + far32;
     out->far_entries_f32 = far32;
     out->dense_entries = h.dense_entries;
@@ -629,6 +644,10 @@ seas_status seas_operator_info(const seas_op_t* op, seas_op_info_t* out) {
     }
     for (const Item& it : h.items[2])
       fb += 4 * (it.kind == 0 ? (int64_t)it.ncol * (it.p + it.q) : (int64_t)it.nlag * it.p * it.q);
+    for (const Item& it : h.items[3]) {
+      const int64_t q8 = round8(it.q);
+      fb += 4 * (it.kind == 0 ? (int64_t)it.ncol * q8 + (int64_t)it.p * round8(it.ncol) : (int64_t)it.nlag * it.p * q8);
+    }
     out->far_bytes = fb;
   });
 }

@@ -318,8 +318,8 @@ struct LagFactor {
 // holds the lags 1..S-1 and the static tail, applied every step. With S = 1 every
 // lag and the tail are in list 0.
 struct BlockOut {
-  std::vector<Item> items[3];
-  std::vector<int32_t> lagT[3], lagCol[3];
+  std::vector<Item> items[4];
+  std::vector<int32_t> lagT[4], lagCol[4];
   std::vector<double> d64;
   std::vector<float> d32;
   std::vector<uint16_t> d16;
@@ -420,7 +420,8 @@ static void pack_list(int r0, int r1, int s0, int s1, const Fault& A, const Faul
 // history (span * nv * q8 values), the projected panel (ncol8 * ncols values) and
 // the lag count.
 static void pack_seg(int r0, int r1, int s0, int s1, const Fault& A, const Fault& B,
-                     std::vector<LagFactor*>& lags, int dtype, int tail_off, int S, int nv, BlockOut& out) {
+                     std::vector<LagFactor*>& lags, int dtype, int tail_off, int S, int nv, BlockOut& out,
+                     int L = 0) {
   const int p = r1 - r0, q = s1 - s0, q8 = round8(q);
   const int ncols = S * nv;
   const bool f32 = dtype == SEAS_F32;
@@ -462,17 +463,17 @@ static void pack_seg(int r0, int r1, int s0, int s1, const Fault& A, const Fault
     it.row0 = A.off + r0;
     it.col0 = B.off + s0;
     it.nlag = (int)(j - i);
-    it.lag_off = (int)out.lagT[0].size();
+    it.lag_off = (int)out.lagT[L].size();
     it.ncol = ncol;
     it.tail_off = tail ? tail_off + s0 : 0;
-    for (size_t l = i; l < j; ++l) out.lagT[0].push_back(lags[l]->T);
-    out.lagCol[0].push_back(0);
+    for (size_t l = i; l < j; ++l) out.lagT[L].push_back(lags[l]->T);
+    out.lagCol[L].push_back(0);
     if (lr) {
       int c = 0;
       double mw = 0.0, mu = 0.0;
       for (size_t l = i; l < j; ++l) {
         c += lags[l]->rank;
-        out.lagCol[0].push_back(c);
+        out.lagCol[L].push_back(c);
         for (double v : lags[l]->W) mw = std::max(mw, std::fabs(v));
         for (double v : lags[l]->U) mu = std::max(mu, std::fabs(v));
       }
@@ -488,7 +489,7 @@ static void pack_seg(int r0, int r1, int s0, int s1, const Fault& A, const Fault
         for (int cc = ncol; cc < ncol8; ++cc) put(0.0);
       }
     } else {
-      for (int l = 0; l < it.nlag; ++l) out.lagCol[0].push_back(0);
+      for (int l = 0; l < it.nlag; ++l) out.lagCol[L].push_back(0);
       double md = 0.0;
       for (size_t l = i; l < j; ++l)
         for (double v : lags[l]->D) md = std::max(md, std::fabs(v));
@@ -499,7 +500,7 @@ static void pack_seg(int r0, int r1, int s0, int s1, const Fault& A, const Fault
           for (int jj = 0; jj < q8; ++jj) put(jj < q ? lags[l]->D[(size_t)ii * q + jj] / sd : 0.0);
     }
     out.stored += elems;
-    out.items[0].push_back(it);
+    out.items[L].push_back(it);
     for (size_t l = i; l < j; ++l) {
       std::vector<double>().swap(lags[l]->U);
       std::vector<double>().swap(lags[l]->W);
@@ -524,6 +525,9 @@ static void build_subblock(const HostOp& op, const BlockDesc& bd, const PairWin&
   // lag's columns must fit the LDS column buffer of the kernel
   int kmax = std::min<int>({(int)(((int64_t)p * q) / (p + q)), kColMax, kZMax / S});
   if (op.seg) kmax = std::min(kmax, ((seg_z_limit(op.ncols, op.seg_eb) / op.ncols) & ~7) - 8);
+  // ensembles: lags that go to the FP32 list (list 3) meet its projection buffer
+  const int kmax32 = op.ens32 ? std::min(kmax, ((seg_z_limit(op.ncols, 4) / op.ncols) & ~7) - 8) : kmax;
+  auto in_list3 = [&](int T) { return op.ens32 && !(bd.adm && T >= kEnsSplit); };
   const PairFrame fr = frame(A, B);
   // The corners r1' +- ds/2 of source element j are the offsets of its two edges,
   // and adjacent elements share an edge: the primitive is evaluated once per edge
@@ -557,7 +561,7 @@ static void build_subblock(const HostOp& op, const BlockDesc& bd, const PairWin&
     lf.T = T;
     lf.rank = 0;
     if (lowrank_ok) {
-      const int k = aca_full(K.data(), p, q, op.prm.aca_tol, kmax, U, W, R);
+      const int k = aca_full(K.data(), p, q, op.prm.aca_tol, in_list3(T) ? kmax32 : kmax, U, W, R);
       if (k > 0) {
         lf.rank = k;  // U: k columns of length p, W: k columns of length q
         lf.U = U;
@@ -593,6 +597,17 @@ static void build_subblock(const HostOp& op, const BlockDesc& bd, const PairWin&
     if (S == 1 || (lf.T >= S)) far.push_back(&lf);
     else near.push_back(&lf);
   }
+  if (op.ens32) {
+    // ensembles: the same split as one variant's time-blocked form, admissible
+    // blocks' lags >= kEnsSplit in 16 bits, the rest (near-field blocks, the early
+    // lags, the static tail) in FP32 on list 3
+    std::vector<LagFactor*> l16, l32;
+    for (LagFactor* lf : far) (in_list3(lf->T) ? l32 : l16).push_back(lf);
+    pack_seg(bd.r0, bd.r1, s0, s1, A, B, l16, op.prm.factor_dtype, toff, S, op.n_variants, out, 0);
+    pack_seg(bd.r0, bd.r1, s0, s1, A, B, l32, SEAS_F32, toff, S, op.n_variants, out, 3);
+    pack_list(bd.r0, bd.r1, s0, s1, A, B, near, true, toff, 1, 1, out);
+    return;
+  }
   if (op.seg) {
     // 16-bit near-field blocks (one variant): far lags in FP32. Their entries span
     // the near-singular range of receivers close to a source (fault crossings), and
@@ -619,6 +634,7 @@ static void build_block(const HostOp& op, const BlockDesc& bd, const PairWin& pw
   // (slices as narrow as one default panel: wider slices need ranks above the cap)
   // (FP32 segment builds keep the FP32 slices, which fit their staging buffer)
   if (op.seg) qmax = std::min(op.x16 ? kHistMax : qmax, ((kHist16 * 2 / op.seg_eb / op.ncols) & ~7) - 8);
+  if (op.ens32) qmax = std::min(qmax, ((seg_hist_limit(op.ncols, 4) / op.n_variants) & ~7) - 8);
   const int pmax = (op.seg && op.n_variants > 1) ? seg_rows_max(op.ncols) : bd.r1 - bd.r0;
   const int nrs = (bd.r1 - bd.r0 + pmax - 1) / pmax;
   for (int k = 0; k < nrs; ++k) {
@@ -674,6 +690,7 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
   op.seg = op.x16 || (prm.factor_dtype == SEAS_F32 && op.time_block == 16 && op.use_mfma &&
                       std::getenv("SEAS_NO_SEG") == nullptr);
   op.seg_eb = op.x16 ? 2 : 4;
+  op.ens32 = op.x16 && op.n_variants > 1;
   if (prm.n_threads > 0) omp_set_num_threads(prm.n_threads);
   // ---- geometry
   op.faults.clear();
@@ -812,10 +829,12 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
   }
   if (!err.empty()) throw Error(SEAS_ERR_INTERNAL, "block build failed: " + err);
   // ---- global item lists, arena offsets, partial layouts
-  for (int L = 0; L < 3; ++L) {
+  for (int L = 0; L < 4; ++L) {
     op.items[L].clear();
     op.lagColOff[L].clear();
   }
+  op.seg_ptr3.clear();
+  op.arena32s_elems = 0;
   op.n_partials[0] = op.n_partials[1] = 0;
   op.lagT.clear();
   op.lagCol.clear();
@@ -832,19 +851,23 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
   hf.f32s.assign(all.size(), {});
   hf.off.assign(all.size(), 0);
   hf.off32.assign(all.size(), 0);
-  std::vector<int32_t> colOff[3];  // lagCol offset of each item, in build order
+  hf.off3.assign(all.size(), 0);
+  std::vector<int32_t> colOff[4];  // lagCol offset of each item, in build order
   for (size_t bi = 0; bi < all.size(); ++bi) {
     BlockOut& bo = outs[bi];
     hf.off[bi] = op.arena_elems;
     hf.off32[bi] = op.arena_near_elems;
-    for (int L = 0; L < 3; ++L) {
+    hf.off3[bi] = op.arena32s_elems;
+    for (int L = 0; L < 4; ++L) {
       const int lag_base = (int)op.lagT.size();
       int col_cursor = (int)op.lagCol.size();
-      // segment operators: the near list and list 2 live in the FP32 near arena
-      const int64_t base = (op.seg && L >= 1) ? op.arena_near_elems : op.arena_elems;
+      // segment operators: the near list and list 2 live in the FP32 near arena,
+      // list 3 in its own FP32 arena
+      const int64_t base = L == 3 ? op.arena32s_elems
+                                  : ((op.seg && L >= 1) ? op.arena_near_elems : op.arena_elems);
       for (Item it : bo.items[L]) {
         it.data += base;
-        if (!op.seg || L >= 1) it.scale = 1.0f;
+        if (!op.seg || L == 1 || L == 2) it.scale = 1.0f;
         colOff[L].push_back(col_cursor);
         col_cursor += it.nlag + 1;
         it.lag_off += lag_base;
@@ -855,6 +878,7 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
     }
     if (op.seg) {
       op.arena_elems += op.x16 ? (int64_t)bo.d16.size() : (int64_t)bo.s32.size();
+      if (op.ens32) op.arena32s_elems += (int64_t)bo.s32.size();
       op.arena_near_elems += (int64_t)bo.d32.size();
       hf.f16[bi].swap(bo.d16);
       hf.f32s[bi].swap(bo.s32);
@@ -870,77 +894,73 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
   // segment far list: items with the same receiver rows are ordered next to each
   // other and grouped into segments, one workgroup each, that keep the sums of
   // their rows in registers and write one partial set; rows beyond what the
-  // registers hold make single-item segments.
-  if (op.seg) {
-    std::vector<size_t> ord(op.items[0].size());
+  // registers hold make single-item segments. (FP16 ensembles: also list 3.)
+  auto make_segments = [&](std::vector<Item>& items, std::vector<int32_t>& colOffL, std::vector<int32_t>& seg_ptr,
+                           int eb) {
+    std::vector<size_t> ord(items.size());
     std::iota(ord.begin(), ord.end(), 0);
     std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) {
-      const Item &a = op.items[0][x], &b = op.items[0][y];
+      const Item &a = items[x], &b = items[y];
       return a.row0 != b.row0 ? a.row0 < b.row0 : a.p < b.p;
     });
     std::vector<Item> its;
     std::vector<int32_t> co;
     for (size_t x : ord) {
-      its.push_back(op.items[0][x]);
-      co.push_back(colOff[0][x]);
+      its.push_back(items[x]);
+      co.push_back(colOffL[x]);
     }
-    op.items[0].swap(its);
-    colOff[0].swap(co);
+    items.swap(its);
+    colOffL.swap(co);
     const int rmax = seg_rows_max(op.ncols);
     auto vals = [](const Item& it) {
       const int64_t q8 = round8(it.q);
       return it.kind == 0 ? (int64_t)it.ncol * q8 + (int64_t)it.p * round8(it.ncol) : (int64_t)it.nlag * it.p * q8;
     };
+    seg_ptr.clear();
     size_t k = 0;
-    while (k < op.items[0].size()) {
-      const Item& f = op.items[0][k];
+    while (k < items.size()) {
+      const Item& f = items[k];
       size_t e = k + 1;
       int64_t v = vals(f);
       if (f.p <= rmax)
-        while (e < op.items[0].size() && op.items[0][e].row0 == f.row0 && op.items[0][e].p == f.p &&
-               v + vals(op.items[0][e]) <= kSegElems * 2 / op.seg_eb)
-          v += vals(op.items[0][e++]);
-      op.seg_ptr.push_back((int32_t)k);
+        while (e < items.size() && items[e].row0 == f.row0 && items[e].p == f.p &&
+               v + vals(items[e]) <= kSegElems * 2 / eb)
+          v += vals(items[e++]);
+      seg_ptr.push_back((int32_t)k);
       k = e;
     }
-    op.seg_ptr.push_back((int32_t)op.items[0].size());
+    seg_ptr.push_back((int32_t)items.size());
     // workgroups start in segment order: largest segments first, so that the
     // small ones fill in at the end of the pass
-    {
-      const size_t ns = op.seg_ptr.size() - 1;
-      std::vector<int64_t> sz(ns, 0);
-      for (size_t g = 0; g < ns; ++g)
-        for (int32_t x = op.seg_ptr[g]; x < op.seg_ptr[g + 1]; ++x) sz[g] += vals(op.items[0][x]);
-      std::vector<size_t> so(ns);
-      std::iota(so.begin(), so.end(), 0);
-      std::stable_sort(so.begin(), so.end(), [&](size_t x, size_t y) { return sz[x] > sz[y]; });
-      std::vector<Item> its2;
-      std::vector<int32_t> co2, sp2;
-      for (size_t g : so) {
-        sp2.push_back((int32_t)its2.size());
-        for (int32_t x = op.seg_ptr[g]; x < op.seg_ptr[g + 1]; ++x) {
-          its2.push_back(op.items[0][x]);
-          co2.push_back(colOff[0][x]);
-        }
-      }
+    const size_t ns = seg_ptr.size() - 1;
+    std::vector<int64_t> sz(ns, 0);
+    for (size_t g = 0; g < ns; ++g)
+      for (int32_t x = seg_ptr[g]; x < seg_ptr[g + 1]; ++x) sz[g] += vals(items[x]);
+    std::vector<size_t> so(ns);
+    std::iota(so.begin(), so.end(), 0);
+    std::stable_sort(so.begin(), so.end(), [&](size_t x, size_t y) { return sz[x] > sz[y]; });
+    std::vector<Item> its2;
+    std::vector<int32_t> co2, sp2;
+    for (size_t g : so) {
       sp2.push_back((int32_t)its2.size());
-      op.items[0].swap(its2);
-      colOff[0].swap(co2);
-      op.seg_ptr.swap(sp2);
+      for (int32_t x = seg_ptr[g]; x < seg_ptr[g + 1]; ++x) {
+        its2.push_back(items[x]);
+        co2.push_back(colOffL[x]);
+      }
     }
-  }
-  // invariants the segment kernel relies on (LDS panel sizes, 16-byte alignment,
-  // one row range per segment, register-held rows of multi-item segments)
-  if (op.seg) {
-    const int eb = op.seg_eb;
-    const int rmax = seg_rows_max(op.ncols);
-    for (size_t sg = 0; sg + 1 < op.seg_ptr.size(); ++sg) {
-      const int32_t a = op.seg_ptr[sg], b = op.seg_ptr[sg + 1];
+    sp2.push_back((int32_t)its2.size());
+    items.swap(its2);
+    colOffL.swap(co2);
+    seg_ptr.swap(sp2);
+    // invariants the segment kernel relies on (LDS panel sizes, 16-byte alignment,
+    // one row range per segment, register-held rows of multi-item segments)
+    for (size_t sg = 0; sg + 1 < seg_ptr.size(); ++sg) {
+      const int32_t a = seg_ptr[sg], b = seg_ptr[sg + 1];
       if (b <= a) throw Error(SEAS_ERR_INTERNAL, "empty segment");
-      const Item& f = op.items[0][a];
+      const Item& f = items[a];
       if (b - a > 1 && f.p > rmax) throw Error(SEAS_ERR_INTERNAL, "tall block in a multi-item segment");
       for (int32_t x = a; x < b; ++x) {
-        const Item& it = op.items[0][x];
+        const Item& it = items[x];
         const int q8 = round8(it.q);
         const int span = it.src == 0 ? it.nlag + S - 1 : 1;
         if (it.row0 != f.row0 || it.p != f.p || it.p < 1 || it.q < 1 || it.nlag < 1 ||
@@ -951,7 +971,9 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
           throw Error(SEAS_ERR_INTERNAL, "segment item violates the kernel's limits");
       }
     }
-  }
+  };
+  if (op.seg) make_segments(op.items[0], colOff[0], op.seg_ptr, op.seg_eb);
+  if (op.ens32) make_segments(op.items[3], colOff[3], op.seg_ptr3, 4);
   // partial offsets: per item, or per segment on the segment far list (far
   // partials are [p][S] or [p][ncols], row-major)
   for (int L = 0; L < 2; ++L) {
@@ -976,6 +998,12 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
     op.n_partials[0] += (int64_t)it.p * op.ncols;
   }
   op.lagColOff[2] = colOff[2];
+  for (size_t sg = 0; sg + 1 < op.seg_ptr3.size(); ++sg) {  // list 3: per segment, in list 0's buffer
+    const int32_t part = (int32_t)op.n_partials[0];
+    for (int32_t x = op.seg_ptr3[sg]; x < op.seg_ptr3[sg + 1]; ++x) op.items[3][x].part = part;
+    op.n_partials[0] += (int64_t)op.items[3][op.seg_ptr3[sg]].p * op.ncols;
+  }
+  op.lagColOff[3] = colOff[3];
   if (op.n_partials[0] > INT32_MAX || op.n_partials[1] > INT32_MAX || (int64_t)op.lagT.size() > INT32_MAX)
     throw Error(SEAS_ERR_INTERNAL, "operator too large for 32-bit item offsets");
   // reduction lists per receiver, in item (segment) order: the base index of the
@@ -988,6 +1016,7 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
     if (op.seg && L == 0) {
       for (size_t sg = 0; sg + 1 < op.seg_ptr.size(); ++sg) heads.push_back(&op.items[0][op.seg_ptr[sg]]);
       for (const Item& it : op.items[2]) heads.push_back(&it);
+      for (size_t sg = 0; sg + 1 < op.seg_ptr3.size(); ++sg) heads.push_back(&op.items[3][op.seg_ptr3[sg]]);
     } else {
       for (const Item& it : op.items[L]) heads.push_back(&it);
     }

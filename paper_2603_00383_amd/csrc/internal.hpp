@@ -61,8 +61,9 @@ constexpr int kHist16 = 16384;   // 16-bit history values staged per item: span 
 // stage twice the history per item
 inline int hist16_limit(int ncols) { return ncols >= 32 ? 2 * kHist16 : kHist16; }
 constexpr int kZ16 = 4096;       // 16-bit projected values per low-rank item: ncol8 * columns
-// (the last 8 values of the kernel's buffer hold the staging maximum)
-inline int z16_limit(int ncols) { return (ncols >= 32 ? 2 * kZ16 : kZ16) - 8; }
+// (the end of the kernel's buffer holds the staging maxima: one per wave, or
+// one per variant for scaled ensemble panels, 2 x 16 or 2 x 64 16-bit slots)
+inline int z16_limit(int ncols) { return (ncols >= 32 ? 2 * kZ16 : kZ16) - (ncols >= 32 ? 128 : 32); }
 constexpr int kMaxVariants = 64;
 constexpr int64_t kSegElems = 1 << 19;  // 16-bit factor values per segment (one workgroup; 1 MiB)
 inline int round8(int x) { return (x + 7) & ~7; }
@@ -72,10 +73,16 @@ inline int ld16(int q8) { return ((q8 >> 3) & 1) ? q8 : q8 + 8; }
 // rows of a multi-item segment: its accumulators stay in registers
 inline int seg_rows_max(int ncols) { return ncols == 16 ? 512 : 256; }
 // Segment far list (matrix-core kernel) with eb bytes per stored value: 2 for
-// BF16 / FP16, 4 for FP32 (one variant, 16 columns). The FP32 form stages the
+// BF16 / FP16, 4 for FP32 (16 windows of one variant, or the FP32 list of FP16
+// ensembles). The FP32 form stages the
 // same LDS bytes as the 16-bit one, so half as many values.
-inline int seg_hist_limit(int ncols, int eb) { return eb == 2 ? hist16_limit(ncols) : kHist16 / 2; }
-inline int seg_z_limit(int ncols, int eb) { return eb == 2 ? z16_limit(ncols) : kZ16 / 2 - 4; }
+inline int seg_hist_limit(int ncols, int eb) { return eb == 2 ? hist16_limit(ncols) : hist16_limit(ncols) / 2; }
+inline int seg_z_limit(int ncols, int eb) {
+  return eb == 2 ? z16_limit(ncols) : (ncols >= 32 ? 2 * kZ16 : kZ16) / 2 - 4;
+}
+// ensembles: lags below this of admissible blocks, every lag of near-field
+// blocks and the static tail are kept in FP32 (list 3)
+constexpr int kEnsSplit = 16;
 // LDS row stride of q8 staged values: an odd number of 16-byte groups
 inline int seg_ld(int q8, int eb) {
   const int g = 16 / eb;
@@ -122,10 +129,18 @@ struct HostOp {
   // list 2 (16-bit builds with one variant): the far lags of near-field (not
   // admissible) blocks, kept in FP32 and applied with list 0 by the FP32 matrix-core
   // pass; their partials share list 0's buffer and reduction lists
-  std::vector<Item> items[3];
+  // list 3 (ensembles, ens32): near-field blocks, lags below kEnsSplit of
+  // admissible blocks and the static tail, in FP32 in the segment layout, applied
+  // by the FP32 instance of the segment kernel (segments seg_ptr3, arena of
+  // arena32s_elems values) on the FP32 history copy (FP16) or the FP64 history
+  // (BF16, whose copy is BF16); partials and reduction lists shared with list 0
+  std::vector<Item> items[4];
   std::vector<int32_t> lagT;          // nlag lag values per item (ascending)
   std::vector<int32_t> lagCol;        // nlag+1 column prefix per item
-  std::vector<int32_t> lagColOff[3];  // per item: offset into lagCol
+  std::vector<int32_t> lagColOff[4];  // per item: offset into lagCol
+  bool ens32 = false;
+  std::vector<int32_t> seg_ptr3;
+  int64_t arena32s_elems = 0;
   int64_t arena_elems = 0;
   int64_t arena_near_elems = 0;       // segment operators: FP32 arena of the near list
   std::vector<int32_t> seg_ptr;       // segment operators: far items of each segment (workgroup)
@@ -151,13 +166,14 @@ struct HostOp {
 // Factor values per block, in block order, and each block's offsets in the arenas.
 // F64 / F32 operators: one arena (f64 or f32, offsets `off`). Segment operators:
 // the far list in f16 (bit patterns of BF16 or FP16) or f32s (FP32), offsets
-// `off`, and the near list in f32 (offsets `off32`).
+// `off`, and the near list in f32 (offsets `off32`). Ensembles: list 3 in f32s
+// (offsets `off3`).
 struct HostFactors {
   std::vector<std::vector<double>> f64;
   std::vector<std::vector<float>> f32;
   std::vector<std::vector<uint16_t>> f16;
   std::vector<std::vector<float>> f32s;
-  std::vector<int64_t> off, off32;
+  std::vector<int64_t> off, off32, off3;
 };
 
 // message returned by seas_last_error() on the calling thread (api.hip)

@@ -85,6 +85,12 @@ void launch_clear_variant(void* base, int64_t rows, int nv, int v, int N, int el
 void launch_hmat_x16(const HostOp& h, const void* items, const int32_t* seg_ptr, const int32_t* lagT,
                      const int32_t* lagCol, const int32_t* lagColOff, const void* arena, const void* ring,
                      int64_t head, const double* tail_acc, float* partials, hipStream_t s);
+// ensembles: list 3 (FP32, segment layout) on the FP32 instance of the segment
+// kernel, nv columns, staged from an FP32 (ring_f64 = false) or FP64 rate ring laid
+// out [R][nv][N]; partials in list 0's buffer
+void launch_hmat_seg32(const HostOp& h, const void* items, const int32_t* seg_ptr, const int32_t* lagT,
+                       const int32_t* lagCol, const int32_t* lagColOff, const float* arena, const void* ring,
+                       bool ring_f64, int64_t head, const double* tail_acc, float* partials, hipStream_t s);
 // FP32 far items of a 16-bit build (near-field blocks), S = 16 windows on the
 // matrix cores, FP32 partials [p][16] in the 16-bit far list's partial buffer
 void launch_hmat_f32far(const HostOp& h, int n_items, const void* items, const int32_t* lagT, const int32_t* lagCol,

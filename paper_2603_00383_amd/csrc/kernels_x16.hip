@@ -144,8 +144,10 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
   __shared__ __attribute__((aligned(16))) T16 h[HL];
   constexpr int ZL = (NT >= 2 ? 2 * kZ16 : kZ16) * 2 / EB;
   __shared__ __attribute__((aligned(16))) T16 z[ZL];
-  // the staging maximum lives in z's last 16 bytes, which projected panels never use
+  // the staging maxima live at the end of z, which projected panels never use:
+  // one per wave (smax), or one per variant (smv) for scaled ensemble panels
   float* smax = reinterpret_cast<float*>(z + ZL - G);
+  float* smv = reinterpret_cast<float*>(z + ZL) - nv;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, g = lane >> 4;
   const int nv_shift = __builtin_ctz((unsigned)nv);  // nv is a power of two
   const int x0 = seg_ptr[blockIdx.x], x1 = seg_ptr[blockIdx.x + 1];
@@ -196,7 +198,50 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
       return (float)ring[(sl * nv + v) * (int64_t)N + it.col0 + j];
     };
     float hs = 1.0f;
-    if (VFAST && it.src == 0) {
+    // scaled ensembles (S = 1): every staged row belongs to one variant, so each
+    // variant's rows get their own power of two, and a variant slipping fast does
+    // not push another's small rates below FP16's range
+    const bool per_variant = SCALE && nv > 1;
+    if (per_variant) {
+      for (int v = tid; v < nv; v += kItemThreads) smv[v] = 0.0f;
+      __syncthreads();
+      for (int e0 = tid; e0 < tot; e0 += 8 * kItemThreads) {
+        float x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int e = e0 + u * kItemThreads;
+          x[u] = e < tot ? hval(e) : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int e = e0 + u * kItemThreads;
+          if (e < tot) {
+            const int rv = (int)(((float)e + 0.5f) * inv_q8s);
+            // non-negative floats order like their bit patterns
+            atomicMax(reinterpret_cast<int*>(smv + (rv & (nv - 1))), __float_as_int(fabsf(x[u])));
+          }
+        }
+      }
+      __syncthreads();
+      for (int v = tid; v < nv; v += kItemThreads) smv[v] = pow2_at_least(smv[v]);
+      __syncthreads();
+      for (int e0 = tid; e0 < tot; e0 += 8 * kItemThreads) {
+        float x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int e = e0 + u * kItemThreads;
+          x[u] = e < tot ? hval(e) : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int e = e0 + u * kItemThreads;
+          if (e < tot) {
+            const int rv = (int)(((float)e + 0.5f) * inv_q8s);
+            h[e + rv * (ldh - q8)] = Mx<T16>::cvt(x[u] / smv[rv & (nv - 1)]);
+          }
+        }
+      }
+    } else if (VFAST && it.src == 0) {
       // 16-bit history copy laid out [R][N][nv]. A thread takes a tile of 8
       // sources x 8 variants: 8 aligned 16-byte loads (one per source, 8 variants
       // each; the 8 lanes of a group read one 128-byte row segment), a transpose
@@ -293,6 +338,11 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
     __syncthreads();
     const T16* base = arena + it.data;
     float sc = it.scale * hs;
+    // the scale of each of this lane's product columns (column n = variant n when
+    // per_variant)
+    float sct[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) sct[t] = per_variant ? it.scale * smv[(t * 16 + l16) & (nv - 1)] : sc;
     int E, stride, zld = 0;
     const T16* M;
     if (it.kind == 0) {
@@ -304,6 +354,8 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
       if (SCALE) {
         zs = 1.0f / pow2_at_least((float)q8);
         sc /= zs;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) sct[t] /= zs;
       }
       // Lag l has ceil(rank_l / 16) tiles of 16 columns; the item's tiles, numbered
       // lag after lag, are dealt round robin to the waves. A wave runs its tiles as
@@ -434,7 +486,7 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
         for (int uu = 0; uu < RW; ++uu) {
           if (uu == u) {
 #pragma unroll
-            for (int t = 0; t < NT; ++t) acc[uu][t] += sc * tmp[t];
+            for (int t = 0; t < NT; ++t) acc[uu][t] += sct[t] * tmp[t];
           }
         }
       } else {  // single-item segment of a tall block (wide): write this row tile
@@ -443,7 +495,7 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int ii = rt * 16 + 4 * g + v;
-            if (ii < p) out[ii * NC + t * 16 + l16] = sc * tmp[t][v];
+            if (ii < p) out[ii * NC + t * 16 + l16] = sct[t] * tmp[t][v];
           }
         }
       }
@@ -492,8 +544,8 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
 template <typename T16, typename TR, bool SCALE, int NT, bool VFAST = false>
 static void x16_launch(const HostOp& h, const void* items, const int32_t* seg_ptr, const int32_t* lagT,
                        const int32_t* lagCol, const int32_t* lagColOff, const void* arena, const void* ring,
-                       int64_t head, const double* tail_acc, float* partials, hipStream_t s) {
-  const int nseg = (int)h.seg_ptr.size() - 1;
+                       int64_t head, const double* tail_acc, float* partials, hipStream_t s, int nseg = -1) {
+  if (nseg < 0) nseg = (int)h.seg_ptr.size() - 1;
   hipLaunchKernelGGL((k_hmat_x16<T16, TR, SCALE, NT, VFAST>), dim3(nseg), dim3(kItemThreads), 0, s, (const Item*)items,
                      seg_ptr, lagT, lagCol, lagColOff, (const T16*)arena, (const TR*)ring, head, (int64_t)h.ring_len,
                      h.N, h.time_block, h.n_variants, tail_acc, (int64_t)h.tail_len, partials);
@@ -527,6 +579,25 @@ void launch_hmat_x16(const HostOp& h, const void* items, const int32_t* seg_ptr,
     default: break;
   }
 #undef SEAS_X16_ENS
+}
+
+void launch_hmat_seg32(const HostOp& h, const void* items, const int32_t* seg_ptr, const int32_t* lagT,
+                       const int32_t* lagCol, const int32_t* lagColOff, const float* arena, const void* ring,
+                       bool ring_f64, int64_t head, const double* tail_acc, float* partials, hipStream_t s) {
+  const int nseg = (int)h.seg_ptr3.size() - 1;
+  if (nseg < 1) return;
+#define SEAS_SEG32(NT)                                                                                         \
+  if (ring_f64) x16_launch<float, double, false, NT>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head, \
+                                                      tail_acc, partials, s, nseg);                             \
+  else x16_launch<float, float, false, NT>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head, tail_acc, \
+                                           partials, s, nseg);
+  switch (h.ncols) {
+    case 16: SEAS_SEG32(1) break;
+    case 32: SEAS_SEG32(2) break;
+    case 64: SEAS_SEG32(4) break;
+    default: break;
+  }
+#undef SEAS_SEG32
 }
 
 }  // namespace seas

@@ -1,13 +1,16 @@
 """Full-size parity of the ensemble path (eight 750-element faults, 64 variants,
 BF16 and FP16 factors): every variant gets the same seeded slip-rate history
 and near-nucleation state, so each variant's interaction history part must be
-the oracle's; sampled receivers are compared, and all 64 variants must agree
-with each other bit for bit (BF16: product columns are formed on their own).
+the oracle's; sampled receivers (with the ones nearest a fault crossing) are
+compared, and all 64 variants must agree with each other bit for bit (product
+columns are formed on their own, FP16 panels with a scale per variant).
 
 The prior history covers 1200 steps (the longest windows are ~3500 lags: the
 older lags multiply zero history, the static tail and lags up to 1200 are
-exercised). Tolerances: those of the small ensemble tests, 8e-3 (BF16) and
-2e-3 (FP16); the errors are printed."""
+exercised). Both formats keep near-field blocks, lags below 16 and the static
+tail in FP32 (BF16 ensembles stage those from the FP64 history). Tolerances:
+those of the small ensemble tests, 8e-3 (BF16, outside the 1e-4 band) and 1e-4
+(FP16); the errors are printed."""
 import numpy as np
 import pytest
 
@@ -20,10 +23,10 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 P = pytest.importorskip("paper_2603_00383_amd")
 
-TOL = {"bf16": 8e-3, "f16": 2e-3}
+TOL = {"bf16": 8e-3, "f16": 1e-4}
 
 
-@pytest.mark.parametrize("dtype", ["bf16"])
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
 def test_ensemble_fullsize_history_part(dtype, loud):
     if not torch.cuda.is_available():
         pytest.skip("no HIP device")
@@ -48,7 +51,7 @@ def test_ensemble_fullsize_history_part(dtype, loud):
     for v in (1, 17, 63):
         assert np.array_equal(st.read("f_hist", stream=s, variant=v), g0)
     rng = np.random.default_rng(3)
-    rows = sorted(set(rng.integers(0, N, 24).tolist()))
+    rows = sorted(set(rng.integers(0, N, 24).tolist()) | set(SI.closest_to_other_faults(faults, 6)[0]))
     prob = OS.Problem(faults, params, dense=False)
     Vh = np.concatenate([prior, ini["V"][None, :]])
     ref = OI.stress_rows(prob.geo, rows, Vh, 0, -len(prior), prob.mu, prob.cs, prob.dt, 0.01, 0.01,

@@ -4,7 +4,8 @@ ACA 1e-6, eta_H 2, leaf 50, saturated history windows), FP32 factors and the
 
 The oracle cannot evaluate all 3000 receivers at every lag in seconds, so it is
 compared on sampled receivers (kernel rows evaluated on the fly) at the same
-steps.  Tolerances: 1e-4 relative for FP32 (FP32 accumulation per work item;
+steps, including the receivers nearest a fault crossing.  Tolerances: 1e-4
+relative for FP32 (FP32 accumulation per work item;
 ACA 1e-6) and FP16 (11-bit factors and history with per-item scales), 2e-3 for
 BF16 (one BF16 rounding, 2^-9; BF16 does not reach 1e-4)."""
 import numpy as np
@@ -19,7 +20,10 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 P = pytest.importorskip("paper_2603_00383_amd")
 
-ROWS = [0, 37, 301, 599, 600, 899, 1200, 1511, 1799, 1800, 2222, 2400, 2650, 2999]
+# fault ends and interiors of every fault, and the eight receivers nearest a
+# fault crossing (the worst-conditioned sums; the closest lies 2.9 m from one)
+ROWS = sorted(set([0, 37, 301, 599, 600, 899, 1200, 1511, 1799, 1800, 2222, 2400, 2650, 2999]
+                  + SI.closest_to_other_faults(SI.five_fault_network(seed=0))[0]))
 
 
 TOL = {"f32": 1e-4, "f16": 1e-4, "bf16": 2e-3}

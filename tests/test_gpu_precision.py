@@ -6,17 +6,19 @@ Error measure: e = max_n |f_gpu^n - f_ref^n|_inf / max_n |f_ref^n|_inf (global o
 steps and elements), per variant for ensembles.
 
 Tolerances. FP16 keeps 11 significant bits (a stored value is off by at most
-2^-12 = 2.4e-4 of itself); with the per-item scales the stress meets the 1e-4
-reduced-precision target, which is the tolerance used. BF16 keeps 8 (2^-9 =
-2.0e-3 per value) and cannot meet 1e-4: a receiver's stress is dominated by a
-few near-field terms whose rounding does not average out. Its bound is one
-value's rounding, 2e-3, with one variant (lags below the time block in FP32,
-history in FP32 until staged) and 8e-3 for ensembles, where the factors of
-every lag, the history copy and the projected panel are each rounded once
-(3 x 2^-9 = 5.9e-3, plus the cancellation margin of the sums). FP16 ensembles
-round the near lags (1..15) and the static tail too, which carry the largest
-terms: measured 6.6e-4 (16 variants) and 1.0e-3 (64); bound 3 x 2^-12 = 7.3e-4
-per term with the same cancellation margin, 2e-3.
+2^-12 = 2.4e-4 of itself); with the per-item scales, and the near-field blocks,
+the lags below 16 and the static tail in FP32 (the terms that carry the largest,
+most strongly cancelling parts of a receiver's sum), the stress meets the 1e-4
+reduced-precision target, which is the tolerance used, with one variant and in
+ensembles. BF16 keeps 8 (2^-9 = 2.0e-3 per value) and cannot meet 1e-4: it is
+reported outside that band. Its bound is one value's rounding, 2e-3, with one
+variant (lags below the time block in FP32, history in FP32 until staged) and
+8e-3 for ensembles, where the factors of every lag, the history copy and the
+projected panel are each rounded once (3 x 2^-9 = 5.9e-3, plus the cancellation
+margin of the sums).
+
+Each ensemble variant's history panel carries its own power-of-two scale, so a
+variant's stress depends on its own history only, bit for bit, in both formats.
 """
 import numpy as np
 import pytest
@@ -30,7 +32,7 @@ torch = pytest.importorskip("torch")
 P = pytest.importorskip("paper_2603_00383_amd")
 
 TOL = {"bf16": 2e-3, "f16": 1e-4}
-TOL_ENS = {"bf16": 8e-3, "f16": 2e-3}
+TOL_ENS = {"bf16": 8e-3, "f16": 1e-4}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -142,10 +144,8 @@ def test_ensemble_prescribed_matches_oracle_per_variant(dtype, nv):
 def test_ensemble_variants_do_not_mix(dtype):
     """Each variant's stress is a function of its own history only: permuting
     the variants permutes the results bit for bit, and changing the other
-    variants' histories leaves a variant's result bit for bit unchanged (BF16:
-    every column of a product is formed on its own; FP16: the history scale of an
-    item depends on all variants, so only the permutation is bitwise and a
-    variant in another mix agrees to the tolerance)."""
+    variants' histories leaves a variant's result bit for bit unchanged (every
+    column of a product is formed on its own, with its own history scale)."""
     nv, steps = 16, 96
     V = _ensemble_V(nv, steps)
     p = SI.default_params(factor_dtype=dtype, aca_tol=1e-6, time_block=1, n_variants=nv)
@@ -156,10 +156,28 @@ def test_ensemble_variants_do_not_mix(dtype):
     V2 = V.copy()
     V2[:, 1:, :] = _ensemble_V(nv - 1, steps, seed0=100)
     f2, _ = gpu_prescribed(E2, p, V2)
-    if dtype == "bf16":
-        assert np.array_equal(f2[:, 0, :], f[:, 0, :])
-    else:
-        assert rel_err(f2[:, 0, :], f[:, 0, :]) < TOL_ENS[dtype]
+    assert np.array_equal(f2[:, 0, :], f[:, 0, :])
+
+
+def test_fp16_ensemble_variant_beside_a_rupture():
+    """An interseismic variant (slip rates 1e-10..1e-8 m/s) batched with variants
+    slipping at seismic rates (0.1..10 m/s): its stress is the one it gets beside
+    quiet variants, bit for bit, and within the FP16 tolerance of the oracle. (A
+    history scale shared over the variants would push its rates below FP16's
+    range.)"""
+    nv, steps = 16, 96
+    quiet = np.stack([SI.prescribed_slip_rate(E2, steps, v, lo_exp=-10, hi_exp=-8) for v in range(nv)], axis=1)
+    loud = quiet.copy()
+    loud[:, 1:, :] = np.stack([SI.prescribed_slip_rate(E2, steps, 50 + v, lo_exp=-1, hi_exp=1)
+                               for v in range(nv - 1)], axis=1)
+    p = SI.default_params(factor_dtype="f16", aca_tol=1e-6, time_block=1, n_variants=nv)
+    fq, _ = gpu_prescribed(E2, p, quiet)
+    fl, _ = gpu_prescribed(E2, p, loud)
+    assert np.array_equal(fl[:, 0, :], fq[:, 0, :])
+    ref = oracle_prescribed(("e2q", 0), E2, SI.default_params(compress=0), quiet[:, 0, :])
+    e = rel_err(fl[:, 0, :], ref)
+    print(f"[gpu] fp16 ensemble variant beside a rupture: err {e:.3e}", flush=True)
+    assert e < TOL_ENS["f16"]
 
 
 @pytest.mark.parametrize("dtype", ["bf16", "f16"])
