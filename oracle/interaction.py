@@ -100,6 +100,15 @@ def pair_kernel(geo, a, b, T, dt, cs):
     return kernel_from_offsets(r1p, r2p, n1p, n2p, geo[b].dx, T, dt, cs)
 
 
+def pair_kernel_row(geo, a, i, b, T, dt, cs):
+    """Row i of the pair kernel at lag T (receiver i of fault a, all sources of b)."""
+    A, B = geo[a], geo[b]
+    d = A.mid[i][None, :] - B.mid
+    r1p = d[:, 0] * B.t[0] + d[:, 1] * B.t[1]
+    r2p = d[:, 0] * B.n[0] + d[:, 1] * B.n[1]
+    return kernel_from_offsets(r1p, r2p, float(A.n @ B.t), float(A.n @ B.n), B.dx, T, dt, cs)
+
+
 def pair_kernel_stack(geo, a, b, lags, dt, cs):
     r1p, r2p, n1p, n2p = local_offsets(geo, a, b)
     out = np.empty((len(lags),) + r1p.shape)

@@ -191,3 +191,105 @@ def prescribed_rows(prob, V_all, first, n, rows, delta0=None):
             if prob.off[k] <= r < prob.off[k + 1]:
                 out[idx] = fs[r - prob.off[k]]
     return out + f_int
+
+
+def lag0_partners(prob, fault):
+    """Global indices of the source elements of other faults that act on some
+    receiver of ``fault`` through the lag-0 kernel (pairs whose window starts at
+    lag 0)."""
+    P = prob
+    out = set()
+    for b in range(len(P.geo)):
+        if b == fault:
+            continue
+        T0, _ = interaction.pair_window_lags(P.geo, fault, b, P.cs, P.dt, float(P.p.get("eta_tmin", 0.01)),
+                                             float(P.p.get("eta_tmax", 0.01)))
+        if T0 == 0:
+            K = interaction.pair_kernel(P.geo, fault, b, 0, P.dt, P.cs)
+            out |= {int(P.off[b] + j) for j in np.nonzero(np.any(K != 0.0, axis=0))[0]}
+    return sorted(out)
+
+
+def step_fault(prob, fric, st, fault, f_hist, eps=1.0):
+    """One predictor-corrector step (Section 2.4, steps 2 and 3) for the elements
+    of one fault of a network too large for dense operators.
+
+    ``st`` holds the state at step n: full-network arrays V, theta, thetadot,
+    delta, tau0, tau0_rate, the step index n, and ``Dh``: for every fault g a
+    list (first_g, rows) of slip coefficients D^m, m = first_g..n (earlier ones
+    zero). ``f_hist`` maps a global receiver index to its interaction history
+    part at this step (lags >= 1 and the static tail, e.g. from
+    ``interaction.stress_rows``); it must cover the fault's elements and the
+    elements of other faults that reach them through the lag-0 kernel.
+
+    The step is SeasState.step restricted to those elements: the corrector's
+    self term needs the averaged rate over the whole fault, and its lag-0 term
+    the averaged rates of the coupled elements, so the predictor is solved on
+    both. Returns V, theta, delta at n + 1 on the fault's elements."""
+    P = prob
+    dt, n = P.dt, st["n"]
+    off = P.off
+    eta = P.eta
+    rk = np.arange(off[fault], off[fault + 1])
+    # lag-0 coupling of the fault's receivers (pairs whose window starts at lag 0)
+    partners = lag0_partners(P, fault)
+    # the partners' own lag-0 terms at the predictor
+    def lag0_at(rows, v):
+        out = np.zeros(len(rows))
+        for idx, r in enumerate(rows):
+            a = int(np.searchsorted(off, r, side="right") - 1)
+            for b in range(len(P.geo)):
+                if b == a:
+                    continue
+                T0, _ = interaction.pair_window_lags(P.geo, a, b, P.cs, dt, float(P.p.get("eta_tmin", 0.01)),
+                                                     float(P.p.get("eta_tmax", 0.01)))
+                if T0 != 0:
+                    continue
+                Krow = interaction.pair_kernel_row(P.geo, a, r - off[a], b, 0, dt, P.cs)
+                out[idx] += -eta * float(Krow @ v[off[b]:off[b + 1]])
+        return out
+    rows = list(rk) + [r for r in partners if not (off[fault] <= r < off[fault + 1])]
+    rows = np.array(rows, dtype=int)
+    F = {k: np.asarray(v, float) for k, v in fric.items()}
+    fh = np.array([f_hist[int(r)] for r in rows])
+    tau0 = st["tau0"][rows] + st["tau0_rate"][rows] * (n + 1) * dt
+    faults_of = [int(np.searchsorted(off, r, side="right") - 1) for r in rows]
+
+    def self_at(delta_new):
+        out = np.zeros(len(rows))
+        for g in sorted(set(faults_of)):
+            first_g, Dg = st["Dh"][g]
+            Dn = P.selfs[g].dft(delta_new[off[g]:off[g + 1]])
+            fs = P.selfs[g].stress(np.asarray(Dg), n + 1, first_g, D_now=Dn)
+            for idx, r in enumerate(rows):
+                if faults_of[idx] == g:
+                    out[idx] = fs[r - off[g]]
+        return out
+    V, th, thd, de = st["V"], st["theta"], st["thetadot"], st["delta"]
+    sub = lambda x: np.asarray(x)[rows]
+    # ---- predictor (every involved element)
+    d_star = de + dt * V
+    th_star = sub(th) + dt * sub(thd)
+    fs_star = self_at(d_star)
+    fi_star = fh + lag0_at(rows, V)
+    solve = lambda A, theta, x0: friction.solve_velocity(A, theta, eta, sub(F["a"]), sub(F["b"]), sub(F["Dc"]),
+                                                         sub(F["sigma_n"]), sub(F["V0"]), sub(F["f0"]), x0)
+    V_star = solve(tau0 + fs_star + fi_star, th_star, np.log(sub(V)))
+    e_ = eps if np.isscalar(eps) else sub(eps)
+    thd_star = friction.state_rate(V_star, th_star, sub(F["Dc"]), e_)
+    # ---- corrector (the fault's elements; its self term needs the whole fault)
+    Vbar_full = V.copy()
+    Vbar_full[rows] = 0.5 * (sub(V) + V_star)
+    nk = len(rk)
+    thd_bar = 0.5 * (sub(thd)[:nk] + thd_star[:nk])
+    d2_full = de.copy()
+    d2_full[rk] = de[rk] + dt * Vbar_full[rk]
+    th2 = sub(th)[:nk] + dt * thd_bar
+    first_k, Dk = st["Dh"][fault]
+    D2 = P.selfs[fault].dft(d2_full[rk])
+    fs2 = P.selfs[fault].stress(np.asarray(Dk), n + 1, first_k, D_now=D2)
+    fi2 = fh[:nk] + lag0_at(list(rk), Vbar_full)
+    Fk = {k: v[rk] for k, v in F.items()}
+    V2 = friction.solve_velocity(tau0[:nk] + fs2 + fi2, th2, eta, Fk["a"], Fk["b"], Fk["Dc"], Fk["sigma_n"],
+                                 Fk["V0"], Fk["f0"], np.log(V_star[:nk]))
+    return dict(V=V2, theta=th2, delta=d2_full[rk], rows=rk, f_self=fs2, f_int=fi2, partners=partners)

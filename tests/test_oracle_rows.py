@@ -118,3 +118,39 @@ def test_static_tail_is_the_late_kernel_limit_at_every_receiver():
         G = I.static_dipole(g, a, b, SI.MU)
         K = I.pair_kernel(g, a, b, 20000, dt, SI.CS)
         assert _rel(-SI.MU / (2 * SI.CS) * K / dt, G) < 1e-3
+
+
+def test_step_fault_equals_dense_step():
+    # Section 2.4 step restricted to one fault (the large-network form): the same
+    # V, theta, delta as the dense SeasState step on every fault of a crossing
+    # network with lag-0 coupling, a prior history and the static tail.
+    faults = [SI.fault(0.0, 0.0, 0.0, 1200.0, 24), SI.fault(110.0, 35.0, 63.0, 1000.0, 20),
+              SI.fault(-300.0, 900.0, 150.0, 800.0, 16)]
+    p = SI.default_params()
+    prob = OS.Problem(faults, p)
+    assert any(P["T0"] == 0 for P in prob.inter.pairs.values())        # faults cross
+    fric = SI.rate_state_fields(faults)
+    ini = SI.near_nucleation_state(faults, fric, seed=4, V_init=1e-5, bump_amp=0.2)
+    prior = SI.prescribed_slip_rate(faults, 70, 9, lo_exp=-7, hi_exp=-3)
+    eps = np.where(np.arange(prob.N) % 2 == 0, 1.0, 0.6)
+    tau0_rate = np.full(prob.N, 1e3)
+    dense = OS.SeasState(prob, fric, ini["V"], ini["theta"], ini["tau0"], tau0_rate, prior_V=prior, eps=eps)
+    for _ in range(3):
+        dense.step()
+    # state at n = 3 for the row form
+    st = dict(V=dense.V.copy(), theta=dense.theta.copy(), thetadot=dense.thetadot.copy(),
+              delta=dense.delta.copy(), tau0=dense.tau0, tau0_rate=dense.tau0_rate, n=dense.n,
+              Dh=[(dense.first, np.array(dense.Dh[k])) for k in range(len(faults))])
+    Vh = np.array(dense.Vh)
+    rows = list(range(prob.N))
+    fh = I.stress_rows(prob.geo, rows, Vh, dense.n, dense.first, prob.mu, prob.cs, prob.dt, min_lag=1)
+    f_hist = dict(zip(rows, fh))
+    dense.step()
+    for k in range(len(faults)):
+        got = OS.step_fault(prob, fric, st, k, f_hist, eps=eps)
+        r = got["rows"]
+        for key, ref in (("V", dense.V), ("theta", dense.theta), ("delta", dense.delta)):
+            assert _rel(got[key], ref[r]) < 1e-12, (k, key, _rel(got[key], ref[r]))
+        assert _rel(got["f_int"], dense.last["f_int"][r]) < 1e-12
+        if k == 0:
+            assert len(got["partners"]) > 0
