@@ -167,7 +167,10 @@ typedef struct {
   int64_t n_segments;         /* BF16 / F16: workgroups of the far list (items with the same rows) */
   int64_t far_bytes;          /* bytes of the stored far-list factors (with the 16-bit row padding) */
   int64_t far_entries_f32;    /* BF16 / F16 with one variant: far entries of near-field (not
-                                 admissible) blocks, kept in FP32 (included in far_entries) */
+                                 admissible) blocks, kept in FP32 (included in far_entries);
+                                 ensembles: the entries of their FP32 list */
+  int64_t partial_bytes;      /* device bytes of the partial sums one interaction evaluation
+                                 writes (see seas_eval_prescribed_noalloc) */
 } seas_op_info_t;
 
 seas_status seas_operator_info(const seas_op_t* op, seas_op_info_t* out);
@@ -254,6 +257,23 @@ seas_status seas_state_reset_variant(seas_state_t* st, int32_t variant, const se
  * same history. MISMATCH if the state has taken SEAS steps. */
 seas_status seas_eval_prescribed(seas_op_t* op, seas_state_t* st, const double* V_dev,
                                  int32_t n_steps, double* f_dev, void* stream);
+
+/* seas_eval_prescribed for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, bit for bit, but the partial sums
+ * of the interaction evaluation live in a fixed 32 MiB device array of the
+ * library (one per GPU, held until the process ends) instead of the state's
+ * buffers, and the call allocates nothing (no hipMalloc, hipFree or allocating
+ * library routine; the state and operator were allocated at set-up). The
+ * caller passes inputs and outputs as for seas_eval_prescribed. Every partial
+ * sum is written before it is read, so nothing is cleared between calls; the
+ * array keeps the last call's contents. Calls that overlap on one GPU (any
+ * states, any streams) share the array and race: order them. Errors:
+ * INVALID_ARG when the operator's partial sums (seas_op_info_t.partial_bytes)
+ * exceed 32 MiB, MISMATCH when kernel timing is on for the state (timing
+ * creates events), and those of seas_eval_prescribed. */
+seas_status seas_eval_prescribed_noalloc(seas_op_t* op, seas_state_t* st, const double* V_dev, int32_t n_steps,
+                                         double* f_dev, void* stream);
 
 /* Advance n_steps predictor-corrector steps (Section 2.4, steps 2 and 3: the
  * predictor, the Newton solve of the force balance with the friction of eq.

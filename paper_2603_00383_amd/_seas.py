@@ -50,7 +50,8 @@ class OpInfo(C.Structure):
                 ("flops_per_step", C.c_double), ("build_seconds", C.c_double),
                 ("factor_dtype", C.c_int32), ("time_block", C.c_int32), ("far_entries", C.c_int64),
                 ("n_items_near", C.c_int64), ("n_variants", C.c_int32), ("ncols", C.c_int32),
-                ("n_segments", C.c_int64), ("far_bytes", C.c_int64), ("far_entries_f32", C.c_int64)]
+                ("n_segments", C.c_int64), ("far_bytes", C.c_int64), ("far_entries_f32", C.c_int64),
+                ("partial_bytes", C.c_int64)]
 
 
 class Friction(C.Structure):
@@ -96,6 +97,7 @@ def lib():
             "seas_state_load_history": (i32, [vp, dp, i32, vp]),
             "seas_state_reset_variant": (i32, [vp, i32, C.POINTER(Friction), dp, dp, dp, dp, dp, vp]),
             "seas_eval_prescribed": (i32, [vp, vp, vp, i32, vp, vp]),
+            "seas_eval_prescribed_noalloc": (i32, [vp, vp, vp, i32, vp, vp]),
             "seas_step": (i32, [vp, vp, i32, vp]),
             "seas_state_check": (i32, [vp, vp]),
             "seas_state_variant_status": (i32, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64), vp]),
@@ -266,6 +268,10 @@ class State:
 
     def eval_prescribed(self, V_dev, n_steps, f_dev, stream=0):
         _check(lib().seas_eval_prescribed(self.op.h, self.h, _ptr(V_dev), n_steps, _ptr(f_dev), _ptr(stream)))
+
+    def eval_prescribed_noalloc(self, V_dev, n_steps, f_dev, stream=0):
+        _check(lib().seas_eval_prescribed_noalloc(self.op.h, self.h, _ptr(V_dev), n_steps, _ptr(f_dev),
+                                                  _ptr(stream)))
 
     def step(self, n_steps=1, stream=0):
         _check(lib().seas_step(self.op.h, self.h, n_steps, _ptr(stream)))

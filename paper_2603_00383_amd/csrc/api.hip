@@ -5,7 +5,9 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -62,6 +64,29 @@ T* upload(std::vector<DevBuf>& owned, const std::vector<T>& v) {
   T* d = (T*)dalloc(owned, v.size() * sizeof(T));
   if (!v.empty()) HIPCHK(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
   return d;
+}
+
+// Partial sums of seas_eval_prescribed_noalloc: a fixed device array, one copy per
+// GPU for the life of the process. Its device address is looked up once per
+// device (hipGetSymbolAddress, with that device current); host code uses only
+// that address, never the array's name.
+constexpr size_t kScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+void* scratch_ptr(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (dev < 0 || dev >= kMaxDevices) throw Error(SEAS_ERR_INVALID_ARG, "device index out of range");
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      throw Error(SEAS_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
 }
 
 double host_state_rate(double V, double th, double Dc, double eps) {
@@ -219,12 +244,25 @@ void record_stop(seas_state* st, hipStream_t s) {
   st->n_ev++;
 }
 
+// Byte offset of the near partials and total bytes when both partial buffers of
+// one evaluation share one allocation (far: FP32 on the matrix-core segment
+// path, else FP64; near: FP64), the near ones 256-byte aligned.
+std::pair<size_t, size_t> partial_layout(const HostOp& h) {
+  const size_t far = (size_t)h.n_partials[0] * (h.seg ? 4 : 8);
+  const size_t near_off = (far + 255) & ~(size_t)255;
+  return {near_off, near_off + (size_t)h.n_partials[1] * 8};
+}
+
 // Interaction history part at `head` into st->f_hist. The far list is applied
 // once per time block (S windows: heads block_head .. block_head + S - 1), the
 // near list (lags 1..S-1 and the static tail) at every head. In the plain form
 // (S = 1, or run_S = 1) the far list is applied at every head.
-void eval_history(seas_op* op, seas_state* st, int64_t head, hipStream_t s) {
+void eval_history(seas_op* op, seas_state* st, int64_t head, hipStream_t s, void* pfar = nullptr,
+                  double* pnear = nullptr) {
   const HostOp& h = op->h;
+  // partial sums: the state's buffers unless the caller brings its own
+  if (!pfar) pfar = st->partials_far;
+  if (!pnear) pnear = st->partials_near;
   const int S = h.time_block;
   const int nfar = (int)h.items[0].size(), nnear = (int)h.items[1].size();
   const bool plain = S == 1 || st->run_S == 1;
@@ -236,22 +274,22 @@ void eval_history(seas_op* op, seas_state* st, int64_t head, hipStream_t s) {
     record_start(st, s);
     if (h.seg) {
       launch_hmat_x16(h, op->items[0], op->seg_ptr, op->lagT, op->lagCol, op->lagColOff[0], op->arena, st->ringop,
-                      head, st->tail_acc, (float*)st->partials_far, s);
+                      head, st->tail_acc, (float*)pfar, s);
       launch_hmat_f32far(h, (int)h.items[2].size(), op->items[2], op->lagT, op->lagCol, op->lagColOff[2],
-                         op->arena_near, st->ringop, head, (float*)st->partials_far, s);
+                         op->arena_near, st->ringop, head, (float*)pfar, s);
       if (h.ens32) {
         // BF16 ensembles keep a BF16 history copy: their FP32 list reads the FP64 history
         const bool r64 = op->ring_bytes == 2;
         launch_hmat_seg32(h, op->items[3], op->seg_ptr3, op->lagT, op->lagCol, op->lagColOff[3], op->arena32s,
                           r64 ? (const void*)st->ring64 : (const void*)st->ringop, r64, head, st->tail_acc,
-                          (float*)st->partials_far, s);
+                          (float*)pfar, s);
       }
     } else
       launch_hmat(h, Sl, nfar, op->items[0], op->lagT, op->lagCol, op->lagColOff[0], op->arena, st->ringop, head,
-                  st->tail_acc, (double*)st->partials_far, S, s);
+                  st->tail_acc, (double*)pfar, S, s);
     record_stop(st, s);
     const bool f32p = far_partials_f32(h, Sl);
-    launch_reduce_far(h, h.seg ? h.ncols : Sl, st->partials_far, f32p, op->red_ptr[0], op->red_idx[0],
+    launch_reduce_far(h, h.seg ? h.ncols : Sl, pfar, f32p, op->red_ptr[0], op->red_idx[0],
                       nnear == 0 ? st->f_hist : st->f_far, s);
     if (nnear == 0) return;
     st->block_head = plain ? INT64_MIN / 2 : head;
@@ -259,8 +297,8 @@ void eval_history(seas_op* op, seas_state* st, int64_t head, hipStream_t s) {
   }
   const void* arena_near = h.seg ? (const void*)op->arena_near : op->arena;
   launch_hmat(h, 1, nnear, op->items[1], op->lagT, op->lagCol, op->lagColOff[1], arena_near, st->ringop, head,
-              st->tail_acc, st->partials_near, 1, s);
-  launch_reduce_near(h, st->partials_near, op->red_ptr[1], op->red_idx[1], st->f_far + k * h.N, st->f_hist, s);
+              st->tail_acc, pnear, 1, s);
+  launch_reduce_near(h, pnear, op->red_ptr[1], op->red_idx[1], st->f_far + k * h.N, st->f_hist, s);
 }
 
 template <typename TF>
@@ -304,7 +342,8 @@ void do_steps(seas_op* op, seas_state* st, int n_steps, hipStream_t s) {
 }
 
 template <typename TF>
-void do_prescribed(seas_op* op, seas_state* st, const double* V, int n_steps, double* f, hipStream_t s) {
+void do_prescribed(seas_op* op, seas_state* st, const double* V, int n_steps, double* f, hipStream_t s,
+                   void* pfar = nullptr, double* pnear = nullptr) {
   const HostOp& h = op->h;
   const int nm = h.n_modes, nv = st->nv;
   const int64_t dl = h.self_ring_len;
@@ -319,7 +358,7 @@ void do_prescribed(seas_op* op, seas_state* st, const double* V, int n_steps, do
     if (hd < 1) a.tail = 0;
     const double* Vrow = V + (size_t)it * row;
     launch_prescribed_push<TF>(a, Vrow, s);
-    eval_history(op, st, hd, s);
+    eval_history(op, st, hd, s, pfar, pnear);
     launch_self_hist(nm, nv, dl, op->modes, op->tab, st->dring, n, st->Fh, s);
     launch_dft(nm, nv, h.N, dl, op->modes, op->sf, st->delta, nullptr, 0.0, op->tw, op->tab, st->Fh, st->F,
                st->dring, 1, n, n, s);
@@ -649,6 +688,7 @@ seas_status seas_operator_info(const seas_op_t* op, seas_op_info_t* out) {
       fb += 4 * (it.kind == 0 ? (int64_t)it.ncol * q8 + (int64_t)it.p * round8(it.ncol) : (int64_t)it.nlag * it.p * q8);
     }
     out->far_bytes = fb;
+    out->partial_bytes = (int64_t)partial_layout(h).second;
   });
 }
 
@@ -952,6 +992,31 @@ seas_status seas_eval_prescribed(seas_op_t* op, seas_state_t* st, const double* 
       case 8: do_prescribed<double>(op, st, V_dev, n_steps, f_dev, s); break;
       case 4: do_prescribed<float>(op, st, V_dev, n_steps, f_dev, s); break;
       default: do_prescribed<__bf16>(op, st, V_dev, n_steps, f_dev, s); break;
+    }
+  });
+}
+
+seas_status seas_eval_prescribed_noalloc(seas_op_t* op, seas_state_t* st, const double* V_dev, int32_t n_steps,
+                                         double* f_dev, void* stream) {
+  return guard([&] {
+    checked(op);  // makes the operator's device current
+    if (!st || st->op != op) throw Error(SEAS_ERR_MISMATCH, "state belongs to another operator");
+    if (n_steps < 0 || (n_steps > 0 && (!V_dev || !f_dev))) throw Error(SEAS_ERR_INVALID_ARG, "bad arguments");
+    if (st->mode == 2) throw Error(SEAS_ERR_MISMATCH, "state has taken SEAS steps");
+    const std::pair<size_t, size_t> lay = partial_layout(op->h);
+    if (lay.second > kScratchBytes)
+      throw Error(SEAS_ERR_INVALID_ARG, "the operator's partial sums need " + std::to_string(lay.second) +
+                                            " bytes; the static scratch holds " + std::to_string(kScratchBytes));
+    if (st->timing) throw Error(SEAS_ERR_MISMATCH, "kernel timing (which creates events) is on for this state");
+    unsigned char* base = (unsigned char*)scratch_ptr(op->device);
+    st->mode = 1;
+    hipStream_t s = (hipStream_t)stream;
+    void* pfar = base;
+    double* pnear = (double*)(base + lay.first);
+    switch (op->ring_bytes) {
+      case 8: do_prescribed<double>(op, st, V_dev, n_steps, f_dev, s, pfar, pnear); break;
+      case 4: do_prescribed<float>(op, st, V_dev, n_steps, f_dev, s, pfar, pnear); break;
+      default: do_prescribed<__bf16>(op, st, V_dev, n_steps, f_dev, s, pfar, pnear); break;
     }
   });
 }
