@@ -116,6 +116,14 @@ typedef struct {
                            many parameter sets on this geometry (BF16 / F16 only), whose
                            interaction sums are one product of the factors with the
                            variants' histories side by side */
+  int32_t state_update; /* states of this operator: 0 = the explicit update of Section 2.4 as
+                           printed (theta* = theta + dt thetadot; the corrector with the averaged
+                           state rate); 1 = the state law of eq. "state_evolution_law" integrated
+                           in closed form over the step at constant slip rate (V in the
+                           predictor, the averaged rate in the corrector), which keeps theta > 0
+                           when the rate jumps by decades in one step (the explicit form cannot
+                           start the two-fault benchmark of Section 3.1) */
+  int32_t reserved;
 } seas_params_t;
 
 typedef struct seas_op seas_op_t;

@@ -6,6 +6,8 @@
   as the paper states next to it);
 * intermediate state law dtheta/dt = (1/eps)[(V theta/D_c)^(-eps) - 1] V theta / D_c,
   eps = 1 giving the aging law dtheta/dt = 1 - V theta / D_c (eq. "state_evolution_law");
+* the state after a step at constant slip rate in closed form (the reading
+  taken when the explicit state update would leave theta <= 0, see seas.py);
 * equilibrium on every element (eq. "force_balance" with the traction split of
   eq. "superimposition2"):  tau0 + f - mu/(2 cs) V = strength(V, theta),
   solved for V by Newton-Raphson (Section 2.4, step 2).
@@ -28,6 +30,25 @@ def state_rate(V, theta, Dc, eps=1.0):
     if np.all(np.asarray(eps) == 1.0):
         return 1.0 - r
     return (1.0 / eps) * (r ** (-eps) - 1.0) * r
+
+
+def state_at_constant_rate(theta0, V, Dc, dt, eps=1.0):
+    """State after dt at a constant slip rate V, from the state law integrated in
+    closed form: with u = (V theta / Dc)^eps the law reads du/dt = (V/Dc)(1 - u),
+    so u(dt) = 1 + (u(0) - 1) exp(-V dt / Dc) and theta = (Dc/V) u^(1/eps)
+    (eps = 1: theta = Dc/V + (theta0 - Dc/V) exp(-V dt/Dc), the aging law).
+    Positive for every dt, unlike the explicit update. Written as
+    theta0 e^-x + (Dc/V)(1 - e^-x), x = V dt/Dc, with 1 - e^-x = -expm1(-x), so
+    that a locked element (x ~ 1e-25) keeps its state instead of losing it to
+    cancellation."""
+    x = V * dt / Dc
+    e = np.exp(-x)
+    one_m = -np.expm1(-x)
+    eps = np.asarray(eps, float)
+    if np.all(eps == 1.0):
+        return theta0 * e + Dc / V * one_m
+    u0 = (V * theta0 / Dc) ** eps
+    return Dc / V * (u0 * e + one_m) ** (1.0 / eps)
 
 
 class NotConverged(RuntimeError):

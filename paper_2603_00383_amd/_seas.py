@@ -39,7 +39,8 @@ class Params(C.Structure):
                 ("eta_w", C.c_double), ("leaf", C.c_int32), ("compress", C.c_int32),
                 ("int_tail", C.c_int32), ("q_w", C.c_int32), ("mode_cap", C.c_int32),
                 ("factor_dtype", C.c_int32), ("n_threads", C.c_int32), ("host_only", C.c_int32),
-                ("time_block", C.c_int32), ("n_variants", C.c_int32)]
+                ("time_block", C.c_int32), ("n_variants", C.c_int32), ("state_update", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class OpInfo(C.Structure):
@@ -162,6 +163,7 @@ def make_params(p):
     q.host_only = int(p.get("host_only", 0))
     q.time_block = int(p.get("time_block", 1))
     q.n_variants = int(p.get("n_variants", 1))
+    q.state_update = {"explicit": 0, "exact": 1, 0: 0, 1: 1}[p.get("state_update", "explicit")]
     return q
 
 

@@ -223,6 +223,7 @@ StepArgs<TF> make_args(seas_op* op, seas_state* st) {
   a.src_pairs_ptr = op->src_pairs_ptr;
   a.first = st->first;
   a.tail = h.prm.int_tail;
+  a.exact_state = h.prm.state_update == 1;
   return a;
 }
 

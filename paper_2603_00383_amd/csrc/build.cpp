@@ -671,6 +671,8 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
     throw Error(SEAS_ERR_INVALID_ARG, "leaf >= 1, eta_H > 0, aca_tol > 0, eta_w > 0 required");
   if (prm.factor_dtype < SEAS_F64 || prm.factor_dtype > SEAS_F16)
     throw Error(SEAS_ERR_INVALID_ARG, "factor_dtype must be SEAS_F64, SEAS_F32, SEAS_BF16 or SEAS_F16");
+  if (prm.state_update != 0 && prm.state_update != 1)
+    throw Error(SEAS_ERR_INVALID_ARG, "state_update must be 0 (explicit) or 1 (closed form at constant rate)");
   if (prm.time_block < 0 || prm.time_block > kMaxTimeBlock ||
       (prm.time_block & (prm.time_block - 1)) != 0)
     throw Error(SEAS_ERR_INVALID_ARG, "time_block must be 0, 1, 2, 4, 8 or 16");

@@ -493,6 +493,17 @@ __device__ __forceinline__ double state_rate(double V, double th, double Dc, dou
   return (pow(r, -eps) - 1.0) * r / eps;
 }
 
+// State after dt at a constant slip rate V: with u = (V theta/Dc)^eps the state
+// law reads du/dt = (V/Dc)(1 - u), so u(dt) = u0 e^-x + (1 - e^-x), x = V dt/Dc,
+// theta = (Dc/V) u^(1/eps); 1 - e^-x as -expm1(-x) keeps a locked element's state.
+__device__ __forceinline__ double state_after(double th0, double V, double Dc, double dt, double eps) {
+  const double x = V * dt / Dc;
+  const double e = exp(-x), om = -expm1(-x);
+  if (eps == 1.0) return th0 * e + Dc / V * om;
+  const double u0 = pow(V * th0 / Dc, eps);
+  return Dc / V * pow(u0 * e + om, 1.0 / eps);
+}
+
 // Newton on x = ln V for A - eta V = sigma_n [f0 + a (x - ln V0) + b ln(V0 theta / Dc)];
 // steps clamped to |dx| <= 5, stop at |dx| <= 1e-14 max(1, |x|), at most 50 iterations.
 __device__ double newton_lnV(double A, double th, double eta, double a, double b, double Dc, double sn, double V0,
@@ -551,14 +562,16 @@ __global__ void k_stage(StepArgs<TF> a, int stage) {
   const Friction& fr = a.fric;
   if (stage == 0) {  // predictor: delta*, theta* from the current rates
     const double V = a.V[e];
-    const double th_s = a.theta[e] + a.dt * a.thdot[e];
+    const double th_s = a.exact_state ? state_after(a.theta[e], V, fr.Dc[e], a.dt, fr.eps[e])
+                                      : a.theta[e] + a.dt * a.thdot[e];
     const double fint = a.f_hist[e] - a.eta * lag0_apply(a.l0_ptr, a.l0_col, a.l0_val, a.V + o, r);
     const double Vs = newton_lnV(tau0 + fself + fint, th_s, a.eta, fr.a[e], fr.b[e], fr.Dc[e], fr.sn[e], fr.V0[e],
                                  fr.f0[e], log(V), a.fail + v);
     const double tds = state_rate(Vs, th_s, fr.Dc[e], fr.eps[e]);
     a.Vstar[e] = Vs;
     a.Vbar[e] = 0.5 * (V + Vs);
-    a.th2[e] = a.theta[e] + a.dt * 0.5 * (a.thdot[e] + tds);
+    a.th2[e] = a.exact_state ? state_after(a.theta[e], 0.5 * (V + Vs), fr.Dc[e], a.dt, fr.eps[e])
+                             : a.theta[e] + a.dt * 0.5 * (a.thdot[e] + tds);
   } else {  // corrector with the averaged rates; only the lag-0 terms change
     const double Vb = a.Vbar[e];
     const double th2 = a.th2[e];

@@ -68,6 +68,7 @@ struct StepArgs {
   const int32_t* src_pairs_ptr; // per fault: range in src_pairs (pairs of 2 ints)
   int64_t first;            // earliest time held in the histories
   int tail;                 // static tail on
+  int exact_state;          // state law integrated in closed form over the step (else explicit)
 };
 
 void launch_hmat(const HostOp& h, int S, int n_items, const void* items, const int32_t* lagT, const int32_t* lagCol,

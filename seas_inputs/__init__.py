@@ -123,6 +123,50 @@ def prescribed_slip_rate(faults, n_steps, seed, lo_exp=-9.0, hi_exp=0.0):
 
 
 # ----------------------------------------------------------------------------
+# The paper's two-fault benchmark (Section 3.1, Table 1): geometry, material,
+# friction and initial conditions as printed (tests/golden/two_fault_benchmark.json).
+# ----------------------------------------------------------------------------
+def two_fault_benchmark(gold, n_elem=1000):
+    """Faults, material and friction of the benchmark, each fault cut into
+    ``n_elem`` elements (the paper uses 1000)."""
+    faults = [dict(f, n_elem=int(n_elem)) for f in gold["faults"]]
+    fr = gold["friction"]
+    N = 2 * int(n_elem)
+    fric = dict(a=np.full(N, fr["a"]), b=np.full(N, fr["a"] * fr["b_over_a"]), Dc=np.full(N, fr["Dc"]),
+                sigma_n=np.full(N, fr["sigma_n"]), V0=np.full(N, fr["V_star"]), f0=np.full(N, fr["f_star"]))
+    return faults, fric
+
+
+def two_fault_benchmark_state(gold, faults, fric):
+    """Steady sliding at V_* everywhere, tau0 = f_* sigma_n + mu V_* / (2 cs) (the
+    printed 30 MPa), and on the first fault the overstress 2 tau_eq B(x') with
+    w = 500 m, kappa = 2.5 about its centre."""
+    fr = gold["friction"]
+    N = len(fric["a"])
+    V = np.full(N, fr["V_star"])
+    theta = fric["Dc"] / V
+    tau_eq = fr["f_star"] * fr["sigma_n"] + gold["mu"] / (2 * gold["cs"]) * fr["V_star"]
+    tau0 = np.full(N, tau_eq)
+    n = faults[0]["n_elem"]
+    xi = (-0.5 + (np.arange(n) + 0.5) / n) * faults[0]["length"]
+    w, kappa = 500.0, 2.5
+    B = np.where(xi <= 0, 0.5 * (np.tanh(kappa * (xi / w + 1.0)) + 1.0),
+                 0.5 * (1.0 - np.tanh(kappa * (xi / w - 1.0))))
+    tau0[:n] += 2.0 * tau_eq * B
+    return dict(V=V, theta=theta, tau0=tau0, tau0_rate=np.zeros(N))
+
+
+def two_fault_benchmark_params(gold, n_elem=1000, **over):
+    """Table 1's H-matrix and truncation parameters (eps_SVD -> ACA tolerance,
+    q_w = 200 for 1000 elements, i.e. N_p / 5)."""
+    p = default_params(mu=gold["mu"], cs=gold["cs"], beta=gold["beta"], eta_H=1.5, aca_tol=1e-6, leaf=50,
+                       eta_tmin=gold["eta_tmin"], eta_tmax=gold["eta_tmax"], eta_w=1.5,
+                       q_w=int(round(n_elem / 5)), state_update="exact")
+    p.update(over)
+    return p
+
+
+# ----------------------------------------------------------------------------
 # Workload 2/3: five 30 km faults, 600 elements each, full SEAS loop.
 # ----------------------------------------------------------------------------
 def random_network(seed, n_faults, n_elem, dx, box, strike_range, min_clear_frac=0.1,

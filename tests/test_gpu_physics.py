@@ -1,7 +1,8 @@
 """GPU parity of the physics variants of the step (through the C ABI, against the FP64 oracle).
 
 * The intermediate state law of Section 2.2 (eq. "state_evolution_law") with an
-  exponent eps < 1, varying per element (eps = 1 is the aging law).
+  exponent eps < 1, varying per element (eps = 1 is the aging law), with the
+  explicit state update and with the closed-form update at constant rate.
 * Tectonic loading: a background stress that grows at a constant rate per
   element (Section 3.2 loads the faults this way).
 
@@ -40,7 +41,7 @@ def rel_err(a, b):
 FAULTS = SI.two_fault_prescribed_faults(n_elem=24, dx=50.0)
 
 
-def _run(p, fric, ini, eps, n_steps):
+def _run(p, fric, ini, eps, n_steps, state_update="explicit"):
     op = P.Operator(FAULTS, p)
     s = _stream()
     fr = dict(fric)
@@ -50,15 +51,16 @@ def _run(p, fric, ini, eps, n_steps):
     st.check(stream=s)
     g = {k: st.read(k, stream=s) for k in ("V", "theta", "delta", "thetadot", "f_self", "f_int")}
     prob = OS.Problem(FAULTS, p)
-    o = OS.SeasState(prob, fric, ini["V"], ini["theta"], ini["tau0"], ini["tau0_rate"], eps=eps)
+    o = OS.SeasState(prob, fric, ini["V"], ini["theta"], ini["tau0"], ini["tau0_rate"], eps=eps,
+                     state_update=state_update)
     for _ in range(n_steps):
         o.step()
     return g, o
 
 
-@pytest.mark.parametrize("S", [1, 8])
-def test_intermediate_state_law(S):
-    p = SI.default_params(compress=0, time_block=S)
+@pytest.mark.parametrize("S,update", [(1, "explicit"), (8, "explicit"), (8, "exact")])
+def test_intermediate_state_law(S, update):
+    p = SI.default_params(compress=0, time_block=S, state_update=update)
     fric = SI.rate_state_fields(FAULTS)
     ini = SI.near_nucleation_state(FAULTS, fric, seed=2, V_init=1e-6, bump_amp=0.1)
     N = len(ini["V"])
@@ -66,15 +68,16 @@ def test_intermediate_state_law(S):
     # off steady state, so that the state law's exponent matters
     ini = dict(ini)
     ini["theta"] = ini["theta"] * np.linspace(0.5, 2.0, N)
-    g, o = _run(p, fric, ini, eps, 120)
+    g, o = _run(p, fric, ini, eps, 120, update)
     errs = {k: rel_err(g[k], ref) for k, ref in (("V", o.V), ("theta", o.theta), ("delta", o.delta),
                                                ("thetadot", o.thetadot), ("f_self", o.last["f_self"]),
                                                ("f_int", o.last["f_int"]))}
-    print(f"[gpu] intermediate law S={S}: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()), flush=True)
+    print(f"[gpu] intermediate law S={S} {update}: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()),
+          flush=True)
     for k, e in errs.items():
         assert e < 1e-9, k
     # the exponent changed the trajectory (not an aging-law run in disguise)
-    ga, _ = _run(p, fric, ini, np.ones(N), 120)
+    ga, _ = _run(p, fric, ini, np.ones(N), 120, update)
     assert rel_err(ga["theta"], g["theta"]) > 1e-4
 
 

@@ -178,3 +178,95 @@ def test_seas_step_reduces_to_heun_without_coupling():
         errs.append(np.abs(st.theta - ref).max() / np.abs(ref).max())
     assert errs[0] < 1e-4
     assert 3.0 < errs[0] / errs[1] < 5.0                # second order in dt
+
+
+@pytest.mark.parametrize("eps", [1.0, 0.5, 0.2])
+def test_state_at_constant_rate_solves_the_state_law(eps):
+    # The closed form against the state law of eq. "state_evolution_law"
+    # integrated numerically at constant slip rate (RK4, 20000 substeps), from
+    # x = V dt / Dc = 1e-25 (a locked element) to 40 (seismic slip over a step),
+    # and from states below and above steady state.
+    Dc = 1e-2
+    rate = lambda th, V: FR.state_rate(V, th, Dc, eps)
+    for V, th0, dt in ((1e-25, 1e7, 1.4e-3), (1e-9, 1e7, 1.4e-3), (1e-3, 3.0, 1.4e-3), (14.0, 1e7, 1.4e-3),
+                       (14.0, 1e-4, 0.03), (0.5, 2e-2, 0.8)):
+        h = dt / 20000
+        th = th0
+        for _ in range(20000):
+            k1 = rate(th, V)
+            k2 = rate(th + 0.5 * h * k1, V)
+            k3 = rate(th + 0.5 * h * k2, V)
+            k4 = rate(th + h * k3, V)
+            th = th + h / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
+        got = FR.state_at_constant_rate(th0, V, Dc, dt, eps)
+        assert got > 0
+        assert abs(got - th) <= 1e-9 * abs(th) + 1e-300, (V, th0, dt, got, th)
+
+
+def test_state_at_constant_rate_is_second_order_close_to_explicit():
+    # For small x the closed form and the explicit update theta + dt thetadot
+    # differ by O(x^2) of the state.
+    Dc, V, th0 = 1e-2, 1e-3, 7.0
+    d = []
+    for dt in (1e-2, 5e-3):
+        exact = FR.state_at_constant_rate(th0, V, Dc, dt)
+        expl = th0 + dt * FR.state_rate(V, th0, Dc)
+        d.append(abs(exact - expl))
+    assert 3.5 < d[0] / d[1] < 4.5
+
+
+def _two_fault_gold():
+    return json.load(open(os.path.join(os.path.dirname(__file__), "golden", "two_fault_benchmark.json")))
+
+
+def test_two_fault_benchmark_inputs():
+    # Section 3.1 / Table 1: L_b = mu Dc / (b sigma_n) = 450 m, tau_eq = 30 MPa,
+    # the overstress peaks near 3 tau_eq at the centre of the first fault
+    gd = _two_fault_gold()
+    faults, fric = SI.two_fault_benchmark(gd, 1000)
+    ini = SI.two_fault_benchmark_state(gd, faults, fric)
+    Lb = gd["mu"] * fric["Dc"][0] / (fric["b"][0] * fric["sigma_n"][0])
+    assert abs(Lb - gd["printed_Lb"]) < 1e-6 * gd["printed_Lb"]
+    assert abs(ini["tau0"][1500] - gd["printed_tau_eq"]) / gd["printed_tau_eq"] < 1e-6
+    # "approximately 3 tau_eq": 1 + 2 B(0) = 1 + tanh(2.5) + 1 = 2.987
+    assert abs(ini["tau0"][:1000].max() / ini["tau0"][1500] - 3.0) < 0.02
+    p = SI.two_fault_benchmark_params(gd, 1000)
+    assert p["q_w"] == 200 and p["eta_H"] == 1.5 and p["aca_tol"] == 1e-6
+
+
+def test_explicit_state_update_cannot_start_the_benchmark():
+    # The explicit update as printed leaves theta <= 0 in the first step of the
+    # two-fault benchmark (the rate jumps by ten decades); the closed-form update
+    # at constant rate runs it (reading R19).
+    gd = _two_fault_gold()
+    n = 50
+    faults, fric = SI.two_fault_benchmark(gd, n)
+    ini = SI.two_fault_benchmark_state(gd, faults, fric)
+    prob = seas.Problem(faults, SI.two_fault_benchmark_params(gd, n))
+    o = seas.SeasState(prob, fric, ini["V"], ini["theta"], ini["tau0"], ini["tau0_rate"])
+    with np.errstate(invalid="ignore", divide="ignore"):
+        try:
+            o.step()
+            bad = not np.all(o.theta > 0)
+        except FR.NotConverged:
+            bad = True
+    assert bad
+    o = seas.SeasState(prob, fric, ini["V"], ini["theta"], ini["tau0"], ini["tau0_rate"], state_update="exact")
+    for _ in range(10):
+        o.step()
+    assert np.all(o.theta > 0) and o.V.max() > 1.0
+
+
+def test_two_fault_benchmark_partition():
+    # Table 1's eta_H = 1.5 makes every block of both pairs admissible (one low-rank
+    # block per leaf-level pairing, 26 in all). Appendix C calls eta_H = 20 the
+    # uncompressed reference; with leaves of at most eta_leaf = 50 elements (the
+    # text's rule) this geometry still has admissible blocks at eta_H = 20, so
+    # the sweep's reference is the operator stored without compression (reading R20).
+    gd = _two_fault_gold()
+    faults, _ = SI.two_fault_benchmark(gd, 1000)
+    geo = geometry.discretize(faults)
+    b15 = [adm for bl in HP.partition(geo, 1.5, 50).values() for *_, adm in bl]
+    assert len(b15) == 26 and all(b15)
+    b20 = [adm for bl in HP.partition(geo, 20.0, 50).values() for *_, adm in bl]
+    assert 0 < sum(b20) < len(b20)
