@@ -202,16 +202,18 @@ def run_precision(args):
     marks = (1000, 5000, 20000)
     faults = SI.five_fault_network(seed=args.seed)
     fric = SI.rate_state_fields(faults)
-    ini = SI.near_nucleation_state(faults, fric, seed=args.seed, bump_amp=0.05)
+    ini = SI.near_nucleation_state(faults, fric, seed=args.seed, bump_amp=args.bump)
     os.environ.setdefault("SEAS_VERBOSE", "1")
     s = torch.cuda.current_stream().cuda_stream
-    snaps, timing, failed = {}, {}, {}
+    snaps, timing, failed, peak = {}, {}, {}, {}
     for d in ("f64", "f32", "f16", "bf16"):
-        params = SI.default_params(factor_dtype=d, aca_tol=args.aca, eta_H=2.0, leaf=50, time_block=16)
+        params = SI.default_params(factor_dtype=d, aca_tol=args.aca, eta_H=2.0, leaf=50, time_block=16,
+                                   state_update=args.state_update)
         print(f"[bench] building the {d} operator", file=sys.stderr, flush=True)
         op = P.Operator(faults, params)
         st = P.State(op, fric, ini["V"], ini["theta"], ini["tau0"], ini["tau0_rate"], stream=s)
         snaps[d] = {}
+        vmax = 0.0
         done, t_run = 0, 0.0
         try:
             for m in marks:
@@ -223,6 +225,7 @@ def run_precision(args):
                     st.check(stream=s)
                     t_run += time.perf_counter() - t0
                     done += k
+                    vmax = max(vmax, float(st.read("V", stream=s).max()))
                     print(f"[bench] {d}: {done} steps", file=sys.stderr, flush=True)
                 snaps[d][m] = {"delta": st.read("delta", stream=s), "V": st.read("V", stream=s),
                                "stress": st.read("f_self", stream=s) + st.read("f_int", stream=s)}
@@ -230,6 +233,7 @@ def run_precision(args):
             failed[d] = f"step {done}: {e}"
             print(f"[bench] {d} stopped: {failed[d]}", file=sys.stderr, flush=True)
         timing[d] = t_run / max(done, 1) * 1e3
+        peak[d] = vmax
         st.close()
         op.close()
     ref = snaps["f64"]
@@ -246,10 +250,13 @@ def run_precision(args):
     out = {"metric": "slip, slip-rate and stress error of the reduced-precision forms vs the FP64 path",
            "data": "synthetic",
            "config": {"workload": "five-fault SEAS step loop, 5 x 600 elements (N=3000, dx=50 m), time block "
-                                  "16, ACA 1e-6, eta_H 2, leaf 50, near-nucleation state, no prior slip",
+                                  f"16, ACA 1e-6, eta_H 2, leaf 50, near-nucleation state (tanh overstress "
+                                  f"{args.bump:g} tau_eq), no prior slip, {args.state_update} state update",
                       "seed": args.seed, "steps": list(marks)},
            "errors": errors, "ms_per_step": timing, "failed": failed,
-           "note": "max |x - x_f64| / max |x_f64| over all elements at each mark; stress = f_self + f_int"}
+           "peak_slip_rate_sampled": peak,
+           "note": "max |x - x_f64| / max |x_f64| over all elements at each mark; stress = f_self + f_int; "
+                   "peak slip rate over the 1000-step marks"}
     print(json.dumps(out), flush=True)
 
 
@@ -497,6 +504,10 @@ def main():
                     help="factor dtype (default f32; bf16 for the ensemble)")
     ap.add_argument("--variants", type=int, default=64, help="ensemble: friction variants (16, 32 or 64)")
     ap.add_argument("--elements", type=int, default=1000, help="two-fault: elements per fault")
+    ap.add_argument("--bump", type=float, default=2.0,
+                    help="precision: overstress of the initial state in units of tau_eq (2: the paper's)")
+    ap.add_argument("--state-update", default="exact", choices=["explicit", "exact"],
+                    help="precision: state update (exact: closed form at constant rate)")
     ap.add_argument("--etas", default="1.0,1.5,2.0,3.0,5.0,20.0", help="two-fault: eta_H values of the sweep")
     ap.add_argument("--templates", type=int, default=4, help="serving: geometry templates")
     ap.add_argument("--requests", type=int, default=32, help="serving: requests in the trace")

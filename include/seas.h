@@ -287,7 +287,8 @@ seas_status seas_eval_prescribed_noalloc(seas_op_t* op, seas_state_t* st, const 
  * predictor, the Newton solve of the force balance with the friction of eq.
  * "R&S_friction", the state law of eq. "state_evolution_law", the corrector
  * with averaged rates, and the history append). Enqueue only.
- * Newton failure (a solve that needs more than 50 iterations): the variant's
+ * Newton failure (a solve that needs more than 50 iterations, or meets a
+ * non-finite force balance, e.g. a non-finite background stress): the variant's
  * commits stop at the failing step, so its slip, rate, state, histories and
  * expired-slip accumulators stay at its last good step, and the rest of the
  * enqueued steps leave it untouched; the other variants keep stepping. The

@@ -13,8 +13,17 @@
   solved for V by Newton-Raphson (Section 2.4, step 2).
 
 The unknown is x = ln V.  g(x) = A - eta e^x - sigma_n [f_* + a (x - ln V_*) +
-b ln(V_* theta/D_c)] is strictly decreasing and concave, so the root is unique;
-iterates are clamped to |dx| <= 5 and stopped when |dx| <= tol max(1, |x|).
+b ln(V_* theta/D_c)] is strictly decreasing and concave, so the root is unique.
+From the right of the root (g < 0) every Newton step is downward and stays
+right of it (the tangent of a concave function lies above it), so downward
+steps are taken whole. From the left (g > 0) the tangent can overshoot far to
+the right; there A - c - sigma_n a x > eta e^x > 0, and at the root
+eta e^x* = A - c - sigma_n a x* < A - c - sigma_n a x, so the root lies below
+ln((A - c - sigma_n a x)/eta): upward steps longer than 1 stop there (but move
+at least 1; near the root that bound is lost to cancellation and the steps are
+short anyway). x is kept >= X_MIN =
+-690 (V >= ~1e-300: a rate that is zero for every purpose), where a root below
+it leaves the iterate. Stop when |dx| <= tol max(1, |x|).
 """
 from __future__ import annotations
 
@@ -55,13 +64,16 @@ class NotConverged(RuntimeError):
     pass
 
 
+X_MIN = -690.0
+
+
 def solve_velocity(A, theta, eta, a, b, Dc, sigma_n, V0, f0, x0, tol=1e-14, max_iter=50):
     """Vectorised Newton on x = ln V for  A - eta V = strength(V, theta).
 
     Every element iterates independently (a converged element is frozen), so the
     result equals a scalar Newton run element by element."""
     A = np.asarray(A, float)
-    x = np.array(x0, dtype=float, copy=True) * np.ones_like(A)
+    x = np.maximum(np.array(x0, dtype=float, copy=True), X_MIN) * np.ones_like(A)
     c = sigma_n * (f0 - a * np.log(V0) + b * np.log(V0 * theta / Dc))
     active = np.ones(A.shape, bool)
     for _ in range(max_iter):
@@ -70,10 +82,16 @@ def solve_velocity(A, theta, eta, a, b, Dc, sigma_n, V0, f0, x0, tol=1e-14, max_
         ex = np.exp(x)
         g = A - eta * ex - c - sigma_n * a * x
         dg = -eta * ex - sigma_n * a
-        dx = np.clip(-g / dg, -5.0, 5.0)
-        dx = np.where(active, dx, 0.0)
+        step = -g / dg
+        with np.errstate(invalid="ignore", divide="ignore"):
+            cap = np.log(np.maximum(A - c - sigma_n * a * x, 1e-300) / eta)
+        up = np.where(step > 1.0, np.minimum(step, np.maximum(cap - x, 1.0)), step)
+        xn = np.where(step > 0, x + up, np.maximum(x + step, X_MIN))
+        dx = np.where(active, xn - x, 0.0)
         x = x + dx
         active = active & (np.abs(dx) > tol * np.maximum(1.0, np.abs(x)))
     if active.any():
         raise NotConverged(f"{int(active.sum())} elements did not converge")
+    if not np.all(np.isfinite(x)):
+        raise NotConverged(f"{int(np.sum(~np.isfinite(x)))} elements met a non-finite force balance")
     return np.exp(x)

@@ -504,19 +504,34 @@ __device__ __forceinline__ double state_after(double th0, double V, double Dc, d
   return Dc / V * pow(u0 * e + om, 1.0 / eps);
 }
 
-// Newton on x = ln V for A - eta V = sigma_n [f0 + a (x - ln V0) + b ln(V0 theta / Dc)];
-// steps clamped to |dx| <= 5, stop at |dx| <= 1e-14 max(1, |x|), at most 50 iterations.
+// Newton on x = ln V for A - eta V = sigma_n [f0 + a (x - ln V0) + b ln(V0 theta / Dc)]:
+// the residual g is decreasing and concave, so a downward step (taken from the
+// right of the root) never crosses it and is taken whole; an upward step longer
+// than 1 (g > 0, where A - c - sn a x > eta e^x > 0) stops at
+// ln((A - c - sn a x)/eta), above which the root cannot lie, but moves at least 1
+// (near the root that bound is lost to cancellation and the steps are short);
+// x stays >= -690 (V >= ~1e-300, a rate that is zero
+// for every purpose). Stop at |dx| <= 1e-14 max(1, |x|), at most 50 iterations; a
+// non-finite iterate fails the solve.
 __device__ double newton_lnV(double A, double th, double eta, double a, double b, double Dc, double sn, double V0,
                              double f0, double x, int* fail) {
+  constexpr double kXMin = -690.0;
   const double c = sn * (f0 - a * log(V0) + b * log(V0 * th / Dc));
+  x = fmax(x, kXMin);
   for (int it = 0; it < 50; ++it) {
     const double ex = exp(x);
     const double g = A - eta * ex - c - sn * a * x;
+    if (!isfinite(g)) break;  // (fmax below would hide a NaN)
     const double dg = -eta * ex - sn * a;
-    double dx = -g / dg;
-    dx = fmin(5.0, fmax(-5.0, dx));
-    x += dx;
-    if (!(fabs(dx) > 1e-14 * fmax(1.0, fabs(x)))) return exp(x);
+    const double step = -g / dg;
+    const double up = step > 1.0 ? fmin(step, fmax(log(fmax(A - c - sn * a * x, 1e-300) / eta) - x, 1.0)) : step;
+    const double xn = step > 0.0 ? x + up : fmax(x + step, kXMin);
+    const double dx = xn - x;
+    x = xn;
+    if (!(fabs(dx) > 1e-14 * fmax(1.0, fabs(x)))) {
+      if (isfinite(x)) return exp(x);
+      break;  // a non-finite force balance (e.g. a non-finite stress) fails the solve
+    }
   }
   *fail = 1;
   return exp(x);

@@ -11,9 +11,9 @@
   same meaning as the oracle's state (V also the newest rate row, delta also the
   newest slip-coefficient row, the state rate recomputed).
 
-The failure is forced from the host by a slip rate so far below the root of the
-force balance that the clamped Newton iteration needs more than 50 steps (every
-kernel still runs to completion).
+The failure is forced from the host by a background stress that is not finite:
+the solve meets a non-finite force balance, which fails it (every kernel still
+runs to completion).
 """
 import numpy as np
 import pytest
@@ -66,9 +66,10 @@ def test_newton_failure_holds_last_good_step(S):
     st = P.State(op, fric, ini["V"], ini["theta"], ini["tau0"], stream=s)
     st.step(33, stream=s)
     st.check(stream=s)
-    good = {k: st.read(k, stream=s) for k in ("V", "theta", "delta", "thetadot")}
-    bad_V = np.full(op.N, 1e-300)
-    st.write("V", bad_V, stream=s)
+    good = {k: st.read(k, stream=s) for k in ("V", "theta", "delta", "thetadot", "tau0")}
+    bad = good["tau0"].copy()
+    bad[5] = np.nan
+    st.write("tau0", bad, stream=s)
     print(f"[gpu] forced Newton failure S={S}", flush=True)
     st.step(7, stream=s)                       # fails at step 34; 35..40 leave it alone
     with pytest.raises(P.SeasError) as e:
@@ -77,12 +78,10 @@ def test_newton_failure_holds_last_good_step(S):
     assert st.step_index == 33
     failed, at = st.variant_status(stream=s)
     assert not failed[0] and at[0] == 33       # flag cleared by the check, held at 33
-    assert np.array_equal(st.read("V", stream=s), bad_V)
-    assert np.array_equal(st.read("theta", stream=s), good["theta"])
-    assert np.array_equal(st.read("delta", stream=s), good["delta"])
-    # put back the rate that made it fail: the run continues as if nothing happened
-    st.write("V", good["V"], stream=s)
-    assert np.allclose(st.read("thetadot", stream=s), good["thetadot"], rtol=1e-14, atol=0)
+    for k in ("V", "theta", "delta", "thetadot"):
+        assert np.array_equal(st.read(k, stream=s), good[k]), k
+    # put back the stress that made it fail: the run continues as if nothing happened
+    st.write("tau0", good["tau0"], stream=s)
     st.step(20, stream=s)
     st.check(stream=s)
     assert st.step_index == 53
@@ -102,11 +101,12 @@ def test_failed_variant_is_held_and_the_others_step_on():
     tile = lambda x: np.tile(x, nv)
     fr = {k: tile(v) for k, v in fric.items()}
     V = tile(ini["V"])
-    V_bad = V.copy()
-    V_bad[3 * N:4 * N] = 1e-300
+    t0 = tile(ini["tau0"])
+    t0_bad = t0.copy()
+    t0_bad[3 * N + 7] = np.nan
     runs = []
-    for V0 in (V, V_bad):
-        st = P.State(op, fr, V0, tile(ini["theta"]), tile(ini["tau0"]), stream=s)
+    for tau0 in (t0, t0_bad):
+        st = P.State(op, fr, V, tile(ini["theta"]), tau0, stream=s)
         st.step(40, stream=s)
         runs.append(st)
     runs[0].check(stream=s)
@@ -115,7 +115,7 @@ def test_failed_variant_is_held_and_the_others_step_on():
     failed, at = runs[1].variant_status(stream=s)
     assert failed.tolist() == [v == 3 for v in range(nv)]
     assert at[3] == 0 and all(at[v] == 40 for v in range(nv) if v != 3)
-    assert np.array_equal(runs[1].read("V", stream=s, variant=3), V_bad[3 * N:4 * N])
+    assert np.array_equal(runs[1].read("V", stream=s, variant=3), V[3 * N:4 * N])
     assert np.array_equal(runs[1].read("delta", stream=s, variant=3), np.zeros(N))
     for v in (0, 2, 4, 15):
         for k in ("V", "theta", "delta"):

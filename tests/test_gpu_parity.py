@@ -218,13 +218,15 @@ def test_checkpoint_resume_is_bitwise(S):
 
 
 def test_newton_failure_is_reported():
-    # slip rates 300 natural-log units below the root need more than 50 clamped steps
+    # a background stress that is not finite fails the solve
     faults = SI.two_fault_prescribed_faults(n_elem=8, dx=1600.0)
     op = P.Operator(faults, SI.default_params())
     N = op.N
     fr = _dummy_friction(N)
     s = _stream()
-    st = P.State(op, fr, np.full(N, 1e-300), np.full(N, 5e-3 / 1e-6), np.full(N, 0.6 * 50e6), stream=s)
+    tau0 = np.full(N, 0.6 * 50e6)
+    tau0[3] = np.nan
+    st = P.State(op, fr, np.full(N, 1e-9), np.full(N, 5e-3 / 1e-6), tau0, stream=s)
     st.step(1, stream=s)
     with pytest.raises(P.SeasError) as e:
         st.check(stream=s)

@@ -110,13 +110,15 @@ def test_server_results_alone_and_in_the_mix():
     # others keep the results they get alone
     bad = dict(reqs[3])
     bw = dict(bad["window"])
-    bw["V"] = np.full(len(bw["V"]), 1e-300)
+    bw["tau0"] = bw["tau0"].copy()
+    bw["tau0"][4] = np.nan
     bad["window"] = bw
     mixed = list(reqs[:8])
     mixed[3] = bad
     resb = sv.run(mixed)
     assert resb[3]["status"] == -4
     assert np.array_equal(resb[3]["V"], bw["V"]) and np.array_equal(resb[3]["theta"], bw["theta"])
+    assert np.array_equal(resb[3]["delta"], np.zeros(len(bw["V"])))
     for i in range(8):
         if i != 3:
             assert resb[i]["status"] == 0

@@ -68,6 +68,25 @@ def test_newton_root_matches_bisection():
     assert np.allclose(np.log(V), 0.5 * (lo + hi), rtol=0, atol=1e-12)
 
 
+def test_newton_far_roots_and_the_rate_floor():
+    # Roots far below the start (a stress deficit of hundreds of MPa, as at an
+    # element next to a fault crossing after a rupture) are reached within the
+    # iteration limit from either side; a root below ln V = -690 leaves V at the
+    # floor exp(-690) (zero for every purpose) instead of underflowing to 0.
+    eta = SI.MU / (2 * SI.CS)
+    a, b, Dc, sn, V0, f0 = 0.01, 0.015, 5e-3, 50e6, 1e-6, 0.6
+    theta = np.full(4, 1e3)
+    c = sn * (f0 - a * np.log(V0) + b * np.log(V0 * theta / Dc))
+    x_root = np.array([-600.0, -300.0, -120.0, 5.0])
+    A = c + sn * a * x_root + eta * np.exp(x_root)       # the force balance holds at x_root
+    for x0 in (np.log(1e-9), 2.0, -650.0):
+        V = FR.solve_velocity(A, theta, eta, a, b, Dc, sn, V0, f0, np.full(4, x0))
+        assert np.allclose(np.log(V), x_root, rtol=0, atol=1e-9), x0
+    A_deep = c[:1] + sn * a * (-3400.0)
+    V = FR.solve_velocity(A_deep, theta[:1], eta, a, b, Dc, sn, V0, f0, np.log(1e-9))
+    assert V[0] == np.exp(FR.X_MIN) and V[0] > 0
+
+
 def test_intermediate_law_limits():
     V, th, Dc = 1e-3, 3.0, 5e-3
     assert FR.state_rate(V, th, Dc, 1.0) == pytest.approx(1 - V * th / Dc)
