@@ -123,7 +123,12 @@ typedef struct {
                            predictor, the averaged rate in the corrector), which keeps theta > 0
                            when the rate jumps by decades in one step (the explicit form cannot
                            start the two-fault benchmark of Section 3.1) */
-  int32_t reserved;
+  int32_t cluster_windows; /* 0: the causality window of Section 2.3.2 per fault pair; 1: per
+                           H-matrix block (the cluster-level truncation Section 4.3 proposes):
+                           a block's upper lag follows the pair rule applied to its clusters
+                           (source midpoints to the receiver cluster's end points), at most the
+                           pair's, and slip older than it contributes the block's static stress
+                           (with int_tail); seas_operator_blocks reports each block's upper lag */
 } seas_params_t;
 
 typedef struct seas_op seas_op_t;
@@ -188,9 +193,11 @@ seas_status seas_operator_info(const seas_op_t* op, seas_op_info_t* out);
  * n_faults * (n_faults - 1) entries each. */
 seas_status seas_operator_windows(const seas_op_t* op, int32_t* T_init, int32_t* T_end);
 
-/* Block partition of the ordered pair (a, b): count (blocks == NULL) or copy
- * rows of 5 int32: r0, r1, s0, s1 (element ranges local to the faults) and
- * 1 for admissible / 0 for near-field, in depth-first traversal order. */
+/* Block partition of the ordered pair (a, b) (the dual-tree traversal of
+ * Section 2.3.2): count (blocks == NULL) or copy rows of 6 int32: r0, r1, s0, s1
+ * (element ranges local to the faults), 1 for admissible / 0 for near-field, and
+ * the block's upper lag (the pair's T_end, or its own with cluster_windows), in
+ * depth-first traversal order. */
 seas_status seas_operator_blocks(const seas_op_t* op, int32_t a, int32_t b,
                                  int32_t* blocks, int64_t* count);
 

@@ -144,6 +144,21 @@ def pair_window_lags(geo, a, b, cs, dt, eta_tmin, eta_tmax):
     return int(math.floor(t0 / dt)), int(math.ceil(t1 / dt))
 
 
+def block_window_end(geo, a, b, blk, cs, dt, eta_tmax):
+    """Upper lag of one H-matrix block under cluster-level truncation (Section 4.3
+    proposes truncating at the level of the cluster pairs of the hierarchical
+    partition instead of whole fault pairs): the pair rule applied to the block,
+    T_max = the largest distance from a source midpoint of the source cluster to an
+    end point of the receiver cluster (its outer element edges), over cs;
+    T_end = ceil((1 + eta_Tmax) T_max / dt)."""
+    r0, r1, s0, s1 = blk[:4]
+    A, B = geo[a], geo[b]
+    ends = np.array([A.c + (-0.5 * A.L + r0 * A.dx) * A.t, A.c + (-0.5 * A.L + r1 * A.dx) * A.t])
+    src = B.mid[s0:s1]
+    dmax = float(np.sqrt(((src[:, None, :] - ends[None, :, :]) ** 2).sum(-1)).max())
+    return int(math.ceil((1.0 + eta_tmax) * dmax / cs / dt))
+
+
 # ----------------------------------------------------------------------------
 # Static dipole stress (late-time limit of -mu/(2cs) K^T / dt)
 # ----------------------------------------------------------------------------
@@ -177,7 +192,11 @@ class DenseInteraction:
     window, and the static tail matrices."""
 
     def __init__(self, geo, mu, cs, dt, eta_tmin=0.01, eta_tmax=0.01, windowed=True,
-                 max_lag=None, with_tail=True):
+                 max_lag=None, with_tail=True, blocks=None):
+        """``blocks`` (the partition of every pair, from hpartition.partition):
+        cluster-level windows, every entry (i, j) truncated at the upper lag of the
+        block that holds it (``block_window_end``, at most the pair's T_end); its
+        older slip then contributes the static stress per block."""
         self.geo, self.mu, self.cs, self.dt = geo, mu, cs, dt
         self.off = [0]
         for f in geo:
@@ -197,7 +216,19 @@ class DenseInteraction:
                 lags = np.arange(T0, T1s + 1)
                 K = pair_kernel_stack(geo, a, b, lags, dt, cs)
                 G = static_dipole(geo, a, b, mu) if with_tail else None
-                self.pairs[(a, b)] = dict(T0=T0, T1=T1, T1s=T1s, K=K, G=G)
+                P = dict(T0=T0, T1=T1, T1s=T1s, K=K, G=G)
+                if blocks is not None:
+                    bl = [(r0, r1, s0, s1, min(T1, block_window_end(geo, a, b, (r0, r1, s0, s1), cs, dt, eta_tmax)))
+                          for r0, r1, s0, s1, _ in blocks[(a, b)]]
+                    Tend = np.full(K.shape[1:], -1, dtype=np.int64)
+                    for r0, r1, s0, s1, te in bl:
+                        Tend[r0:r1, s0:s1] = te
+                    assert np.all(Tend >= 0), "the partition must cover the pair"
+                    P["blocks"] = bl
+                    P["Tend"] = Tend
+                    # entries past their block's window are dropped from the stack
+                    P["K"] = np.where(lags[:, None, None] <= Tend[None], K, 0.0)
+                self.pairs[(a, b)] = P
 
     def stress(self, Vh, head, first, min_lag=0, expired=None):
         """f_i = -mu/(2cs) sum_{b != a} sum_{T=max(T_init,min_lag)}^{T_end} sum_j K^T_ij V_j^{head-T}
@@ -220,7 +251,15 @@ class DenseInteraction:
                 hv = Vh[ms[ok] - first][:, rb]                  # (n_lags, q)
                 acc = -eta * np.einsum("tpq,tq->p", P["K"][ok], hv, optimize=False)
             if expired is not None and P["G"] is not None:
-                acc = acc + P["G"] @ expired[(a, b)]
+                if "blocks" in P:
+                    # per block: slip older than the block's window, static stress
+                    for r0, r1, s0, s1, te in P["blocks"]:
+                        last = head - te - 1
+                        if last >= first:
+                            E = self.dt * np.sum(Vh[: last - first + 1, self.off[b] + s0:self.off[b] + s1], axis=0)
+                            acc[r0:r1] += P["G"][r0:r1, s0:s1] @ E
+                else:
+                    acc = acc + P["G"] @ expired[(a, b)]
             f[self.off[a]:self.off[a + 1]] += acc
         return f
 

@@ -21,7 +21,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import friction, geometry, interaction, selfterm
+from . import friction, geometry, hpartition, interaction, selfterm
 
 
 class Problem:
@@ -37,10 +37,13 @@ class Problem:
         self.with_tail = bool(p.get("int_tail", 1))
         self.inter = None
         if dense:
+            blocks = None
+            if int(p.get("cluster_windows", 0)):
+                blocks = hpartition.partition(self.geo, float(p.get("eta_H", 2.0)), int(p.get("leaf", 50)))
             self.inter = interaction.DenseInteraction(
                 self.geo, self.mu, self.cs, self.dt, float(p.get("eta_tmin", 0.01)),
                 float(p.get("eta_tmax", 0.01)), windowed=True, max_lag=n_hist_max,
-                with_tail=self.with_tail)
+                with_tail=self.with_tail, blocks=blocks)
         self.selfs = []
         cache = {}
         for f in self.geo:

@@ -40,7 +40,7 @@ class Params(C.Structure):
                 ("int_tail", C.c_int32), ("q_w", C.c_int32), ("mode_cap", C.c_int32),
                 ("factor_dtype", C.c_int32), ("n_threads", C.c_int32), ("host_only", C.c_int32),
                 ("time_block", C.c_int32), ("n_variants", C.c_int32), ("state_update", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("cluster_windows", C.c_int32)]
 
 
 class OpInfo(C.Structure):
@@ -164,6 +164,7 @@ def make_params(p):
     q.time_block = int(p.get("time_block", 1))
     q.n_variants = int(p.get("n_variants", 1))
     q.state_update = {"explicit": 0, "exact": 1, 0: 0, 1: 1}[p.get("state_update", "explicit")]
+    q.cluster_windows = int(p.get("cluster_windows", 0))
     return q
 
 
@@ -200,10 +201,18 @@ class Operator:
     def blocks(self, a, b):
         cnt = C.c_int64(0)
         _check(lib().seas_operator_blocks(self.h, a, b, None, C.byref(cnt)))
-        buf = (C.c_int32 * (5 * cnt.value))()
+        buf = (C.c_int32 * (6 * cnt.value))()
         _check(lib().seas_operator_blocks(self.h, a, b, buf, C.byref(cnt)))
-        v = np.frombuffer(buf, dtype=np.int32).reshape(-1, 5)
+        v = np.frombuffer(buf, dtype=np.int32).reshape(-1, 6)
         return [(int(r[0]), int(r[1]), int(r[2]), int(r[3]), bool(r[4])) for r in v]
+
+    def block_windows(self, a, b):
+        """Upper lag of every block of the pair (a, b), in the order of ``blocks``."""
+        cnt = C.c_int64(0)
+        _check(lib().seas_operator_blocks(self.h, a, b, None, C.byref(cnt)))
+        buf = (C.c_int32 * (6 * cnt.value))()
+        _check(lib().seas_operator_blocks(self.h, a, b, buf, C.byref(cnt)))
+        return [int(x) for x in np.frombuffer(buf, dtype=np.int32).reshape(-1, 6)[:, 5]]
 
     def self_table(self, k, n):
         W = C.c_int32(0)

@@ -118,7 +118,7 @@ struct seas_op {
   double2* tw = nullptr;
   double* tab = nullptr;
   int* fault_of = nullptr;
-  int32_t *src_pairs = nullptr, *src_pairs_ptr = nullptr;
+  int32_t *tail_src = nullptr, *tail_src_ptr = nullptr;
   std::vector<SelfMode> hmodes;
   std::vector<SelfFaultDev> hsf;
   size_t elem_bytes = 8;  // bytes of a stored far-list factor value
@@ -219,8 +219,8 @@ StepArgs<TF> make_args(seas_op* op, seas_state* st) {
   a.op_vfast = op->ring_bytes == 2;
   a.R = h.ring_len;
   a.tail_acc = st->tail_acc;
-  a.src_pairs = op->src_pairs;
-  a.src_pairs_ptr = op->src_pairs_ptr;
+  a.tail_src = op->tail_src;
+  a.tail_src_ptr = op->tail_src_ptr;
   a.first = st->first;
   a.tail = h.prm.int_tail;
   a.exact_state = h.prm.state_update == 1;
@@ -527,18 +527,9 @@ seas_status seas_build_operator(const seas_fault_t* faults, int32_t n_faults, co
     op->modes = upload(op->owned, op->hmodes);
     op->tw = upload(op->owned, tw);
     op->fault_of = upload(op->owned, fault_of);
-    // pairs by source fault (expired-slip updates)
-    std::vector<int32_t> sp, spp(h.faults.size() + 1, 0);
-    for (size_t k = 0; k < h.faults.size(); ++k) {
-      for (size_t pi = 0; pi < h.pairs.size(); ++pi)
-        if (h.pairs[pi].b == (int)k) {
-          sp.push_back(h.tail_off[pi]);
-          sp.push_back(h.pairs[pi].T_end);
-        }
-      spp[k + 1] = (int32_t)(sp.size() / 2);
-    }
-    op->src_pairs = upload(op->owned, sp);
-    op->src_pairs_ptr = upload(op->owned, spp);
+    // expired-slip updates per source element
+    op->tail_src = upload(op->owned, h.tail_src);
+    op->tail_src_ptr = upload(op->owned, h.tail_src_ptr);
     *out = op.release();
   });
 }
@@ -716,11 +707,12 @@ seas_status seas_operator_blocks(const seas_op_t* op, int32_t a, int32_t b, int3
     if (blocks) {
       if (*count < (int64_t)bl.size()) throw Error(SEAS_ERR_INVALID_ARG, "block buffer too small");
       for (size_t i = 0; i < bl.size(); ++i) {
-        blocks[5 * i + 0] = bl[i].r0;
-        blocks[5 * i + 1] = bl[i].r1;
-        blocks[5 * i + 2] = bl[i].s0;
-        blocks[5 * i + 3] = bl[i].s1;
-        blocks[5 * i + 4] = bl[i].adm;
+        blocks[6 * i + 0] = bl[i].r0;
+        blocks[6 * i + 1] = bl[i].r1;
+        blocks[6 * i + 2] = bl[i].s0;
+        blocks[6 * i + 3] = bl[i].s1;
+        blocks[6 * i + 4] = bl[i].adm;
+        blocks[6 * i + 5] = bl[i].T_end;
       }
     }
     *count = (int64_t)bl.size();
@@ -897,17 +889,18 @@ seas_status seas_state_load_history(seas_state_t* st, const double* V_hist, int3
                  nullptr, st->F, st->dring, 1, m, 0, s);
       HIPCHK(hipStreamSynchronize(s));
     }
-    // expired-slip accumulators: dt sum of V^m, m <= -T_end - 1
+    // expired-slip accumulators: dt sum of V^m, m <= -T_end - 1, for every
+    // (accumulator, upper lag) entry of every source element
     if (h.prm.int_tail) {
       std::vector<double> E((size_t)h.tail_len * nv, 0.0);
       for (int v = 0; v < nv; ++v)
-        for (size_t pi = 0; pi < h.pairs.size(); ++pi) {
-          const Fault& B = h.faults[h.pairs[pi].b];
-          for (int64_t m = -H; m <= -(int64_t)h.pairs[pi].T_end - 1; ++m) {
-            const double* row = V_hist + (size_t)(H + m) * N + (size_t)v * Ne + B.off;
-            for (int j = 0; j < B.Np; ++j) E[(size_t)v * h.tail_len + h.tail_off[pi] + j] += h.dt * row[j];
+        for (size_t r = 0; r < Ne; ++r)
+          for (int32_t e = h.tail_src_ptr[r]; e < h.tail_src_ptr[r + 1]; ++e) {
+            const int32_t acc = h.tail_src[2 * e], Tend = h.tail_src[2 * e + 1];
+            double sum = 0.0;
+            for (int64_t m = -H; m <= -(int64_t)Tend - 1; ++m) sum += h.dt * V_hist[(size_t)(H + m) * N + (size_t)v * Ne + r];
+            E[(size_t)v * h.tail_len + acc] += sum;
           }
-        }
       HIPCHK(hipMemcpyAsync(st->tail_acc, E.data(), E.size() * 8, hipMemcpyHostToDevice, s));
       HIPCHK(hipStreamSynchronize(s));
     }

@@ -191,11 +191,11 @@ static void traverse(const std::vector<Node>& to, const std::vector<Node>& ts, d
     const double d = std::hypot(O.cx - S.cx, O.cy - S.cy);
     const bool oleaf = O.kid0 < 0, sleaf = S.kid0 < 0;
     if (d > eta_H * (O.r + S.r)) {
-      out.push_back({pair, a, b, O.lo, O.hi, S.lo, S.hi, 1});
+      out.push_back({pair, a, b, O.lo, O.hi, S.lo, S.hi, 1, 0, 0});
       return;
     }
     if (oleaf && sleaf) {
-      out.push_back({pair, a, b, O.lo, O.hi, S.lo, S.hi, 0});
+      out.push_back({pair, a, b, O.lo, O.hi, S.lo, S.hi, 0, 0, 0});
       return;
     }
     bool split_o;
@@ -554,7 +554,7 @@ static void build_subblock(const HostOp& op, const BlockDesc& bd, const PairWin&
   };
   std::vector<double> G0((size_t)p * q), G1((size_t)p * q), K((size_t)p * q), U, W, R;
   std::vector<LagFactor> lags;
-  const int T_lo = std::max(1, pw.T_init), T_hi = pw.T_end;
+  const int T_lo = std::max(1, pw.T_init), T_hi = bd.T_end;
   out.dense += (int64_t)p * q * (pw.T_end - pw.T_init + 1);
   auto compress = [&](int T) {
     LagFactor lf;
@@ -590,7 +590,7 @@ static void build_subblock(const HostOp& op, const BlockDesc& bd, const PairWin&
       for (int j = 0; j < q; ++j)
         K[(size_t)i * q + j] = -static_stress(A, bd.r0 + i, B, s0 + j, op.prm.mu) / op.eta;
     compress(-1);
-    toff = op.tail_off[bd.pair];
+    toff = bd.tail_base - bd.s0;  // accumulator of source column s0 + j is toff + s0 + j
   }
   std::vector<LagFactor*> far, near;
   for (auto& lf : lags) {
@@ -671,6 +671,8 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
     throw Error(SEAS_ERR_INVALID_ARG, "leaf >= 1, eta_H > 0, aca_tol > 0, eta_w > 0 required");
   if (prm.factor_dtype < SEAS_F64 || prm.factor_dtype > SEAS_F16)
     throw Error(SEAS_ERR_INVALID_ARG, "factor_dtype must be SEAS_F64, SEAS_F32, SEAS_BF16 or SEAS_F16");
+  if (prm.cluster_windows != 0 && prm.cluster_windows != 1)
+    throw Error(SEAS_ERR_INVALID_ARG, "cluster_windows must be 0 or 1");
   if (prm.state_update != 0 && prm.state_update != 1)
     throw Error(SEAS_ERR_INVALID_ARG, "state_update must be 0 (explicit) or 1 (closed form at constant rate)");
   if (prm.time_block < 0 || prm.time_block > kMaxTimeBlock ||
@@ -758,17 +760,55 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
   for (int k = 0; k < nf; ++k) build_tree(op.faults[k], prm.leaf, trees[k]);
   op.blocks.assign(op.pairs.size(), {});
   std::vector<BlockDesc> all;
-  for (size_t pi = 0; pi < op.pairs.size(); ++pi) {
-    traverse(trees[op.pairs[pi].a], trees[op.pairs[pi].b], prm.eta_H, (int)pi, op.pairs[pi].a, op.pairs[pi].b,
-             op.blocks[pi]);
-    all.insert(all.end(), op.blocks[pi].begin(), op.blocks[pi].end());
-  }
-  // tail accumulators: one per (pair, source element)
+  // tail accumulators: one per (pair, source element), or per (block, source
+  // element) with cluster-level windows
   op.tail_off.assign(op.pairs.size(), 0);
   op.tail_len = 0;
   for (size_t pi = 0; pi < op.pairs.size(); ++pi) {
+    const PairWin& w = op.pairs[pi];
+    traverse(trees[w.a], trees[w.b], prm.eta_H, (int)pi, w.a, w.b, op.blocks[pi]);
     op.tail_off[pi] = (int32_t)op.tail_len;
-    op.tail_len += op.faults[op.pairs[pi].b].Np;
+    if (!prm.cluster_windows) op.tail_len += op.faults[w.b].Np;
+    const Fault &A = op.faults[w.a], &B = op.faults[w.b];
+    for (BlockDesc& bd : op.blocks[pi]) {
+      bd.T_end = w.T_end;
+      bd.tail_base = op.tail_off[pi] + bd.s0;
+      if (prm.cluster_windows) {
+        // the pair rule on the block: source midpoints to the receiver cluster's end points
+        double dmax = 0.0;
+        for (int e = 0; e < 2; ++e) {
+          const double sa = -0.5 * A.L + (e == 0 ? bd.r0 : bd.r1) * A.dx;
+          const double ex = A.cx + sa * A.tx, ey = A.cy + sa * A.ty;
+          for (int j = bd.s0; j < bd.s1; ++j) dmax = std::max(dmax, std::hypot(B.midx(j) - ex, B.midy(j) - ey));
+        }
+        bd.T_end = std::min(w.T_end, (int)std::ceil((1.0 + prm.eta_tmax) * dmax / cs / dt));
+        bd.tail_base = (int32_t)op.tail_len;
+        op.tail_len += bd.s1 - bd.s0;
+      }
+    }
+    all.insert(all.end(), op.blocks[pi].begin(), op.blocks[pi].end());
+  }
+  // expired-slip updates per source element: (accumulator, upper lag) entries
+  {
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> per(op.N);
+    for (size_t pi = 0; pi < op.pairs.size(); ++pi) {
+      const Fault& B = op.faults[op.pairs[pi].b];
+      if (!prm.cluster_windows) {
+        for (int j = 0; j < B.Np; ++j) per[B.off + j].push_back({op.tail_off[pi] + j, op.pairs[pi].T_end});
+      } else {
+        for (const BlockDesc& bd : op.blocks[pi])
+          for (int j = bd.s0; j < bd.s1; ++j) per[B.off + j].push_back({bd.tail_base + (j - bd.s0), bd.T_end});
+      }
+    }
+    op.tail_src_ptr.assign(op.N + 1, 0);
+    op.tail_src.clear();
+    for (int r = 0; r < op.N; ++r) {
+      for (auto& e : per[r]) {
+        op.tail_src.push_back(e.first);
+        op.tail_src.push_back(e.second);
+      }
+      op.tail_src_ptr[r + 1] = (int32_t)(op.tail_src.size() / 2);
+    }
   }
   // ---- lag-0 CSR (pairs whose window starts at lag 0)
   {
@@ -798,7 +838,7 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
   std::iota(order.begin(), order.end(), 0);
   auto cost = [&](const BlockDesc& b) {
     const PairWin& w = op.pairs[b.pair];
-    return (double)(b.r1 - b.r0) * (b.s1 - b.s0) * (w.T_end - w.T_init + 1);
+    return (double)(b.r1 - b.r0) * (b.s1 - b.s0) * (b.T_end - w.T_init + 1);
   };
   std::sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cost(all[x]) > cost(all[y]); });
   std::vector<BlockOut> outs(all.size());

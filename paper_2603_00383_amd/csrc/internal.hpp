@@ -96,6 +96,8 @@ struct PairWin {
 
 struct BlockDesc {
   int pair, a, b, r0, r1, s0, s1, adm;
+  int T_end;      // upper lag of the block (the pair's, or its own with cluster_windows)
+  int tail_base;  // first expired-slip accumulator of the block's source columns (its own or the pair's)
 };
 
 struct SelfFault {          // self-term tables of one fault
@@ -149,6 +151,10 @@ struct HostOp {
   std::vector<int32_t> red_idx[2];    // base partial index of each (receiver, item)
   std::vector<int32_t> tail_off; // per pair: offset of its accumulator; total tail_len
   int64_t tail_len = 0;
+  // expired-slip updates per source element (global index): CSR over (accumulator,
+  // upper lag) entries, one per pair (or per block with cluster_windows) whose
+  // source columns hold the element
+  std::vector<int32_t> tail_src_ptr, tail_src;
   // lag-0 CSR (FP64)
   std::vector<int32_t> l0_ptr, l0_col;
   std::vector<double> l0_val;

@@ -537,15 +537,16 @@ __device__ double newton_lnV(double A, double th, double eta, double a, double b
   return exp(x);
 }
 
-// Expired-slip accumulators of the pairs whose source is element r's fault:
-// E += dt V^{t}, t = time_new - T_end - 1 (the rate that just left the window).
+// Expired-slip accumulators that source element r feeds (one per pair, or per
+// block with cluster-level windows): E += dt V^t, t = time_new - T_end - 1 (the
+// rate that just left that window).
 template <typename TF>
-__device__ __forceinline__ void tail_update(const StepArgs<TF>& a, int v, int r, int k, int j) {
+__device__ __forceinline__ void tail_update(const StepArgs<TF>& a, int v, int r) {
   double* E = a.tail_acc + v * a.tail_len;
-  for (int e = a.src_pairs_ptr[k]; e < a.src_pairs_ptr[k + 1]; ++e) {
-    const int toff = a.src_pairs[2 * e], Tend = a.src_pairs[2 * e + 1];
+  for (int e = a.tail_src_ptr[r]; e < a.tail_src_ptr[r + 1]; ++e) {
+    const int acc = a.tail_src[2 * e], Tend = a.tail_src[2 * e + 1];
     const int64_t t = a.time_new - Tend - 1;
-    if (t >= a.first) E[toff + j] += a.dt * a.ring64[(ring_slot(t, a.R) * a.nv + v) * a.N + r];
+    if (t >= a.first) E[acc] += a.dt * a.ring64[(ring_slot(t, a.R) * a.nv + v) * a.N + r];
   }
 }
 
@@ -626,10 +627,7 @@ __global__ void k_commit(StepArgs<TF> a) {
     a.ring64[ri] = V2;
     if ((void*)a.ringop != (void*)a.ring64)
       a.ringop[a.op_vfast ? (sl * a.N + r) * a.nv + v : ri] = to_op<TF>(V2);
-    if (a.tail) {
-      const int k = a.fault_of[r];
-      tail_update(a, v, r, k, r - a.sf[k].off);
-    }
+    if (a.tail) tail_update(a, v, r);
     if (r == 0) a.good[v] = a.time_new;
     return;
   }
@@ -653,10 +651,7 @@ __global__ void k_pre_push(StepArgs<TF> a, const double* __restrict__ Vin) {
   a.ring64[ri] = x;
   if ((void*)a.ringop != (void*)a.ring64) a.ringop[a.op_vfast ? (sl * a.N + r) * a.nv + v : ri] = to_op<TF>(x);
   a.delta[rg] += a.dt * x;
-  if (a.tail) {
-    const int k = a.fault_of[r];
-    tail_update(a, v, r, k, r - a.sf[k].off);
-  }
+  if (a.tail) tail_update(a, v, r);
 }
 
 // Prescribed mode output: f^n = f_self + f_hist - mu/(2cs) K^0 V^{n-1} (one wave

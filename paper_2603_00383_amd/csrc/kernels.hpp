@@ -64,8 +64,8 @@ struct StepArgs {
   int64_t R, time_new;      // ring length, time of the appended row
   // expired-slip accumulators
   double* tail_acc;
-  const int32_t* src_pairs;     // per fault: list of (pair tail offset, T_end) for pairs with that source
-  const int32_t* src_pairs_ptr; // per fault: range in src_pairs (pairs of 2 ints)
+  const int32_t* tail_src;      // per source element: (accumulator, upper lag) entries (pairs of 2 ints)
+  const int32_t* tail_src_ptr;  // per source element: range in tail_src
   int64_t first;            // earliest time held in the histories
   int tail;                 // static tail on
   int exact_state;          // state law integrated in closed form over the step (else explicit)

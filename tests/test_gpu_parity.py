@@ -286,3 +286,39 @@ def test_fp32_segment_kernel_matches_item_kernel(monkeypatch):
     print(f"[gpu] FP32 segment vs item kernel: {e:.2e} ({op_s.info['n_segments']} segments, "
           f"{op_i.info['n_items']} items)", flush=True)
     assert e < 1e-5
+
+
+# ----------------------------------------------------------------- cluster-level windows
+@pytest.mark.parametrize("S", [1, 16])
+def test_cluster_windows_prescribed_against_oracle(S):
+    # per-block upper lags (Section 4.3's cluster-level truncation) with the static
+    # tail per block: the ragged network with a prior history long enough for slip
+    # to leave every block window
+    p = SI.default_params(compress=1, aca_tol=1e-13, eta_H=1.5, leaf=5, int_tail=1, time_block=S,
+                          cluster_windows=1)
+    n_steps = 140
+    V = SI.prescribed_slip_rate(RAG, n_steps, 7, lo_exp=-6, hi_exp=0)
+    prior = SI.prescribed_slip_rate(RAG, 90, 8, lo_exp=-6, hi_exp=0)
+    f, op = gpu_prescribed(RAG, p, V, prior=prior)
+    assert any(te < op.windows()[(0, 1)][1] for te in op.block_windows(0, 1))
+    ref = oracle_prescribed(("rag-cluster",), RAG, p, V, prior)
+    e = rel_err(f, ref)
+    print(f"[gpu] ragged cluster windows S={S}: err {e:.3e}")
+    assert e < 1e-10
+    # and the windows changed the result (the pair-window sum differs)
+    ref_pair = oracle_prescribed(("rag", 1), RAG, dict(p, cluster_windows=0), V, prior)
+    assert rel_err(ref, ref_pair) > 1e-6
+
+
+def test_cluster_windows_seas_trajectory():
+    faults = [SI.fault(0.0, 0.0, 0.0, 1200.0, 24), SI.fault(110.0, 35.0, 63.0, 1000.0, 20),
+              SI.fault(-300.0, 900.0, 150.0, 800.0, 16)]
+    p = SI.default_params(compress=1, aca_tol=1e-13, eta_H=1.5, leaf=4, time_block=8, cluster_windows=1)
+    fric, ini, prior = _seas_setup(faults, 5, prior_len=120, V_init=1e-6, bump=0.1)
+    g, _, op = _gpu_seas(faults, p, fric, ini, prior, 60, ("V", "theta", "delta", "f_hist"))
+    o = _oracle_seas(faults, p, fric, ini, prior, 60)
+    errs = {k: rel_err(g[k], ref) for k, ref in (("V", o.V), ("theta", o.theta), ("delta", o.delta),
+                                               ("f_hist", o.last["f_hist"]))}
+    print("[gpu] cluster windows SEAS: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()), flush=True)
+    for k, v in errs.items():
+        assert v < 1e-9, k

@@ -239,3 +239,34 @@ def test_wide_cluster_is_split_into_column_slices():
         R = op.lag_matrix(0, 1, T, 400, 400)
         assert np.linalg.norm(K) > 0
         assert np.linalg.norm(R - K) / np.linalg.norm(K) < 3e-6
+
+
+@pytest.mark.parametrize("dtype,S", [("f64", 1), ("f32", 16)])
+def test_cluster_windows_match_oracle(dtype, S):
+    """Cluster-level windows (cluster_windows = 1): every block's upper lag is the
+    oracle's block_window_end (at most the pair's T_end, some shorter), and the
+    reconstructed lag matrices are the dense kernel with each entry cut at its
+    block's upper lag; the static-tail matrix is unchanged."""
+    faults = SI.five_fault_network(seed=1, n_elem=40)
+    op = _op(faults, compress=0, eta_H=1.5, leaf=6, time_block=S, factor_dtype=dtype, cluster_windows=1)
+    geo = geometry.discretize(faults)
+    dt = geometry.time_step(geo, SI.CS)
+    blocks = HP.partition(geo, 1.5, 6)
+    shortened = 0
+    for (a, b), (t0, t1) in op.windows().items():
+        tw = op.block_windows(a, b)
+        for blk, te in zip(blocks[(a, b)], tw):
+            assert te == min(t1, I.block_window_end(geo, a, b, blk, SI.CS, dt, 0.01))
+            shortened += te < t1
+        Tend = np.zeros((40, 40), dtype=int)
+        for (r0, r1, s0, s1, _), te in zip(blocks[(a, b)], tw):
+            Tend[r0:r1, s0:s1] = te
+        for T in sorted({max(t0, 1), int(np.median(tw)), min(tw), max(tw), t1}):
+            if T < max(t0, 1):
+                continue
+            K = np.where(T <= Tend, I.pair_kernel(geo, a, b, T, dt, SI.CS), 0.0)
+            R = op.lag_matrix(a, b, T, 40, 40)
+            nrm = max(np.linalg.norm(K), 1e-300)
+            # (FP64: rounding of late-lag entries, differences of two time levels)
+            assert np.linalg.norm(R - K) / nrm < (1e-11 if dtype == "f64" else 1e-6), (a, b, T)
+    assert shortened > 0

@@ -154,3 +154,48 @@ def test_step_fault_equals_dense_step():
         assert _rel(got["f_int"], dense.last["f_int"][r]) < 1e-12
         if k == 0:
             assert len(got["partners"]) > 0
+
+
+# ----------------------------------------------------------------- cluster-level windows
+def test_cluster_windows_with_one_block_per_pair_are_the_pair_windows(rag):
+    # Section 4.3's cluster-level truncation reduces to the pair rule when a pair
+    # is one block (leaves as large as the faults)
+    prob, prior, V = rag
+    p1 = SI.default_params(eta_H=1.5, leaf=10_000, cluster_windows=1)
+    pc = OS.Problem(RAG, p1)
+    Vall = np.concatenate([prior, V])
+    first = -len(prior)
+    for (a, b), P in pc.inter.pairs.items():
+        assert len(P["blocks"]) == 1 and P["blocks"][0][4] == P["T1"]
+    for head in (5, 139):
+        ref = prob.inter.stress(Vall, head, first, expired=prob.inter.expired_slip(Vall, head, first, prob.dt))
+        got = pc.inter.stress(Vall, head, first, expired={})
+        assert _rel(got, ref) < 1e-14
+
+
+def test_cluster_windows_shorten_blocks_and_hand_over_per_block():
+    # every entry is seen through the dynamic kernel up to its block's upper lag and
+    # from the next lag on as exactly dt times the static stress of the dislocation
+    faults = [SI.fault(0.0, 0.0, 0.0, 2000.0, 20), SI.fault(200.0, 1800.0, 30.0, 1600.0, 16)]
+    p = SI.default_params(eta_H=1.5, leaf=4, cluster_windows=1)
+    prob = OS.Problem(faults, p)
+    eta = prob.mu / (2 * prob.cs)
+    off = prob.off
+    shortened = 0
+    for (a, b), P in prob.inter.pairs.items():
+        G = I.static_dipole(prob.geo, a, b, prob.mu)
+        shortened += sum(te < P["T1"] for *_, te in P["blocks"])
+        for r0, r1, s0, s1, te in P["blocks"][:: max(1, len(P["blocks"]) // 5)]:
+            assert P["T0"] <= te <= P["T1"]
+            jj = s0
+            i = r0
+            Vh = np.zeros((te + 4, prob.N))
+            Vh[0, off[b] + jj] = 1.0
+            for head in (te - 1, te, te + 1, te + 3):
+                f = prob.inter.stress(Vh, head, 0, expired={})[off[a] + i]
+                if head <= te:
+                    K = I.pair_kernel(prob.geo, a, b, head, prob.dt, prob.cs)[i, jj]
+                    assert np.isclose(f, -eta * K, rtol=1e-14, atol=0.0)
+                else:
+                    assert np.isclose(f, G[i, jj] * prob.dt, rtol=1e-14, atol=0.0)
+    assert shortened > 0
