@@ -615,17 +615,24 @@ def main():
         st.check(stream=s)
         return op, inf, st, bs, err
 
-    def alg_bytes(inf, eb):
-        """Stored far-factor bytes one far launch reads: 16-bit forms keep the
+    def alg_bytes(inf, eb, S=16):
+        """Stored far-factor bytes the timed far launch reads: with time blocks (S > 1)
+        the part with lags >= 2S (the block-start items, lags S..2S-1, run in a launch
+        of their own), in the plain form (S = 1) all of them. 16-bit forms keep the
         near-field blocks in FP32 (far_entries_f32)."""
+        far, f32 = inf["far_entries"], inf["far_entries_f32"]
+        if S > 1:
+            far, f32 = far - inf["far_entries_first"], f32 - inf["far_entries_first_f32"]
         if eb == 2:
-            return (inf["far_entries"] - inf["far_entries_f32"]) * 2 + inf["far_entries_f32"] * 4
-        return inf["far_entries"] * eb
+            return (far - f32) * 2 + f32 * 4
+        return far * eb
 
-    def timed_on(st, inf, eb, S, n):
+    def timed_on(st, inf, eb, S, n, overlap=True):
         """n steps timed from the start of a time block: the region holds every far
-        launch its steps need (ceil(n / S)), none run before the timer starts."""
+        launch its steps need (ceil(n / S)), none run before the timer starts (the
+        block lookahead only runs ahead inside one step call)."""
         st.set_time_block(S)          # the next step starts a new block
+        st.set_overlap(overlap)
         st.set_timing(True)
         st.read_timing(stream=s)
         torch.cuda.synchronize()
@@ -641,7 +648,8 @@ def main():
         want = -(-n // S)
         assert launches == want, f"{launches} far launches for {n} steps at S = {S} (expected {want})"
         avg = ms / max(launches, 1)
-        gbs = alg_bytes(inf, eb) / (avg * 1e-3) / 1e9
+        gbs = alg_bytes(inf, eb, S) / (avg * 1e-3) / 1e9
+        st.set_overlap(True)
         return dict(wall=wall, ev_ms=e0.elapsed_time(e1), avg_ms=avg, launches=launches, gbs=gbs,
                     value=inf_N(inf) * n / wall, ms_per_step=wall / n * 1e3)
 
@@ -654,9 +662,10 @@ def main():
     S = info["time_block"]
     main_run = timed_on(st, info, elem_bytes, S, K)
     steady = timed_on(st, info, elem_bytes, S, 10 * S)
+    serial = timed_on(st, info, elem_bytes, S, 10 * S, overlap=False) if S > 1 else None
     plain = None if (args.no_plain or S == 1) else timed_on(st, info, elem_bytes, 1, K)
     wall, avg_ms, achieved = main_run["wall"], main_run["avg_ms"], main_run["gbs"]
-    hmat_bytes = alg_bytes(info, elem_bytes)
+    hmat_bytes = alg_bytes(info, elem_bytes, S)
     if args.dtype in ("bf16", "f16"):
         kname = f"k_hmat_x16<{'bf16' if args.dtype == 'bf16' else 'f16'},16 columns>"
     elif args.dtype == "f32" and S == 16 and info["n_segments"] > 0:
@@ -692,6 +701,12 @@ def main():
                          "launches": steady["launches"], "kernel_avg_ms": steady["avg_ms"],
                          "frac": steady["gbs"] / HBM_PEAK_GBS,
                          "note": f"{10 * S} steps from a block start (whole time blocks)"},
+        "block_lookahead": None if serial is None else {
+            "note": "far lags >= 2S of the next time block run on a second stream beside the current "
+                    "block's steps (seas_state_set_overlap); the block-start lags S..2S-1 at the block start",
+            "block_start_share_of_far_entries": info["far_entries_first"] / info["far_entries"],
+            "steady_state_serial_value": serial["value"], "steady_state_serial_ms_per_step": serial["ms_per_step"],
+            "steady_state_serial_kernel_avg_ms": serial["avg_ms"]},
         "build_s": build_s,
         "stored_over_dense": info["stored_entries"] / info["dense_entries"],
     }
@@ -716,7 +731,7 @@ def main():
             out["forms"][d] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
                                "steady_state_value": r_ss["value"], "kernel": kn, "kernel_avg_ms": r["avg_ms"],
                                "achieved_GBs": r["gbs"], "frac": r["gbs"] / HBM_PEAK_GBS,
-                               "algorithmic_bytes": alg_bytes(inf_d, eb), "rel_err": err_d,
+                               "algorithmic_bytes": alg_bytes(inf_d, eb, 16), "rel_err": err_d,
                                "within_1e-4": None if err_d is None else bool(err_d <= 1e-4),
                                "traffic": measured_traffic(kn, args), "build_s": bs_d,
                                "note": ("admissible blocks' lags >= 16 in 16 bits; near-field blocks, lags "
@@ -733,7 +748,7 @@ def main():
         out["forms"]["f32_cluster_windows"] = {
             "value": r["value"], "ms_per_step": r["ms_per_step"], "steady_state_value": r_ss["value"],
             "kernel": "k_hmat_x16<f32,16 columns>", "kernel_avg_ms": r["avg_ms"], "achieved_GBs": r["gbs"],
-            "frac": r["gbs"] / HBM_PEAK_GBS, "algorithmic_bytes": alg_bytes(inf_c, 4),
+            "frac": r["gbs"] / HBM_PEAK_GBS, "algorithmic_bytes": alg_bytes(inf_c, 4, 16),
             "stored_entries": inf_c["stored_entries"], "stored_entries_pair_windows": info["stored_entries"],
             "rel_err": err_c, "within_1e-4": None if err_c is None else bool(err_c <= 1e-4), "build_s": bs_c,
             "note": "FP32 factors, every block truncated at the pair rule applied to its clusters, static "

@@ -184,6 +184,9 @@ typedef struct {
                                  ensembles: the entries of their FP32 list */
   int64_t partial_bytes;      /* device bytes of the partial sums one interaction evaluation
                                  writes (see seas_eval_prescribed_noalloc) */
+  int64_t far_entries_first;  /* time_block S > 1: far entries of lags S..2S-1 (the block-start
+                                 items; included in far_entries) */
+  int64_t far_entries_first_f32; /* the part of far_entries_first kept in FP32 by 16-bit builds */
 } seas_op_info_t;
 
 seas_status seas_operator_info(const seas_op_t* op, seas_op_info_t* out);
@@ -349,9 +352,26 @@ seas_status seas_write_state(seas_state_t* st, int32_t field, int32_t variant, c
                              int32_t src_is_device, void* stream);
 /* Device time of the interaction-evaluation kernel: when enabled, every launch of
  * it inside seas_step / seas_eval_prescribed is bracketed by HIP events recorded
- * on the launch stream. read_timing synchronises `stream`, returns the summed
- * milliseconds and the number of launches since the last read, and resets them. */
+ * on the launch stream. With time_block S > 1 the timed launch is the far part
+ * with lags >= 2S (seas_op_info_t.far_entries - far_entries_first entries), one
+ * per time block; the block-start items (lags S..2S-1) are not timed. In the plain
+ * form every far launch is timed. read_timing synchronises `stream`, returns the
+ * summed milliseconds and the number of launches since the last read, and resets
+ * them. */
 seas_status seas_state_set_timing(seas_state_t* st, int32_t enable);
+
+/* Block lookahead of seas_step (time_block S > 1; on by default). The stress at
+ * the S steps of a time block from lags >= 2S needs rates up to the step before
+ * the previous block only (Section 2.4 evaluates the history sum from stored
+ * rates; eq. "fault-to-fault_interactions_discretized"), so seas_step launches
+ * that part for the next block on a second stream of its own as soon as the
+ * current block's far sums are reduced, and it runs beside the current block's
+ * steps; the next block waits for it and adds its lags S..2S-1. A lookahead is
+ * only started for a block the same seas_step call reaches, so every call leaves
+ * no work behind on that stream. enable = 0 applies both parts at each block
+ * start on the caller's stream. The sums are identical either way. The lookahead
+ * stream is non-blocking, so a caller's stream of any kind overlaps with it. */
+seas_status seas_state_set_overlap(seas_state_t* st, int32_t enable);
 
 /* Evaluation order of a state built with time_block S > 1: S (default) applies the
  * lags >= S once per S steps; 1 applies them every step (the plain per-step form).

@@ -52,7 +52,8 @@ class OpInfo(C.Structure):
                 ("factor_dtype", C.c_int32), ("time_block", C.c_int32), ("far_entries", C.c_int64),
                 ("n_items_near", C.c_int64), ("n_variants", C.c_int32), ("ncols", C.c_int32),
                 ("n_segments", C.c_int64), ("far_bytes", C.c_int64), ("far_entries_f32", C.c_int64),
-                ("partial_bytes", C.c_int64)]
+                ("partial_bytes", C.c_int64), ("far_entries_first", C.c_int64),
+                ("far_entries_first_f32", C.c_int64)]
 
 
 class Friction(C.Structure):
@@ -106,6 +107,7 @@ def lib():
             "seas_read_state": (i32, [vp, i32, i32, vp, C.c_size_t, i32, vp]),
             "seas_state_step_index": (i64, [vp]),
             "seas_state_set_timing": (i32, [vp, i32]),
+            "seas_state_set_overlap": (i32, [vp, i32]),
             "seas_state_set_time_block": (i32, [vp, i32]),
             "seas_state_read_timing": (i32, [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
             "seas_state_checkpoint_bytes": (C.c_size_t, [vp]),
@@ -314,6 +316,9 @@ class State:
 
     def set_timing(self, enable=True):
         _check(lib().seas_state_set_timing(self.h, 1 if enable else 0))
+
+    def set_overlap(self, enable=True):
+        _check(lib().seas_state_set_overlap(self.h, 1 if enable else 0))
 
     def read_timing(self, stream=0):
         ms, n = C.c_double(0), C.c_int64(0)

@@ -161,11 +161,23 @@ struct seas_state {
   // predictor transform run there beside the interaction history part
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // block lookahead (time-blocked builds): the far items with lags >= 2S of the
+  // next time block run on their own stream (default priority) while the current
+  // block steps; la_head is the block head whose share is in flight there (only
+  // within one seas_state_step call, which always consumes it)
+  bool overlap = true;
+  hipStream_t la = nullptr;
+  hipEvent_t ev_la_go = nullptr, ev_la_done = nullptr;
+  int64_t la_head = INT64_MIN / 2;
   ~seas_state() {
     if (side) (void)hipStreamSynchronize(side);
+    if (la) (void)hipStreamSynchronize(la);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
+    if (ev_la_go) (void)hipEventDestroy(ev_la_go);
+    if (ev_la_done) (void)hipEventDestroy(ev_la_done);
     if (side) (void)hipStreamDestroy(side);
+    if (la) (void)hipStreamDestroy(la);
     for (auto e : ev) (void)hipEventDestroy(e);
     for (auto& b : owned) (void)hipFree(b.p);
   }
@@ -254,44 +266,97 @@ std::pair<size_t, size_t> partial_layout(const HostOp& h) {
   return {near_off, near_off + (size_t)h.n_partials[1] * 8};
 }
 
+// Far lists, or one part of them, for the S windows starting at `head`: all items
+// (kFarAll), the items with lags >= 2S (kFarRest) or the block-start items with
+// lags in [S, 2S) (kFarFirst); the parts write disjoint partial sums.
+enum FarPart { kFarAll, kFarRest, kFarFirst };
+
+void launch_far(seas_op* op, seas_state* st, int64_t head, FarPart part, int Sl, void* pfar, hipStream_t s) {
+  const HostOp& h = op->h;
+  // [a, b) of a list of n entries whose last nfirst are block-start ones
+  auto range = [&](int64_t n, int64_t nfirst, int64_t& a, int64_t& b) {
+    a = part == kFarFirst ? n - nfirst : 0;
+    b = part == kFarRest ? n - nfirst : n;
+  };
+  int64_t a, b;
+  if (h.seg) {
+    range((int64_t)h.seg_ptr.size() - 1, h.first_segs, a, b);
+    launch_hmat_x16(h, op->items[0], op->seg_ptr + a, (int)(b - a), op->lagT, op->lagCol, op->lagColOff[0],
+                    op->arena, st->ringop, head, st->tail_acc, (float*)pfar, s);
+    range((int64_t)h.items[2].size(), h.first_items[2], a, b);
+    launch_hmat_f32far(h, (int)(b - a), op->items[2] + a, op->lagT, op->lagCol, op->lagColOff[2] + a,
+                       op->arena_near, st->ringop, head, (float*)pfar, s);
+    if (h.ens32 && part == kFarAll) {
+      // BF16 ensembles keep a BF16 history copy: their FP32 list reads the FP64 history
+      const bool r64 = op->ring_bytes == 2;
+      launch_hmat_seg32(h, op->items[3], op->seg_ptr3, op->lagT, op->lagCol, op->lagColOff[3], op->arena32s,
+                        r64 ? (const void*)st->ring64 : (const void*)st->ringop, r64, head, st->tail_acc,
+                        (float*)pfar, s);
+    }
+  } else {
+    range((int64_t)h.items[0].size(), h.first_items[0], a, b);
+    launch_hmat(h, Sl, (int)(b - a), op->items[0] + a, op->lagT, op->lagCol, op->lagColOff[0] + a, op->arena,
+                st->ringop, head, st->tail_acc, (double*)pfar, h.time_block, s);
+  }
+}
+
+// Block lookahead of one step: `next` asks for the next block's far items with
+// lags >= 2S to be launched on the lookahead stream when this step starts a block.
+struct Lookahead {
+  bool next;
+};
+
 // Interaction history part at `head` into st->f_hist. The far list is applied
 // once per time block (S windows: heads block_head .. block_head + S - 1), the
 // near list (lags 1..S-1 and the static tail) at every head. In the plain form
-// (S = 1, or run_S = 1) the far list is applied at every head.
+// (S = 1, or run_S = 1) the far list is applied at every head. Time-blocked:
+// the items with lags >= 2S read history rows up to head - S - 1 only, so with a
+// lookahead (`la`) they are launched for the next block on the lookahead stream as
+// soon as this block's far sums are reduced, and the next block start waits for
+// them and applies its block-start items (lags [S, 2S)) alone.
 void eval_history(seas_op* op, seas_state* st, int64_t head, hipStream_t s, void* pfar = nullptr,
-                  double* pnear = nullptr) {
+                  double* pnear = nullptr, const Lookahead* la = nullptr) {
   const HostOp& h = op->h;
   // partial sums: the state's buffers unless the caller brings its own
   if (!pfar) pfar = st->partials_far;
   if (!pnear) pnear = st->partials_near;
   const int S = h.time_block;
-  const int nfar = (int)h.items[0].size(), nnear = (int)h.items[1].size();
+  const int nnear = (int)h.items[1].size();
   const bool plain = S == 1 || st->run_S == 1;
   int64_t k = head - st->block_head;
   if (plain || k < 0 || k >= S) {
     // plain form on a time-blocked build: window 0 of the far list at this head
     // (the segment kernel always forms its S windows; the plain form uses window 0)
     const int Sl = (plain && !h.seg) ? 1 : S;
-    record_start(st, s);
-    if (h.seg) {
-      launch_hmat_x16(h, op->items[0], op->seg_ptr, op->lagT, op->lagCol, op->lagColOff[0], op->arena, st->ringop,
-                      head, st->tail_acc, (float*)pfar, s);
-      launch_hmat_f32far(h, (int)h.items[2].size(), op->items[2], op->lagT, op->lagCol, op->lagColOff[2],
-                         op->arena_near, st->ringop, head, (float*)pfar, s);
-      if (h.ens32) {
-        // BF16 ensembles keep a BF16 history copy: their FP32 list reads the FP64 history
-        const bool r64 = op->ring_bytes == 2;
-        launch_hmat_seg32(h, op->items[3], op->seg_ptr3, op->lagT, op->lagCol, op->lagColOff[3], op->arena32s,
-                          r64 ? (const void*)st->ring64 : (const void*)st->ringop, r64, head, st->tail_acc,
-                          (float*)pfar, s);
+    if (plain) {
+      record_start(st, s);
+      launch_far(op, st, head, kFarAll, Sl, pfar, s);
+      record_stop(st, s);
+    } else {
+      // the timed launch is the part with lags >= 2S (most of the far list)
+      if (la && st->la_head == head) {
+        HIPCHK(hipStreamWaitEvent(s, st->ev_la_done, 0));
+      } else {
+        record_start(st, s);
+        launch_far(op, st, head, kFarRest, Sl, pfar, s);
+        record_stop(st, s);
       }
-    } else
-      launch_hmat(h, Sl, nfar, op->items[0], op->lagT, op->lagCol, op->lagColOff[0], op->arena, st->ringop, head,
-                  st->tail_acc, (double*)pfar, S, s);
-    record_stop(st, s);
+      launch_far(op, st, head, kFarFirst, Sl, pfar, s);
+    }
+    st->la_head = INT64_MIN / 2;
     const bool f32p = far_partials_f32(h, Sl);
     launch_reduce_far(h, h.seg ? h.ncols : Sl, pfar, f32p, op->red_ptr[0], op->red_idx[0],
                       nnear == 0 ? st->f_hist : st->f_far, s);
+    if (la && la->next && !plain) {
+      // the partial sums are free again once the reduction has read them
+      HIPCHK(hipEventRecord(st->ev_la_go, s));
+      HIPCHK(hipStreamWaitEvent(st->la, st->ev_la_go, 0));
+      record_start(st, st->la);
+      launch_far(op, st, head + S, kFarRest, Sl, pfar, st->la);
+      record_stop(st, st->la);
+      HIPCHK(hipEventRecord(st->ev_la_done, st->la));
+      st->la_head = head + S;
+    }
     if (nnear == 0) return;
     st->block_head = plain ? INT64_MIN / 2 : head;
     k = 0;
@@ -312,8 +377,19 @@ void do_steps(seas_op* op, seas_state* st, int n_steps, hipStream_t s) {
     HIPCHK(hipEventCreateWithFlags(&st->ev_fork, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&st->ev_join, hipEventDisableTiming));
   }
+  const int S = h.time_block;
+  const bool la_on = st->overlap && S > 1 && st->run_S != 1;
+  if (la_on && !st->la) {
+    HIPCHK(hipStreamCreateWithFlags(&st->la, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&st->ev_la_go, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&st->ev_la_done, hipEventDisableTiming));
+  }
+  st->la_head = INT64_MIN / 2;
   for (int it = 0; it < n_steps; ++it) {
     const int64_t n = st->step;
+    // a lookahead is launched only for a block this call reaches, so the call
+    // itself consumes every lookahead it starts
+    const Lookahead la{it + S < n_steps};
     // The self history and the predictor transform read only what the previous
     // step left (coefficient rings, slip, rate) and write Fh and F, which the
     // interaction history part neither reads nor writes: they run on the side
@@ -324,7 +400,7 @@ void do_steps(seas_op* op, seas_state* st, int n_steps, hipStream_t s) {
     launch_dft(nm, nv, h.N, dl, op->modes, op->sf, st->delta, st->V, h.dt, op->tw, op->tab, st->Fh, st->F,
                st->dring, 0, 0, 0, st->side);
     HIPCHK(hipEventRecord(st->ev_join, st->side));
-    eval_history(op, st, n, s);
+    eval_history(op, st, n, s, nullptr, nullptr, la_on ? &la : nullptr);
     HIPCHK(hipStreamWaitEvent(s, st->ev_join, 0));
     StepArgs<TF> a = make_args<TF>(op, st);
     a.t_next = (double)(n + 1) * h.dt;
@@ -339,6 +415,7 @@ void do_steps(seas_op* op, seas_state* st, int n_steps, hipStream_t s) {
     launch_commit<TF>(a, s);
     st->step = n + 1;
   }
+  st->la_head = INT64_MIN / 2;
   HIPCHK(hipGetLastError());
 }
 
@@ -652,6 +729,18 @@ seas_status seas_operator_info(const seas_op_t* op, seas_op_info_t* out) {
         far32 += it.kind == 0 ? (int64_t)it.ncol * (it.p + it.q) : (int64_t)it.nlag * it.p * it.q;
     out->far_entries = far + far32;
     out->far_entries_f32 = far32;
+    int64_t ff = 0, ff32 = 0;
+    for (int L = 0; L < 3; L += 2) {
+      const auto& its = h.items[L];
+      for (size_t x = its.size() - (size_t)h.first_items[L]; x < its.size(); ++x) {
+        const Item& it = its[x];
+        const int64_t e = it.kind == 0 ? (int64_t)it.ncol * (it.p + it.q) : (int64_t)it.nlag * it.p * it.q;
+        ff += e;
+        if (L == 2) ff32 += e;
+      }
+    }
+    out->far_entries_first = ff;
+    out->far_entries_first_f32 = ff32;
     out->dense_entries = h.dense_entries;
     out->stored_entries = h.stored_entries;
     out->lag0_nnz = (int64_t)h.l0_val.size();
@@ -1182,6 +1271,13 @@ seas_status seas_state_set_timing(seas_state_t* st, int32_t enable) {
   return guard([&] {
     if (!st) throw Error(SEAS_ERR_INVALID_ARG, "null state");
     st->timing = enable != 0;
+  });
+}
+
+seas_status seas_state_set_overlap(seas_state_t* st, int32_t enable) {
+  return guard([&] {
+    if (!st) throw Error(SEAS_ERR_INVALID_ARG, "null state");
+    st->overlap = enable != 0;
   });
 }
 

@@ -353,6 +353,7 @@ static void pack_list(int r0, int r1, int s0, int s1, const Fault& A, const Faul
       if (j > i) {
         if (tail) break;
         if (lags[j]->T != lags[j - 1]->T + 1) break;  // an item's lags are consecutive
+        if (S > 1 && lags[j]->T == 2 * S) break;      // block-start items hold lags below 2S only
         const int span = lags[j]->T - lags[i]->T + S;
         if ((int64_t)span * q > kHistMax) break;
         if (nl > kColMax) break;
@@ -426,7 +427,10 @@ static void pack_seg(int r0, int r1, int s0, int s1, const Fault& A, const Fault
   const int ncols = S * nv;
   const bool f32 = dtype == SEAS_F32;
   const int eb = f32 ? 4 : 2;
-  const int64_t target = f32 ? 65536 : 131072;  // stored values per item
+  // stored values per item: 1 MiB of factors, so that the fixed cost of an item in
+  // the kernel (a barrier and the staging of its history panel, most of which the
+  // previous item of the block staged too) is small next to its stream of factors
+  const int64_t target = f32 ? 262144 : 524288;
   auto put = [&](double v) {
     if (f32) out.s32.push_back((float)v);
     else out.d16.push_back(dtype == SEAS_BF16 ? to_bf16((float)v) : to_f16((float)v));
@@ -444,6 +448,7 @@ static void pack_seg(int r0, int r1, int s0, int s1, const Fault& A, const Fault
       if (j > i) {
         if (tail) break;
         if (lags[j]->T != lags[j - 1]->T + 1) break;
+        if (S > 1 && lags[j]->T == 2 * S) break;  // block-start items hold lags below 2S only
         const int span = lags[j]->T - lags[i]->T + S;
         if ((int64_t)span * nv * seg_ld(q8, eb) > seg_hist_limit(ncols, eb)) break;
         if (nl > kColMax) break;
@@ -937,12 +942,16 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
   // other and grouped into segments, one workgroup each, that keep the sums of
   // their rows in registers and write one partial set; rows beyond what the
   // registers hold make single-item segments. (FP16 ensembles: also list 3.)
+  // block-start items: lags in [S, 2S) (time-blocked builds; never a tail item)
+  auto first_item = [&](const Item& it) { return S > 1 && it.src == 0 && op.lagT[it.lag_off] < 2 * S; };
   auto make_segments = [&](std::vector<Item>& items, std::vector<int32_t>& colOffL, std::vector<int32_t>& seg_ptr,
-                           int eb) {
+                           int eb) -> int64_t {
     std::vector<size_t> ord(items.size());
     std::iota(ord.begin(), ord.end(), 0);
     std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) {
       const Item &a = items[x], &b = items[y];
+      const bool fa = first_item(a), fb = first_item(b);
+      if (fa != fb) return fb;
       return a.row0 != b.row0 ? a.row0 < b.row0 : a.p < b.p;
     });
     std::vector<Item> its;
@@ -966,21 +975,28 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
       int64_t v = vals(f);
       if (f.p <= rmax)
         while (e < items.size() && items[e].row0 == f.row0 && items[e].p == f.p &&
-               v + vals(items[e]) <= kSegElems * 2 / eb)
+               first_item(items[e]) == first_item(f) && v + vals(items[e]) <= kSegElems * 2 / eb)
           v += vals(items[e++]);
       seg_ptr.push_back((int32_t)k);
       k = e;
     }
     seg_ptr.push_back((int32_t)items.size());
     // workgroups start in segment order: largest segments first, so that the
-    // small ones fill in at the end of the pass
+    // small ones fill in at the end of the pass (block-start segments after all others)
     const size_t ns = seg_ptr.size() - 1;
     std::vector<int64_t> sz(ns, 0);
-    for (size_t g = 0; g < ns; ++g)
+    std::vector<char> fs(ns, 0);
+    int64_t nfirst = 0;
+    for (size_t g = 0; g < ns; ++g) {
       for (int32_t x = seg_ptr[g]; x < seg_ptr[g + 1]; ++x) sz[g] += vals(items[x]);
+      fs[g] = first_item(items[seg_ptr[g]]);
+      nfirst += fs[g];
+    }
     std::vector<size_t> so(ns);
     std::iota(so.begin(), so.end(), 0);
-    std::stable_sort(so.begin(), so.end(), [&](size_t x, size_t y) { return sz[x] > sz[y]; });
+    std::stable_sort(so.begin(), so.end(), [&](size_t x, size_t y) {
+      return fs[x] != fs[y] ? fs[y] != 0 : sz[x] > sz[y];
+    });
     std::vector<Item> its2;
     std::vector<int32_t> co2, sp2;
     for (size_t g : so) {
@@ -1011,10 +1027,36 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
             (it.src == 1 && op.n_variants == 1) ||
             it.row0 + it.p > op.N || it.col0 + it.q > op.N)
           throw Error(SEAS_ERR_INTERNAL, "segment item violates the kernel's limits");
+        if (first_item(it) != first_item(f)) throw Error(SEAS_ERR_INTERNAL, "block-start item in a mixed segment");
       }
     }
+    return nfirst;
   };
-  if (op.seg) make_segments(op.items[0], colOff[0], op.seg_ptr, op.seg_eb);
+  // item lists applied by one workgroup per item: block-start items last
+  auto move_first_last = [&](int L) {
+    std::vector<Item>& its = op.items[L];
+    std::vector<size_t> ord(its.size());
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_partition(ord.begin(), ord.end(), [&](size_t x) { return !first_item(its[x]); });
+    std::vector<Item> i2;
+    std::vector<int32_t> c2;
+    for (size_t x : ord) {
+      i2.push_back(its[x]);
+      c2.push_back(colOff[L][x]);
+    }
+    its.swap(i2);
+    colOff[L].swap(c2);
+    op.first_items[L] = 0;
+    for (const Item& it : its) op.first_items[L] += first_item(it);
+  };
+  for (int L = 0; L < 4; ++L) op.first_items[L] = 0;
+  op.first_segs = 0;
+  if (!op.seg) move_first_last(0);
+  move_first_last(2);
+  if (op.seg) {
+    op.first_segs = make_segments(op.items[0], colOff[0], op.seg_ptr, op.seg_eb);
+    for (const Item& it : op.items[0]) op.first_items[0] += first_item(it);
+  }
   if (op.ens32) make_segments(op.items[3], colOff[3], op.seg_ptr3, 4);
   // partial offsets: per item, or per segment on the segment far list (far
   // partials are [p][S] or [p][ncols], row-major)

@@ -140,6 +140,12 @@ struct HostOp {
   std::vector<int32_t> lagT;          // nlag lag values per item (ascending)
   std::vector<int32_t> lagCol;        // nlag+1 column prefix per item
   std::vector<int32_t> lagColOff[4];  // per item: offset into lagCol
+  // time-blocked builds (S > 1): the far items whose lags lie in [S, 2S) (block-start
+  // items) come last in their list, in segments of their own; the rest (lags >= 2S)
+  // reads only history that is complete when the previous time block starts, so it
+  // can be applied while the previous block steps
+  int64_t first_items[4] = {0, 0, 0, 0};  // block-start items at the end of items[L]
+  int64_t first_segs = 0;                 // block-start segments at the end of seg_ptr
   bool ens32 = false;
   std::vector<int32_t> seg_ptr3;
   int64_t arena32s_elems = 0;

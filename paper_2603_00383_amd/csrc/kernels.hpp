@@ -82,8 +82,9 @@ void launch_reduce_near(const HostOp& h, const double* partials, const int32_t* 
                         const double* base, double* f, hipStream_t s);
 // zero one variant's rows of a [rows][nv][N] array of elem_bytes-sized values (elem_bytes even)
 void launch_clear_variant(void* base, int64_t rows, int nv, int v, int N, int elem_bytes, hipStream_t s);
-// 16-bit far list, one workgroup per segment
-void launch_hmat_x16(const HostOp& h, const void* items, const int32_t* seg_ptr, const int32_t* lagT,
+// far list on the matrix cores, one workgroup per segment: nseg segments from
+// seg_ptr (a device pointer into the operator's segment offsets)
+void launch_hmat_x16(const HostOp& h, const void* items, const int32_t* seg_ptr, int nseg, const int32_t* lagT,
                      const int32_t* lagCol, const int32_t* lagColOff, const void* arena, const void* ring,
                      int64_t head, const double* tail_acc, float* partials, hipStream_t s);
 // ensembles: list 3 (FP32, segment layout) on the FP32 instance of the segment

@@ -551,27 +551,27 @@ static void x16_launch(const HostOp& h, const void* items, const int32_t* seg_pt
                      h.N, h.time_block, h.n_variants, tail_acc, (int64_t)h.tail_len, partials);
 }
 
-void launch_hmat_x16(const HostOp& h, const void* items, const int32_t* seg_ptr, const int32_t* lagT,
+void launch_hmat_x16(const HostOp& h, const void* items, const int32_t* seg_ptr, int nseg, const int32_t* lagT,
                      const int32_t* lagCol, const int32_t* lagColOff, const void* arena, const void* ring,
                      int64_t head, const double* tail_acc, float* partials, hipStream_t s) {
-  if (h.seg_ptr.size() < 2) return;
+  if (nseg < 1) return;
   const bool bf = h.prm.factor_dtype == SEAS_BF16;
   if (!h.x16) {  // FP32 factors, one variant, 16 windows
     x16_launch<float, float, false, 1>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head, tail_acc,
-                                       partials, s);
+                                       partials, s, nseg);
     return;
   }
   if (h.n_variants == 1) {
-    if (bf) x16_launch<__bf16, float, false, 1>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head, tail_acc, partials, s);
-    else x16_launch<_Float16, float, true, 1>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head, tail_acc, partials, s);
+    if (bf) x16_launch<__bf16, float, false, 1>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head, tail_acc, partials, s, nseg);
+    else x16_launch<_Float16, float, true, 1>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head, tail_acc, partials, s, nseg);
     return;
   }
   // ensembles: BF16 with a BF16 rate history, or FP16 with an FP32 one scaled per item
 #define SEAS_X16_ENS(NT)                                                                                      \
   if (bf) x16_launch<__bf16, __bf16, false, NT, true>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head, \
-                                                tail_acc, partials, s);                                        \
-  else x16_launch<_Float16, float, true, NT>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head,     \
-                                             tail_acc, partials, s);
+                                                      tail_acc, partials, s, nseg);                                \
+  else x16_launch<_Float16, float, true, NT>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head,       \
+                                             tail_acc, partials, s, nseg);
   switch (h.ncols) {
     case 16: SEAS_X16_ENS(1) break;
     case 32: SEAS_X16_ENS(2) break;
