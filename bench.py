@@ -47,25 +47,21 @@ def measured_traffic(kname, args=None):
 
 
 KIB = 1024
-# HBM bytes per far pass (five-fault workload, time block 16, unless noted), from rocprofv3 --pmc FETCH_SIZE and
-# WRITE_SIZE runs of this script (KiB per dispatch), scaled by what the same counters read
-# for a plain 2 GiB copy (2.0 for FETCH_SIZE, 1.0 for WRITE_SIZE); each entry names the
-# SHA-256 of the kernel sources it was measured on. The 16-bit forms' far pass is the
-# 16-bit kernel plus the FP32 pass over the near-field blocks.
-_K = "bacbc5b23e8d53bbf0c3b0e783a71d57a451ce47bc99d15917c7fe7208079646"    # kernels.hip
-_X = "26b59bd6f617cb3087b3c819f934f447f9cec7cce6b58cb29a156dfcc3e1c420"    # kernels_x16.hip
-_B = "e0b2012e43e82778659f831efd24e229f83f1cf58a7ae11e5ddaec72abd03c66"    # build.cpp (item layout)
+# HBM bytes of the timed far launch (five-fault workload, time block 16: the part with
+# lags >= 2S), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of this script (KiB per
+# dispatch), scaled by what the same counters read for a plain 2 GiB copy (2.0 for
+# FETCH_SIZE, 1.0 for WRITE_SIZE); each entry names the SHA-256 of the sources it was
+# measured on. The 16-bit forms' timed launch is the 16-bit kernel plus the FP32 pass
+# over the near-field blocks (k_hmat_mfma16).
+_K = "d1afe5e9c951f88a41142886038ab75342d3d73c8eda84b7e03b59209a7eaf79"    # kernels.hip
+_X = "12010c76f803850476217b6e6a6e2c600d65c0176337ca6a81ffc7a83fe26e93"    # kernels_x16.hip
+_B = "8d03690674b3e1038d45786406265121a53e7878ad2f0b0c1d34c6f8f6b1c523"    # build.cpp (item layout)
+_SRC = {"kernels.hip": _K, "kernels_x16.hip": _X, "build.cpp": _B}
 MEASURED_TRAFFIC = {
-    # FP32 item kernel (SEAS_NO_SEG builds)
-    "k_hmat_mfma16": (2.0 * 10_762_300 * KIB + 926_551 * KIB, {"kernels.hip": _K}),
-    # FP32 segment kernel (the default FP32 build)
-    "k_hmat_x16<f32,16 columns>": (2.0 * 10_394_100 * KIB + 242_541 * KIB,
-                                   {"kernels.hip": _K, "kernels_x16.hip": _X, "build.cpp": _B}),
-    "k_hmat_x16<f16,16 columns>": (2.0 * 4_627_600 * KIB + 102_572 * KIB + 2.0 * 1_253_970 * KIB + 22_377 * KIB,
-                                   {"kernels.hip": _K, "kernels_x16.hip": _X, "build.cpp": _B}),
-    # ensemble workload (8 x 750 elements, 64 BF16 variants, one launch per step)
-    "k_hmat_x16<bf16,64 columns>": (2.0 * 34_138_500 * KIB + 1_234_150 * KIB,
-                                    {"kernels.hip": _K, "kernels_x16.hip": _X, "build.cpp": _B}),
+    "k_hmat_x16<f32,16 columns>": (2.0 * 10_048_900 * KIB + 239_937 * KIB, _SRC),
+    "k_hmat_x16<f16,16 columns>": (2.0 * 4_516_700 * KIB + 102_368 * KIB + 2.0 * 1_252_050 * KIB + 22_340 * KIB, _SRC),
+    "k_hmat_x16<bf16,16 columns>": (2.0 * 4_412_570 * KIB + 102_408 * KIB + 2.0 * 1_252_050 * KIB + 22_340 * KIB,
+                                    _SRC),
 }
 
 
@@ -522,6 +518,8 @@ def main():
                     help="S: lags >= S applied once per S steps (1 = plain per-step form)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form measurement")
     ap.add_argument("--no-forms", action="store_true", help="skip the 16-bit forms (FP32 runs only)")
+    ap.add_argument("--forms", default="f16,bf16,f64,cluster",
+                    help="forms measured beside the FP32 headline (comma list of f16, bf16, f64, cluster)")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle CPU leg (the forms' errors are then not measured)")
     ap.add_argument("--no-serving", action="store_true", help="skip the bounded serving leg")
@@ -722,7 +720,8 @@ def main():
     if args.dtype == "f32" and not args.no_forms and S == 16:
         # the other forms of the same workload (same geometry, state and history)
         out["forms"] = {}
-        for d in ("f16", "bf16", "f64"):
+        wanted = set(args.forms.split(","))
+        for d in [d for d in ("f16", "bf16", "f64") if d in wanted]:
             op_d, inf_d, st_d, bs_d, err_d = prepare(d)
             eb = {"f16": 2, "bf16": 2, "f64": 8}[d]
             r = timed_on(st_d, inf_d, eb, 16, K)
@@ -741,6 +740,7 @@ def main():
                   flush=True)
             st_d.close()
             op_d.close()
+    if args.dtype == "f32" and not args.no_forms and S == 16 and "cluster" in args.forms.split(","):
         # cluster-level windows (Section 4.3): FP32, each block truncated at its own upper lag
         op_c, inf_c, st_c, bs_c, err_c = prepare("f32", cluster=1)
         r = timed_on(st_c, inf_c, 4, 16, K)
