@@ -15,9 +15,14 @@ the transform of the slip at t_s.
 * SEAS mode, one step t_n -> t_{n+1} (Section 2.4 steps 2 and 3): predictor with
   delta* = delta^n + dt V^n, theta* = theta^n + dt thetadot^n, D* = DFT(delta*),
   Newton for V*; corrector with the averages of V and thetadot, in which only the
-  lag-0 terms change; V** and D** are appended to the histories.
+  lag-0 terms change; V** and D** are appended to the histories;
+* adaptive steps (Section 2.4.1, step 1): a step of g = ceil(min_i xi Dc_i/V_i /
+  dt) grid steps (at least 1) with the histories kept on the dt grid; the interior
+  grid rows of a step are filled as SeasState.step states.
 """
 from __future__ import annotations
+
+import math
 
 import numpy as np
 
@@ -111,8 +116,11 @@ class SeasState:
     step, as at the nucleation of the paper's two-fault benchmark)."""
 
     def __init__(self, prob, fric, V0, theta0, tau0, tau0_rate=None, delta0=None,
-                 prior_V=None, eps=1.0, state_update="explicit"):
+                 prior_V=None, eps=1.0, state_update="explicit", adaptive=False, xi=0.5, gamma_max=1 << 20):
         self.prob = prob
+        self.adaptive = bool(adaptive)
+        self.xi = xi
+        self.gamma_max = int(gamma_max)
         self.fric = {k: np.asarray(v, float) for k, v in fric.items()}
         self.eps = eps
         assert state_update in ("explicit", "exact")
@@ -142,14 +150,39 @@ class SeasState:
         return friction.solve_velocity(A, theta, self.prob.eta, F["a"], F["b"], F["Dc"],
                                        F["sigma_n"], F["V0"], F["f0"], x0)
 
+    def gamma(self):
+        """Length of the next step in units of Delta t_min (Section 2.4.1, step 1):
+        gamma = ceil(Delta t_ev / Delta t_min), Delta t_ev = min_i xi Dc_i / V_i, at
+        least 1 and at most gamma_max; 1 for the fixed step."""
+        if not self.adaptive:
+            return 1
+        dt_ev = float(np.min(self.xi * self.fric["Dc"] / self.V))
+        return max(1, min(int(math.ceil(dt_ev / self.prob.dt)), self.gamma_max))
+
     def step(self):
-        """Advance one predictor-corrector step t_n -> t_{n+1}."""
+        """Advance one predictor-corrector step t_n -> t_{n+g}, g = gamma().
+
+        The rate and slip histories stay on the Delta t_min grid of the kernels.
+        Row m of the rate history stands for the interval [t_m, t_m+1); the step's
+        intervals are n .. n+g-1, whose last one is the lag-0 interval of the new
+        time (its rate: V^n in the predictor, the averaged rate in the corrector).
+        Its interior intervals n+1 .. n+g-2 enter the history sums at the step's
+        starting rate V^n (one history evaluation per step), and the slip
+        coefficients of the interior grid times at the straight line from D^n to the
+        predicted D*. Committed: the interior rows n+1 .. n+g-1 take the averaged
+        rate (the rate of the slip increment), row n+g the corrected rate, the
+        interior slip coefficients the line from D^n to D**. With g = 1 this is the
+        fixed step."""
         P = self.prob
-        dt, n = P.dt, self.n
+        n = self.n
+        g = self.gamma()
+        dt = g * P.dt
+        for _ in range(1, g):                       # interior rows at the starting rate
+            self.Vh.append(self.V.copy())
+        head = n + g - 1
         Vh = np.array(self.Vh)
-        Dh = [np.array(d) for d in self.Dh]
         # interaction history part (lags >= 1) and the static tail
-        f_hist = P.inter.stress(Vh, n, self.first, min_lag=1, expired=P.expired(Vh, n, self.first))
+        f_hist = P.inter.stress(Vh, head, self.first, min_lag=1, expired=P.expired(Vh, head, self.first))
         # ---- predictor
         d_star = self.delta + dt * self.V
         if self.exact:
@@ -157,9 +190,14 @@ class SeasState:
         else:
             th_star = self.theta + dt * self.thetadot
         D_star = P.dfts(d_star)
-        fs_star = P.self_stress(Dh, n + 1, self.first, D_now=D_star)
+        D_n = [self.Dh[k][-1] for k in range(len(P.geo))]
+        for k in range(len(P.geo)):                 # interior slip coefficients, predicted
+            for m in range(1, g):
+                self.Dh[k].append(D_n[k] + (m / g) * (D_star[k] - D_n[k]))
+        Dh = [np.array(d) for d in self.Dh]
+        fs_star = P.self_stress(Dh, n + g, self.first, D_now=D_star)
         fi_star = f_hist + P.inter.lag0_apply(self.V)
-        tau0 = self.tau0 + self.tau0_rate * (n + 1) * dt
+        tau0 = self.tau0 + self.tau0_rate * (n + g) * P.dt
         V_star = self._solve(tau0 + fs_star + fi_star, th_star, np.log(self.V))
         thd_star = friction.state_rate(V_star, th_star, self.fric["Dc"], self.eps)
         # ---- corrector
@@ -171,17 +209,21 @@ class SeasState:
         else:
             th_2 = self.theta + dt * thd_bar
         D_2 = P.dfts(d_2)
-        fs_2 = P.self_stress(Dh, n + 1, self.first, D_now=D_2)
+        fs_2 = P.self_stress(Dh, n + g, self.first, D_now=D_2)
         fi_2 = f_hist + P.inter.lag0_apply(Vbar)
         V_2 = self._solve(tau0 + fs_2 + fi_2, th_2, np.log(V_star))
         thd_2 = friction.state_rate(V_2, th_2, self.fric["Dc"], self.eps)
-        self.last = dict(f_hist=f_hist, f_self=fs_2, f_int=fi_2, V_star=V_star)
+        self.last = dict(f_hist=f_hist, f_self=fs_2, f_int=fi_2, V_star=V_star, gamma=g)
         # ---- commit and append
         self.delta, self.theta, self.V, self.thetadot = d_2, th_2, V_2, thd_2
+        for m in range(1, g):
+            self.Vh[n + m - self.first] = Vbar.copy()
+            for k in range(len(P.geo)):
+                self.Dh[k][n + m - self.first] = D_n[k] + (m / g) * (D_2[k] - D_n[k])
         self.Vh.append(V_2.copy())
         for k in range(len(P.geo)):
             self.Dh[k].append(D_2[k])
-        self.n = n + 1
+        self.n = n + g
 
 
 def prescribed_rows(prob, V_all, first, n, rows, delta0=None):
