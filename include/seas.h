@@ -129,6 +129,13 @@ typedef struct {
                            (source midpoints to the receiver cluster's end points), at most the
                            pair's, and slip older than it contributes the block's static stress
                            (with int_tail); seas_operator_blocks reports each block's upper lag */
+  int32_t adaptive_dt;  /* 0: every step is Delta t_min; 1: step 1 of Section 2.4.1: each step is
+                           gamma Delta t_min with gamma = ceil(min_i adapt_xi Dc_i / V_i / Delta t_min)
+                           (at least 1, at most gamma_max; the minimum over all variants), the rate
+                           and slip histories kept on the Delta t_min grid (needs time_block 0/1) */
+  int32_t gamma_max;    /* largest gamma (0 = 2^20) */
+  double adapt_xi;      /* xi of the rule (0 = 0.5); the paper ties it to each element's stiffness
+                           and friction through a formula it does not print, so it is an input here */
 } seas_params_t;
 
 typedef struct seas_op seas_op_t;
@@ -379,8 +386,14 @@ seas_status seas_state_set_overlap(seas_state_t* st, int32_t enable);
 seas_status seas_state_set_time_block(seas_state_t* st, int32_t S);
 seas_status seas_state_read_timing(seas_state_t* st, void* stream, double* ms_total, int64_t* launches);
 
-/* Current step index (number of steps taken, or prescribed steps evaluated). */
+/* Current step index: the grid time t / Delta t_min reached (with fixed steps the
+ * number of steps taken, or of prescribed steps evaluated). */
 int64_t seas_state_step_index(const seas_state_t* st);
+
+/* Progress of a stepping state (adaptive steps, seas_params_t.adaptive_dt): steps
+ * taken by seas_step, gamma of the last one, and the time reached in seconds
+ * (grid index times Delta t_min). Any output may be NULL. */
+seas_status seas_state_progress(const seas_state_t* st, int64_t* steps_taken, int64_t* last_gamma, double* time_s);
 
 /* Checkpoint: size in bytes, save to / restore from a host buffer (synchronises
  * the stream). Restoring into a state of the same operator reproduces the

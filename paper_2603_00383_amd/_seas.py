@@ -40,7 +40,8 @@ class Params(C.Structure):
                 ("int_tail", C.c_int32), ("q_w", C.c_int32), ("mode_cap", C.c_int32),
                 ("factor_dtype", C.c_int32), ("n_threads", C.c_int32), ("host_only", C.c_int32),
                 ("time_block", C.c_int32), ("n_variants", C.c_int32), ("state_update", C.c_int32),
-                ("cluster_windows", C.c_int32)]
+                ("cluster_windows", C.c_int32), ("adaptive_dt", C.c_int32), ("gamma_max", C.c_int32),
+                ("adapt_xi", C.c_double)]
 
 
 class OpInfo(C.Structure):
@@ -108,6 +109,7 @@ def lib():
             "seas_state_step_index": (i64, [vp]),
             "seas_state_set_timing": (i32, [vp, i32]),
             "seas_state_set_overlap": (i32, [vp, i32]),
+            "seas_state_progress": (i32, [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
             "seas_state_set_time_block": (i32, [vp, i32]),
             "seas_state_read_timing": (i32, [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
             "seas_state_checkpoint_bytes": (C.c_size_t, [vp]),
@@ -167,6 +169,9 @@ def make_params(p):
     q.n_variants = int(p.get("n_variants", 1))
     q.state_update = {"explicit": 0, "exact": 1, 0: 0, 1: 1}[p.get("state_update", "explicit")]
     q.cluster_windows = int(p.get("cluster_windows", 0))
+    q.adaptive_dt = int(p.get("adaptive_dt", 0))
+    q.gamma_max = int(p.get("gamma_max", 0))
+    q.adapt_xi = float(p.get("adapt_xi", 0.0))
     return q
 
 
@@ -316,6 +321,12 @@ class State:
 
     def set_timing(self, enable=True):
         _check(lib().seas_state_set_timing(self.h, 1 if enable else 0))
+
+    def progress(self):
+        """Steps taken, gamma of the last step and the time reached (seconds)."""
+        n, g, t = C.c_int64(0), C.c_int64(0), C.c_double(0.0)
+        _check(lib().seas_state_progress(self.h, C.byref(n), C.byref(g), C.byref(t)))
+        return {"steps_taken": n.value, "last_gamma": g.value, "time_s": t.value}
 
     def set_overlap(self, enable=True):
         _check(lib().seas_state_set_overlap(self.h, 1 if enable else 0))

@@ -148,6 +148,11 @@ struct seas_state {
   double* partials_near;
   double* f_far;             // far part of the interaction for the S evaluations of a time block
   int64_t block_head = INT64_MIN / 2;  // head at which f_far was computed
+  // adaptive steps: steps taken, gamma of the last one, per-block minima of the
+  // step rule (device) and the slip coefficients at a long step's start
+  int64_t steps_taken = 0, last_gamma = 1;
+  double* dtev = nullptr;
+  double2* Dsv = nullptr;
   int run_S = 0;                        // 1: far list applied every step (plain form); else the build's S
   double2 *dring, *Fh, *F;
   int* fail;                 // per variant: a Newton solve failed (state held at its last good step)
@@ -236,6 +241,8 @@ StepArgs<TF> make_args(seas_op* op, seas_state* st) {
   a.first = st->first;
   a.tail = h.prm.int_tail;
   a.exact_state = h.prm.state_update == 1;
+  a.dts = h.dt;
+  a.gamma = 1;
   return a;
 }
 
@@ -367,6 +374,66 @@ void eval_history(seas_op* op, seas_state* st, int64_t head, hipStream_t s, void
   launch_reduce_near(h, pnear, op->red_ptr[1], op->red_idx[1], st->f_far + k * h.N, st->f_hist, s);
 }
 
+// Adaptive steps (Section 2.4.1, step 1): gamma = ceil(min xi Dc / V / dt) over
+// every element and variant, at least 1, at most gamma_max (read back to the host:
+// the evaluation heads depend on it).
+int64_t choose_gamma(seas_op* op, seas_state* st, hipStream_t s) {
+  const HostOp& h = op->h;
+  const int64_t ne = (int64_t)h.N * st->nv;
+  const int nb = (int)std::min<int64_t>(kDtEvBlocks, (ne + 255) / 256);
+  const double xi = h.prm.adapt_xi > 0.0 ? h.prm.adapt_xi : 0.5;
+  launch_dt_ev(st->V, st->fDc, ne, xi, st->dtev, nb, s);
+  double part[kDtEvBlocks];
+  HIPCHK(hipMemcpyAsync(part, st->dtev, nb * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  double m = part[0];
+  for (int b = 1; b < nb; ++b) m = std::min(m, part[b]);
+  const int64_t gmax = h.prm.gamma_max > 0 ? h.prm.gamma_max : (int64_t)1 << 20;
+  if (!(m > 0.0)) return 1;  // a rate that is not finite and positive: the solve reports it
+  const double q = std::ceil(m / h.dt);
+  return q >= (double)gmax ? gmax : std::max<int64_t>(1, (int64_t)q);
+}
+
+// One step of gamma > 1 grid steps from n: the rate and slip histories stay on the
+// grid. The step's interior intervals n+1 .. n+gamma-1 enter its history sums at the
+// starting rate V^n and the interior slip coefficients at the line from D^n to D*;
+// the commit gives the interior rows the averaged rate and the coefficients the
+// line to D** (the oracle's SeasState.step states the same). Rows and coefficients
+// older than the windows need not be written: only the last ring_len - 2 rows and
+// W_n coefficients of a mode can be read again.
+template <typename TF>
+void do_long_step(seas_op* op, seas_state* st, int64_t g, hipStream_t s) {
+  const HostOp& h = op->h;
+  const int nm = h.n_modes, nv = st->nv;
+  const int64_t dl = h.self_ring_len;
+  const int64_t n = st->step;
+  StepArgs<TF> a = make_args<TF>(op, st);
+  a.gamma = g;
+  a.dts = (double)g * h.dt;
+  a.t_next = (double)(n + g) * h.dt;
+  a.time_new = n + g;
+  a.self_head = n + g;
+  const int64_t lo = std::max<int64_t>(n + 1, n + g - h.ring_len + 2), hi = n + g - 1;
+  if (a.tail) launch_tail_advance<TF>(a, s);          // before the interior rows overwrite old ones
+  launch_fill_rows<TF>(a, lo, hi, st->V, s);
+  // self term: D* (kept in Dnew), the interior coefficients, the history at n+gamma, F*
+  launch_dft(nm, nv, h.N, dl, op->modes, op->sf, st->delta, st->V, a.dts, op->tw, op->tab, nullptr, st->F, st->dring,
+             0, 0, 0, s, st->Dnew);
+  launch_fill_modes(nm, nv, dl, op->modes, st->dring, n, g, st->Dnew, st->Dsv, 0, s);
+  launch_self_hist(nm, nv, dl, op->modes, op->tab, st->dring, n + g, st->Fh, s);
+  launch_dft(nm, nv, h.N, dl, op->modes, op->sf, st->delta, st->V, a.dts, op->tw, op->tab, st->Fh, st->F, st->dring,
+             0, 0, 0, s);
+  eval_history(op, st, n + g - 1, s);                 // interaction at t_{n+gamma}: lags >= 1 and the tail
+  launch_stage<TF>(a, 0, s);
+  launch_dft(nm, nv, h.N, dl, op->modes, op->sf, st->delta, st->Vbar, a.dts, op->tw, op->tab, st->Fh, st->F,
+             st->dring, 0, n + g, n + g, s, st->Dnew);
+  launch_stage<TF>(a, 1, s);
+  launch_commit<TF>(a, s);
+  launch_fill_rows<TF>(a, lo, hi, st->Vbar, s);
+  launch_fill_modes(nm, nv, dl, op->modes, st->dring, n, g, st->Dnew, st->Dsv, 1, s);
+  st->step = n + g;
+}
+
 template <typename TF>
 void do_steps(seas_op* op, seas_state* st, int n_steps, hipStream_t s) {
   const HostOp& h = op->h;
@@ -387,6 +454,13 @@ void do_steps(seas_op* op, seas_state* st, int n_steps, hipStream_t s) {
   st->la_head = INT64_MIN / 2;
   for (int it = 0; it < n_steps; ++it) {
     const int64_t n = st->step;
+    const int64_t g = h.prm.adaptive_dt ? choose_gamma(op, st, s) : 1;
+    st->last_gamma = g;
+    st->steps_taken++;
+    if (g > 1) {
+      do_long_step<TF>(op, st, g, s);
+      continue;
+    }
     // a lookahead is launched only for a block this call reaches, so the call
     // itself consumes every lookahead it starts
     const Lookahead la{it + S < n_steps};
@@ -902,6 +976,10 @@ seas_status seas_state_create(seas_op_t* op, int32_t n_variants, const seas_fric
     st->fs2 = (double*)A(vb, false);
     st->fi2 = (double*)A(vb, false);
     st->Dnew = (double2*)A((size_t)h.n_modes * 16 * nv, false);
+    if (h.prm.adaptive_dt) {
+      st->dtev = (double*)A(kDtEvBlocks * sizeof(double), false);
+      st->Dsv = (double2*)A((size_t)h.n_modes * 16 * nv, false);
+    }
     // host-side initial values
     std::vector<double> eps(N, 1.0), thd(N), zero(N, 0.0);
     if (fric->eps) eps.assign(fric->eps, fric->eps + N);
@@ -1271,6 +1349,15 @@ seas_status seas_state_set_timing(seas_state_t* st, int32_t enable) {
   return guard([&] {
     if (!st) throw Error(SEAS_ERR_INVALID_ARG, "null state");
     st->timing = enable != 0;
+  });
+}
+
+seas_status seas_state_progress(const seas_state_t* st, int64_t* steps_taken, int64_t* last_gamma, double* time_s) {
+  return guard([&] {
+    if (!st) throw Error(SEAS_ERR_INVALID_ARG, "null state");
+    if (steps_taken) *steps_taken = st->steps_taken;
+    if (last_gamma) *last_gamma = st->last_gamma;
+    if (time_s) *time_s = (double)st->step * st->op->h.dt;
   });
 }
 

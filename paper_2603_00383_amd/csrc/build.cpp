@@ -680,6 +680,11 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
     throw Error(SEAS_ERR_INVALID_ARG, "cluster_windows must be 0 or 1");
   if (prm.state_update != 0 && prm.state_update != 1)
     throw Error(SEAS_ERR_INVALID_ARG, "state_update must be 0 (explicit) or 1 (closed form at constant rate)");
+  if (prm.adaptive_dt != 0 && prm.adaptive_dt != 1) throw Error(SEAS_ERR_INVALID_ARG, "adaptive_dt must be 0 or 1");
+  if (prm.adaptive_dt && prm.time_block > 1)
+    throw Error(SEAS_ERR_INVALID_ARG, "adaptive_dt needs time_block 0 or 1 (steps of varying length)");
+  if (prm.gamma_max < 0 || !(prm.adapt_xi >= 0.0) || !std::isfinite(prm.adapt_xi))
+    throw Error(SEAS_ERR_INVALID_ARG, "gamma_max must be >= 0 and adapt_xi finite and >= 0");
   if (prm.time_block < 0 || prm.time_block > kMaxTimeBlock ||
       (prm.time_block & (prm.time_block - 1)) != 0)
     throw Error(SEAS_ERR_INVALID_ARG, "time_block must be 0, 1, 2, 4, 8 or 16");

@@ -51,6 +51,7 @@ struct Item {
 static_assert(sizeof(Item) == 56, "Item layout");
 
 constexpr int kItemThreads = 256;
+constexpr int kDtEvBlocks = 1024;  // blocks of the adaptive step rule's minimum
 constexpr int kHistMax = 6144;   // history values staged in LDS per item: (span of lags + S - 1) * q
 constexpr int kColMax = 1024;    // low-rank columns (and lags) per item
 constexpr int kZMax = 2048;      // low-rank columns times steps per item

@@ -550,6 +550,42 @@ __device__ __forceinline__ void tail_update(const StepArgs<TF>& a, int v, int r)
   }
 }
 
+// Long steps (gamma > 1 grid steps from n = time_new - gamma). Invariant between
+// steps: an accumulator with upper lag T_end holds dt times the rows t <= n - T_end
+// - 1. At the step's start (tail_advance) it takes the rows up to the step's
+// evaluation head minus T_end + 1: the committed ones n - T_end .. n (from the
+// ring) and the interior ones n+1 .. n+gamma-T_end-2 at the starting rate V^n; the
+// commit (tail_commit_long) replaces those interior values by the averaged rate
+// they are committed with and adds the row n+gamma-T_end-1, restoring the invariant.
+template <typename TF>
+__device__ __forceinline__ void tail_advance(const StepArgs<TF>& a, int v, int r, double Vn) {
+  double* E = a.tail_acc + v * a.tail_len;
+  const int64_t g = a.gamma, n = a.time_new - g;
+  for (int e = a.tail_src_ptr[r]; e < a.tail_src_ptr[r + 1]; ++e) {
+    const int acc = a.tail_src[2 * e], Tend = a.tail_src[2 * e + 1];
+    const int64_t hi = n + g - Tend - 2 < n ? n + g - Tend - 2 : n;
+    double add = 0.0;
+    for (int64_t t = n - Tend > a.first ? n - Tend : a.first; t <= hi; ++t)
+      add += a.dt * a.ring64[(ring_slot(t, a.R) * a.nv + v) * a.N + r];
+    const int64_t c = g - Tend - 2 > 0 ? g - Tend - 2 : 0;
+    E[acc] += add + (double)c * a.dt * Vn;
+  }
+}
+
+template <typename TF>
+__device__ __forceinline__ void tail_commit_long(const StepArgs<TF>& a, int v, int r, double Vn, double Vb) {
+  double* E = a.tail_acc + v * a.tail_len;
+  const int64_t g = a.gamma, n = a.time_new - g;
+  for (int e = a.tail_src_ptr[r]; e < a.tail_src_ptr[r + 1]; ++e) {
+    const int acc = a.tail_src[2 * e], Tend = a.tail_src[2 * e + 1];
+    const int64_t c = g - Tend - 2 > 0 ? g - Tend - 2 : 0;
+    const int64_t ts = n + g - Tend - 1;
+    double add = (double)c * a.dt * (Vb - Vn);
+    if (ts >= a.first) add += a.dt * (ts <= n ? a.ring64[(ring_slot(ts, a.R) * a.nv + v) * a.N + r] : Vb);
+    E[acc] += add;
+  }
+}
+
 // operand copy of a rate value
 template <typename TF>
 __device__ __forceinline__ TF to_op(double x) {
@@ -578,16 +614,16 @@ __global__ void k_stage(StepArgs<TF> a, int stage) {
   const Friction& fr = a.fric;
   if (stage == 0) {  // predictor: delta*, theta* from the current rates
     const double V = a.V[e];
-    const double th_s = a.exact_state ? state_after(a.theta[e], V, fr.Dc[e], a.dt, fr.eps[e])
-                                      : a.theta[e] + a.dt * a.thdot[e];
+    const double th_s = a.exact_state ? state_after(a.theta[e], V, fr.Dc[e], a.dts, fr.eps[e])
+                                      : a.theta[e] + a.dts * a.thdot[e];
     const double fint = a.f_hist[e] - a.eta * lag0_apply(a.l0_ptr, a.l0_col, a.l0_val, a.V + o, r);
     const double Vs = newton_lnV(tau0 + fself + fint, th_s, a.eta, fr.a[e], fr.b[e], fr.Dc[e], fr.sn[e], fr.V0[e],
                                  fr.f0[e], log(V), a.fail + v);
     const double tds = state_rate(Vs, th_s, fr.Dc[e], fr.eps[e]);
     a.Vstar[e] = Vs;
     a.Vbar[e] = 0.5 * (V + Vs);
-    a.th2[e] = a.exact_state ? state_after(a.theta[e], 0.5 * (V + Vs), fr.Dc[e], a.dt, fr.eps[e])
-                             : a.theta[e] + a.dt * 0.5 * (a.thdot[e] + tds);
+    a.th2[e] = a.exact_state ? state_after(a.theta[e], 0.5 * (V + Vs), fr.Dc[e], a.dts, fr.eps[e])
+                             : a.theta[e] + a.dts * 0.5 * (a.thdot[e] + tds);
   } else {  // corrector with the averaged rates; only the lag-0 terms change
     const double Vb = a.Vbar[e];
     const double th2 = a.th2[e];
@@ -617,7 +653,8 @@ __global__ void k_commit(StepArgs<TF> a) {
     if (a.fail[v]) return;
     const int64_t e = g;
     const double V2 = a.V2[e];
-    a.delta[e] += a.dt * a.Vbar[e];
+    if (a.tail && a.gamma > 1) tail_commit_long(a, v, r, a.V[e], a.Vbar[e]);
+    a.delta[e] += a.dts * a.Vbar[e];
     a.theta[e] = a.th2[e];
     a.thdot[e] = a.td2[e];
     a.V[e] = V2;
@@ -627,7 +664,7 @@ __global__ void k_commit(StepArgs<TF> a) {
     a.ring64[ri] = V2;
     if ((void*)a.ringop != (void*)a.ring64)
       a.ringop[a.op_vfast ? (sl * a.N + r) * a.nv + v : ri] = to_op<TF>(V2);
-    if (a.tail) tail_update(a, v, r);
+    if (a.tail && a.gamma == 1) tail_update(a, v, r);
     if (r == 0) a.good[v] = a.time_new;
     return;
   }
@@ -784,6 +821,89 @@ void launch_dft(int n_modes, int nv, int N, int64_t dring_len, const SelfMode* m
                      dring_len, sf, delta, vel, coef, tw, tab, Fh, Fout, dring, push, push_time, ring_head, Dsave);
 }
 
+__global__ void k_dt_ev(const double* __restrict__ V, const double* __restrict__ Dc, int64_t ne, double xi,
+                        double* __restrict__ part) {
+  __shared__ double wmin[4];
+  double m = INFINITY;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += (int64_t)gridDim.x * blockDim.x)
+    m = fmin(m, xi * Dc[e] / V[e]);
+  for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = fmin(fmin(wmin[0], wmin[1]), fmin(wmin[2], wmin[3]));
+}
+
+template <typename TF>
+__global__ void k_tail_advance(StepArgs<TF> a) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (int64_t)a.N * a.nv) return;
+  const int v = (int)(g / a.N), r = (int)(g - (int64_t)v * a.N);
+  if (a.fail[v]) return;
+  tail_advance(a, v, r, a.V[g]);
+}
+
+template <typename TF>
+__global__ void k_fill_rows(StepArgs<TF> a, int64_t lo, int64_t rows, const double* __restrict__ src) {
+  const int64_t ne = (int64_t)a.N * a.nv;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= rows * ne) return;
+  const int64_t k = g / ne, e = g - k * ne;
+  const int v = (int)(e / a.N), r = (int)(e - (int64_t)v * a.N);
+  const double x = src[e];
+  const int64_t sl = ring_slot(lo + k, a.R), ri = (sl * a.nv + v) * a.N + r;
+  a.ring64[ri] = x;
+  if ((void*)a.ringop != (void*)a.ring64) a.ringop[a.op_vfast ? (sl * a.N + r) * a.nv + v : ri] = to_op<TF>(x);
+}
+
+__global__ void k_fill_modes(int n_modes, int nv, int64_t dring_len, const SelfMode* __restrict__ modes,
+                             double2* __restrict__ dring, int64_t n, int64_t gamma, const double2* __restrict__ Dend,
+                             double2* __restrict__ Dsv, int commit) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (int64_t)n_modes * nv) return;
+  const int v = (int)(g / n_modes), gm = (int)(g - (int64_t)v * n_modes);
+  const SelfMode md = modes[gm];
+  if (md.W <= 0) return;
+  double2* ring = dring + v * dring_len + md.ring;
+  double2 d0;
+  if (commit) {
+    d0 = Dsv[g];
+  } else {
+    d0 = ring[ring_slot(n, md.W)];
+    Dsv[g] = d0;
+  }
+  const double2 d1 = Dend[g];
+  // the entries the next history sums read: predictor n+gamma-W .. n+gamma-1, after
+  // the commit n+gamma-W+1 .. n+gamma-1 (its push adds n+gamma); interior only
+  const int64_t m0 = commit ? gamma - md.W + 1 : gamma - md.W;
+  for (int64_t m = m0 > 1 ? m0 : 1; m < gamma; ++m) {
+    const double w = (double)m / (double)gamma;
+    ring[ring_slot(n + m, md.W)] = make_double2(d0.x + w * (d1.x - d0.x), d0.y + w * (d1.y - d0.y));
+  }
+}
+
+void launch_dt_ev(const double* V, const double* Dc, int64_t ne, double xi, double* part, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_dt_ev, dim3(nblocks), dim3(256), 0, s, V, Dc, ne, xi, part);
+}
+
+template <typename TF>
+void launch_tail_advance(const StepArgs<TF>& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_tail_advance<TF>), dim3(blocks_for((int64_t)a.N * a.nv, 256)), dim3(256), 0, s, a);
+}
+
+template <typename TF>
+void launch_fill_rows(const StepArgs<TF>& a, int64_t lo, int64_t hi, const double* src, hipStream_t s) {
+  if (hi < lo) return;
+  const int64_t rows = hi - lo + 1;
+  hipLaunchKernelGGL((k_fill_rows<TF>), dim3(blocks_for(rows * a.N * a.nv, 256)), dim3(256), 0, s, a, lo, rows,
+                     src);
+}
+
+void launch_fill_modes(int n_modes, int nv, int64_t dring_len, const SelfMode* modes, double2* dring, int64_t n,
+                       int64_t gamma, const double2* Dend, double2* Dsv, int commit, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_modes, dim3(blocks_for((int64_t)n_modes * nv, 256)), dim3(256), 0, s, n_modes, nv,
+                     dring_len, modes, dring, n, gamma, Dend, Dsv, commit);
+}
+
 template <typename TF>
 void launch_stage(const StepArgs<TF>& a, int stage, hipStream_t s) {
   hipLaunchKernelGGL((k_stage<TF>), dim3(blocks_for((int64_t)a.N * a.nv, 4)), dim3(256), 0, s, a, stage);
@@ -805,6 +925,12 @@ void launch_prescribed_out(const StepArgs<TF>& a, const double* Vprev, double* f
   hipLaunchKernelGGL((k_pre_out<TF>), dim3(blocks_for((int64_t)a.N * a.nv, 4)), dim3(256), 0, s, a, Vprev, fout);
 }
 
+template void launch_tail_advance<double>(const StepArgs<double>&, hipStream_t);
+template void launch_tail_advance<float>(const StepArgs<float>&, hipStream_t);
+template void launch_tail_advance<__bf16>(const StepArgs<__bf16>&, hipStream_t);
+template void launch_fill_rows<double>(const StepArgs<double>&, int64_t, int64_t, const double*, hipStream_t);
+template void launch_fill_rows<float>(const StepArgs<float>&, int64_t, int64_t, const double*, hipStream_t);
+template void launch_fill_rows<__bf16>(const StepArgs<__bf16>&, int64_t, int64_t, const double*, hipStream_t);
 template void launch_commit<double>(const StepArgs<double>&, hipStream_t);
 template void launch_commit<float>(const StepArgs<float>&, hipStream_t);
 template void launch_commit<__bf16>(const StepArgs<__bf16>&, hipStream_t);

@@ -34,6 +34,8 @@ struct StepArgs {
   int N, nv, n_modes;
   int64_t tail_len, dring_len;
   double dt, eta, t_next;
+  double dts;               // length of this step: dt (the grid step) times gamma
+  int64_t gamma;            // grid steps in this step (1: the fixed step)
   const int* fault_of;
   const SelfFaultDev* sf;
   const double2* tw;
@@ -113,6 +115,21 @@ void launch_stage(const StepArgs<TF>& a, int stage, hipStream_t s);
 // Newton solves of the step converged (a failed variant keeps its last good step)
 template <typename TF>
 void launch_commit(const StepArgs<TF>& a, hipStream_t s);
+// Adaptive steps (a.gamma grid steps from n = a.time_new - a.gamma):
+// per-block minima of xi Dc_e / V_e over ne values into part[0..nblocks)
+void launch_dt_ev(const double* V, const double* Dc, int64_t ne, double xi, double* part, int nblocks, hipStream_t s);
+// expired-slip accumulators at a long step's start: the committed rows that leave
+// the windows, and its interior rows that do, at the starting rate V
+template <typename TF>
+void launch_tail_advance(const StepArgs<TF>& a, hipStream_t s);
+// rate rows [lo, hi] (grid times) of every variant := src ([nv][N]), FP64 ring and operand copy
+template <typename TF>
+void launch_fill_rows(const StepArgs<TF>& a, int64_t lo, int64_t hi, const double* src, hipStream_t s);
+// slip coefficients of a long step's interior grid times on the line from D^n to
+// Dend ([nv][n_modes]); commit = 0 also keeps D^n in Dsv first (the ring slot of
+// D^n may be among those written), commit = 1 takes D^n from Dsv
+void launch_fill_modes(int n_modes, int nv, int64_t dring_len, const SelfMode* modes, double2* dring, int64_t n,
+                       int64_t gamma, const double2* Dend, double2* Dsv, int commit, hipStream_t s);
 template <typename TF>
 void launch_prescribed_push(const StepArgs<TF>& a, const double* Vin, hipStream_t s);
 template <typename TF>
