@@ -323,6 +323,66 @@ def run_two_fault(args):
     print(json.dumps(out), flush=True)
 
 
+def adaptive_leg(n=1000, max_steps=3000, t_target=60.0):
+    """Adaptive steps (Section 2.4.1, step 1) on the paper's two-fault benchmark (Section
+    3.1, Table 1) at 2 x n elements, FP64 factors: two steps of gamma = 1 settle the
+    printed initial state (a rate held under the overstress), then gamma follows the
+    rule (xi = 0.5) through the rupture and after it, until t_target seconds or
+    max_steps steps. Reports the steps, the Delta t_min grid steps they cover and the
+    element-steps per second of both."""
+    import numpy as np
+    import torch
+
+    import paper_2603_00383_amd as P
+    import seas_inputs as SI
+
+    with open(os.path.join(ROOT, "tests", "golden", "two_fault_benchmark.json")) as fh:
+        gold = json.load(fh)
+    faults, fric = SI.two_fault_benchmark(gold, n)
+    ini = SI.two_fault_benchmark_state(gold, faults, fric)
+    p = SI.two_fault_benchmark_params(gold, n, time_block=1, factor_dtype="f64", adaptive_dt=1, adapt_xi=0.5)
+    s = torch.cuda.current_stream().cuda_stream
+    t0 = time.perf_counter()
+    op = P.Operator(faults, p)
+    bs = time.perf_counter() - t0
+    N, dt = op.N, op.info["dt"]
+    st = P.State(op, fric, ini["V"], ini["theta"], ini["tau0"], ini["tau0_rate"], stream=s)
+    st.set_gamma_cap(1)
+    st.step(2, stream=s)
+    st.check(stream=s)
+    st.set_gamma_cap(0)
+    g0 = st.step_index
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    gammas = []
+    while len(gammas) < max_steps and st.step_index * dt < t_target:
+        st.step(1, stream=s)
+        gammas.append(st.progress()["last_gamma"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    st.check(stream=s)
+    V = st.read("V", stream=s)
+    grid = st.step_index - g0
+    k1 = next((i for i, g in enumerate(gammas) if g > 1 and i > 10), None)
+    out = {"workload": f"two-fault benchmark of Section 3.1 / Table 1, 2 x {n} elements, FP64, eta_H 1.5, ACA 1e-6, "
+                       "per-step evaluation (time block 1), adaptive steps xi = 0.5 after two steps of gamma = 1",
+           "steps": len(gammas), "grid_steps": int(grid), "time_reached_s": float(st.step_index * dt),
+           "wall_s": wall, "ms_per_step": wall / max(len(gammas), 1) * 1e3,
+           "element_steps_per_s": N * len(gammas) / wall,
+           "grid_element_steps_per_s": N * grid / wall,
+           "fixed_steps_for_same_time": int(grid), "step_reduction": grid / max(len(gammas), 1),
+           "gamma_first_above_1_at_step": k1, "gamma_max": int(max(gammas)),
+           "gamma_median": float(np.median(gammas)), "V_max_end": [float(V[:n].max()), float(V[n:].max())],
+           "build_s": bs}
+    st.close()
+    op.close()
+    return out
+
+
+def run_adaptive(args):
+    print(json.dumps({"adaptive": adaptive_leg(args.elements, args.adaptive_steps, args.adaptive_time)}), flush=True)
+
+
 def run_ensemble(args):
     """Ensemble throughput: one geometry, many friction variants stepped together;
     the interaction sums of all variants are one 16-bit product per work item."""
@@ -492,7 +552,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=160)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="seas", choices=["seas", "ensemble", "serving", "precision", "two-fault"],
+    ap.add_argument("--workload", default="seas",
+                    choices=["seas", "ensemble", "serving", "precision", "two-fault", "adaptive"],
                     help="seas: five-fault step loop (one variant); ensemble: eight faults x 750 elements, "
                          "64 friction variants in one launch (BF16); precision: 20,000-step trajectories of "
                          "the reduced-precision forms against FP64")
@@ -524,6 +585,10 @@ def main():
                     help="skip the oracle CPU leg (the forms' errors are then not measured)")
     ap.add_argument("--no-serving", action="store_true", help="skip the bounded serving leg")
     ap.add_argument("--no-two-fault", action="store_true", help="skip the two-fault FP64 workload")
+    ap.add_argument("--adaptive", action="store_true",
+                    help="add the adaptive-step leg (two-fault benchmark, ~90 s with its operator build)")
+    ap.add_argument("--adaptive-steps", type=int, default=3000, help="adaptive: steps at most")
+    ap.add_argument("--adaptive-time", type=float, default=60.0, help="adaptive: simulated seconds to reach")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 2 GiB buffer three times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -565,6 +630,8 @@ def main():
         return run_precision(args)
     if args.workload == "two-fault":
         return run_two_fault(args)
+    if args.workload == "adaptive":
+        return run_adaptive(args)
     if args.dtype is None:
         args.dtype = "f32"
     faults = SI.five_fault_network(seed=args.seed)
@@ -792,6 +859,11 @@ def main():
         op1.close()
         print(f"[bench] two-fault FP64: {out['two_fault_fp64']['value']:.3e} element-steps/s, error {e1}",
               file=sys.stderr, flush=True)
+    if args.adaptive:
+        out["adaptive"] = adaptive_leg(1000, args.adaptive_steps, args.adaptive_time)
+        a = out["adaptive"]
+        print(f"[bench] adaptive: {a['steps']} steps to t = {a['time_reached_s']:.3g} s ({a['grid_steps']} grid steps, "
+              f"{a['wall_s']:.1f} s wall, gamma up to {a['gamma_max']})", file=sys.stderr, flush=True)
     if not args.no_serving:
         out["serving"] = serving_leg(args.seed, "f16", 3, (500, 1000, 2000), 24, 4.0, 200, 1000, 16, 64.0)
         print(f"[bench] serving p50 {out['serving']['latency_s']['p50']:.2f} s p99 "

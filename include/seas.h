@@ -395,6 +395,14 @@ int64_t seas_state_step_index(const seas_state_t* st);
  * (grid index times Delta t_min). Any output may be NULL. */
 seas_status seas_state_progress(const seas_state_t* st, int64_t* steps_taken, int64_t* last_gamma, double* time_s);
 
+/* Adaptive steps: a cap on gamma for this state below the operator's gamma_max (0
+ * removes it). The rule reads the rates of the current state, which must balance
+ * the stresses: from an initial state that does not (a rate held while an
+ * overstress is applied, as in Section 3.1), the first steps are taken with cap 1
+ * and the cap is lifted once the solves have set the rates. INVALID_ARG for
+ * cap < 0. */
+seas_status seas_state_set_gamma_cap(seas_state_t* st, int64_t cap);
+
 /* Checkpoint: size in bytes, save to / restore from a host buffer (synchronises
  * the stream). Restoring into a state of the same operator reproduces the
  * saved state exactly. */

@@ -110,6 +110,7 @@ def lib():
             "seas_state_set_timing": (i32, [vp, i32]),
             "seas_state_set_overlap": (i32, [vp, i32]),
             "seas_state_progress": (i32, [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+            "seas_state_set_gamma_cap": (i32, [vp, C.c_int64]),
             "seas_state_set_time_block": (i32, [vp, i32]),
             "seas_state_read_timing": (i32, [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
             "seas_state_checkpoint_bytes": (C.c_size_t, [vp]),
@@ -321,6 +322,9 @@ class State:
 
     def set_timing(self, enable=True):
         _check(lib().seas_state_set_timing(self.h, 1 if enable else 0))
+
+    def set_gamma_cap(self, cap):
+        _check(lib().seas_state_set_gamma_cap(self.h, int(cap)))
 
     def progress(self):
         """Steps taken, gamma of the last step and the time reached (seconds)."""

@@ -151,6 +151,7 @@ struct seas_state {
   // adaptive steps: steps taken, gamma of the last one, per-block minima of the
   // step rule (device) and the slip coefficients at a long step's start
   int64_t steps_taken = 0, last_gamma = 1;
+  int64_t gamma_cap = 0;  // > 0: this state's cap on gamma (below the operator's gamma_max)
   double* dtev = nullptr;
   double2* Dsv = nullptr;
   int run_S = 0;                        // 1: far list applied every step (plain form); else the build's S
@@ -388,7 +389,8 @@ int64_t choose_gamma(seas_op* op, seas_state* st, hipStream_t s) {
   HIPCHK(hipStreamSynchronize(s));
   double m = part[0];
   for (int b = 1; b < nb; ++b) m = std::min(m, part[b]);
-  const int64_t gmax = h.prm.gamma_max > 0 ? h.prm.gamma_max : (int64_t)1 << 20;
+  int64_t gmax = h.prm.gamma_max > 0 ? h.prm.gamma_max : (int64_t)1 << 20;
+  if (st->gamma_cap > 0) gmax = std::min(gmax, st->gamma_cap);
   if (!(m > 0.0)) return 1;  // a rate that is not finite and positive: the solve reports it
   const double q = std::ceil(m / h.dt);
   return q >= (double)gmax ? gmax : std::max<int64_t>(1, (int64_t)q);
@@ -1349,6 +1351,14 @@ seas_status seas_state_set_timing(seas_state_t* st, int32_t enable) {
   return guard([&] {
     if (!st) throw Error(SEAS_ERR_INVALID_ARG, "null state");
     st->timing = enable != 0;
+  });
+}
+
+seas_status seas_state_set_gamma_cap(seas_state_t* st, int64_t cap) {
+  return guard([&] {
+    if (!st) throw Error(SEAS_ERR_INVALID_ARG, "null state");
+    if (cap < 0) throw Error(SEAS_ERR_INVALID_ARG, "cap < 0");
+    st->gamma_cap = cap;
   });
 }
 

@@ -118,3 +118,28 @@ def test_adaptive_with_unit_gamma_is_the_fixed_step():
 def test_adaptive_needs_unblocked_steps():
     with pytest.raises(P.SeasError):
         P.Operator(FAULTS, SI.default_params(time_block=8, adaptive_dt=1))
+
+
+def test_state_gamma_cap():
+    # a per-state cap below the operator's: the steps of an oracle whose cap is the same
+    fric, ini, rate = _setup()
+    s = _stream()
+    p = SI.default_params(time_block=1, factor_dtype="f64", compress=0, state_update="exact", adaptive_dt=1,
+                          adapt_xi=0.01, gamma_max=300)
+    op = P.Operator(FAULTS, p)
+    st = P.State(op, fric, ini["V"], ini["theta"], ini["tau0"], rate, stream=s)
+    o = OS.SeasState(OS.Problem(FAULTS, p), fric, ini["V"], ini["theta"], ini["tau0"], rate, state_update="exact",
+                     adaptive=True, xi=0.01, gamma_max=1)
+    st.set_gamma_cap(1)
+    st.step(3, stream=s)
+    for _ in range(3):
+        o.step()
+    assert st.step_index == o.n == 3
+    st.set_gamma_cap(20)
+    o.gamma_max = 20
+    for _ in range(10):
+        st.step(1, stream=s)
+        o.step()
+        assert st.progress()["last_gamma"] == o.last["gamma"] <= 20
+    st.check(stream=s)
+    assert rel_err(st.read("V", stream=s), o.V) < 1e-9
