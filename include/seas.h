@@ -136,6 +136,14 @@ typedef struct {
   int32_t gamma_max;    /* largest gamma (0 = 2^20) */
   double adapt_xi;      /* xi of the rule (0 = 0.5); the paper ties it to each element's stiffness
                            and friction through a formula it does not print, so it is an input here */
+  int32_t free_surface; /* 1: a traction-free surface on the line y = surface_y, the medium below it
+                           (y < surface_y), by the method of images (exact in anti-plane, the
+                           construction of Appendix A's BP1-FD check): every source fault acts
+                           also through its mirror image, with the slip continued across the
+                           surface; each receiver fault therefore also has a pair with its own
+                           image. Faults must lie below the line (end points may touch it). */
+  int32_t reserved_fs;
+  double surface_y;
 } seas_params_t;
 
 typedef struct seas_op seas_op_t;
@@ -202,6 +210,12 @@ seas_status seas_operator_info(const seas_op_t* op, seas_op_info_t* out);
  * a != b, row-major over a then b with the diagonal skipped:
  * n_faults * (n_faults - 1) entries each. */
 seas_status seas_operator_windows(const seas_op_t* op, int32_t* T_init, int32_t* T_end);
+/* Causality window [T_init, T_end] of one pair: b < n_faults the fault pair (a, b),
+ * b in [n_faults, 2 n_faults) the pair of receiver fault a with the mirror image of
+ * fault b - n_faults (free_surface; seas_operator_windows lists the fault pairs
+ * only). The same index also selects image pairs in seas_operator_blocks.
+ * INVALID_ARG for a pair that does not exist. */
+seas_status seas_operator_pair_window(const seas_op_t* op, int32_t a, int32_t b, int32_t* T_init, int32_t* T_end);
 
 /* Block partition of the ordered pair (a, b) (the dual-tree traversal of
  * Section 2.3.2): count (blocks == NULL) or copy rows of 6 int32: r0, r1, s0, s1
@@ -219,7 +233,9 @@ seas_status seas_operator_self_table(const seas_op_t* op, int32_t k, int32_t n,
 /* Reconstruct the kernel matrix of the ordered pair (a, b) at lag T (T >= 0; T = -1
  * for the static-tail matrix, stored as -G/eta with G the static stress per unit
  * slip) from the stored factors: out is n_elem(a) x n_elem(b), row-major, host.
- * Only for operators built with host_only = 1 (the factors are on the host). */
+ * b = n_faults + a selects the pair of fault a with its own mirror image
+ * (free_surface; the image pair's sign included). Only for operators built with
+ * host_only = 1 (the factors are on the host). */
 seas_status seas_operator_lag_matrix(const seas_op_t* op, int32_t a, int32_t b, int32_t T, double* out);
 
 /* Rate-and-state parameters, one value per element and variant (host arrays of

@@ -31,6 +31,18 @@ def discretize(faults):
     return [Fault(d) for d in faults]
 
 
+def mirror_images(faults, y0):
+    """Method of images for a traction-free line y = y0 (anti-plane): each fault's
+    reflection. Reflection maps the normal (nx, ny) to (nx, -ny) and reverses the
+    order of the elements along the tangent; the image is given the opposite
+    normal (-nx, ny), which restores the order (element j of the image is the
+    reflection of element j), so that the even continuation of the displacement,
+    whose jump across the reflected normal equals the original slip, is a slip of
+    minus the original's across this normal."""
+    return [dict(f, cx=float(f["cx"]), cy=2.0 * y0 - float(f["cy"]), nx=-float(f["nx"]), ny=float(f["ny"]))
+            for f in faults]
+
+
 def offsets(geo):
     """Global index of each fault's first element."""
     off = [0]

@@ -192,17 +192,28 @@ class DenseInteraction:
     window, and the static tail matrices."""
 
     def __init__(self, geo, mu, cs, dt, eta_tmin=0.01, eta_tmax=0.01, windowed=True,
-                 max_lag=None, with_tail=True, blocks=None):
+                 max_lag=None, with_tail=True, blocks=None, images=None):
         """``blocks`` (the partition of every pair, from hpartition.partition):
         cluster-level windows, every entry (i, j) truncated at the upper lag of the
         block that holds it (``block_window_end``, at most the pair's T_end); its
-        older slip then contributes the static stress per block."""
+        older slip then contributes the static stress per block.
+
+        ``images``: the discretised mirror images of the faults (free surface,
+        geometry.mirror_images): every receiver fault a also takes the pair (a,
+        image of b) for every b, a included, whose kernel and static matrix enter with
+        sign -1 (the image carries minus the slip of b across its own normal) and act
+        on the slip rates of fault b. Those pairs are keyed (a, n_faults + b); with
+        ``blocks`` the partition must cover them under the same keys."""
+        nf = len(geo)
+        self.nf = nf
+        self.geo_all = list(geo) + (list(images) if images is not None else [])
+        geo = self.geo_all
         self.geo, self.mu, self.cs, self.dt = geo, mu, cs, dt
         self.off = [0]
-        for f in geo:
+        for f in geo[:nf]:
             self.off.append(self.off[-1] + f.Np)
         self.pairs = {}
-        for a in range(len(geo)):
+        for a in range(nf):
             for b in range(len(geo)):
                 if a == b:
                     continue
@@ -214,9 +225,10 @@ class DenseInteraction:
                 # meet zero history there (checked in stress()).
                 T1s = T1 if max_lag is None else min(T1, int(max_lag))
                 lags = np.arange(T0, T1s + 1)
-                K = pair_kernel_stack(geo, a, b, lags, dt, cs)
-                G = static_dipole(geo, a, b, mu) if with_tail else None
-                P = dict(T0=T0, T1=T1, T1s=T1s, K=K, G=G)
+                sgn = -1.0 if b >= nf else 1.0
+                K = sgn * pair_kernel_stack(geo, a, b, lags, dt, cs)
+                G = sgn * static_dipole(geo, a, b, mu) if with_tail else None
+                P = dict(T0=T0, T1=T1, T1s=T1s, K=K, G=G, src=b % nf)
                 if blocks is not None:
                     bl = [(r0, r1, s0, s1, min(T1, block_window_end(geo, a, b, (r0, r1, s0, s1), cs, dt, eta_tmax)))
                           for r0, r1, s0, s1, _ in blocks[(a, b)]]
@@ -240,7 +252,7 @@ class DenseInteraction:
         eta = self.mu / (2 * self.cs)
         f = np.zeros(self.off[-1])
         for (a, b), P in self.pairs.items():
-            rb = slice(self.off[b], self.off[b + 1])
+            rb = slice(self.off[P["src"]], self.off[P["src"] + 1])
             if P["T1s"] < P["T1"] and head - (P["T1s"] + 1) >= first:
                 raise ValueError("history reaches lags that were not stored")
             lags = np.arange(P["T0"], P["T1s"] + 1)
@@ -256,7 +268,8 @@ class DenseInteraction:
                     for r0, r1, s0, s1, te in P["blocks"]:
                         last = head - te - 1
                         if last >= first:
-                            E = self.dt * np.sum(Vh[: last - first + 1, self.off[b] + s0:self.off[b] + s1], axis=0)
+                            c0 = self.off[P["src"]]
+                            E = self.dt * np.sum(Vh[: last - first + 1, c0 + s0:c0 + s1], axis=0)
                             acc[r0:r1] += P["G"][r0:r1, s0:s1] @ E
                 else:
                     acc = acc + P["G"] @ expired[(a, b)]
@@ -269,7 +282,8 @@ class DenseInteraction:
         f = np.zeros(self.off[-1])
         for (a, b), P in self.pairs.items():
             if P["T0"] == 0:
-                f[self.off[a]:self.off[a + 1]] += -eta * (P["K"][0] @ v[self.off[b]:self.off[b + 1]])
+                sb = P["src"]
+                f[self.off[a]:self.off[a + 1]] += -eta * (P["K"][0] @ v[self.off[sb]:self.off[sb + 1]])
         return f
 
     def expired_slip(self, Vh, head, first, dt):
@@ -277,7 +291,7 @@ class DenseInteraction:
         out = {}
         for (a, b), P in self.pairs.items():
             last = head - P["T1"] - 1
-            rb = slice(self.off[b], self.off[b + 1])
+            rb = slice(self.off[P["src"]], self.off[P["src"] + 1])
             if last >= first:
                 out[(a, b)] = dt * np.sum(Vh[: last - first + 1, rb], axis=0)
             else:

@@ -41,14 +41,19 @@ class Problem:
         self.dt = geometry.time_step(self.geo, self.cs, float(p.get("beta", 0.5)))
         self.with_tail = bool(p.get("int_tail", 1))
         self.inter = None
+        # free surface (method of images): the mirror images act as extra sources
+        self.images = None
+        if int(p.get("free_surface", 0)):
+            self.images = geometry.discretize(geometry.mirror_images(faults, float(p.get("surface_y", 0.0))))
         if dense:
             blocks = None
             if int(p.get("cluster_windows", 0)):
-                blocks = hpartition.partition(self.geo, float(p.get("eta_H", 2.0)), int(p.get("leaf", 50)))
+                blocks = hpartition.partition(self.geo + (self.images or []), float(p.get("eta_H", 2.0)),
+                                              int(p.get("leaf", 50)))
             self.inter = interaction.DenseInteraction(
                 self.geo, self.mu, self.cs, self.dt, float(p.get("eta_tmin", 0.01)),
                 float(p.get("eta_tmax", 0.01)), windowed=True, max_lag=n_hist_max,
-                with_tail=self.with_tail, blocks=blocks)
+                with_tail=self.with_tail, blocks=blocks, images=self.images)
         self.selfs = []
         cache = {}
         for f in self.geo:

@@ -41,7 +41,8 @@ class Params(C.Structure):
                 ("factor_dtype", C.c_int32), ("n_threads", C.c_int32), ("host_only", C.c_int32),
                 ("time_block", C.c_int32), ("n_variants", C.c_int32), ("state_update", C.c_int32),
                 ("cluster_windows", C.c_int32), ("adaptive_dt", C.c_int32), ("gamma_max", C.c_int32),
-                ("adapt_xi", C.c_double)]
+                ("adapt_xi", C.c_double), ("free_surface", C.c_int32), ("reserved_fs", C.c_int32),
+                ("surface_y", C.c_double)]
 
 
 class OpInfo(C.Structure):
@@ -92,6 +93,7 @@ def lib():
             "seas_operator_info": (i32, [vp, C.POINTER(OpInfo)]),
             "seas_operator_windows": (i32, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
             "seas_operator_blocks": (i32, [vp, i32, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
+            "seas_operator_pair_window": (i32, [vp, i32, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
             "seas_operator_self_table": (i32, [vp, i32, i32, dp, i32, C.POINTER(C.c_int32)]),
             "seas_operator_lag_matrix": (i32, [vp, i32, i32, i32, dp]),
             "seas_state_bytes": (C.c_size_t, [vp, i32]),
@@ -173,6 +175,8 @@ def make_params(p):
     q.adaptive_dt = int(p.get("adaptive_dt", 0))
     q.gamma_max = int(p.get("gamma_max", 0))
     q.adapt_xi = float(p.get("adapt_xi", 0.0))
+    q.free_surface = int(p.get("free_surface", 0))
+    q.surface_y = float(p.get("surface_y", 0.0))
     return q
 
 
@@ -205,6 +209,12 @@ class Operator:
                     out[(i, j)] = (a[k], b[k])
                     k += 1
         return out
+
+    def pair_window(self, a, b):
+        """(T_init, T_end) of pair (a, b); b >= n_faults selects the image of fault b - n_faults."""
+        t0, t1 = C.c_int32(0), C.c_int32(0)
+        _check(lib().seas_operator_pair_window(self.h, a, b, C.byref(t0), C.byref(t1)))
+        return t0.value, t1.value
 
     def blocks(self, a, b):
         cnt = C.c_int64(0)

@@ -700,8 +700,12 @@ seas_status seas_operator_lag_matrix(const seas_op_t* op, int32_t a, int32_t b, 
     if (!op->host_only) throw Error(SEAS_ERR_MISMATCH, "factors are only kept on the host with host_only = 1");
     const HostOp& h = op->h;
     const int nf = (int)h.faults.size();
-    if (a < 0 || b < 0 || a >= nf || b >= nf || a == b || T < -1) throw Error(SEAS_ERR_INVALID_ARG, "bad pair/lag");
-    const Fault &A = h.faults[a], &B = h.faults[b];
+    // b = nf + a: the pair of fault a with its own image (free surface), the only image
+    // pair whose source columns no fault pair shares
+    const bool own_img = !h.images.empty() && b == nf + a;
+    if (a < 0 || b < 0 || a >= nf || (b >= nf && !own_img) || a == b || T < -1)
+      throw Error(SEAS_ERR_INVALID_ARG, "bad pair/lag");
+    const Fault &A = h.faults[a], &B = h.faults[own_img ? a : b];
     const int p_all = A.Np, q_all = B.Np;
     std::fill(out, out + (size_t)p_all * q_all, 0.0);
     if (T == 0) {
@@ -852,10 +856,34 @@ seas_status seas_operator_info(const seas_op_t* op, seas_op_info_t* out) {
 seas_status seas_operator_windows(const seas_op_t* op, int32_t* T_init, int32_t* T_end) {
   return guard([&] {
     if (!op || !T_init || !T_end) throw Error(SEAS_ERR_INVALID_ARG, "null argument");
-    for (size_t i = 0; i < op->h.pairs.size(); ++i) {
-      T_init[i] = op->h.pairs[i].T_init;
-      T_end[i] = op->h.pairs[i].T_end;
+    size_t k = 0;
+    for (const PairWin& w : op->h.pairs) {
+      if (w.img) continue;  // the image pairs follow the fault pairs; see seas_operator_pair_window
+      T_init[k] = w.T_init;
+      T_end[k] = w.T_end;
+      ++k;
     }
+  });
+}
+
+// pair index of (a, b): b < nf the fault pair, b in [nf, 2 nf) the image of fault b - nf
+static size_t pair_index(const HostOp& h, int32_t a, int32_t b) {
+  const int nf = (int)h.faults.size();
+  const bool img = b >= nf;
+  const int bb = img ? b - nf : b;
+  if (a < 0 || a >= nf || bb < 0 || bb >= nf || (a == bb && !img) || (img && h.images.empty()))
+    throw Error(SEAS_ERR_INVALID_ARG, "bad pair");
+  for (size_t pi = 0; pi < h.pairs.size(); ++pi)
+    if (h.pairs[pi].a == a && h.pairs[pi].b == bb && h.pairs[pi].img == (img ? 1 : 0)) return pi;
+  throw Error(SEAS_ERR_INTERNAL, "pair not found");
+}
+
+seas_status seas_operator_pair_window(const seas_op_t* op, int32_t a, int32_t b, int32_t* T_init, int32_t* T_end) {
+  return guard([&] {
+    if (!op || !T_init || !T_end) throw Error(SEAS_ERR_INVALID_ARG, "null argument");
+    const PairWin& w = op->h.pairs[pair_index(op->h, a, b)];
+    *T_init = w.T_init;
+    *T_end = w.T_end;
   });
 }
 
@@ -863,12 +891,7 @@ seas_status seas_operator_blocks(const seas_op_t* op, int32_t a, int32_t b, int3
   return guard([&] {
     if (!op || !count) throw Error(SEAS_ERR_INVALID_ARG, "null argument");
     const HostOp& h = op->h;
-    const int nf = (int)h.faults.size();
-    if (a < 0 || b < 0 || a >= nf || b >= nf || a == b) throw Error(SEAS_ERR_INVALID_ARG, "bad pair");
-    size_t pi = 0;
-    for (; pi < h.pairs.size(); ++pi)
-      if (h.pairs[pi].a == a && h.pairs[pi].b == b) break;
-    const auto& bl = h.blocks[pi];
+    const auto& bl = h.blocks[pair_index(h, a, b)];
     if (blocks) {
       if (*count < (int64_t)bl.size()) throw Error(SEAS_ERR_INVALID_ARG, "block buffer too small");
       for (size_t i = 0; i < bl.size(); ++i) {

@@ -521,7 +521,11 @@ static void pack_seg(int r0, int r1, int s0, int s1, const Fault& A, const Fault
 static void build_subblock(const HostOp& op, const BlockDesc& bd, const PairWin& pw, int s0, int s1,
                            BlockOut& out) {
   const Fault& A = op.faults[bd.a];
-  const Fault& B = op.faults[bd.b];
+  const Fault& B = pw.img ? op.images[bd.b] : op.faults[bd.b];
+  // an image element carries the opposite slip of its original relative to its own
+  // normal (the mirrored normal, negated to keep the element order), so its kernel
+  // enters with sign -1
+  const double sgn = pw.img ? -1.0 : 1.0;
   const int p = bd.r1 - bd.r0, q = s1 - s0;
   const double cs = op.prm.cs, dt = op.dt;
   const int S = op.time_block;
@@ -554,7 +558,7 @@ static void build_subblock(const HostOp& op, const BlockDesc& bd, const PairWin&
       const double* r1e = &re[(size_t)i * qe];
       for (int e = 0; e < qe; ++e) C[e] = corner(r1e[e], r2i[i], ct, fr.n1, fr.n2);
       double* g = &G[(size_t)i * q];
-      for (int j = 0; j < q; ++j) g[j] = C[j] - C[j + 1];
+      for (int j = 0; j < q; ++j) g[j] = sgn * (C[j] - C[j + 1]);
     }
   };
   std::vector<double> G0((size_t)p * q), G1((size_t)p * q), K((size_t)p * q), U, W, R;
@@ -593,7 +597,7 @@ static void build_subblock(const HostOp& op, const BlockDesc& bd, const PairWin&
     // common -eta factor of the evaluation restores it
     for (int i = 0; i < p; ++i)
       for (int j = 0; j < q; ++j)
-        K[(size_t)i * q + j] = -static_stress(A, bd.r0 + i, B, s0 + j, op.prm.mu) / op.eta;
+        K[(size_t)i * q + j] = -sgn * static_stress(A, bd.r0 + i, B, s0 + j, op.prm.mu) / op.eta;
     compress(-1);
     toff = bd.tail_base - bd.s0;  // accumulator of source column s0 + j is toff + s0 + j
   }
@@ -734,14 +738,40 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
   op.dt = prm.beta * dxmin / prm.cs;
   op.eta = prm.mu / (2.0 * prm.cs);
   check_geometry(op.faults);
+  op.images.clear();
+  if (prm.free_surface != 0 && prm.free_surface != 1)
+    throw Error(SEAS_ERR_INVALID_ARG, "free_surface must be 0 or 1");
+  if (prm.free_surface) {
+    if (!std::isfinite(prm.surface_y)) throw Error(SEAS_ERR_INVALID_ARG, "surface_y must be finite");
+    const double y0 = prm.surface_y;
+    for (const Fault& f : op.faults) {
+      const double tol = 1e-9 * f.L;
+      for (int e = 0; e < 2; ++e)
+        if (f.cy + (e == 0 ? -0.5 : 0.5) * f.L * f.ty > y0 + tol)
+          throw Error(SEAS_ERR_INVALID_ARG, "a fault reaches above the free surface");
+      for (int i = 0; i < f.Np; ++i)
+        if (!(f.midy(i) < y0 - tol)) throw Error(SEAS_ERR_INVALID_ARG, "a collocation point lies on the free surface");
+      // mirror across y = y0; the normal (nx, -ny) negated keeps the tangent the mirror
+      // of the original's, so element j of the image is the mirror of element j
+      Fault g = f;
+      g.cy = 2.0 * y0 - f.cy;
+      g.nx = -f.nx;
+      g.ny = f.ny;
+      g.tx = -g.ny;
+      g.ty = g.nx;
+      op.images.push_back(g);
+    }
+  }
   const double cs = prm.cs, dt = op.dt;
   // ---- causality windows (Section 2.3.2, "Truncation of elastodynamic time-window")
   op.pairs.clear();
   op.max_lag = 0;
+  // real pairs (a != b) first, then (free surface) every receiver with every image
+  for (int img = 0; img < (prm.free_surface ? 2 : 1); ++img)
   for (int a = 0; a < nf; ++a)
     for (int b = 0; b < nf; ++b) {
-      if (a == b) continue;
-      const Fault &A = op.faults[a], &B = op.faults[b];
+      if (a == b && !img) continue;
+      const Fault &A = op.faults[a], &B = img ? op.images[b] : op.faults[b];
       double earl = 1e300, dmax = 0.0;
       for (int i = 0; i < A.Np; ++i)
         for (int j = 0; j < B.Np; ++j) {
@@ -761,13 +791,15 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
       w.b = b;
       w.T_init = (int)std::floor((1.0 - prm.eta_tmin) * earl / dt);
       w.T_end = (int)std::ceil((1.0 + prm.eta_tmax) * dmax / cs / dt);
+      w.img = img;
       op.pairs.push_back(w);
       op.max_lag = std::max(op.max_lag, w.T_end);
     }
   op.ring_len = op.max_lag + 3;
   // ---- partition
-  std::vector<std::vector<Node>> trees(nf);
+  std::vector<std::vector<Node>> trees(nf), itrees(op.images.size());
   for (int k = 0; k < nf; ++k) build_tree(op.faults[k], prm.leaf, trees[k]);
+  for (size_t k = 0; k < op.images.size(); ++k) build_tree(op.images[k], prm.leaf, itrees[k]);
   op.blocks.assign(op.pairs.size(), {});
   std::vector<BlockDesc> all;
   // tail accumulators: one per (pair, source element), or per (block, source
@@ -776,10 +808,10 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
   op.tail_len = 0;
   for (size_t pi = 0; pi < op.pairs.size(); ++pi) {
     const PairWin& w = op.pairs[pi];
-    traverse(trees[w.a], trees[w.b], prm.eta_H, (int)pi, w.a, w.b, op.blocks[pi]);
+    traverse(trees[w.a], w.img ? itrees[w.b] : trees[w.b], prm.eta_H, (int)pi, w.a, w.b, op.blocks[pi]);
     op.tail_off[pi] = (int32_t)op.tail_len;
     if (!prm.cluster_windows) op.tail_len += op.faults[w.b].Np;
-    const Fault &A = op.faults[w.a], &B = op.faults[w.b];
+    const Fault &A = op.faults[w.a], &B = w.img ? op.images[w.b] : op.faults[w.b];
     for (BlockDesc& bd : op.blocks[pi]) {
       bd.T_end = w.T_end;
       bd.tail_base = op.tail_off[pi] + bd.s0;
@@ -825,10 +857,11 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
     std::vector<std::vector<std::pair<int, double>>> rows(op.N);
     for (const PairWin& w : op.pairs) {
       if (w.T_init != 0) continue;
-      const Fault &A = op.faults[w.a], &B = op.faults[w.b];
+      const Fault &A = op.faults[w.a], &B = w.img ? op.images[w.b] : op.faults[w.b];
+      const double sgn = w.img ? -1.0 : 1.0;
       for (int i = 0; i < A.Np; ++i)
         for (int j = 0; j < B.Np; ++j) {
-          const double k0 = kernel_entry(A, i, B, j, 0, dt, cs);
+          const double k0 = sgn * kernel_entry(A, i, B, j, 0, dt, cs);
           if (k0 != 0.0) rows[A.off + i].push_back({B.off + j, k0});
         }
     }

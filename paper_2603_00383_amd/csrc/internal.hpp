@@ -93,6 +93,7 @@ inline int seg_ld(int q8, int eb) {
 // ---------------------------------------------------------------- host operator
 struct PairWin {
   int a, b, T_init, T_end;
+  int img = 0;  // 1: the source is the mirror image of fault b (free surface); its kernel enters with sign -1
 };
 
 struct BlockDesc {
@@ -113,6 +114,9 @@ struct SelfFault {          // self-term tables of one fault
 struct HostOp {
   seas_params_t prm;
   std::vector<Fault> faults;
+  // free surface: the mirror image of each fault across the surface line, its
+  // elements in the order of the original's (same offsets into the rate history)
+  std::vector<Fault> images;
   int N = 0;
   double dt = 0, eta = 0;
   std::vector<PairWin> pairs;

@@ -30,6 +30,18 @@ def fault(cx, cy, strike_deg, length, n_elem):
                 length=float(length), n_elem=int(n_elem))
 
 
+def free_surface_network(n_elem=32, dx=50.0, y0=0.0):
+    """Two faults below a traction-free line y = y0: a vertical one whose upper end
+    touches the line (the BP1-FD geometry of the paper's appendix, shortened) and a
+    buried one dipping 30 degrees whose upper end sits 200 m below the line."""
+    L = n_elem * dx
+    f1 = fault(0.0, y0 - 0.5 * L, 90.0, L, n_elem)
+    phi = math.radians(30.0)
+    top = (700.0, y0 - 200.0)
+    f2 = fault(top[0] + 0.5 * L * math.cos(phi), top[1] - 0.5 * L * math.sin(phi), -30.0, L, n_elem)
+    return [f1, f2]
+
+
 def fault_nodes(f):
     """Element end points of a fault, shape (n_elem+1, 2) (input validation only)."""
     tx, ty = -f["ny"], f["nx"]

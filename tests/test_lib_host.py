@@ -270,3 +270,42 @@ def test_cluster_windows_match_oracle(dtype, S):
             # (FP64: rounding of late-lag entries, differences of two time levels)
             assert np.linalg.norm(R - K) / nrm < (1e-11 if dtype == "f64" else 1e-6), (a, b, T)
     assert shortened > 0
+
+
+def test_free_surface_image_pairs_match_oracle():
+    # method of images: the library's pairs (a, image of b) take the oracle's windows
+    # and partition of the receiver fault against the mirrored source fault
+    y0 = 0.0
+    faults = SI.free_surface_network(n_elem=32, y0=y0)
+    op = _op(faults, free_surface=1, surface_y=y0, eta_H=2.0, leaf=8)
+    geo = geometry.discretize(faults + geometry.mirror_images(faults, y0))
+    dt = op.info["dt"]
+    blocks = HP.partition(geo, 2.0, 8)
+    nf = len(faults)
+    for a in range(nf):
+        for b in range(nf):
+            t = op.pair_window(a, nf + b)
+            assert t == I.pair_window_lags(geo, a, nf + b, SI.CS, dt, 0.01, 0.01), (a, b)
+            assert op.blocks(a, nf + b) == blocks[(a, nf + b)]
+    assert op.pair_window(0, nf + 0)[0] == 0            # the surface fault touches its image
+    with pytest.raises(P.SeasError):
+        _op(faults, free_surface=1, surface_y=-200.0)  # a fault reaching above the surface
+
+
+def test_free_surface_own_image_matrices_match_oracle():
+    # the stored kernel of a surface-reaching fault with its own image, lag by lag and
+    # its static tail, against the oracle's mirrored pair (sign -1 included)
+    y0 = 0.0
+    f1 = SI.free_surface_network(n_elem=24, y0=y0)[0]
+    op = _op([f1], free_surface=1, surface_y=y0, compress=0, factor_dtype="f64")
+    dt = op.info["dt"]
+    geo = geometry.discretize([f1] + geometry.mirror_images([f1], y0))
+    T0, T1 = op.pair_window(0, 1)
+    assert T0 == 0
+    for T in sorted({0, 1, 2, 7, T1 // 2, T1}):
+        got = op.lag_matrix(0, 1, T, 24, 24)
+        ref = -I.pair_kernel(geo, 0, 1, T, dt, SI.CS)
+        assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max(), T
+    tail = op.lag_matrix(0, 1, -1, 24, 24)
+    G = -I.static_dipole(geo, 0, 1, SI.MU)
+    assert np.allclose(tail, -G / (SI.MU / (2 * SI.CS)), rtol=1e-12, atol=0)
