@@ -61,7 +61,8 @@ class Problem:
             if key not in cache:
                 cache[key] = selfterm.SelfTerm(f.Np, f.L, self.mu, self.cs, self.dt,
                                                float(p.get("eta_w", 1.5)), int(p.get("q_w", 0)),
-                                               int(p.get("mode_cap", 0)), use_c=use_c)
+                                               int(p.get("mode_cap", 0)), use_c=use_c,
+                                               tail=bool(int(p.get("self_tail", 0))))
             self.selfs.append(cache[key])
 
     # ------------------------------------------------------------------ helpers
@@ -251,8 +252,7 @@ def prescribed_rows(prob, V_all, first, n, rows, delta0=None):
     faults_needed = sorted({int(np.searchsorted(prob.off, r, side="right") - 1) for r in rows})
     for k in faults_needed:
         st = prob.selfs[k]
-        Wmax = int(st.W.max())
-        lo = max(first, n - Wmax)
+        lo = max(first, n - st.reach)
         Dh = st.dft(delta[lo - first:n - first + 1, prob.off[k]:prob.off[k + 1]])
         fs = st.stress(Dh, n, lo)
         for idx, r in enumerate(rows):

@@ -14,7 +14,17 @@ Section 2.3.1 of the paper, followed step by step:
 * mode-dependent windows T_end(n) = T_end(1) L(n), T_end(1) = eta_w L / cs
   (eq. "mode_dependent_truncation");
 * the transforms are explicit sums (no FFT): D_n = sum_j delta_j e^{-2 pi i n j / M},
-  n = 0..N_p, and the inverse keeps the real part of the Hermitian sum.
+  n = 0..N_p, and the inverse keeps the real part of the Hermitian sum;
+* optional static tail of the truncated kernel (reading C2 of the scope table, not
+  in the paper): the window drops the part of K(n, .) beyond the cell of lag W_n,
+  which carries static response; with ``tail=True`` each mode adds
+  R_n D_n^{t-W_n-1}, R_n = |k_n| times the integral of K(n, .) over
+  t >= (W_n + 1/2) dt, i.e. slip older than the window responds with the rest
+  of the kernel. The full integral is finite (K decays as t^-3 for integer n),
+  and with it a slip held long enough gives the static stress of the fault.
+  Pins: that static limit against the element-wise static stress (second order
+  in the element size), R_n against the cell integrals it continues and against
+  the kernel's large-time expansion (tests/test_oracle_selftail.py).
 """
 from __future__ import annotations
 
@@ -82,6 +92,50 @@ def K_cells_numpy(n, W, dt, L, cs):
     return out
 
 
+def _K_early_integral(n, t0, t1, L, cs):
+    """Integral of K(n, t) over [t0, t1] inside t <= L/cs (Gauss-Legendre panels,
+    about two per oscillation of K)."""
+    if t1 <= t0:
+        return 0.0
+    gx, gw = _gl(20)
+    edges = np.linspace(t0, t1, n + 5)
+    s = 0.0
+    for a, b in zip(edges[:-1], edges[1:]):
+        h = b - a
+        s += np.sum(0.5 * h * gw * K_mode(n, 0.5 * (a + b) + 0.5 * h * gx, L, cs))
+    return s
+
+
+def _K_late_integral(n, t1, L, cs):
+    """Integral of K(n, t) over t >= t1 >= L/cs. With t = L / (cs sin phi), the
+    late branch of the definition reads K = (2/pi) int_0^phi cos^2 psi
+    cos((n pi / sin phi) sin psi) dpsi and dt = (L/cs) cos phi / sin^2 phi dphi;
+    K ~ t^-3 makes the integrand vanish like sin phi at phi = 0, so the infinite
+    range becomes the finite, smooth phi in (0, asin(L / (cs t1))]."""
+    gx, gw = _gl(20)
+    phi1 = math.asin(min(1.0, L / (cs * t1)))
+    edges = np.linspace(0.0, phi1, n + 9)
+    h = edges[1] - edges[0]
+    phi = ((0.5 * (edges[:-1] + edges[1:]))[:, None] + 0.5 * h * gx[None, :]).ravel()
+    wphi = np.tile(0.5 * h * gw, len(edges) - 1)
+    # inner psi-integral for every phi at once: psi = phi * u, u in [0, 1]
+    ip = n // 2 + 4
+    ue = np.linspace(0.0, 1.0, ip + 1)
+    uh = ue[1] - ue[0]
+    u = ((0.5 * (ue[:-1] + ue[1:]))[:, None] + 0.5 * uh * gx[None, :]).ravel()
+    wu = np.tile(0.5 * uh * gw, ip)
+    psi = phi[:, None] * u[None, :]
+    x = n * math.pi / np.sin(phi)
+    K = 2.0 / math.pi * phi * ((np.cos(psi) ** 2 * np.cos(x[:, None] * np.sin(psi))) @ wu)
+    return (L / cs) * float(np.sum(wphi * K * np.cos(phi) / np.sin(phi) ** 2))
+
+
+def K_tail_integral(n, t0, L, cs):
+    """Integral of K(n, t) over t >= t0 (the part a window ending at t0 drops)."""
+    tl = L / cs
+    return _K_early_integral(n, t0, tl, L, cs) + _K_late_integral(n, max(t0, tl), L, cs)
+
+
 def _lib():
     global _LIB
     if _LIB is None:
@@ -138,7 +192,7 @@ def default_qw(Np):
 class SelfTerm:
     """Self-term tables of one fault: windows W_n and K_n^T for n = 1..N_p."""
 
-    def __init__(self, Np, L, mu, cs, dt, eta_w=1.5, q_w=0, mode_cap=0, use_c=True):
+    def __init__(self, Np, L, mu, cs, dt, eta_w=1.5, q_w=0, mode_cap=0, use_c=True, tail=False):
         self.Np, self.L, self.mu, self.cs, self.dt = Np, L, mu, cs, dt
         self.M = 2 * Np
         q = q_w if q_w > 0 else default_qw(Np)
@@ -162,6 +216,14 @@ class SelfTerm:
         for i in range(len(self.modes)):
             flat[offs[i]:offs[i + 1]] *= self.k[i]
         self.flat = flat
+        # static tail of each mode: R_n = |k_n| int_{(W_n + 1/2) dt}^inf K(n, t) dt
+        self.tail = bool(tail)
+        self.R = np.zeros(len(self.modes))
+        if self.tail:
+            for i, n in enumerate(self.modes):
+                self.R[i] = self.k[i] * K_tail_integral(int(n), (self.W[i] + 0.5) * dt, L, cs)
+        # oldest lag whose coefficients the stress reads
+        self.reach = int(self.W.max()) + (1 if self.tail else 0) if len(self.W) else 0
 
     def table(self, i):
         return self.flat[self.offs[i]:self.offs[i + 1]]
@@ -188,11 +250,12 @@ class SelfTerm:
 
     # ---------------------------------------------------------------- stress
     def modal_stress(self, Dh, t, first, D_now=None):
-        """F_n = -(mu cs |k_n| / 2) sum_{T=0}^{W_n} K_n^T D_n^{t-T}.
+        """F_n = -(mu cs |k_n| / 2) (sum_{T=0}^{W_n} K_n^T D_n^{t-T} [+ R_n D_n^{t-W_n-1}]).
 
         ``Dh[m - first]`` holds D^m (length N_p+1) for m >= first; earlier
         coefficients are zero (no slip history).  When ``D_now`` is given it is
-        used as D^t (the T = 0 term) instead of the stored row."""
+        used as D^t (the T = 0 term) instead of the stored row. The bracketed
+        static tail is added when the table was built with ``tail=True``."""
         F = np.zeros(self.Np + 1, dtype=complex)
         for i, n in enumerate(self.modes):
             Kt = self.table(i)
@@ -205,6 +268,8 @@ class SelfTerm:
             s = np.dot(Kt[ok], vals)
             if D_now is not None:
                 s = s + Kt[0] * D_now[n]
+            if self.tail and t - W - 1 >= first:
+                s = s + self.R[i] * Dh[t - W - 1 - first, n]
             F[n] = -(self.mu * self.cs * self.k[i] / 2.0) * s
         return F
 
