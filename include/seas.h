@@ -144,6 +144,13 @@ typedef struct {
                            image. Faults must lie below the line (end points may touch it). */
   int32_t reserved_fs;
   double surface_y;
+  int32_t self_tail;    /* 0: the self term of eq. "funcational_discretized_form" as printed, each
+                           mode's kernel cut after the cell of lag W_n; 1: slip older than the
+                           window responds with the rest of the kernel, R_n D_n^{t-W_n-1},
+                           R_n = |k_n| int over t >= (W_n + 1/2) dt of K(n, t) (the static tail
+                           the cut drops; with it a slip held longer than the windows gives the
+                           fault's static stress). Not in the paper: an optional correction */
+  int32_t reserved_st;
 } seas_params_t;
 
 typedef struct seas_op seas_op_t;
@@ -176,13 +183,14 @@ typedef struct {
   int32_t n_faults, n_elem;   /* faults, total elements N */
   double dt;                  /* time step [s] */
   int32_t max_lag;            /* largest interaction lag T_end over pairs */
-  int32_t max_self_window;    /* largest self window W_n over faults and modes */
+  int32_t max_self_window;    /* largest self window W_n over faults and modes (W_n + 1 with
+                                 self_tail: the oldest lag the self term reads) */
   int64_t n_blocks;           /* H-matrix blocks over all ordered pairs */
   int64_t n_items;            /* work items applied once per time block */
   int64_t dense_entries;      /* entries of the uncompressed kernel in the pair windows */
   int64_t stored_entries;     /* stored factor entries (low rank + dense), lags >= 1 and tail */
   int64_t lag0_nnz;           /* nonzeros of the lag-0 interaction (pairs with T_init = 0) */
-  int64_t self_entries;       /* sum over faults and modes of (W_n + 1) */
+  int64_t self_entries;       /* sum over faults and modes of (W_n + 1), + 1 each with self_tail */
   double bytes_per_step;      /* algorithmic HBM bytes of one stress evaluation */
   double flops_per_step;      /* 2 x stored entries + self term MACs */
   double build_seconds;
@@ -226,7 +234,9 @@ seas_status seas_operator_blocks(const seas_op_t* op, int32_t a, int32_t b,
                                  int32_t* blocks, int64_t* count);
 
 /* Self-kernel table K_n^T of fault k, mode n (1..), T = 0..W_n, and W_n.
- * Host copy of the values the device uses. */
+ * Host copy of the values the device uses. With self_tail = 1 the table has one
+ * more entry, out[W_n + 1] = R_n (the tail coefficient applied to D_n^{t-W_n-1});
+ * capacity must then be at least W_n + 2. */
 seas_status seas_operator_self_table(const seas_op_t* op, int32_t k, int32_t n,
                                      double* out, int32_t capacity, int32_t* W_n);
 

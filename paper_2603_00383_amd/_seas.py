@@ -42,7 +42,7 @@ class Params(C.Structure):
                 ("time_block", C.c_int32), ("n_variants", C.c_int32), ("state_update", C.c_int32),
                 ("cluster_windows", C.c_int32), ("adaptive_dt", C.c_int32), ("gamma_max", C.c_int32),
                 ("adapt_xi", C.c_double), ("free_surface", C.c_int32), ("reserved_fs", C.c_int32),
-                ("surface_y", C.c_double)]
+                ("surface_y", C.c_double), ("self_tail", C.c_int32), ("reserved_st", C.c_int32)]
 
 
 class OpInfo(C.Structure):
@@ -177,6 +177,7 @@ def make_params(p):
     q.adapt_xi = float(p.get("adapt_xi", 0.0))
     q.free_surface = int(p.get("free_surface", 0))
     q.surface_y = float(p.get("surface_y", 0.0))
+    q.self_tail = int(p.get("self_tail", 0))
     return q
 
 
@@ -233,11 +234,13 @@ class Operator:
         return [int(x) for x in np.frombuffer(buf, dtype=np.int32).reshape(-1, 6)[:, 5]]
 
     def self_table(self, k, n):
+        """K_n^T, T = 0..W_n, and with self_tail the tail coefficient R_n last."""
         W = C.c_int32(0)
         _check(lib().seas_operator_self_table(self.h, k, n, None, 0, C.byref(W)))
-        out = np.zeros(W.value + 1)
+        m = W.value + 1 + int(self._prm.self_tail)
+        out = np.zeros(m)
         _check(lib().seas_operator_self_table(self.h, k, n, out.ctypes.data_as(C.POINTER(C.c_double)),
-                                              W.value + 1, C.byref(W)))
+                                              m, C.byref(W)))
         return out
 
     def lag_matrix(self, a, b, T, p, q):

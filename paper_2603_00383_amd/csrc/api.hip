@@ -668,7 +668,7 @@ seas_status seas_build_operator(const seas_fault_t* faults, int32_t n_faults, co
         SelfMode m;
         m.fault = (int)k;
         m.n = n;
-        m.W = s.W[n - 1];
+        m.W = s.W[n - 1] + s.tail;  // the static tail is one more lag of the ring
         m.pad = 0;
         m.tab = s.tab_off[n - 1];
         m.ring = s.ring_off[n - 1];
@@ -916,8 +916,9 @@ seas_status seas_operator_self_table(const seas_op_t* op, int32_t k, int32_t n, 
     const SelfFault& s = h.self[k];
     *W_n = s.W[n - 1];
     if (out) {
-      if (capacity < s.W[n - 1] + 1) throw Error(SEAS_ERR_INVALID_ARG, "capacity too small");
-      std::memcpy(out, &h.self_tab[s.tab_off[n - 1]], sizeof(double) * (s.W[n - 1] + 1));
+      const int len = s.W[n - 1] + 1 + s.tail;
+      if (capacity < len) throw Error(SEAS_ERR_INVALID_ARG, "capacity too small");
+      std::memcpy(out, &h.self_tab[s.tab_off[n - 1]], sizeof(double) * len);
     }
   });
 }

@@ -155,6 +155,63 @@ void self_cells(int n, int W, double dt, double L, double cs, double* out) {
   }
 }
 
+// Integral of K(n, t) over t >= t0: the static tail a window ending at t0 drops.
+// Over [t0, tb], tb = 64 max(t0, L/cs), the exchanged order of self_cells: the
+// full piece psi in [0, psi_b] (sin psi_b = L/(cs tb)) integrates cos(a s t) over
+// the whole range, the cut piece psi in [psi_b, psi_0] up to t = L/(cs s). The
+// oscillation in psi is at most n pi there, whatever tb is. Beyond tb, the late
+// branch K = (2/pi) int_0^{s0} sqrt(1 - s^2) cos(a t s) ds (s0 = L/(cs t),
+// a t s0 = n pi) expands in powers of 1/(a t): K = (2/pi) sum_m c_m J_m
+// (a t)^-(2m+1), c_m the coefficients of sqrt(1 - y), J_m = int_0^{n pi} u^{2m}
+// cos u du (J_0 = 0), and each term integrates in closed form; the ratio of
+// successive terms is about (L/(cs tb))^2 = 1/4096.
+double self_tail_integral(int n, double t0, double L, double cs) {
+  static const GL g(16);
+  const double a = n * M_PI * cs / L;
+  const double tl = L / cs;
+  const double tb = 64.0 * std::max(t0, tl);
+  auto piece = [&](double lo, double hi, int panels, const std::function<double(double)>& f) {
+    if (hi <= lo) return 0.0;
+    const double h = (hi - lo) / panels;
+    double acc = 0.0;
+    for (int p = 0; p < panels; ++p) {
+      const double m = lo + (p + 0.5) * h;
+      double q = 0.0;
+      for (size_t k = 0; k < g.x.size(); ++k) q += g.w[k] * f(m + 0.5 * h * g.x[k]);
+      acc += 0.5 * h * q;
+    }
+    return acc;
+  };
+  const double psib = std::asin(L / (cs * tb));
+  const double psi0 = t0 <= tl ? 0.5 * M_PI : std::asin(L / (cs * t0));
+  const int pan = 8 + 2 * n;
+  // int_t0^tb cos(a s t) dt = (sin(a s tb) - sin(a s t0)) / (a s)
+  const double full = piece(0.0, psib, pan, [&](double psi) {
+    const double s = std::sin(psi), c = std::cos(psi);
+    const double as = a * s;
+    const double v = as * tb < 1e-6 ? tb - t0 : (std::sin(as * tb) - std::sin(as * t0)) / as;
+    return c * c * v;
+  });
+  // int_t0^{L/(cs s)} cos(a s t) dt = (sin(n pi) - sin(a s t0)) / (a s), sin(n pi) = 0
+  const double cut = piece(psib, psi0, pan, [&](double psi) {
+    const double s = std::sin(psi), c = std::cos(psi);
+    return -c * c * std::sin(a * s * t0) / (a * s);
+  });
+  // closed-form terms past tb: int_tb^inf (a t)^-(2m+1) dt = 1 / (2m a^(2m+1) tb^(2m))
+  const double X = n * M_PI, cosX = (n & 1) ? -1.0 : 1.0;
+  double C[10], S[10];  // int_0^X u^k cos u du and int_0^X u^k sin u du (sin X = 0)
+  C[0] = 0.0;
+  S[0] = 1.0 - cosX;
+  for (int k = 1; k < 10; ++k) {
+    C[k] = -k * S[k - 1];
+    S[k] = -std::pow(X, k) * cosX + k * C[k - 1];
+  }
+  const double cm[5] = {1.0, -0.5, -0.125, -0.0625, -5.0 / 128.0};
+  double far = 0.0;
+  for (int m = 1; m <= 4; ++m) far += cm[m] * C[2 * m] / (2.0 * m * std::pow(a, 2 * m + 1) * std::pow(tb, 2 * m));
+  return 2.0 / M_PI * (full + cut + far);
+}
+
 // ============================================================== partition
 struct Node {
   int lo, hi, kid0 = -1, kid1 = -1;
@@ -741,6 +798,7 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
   op.images.clear();
   if (prm.free_surface != 0 && prm.free_surface != 1)
     throw Error(SEAS_ERR_INVALID_ARG, "free_surface must be 0 or 1");
+  if (prm.self_tail != 0 && prm.self_tail != 1) throw Error(SEAS_ERR_INVALID_ARG, "self_tail must be 0 or 1");
   if (prm.free_surface) {
     if (!std::isfinite(prm.surface_y)) throw Error(SEAS_ERR_INVALID_ARG, "surface_y must be finite");
     const double y0 = prm.surface_y;
@@ -1175,17 +1233,19 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
     sf.cfac = prm.mu * prm.cs * M_PI / (2.0 * f.L);
     const int qw = prm.q_w > 0 ? prm.q_w : (int)std::lround(f.Np / 5.0);
     sf.W.resize(sf.nm);
+    sf.tail = prm.self_tail;
     for (int n = 1; n <= sf.nm; ++n) {
       double Ln = 1.0;
       if (f.Np / 2.0 - 1.0 > 0.0) Ln = 1.0 / n + (qw - 1.0) / (f.Np / 2.0 - 1.0) * (1.0 - 1.0 / n);
       sf.W[n - 1] = (int)std::floor(prm.eta_w * (f.L / prm.cs) * Ln / dt * (1.0 + 1e-12));
-      op.max_self_W = std::max(op.max_self_W, sf.W[n - 1]);
-      op.self_entries += sf.W[n - 1] + 1;
+      // the tail is one more lag, W_n + 1, whose coefficient is R_n
+      op.max_self_W = std::max(op.max_self_W, sf.W[n - 1] + sf.tail);
+      op.self_entries += sf.W[n - 1] + 1 + sf.tail;
     }
     sf.ring_off.resize(sf.nm);
     for (int n = 0; n < sf.nm; ++n) {
       sf.ring_off[n] = op.self_ring_len;
-      op.self_ring_len += sf.W[n];
+      op.self_ring_len += sf.W[n] + sf.tail;
     }
     size_t reuse = SIZE_MAX;
     for (auto& s : seen)
@@ -1197,15 +1257,17 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
       int64_t base = (int64_t)op.self_tab.size();
       for (int n = 0; n < sf.nm; ++n) {
         sf.tab_off[n] = base;
-        base += sf.W[n] + 1;
+        base += sf.W[n] + 1 + sf.tail;
       }
       op.self_tab.resize(base);
 #pragma omp parallel for schedule(dynamic, 1)
       for (int n = 1; n <= sf.nm; ++n) {
         double* o = &op.self_tab[sf.tab_off[n - 1]];
-        self_cells(n, sf.W[n - 1], dt, f.L, prm.cs, o);
+        const int W = sf.W[n - 1];
+        self_cells(n, W, dt, f.L, prm.cs, o);
+        if (sf.tail) o[W + 1] = self_tail_integral(n, (W + 0.5) * dt, f.L, prm.cs);
         const double kn = M_PI * n / f.L;
-        for (int T = 0; T <= sf.W[n - 1]; ++T) o[T] *= kn;
+        for (int T = 0; T <= W + sf.tail; ++T) o[T] *= kn;
       }
       seen.push_back({{f.Np, f.L}, op.self.size()});
     }

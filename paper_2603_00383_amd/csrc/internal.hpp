@@ -106,8 +106,9 @@ struct SelfFault {          // self-term tables of one fault
   int Np, M, nm;            // elements, padded length, retained modes
   int mode_off;             // global offset of this fault's modes (1..nm)
   std::vector<int> W;       // W_n, n = 1..nm
-  std::vector<int64_t> tab_off;   // offset of K_n^T (T = 0..W_n) in the table
-  std::vector<int64_t> ring_off;  // offset of the D ring of mode n (length W_n)
+  int tail = 0;             // 1: the table's entry W_n + 1 is the static tail R_n
+  std::vector<int64_t> tab_off;   // offset of K_n^T (T = 0..W_n + tail) in the table
+  std::vector<int64_t> ring_off;  // offset of the D ring of mode n (length W_n + tail)
   double cfac;              // mu cs pi / (2 L): F_n = -cfac * n * sum K_n^T D
 };
 

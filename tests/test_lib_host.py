@@ -68,6 +68,27 @@ def test_self_tables_match_oracle():
     assert worst < 1e-12
 
 
+def test_self_tail_matches_oracle():
+    # the library's tail (exchanged order to 64 max(t0, L/cs), closed-form terms past
+    # it) against the oracle's (substitution t = L/(cs sin phi)); the cells unchanged
+    faults = SI.two_fault_prescribed_faults(n_elem=48, dx=100.0)
+    op = _op(faults, self_tail=1)
+    op0 = _op(faults)
+    geo = geometry.discretize(faults)
+    dt = geometry.time_step(geo, SI.CS)
+    st = S.SelfTerm(48, 4800.0, SI.MU, SI.CS, dt, tail=True)
+    assert op.info["max_self_window"] == op0.info["max_self_window"] + 1
+    for n in (1, 2, 3, 10, 24, 47, 48):
+        lt, l0 = op.self_table(0, n), op0.self_table(0, n)
+        W = int(st.W[n - 1])
+        assert len(lt) == W + 2 and len(l0) == W + 1
+        assert np.array_equal(lt[:W + 1], l0)
+        # both quadratures reach ~1e-15 absolute (the late-time integrand cancels); that
+        # is ~1e-10 of the smallest R_n and ~1e-13 of the mode's whole kernel
+        assert abs(lt[W + 1] - st.R[n - 1]) <= 1e-11 * np.abs(l0).sum()
+        assert abs(lt[W + 1]) > 1e-3 * np.abs(l0).sum()
+
+
 @pytest.mark.parametrize("compress,S,dtype", [(0, 1, "f64"), (1, 1, "f64"), (1, 4, "f64"), (0, 16, "f64"),
                                               (0, 16, "f32"), (1, 16, "f32")])
 def test_lag_matrices_match_dense_kernel(compress, S, dtype):
