@@ -65,6 +65,44 @@ MEASURED_TRAFFIC = {
 }
 
 
+def graph_leg(n_steps=640):
+    """SEAS steps of a small network (two 12.8 km faults x 128 elements, FP64, ACA
+    1e-12, time block 16), plain launches against graph replays of whole blocks
+    (seas_state_set_graph), from the same state; the results are identical."""
+    import numpy as np
+    import torch
+    import paper_2603_00383_amd as P
+    import seas_inputs as SI
+    s = torch.cuda.current_stream().cuda_stream
+    faults = SI.two_fault_prescribed_faults()
+    op = P.Operator(faults, SI.default_params(factor_dtype="f64", aca_tol=1e-12, time_block=16,
+                                              state_update="exact"))
+    fric = SI.rate_state_fields(faults)
+    ini = SI.near_nucleation_state(faults, fric, seed=0, V_init=1e-9, bump_amp=0.05)
+    res = {}
+    fields = {}
+    for mode in ("plain", "graph"):
+        st = P.State(op, fric, ini["V"], ini["theta"], ini["tau0"], stream=s)
+        st.set_graph(mode == "graph")
+        st.step(32, stream=s)                       # warm-up (captures the graph)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        st.step(n_steps, stream=s)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        st.check(stream=s)
+        fields[mode] = st.read("V", stream=s)
+        res[mode] = {"ms_per_step": wall / n_steps * 1e3, "value": op.N * n_steps / wall}
+        if mode == "graph":
+            res[mode].update(st.graph_info())
+        st.close()
+    op.close()
+    return {"workload": "SEAS steps, two faults x 128 elements (N=256), FP64, ACA 1e-12, time block 16, "
+                        f"{n_steps} steps after 32", "unit": "element-steps/s", **res,
+            "speedup": res["plain"]["ms_per_step"] / res["graph"]["ms_per_step"],
+            "identical": bool(np.array_equal(fields["plain"], fields["graph"]))}
+
+
 def cpu_cores():
     """Host cores the CPU legs use: the process's CPU affinity (what nproc reports),
     at most 16 (one GPU's share of the host)."""
@@ -585,6 +623,7 @@ def main():
                     help="skip the oracle CPU leg (the forms' errors are then not measured)")
     ap.add_argument("--no-serving", action="store_true", help="skip the bounded serving leg")
     ap.add_argument("--no-two-fault", action="store_true", help="skip the two-fault FP64 workload")
+    ap.add_argument("--no-graph", action="store_true", help="skip the captured-steps leg")
     ap.add_argument("--adaptive", action="store_true",
                     help="add the adaptive-step leg (two-fault benchmark, ~90 s with its operator build)")
     ap.add_argument("--adaptive-steps", type=int, default=3000, help="adaptive: steps at most")
@@ -859,6 +898,11 @@ def main():
         op1.close()
         print(f"[bench] two-fault FP64: {out['two_fault_fp64']['value']:.3e} element-steps/s, error {e1}",
               file=sys.stderr, flush=True)
+    if not args.no_graph:
+        out["captured_steps"] = graph_leg()
+        g = out["captured_steps"]
+        print(f"[bench] captured steps: {g['graph']['ms_per_step']:.4f} ms/step vs {g['plain']['ms_per_step']:.4f} "
+              f"plain ({g['speedup']:.2f}x)", file=sys.stderr, flush=True)
     if args.adaptive:
         out["adaptive"] = adaptive_leg(1000, args.adaptive_steps, args.adaptive_time)
         a = out["adaptive"]

@@ -406,6 +406,27 @@ seas_status seas_state_set_timing(seas_state_t* st, int32_t enable);
  * stream is non-blocking, so a caller's stream of any kind overlaps with it. */
 seas_status seas_state_set_overlap(seas_state_t* st, int32_t enable);
 
+/* Captured steps: with enable = 1, seas_step runs the fixed steps that fill whole
+ * time blocks (S steps; 16 steps when every step applies the far list, S = 1 or
+ * seas_state_set_time_block(1)) as replays of one HIP graph per state, captured at
+ * its first use on a stream of the state's own and launched on the caller's
+ * stream; steps before the next block start and a remainder shorter than a block
+ * run as before. Every step evaluates exactly as an uncaptured one: the captured
+ * kernels read the step base from a device word of the state that the graph
+ * itself advances, so one graph serves every block. The block lookahead and
+ * kernel timing do not apply inside a replay. The graph holds the state's and
+ * the operator's device pointers: it is recaptured when the evaluation order
+ * changes and released with the state. Graph launches remove the per-kernel
+ * launch cost of a step (about 14 kernels), which is what bounds small networks.
+ * MISMATCH for states of an adaptive operator (each step's length is chosen on
+ * the host); enable = 0 returns to plain launches. */
+seas_status seas_state_set_graph(seas_state_t* st, int32_t enable);
+
+/* Graph replays launched by seas_step since the state was created, and the steps
+ * per replay of its current graph (0 before the first capture). Either output may
+ * be NULL. */
+seas_status seas_state_graph_info(const seas_state_t* st, int64_t* replays, int32_t* steps_per_replay);
+
 /* Evaluation order of a state built with time_block S > 1: S (default) applies the
  * lags >= S once per S steps; 1 applies them every step (the plain per-step form).
  * Results agree to rounding; used to compare both forms on one operator. */

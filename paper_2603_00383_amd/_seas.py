@@ -111,6 +111,8 @@ def lib():
             "seas_state_step_index": (i64, [vp]),
             "seas_state_set_timing": (i32, [vp, i32]),
             "seas_state_set_overlap": (i32, [vp, i32]),
+            "seas_state_set_graph": (i32, [vp, i32]),
+            "seas_state_graph_info": (i32, [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
             "seas_state_progress": (i32, [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
             "seas_state_set_gamma_cap": (i32, [vp, C.c_int64]),
             "seas_state_set_time_block": (i32, [vp, i32]),
@@ -347,6 +349,15 @@ class State:
 
     def set_overlap(self, enable=True):
         _check(lib().seas_state_set_overlap(self.h, 1 if enable else 0))
+
+    def set_graph(self, enable=True):
+        """Fixed steps of whole time blocks as replays of one captured HIP graph."""
+        _check(lib().seas_state_set_graph(self.h, 1 if enable else 0))
+
+    def graph_info(self):
+        r, u = C.c_int64(0), C.c_int32(0)
+        _check(lib().seas_state_graph_info(self.h, C.byref(r), C.byref(u)))
+        return {"replays": r.value, "steps_per_replay": u.value}
 
     def read_timing(self, stream=0):
         ms, n = C.c_double(0), C.c_int64(0)

@@ -175,9 +175,21 @@ struct seas_state {
   hipStream_t la = nullptr;
   hipEvent_t ev_la_go = nullptr, ev_la_done = nullptr;
   int64_t la_head = INT64_MIN / 2;
+  // captured steps (seas_state_set_graph): one graph of g_unit steps that starts at
+  // a time-block start, captured with step times relative to 0 on the capture
+  // stream and replayed on the caller's stream; its kernels add the step base
+  // *clk, which the graph's last node advances by g_unit
+  bool graph = false, capturing = false;
+  int64_t* clk = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int g_unit = 0, g_runS = -1;
+  int64_t g_replays = 0;
   ~seas_state() {
     if (side) (void)hipStreamSynchronize(side);
     if (la) (void)hipStreamSynchronize(la);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (cap) (void)hipStreamDestroy(cap);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (ev_la_go) (void)hipEventDestroy(ev_la_go);
@@ -190,6 +202,9 @@ struct seas_state {
 };
 
 namespace {
+
+// step base of the kernels being recorded: only while a step sequence is captured
+inline const int64_t* clk_of(const seas_state* st) { return st->capturing ? st->clk : nullptr; }
 
 template <typename TF>
 StepArgs<TF> make_args(seas_op* op, seas_state* st) {
@@ -244,6 +259,7 @@ StepArgs<TF> make_args(seas_op* op, seas_state* st) {
   a.exact_state = h.prm.state_update == 1;
   a.dts = h.dt;
   a.gamma = 1;
+  a.clk = clk_of(st);
   return a;
 }
 
@@ -290,21 +306,21 @@ void launch_far(seas_op* op, seas_state* st, int64_t head, FarPart part, int Sl,
   if (h.seg) {
     range((int64_t)h.seg_ptr.size() - 1, h.first_segs, a, b);
     launch_hmat_x16(h, op->items[0], op->seg_ptr + a, (int)(b - a), op->lagT, op->lagCol, op->lagColOff[0],
-                    op->arena, st->ringop, head, st->tail_acc, (float*)pfar, s);
+                    op->arena, st->ringop, head, st->tail_acc, (float*)pfar, s, clk_of(st));
     range((int64_t)h.items[2].size(), h.first_items[2], a, b);
     launch_hmat_f32far(h, (int)(b - a), op->items[2] + a, op->lagT, op->lagCol, op->lagColOff[2] + a,
-                       op->arena_near, st->ringop, head, (float*)pfar, s);
+                       op->arena_near, st->ringop, head, (float*)pfar, s, clk_of(st));
     if (h.ens32 && part == kFarAll) {
       // BF16 ensembles keep a BF16 history copy: their FP32 list reads the FP64 history
       const bool r64 = op->ring_bytes == 2;
       launch_hmat_seg32(h, op->items[3], op->seg_ptr3, op->lagT, op->lagCol, op->lagColOff[3], op->arena32s,
                         r64 ? (const void*)st->ring64 : (const void*)st->ringop, r64, head, st->tail_acc,
-                        (float*)pfar, s);
+                        (float*)pfar, s, clk_of(st));
     }
   } else {
     range((int64_t)h.items[0].size(), h.first_items[0], a, b);
     launch_hmat(h, Sl, (int)(b - a), op->items[0] + a, op->lagT, op->lagCol, op->lagColOff[0] + a, op->arena,
-                st->ringop, head, st->tail_acc, (double*)pfar, h.time_block, s);
+                st->ringop, head, st->tail_acc, (double*)pfar, h.time_block, s, clk_of(st));
   }
 }
 
@@ -371,7 +387,7 @@ void eval_history(seas_op* op, seas_state* st, int64_t head, hipStream_t s, void
   }
   const void* arena_near = h.seg ? (const void*)op->arena_near : op->arena;
   launch_hmat(h, 1, nnear, op->items[1], op->lagT, op->lagCol, op->lagColOff[1], arena_near, st->ringop, head,
-              st->tail_acc, pnear, 1, s);
+              st->tail_acc, pnear, 1, s, clk_of(st));
   launch_reduce_near(h, pnear, op->red_ptr[1], op->red_idx[1], st->f_far + k * h.N, st->f_hist, s);
 }
 
@@ -436,16 +452,19 @@ void do_long_step(seas_op* op, seas_state* st, int64_t g, hipStream_t s) {
   st->step = n + g;
 }
 
+void ensure_side(seas_state* st) {
+  if (st->side) return;
+  HIPCHK(hipStreamCreateWithFlags(&st->side, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&st->ev_fork, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&st->ev_join, hipEventDisableTiming));
+}
+
 template <typename TF>
-void do_steps(seas_op* op, seas_state* st, int n_steps, hipStream_t s) {
+void step_loop(seas_op* op, seas_state* st, int n_steps, hipStream_t s) {
   const HostOp& h = op->h;
   const int nm = h.n_modes, nv = st->nv;
   const int64_t dl = h.self_ring_len;
-  if (n_steps > 0 && !st->side) {
-    HIPCHK(hipStreamCreateWithFlags(&st->side, hipStreamNonBlocking));
-    HIPCHK(hipEventCreateWithFlags(&st->ev_fork, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&st->ev_join, hipEventDisableTiming));
-  }
+  if (n_steps > 0) ensure_side(st);
   const int S = h.time_block;
   const bool la_on = st->overlap && S > 1 && st->run_S != 1;
   if (la_on && !st->la) {
@@ -472,9 +491,9 @@ void do_steps(seas_op* op, seas_state* st, int n_steps, hipStream_t s) {
     // stream from the step's start and rejoin before the predictor stage.
     HIPCHK(hipEventRecord(st->ev_fork, s));
     HIPCHK(hipStreamWaitEvent(st->side, st->ev_fork, 0));
-    launch_self_hist(nm, nv, dl, op->modes, op->tab, st->dring, n + 1, st->Fh, st->side);
+    launch_self_hist(nm, nv, dl, op->modes, op->tab, st->dring, n + 1, st->Fh, st->side, clk_of(st));
     launch_dft(nm, nv, h.N, dl, op->modes, op->sf, st->delta, st->V, h.dt, op->tw, op->tab, st->Fh, st->F,
-               st->dring, 0, 0, 0, st->side);
+               st->dring, 0, 0, 0, st->side, nullptr, clk_of(st));
     HIPCHK(hipEventRecord(st->ev_join, st->side));
     eval_history(op, st, n, s, nullptr, nullptr, la_on ? &la : nullptr);
     HIPCHK(hipStreamWaitEvent(s, st->ev_join, 0));
@@ -486,13 +505,104 @@ void do_steps(seas_op* op, seas_state* st, int n_steps, hipStream_t s) {
     // corrector: D** waits in Dnew; the commit appends it with the rest of the step
     // unless a solve of the variant failed
     launch_dft(nm, nv, h.N, dl, op->modes, op->sf, st->delta, st->Vbar, h.dt, op->tw, op->tab, st->Fh, st->F,
-               st->dring, 0, n + 1, n + 1, s, st->Dnew);
+               st->dring, 0, n + 1, n + 1, s, st->Dnew, clk_of(st));
     launch_stage<TF>(a, 1, s);
     launch_commit<TF>(a, s);
     st->step = n + 1;
   }
   st->la_head = INT64_MIN / 2;
   HIPCHK(hipGetLastError());
+}
+
+// Steps per captured graph when every step starts a time block (the plain form)
+constexpr int kGraphPlainSteps = 16;
+
+// Capture U fixed steps that start at a time-block start: recorded on the capture
+// stream with step times 0 .. U-1 (the kernels add *clk), then a node that adds U
+// to *clk. No block lookahead (it would reach into the next replay) and no timing
+// events inside the graph.
+template <typename TF>
+void capture_steps(seas_op* op, seas_state* st, int U) {
+  if (st->gexec) {
+    HIPCHK(hipGraphExecDestroy(st->gexec));
+    st->gexec = nullptr;
+  }
+  ensure_side(st);
+  if (!st->cap) HIPCHK(hipStreamCreateWithFlags(&st->cap, hipStreamNonBlocking));
+  const int64_t step = st->step, bh = st->block_head, taken = st->steps_taken, lg = st->last_gamma;
+  const bool timing = st->timing, overlap = st->overlap;
+  auto restore = [&] {
+    st->step = step;
+    st->block_head = bh;
+    st->steps_taken = taken;
+    st->last_gamma = lg;
+    st->timing = timing;
+    st->overlap = overlap;
+    st->capturing = false;
+  };
+  st->step = 0;
+  st->block_head = INT64_MIN / 2;
+  st->timing = false;
+  st->overlap = false;
+  st->capturing = true;
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(st->cap, hipStreamCaptureModeThreadLocal));
+  try {
+    step_loop<TF>(op, st, U, st->cap);
+    launch_clock(st->clk, U, 1, st->cap);
+  } catch (...) {
+    (void)hipStreamEndCapture(st->cap, &g);
+    if (g) (void)hipGraphDestroy(g);
+    restore();
+    throw;
+  }
+  restore();
+  HIPCHK(hipStreamEndCapture(st->cap, &g));
+  const hipError_t e = hipGraphInstantiate(&st->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    st->gexec = nullptr;
+    throw Error(SEAS_ERR_HIP, std::string("graph instantiation: ") + hipGetErrorString(e));
+  }
+  st->g_unit = U;
+  st->g_runS = st->run_S;
+}
+
+// Fixed steps as replays of the captured graph where whole time blocks fit: eager
+// steps up to the next block start, the replays, eager steps for the rest. Every
+// step evaluates exactly as an eager one (same kernels, same values).
+template <typename TF>
+void do_steps(seas_op* op, seas_state* st, int n_steps, hipStream_t s) {
+  const HostOp& h = op->h;
+  if (!st->graph || h.prm.adaptive_dt) {
+    step_loop<TF>(op, st, n_steps, s);
+    return;
+  }
+  const int S = h.time_block;
+  const bool plain = S == 1 || st->run_S == 1;
+  const int U = plain ? kGraphPlainSteps : S;
+  int done = 0;
+  auto starts_block = [&] {
+    const int64_t k = st->step - st->block_head;
+    return plain || k < 0 || k >= S;
+  };
+  while (done < n_steps && !starts_block()) {
+    step_loop<TF>(op, st, 1, s);
+    ++done;
+  }
+  const int reps = (n_steps - done) / U;
+  if (reps > 0) {
+    if (!st->gexec || st->g_unit != U || st->g_runS != st->run_S) capture_steps<TF>(op, st, U);
+    launch_clock(st->clk, st->step, 0, s);
+    for (int r = 0; r < reps; ++r) HIPCHK(hipGraphLaunch(st->gexec, s));
+    st->step += (int64_t)reps * U;
+    st->steps_taken += (int64_t)reps * U;
+    st->last_gamma = 1;
+    st->block_head = plain ? INT64_MIN / 2 : st->step - U;
+    st->g_replays += reps;
+    done += reps * U;
+  }
+  if (done < n_steps) step_loop<TF>(op, st, n_steps - done, s);
 }
 
 template <typename TF>
@@ -1392,6 +1502,25 @@ seas_status seas_state_progress(const seas_state_t* st, int64_t* steps_taken, in
     if (steps_taken) *steps_taken = st->steps_taken;
     if (last_gamma) *last_gamma = st->last_gamma;
     if (time_s) *time_s = (double)st->step * st->op->h.dt;
+  });
+}
+
+seas_status seas_state_set_graph(seas_state_t* st, int32_t enable) {
+  return guard([&] {
+    if (!st) throw Error(SEAS_ERR_INVALID_ARG, "null state");
+    checked(st->op);
+    if (enable && st->op->h.prm.adaptive_dt)
+      throw Error(SEAS_ERR_MISMATCH, "adaptive steps choose each step's length on the host");
+    if (enable && !st->clk) st->clk = (int64_t*)dalloc(st->owned, 256);
+    st->graph = enable != 0;
+  });
+}
+
+seas_status seas_state_graph_info(const seas_state_t* st, int64_t* replays, int32_t* steps_per_replay) {
+  return guard([&] {
+    if (!st) throw Error(SEAS_ERR_INVALID_ARG, "null state");
+    if (replays) *replays = st->g_replays;
+    if (steps_per_replay) *steps_per_replay = st->gexec ? st->g_unit : 0;
   });
 }
 

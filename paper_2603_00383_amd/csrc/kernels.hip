@@ -103,7 +103,9 @@ __global__ __launch_bounds__(kItemThreads) void k_hmat(const Item* __restrict__ 
                                                        const TF* __restrict__ arena, const TF* __restrict__ ring,
                                                        int64_t head, int64_t R, int N,
                                                        const double* __restrict__ tail_acc,
-                                                       double* __restrict__ partials, int pstride) {
+                                                       double* __restrict__ partials, int pstride,
+                                                       const int64_t* __restrict__ clk) {
+  if (clk) head += *clk;
   __shared__ TA h[kHistMax];
   __shared__ TA z[kZMax];
   __shared__ int cl[kColMax];  // lag index of each low-rank column
@@ -306,7 +308,8 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(4)
                                                               const float* __restrict__ arena,
                                                               const float* __restrict__ ring, int64_t head,
                                                               int64_t R, int N, float* __restrict__ partials,
-                                                              int pstride) {
+                                                              int pstride, const int64_t* __restrict__ clk) {
+  if (clk) head += *clk;
   constexpr int S = 16;
   __shared__ float h[kHistMax];
   __shared__ float z[kZMax];
@@ -395,7 +398,8 @@ __global__ void k_reduce_near(const double* __restrict__ partials, const int32_t
 // time0 is the time of the coefficient being formed; butterfly sum over lanes.
 __global__ void k_self_hist(const SelfMode* __restrict__ modes, int n_modes, int nv, int64_t dring_len,
                             const double* __restrict__ tab, const double2* __restrict__ dring, int64_t time0,
-                            double2* __restrict__ Fh) {
+                            double2* __restrict__ Fh, const int64_t* __restrict__ clk) {
+  if (clk) time0 += *clk;
   const int lane = threadIdx.x & 63;
   const int gg = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (gg >= n_modes * nv) return;
@@ -432,7 +436,11 @@ __global__ void k_dft(const SelfMode* __restrict__ modes, int n_modes, int nv, i
                       const double* __restrict__ vel, double coef, const double2* __restrict__ tw,
                       const double* __restrict__ tab, const double2* __restrict__ Fh, double2* __restrict__ Fout,
                       double2* __restrict__ dring, int push, int64_t push_time, int64_t ring_head,
-                      double2* __restrict__ Dsave) {
+                      double2* __restrict__ Dsave, const int64_t* __restrict__ clk) {
+  if (clk) {
+    push_time += *clk;
+    ring_head += *clk;
+  }
   const int lane = threadIdx.x & 63;
   const int gg = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (gg >= n_modes * nv) return;
@@ -538,14 +546,14 @@ __device__ double newton_lnV(double A, double th, double eta, double a, double b
 }
 
 // Expired-slip accumulators that source element r feeds (one per pair, or per
-// block with cluster-level windows): E += dt V^t, t = time_new - T_end - 1 (the
-// rate that just left that window).
+// block with cluster-level windows): E += dt V^t, t = tn - T_end - 1 (the rate
+// that just left that window; tn the time of the row just appended).
 template <typename TF>
-__device__ __forceinline__ void tail_update(const StepArgs<TF>& a, int v, int r) {
+__device__ __forceinline__ void tail_update(const StepArgs<TF>& a, int v, int r, int64_t tn) {
   double* E = a.tail_acc + v * a.tail_len;
   for (int e = a.tail_src_ptr[r]; e < a.tail_src_ptr[r + 1]; ++e) {
     const int acc = a.tail_src[2 * e], Tend = a.tail_src[2 * e + 1];
-    const int64_t t = a.time_new - Tend - 1;
+    const int64_t t = tn - Tend - 1;
     if (t >= a.first) E[acc] += a.dt * a.ring64[(ring_slot(t, a.R) * a.nv + v) * a.N + r];
   }
 }
@@ -610,7 +618,8 @@ __global__ void k_stage(StepArgs<TF> a, int stage) {
   const int j = r - f.off;
   const double fself = idft_wave(f, a.F + (int64_t)v * a.n_modes + f.mode_off, a.tw + f.tw, j, lane);
   if (lane != 0) return;
-  const double tau0 = a.tau0[e] + a.tau0_rate[e] * (a.t_next - (double)a.step0[v] * a.dt);
+  const double t_next = a.clk ? (double)(a.time_new + *a.clk) * a.dt : a.t_next;
+  const double tau0 = a.tau0[e] + a.tau0_rate[e] * (t_next - (double)a.step0[v] * a.dt);
   const Friction& fr = a.fric;
   if (stage == 0) {  // predictor: delta*, theta* from the current rates
     const double V = a.V[e];
@@ -648,6 +657,7 @@ template <typename TF>
 __global__ void k_commit(StepArgs<TF> a) {
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t ne = (int64_t)a.N * a.nv;
+  const int64_t c = a.clk ? *a.clk : 0;
   if (g < ne) {
     const int v = (int)(g / a.N), r = (int)(g - (int64_t)v * a.N);
     if (a.fail[v]) return;
@@ -660,12 +670,13 @@ __global__ void k_commit(StepArgs<TF> a) {
     a.V[e] = V2;
     a.f_self_out[e] = a.fs2[e];
     a.f_int_out[e] = a.fi2[e];
-    const int64_t sl = ring_slot(a.time_new, a.R), ri = (sl * a.nv + v) * a.N + r;
+    const int64_t tn = a.time_new + c;
+    const int64_t sl = ring_slot(tn, a.R), ri = (sl * a.nv + v) * a.N + r;
     a.ring64[ri] = V2;
     if ((void*)a.ringop != (void*)a.ring64)
       a.ringop[a.op_vfast ? (sl * a.N + r) * a.nv + v : ri] = to_op<TF>(V2);
-    if (a.tail && a.gamma == 1) tail_update(a, v, r);
-    if (r == 0) a.good[v] = a.time_new;
+    if (a.tail && a.gamma == 1) tail_update(a, v, r, tn);
+    if (r == 0) a.good[v] = tn;
     return;
   }
   g -= ne;
@@ -673,7 +684,7 @@ __global__ void k_commit(StepArgs<TF> a) {
   const int v = (int)(g / a.n_modes), gm = (int)(g - (int64_t)v * a.n_modes);
   if (a.fail[v]) return;
   const SelfMode md = a.modes[gm];
-  if (md.W > 0) a.dring[v * a.dring_len + md.ring + ring_slot(a.self_head, md.W)] = a.Dnew[g];
+  if (md.W > 0) a.dring[v * a.dring_len + md.ring + ring_slot(a.self_head + c, md.W)] = a.Dnew[g];
 }
 
 // Prescribed mode, before the evaluation of step n: append V^{n-1}, advance slip.
@@ -688,7 +699,7 @@ __global__ void k_pre_push(StepArgs<TF> a, const double* __restrict__ Vin) {
   a.ring64[ri] = x;
   if ((void*)a.ringop != (void*)a.ring64) a.ringop[a.op_vfast ? (sl * a.N + r) * a.nv + v : ri] = to_op<TF>(x);
   a.delta[rg] += a.dt * x;
-  if (a.tail) tail_update(a, v, r);
+  if (a.tail) tail_update(a, v, r, a.time_new);
 }
 
 // Prescribed mode output: f^n = f_self + f_hist - mu/(2cs) K^0 V^{n-1} (one wave
@@ -729,49 +740,49 @@ void launch_clear_variant(void* base, int64_t rows, int nv, int v, int N, int el
 template <typename TF, int S>
 static void hmat_s(int n, const void* items, const int32_t* lagT, const int32_t* lagCol, const int32_t* lagColOff,
                    const void* arena, const void* ring, int64_t head, int64_t R, int N, const double* tail_acc,
-                   double* partials, int pstride, hipStream_t s) {
+                   double* partials, int pstride, hipStream_t s, const int64_t* clk) {
   hipLaunchKernelGGL((k_hmat<TF, TF, S>), dim3(n), dim3(kItemThreads), 0, s, (const Item*)items, lagT, lagCol,
-                     lagColOff, (const TF*)arena, (const TF*)ring, head, R, N, tail_acc, partials, pstride);
+                     lagColOff, (const TF*)arena, (const TF*)ring, head, R, N, tail_acc, partials, pstride, clk);
 }
 
 template <typename TF>
 static void hmat_t(int S, int n, const void* items, const int32_t* lagT, const int32_t* lagCol,
                    const int32_t* lagColOff, const void* arena, const void* ring, int64_t head, int64_t R, int N,
-                   const double* tail_acc, double* partials, int ps, hipStream_t s) {
+                   const double* tail_acc, double* partials, int ps, hipStream_t s, const int64_t* clk) {
   switch (S) {
-    case 1: hmat_s<TF, 1>(n, items, lagT, lagCol, lagColOff, arena, ring, head, R, N, tail_acc, partials, ps, s); break;
-    case 2: hmat_s<TF, 2>(n, items, lagT, lagCol, lagColOff, arena, ring, head, R, N, tail_acc, partials, ps, s); break;
-    case 4: hmat_s<TF, 4>(n, items, lagT, lagCol, lagColOff, arena, ring, head, R, N, tail_acc, partials, ps, s); break;
-    case 8: hmat_s<TF, 8>(n, items, lagT, lagCol, lagColOff, arena, ring, head, R, N, tail_acc, partials, ps, s); break;
-    case 16: hmat_s<TF, 16>(n, items, lagT, lagCol, lagColOff, arena, ring, head, R, N, tail_acc, partials, ps, s); break;
+    case 1: hmat_s<TF, 1>(n, items, lagT, lagCol, lagColOff, arena, ring, head, R, N, tail_acc, partials, ps, s, clk); break;
+    case 2: hmat_s<TF, 2>(n, items, lagT, lagCol, lagColOff, arena, ring, head, R, N, tail_acc, partials, ps, s, clk); break;
+    case 4: hmat_s<TF, 4>(n, items, lagT, lagCol, lagColOff, arena, ring, head, R, N, tail_acc, partials, ps, s, clk); break;
+    case 8: hmat_s<TF, 8>(n, items, lagT, lagCol, lagColOff, arena, ring, head, R, N, tail_acc, partials, ps, s, clk); break;
+    case 16: hmat_s<TF, 16>(n, items, lagT, lagCol, lagColOff, arena, ring, head, R, N, tail_acc, partials, ps, s, clk); break;
     default: break;
   }
 }
 
 void launch_hmat(const HostOp& h, int S, int n_items, const void* items, const int32_t* lagT, const int32_t* lagCol,
                  const int32_t* lagColOff, const void* arena, const void* ring, int64_t head,
-                 const double* tail_acc, double* partials, int pstride, hipStream_t s) {
+                 const double* tail_acc, double* partials, int pstride, hipStream_t s, const int64_t* clk) {
   if (n_items == 0) return;
   if (h.prm.factor_dtype == SEAS_F32 && S == 16 && h.use_mfma) {
     hipLaunchKernelGGL(k_hmat_mfma16, dim3(n_items), dim3(kItemThreads), 0, s, (const Item*)items, lagT, lagCol,
                        lagColOff, (const float*)arena, (const float*)ring, head, (int64_t)h.ring_len, h.N,
-                       (float*)partials, pstride);
+                       (float*)partials, pstride, clk);
     return;
   }
   if (h.prm.factor_dtype == SEAS_F64)
     hmat_t<double>(S, n_items, items, lagT, lagCol, lagColOff, arena, ring, head, h.ring_len, h.N, tail_acc,
-                   partials, pstride, s);
+                   partials, pstride, s, clk);
   else
     hmat_t<float>(S, n_items, items, lagT, lagCol, lagColOff, arena, ring, head, h.ring_len, h.N, tail_acc,
-                  partials, pstride, s);
+                  partials, pstride, s, clk);
 }
 
 void launch_hmat_f32far(const HostOp& h, int n_items, const void* items, const int32_t* lagT, const int32_t* lagCol,
                         const int32_t* lagColOff, const float* arena, const void* ring, int64_t head,
-                        float* partials, hipStream_t s) {
+                        float* partials, hipStream_t s, const int64_t* clk) {
   if (n_items == 0) return;
   hipLaunchKernelGGL(k_hmat_mfma16, dim3(n_items), dim3(kItemThreads), 0, s, (const Item*)items, lagT, lagCol,
-                     lagColOff, arena, (const float*)ring, head, (int64_t)h.ring_len, h.N, partials, 16);
+                     lagColOff, arena, (const float*)ring, head, (int64_t)h.ring_len, h.N, partials, 16, clk);
 }
 
 bool far_partials_f32(const HostOp& h, int S) {
@@ -808,17 +819,26 @@ void launch_reduce_near(const HostOp& h, const double* partials, const int32_t* 
 }
 
 void launch_self_hist(int n_modes, int nv, int64_t dring_len, const SelfMode* modes, const double* tab,
-                      const double2* dring, int64_t time0, double2* Fh, hipStream_t s) {
+                      const double2* dring, int64_t time0, double2* Fh, hipStream_t s, const int64_t* clk) {
   hipLaunchKernelGGL(k_self_hist, dim3(blocks_for((int64_t)n_modes * nv, 4)), dim3(256), 0, s, modes, n_modes, nv,
-                     dring_len, tab, dring, time0, Fh);
+                     dring_len, tab, dring, time0, Fh, clk);
 }
 
 void launch_dft(int n_modes, int nv, int N, int64_t dring_len, const SelfMode* modes, const SelfFaultDev* sf,
                 const double* delta, const double* vel, double coef, const double2* tw, const double* tab,
                 const double2* Fh, double2* Fout, double2* dring, int push, int64_t push_time, int64_t ring_head,
-                hipStream_t s, double2* Dsave) {
+                hipStream_t s, double2* Dsave, const int64_t* clk) {
   hipLaunchKernelGGL(k_dft, dim3(blocks_for((int64_t)n_modes * nv, 4)), dim3(256), 0, s, modes, n_modes, nv, N,
-                     dring_len, sf, delta, vel, coef, tw, tab, Fh, Fout, dring, push, push_time, ring_head, Dsave);
+                     dring_len, sf, delta, vel, coef, tw, tab, Fh, Fout, dring, push, push_time, ring_head, Dsave,
+                     clk);
+}
+
+__global__ void k_clock(int64_t* __restrict__ clk, int64_t v, int add) {
+  if (threadIdx.x == 0) *clk = add ? *clk + v : v;
+}
+
+void launch_clock(int64_t* clk, int64_t v, int add, hipStream_t s) {
+  hipLaunchKernelGGL(k_clock, dim3(1), dim3(64), 0, s, clk, v, add);
 }
 
 __global__ void k_dt_ev(const double* __restrict__ V, const double* __restrict__ Dc, int64_t ne, double xi,

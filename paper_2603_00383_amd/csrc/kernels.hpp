@@ -71,11 +71,15 @@ struct StepArgs {
   int64_t first;            // earliest time held in the histories
   int tail;                 // static tail on
   int exact_state;          // state law integrated in closed form over the step (else explicit)
+  // replays of a captured step sequence: the device-held step base is added to
+  // time_new and self_head, and t_next = time_new dt (null: the values as given)
+  const int64_t* clk;
 };
 
 void launch_hmat(const HostOp& h, int S, int n_items, const void* items, const int32_t* lagT, const int32_t* lagCol,
                  const int32_t* lagColOff, const void* arena, const void* ring, int64_t head,
-                 const double* tail_acc, double* partials, int pstride, hipStream_t s);
+                 const double* tail_acc, double* partials, int pstride, hipStream_t s,
+                 const int64_t* clk = nullptr);
 // far partials are FP32 when the far list runs on the matrix cores (FP32, S = 16)
 bool far_partials_f32(const HostOp& h, int S);
 void launch_reduce_far(const HostOp& h, int S, const void* partials, bool f32, const int32_t* ptr,
@@ -86,29 +90,36 @@ void launch_reduce_near(const HostOp& h, const double* partials, const int32_t* 
 void launch_clear_variant(void* base, int64_t rows, int nv, int v, int N, int elem_bytes, hipStream_t s);
 // far list on the matrix cores, one workgroup per segment: nseg segments from
 // seg_ptr (a device pointer into the operator's segment offsets)
+// (every launcher below that takes clk: a non-null clk holds a step base the
+// kernel adds to its head / times, for replays of a captured step sequence)
 void launch_hmat_x16(const HostOp& h, const void* items, const int32_t* seg_ptr, int nseg, const int32_t* lagT,
                      const int32_t* lagCol, const int32_t* lagColOff, const void* arena, const void* ring,
-                     int64_t head, const double* tail_acc, float* partials, hipStream_t s);
+                     int64_t head, const double* tail_acc, float* partials, hipStream_t s,
+                     const int64_t* clk = nullptr);
 // ensembles: list 3 (FP32, segment layout) on the FP32 instance of the segment
 // kernel, nv columns, staged from an FP32 (ring_f64 = false) or FP64 rate ring laid
 // out [R][nv][N]; partials in list 0's buffer
 void launch_hmat_seg32(const HostOp& h, const void* items, const int32_t* seg_ptr, const int32_t* lagT,
                        const int32_t* lagCol, const int32_t* lagColOff, const float* arena, const void* ring,
-                       bool ring_f64, int64_t head, const double* tail_acc, float* partials, hipStream_t s);
+                       bool ring_f64, int64_t head, const double* tail_acc, float* partials, hipStream_t s,
+                       const int64_t* clk = nullptr);
 // FP32 far items of a 16-bit build (near-field blocks), S = 16 windows on the
 // matrix cores, FP32 partials [p][16] in the 16-bit far list's partial buffer
 void launch_hmat_f32far(const HostOp& h, int n_items, const void* items, const int32_t* lagT, const int32_t* lagCol,
                         const int32_t* lagColOff, const float* arena, const void* ring, int64_t head,
-                        float* partials, hipStream_t s);
+                        float* partials, hipStream_t s, const int64_t* clk = nullptr);
 // self term over nv variants: modal arrays [nv][n_modes], rings [nv][dring_len], slip [nv][N]
 void launch_self_hist(int n_modes, int nv, int64_t dring_len, const SelfMode* modes, const double* tab,
-                      const double2* dring, int64_t time0, double2* Fh, hipStream_t s);
+                      const double2* dring, int64_t time0, double2* Fh, hipStream_t s,
+                      const int64_t* clk = nullptr);
 // push: 1 stores the coefficients in the mode rings at push_time; Dsave (may be
 // null) receives them instead, [nv][n_modes], for a later conditional push
 void launch_dft(int n_modes, int nv, int N, int64_t dring_len, const SelfMode* modes, const SelfFaultDev* sf,
                 const double* delta, const double* vel, double coef, const double2* tw, const double* tab,
                 const double2* Fh, double2* Fout, double2* dring, int push, int64_t push_time, int64_t ring_head,
-                hipStream_t s, double2* Dsave = nullptr);
+                hipStream_t s, double2* Dsave = nullptr, const int64_t* clk = nullptr);
+// *clk = v (add = 0) or *clk += v (add = 1), one thread
+void launch_clock(int64_t* clk, int64_t v, int add, hipStream_t s);
 template <typename TF>
 void launch_stage(const StepArgs<TF>& a, int stage, hipStream_t s);
 // commit of a corrector: state, histories and outputs of every variant whose

@@ -131,7 +131,9 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
     const Item* __restrict__ items, const int32_t* __restrict__ seg_ptr, const int32_t* __restrict__ lagT,
     const int32_t* __restrict__ lagCol, const int32_t* __restrict__ lagColOff, const T16* __restrict__ arena,
     const TR* __restrict__ ring, int64_t head, int64_t R, int N, int S, int nv,
-    const double* __restrict__ tail_acc, int64_t tail_len, float* __restrict__ partials) {
+    const double* __restrict__ tail_acc, int64_t tail_len, float* __restrict__ partials,
+    const int64_t* __restrict__ clk) {
+  if (clk) head += *clk;
   typedef typename Mx<T16>::v8 v8;
   constexpr int NC = 16 * NT;
   constexpr int EB = (int)sizeof(T16);  // bytes per stored value
@@ -544,34 +546,34 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
 template <typename T16, typename TR, bool SCALE, int NT, bool VFAST = false>
 static void x16_launch(const HostOp& h, const void* items, const int32_t* seg_ptr, const int32_t* lagT,
                        const int32_t* lagCol, const int32_t* lagColOff, const void* arena, const void* ring,
-                       int64_t head, const double* tail_acc, float* partials, hipStream_t s, int nseg = -1) {
-  if (nseg < 0) nseg = (int)h.seg_ptr.size() - 1;
+                       int64_t head, const double* tail_acc, float* partials, hipStream_t s, int nseg,
+                       const int64_t* clk) {
   hipLaunchKernelGGL((k_hmat_x16<T16, TR, SCALE, NT, VFAST>), dim3(nseg), dim3(kItemThreads), 0, s, (const Item*)items,
                      seg_ptr, lagT, lagCol, lagColOff, (const T16*)arena, (const TR*)ring, head, (int64_t)h.ring_len,
-                     h.N, h.time_block, h.n_variants, tail_acc, (int64_t)h.tail_len, partials);
+                     h.N, h.time_block, h.n_variants, tail_acc, (int64_t)h.tail_len, partials, clk);
 }
 
 void launch_hmat_x16(const HostOp& h, const void* items, const int32_t* seg_ptr, int nseg, const int32_t* lagT,
                      const int32_t* lagCol, const int32_t* lagColOff, const void* arena, const void* ring,
-                     int64_t head, const double* tail_acc, float* partials, hipStream_t s) {
+                     int64_t head, const double* tail_acc, float* partials, hipStream_t s, const int64_t* clk) {
   if (nseg < 1) return;
   const bool bf = h.prm.factor_dtype == SEAS_BF16;
   if (!h.x16) {  // FP32 factors, one variant, 16 windows
     x16_launch<float, float, false, 1>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head, tail_acc,
-                                       partials, s, nseg);
+                                       partials, s, nseg, clk);
     return;
   }
   if (h.n_variants == 1) {
-    if (bf) x16_launch<__bf16, float, false, 1>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head, tail_acc, partials, s, nseg);
-    else x16_launch<_Float16, float, true, 1>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head, tail_acc, partials, s, nseg);
+    if (bf) x16_launch<__bf16, float, false, 1>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head, tail_acc, partials, s, nseg, clk);
+    else x16_launch<_Float16, float, true, 1>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head, tail_acc, partials, s, nseg, clk);
     return;
   }
   // ensembles: BF16 with a BF16 rate history, or FP16 with an FP32 one scaled per item
 #define SEAS_X16_ENS(NT)                                                                                      \
   if (bf) x16_launch<__bf16, __bf16, false, NT, true>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head, \
-                                                      tail_acc, partials, s, nseg);                                \
+                                                      tail_acc, partials, s, nseg, clk);                                \
   else x16_launch<_Float16, float, true, NT>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head,       \
-                                             tail_acc, partials, s, nseg);
+                                             tail_acc, partials, s, nseg, clk);
   switch (h.ncols) {
     case 16: SEAS_X16_ENS(1) break;
     case 32: SEAS_X16_ENS(2) break;
@@ -583,14 +585,15 @@ void launch_hmat_x16(const HostOp& h, const void* items, const int32_t* seg_ptr,
 
 void launch_hmat_seg32(const HostOp& h, const void* items, const int32_t* seg_ptr, const int32_t* lagT,
                        const int32_t* lagCol, const int32_t* lagColOff, const float* arena, const void* ring,
-                       bool ring_f64, int64_t head, const double* tail_acc, float* partials, hipStream_t s) {
+                       bool ring_f64, int64_t head, const double* tail_acc, float* partials, hipStream_t s,
+                       const int64_t* clk) {
   const int nseg = (int)h.seg_ptr3.size() - 1;
   if (nseg < 1) return;
 #define SEAS_SEG32(NT)                                                                                         \
   if (ring_f64) x16_launch<float, double, false, NT>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head, \
-                                                      tail_acc, partials, s, nseg);                             \
+                                                      tail_acc, partials, s, nseg, clk);                             \
   else x16_launch<float, float, false, NT>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head, tail_acc, \
-                                           partials, s, nseg);
+                                           partials, s, nseg, clk);
   switch (h.ncols) {
     case 16: SEAS_SEG32(1) break;
     case 32: SEAS_SEG32(2) break;
