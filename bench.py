@@ -613,8 +613,9 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: device memory for states")
     ap.add_argument("--aca", type=float, default=1e-6)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--time-block", type=int, default=16,
-                    help="S: lags >= S applied once per S steps (1 = plain per-step form)")
+    ap.add_argument("--time-block", type=int, default=None,
+                    help="S: lags >= S applied once per S steps (1 = plain per-step form); default 32 for "
+                         "FP32 factors, 16 for the 16-bit and FP64 ones")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form measurement")
     ap.add_argument("--no-forms", action="store_true", help="skip the 16-bit forms (FP32 runs only)")
     ap.add_argument("--forms", default="f16,bf16,f64,cluster",
@@ -673,6 +674,8 @@ def main():
         return run_adaptive(args)
     if args.dtype is None:
         args.dtype = "f32"
+    if args.time_block is None:
+        args.time_block = 32 if args.dtype == "f32" else 16
     faults = SI.five_fault_network(seed=args.seed)
     os.environ.setdefault("SEAS_VERBOSE", "1")
     fric = SI.rate_state_fields(faults)
@@ -691,11 +694,11 @@ def main():
         f = st.read("f_hist", stream=s)[ref["rows"]]
         return float(np.abs(f - ref["ref0"]).max() / np.abs(ref["ref0"]).max())
 
-    def prepare(dtype, cluster=0):
+    def prepare(dtype, cluster=0, S=None):
         """Operator of one factor dtype and a state with full history windows: the
         first step is compared with the oracle, then the rest of the warmup."""
         params = SI.default_params(factor_dtype=dtype, aca_tol=args.aca, eta_H=2.0, leaf=50,
-                                   time_block=args.time_block, cluster_windows=cluster)
+                                   time_block=S or args.time_block, cluster_windows=cluster)
         print(f"[bench] building the {dtype} operator", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
         op = P.Operator(faults, params)
@@ -767,13 +770,15 @@ def main():
     main_run = timed_on(st, info, elem_bytes, S, K)
     steady = timed_on(st, info, elem_bytes, S, 10 * S)
     serial = timed_on(st, info, elem_bytes, S, 10 * S, overlap=False) if S > 1 else None
-    plain = None if (args.no_plain or S == 1) else timed_on(st, info, elem_bytes, 1, K)
+    # the plain per-step form (S = 1) on the operator built for 16 windows, as the segment
+    # kernel forms all its windows in every launch
+    plain = None if (args.no_plain or S not in (2, 4, 8, 16)) else timed_on(st, info, elem_bytes, 1, K)
     wall, avg_ms, achieved = main_run["wall"], main_run["avg_ms"], main_run["gbs"]
     hmat_bytes = alg_bytes(info, elem_bytes, S)
     if args.dtype in ("bf16", "f16"):
         kname = f"k_hmat_x16<{'bf16' if args.dtype == 'bf16' else 'f16'},16 columns>"
-    elif args.dtype == "f32" and S == 16 and info["n_segments"] > 0:
-        kname = "k_hmat_x16<f32,16 columns>"  # the segment kernel, FP32 instance
+    elif args.dtype == "f32" and S in (16, 32) and info["n_segments"] > 0:
+        kname = f"k_hmat_x16<f32,{S} columns>"  # the segment kernel, FP32 instance
     elif args.dtype == "f32" and S == 16 and not os.environ.get("SEAS_NO_MFMA"):
         kname = "k_hmat_mfma16"
     else:
@@ -823,12 +828,35 @@ def main():
     print(f"[bench] timed {K} steps: {wall:.3f} s", file=sys.stderr, flush=True)
     st.close()
     op.close()
-    if args.dtype == "f32" and not args.no_forms and S == 16:
+    if args.dtype == "f32" and S == 32 and not args.no_plain:
+        # 16 windows per far launch (the FP32 form with half the columns per factor byte),
+        # and the plain per-step form on that operator
+        op_d, inf_d, st_d, bs_d, err_d = prepare("f32", S=16)
+        r = timed_on(st_d, inf_d, 4, 16, K)
+        r_ss = timed_on(st_d, inf_d, 4, 16, 160)
+        pl = timed_on(st_d, inf_d, 4, 1, K)
+        kn = "k_hmat_x16<f32,16 columns>"
+        out.setdefault("forms", {})["f32_S16"] = {
+            "value": r["value"], "ms_per_step": r["ms_per_step"], "steady_state_value": r_ss["value"],
+            "kernel": kn, "kernel_avg_ms": r["avg_ms"], "achieved_GBs": r["gbs"], "frac": r["gbs"] / HBM_PEAK_GBS,
+            "algorithmic_bytes": alg_bytes(inf_d, 4, 16), "rel_err": err_d,
+            "within_1e-4": None if err_d is None else bool(err_d <= 1e-4),
+            "traffic": measured_traffic(kn, args), "build_s": bs_d,
+            "note": "FP32 factors, time block 16 (16 windows per far launch)"}
+        out["plain"] = {"value": pl["value"], "ms_per_step": pl["ms_per_step"], "kernel_avg_ms": pl["avg_ms"],
+                        "achieved_GBs": pl["gbs"], "frac": pl["gbs"] / HBM_PEAK_GBS, "rel_err": err_d,
+                        "speedup_of_value": (N * K / wall) / pl["value"],
+                        "note": "FP32 operator with time block 16, every lag applied every step (S = 1)"}
+        print(f"[bench] form f32 S=16: {r['value']:.3e} element-steps/s; plain {pl['value']:.3e}",
+              file=sys.stderr, flush=True)
+        st_d.close()
+        op_d.close()
+    if args.dtype == "f32" and not args.no_forms and S in (16, 32):
         # the other forms of the same workload (same geometry, state and history)
-        out["forms"] = {}
+        out.setdefault("forms", {})
         wanted = set(args.forms.split(","))
         for d in [d for d in ("f16", "bf16", "f64") if d in wanted]:
-            op_d, inf_d, st_d, bs_d, err_d = prepare(d)
+            op_d, inf_d, st_d, bs_d, err_d = prepare(d, S=16)
             eb = {"f16": 2, "bf16": 2, "f64": 8}[d]
             r = timed_on(st_d, inf_d, eb, 16, K)
             r_ss = timed_on(st_d, inf_d, eb, 16, 160)
@@ -846,15 +874,15 @@ def main():
                   flush=True)
             st_d.close()
             op_d.close()
-    if args.dtype == "f32" and not args.no_forms and S == 16 and "cluster" in args.forms.split(","):
+    if args.dtype == "f32" and not args.no_forms and S in (16, 32) and "cluster" in args.forms.split(","):
         # cluster-level windows (Section 4.3): FP32, each block truncated at its own upper lag
         op_c, inf_c, st_c, bs_c, err_c = prepare("f32", cluster=1)
-        r = timed_on(st_c, inf_c, 4, 16, K)
-        r_ss = timed_on(st_c, inf_c, 4, 16, 160)
+        r = timed_on(st_c, inf_c, 4, S, K)
+        r_ss = timed_on(st_c, inf_c, 4, S, 10 * S)
         out["forms"]["f32_cluster_windows"] = {
             "value": r["value"], "ms_per_step": r["ms_per_step"], "steady_state_value": r_ss["value"],
-            "kernel": "k_hmat_x16<f32,16 columns>", "kernel_avg_ms": r["avg_ms"], "achieved_GBs": r["gbs"],
-            "frac": r["gbs"] / HBM_PEAK_GBS, "algorithmic_bytes": alg_bytes(inf_c, 4, 16),
+            "kernel": f"k_hmat_x16<f32,{S} columns>", "kernel_avg_ms": r["avg_ms"], "achieved_GBs": r["gbs"],
+            "frac": r["gbs"] / HBM_PEAK_GBS, "algorithmic_bytes": alg_bytes(inf_c, 4, S),
             "stored_entries": inf_c["stored_entries"], "stored_entries_pair_windows": info["stored_entries"],
             "rel_err": err_c, "within_1e-4": None if err_c is None else bool(err_c <= 1e-4), "build_s": bs_c,
             "note": "FP32 factors, every block truncated at the pair rule applied to its clusters, static "

@@ -107,11 +107,12 @@ typedef struct {
   int32_t host_only;    /* 1: build on the host only (no device memory; for inspecting the
                            partition, windows, tables and factors); evaluation and state calls
                            then fail with MISMATCH */
-  int32_t time_block;   /* S in {0 (= 1), 1, 2, 4, 8, 16}: lags T >= S are applied once per S
+  int32_t time_block;   /* S in {0 (= 1), 1, 2, 4, 8, 16, 32}: lags T >= S are applied once per S
                            steps to S history windows (a lag-T factor only needs rates at least
                            T steps old), lags 1..S-1 and the static tail every step; the sum is
                            the same, only its evaluation order changes. BF16 / F16 operators
-                           with one variant need 16; with several variants, 0 or 1 */
+                           with one variant need 16; with several variants, 0 or 1; 32 needs
+                           F32 factors (the 32-column matrix-core products) */
   int32_t n_variants;   /* 0 or 1: one friction parameter set; 16, 32 or 64: an ensemble of that
                            many parameter sets on this geometry (BF16 / F16 only), whose
                            interaction sums are one product of the factors with the

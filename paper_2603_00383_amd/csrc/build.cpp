@@ -507,9 +507,9 @@ static void pack_seg(int r0, int r1, int s0, int s1, const Fault& A, const Fault
         if (lags[j]->T != lags[j - 1]->T + 1) break;
         if (S > 1 && lags[j]->T == 2 * S) break;  // block-start items hold lags below 2S only
         const int span = lags[j]->T - lags[i]->T + S;
-        if ((int64_t)span * nv * seg_ld(q8, eb) > seg_hist_limit(ncols, eb)) break;
+        if ((int64_t)span * nv * seg_ld(q8, eb) > seg_hist_limit(ncols, eb, nv)) break;
         if (nl > kColMax) break;
-        if (lr && (int64_t)seg_ld(round8(ncol + lags[j]->rank), eb) * ncols > seg_z_limit(ncols, eb)) break;
+        if (lr && (int64_t)seg_ld(round8(ncol + lags[j]->rank), eb) * ncols > seg_z_limit(ncols, eb, nv)) break;
         if (elems + e > target) break;
       }
       elems += e;
@@ -590,9 +590,10 @@ static void build_subblock(const HostOp& op, const BlockDesc& bd, const PairWin&
   // ranks above kmax are stored dense: the factors would not be smaller, and one
   // lag's columns must fit the LDS column buffer of the kernel
   int kmax = std::min<int>({(int)(((int64_t)p * q) / (p + q)), kColMax, kZMax / S});
-  if (op.seg) kmax = std::min(kmax, ((seg_z_limit(op.ncols, op.seg_eb) / op.ncols) & ~7) - 8);
+  if (op.seg) kmax = std::min(kmax, ((seg_z_limit(op.ncols, op.seg_eb, op.n_variants) / op.ncols) & ~7) - 8);
   // ensembles: lags that go to the FP32 list (list 3) meet its projection buffer
-  const int kmax32 = op.ens32 ? std::min(kmax, ((seg_z_limit(op.ncols, 4) / op.ncols) & ~7) - 8) : kmax;
+  const int kmax32 =
+      op.ens32 ? std::min(kmax, ((seg_z_limit(op.ncols, 4, op.n_variants) / op.ncols) & ~7) - 8) : kmax;
   auto in_list3 = [&](int T) { return op.ens32 && !(bd.adm && T >= kEnsSplit); };
   const PairFrame fr = frame(A, B);
   // The corners r1' +- ds/2 of source element j are the offsets of its two edges,
@@ -700,7 +701,7 @@ static void build_block(const HostOp& op, const BlockDesc& bd, const PairWin& pw
   // (slices as narrow as one default panel: wider slices need ranks above the cap)
   // (FP32 segment builds keep the FP32 slices, which fit their staging buffer)
   if (op.seg) qmax = std::min(op.x16 ? kHistMax : qmax, ((kHist16 * 2 / op.seg_eb / op.ncols) & ~7) - 8);
-  if (op.ens32) qmax = std::min(qmax, ((seg_hist_limit(op.ncols, 4) / op.n_variants) & ~7) - 8);
+  if (op.ens32) qmax = std::min(qmax, ((seg_hist_limit(op.ncols, 4, op.n_variants) / op.n_variants) & ~7) - 8);
   const int pmax = (op.seg && op.n_variants > 1) ? seg_rows_max(op.ncols) : bd.r1 - bd.r0;
   const int nrs = (bd.r1 - bd.r0 + pmax - 1) / pmax;
   for (int k = 0; k < nrs; ++k) {
@@ -748,7 +749,7 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
     throw Error(SEAS_ERR_INVALID_ARG, "gamma_max must be >= 0 and adapt_xi finite and >= 0");
   if (prm.time_block < 0 || prm.time_block > kMaxTimeBlock ||
       (prm.time_block & (prm.time_block - 1)) != 0)
-    throw Error(SEAS_ERR_INVALID_ARG, "time_block must be 0, 1, 2, 4, 8 or 16");
+    throw Error(SEAS_ERR_INVALID_ARG, "time_block must be 0, 1, 2, 4, 8, 16 or 32");
   op.time_block = prm.time_block > 0 ? prm.time_block : 1;
   op.n_variants = prm.n_variants > 0 ? prm.n_variants : 1;
   op.x16 = prm.factor_dtype == SEAS_BF16 || prm.factor_dtype == SEAS_F16;
@@ -762,8 +763,11 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
   }
   op.ncols = op.time_block * op.n_variants;
   op.use_mfma = std::getenv("SEAS_NO_MFMA") == nullptr;
-  op.seg = op.x16 || (prm.factor_dtype == SEAS_F32 && op.time_block == 16 && op.use_mfma &&
-                      std::getenv("SEAS_NO_SEG") == nullptr);
+  op.seg = op.x16 || (prm.factor_dtype == SEAS_F32 && (op.time_block == 16 || op.time_block == 32) &&
+                      op.use_mfma && std::getenv("SEAS_NO_SEG") == nullptr);
+  // 32 windows: the 32-column FP32 instance of the segment kernel
+  if (op.time_block == 32 && !(prm.factor_dtype == SEAS_F32 && op.seg))
+    throw Error(SEAS_ERR_INVALID_ARG, "time_block 32 needs FP32 factors (the matrix-core segment kernel)");
   op.seg_eb = op.x16 ? 2 : 4;
   op.ens32 = op.x16 && op.n_variants > 1;
   if (prm.n_threads > 0) omp_set_num_threads(prm.n_threads);
@@ -1118,8 +1122,9 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
         const int q8 = round8(it.q);
         const int span = it.src == 0 ? it.nlag + S - 1 : 1;
         if (it.row0 != f.row0 || it.p != f.p || it.p < 1 || it.q < 1 || it.nlag < 1 ||
-            (int64_t)span * op.n_variants * seg_ld(q8, eb) > seg_hist_limit(op.ncols, eb) || (it.data & 7) != 0 ||
-            (it.kind == 0 && (int64_t)seg_ld(round8(it.ncol), eb) * op.ncols > seg_z_limit(op.ncols, eb)) ||
+            (int64_t)span * op.n_variants * seg_ld(q8, eb) > seg_hist_limit(op.ncols, eb, op.n_variants) ||
+            (it.data & 7) != 0 ||
+            (it.kind == 0 && (int64_t)seg_ld(round8(it.ncol), eb) * op.ncols > seg_z_limit(op.ncols, eb, op.n_variants)) ||
             (it.src == 1 && op.n_variants == 1) ||
             it.row0 + it.p > op.N || it.col0 + it.q > op.N)
           throw Error(SEAS_ERR_INTERNAL, "segment item violates the kernel's limits");

@@ -55,16 +55,18 @@ constexpr int kDtEvBlocks = 1024;  // blocks of the adaptive step rule's minimum
 constexpr int kHistMax = 6144;   // history values staged in LDS per item: (span of lags + S - 1) * q
 constexpr int kColMax = 1024;    // low-rank columns (and lags) per item
 constexpr int kZMax = 2048;      // low-rank columns times steps per item
-constexpr int kMaxTimeBlock = 16;
+constexpr int kMaxTimeBlock = 32;
 // 16-bit factors (the matrix-core path): rows padded to 8 values (16 B)
 constexpr int kHist16 = 16384;   // 16-bit history values staged per item: span * variants * q8
-// products of 32 or more columns run two workgroups per CU (registers), so they
-// stage twice the history per item
-inline int hist16_limit(int ncols) { return ncols >= 32 ? 2 * kHist16 : kHist16; }
+// ensemble products of 32 or more columns run two workgroups per CU (registers),
+// so they stage twice the history per item; one variant's 32 time windows keep
+// the 16-column budget (four workgroups per CU)
+inline bool seg_wide(int ncols, int nv) { return ncols >= 32 && nv > 1; }
+inline int hist16_limit(int ncols, int nv) { return seg_wide(ncols, nv) ? 2 * kHist16 : kHist16; }
 constexpr int kZ16 = 4096;       // 16-bit projected values per low-rank item: ncol8 * columns
 // (the end of the kernel's buffer holds the staging maxima: one per wave, or
 // one per variant for scaled ensemble panels, 2 x 16 or 2 x 64 16-bit slots)
-inline int z16_limit(int ncols) { return (ncols >= 32 ? 2 * kZ16 : kZ16) - (ncols >= 32 ? 128 : 32); }
+inline int z16_limit(int ncols, int nv) { return seg_wide(ncols, nv) ? 2 * kZ16 - 128 : kZ16 - 32; }
 constexpr int kMaxVariants = 64;
 constexpr int64_t kSegElems = 1 << 19;  // 16-bit factor values per segment (one workgroup; 1 MiB)
 inline int round8(int x) { return (x + 7) & ~7; }
@@ -77,9 +79,11 @@ inline int seg_rows_max(int ncols) { return ncols == 16 ? 512 : 256; }
 // BF16 / FP16, 4 for FP32 (16 windows of one variant, or the FP32 list of FP16
 // ensembles). The FP32 form stages the
 // same LDS bytes as the 16-bit one, so half as many values.
-inline int seg_hist_limit(int ncols, int eb) { return eb == 2 ? hist16_limit(ncols) : hist16_limit(ncols) / 2; }
-inline int seg_z_limit(int ncols, int eb) {
-  return eb == 2 ? z16_limit(ncols) : (ncols >= 32 ? 2 * kZ16 : kZ16) / 2 - 4;
+inline int seg_hist_limit(int ncols, int eb, int nv) {
+  return eb == 2 ? hist16_limit(ncols, nv) : hist16_limit(ncols, nv) / 2;
+}
+inline int seg_z_limit(int ncols, int eb, int nv) {
+  return eb == 2 ? z16_limit(ncols, nv) : (seg_wide(ncols, nv) ? 2 * kZ16 : kZ16) / 2 - 4;
 }
 // ensembles: lags below this of admissible blocks, every lag of near-field
 // blocks and the static tail are kept in FP32 (list 3)

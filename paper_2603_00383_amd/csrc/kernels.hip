@@ -786,7 +786,7 @@ void launch_hmat_f32far(const HostOp& h, int n_items, const void* items, const i
 }
 
 bool far_partials_f32(const HostOp& h, int S) {
-  return h.x16 || (h.prm.factor_dtype == SEAS_F32 && S == 16 && h.use_mfma);
+  return h.seg || (h.prm.factor_dtype == SEAS_F32 && S == 16 && h.use_mfma);
 }
 
 

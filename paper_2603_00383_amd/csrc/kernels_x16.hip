@@ -1,9 +1,12 @@
 // Segment far-list pass on the matrix cores (BF16 / FP16 factors, and FP32
-// factors with 16 windows) and its launcher.
+// factors with 16 or 32 windows) and its launcher.
 #include <hip/hip_runtime.h>
 
 #include "device_common.hpp"
 
+#ifndef WIN_WAVES
+#define WIN_WAVES 4
+#endif
 namespace seas {
 
 // ------------------------------------------------------------------ segment matrix-core form
@@ -126,8 +129,10 @@ __device__ __forceinline__ void x16_kloop(int k0, int k1, FA A, FB B, mfma_f4 (&
   }
 }
 
-template <typename T16, typename TR, bool SCALE, int NT, bool VFAST>
-__global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT == 1 && !VFAST ? (SCALE ? 3 : 4) : 2))) void k_hmat_x16(
+// WIN: one variant's time windows (NT = 2: 32 windows of FP32 factors), staged
+// with the 16-column budget so that four workgroups share a CU
+template <typename T16, typename TR, bool SCALE, int NT, bool VFAST, bool WIN>
+__global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT == 1 && !VFAST ? (SCALE ? 3 : 4) : (WIN ? WIN_WAVES : 2)))) void k_hmat_x16(
     const Item* __restrict__ items, const int32_t* __restrict__ seg_ptr, const int32_t* __restrict__ lagT,
     const int32_t* __restrict__ lagCol, const int32_t* __restrict__ lagColOff, const T16* __restrict__ arena,
     const TR* __restrict__ ring, int64_t head, int64_t R, int N, int S, int nv,
@@ -142,9 +147,9 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
   constexpr int PF = EB == 4 ? 2 : 8;   // inner steps whose global operand is loaded ahead
   // staged history and projected values (seg_hist_limit, seg_z_limit + 16 bytes):
   // the same bytes for every value type
-  constexpr int HL = (NT >= 2 ? 2 * kHist16 : kHist16) * 2 / EB;
+  constexpr int HL = (NT >= 2 && !WIN ? 2 * kHist16 : kHist16) * 2 / EB;
   __shared__ __attribute__((aligned(16))) T16 h[HL];
-  constexpr int ZL = (NT >= 2 ? 2 * kZ16 : kZ16) * 2 / EB;
+  constexpr int ZL = (NT >= 2 && !WIN ? 2 * kZ16 : kZ16) * 2 / EB;
   __shared__ __attribute__((aligned(16))) T16 z[ZL];
   // the staging maxima live at the end of z, which projected panels never use:
   // one per wave (smax), or one per variant (smv) for scaled ensemble panels
@@ -543,12 +548,12 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
   }
 }
 
-template <typename T16, typename TR, bool SCALE, int NT, bool VFAST = false>
+template <typename T16, typename TR, bool SCALE, int NT, bool VFAST = false, bool WIN = false>
 static void x16_launch(const HostOp& h, const void* items, const int32_t* seg_ptr, const int32_t* lagT,
                        const int32_t* lagCol, const int32_t* lagColOff, const void* arena, const void* ring,
                        int64_t head, const double* tail_acc, float* partials, hipStream_t s, int nseg,
                        const int64_t* clk) {
-  hipLaunchKernelGGL((k_hmat_x16<T16, TR, SCALE, NT, VFAST>), dim3(nseg), dim3(kItemThreads), 0, s, (const Item*)items,
+  hipLaunchKernelGGL((k_hmat_x16<T16, TR, SCALE, NT, VFAST, WIN>), dim3(nseg), dim3(kItemThreads), 0, s, (const Item*)items,
                      seg_ptr, lagT, lagCol, lagColOff, (const T16*)arena, (const TR*)ring, head, (int64_t)h.ring_len,
                      h.N, h.time_block, h.n_variants, tail_acc, (int64_t)h.tail_len, partials, clk);
 }
@@ -558,9 +563,13 @@ void launch_hmat_x16(const HostOp& h, const void* items, const int32_t* seg_ptr,
                      int64_t head, const double* tail_acc, float* partials, hipStream_t s, const int64_t* clk) {
   if (nseg < 1) return;
   const bool bf = h.prm.factor_dtype == SEAS_BF16;
-  if (!h.x16) {  // FP32 factors, one variant, 16 windows
-    x16_launch<float, float, false, 1>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head, tail_acc,
-                                       partials, s, nseg, clk);
+  if (!h.x16) {  // FP32 factors, one variant, 16 or 32 windows
+    if (h.ncols == 32)
+      x16_launch<float, float, false, 2, false, true>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring,
+                                                      head, tail_acc, partials, s, nseg, clk);
+    else
+      x16_launch<float, float, false, 1>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head, tail_acc,
+                                         partials, s, nseg, clk);
     return;
   }
   if (h.n_variants == 1) {

@@ -27,14 +27,17 @@ ROWS = sorted(set([0, 37, 301, 599, 600, 899, 1200, 1511, 1799, 1800, 2222, 2400
 
 
 TOL = {"f32": 1e-4, "f16": 1e-4, "bf16": 2e-3}
+# (factor dtype, time block): FP32 with 16 and 32 windows per far launch
+FORMS = {"f32": ("f32", 16), "f32_S32": ("f32", 32), "f16": ("f16", 16), "bf16": ("bf16", 16)}
 
 
-@pytest.fixture(scope="module", params=["f32", "f16", "bf16"])
+@pytest.fixture(scope="module", params=list(FORMS))
 def fullsize(request, loud):
     if not torch.cuda.is_available():
         pytest.skip("no HIP device")
     faults = SI.five_fault_network(seed=0)
-    params = SI.default_params(factor_dtype=request.param, aca_tol=1e-6, eta_H=2.0, leaf=50, time_block=16)
+    dtype, S = FORMS[request.param]
+    params = SI.default_params(factor_dtype=dtype, aca_tol=1e-6, eta_H=2.0, leaf=50, time_block=S)
     with loud(f"[gpu] building the five-fault operator ({request.param})"):
         op = P.Operator(faults, params)
     prior = SI.saturated_history(faults, op.info["max_lag"] + 2, 0)

@@ -58,16 +58,17 @@ CASES = [
     ("f64_S8", TWO, 1, dict(factor_dtype="f64", compress=1, aca_tol=1e-12, time_block=8)),
     ("f32_S16_seg", FIVE, 1, dict(factor_dtype="f32", aca_tol=1e-8, leaf=8, time_block=16)),
     ("f16_S16", FIVE, 1, dict(factor_dtype="f16", aca_tol=1e-8, leaf=8, time_block=16)),
+    ("f32_S32_seg", FIVE, 1, dict(factor_dtype="f32", aca_tol=1e-8, leaf=8, time_block=32)),
     ("bf16_ens16", TWO, 16, dict(factor_dtype="bf16", aca_tol=1e-8, leaf=8, time_block=1, n_variants=16)),
 ]
-CHUNKS = [5, 37, 3, 50, 40, 1]
+CHUNKS = [5, 37, 3, 50, 40, 1, 70]
 
 
 @pytest.mark.parametrize("name,faults,nv,kw", CASES, ids=[c[0] for c in CASES])
 def test_graph_replays_equal_plain_steps(name, faults, nv, kw):
     p = SI.default_params(state_update="exact", **kw)
     op = P.Operator(faults, p)
-    if name.startswith("f32") or name.startswith("f16"):
+    if "seg" in name or name.startswith("f16"):
         assert op.info["n_segments"] > 0
     s = _stream()
     fr, V, th, tau0, rate = _init(faults, nv)
@@ -86,7 +87,7 @@ def test_graph_replays_equal_plain_steps(name, faults, nv, kw):
     graph.check(stream=s)
     info = graph.graph_info()
     unit = 16 if op.info["time_block"] == 1 else op.info["time_block"]
-    assert info["steps_per_replay"] == unit and info["replays"] >= 4
+    assert info["steps_per_replay"] == unit and info["replays"] >= (4 if unit <= 16 else 2)
     print(f"[gpu] graph {name}: {info['replays']} replays of {unit} steps, all fields equal", flush=True)
 
 

@@ -47,6 +47,7 @@ def _faults():
 
 CASES = [
     ("f32", 16, dict(factor_dtype="f32", aca_tol=1e-8, time_block=16)),
+    ("f32_S32", 32, dict(factor_dtype="f32", aca_tol=1e-8, time_block=32)),
     ("f16", 16, dict(factor_dtype="f16", aca_tol=1e-8, time_block=16)),
     ("f64", 16, dict(factor_dtype="f64", aca_tol=1e-12, time_block=16)),
 ]

@@ -98,11 +98,15 @@ def test_two_fault_prescribed_aca_1e6_fp64_and_fp32():
     e32 = rel_err(f32, ref)
     f16b, _ = gpu_prescribed(C1, SI.default_params(aca_tol=1e-6, factor_dtype="f32", time_block=16), V)
     e16b = rel_err(f16b, ref)
+    f32b, op32 = gpu_prescribed(C1, SI.default_params(aca_tol=1e-6, factor_dtype="f32", time_block=32), V)
+    e32b = rel_err(f32b, ref)
     print(f"[gpu] aca 1e-6: fp64 err {e64:.3e}, fp32 err {e32:.3e}, fp32 S=16 (MFMA) err {e16b:.3e}, "
-          f"stored/dense {op.info['stored_entries'] / op.info['dense_entries']:.3f}")
+          f"fp32 S=32 err {e32b:.3e}, stored/dense {op.info['stored_entries'] / op.info['dense_entries']:.3f}")
+    assert op32.info["n_segments"] > 0
     assert e64 < 1e-5
     assert e32 < 1e-4
     assert e16b < 1e-4
+    assert e32b < 1e-4
 
 
 # ----------------------------------------------------------------- ragged, saturated windows
@@ -246,7 +250,7 @@ def test_kernel_timing_counts_launches():
     assert n == 7 and ms > 0
 
 
-@pytest.mark.parametrize("SB", [8, 16])
+@pytest.mark.parametrize("SB", [8, 16, 32])
 def test_plain_and_blocked_orders_agree(SB):
     # one operator built with S = SB, evaluated once per step (S = 1) and per block
     # (S = 16 in FP32 runs on the matrix cores)

@@ -90,7 +90,7 @@ def test_self_tail_matches_oracle():
 
 
 @pytest.mark.parametrize("compress,S,dtype", [(0, 1, "f64"), (1, 1, "f64"), (1, 4, "f64"), (0, 16, "f64"),
-                                              (0, 16, "f32"), (1, 16, "f32")])
+                                              (0, 16, "f32"), (1, 16, "f32"), (1, 32, "f32")])
 def test_lag_matrices_match_dense_kernel(compress, S, dtype):
     # FP32 with S = 16 packs its far list in the segment layout of the matrix-core
     # kernel (inner index fastest, rows padded to 8 values, items grouped by rows)
