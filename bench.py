@@ -47,20 +47,21 @@ def measured_traffic(kname, args=None):
 
 
 KIB = 1024
-# HBM bytes of the timed far launch (five-fault workload, time block 16: the part with
-# lags >= 2S), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of this script (KiB per
+# HBM bytes of the timed far launch (five-fault workload, the part with lags >= 2S at the
+# form's time block: 32 for the FP32 headline, 16 for the other forms), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of this script (KiB per
 # dispatch), scaled by what the same counters read for a plain 2 GiB copy (2.0 for
 # FETCH_SIZE, 1.0 for WRITE_SIZE); each entry names the SHA-256 of the sources it was
 # measured on. The 16-bit forms' timed launch is the 16-bit kernel plus the FP32 pass
 # over the near-field blocks (k_hmat_mfma16).
-_K = "d1afe5e9c951f88a41142886038ab75342d3d73c8eda84b7e03b59209a7eaf79"    # kernels.hip
-_X = "12010c76f803850476217b6e6a6e2c600d65c0176337ca6a81ffc7a83fe26e93"    # kernels_x16.hip
-_B = "8d03690674b3e1038d45786406265121a53e7878ad2f0b0c1d34c6f8f6b1c523"    # build.cpp (item layout)
+_K = "b356a4168284d5794ec84ff58826d368597de9aab75841010a57eca0cdfdbd6e"    # kernels.hip
+_X = "c9f2757e74695ce3ca61131b0e0ad5be25f650038b0d56431c02b913c3e74894"    # kernels_x16.hip
+_B = "e191b9dc91ff8717880dd9a6989b958d7f8a47580343d045b78a67ee4e43cd8c"    # build.cpp (item layout)
 _SRC = {"kernels.hip": _K, "kernels_x16.hip": _X, "build.cpp": _B}
 MEASURED_TRAFFIC = {
-    "k_hmat_x16<f32,16 columns>": (2.0 * 10_048_900 * KIB + 239_937 * KIB, _SRC),
-    "k_hmat_x16<f16,16 columns>": (2.0 * 4_516_700 * KIB + 102_368 * KIB + 2.0 * 1_252_050 * KIB + 22_340 * KIB, _SRC),
-    "k_hmat_x16<bf16,16 columns>": (2.0 * 4_412_570 * KIB + 102_408 * KIB + 2.0 * 1_252_050 * KIB + 22_340 * KIB,
+    "k_hmat_x16<f32,32 columns>": (2.0 * 9_525_360 * KIB + 589_297 * KIB, _SRC),
+    "k_hmat_x16<f32,16 columns>": (2.0 * 10_049_700 * KIB + 239_935 * KIB, _SRC),
+    "k_hmat_x16<f16,16 columns>": (2.0 * 4_516_730 * KIB + 102_364 * KIB + 2.0 * 1_252_060 * KIB + 22_340 * KIB, _SRC),
+    "k_hmat_x16<bf16,16 columns>": (2.0 * 4_412_150 * KIB + 102_408 * KIB + 2.0 * 1_252_060 * KIB + 22_340 * KIB,
                                     _SRC),
 }
 
