@@ -505,6 +505,23 @@ def run_ensemble(args):
         "stored_over_dense": info["stored_entries"] / info["dense_entries"],
     }
     print(f"[bench] timed {args.steps} steps: {wall:.3f} s", file=sys.stderr, flush=True)
+    # the same steps as replays of one captured graph of 16 steps (no kernel timing inside)
+    st.set_timing(False)
+    st.set_graph(True)
+    st.step(16, stream=s)
+    torch.cuda.synchronize()
+    w1 = time.perf_counter()
+    st.step(args.steps, stream=s)
+    torch.cuda.synchronize()
+    wall_g = time.perf_counter() - w1
+    st.check(stream=s)
+    gi = st.graph_info()
+    out["captured"] = {"value": N * nv * args.steps / wall_g, "ms_per_step": wall_g / args.steps * 1e3,
+                       "replays": gi["replays"], "steps_per_replay": gi["steps_per_replay"],
+                       "note": "the timed steps again, whole 16-step blocks replayed from one HIP graph "
+                               "(seas_state_set_graph)"}
+    print(f"[bench] captured: {wall_g / args.steps * 1e3:.3f} ms per step ({gi['replays']} replays)",
+          file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 
