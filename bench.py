@@ -783,6 +783,10 @@ def main():
 
     op, info, st, build_s, err32 = prepare(args.dtype)
     N = op.N
+    # tile tuning of the far pass on this operator and state (FP32 segment builds)
+    tune = op.tune(st, stream=s, reps=3)
+    print(f"[bench] tuned far-pass variant {tune['choice']}: {tune['ms']} ms per launch", file=sys.stderr,
+          flush=True)
     elem_bytes = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}[args.dtype]
     S = info["time_block"]
     main_run = timed_on(st, info, elem_bytes, S, K)
@@ -836,6 +840,11 @@ def main():
             "steady_state_serial_kernel_avg_ms": serial["avg_ms"]},
         "build_s": build_s,
         "stored_over_dense": info["stored_entries"] / info["dense_entries"],
+        "autotune": {"choice": tune["choice"], "ms_per_launch": tune["ms"],
+                     "variants": ["prefetch 2, 4 waves/SIMD", "prefetch 2, 3 waves/SIMD", "prefetch 3, 3 waves/SIMD"],
+                     "note": "far launch of one time block per variant of the FP32 segment kernel on this "
+                             "operator and state (seas_operator_tune); the fastest is used for the timed steps; "
+                             "-1 where the operator has one form"},
     }
     if plain is not None:
         out["plain"] = {"value": plain["value"], "ms_per_step": plain["ms_per_step"],

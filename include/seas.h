@@ -407,6 +407,25 @@ seas_status seas_state_set_timing(seas_state_t* st, int32_t enable);
  * stream is non-blocking, so a caller's stream of any kind overlaps with it. */
 seas_status seas_state_set_overlap(seas_state_t* st, int32_t enable);
 
+/* Tile tuning of the far pass on the operator's own factors. FP32 operators on the
+ * matrix-core segment kernel (time_block 16 or 32) have 3 compiled variants of it,
+ * which differ in how far ahead the global operand is loaded and in how many waves
+ * per SIMD their registers are fitted to (0: 2 steps ahead, 4 waves; 1: 2 steps, 3
+ * waves; 2: 3 steps, 3 waves); every variant computes the same sums in the same
+ * order, so results are identical. seas_operator_tune times the far launch of a
+ * whole time block (the lags >= 2S) of each variant on the state's current history,
+ * reps launches each after one untimed, on the stream (it synchronises), writes the
+ * average milliseconds per launch to ms[0..2] and selects the fastest (*choice) for
+ * every later launch of the operator; the state's fields are not changed (only its
+ * partial-sum buffer, which the next time block rewrites). Other operators have one
+ * form: ms[] = -1 and *choice = the current variant. A graph captured before keeps
+ * the variant it recorded. ms and choice may be NULL. INVALID_ARG for reps < 1,
+ * MISMATCH for a state of another operator. seas_operator_set_tune selects a variant
+ * directly (INVALID_ARG outside 0..2). */
+seas_status seas_operator_tune(seas_op_t* op, seas_state_t* st, void* stream, int32_t reps, double* ms,
+                               int32_t* choice);
+seas_status seas_operator_set_tune(seas_op_t* op, int32_t variant);
+
 /* Captured steps: with enable = 1, seas_step runs the fixed steps that fill whole
  * time blocks (S steps; 16 steps when every step applies the far list, S = 1 or
  * seas_state_set_time_block(1)) as replays of one HIP graph per state, captured at

@@ -112,6 +112,8 @@ def lib():
             "seas_state_set_timing": (i32, [vp, i32]),
             "seas_state_set_overlap": (i32, [vp, i32]),
             "seas_state_set_graph": (i32, [vp, i32]),
+            "seas_operator_tune": (i32, [vp, vp, vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+            "seas_operator_set_tune": (i32, [vp, i32]),
             "seas_state_graph_info": (i32, [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
             "seas_state_progress": (i32, [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
             "seas_state_set_gamma_cap": (i32, [vp, C.c_int64]),
@@ -244,6 +246,17 @@ class Operator:
         _check(lib().seas_operator_self_table(self.h, k, n, out.ctypes.data_as(C.POINTER(C.c_double)),
                                               m, C.byref(W)))
         return out
+
+    def tune(self, state, stream=0, reps=3):
+        """Time the far launch of each compiled variant on the state's history and keep
+        the fastest: {"ms": [per variant, -1 where not applicable], "choice": variant}."""
+        ms = (C.c_double * 3)()
+        ch = C.c_int32(0)
+        _check(lib().seas_operator_tune(self.h, state.h, _ptr(stream), int(reps), ms, C.byref(ch)))
+        return {"ms": [float(x) for x in ms], "choice": ch.value}
+
+    def set_tune(self, variant):
+        _check(lib().seas_operator_set_tune(self.h, int(variant)))
 
     def lag_matrix(self, a, b, T, p, q):
         out = np.zeros((p, q))

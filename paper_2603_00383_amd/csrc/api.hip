@@ -1505,6 +1505,68 @@ seas_status seas_state_progress(const seas_state_t* st, int64_t* steps_taken, in
   });
 }
 
+seas_status seas_operator_set_tune(seas_op_t* op, int32_t variant) {
+  return guard([&] {
+    checked(op);
+    if (variant < 0 || variant >= kTuneVariants) throw Error(SEAS_ERR_INVALID_ARG, "no such variant");
+    op->h.x16_tune = variant;
+  });
+}
+
+seas_status seas_operator_tune(seas_op_t* op, seas_state_t* st, void* stream, int32_t reps, double* ms,
+                               int32_t* choice) {
+  return guard([&] {
+    checked(op);
+    if (!st || st->op != op) throw Error(SEAS_ERR_MISMATCH, "state belongs to another operator");
+    if (reps < 1) throw Error(SEAS_ERR_INVALID_ARG, "reps >= 1");
+    HostOp& h = op->h;
+    const bool tunable = h.seg && !h.x16;
+    if (ms)
+      for (int c = 0; c < kTuneVariants; ++c) ms[c] = -1.0;
+    if (!tunable) {
+      if (choice) *choice = h.x16_tune;
+      return;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const int S = h.time_block;
+    const int64_t head = st->step;
+    int best = 0;
+    double best_ms = 0.0;
+    try {
+      for (int c = 0; c < kTuneVariants; ++c) {
+        h.x16_tune = c;
+        // the far sums of a whole time block land in the state's partial buffer,
+        // which the next block start overwrites before reading
+        launch_far(op, st, head, kFarRest, S, st->partials_far, s);
+        HIPCHK(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; ++r) launch_far(op, st, head, kFarRest, S, st->partials_far, s);
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
+        float t = 0.0f;
+        HIPCHK(hipEventElapsedTime(&t, e0, e1));
+        const double per = (double)t / reps;
+        if (ms) ms[c] = per;
+        if (c == 0 || per < best_ms) {
+          best = c;
+          best_ms = per;
+        }
+      }
+    } catch (...) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      h.x16_tune = 0;
+      throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h.x16_tune = best;
+    if (choice) *choice = best;
+  });
+}
+
 seas_status seas_state_set_graph(seas_state_t* st, int32_t enable) {
   return guard([&] {
     if (!st) throw Error(SEAS_ERR_INVALID_ARG, "null state");

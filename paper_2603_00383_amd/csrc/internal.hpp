@@ -56,6 +56,7 @@ constexpr int kHistMax = 6144;   // history values staged in LDS per item: (span
 constexpr int kColMax = 1024;    // low-rank columns (and lags) per item
 constexpr int kZMax = 2048;      // low-rank columns times steps per item
 constexpr int kMaxTimeBlock = 32;
+constexpr int kTuneVariants = 3;  // variants of the FP32 one-variant segment kernel
 // 16-bit factors (the matrix-core path): rows padded to 8 values (16 B)
 constexpr int kHist16 = 16384;   // 16-bit history values staged per item: span * variants * q8
 // ensemble products of 32 or more columns run two workgroups per CU (registers),
@@ -131,6 +132,7 @@ struct HostOp {
   int time_block = 1;
   int n_variants = 1;                 // friction variants sharing the operator (ensemble columns)
   int ncols = 1;                      // columns of the far-list products: time_block * n_variants
+  int x16_tune = 0;                   // variant of the FP32 one-variant segment kernel (seas_operator_tune)
   bool x16 = false;                   // far list in BF16/FP16 on the matrix cores, near list in FP32
   bool use_mfma = true;               // FP32, S = 16 far list on the matrix cores
   // far list in the segment layout of the matrix-core kernel (16-bit builds, and

@@ -4,9 +4,6 @@
 
 #include "device_common.hpp"
 
-#ifndef WIN_WAVES
-#define WIN_WAVES 4
-#endif
 namespace seas {
 
 // ------------------------------------------------------------------ segment matrix-core form
@@ -129,10 +126,21 @@ __device__ __forceinline__ void x16_kloop(int k0, int k1, FA A, FB B, mfma_f4 (&
   }
 }
 
+// Tuned variants of the FP32 one-variant instances (seas_operator_tune): the
+// prefetch depth of the global operand and the waves per SIMD the registers are
+// fitted to. The arithmetic and its order are the same in every variant.
+//   0: prefetch 2 steps, 4 waves (the 32-window instance spills 12 VGPRs for it)
+//   1: prefetch 2 steps, 3 waves
+//   2: prefetch 3 steps, 3 waves
+constexpr int x16_pf(int eb, int tune) { return eb == 4 ? (tune == 2 ? 3 : 2) : 8; }
+constexpr int x16_waves(bool scale, int nt, bool vfast, bool win, int tune) {
+  return (nt == 1 && !vfast) ? (scale ? 3 : (tune == 0 ? 4 : 3)) : (win ? (tune == 0 ? 4 : 3) : 2);
+}
+
 // WIN: one variant's time windows (NT = 2: 32 windows of FP32 factors), staged
 // with the 16-column budget so that four workgroups share a CU
-template <typename T16, typename TR, bool SCALE, int NT, bool VFAST, bool WIN>
-__global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT == 1 && !VFAST ? (SCALE ? 3 : 4) : (WIN ? WIN_WAVES : 2)))) void k_hmat_x16(
+template <typename T16, typename TR, bool SCALE, int NT, bool VFAST, bool WIN, int TUNE>
+__global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(x16_waves(SCALE, NT, VFAST, WIN, TUNE)))) void k_hmat_x16(
     const Item* __restrict__ items, const int32_t* __restrict__ seg_ptr, const int32_t* __restrict__ lagT,
     const int32_t* __restrict__ lagCol, const int32_t* __restrict__ lagColOff, const T16* __restrict__ arena,
     const TR* __restrict__ ring, int64_t head, int64_t R, int N, int S, int nv,
@@ -144,7 +152,7 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
   constexpr int EB = (int)sizeof(T16);  // bytes per stored value
   constexpr int G = 16 / EB;            // values per 16-byte group
   constexpr int RW = NT == 1 ? 8 : 4;   // row tiles per wave held across a segment
-  constexpr int PF = EB == 4 ? 2 : 8;   // inner steps whose global operand is loaded ahead
+  constexpr int PF = x16_pf(EB, TUNE);  // inner steps whose global operand is loaded ahead
   // staged history and projected values (seg_hist_limit, seg_z_limit + 16 bytes):
   // the same bytes for every value type
   constexpr int HL = (NT >= 2 && !WIN ? 2 * kHist16 : kHist16) * 2 / EB;
@@ -548,12 +556,12 @@ __global__ __launch_bounds__(kItemThreads) __attribute__((amdgpu_waves_per_eu(NT
   }
 }
 
-template <typename T16, typename TR, bool SCALE, int NT, bool VFAST = false, bool WIN = false>
+template <typename T16, typename TR, bool SCALE, int NT, bool VFAST = false, bool WIN = false, int TUNE = 0>
 static void x16_launch(const HostOp& h, const void* items, const int32_t* seg_ptr, const int32_t* lagT,
                        const int32_t* lagCol, const int32_t* lagColOff, const void* arena, const void* ring,
                        int64_t head, const double* tail_acc, float* partials, hipStream_t s, int nseg,
                        const int64_t* clk) {
-  hipLaunchKernelGGL((k_hmat_x16<T16, TR, SCALE, NT, VFAST, WIN>), dim3(nseg), dim3(kItemThreads), 0, s, (const Item*)items,
+  hipLaunchKernelGGL((k_hmat_x16<T16, TR, SCALE, NT, VFAST, WIN, TUNE>), dim3(nseg), dim3(kItemThreads), 0, s, (const Item*)items,
                      seg_ptr, lagT, lagCol, lagColOff, (const T16*)arena, (const TR*)ring, head, (int64_t)h.ring_len,
                      h.N, h.time_block, h.n_variants, tail_acc, (int64_t)h.tail_len, partials, clk);
 }
@@ -563,13 +571,20 @@ void launch_hmat_x16(const HostOp& h, const void* items, const int32_t* seg_ptr,
                      int64_t head, const double* tail_acc, float* partials, hipStream_t s, const int64_t* clk) {
   if (nseg < 1) return;
   const bool bf = h.prm.factor_dtype == SEAS_BF16;
-  if (!h.x16) {  // FP32 factors, one variant, 16 or 32 windows
-    if (h.ncols == 32)
-      x16_launch<float, float, false, 2, false, true>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring,
-                                                      head, tail_acc, partials, s, nseg, clk);
-    else
-      x16_launch<float, float, false, 1>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head, tail_acc,
-                                         partials, s, nseg, clk);
+  if (!h.x16) {  // FP32 factors, one variant, 16 or 32 windows, in the operator's tuned variant
+#define SEAS_X16_F32(TU)                                                                                      \
+  if (h.ncols == 32)                                                                                          \
+    x16_launch<float, float, false, 2, false, true, TU>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, \
+                                                        head, tail_acc, partials, s, nseg, clk);              \
+  else                                                                                                        \
+    x16_launch<float, float, false, 1, false, false, TU>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena,     \
+                                                         ring, head, tail_acc, partials, s, nseg, clk);
+    switch (h.x16_tune) {
+      case 1: SEAS_X16_F32(1) break;
+      case 2: SEAS_X16_F32(2) break;
+      default: SEAS_X16_F32(0) break;
+    }
+#undef SEAS_X16_F32
     return;
   }
   if (h.n_variants == 1) {
