@@ -464,6 +464,9 @@ def run_ensemble(args):
     print(f"[bench] state of {nv} variants created, warmup {args.warmup}", file=sys.stderr, flush=True)
     st.step(args.warmup, stream=s)
     st.check(stream=s)
+    tune = op.tune(st, stream=s, reps=2)
+    print(f"[bench] tuned far-pass variant {tune['choice']}: {tune['ms']} ms per launch", file=sys.stderr,
+          flush=True)
     st.set_timing(True)
     st.read_timing(stream=s)
     torch.cuda.synchronize()
@@ -503,6 +506,10 @@ def run_ensemble(args):
         "gpu_event_ms_per_step": e0.elapsed_time(e1) / args.steps,
         "build_s": build_s,
         "stored_over_dense": info["stored_entries"] / info["dense_entries"],
+        "autotune": {"choice": tune["choice"], "ms_per_launch": tune["ms"],
+                     "variants": ["prefetch 8", "prefetch 4", "prefetch 12"],
+                     "note": "far launch per variant of the 16-bit segment kernel on this operator and state "
+                             "(seas_operator_tune); the fastest is used for the timed steps"},
     }
     print(f"[bench] timed {args.steps} steps: {wall:.3f} s", file=sys.stderr, flush=True)
     # the same steps as replays of one captured graph of 16 steps (no kernel timing inside)
@@ -841,7 +848,8 @@ def main():
         "build_s": build_s,
         "stored_over_dense": info["stored_entries"] / info["dense_entries"],
         "autotune": {"choice": tune["choice"], "ms_per_launch": tune["ms"],
-                     "variants": ["prefetch 2, 4 waves/SIMD", "prefetch 2, 3 waves/SIMD", "prefetch 3, 3 waves/SIMD"],
+                     "variants": (["prefetch 2, 4 waves/SIMD", "prefetch 2, 3 waves/SIMD", "prefetch 3, 3 waves/SIMD"]
+                                  if args.dtype == "f32" else ["prefetch 8", "prefetch 4", "prefetch 12"]),
                      "note": "far launch of one time block per variant of the FP32 segment kernel on this "
                              "operator and state (seas_operator_tune); the fastest is used for the timed steps; "
                              "-1 where the operator has one form"},

@@ -407,13 +407,15 @@ seas_status seas_state_set_timing(seas_state_t* st, int32_t enable);
  * stream is non-blocking, so a caller's stream of any kind overlaps with it. */
 seas_status seas_state_set_overlap(seas_state_t* st, int32_t enable);
 
-/* Tile tuning of the far pass on the operator's own factors. FP32 operators on the
- * matrix-core segment kernel (time_block 16 or 32) have 3 compiled variants of it,
- * which differ in how far ahead the global operand is loaded and in how many waves
- * per SIMD their registers are fitted to (0: 2 steps ahead, 4 waves; 1: 2 steps, 3
- * waves; 2: 3 steps, 3 waves); every variant computes the same sums in the same
- * order, so results are identical. seas_operator_tune times the far launch of a
- * whole time block (the lags >= 2S) of each variant on the state's current history,
+/* Tile tuning of the far pass on the operator's own factors. Operators on the
+ * matrix-core segment kernel (FP32 with time_block 16 or 32, BF16 / FP16 with one
+ * variant or ensembles) have 3 compiled variants of it, which differ in how far
+ * ahead the global operand is loaded and, for FP32, in how many waves per SIMD their
+ * registers are fitted to (FP32 0: 2 steps ahead, 4 waves; 1: 2 steps, 3 waves; 2: 3
+ * steps, 3 waves; 16-bit 0: 8 steps; 1: 4; 2: 12); every variant computes the same
+ * sums in the same order, so results are identical. seas_operator_tune times the
+ * far launch of a whole time block (the lags >= 2S; ensembles: the whole far list of
+ * a step, whose FP32 list is not tuned) of each variant on the state's current history,
  * reps launches each after one untimed, on the stream (it synchronises), writes the
  * average milliseconds per launch to ms[0..2] and selects the fastest (*choice) for
  * every later launch of the operator; the state's fields are not changed (only its

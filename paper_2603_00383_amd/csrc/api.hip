@@ -1520,7 +1520,7 @@ seas_status seas_operator_tune(seas_op_t* op, seas_state_t* st, void* stream, in
     if (!st || st->op != op) throw Error(SEAS_ERR_MISMATCH, "state belongs to another operator");
     if (reps < 1) throw Error(SEAS_ERR_INVALID_ARG, "reps >= 1");
     HostOp& h = op->h;
-    const bool tunable = h.seg && !h.x16;
+    const bool tunable = h.seg;
     if (ms)
       for (int c = 0; c < kTuneVariants; ++c) ms[c] = -1.0;
     if (!tunable) {
@@ -1539,10 +1539,11 @@ seas_status seas_operator_tune(seas_op_t* op, seas_state_t* st, void* stream, in
       for (int c = 0; c < kTuneVariants; ++c) {
         h.x16_tune = c;
         // the far sums of a whole time block land in the state's partial buffer,
-        // which the next block start overwrites before reading
-        launch_far(op, st, head, kFarRest, S, st->partials_far, s);
+        // which the next block start overwrites before reading (ensembles: every step)
+        const FarPart part = S > 1 ? kFarRest : kFarAll;
+        launch_far(op, st, head, part, S, st->partials_far, s);
         HIPCHK(hipEventRecord(e0, s));
-        for (int r = 0; r < reps; ++r) launch_far(op, st, head, kFarRest, S, st->partials_far, s);
+        for (int r = 0; r < reps; ++r) launch_far(op, st, head, part, S, st->partials_far, s);
         HIPCHK(hipEventRecord(e1, s));
         HIPCHK(hipEventSynchronize(e1));
         float t = 0.0f;

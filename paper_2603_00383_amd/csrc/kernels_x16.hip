@@ -126,13 +126,14 @@ __device__ __forceinline__ void x16_kloop(int k0, int k1, FA A, FB B, mfma_f4 (&
   }
 }
 
-// Tuned variants of the FP32 one-variant instances (seas_operator_tune): the
-// prefetch depth of the global operand and the waves per SIMD the registers are
-// fitted to. The arithmetic and its order are the same in every variant.
-//   0: prefetch 2 steps, 4 waves (the 32-window instance spills 12 VGPRs for it)
-//   1: prefetch 2 steps, 3 waves
-//   2: prefetch 3 steps, 3 waves
-constexpr int x16_pf(int eb, int tune) { return eb == 4 ? (tune == 2 ? 3 : 2) : 8; }
+// Tuned variants of the operator's far kernel (seas_operator_tune): the prefetch
+// depth of the global operand and, for the FP32 one-variant instances, the waves
+// per SIMD the registers are fitted to. The arithmetic and its order are the same
+// in every variant.
+//   FP32:   0: prefetch 2 steps, 4 waves (the 32-window instance spills 12 VGPRs
+//              for it); 1: prefetch 2 steps, 3 waves; 2: prefetch 3 steps, 3 waves
+//   16-bit: 0: prefetch 8 steps; 1: 4 steps; 2: 12 steps (waves as untuned)
+constexpr int x16_pf(int eb, int tune) { return eb == 4 ? (tune == 2 ? 3 : 2) : (tune == 1 ? 4 : tune == 2 ? 12 : 8); }
 constexpr int x16_waves(bool scale, int nt, bool vfast, bool win, int tune) {
   return (nt == 1 && !vfast) ? (scale ? 3 : (tune == 0 ? 4 : 3)) : (win ? (tune == 0 ? 4 : 3) : 2);
 }
@@ -587,24 +588,37 @@ void launch_hmat_x16(const HostOp& h, const void* items, const int32_t* seg_ptr,
 #undef SEAS_X16_F32
     return;
   }
-  if (h.n_variants == 1) {
-    if (bf) x16_launch<__bf16, float, false, 1>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head, tail_acc, partials, s, nseg, clk);
-    else x16_launch<_Float16, float, true, 1>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head, tail_acc, partials, s, nseg, clk);
-    return;
+  // one variant: 16 windows; ensembles: BF16 with a BF16 rate history, or FP16 with
+  // an FP32 one scaled per item; in the operator's tuned variant
+#define SEAS_X16_ONE(TU)                                                                                      \
+  if (bf) x16_launch<__bf16, float, false, 1, false, false, TU>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, \
+                                                                ring, head, tail_acc, partials, s, nseg, clk);  \
+  else x16_launch<_Float16, float, true, 1, false, false, TU>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, \
+                                                              ring, head, tail_acc, partials, s, nseg, clk);
+#define SEAS_X16_ENS(NT, TU)                                                                                  \
+  if (bf) x16_launch<__bf16, __bf16, false, NT, true, false, TU>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, \
+                                                                 ring, head, tail_acc, partials, s, nseg, clk); \
+  else x16_launch<_Float16, float, true, NT, false, false, TU>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, \
+                                                               ring, head, tail_acc, partials, s, nseg, clk);
+#define SEAS_X16_TUNED(TU)                   \
+  if (h.n_variants == 1) {                   \
+    SEAS_X16_ONE(TU)                         \
+  } else {                                   \
+    switch (h.ncols) {                       \
+      case 16: SEAS_X16_ENS(1, TU) break;    \
+      case 32: SEAS_X16_ENS(2, TU) break;    \
+      case 64: SEAS_X16_ENS(4, TU) break;    \
+      default: break;                        \
+    }                                        \
   }
-  // ensembles: BF16 with a BF16 rate history, or FP16 with an FP32 one scaled per item
-#define SEAS_X16_ENS(NT)                                                                                      \
-  if (bf) x16_launch<__bf16, __bf16, false, NT, true>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head, \
-                                                      tail_acc, partials, s, nseg, clk);                                \
-  else x16_launch<_Float16, float, true, NT>(h, items, seg_ptr, lagT, lagCol, lagColOff, arena, ring, head,       \
-                                             tail_acc, partials, s, nseg, clk);
-  switch (h.ncols) {
-    case 16: SEAS_X16_ENS(1) break;
-    case 32: SEAS_X16_ENS(2) break;
-    case 64: SEAS_X16_ENS(4) break;
-    default: break;
+  switch (h.x16_tune) {
+    case 1: SEAS_X16_TUNED(1) break;
+    case 2: SEAS_X16_TUNED(2) break;
+    default: SEAS_X16_TUNED(0) break;
   }
+#undef SEAS_X16_TUNED
 #undef SEAS_X16_ENS
+#undef SEAS_X16_ONE
 }
 
 void launch_hmat_seg32(const HostOp& h, const void* items, const int32_t* seg_ptr, const int32_t* lagT,
