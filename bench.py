@@ -28,12 +28,13 @@ HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0   # dense matrix-core peak
 METRIC = "element-steps/s (stress eval) vs plain at rel err≤1e-4; p50/p99 window latency"
 
-def measured_traffic(kname, args=None):
-    """HBM bytes per far pass from the table below, or None when a source file it
-    depends on changed since the counters were taken or the inputs are not the
-    default ones (seed 0, ACA 1e-6) the counters were taken on."""
+def measured_traffic(kname, args=None, variant=0):
+    """HBM bytes per far pass from the table below (for the tuned variant of the
+    segment kernel in use), or None when a source file it depends on changed since
+    the counters were taken or the inputs are not the default ones (seed 0, ACA 1e-6)
+    the counters were taken on."""
     import hashlib
-    entry = MEASURED_TRAFFIC.get(kname)
+    entry = MEASURED_TRAFFIC.get((kname, variant))
     if args is not None and (args.seed != 0 or args.aca != 1e-6):
         return None
     if entry is None:
@@ -48,21 +49,25 @@ def measured_traffic(kname, args=None):
 
 KIB = 1024
 # HBM bytes of the timed far launch (five-fault workload, the part with lags >= 2S at the
-# form's time block: 32 for the FP32 headline, 16 for the other forms), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of this script (KiB per
-# dispatch), scaled by what the same counters read for a plain 2 GiB copy (2.0 for
+# form's time block: 32 for the FP32 headline, 16 for the other forms), from rocprofv3
+# --pmc FETCH_SIZE and WRITE_SIZE runs of this script (KiB per dispatch), scaled by what the same counters read for a plain 2 GiB copy (2.0 for
 # FETCH_SIZE, 1.0 for WRITE_SIZE); each entry names the SHA-256 of the sources it was
 # measured on. The 16-bit forms' timed launch is the 16-bit kernel plus the FP32 pass
 # over the near-field blocks (k_hmat_mfma16).
 _K = "b356a4168284d5794ec84ff58826d368597de9aab75841010a57eca0cdfdbd6e"    # kernels.hip
-_X = "c9f2757e74695ce3ca61131b0e0ad5be25f650038b0d56431c02b913c3e74894"    # kernels_x16.hip
+_X = "acde92eb022c298f9c457827ac8ce58d10afdfe13f6a663bd201dd9fcbc2ebaa"    # kernels_x16.hip
 _B = "e191b9dc91ff8717880dd9a6989b958d7f8a47580343d045b78a67ee4e43cd8c"    # build.cpp (item layout)
 _SRC = {"kernels.hip": _K, "kernels_x16.hip": _X, "build.cpp": _B}
+# (kernel, tuned variant of the segment kernel) -> bytes per timed launch
 MEASURED_TRAFFIC = {
-    "k_hmat_x16<f32,32 columns>": (2.0 * 9_525_360 * KIB + 589_297 * KIB, _SRC),
-    "k_hmat_x16<f32,16 columns>": (2.0 * 10_049_700 * KIB + 239_935 * KIB, _SRC),
-    "k_hmat_x16<f16,16 columns>": (2.0 * 4_516_730 * KIB + 102_364 * KIB + 2.0 * 1_252_060 * KIB + 22_340 * KIB, _SRC),
-    "k_hmat_x16<bf16,16 columns>": (2.0 * 4_412_150 * KIB + 102_408 * KIB + 2.0 * 1_252_060 * KIB + 22_340 * KIB,
-                                    _SRC),
+    ("k_hmat_x16<f32,32 columns>", 0): (2.0 * 10_265_900 * KIB + 885_138 * KIB, _SRC),
+    ("k_hmat_x16<f32,32 columns>", 1): (2.0 * 9_526_570 * KIB + 594_729 * KIB, _SRC),
+    ("k_hmat_x16<f32,32 columns>", 2): (2.0 * 9_529_830 * KIB + 601_923 * KIB, _SRC),
+    ("k_hmat_x16<f32,16 columns>", 0): (2.0 * 10_049_300 * KIB + 239_933 * KIB, _SRC),
+    ("k_hmat_x16<f16,16 columns>", 0): (2.0 * 4_516_800 * KIB + 102_364 * KIB + 2.0 * 1_252_080 * KIB + 22_340 * KIB,
+                                        _SRC),
+    ("k_hmat_x16<bf16,16 columns>", 0): (2.0 * 4_412_090 * KIB + 102_407 * KIB + 2.0 * 1_252_080 * KIB + 22_340 * KIB,
+                                         _SRC),
 }
 
 
@@ -813,7 +818,7 @@ def main():
     else:
         t = 'float' if args.dtype == 'f32' else 'double'
         kname = f"k_hmat<{t},{t},{S}>"
-    traffic = measured_traffic(kname, args)
+    traffic = measured_traffic(kname, args, tune["choice"])
     out = {
         "metric": METRIC,
         "value": N * K / wall,
