@@ -420,10 +420,12 @@ seas_status seas_state_set_overlap(seas_state_t* st, int32_t enable);
  * average milliseconds per launch to ms[0..2] and selects the fastest (*choice) for
  * every later launch of the operator; the state's fields are not changed (only its
  * partial-sum buffer, which the next time block rewrites). Other operators have one
- * form: ms[] = -1 and *choice = the current variant. A graph captured before keeps
- * the variant it recorded. ms and choice may be NULL. INVALID_ARG for reps < 1,
- * MISMATCH for a state of another operator. seas_operator_set_tune selects a variant
- * directly (INVALID_ARG outside 0..2). */
+ * form: ms[] = -1 and *choice = the current variant. The choice is a setting of the
+ * operator, read when a far launch is enqueued: tune or set it while no other thread
+ * enqueues steps of the operator's states. A graph captured before keeps the variant
+ * it recorded. ms and choice may be NULL. INVALID_ARG for reps < 1, MISMATCH for a
+ * state of another operator. seas_operator_set_tune selects a variant directly
+ * (INVALID_ARG outside 0..2). */
 seas_status seas_operator_tune(seas_op_t* op, seas_state_t* st, void* stream, int32_t reps, double* ms,
                                int32_t* choice);
 seas_status seas_operator_set_tune(seas_op_t* op, int32_t variant);
