@@ -229,10 +229,11 @@ def cpu_leg(seed):
 
 def run_precision(args):
     """Trajectory error of the reduced-precision forms: the five-fault SEAS step loop
-    (5 x 600 elements, time block 16) from one near-nucleation state with no prior
-    slip, stepped 20,000 steps with FP64, FP32, FP16 and BF16 factors; slip, slip rate
-    and stress (f_self + f_int) compared with the FP64 run at 1k, 5k and 20k steps.
-    The FP64 path is the one the parity tests hold to the oracle at 1e-10."""
+    (5 x 600 elements, time block 16, and 32 for the FP32 headline form) from one
+    near-nucleation state with no prior slip, stepped 20,000 steps with FP64, FP32,
+    FP16 and BF16 factors; slip, slip rate and stress (f_self + f_int) compared with
+    the FP64 run at 1k, 5k and 20k steps. The FP64 path is the one the parity tests
+    hold to the oracle at 1e-10."""
     import numpy as np
     import torch
 
@@ -246,8 +247,10 @@ def run_precision(args):
     os.environ.setdefault("SEAS_VERBOSE", "1")
     s = torch.cuda.current_stream().cuda_stream
     snaps, timing, failed, peak = {}, {}, {}, {}
-    for d in ("f64", "f32", "f16", "bf16"):
-        params = SI.default_params(factor_dtype=d, aca_tol=args.aca, eta_H=2.0, leaf=50, time_block=16,
+    forms = {"f64": ("f64", 16), "f32": ("f32", 16), "f32_S32": ("f32", 32), "f16": ("f16", 16),
+             "bf16": ("bf16", 16)}
+    for d, (dtype, S) in forms.items():
+        params = SI.default_params(factor_dtype=dtype, aca_tol=args.aca, eta_H=2.0, leaf=50, time_block=S,
                                    state_update=args.state_update)
         print(f"[bench] building the {d} operator", file=sys.stderr, flush=True)
         op = P.Operator(faults, params)
@@ -278,7 +281,7 @@ def run_precision(args):
         op.close()
     ref = snaps["f64"]
     errors = {}
-    for d in ("f32", "f16", "bf16"):
+    for d in [f for f in forms if f != "f64"]:
         errors[d] = {}
         for m in marks:
             if m not in snaps[d] or m not in ref:
@@ -290,7 +293,7 @@ def run_precision(args):
     out = {"metric": "slip, slip-rate and stress error of the reduced-precision forms vs the FP64 path",
            "data": "synthetic",
            "config": {"workload": "five-fault SEAS step loop, 5 x 600 elements (N=3000, dx=50 m), time block "
-                                  f"16, ACA 1e-6, eta_H 2, leaf 50, near-nucleation state (tanh overstress "
+                                  f"16 (f32_S32: 32), ACA 1e-6, eta_H 2, leaf 50, near-nucleation state (tanh overstress "
                                   f"{args.bump:g} tau_eq), no prior slip, {args.state_update} state update",
                       "seed": args.seed, "steps": list(marks)},
            "errors": errors, "ms_per_step": timing, "failed": failed,
