@@ -606,7 +606,8 @@ def serving_leg(seed, dtype, templates, sizes, n_requests, rate, min_steps, max_
 
 def run_serving(args):
     dtype = args.dtype or "f16"
-    r = serving_leg(args.seed, dtype, args.templates, (500, 1000, 2000), args.requests, args.rate,
+    sizes = tuple(int(x) for x in args.sizes.split(","))
+    r = serving_leg(args.seed, dtype, args.templates, sizes, args.requests, args.rate,
                     args.min_steps, args.max_steps, args.chunk, args.budget_gb)
     out = {"metric": METRIC, "value": r["value"], "unit": r["unit"], "n_gpus": 1,
            "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
@@ -643,6 +644,7 @@ def main():
     ap.add_argument("--min-steps", type=int, default=200, help="serving: shortest window")
     ap.add_argument("--max-steps", type=int, default=2000, help="serving: longest window")
     ap.add_argument("--chunk", type=int, default=16, help="serving: steps per launch chunk")
+    ap.add_argument("--sizes", default="500,1000,2000", help="serving: template sizes N to draw from")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: device memory for states")
     ap.add_argument("--aca", type=float, default=1e-6)
     ap.add_argument("--seed", type=int, default=0)
