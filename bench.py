@@ -606,6 +606,7 @@ def serving_leg(seed, dtype, templates, sizes, n_requests, rate, min_steps, max_
 
 def run_serving(args):
     dtype = args.dtype or "f16"
+    os.environ.setdefault("SEAS_VERBOSE", "1")    # build and request-loop progress on stderr
     sizes = tuple(int(x) for x in args.sizes.split(","))
     r = serving_leg(args.seed, dtype, args.templates, sizes, args.requests, args.rate,
                     args.min_steps, args.max_steps, args.chunk, args.budget_gb)

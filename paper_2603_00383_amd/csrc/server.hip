@@ -15,6 +15,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <deque>
 #include <memory>
 #include <string>
@@ -42,6 +44,7 @@ struct Pool {
   hipEvent_t ev = nullptr;
   bool busy = false;
   int K = 0;  // steps of the chunk in flight
+  int64_t stepped = 0;  // steps the pool's state has taken (progress reports)
   std::vector<Slot> slots;
   std::deque<int> waiting;
 };
@@ -170,6 +173,8 @@ seas_status seas_server_run(seas_server_t* sv, seas_request_t* rq, int32_t n) {
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return rq[x].arrival_s < rq[y].arrival_s; });
     const auto t0 = std::chrono::steady_clock::now();
     auto now = [&] { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
+    // SEAS_VERBOSE: a line on stderr per finished request and per 1000 steps of a pool
+    const bool verbose = std::getenv("SEAS_VERBOSE") != nullptr;
     int next = 0, finished = 0;
     while (finished < n) {
       bool progress = false;
@@ -186,6 +191,10 @@ seas_status seas_server_run(seas_server_t* sv, seas_request_t* rq, int32_t n) {
           if (q != hipSuccess) throw Error(SEAS_ERR_HIP, "hipEventQuery failed");
           p.busy = false;
           progress = true;
+          if (verbose && (p.stepped + p.K) / 1000 != p.stepped / 1000)
+            std::fprintf(stderr, "[seas server] %.1f s: pool %d at step %lld\n", now(), (int)(&p - &sv->pools[0]),
+                         (long long)(p.stepped + p.K));
+          p.stepped += p.K;
           // a slot whose Newton solve failed is held at its last good step; the
           // others are not affected
           std::vector<int32_t> failed(p.nv, 0);
@@ -208,6 +217,9 @@ seas_status seas_server_run(seas_server_t* sv, seas_request_t* rq, int32_t n) {
                 raise_status(seas_read_state(p.st, fields[k], s, outs[k], (size_t)p.N, 0, p.stream), "seas_read_state");
             r.finish_s = now();
             ++finished;
+            if (verbose)
+              std::fprintf(stderr, "[seas server] %.1f s: request %d done (%d of %d)\n", r.finish_s, sl.req, finished,
+                           n);
             sl = Slot{};
             reset_slot(p, s, p.idle);  // the slot idles until the next request takes it
           }
