@@ -15,8 +15,8 @@ Section 2.3.1 of the paper, followed step by step:
   (eq. "mode_dependent_truncation");
 * the transforms are explicit sums (no FFT): D_n = sum_j delta_j e^{-2 pi i n j / M},
   n = 0..N_p, and the inverse keeps the real part of the Hermitian sum;
-* optional static tail of the truncated kernel (reading C2 of the scope table, not
-  in the paper): the window drops the part of K(n, .) beyond the cell of lag W_n,
+* optional static tail of the truncated kernel (a correction, not in the paper):
+  the window drops the part of K(n, .) beyond the cell of lag W_n,
   which carries static response; with ``tail=True`` each mode adds
   R_n D_n^{t-W_n-1}, R_n = |k_n| times the integral of K(n, .) over
   t >= (W_n + 1/2) dt, i.e. slip older than the window responds with the rest

@@ -1,4 +1,4 @@
-"""Pins of the self term's optional static tail (reading C2 of the scope table) (CPU).
+"""Pins of the self term's optional static tail, a correction not in the paper (CPU).
 
 The window of eq. "funcational_discretized_form" drops the part of K(n, .) beyond
 the cell of lag W_n. With the tail, slip older than the window responds with the
