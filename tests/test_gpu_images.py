@@ -66,6 +66,7 @@ CASES = [
     ("f64_dense_S1", 3e-10, dict(factor_dtype="f64", compress=0, time_block=1)),
     ("f64_aca_S8", 3e-10, dict(factor_dtype="f64", aca_tol=1e-13, time_block=8)),
     ("f32_seg_S16", 1e-5, dict(factor_dtype="f32", aca_tol=1e-10, time_block=16)),
+    ("f32_seg_S32", 1e-5, dict(factor_dtype="f32", aca_tol=1e-10, time_block=32)),
     ("f64_cluster", 3e-10, dict(factor_dtype="f64", aca_tol=1e-13, time_block=8, cluster_windows=1, leaf=8)),
 ]
 
@@ -76,7 +77,7 @@ def test_prescribed_with_free_surface(name, tol, kw):
     V = SI.prescribed_slip_rate(FAULTS, 120, 4)
     f, op = _prescribed(p, V)
     if name.startswith("f32_seg"):
-        assert op.info["n_segments"] > 0
+        assert op.info["n_segments"] > 0 and op.info["time_block"] == kw["time_block"]
     ref = OS.prescribed(OS.Problem(FAULTS, p), V)
     e = rel_err(f, ref)
     print(f"[gpu] free surface {name}: {e:.2e}", flush=True)

@@ -59,6 +59,7 @@ CASES = [
     ("f64_S1", 1e-10, dict(compress=1, aca_tol=1e-13, time_block=1)),
     ("f64_S16", 1e-10, dict(compress=1, aca_tol=1e-13, time_block=16)),
     ("f32_seg_S16", 1e-5, dict(factor_dtype="f32", compress=1, aca_tol=1e-10, time_block=16)),
+    ("f32_seg_S32", 1e-5, dict(factor_dtype="f32", compress=1, aca_tol=1e-10, time_block=32)),
 ]
 
 
