@@ -234,6 +234,34 @@ def test_rejects_degenerate_input():
     assert e.value.code == -1
 
 
+@pytest.mark.parametrize("kw", [
+    dict(time_block=32, factor_dtype="f64"),          # 32 windows need FP32 on the segment kernel
+    dict(time_block=32, factor_dtype="f16"),          # one-variant 16-bit forms need 16
+    dict(time_block=64, factor_dtype="f32"),
+    dict(time_block=12, factor_dtype="f32"),
+    dict(self_tail=2),
+    dict(free_surface=2),
+    dict(adaptive_dt=1, time_block=16),              # adaptive steps need unblocked evaluation
+    dict(adaptive_dt=2),
+    dict(gamma_max=-1, adaptive_dt=1),
+    dict(n_variants=8, factor_dtype="bf16", time_block=1),
+    dict(n_variants=16, factor_dtype="f32", time_block=1),
+    dict(n_variants=16, factor_dtype="bf16", time_block=16),
+])
+def test_rejects_invalid_options(kw):
+    _lib_or_skip()
+    with pytest.raises(P.SeasError) as e:
+        P.Operator(SI.two_fault_prescribed_faults(n_elem=16, dx=100.0), SI.default_params(host_only=1, **kw))
+    assert e.value.code == -1
+
+
+def test_accepts_the_valid_time_blocks():
+    faults = SI.two_fault_prescribed_faults(n_elem=16, dx=100.0)
+    for S, d in ((0, "f64"), (1, "f32"), (2, "f64"), (4, "f32"), (8, "f64"), (16, "f32"), (32, "f32"), (16, "f16")):
+        op = _op(faults, time_block=S, factor_dtype=d)
+        assert op.info["time_block"] == max(S, 1)
+
+
 def test_host_only_operator_refuses_evaluation():
     op = _op(SI.two_fault_prescribed_faults(n_elem=16, dx=800.0))
     n = op.N
