@@ -68,6 +68,9 @@ MEASURED_TRAFFIC = {
                                         _SRC),
     ("k_hmat_x16<bf16,16 columns>", 0): (2.0 * 4_412_090 * KIB + 102_407 * KIB + 2.0 * 1_252_080 * KIB + 22_340 * KIB,
                                          _SRC),
+    # the 64-variant BF16 ensemble's far pass (workload 4): the 16-bit kernel and the FP32 list
+    ("k_hmat_x16<bf16,64 columns>", 0): (2.0 * 32_277_300 * KIB + 1_215_790 * KIB + 2.0 * 6_920_150 * KIB
+                                         + 39_376 * KIB, _SRC),
 }
 
 
@@ -488,7 +491,8 @@ def run_ensemble(args):
     ms, n = st.read_timing(stream=s)
     st.check(stream=s)
     avg = ms / max(n, 1)
-    alg_bytes = info["far_entries"] * 2
+    # the 16-bit entries at 2 B, the FP32 list (near-field blocks, early lags, tail) at 4 B
+    alg_bytes = (info["far_entries"] - info["far_entries_f32"]) * 2 + info["far_entries_f32"] * 4
     flops = 2.0 * info["far_entries"] * info["ncols"]
     achieved = alg_bytes / (avg * 1e-3) / 1e9
     kname = f"k_hmat_x16<{dtype},{info['ncols']} columns>"
@@ -506,7 +510,7 @@ def run_ensemble(args):
                                "accumulation, FP64 state, ACA 1e-6, eta_H 2, leaf 50",
                    "seed": args.seed, "N": N, "variants": nv, "max_lag": info["max_lag"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname, args),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname, args, tune["choice"]),
                      "kernel": kname, "kernel_avg_ms": avg,
                      "algorithmic_bytes": alg_bytes, "launches_per_step": n / args.steps,
                      "mfma": {"achieved": tflops, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
