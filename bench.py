@@ -684,8 +684,8 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU; --gpus N > 1 is not supported "
-              "(sharding over GPUs is not built)", file=sys.stderr)
+        print("bench.py: runs on one GPU; --gpus N > 1 is not supported "
+              "(the path is not sharded over GPUs)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
