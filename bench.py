@@ -56,7 +56,7 @@ KIB = 1024
 # over the near-field blocks (k_hmat_mfma16).
 _K = "b356a4168284d5794ec84ff58826d368597de9aab75841010a57eca0cdfdbd6e"    # kernels.hip
 _X = "acde92eb022c298f9c457827ac8ce58d10afdfe13f6a663bd201dd9fcbc2ebaa"    # kernels_x16.hip
-_B = "e191b9dc91ff8717880dd9a6989b958d7f8a47580343d045b78a67ee4e43cd8c"    # build.cpp (item layout)
+_B = "cddf8d433d1bec38691053ddc4ec3a3d96373d0561bbdbc4743646ed0153b68b"    # build.cpp (item layout)
 _SRC = {"kernels.hip": _K, "kernels_x16.hip": _X, "build.cpp": _B}
 # (kernel, tuned variant of the segment kernel) -> bytes per timed launch
 MEASURED_TRAFFIC = {

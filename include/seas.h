@@ -151,7 +151,16 @@ typedef struct {
                            R_n = |k_n| int over t >= (W_n + 1/2) dt of K(n, t) (the static tail
                            the cut drops; with it a slip held longer than the windows gives the
                            fault's static stress). Not in the paper: an optional correction */
-  int32_t reserved_st;
+  int32_t aca_partial;  /* 0: every admissible block-lag is evaluated whole and compressed by ACA
+                           with full pivoting; 1: the lags at which every entry of an admissible
+                           block lies behind both wave fronts (cs T dt beyond the largest distance
+                           from a receiver midpoint to a source element edge) are compressed by
+                           ACA with partial pivoting to aca_tol / 4, from rows and columns of
+                           the block evaluated on demand (the cheaper construction the paper's
+                           outlook proposes in place of its SVD; the convergence estimate is
+                           checked on rows and columns spread over the block), then the SVD of
+                           the crosses truncated at 3 aca_tol / 4. Earlier lags, near-field
+                           blocks and static tails are built as with 0 (bit for bit) */
 } seas_params_t;
 
 typedef struct seas_op seas_op_t;

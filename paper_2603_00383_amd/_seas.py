@@ -42,7 +42,7 @@ class Params(C.Structure):
                 ("time_block", C.c_int32), ("n_variants", C.c_int32), ("state_update", C.c_int32),
                 ("cluster_windows", C.c_int32), ("adaptive_dt", C.c_int32), ("gamma_max", C.c_int32),
                 ("adapt_xi", C.c_double), ("free_surface", C.c_int32), ("reserved_fs", C.c_int32),
-                ("surface_y", C.c_double), ("self_tail", C.c_int32), ("reserved_st", C.c_int32)]
+                ("surface_y", C.c_double), ("self_tail", C.c_int32), ("aca_partial", C.c_int32)]
 
 
 class OpInfo(C.Structure):
@@ -182,6 +182,7 @@ def make_params(p):
     q.free_surface = int(p.get("free_surface", 0))
     q.surface_y = float(p.get("surface_y", 0.0))
     q.self_tail = int(p.get("self_tail", 0))
+    q.aca_partial = int(p.get("aca_partial", 0))
     return q
 
 

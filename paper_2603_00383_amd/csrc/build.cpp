@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -326,6 +327,226 @@ static int aca_full(const double* A, int p, int q, double tol, int kmax, std::ve
   return k;
 }
 
+// Adaptive cross approximation with partial pivoting (Bebendorf's construction):
+// the block is never formed; row(i, r) and col(j, c) evaluate one row or column,
+// and the residual of the rank-k approximation there is that minus the crosses
+// so far. Each cross takes the residual row's largest entry as pivot; the next
+// row is the largest entry of the new residual column among rows not yet used.
+// A cross with |u| |w| <= tol ||S_k||_F (S_k the approximation, its norm updated
+// exactly) proposes convergence; residual rows and columns away from the pivots,
+// spread over the block, then estimate ||A - S_k||_F, and the worst of those rows
+// is the next pivot unless the estimate is within tol ||S_k||_F. Same factor
+// layout and return values as aca_full (0: every row evaluated and zero).
+template <class Row, class Col>
+static int aca_partial(int p, int q, double tol, int kmax, Row&& row, Col&& col, std::vector<double>& U,
+                       std::vector<double>& Wf) {
+  U.clear();
+  Wf.clear();
+  std::vector<char> used(p, 0), usedc(q, 0);
+  std::vector<double> r(q), c(p), w(q), rc(q), cc(p);
+  int k = 0;
+  double s2 = 0.0;
+  auto residual_row = [&](int ii, double* out) {
+    row(ii, out);
+    for (int l = 0; l < k; ++l) {
+      const double ul = U[(size_t)l * p + ii];
+      const double* wl = &Wf[(size_t)l * q];
+      for (int j = 0; j < q; ++j) out[j] -= ul * wl[j];
+    }
+  };
+  auto residual_col = [&](int jj, double* out) {
+    col(jj, out);
+    for (int l = 0; l < k; ++l) {
+      const double wl = Wf[(size_t)l * q + jj];
+      const double* ul = &U[(size_t)l * p];
+      for (int ii = 0; ii < p; ++ii) out[ii] -= wl * ul[ii];
+    }
+  };
+  auto free_from = [](const std::vector<char>& u, int at) {  // first unused index from at, cyclically
+    const int n = (int)u.size();
+    for (int d = 0; d < n; ++d)
+      if (!u[(at + d) % n]) return (at + d) % n;
+    return -1;
+  };
+  const int nchk = std::min(4, std::min(p, q));
+  int i = p / 2;
+  while (i >= 0) {
+    used[i] = 1;
+    residual_row(i, r.data());
+    int js = 0;
+    for (int j = 1; j < q; ++j)
+      if (std::fabs(r[j]) > std::fabs(r[js])) js = j;
+    if (r[js] == 0.0) {  // row reproduced exactly: take the next unused one
+      i = free_from(used, i);
+      continue;
+    }
+    if (k >= kmax) return -1;
+    const double piv = r[js];
+    for (int j = 0; j < q; ++j) w[j] = r[j] / piv;
+    residual_col(js, c.data());
+    usedc[js] = 1;
+    double cross = 0.0, uu = 0.0, ww = 0.0;
+    for (int l = 0; l < k; ++l) {
+      double du = 0.0, dw = 0.0;
+      for (int ii = 0; ii < p; ++ii) du += U[(size_t)l * p + ii] * c[ii];
+      for (int j = 0; j < q; ++j) dw += Wf[(size_t)l * q + j] * w[j];
+      cross += du * dw;
+    }
+    for (int ii = 0; ii < p; ++ii) uu += c[ii] * c[ii];
+    for (int j = 0; j < q; ++j) ww += w[j] * w[j];
+    s2 += 2.0 * cross + uu * ww;
+    U.insert(U.end(), c.begin(), c.end());
+    Wf.insert(Wf.end(), w.begin(), w.end());
+    ++k;
+    int in = -1;
+    for (int ii = 0; ii < p; ++ii)
+      if (!used[ii] && (in < 0 || std::fabs(c[ii]) > std::fabs(c[in]))) in = ii;
+    if (uu * ww <= tol * tol * s2 || in < 0) {
+      double er = 0.0, ec = 0.0, worst = -1.0;
+      int nr = 0, ncl = 0, iw = -1;
+      for (int m = 0; m < nchk; ++m) {
+        const int ii = free_from(used, (int)(((2 * m + 1) * (int64_t)p) / (2 * nchk)));
+        if (ii >= 0) {
+          residual_row(ii, rc.data());
+          double e = 0.0;
+          for (int j = 0; j < q; ++j) e += rc[j] * rc[j];
+          er += e;
+          ++nr;
+          if (e > worst) {
+            worst = e;
+            iw = ii;
+          }
+        }
+        const int jj = free_from(usedc, (int)(((2 * m + 1) * (int64_t)q) / (2 * nchk)));
+        if (jj >= 0) {
+          residual_col(jj, cc.data());
+          for (int i2 = 0; i2 < p; ++i2) ec += cc[i2] * cc[i2];
+          ++ncl;
+        }
+      }
+      const double est = std::max(nr ? er * p / nr : 0.0, ncl ? ec * q / ncl : 0.0);
+      if (est <= tol * tol * s2 || iw < 0) break;
+      in = iw;
+    }
+    i = in;
+  }
+  if (k >= kmax) return -1;
+  return k;  // 0: every row was zero
+}
+
+// Orthonormalise the k columns of length n of X in place (Gram-Schmidt, twice);
+// R (k x k, row-major, upper triangular) gets X = Q R. A column that vanishes
+// against the earlier ones is set to zero with a zero diagonal.
+static void thin_qr(std::vector<double>& X, int n, int k, std::vector<double>& R) {
+  R.assign((size_t)k * k, 0.0);
+  for (int c = 0; c < k; ++c) {
+    double* x = &X[(size_t)c * n];
+    double n0 = 0.0;
+    for (int i = 0; i < n; ++i) n0 += x[i] * x[i];
+    for (int pass = 0; pass < 2; ++pass)
+      for (int l = 0; l < c; ++l) {
+        const double* ql = &X[(size_t)l * n];
+        double d = 0.0;
+        for (int i = 0; i < n; ++i) d += ql[i] * x[i];
+        for (int i = 0; i < n; ++i) x[i] -= d * ql[i];
+        R[(size_t)l * k + c] += d;
+      }
+    double nn = 0.0;
+    for (int i = 0; i < n; ++i) nn += x[i] * x[i];
+    if (!(nn > 1e-28 * n0)) {
+      for (int i = 0; i < n; ++i) x[i] = 0.0;
+      continue;
+    }
+    const double s = std::sqrt(nn);
+    R[(size_t)c * k + c] = s;
+    for (int i = 0; i < n; ++i) x[i] /= s;
+  }
+}
+
+// Truncate S = U W^T (rank k, the layout of aca_full) by its singular values:
+// U = Qu Ru, W = Qw Rw, Ru Rw^T = X Sigma Y^T by one-sided Jacobi rotations,
+// then U <- Qu X_r Sigma_r and W <- Qw Y_r with the smallest r whose dropped
+// singular values have a root sum of squares of at most tol ||S||_F. Returns r.
+static int svd_truncate(std::vector<double>& U, std::vector<double>& Wf, int p, int q, int k, double tol) {
+  std::vector<double> Ru, Rw;
+  thin_qr(U, p, k, Ru);
+  thin_qr(Wf, q, k, Rw);
+  // M = Ru Rw^T, stored by columns: M[c][r] = sum_l Ru[r][l] Rw[c][l]
+  std::vector<double> M((size_t)k * k, 0.0), Y((size_t)k * k, 0.0);
+  for (int c = 0; c < k; ++c)
+    for (int r = 0; r < k; ++r) {
+      double s = 0.0;
+      for (int l = 0; l < k; ++l) s += Ru[(size_t)r * k + l] * Rw[(size_t)c * k + l];
+      M[(size_t)c * k + r] = s;
+    }
+  for (int c = 0; c < k; ++c) Y[(size_t)c * k + c] = 1.0;
+  // columns of M rotated pairwise until orthogonal: M Y' = X Sigma
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    bool rotated = false;
+    for (int a = 0; a < k - 1; ++a)
+      for (int b = a + 1; b < k; ++b) {
+        double* ma = &M[(size_t)a * k];
+        double* mb = &M[(size_t)b * k];
+        double aa = 0.0, bb = 0.0, ab = 0.0;
+        for (int r = 0; r < k; ++r) {
+          aa += ma[r] * ma[r];
+          bb += mb[r] * mb[r];
+          ab += ma[r] * mb[r];
+        }
+        if (!(std::fabs(ab) > 1e-15 * std::sqrt(aa * bb))) continue;
+        rotated = true;
+        const double zeta = (bb - aa) / (2.0 * ab);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+        const double cn = 1.0 / std::sqrt(1.0 + t * t), sn = cn * t;
+        double* ya = &Y[(size_t)a * k];
+        double* yb = &Y[(size_t)b * k];
+        for (int r = 0; r < k; ++r) {
+          const double x = ma[r], y = mb[r];
+          ma[r] = cn * x - sn * y;
+          mb[r] = sn * x + cn * y;
+          const double u = ya[r], v = yb[r];
+          ya[r] = cn * u - sn * v;
+          yb[r] = sn * u + cn * v;
+        }
+      }
+    if (!rotated) break;
+  }
+  std::vector<double> sig(k);
+  std::vector<int> ord(k);
+  double tot = 0.0;
+  for (int c = 0; c < k; ++c) {
+    double s = 0.0;
+    for (int r = 0; r < k; ++r) s += M[(size_t)c * k + r] * M[(size_t)c * k + r];
+    sig[c] = std::sqrt(s);
+    tot += s;
+    ord[c] = c;
+  }
+  std::sort(ord.begin(), ord.end(), [&](int x, int y) { return sig[x] > sig[y]; });
+  int r = k;
+  double drop = 0.0;
+  while (r > 0 && drop + sig[ord[r - 1]] * sig[ord[r - 1]] <= tol * tol * tot) {
+    drop += sig[ord[r - 1]] * sig[ord[r - 1]];
+    --r;
+  }
+  std::vector<double> U2((size_t)r * p, 0.0), W2((size_t)r * q, 0.0);
+  for (int l = 0; l < r; ++l) {
+    const int c = ord[l];
+    const double* m = &M[(size_t)c * k];  // sigma x_c: U' column l = Qu m
+    const double* y = &Y[(size_t)c * k];  // W' column l = Qw y_c
+    double* u2 = &U2[(size_t)l * p];
+    double* w2 = &W2[(size_t)l * q];
+    for (int j = 0; j < k; ++j) {
+      const double* qu = &U[(size_t)j * p];
+      const double* qw = &Wf[(size_t)j * q];
+      for (int i = 0; i < p; ++i) u2[i] += qu[i] * m[j];
+      for (int i = 0; i < q; ++i) w2[i] += qw[i] * y[j];
+    }
+  }
+  U.swap(U2);
+  Wf.swap(W2);
+  return r;
+}
+
 // ============================================================== 16-bit storage
 // Round to nearest even. BF16 keeps the FP32 exponent and 8 significand bits;
 // FP16 is IEEE binary16 (values here are scaled into [-1, 1] first).
@@ -638,8 +859,21 @@ static void build_subblock(const HostOp& op, const BlockDesc& bd, const PairWin&
     if (lf.rank == 0) lf.D = K;
     lags.push_back(std::move(lf));
   };
-  if (T_hi >= T_lo) level(T_lo, G0);
-  for (int T = T_lo; T <= T_hi; ++T) {
+  // aca_partial: from the first lag at which cs T dt exceeds every corner distance,
+  // each entry of the block takes the primitive's branch behind both fronts at both
+  // time levels (a smooth function of the offsets), and those lags are compressed
+  // from rows and columns evaluated on demand
+  int T_part = INT_MAX;
+  if (lowrank_ok && op.prm.aca_partial) {
+    double rmax = 0.0;
+    for (int i = 0; i < p; ++i)
+      for (int e = 0; e < qe; ++e) rmax = std::max(rmax, std::hypot(re[(size_t)i * qe + e], r2i[i]));
+    T_part = std::max(T_lo, (int)(rmax / (cs * dt)));
+    while (!(cs * (T_part * dt) > rmax)) ++T_part;
+  }
+  const int T_whole = std::min(T_hi, T_part - 1);
+  if (T_whole >= T_lo) level(T_lo, G0);
+  for (int T = T_lo; T <= T_whole; ++T) {
     level(T + 1, G1);
     bool any = false;
     for (size_t e = 0; e < K.size(); ++e) {
@@ -648,6 +882,47 @@ static void build_subblock(const HostOp& op, const BlockDesc& bd, const PairWin&
     }
     std::swap(G0, G1);
     if (any) compress(T);
+  }
+  // one row or column of lag T, with the arithmetic of level() at T and T + 1
+  std::vector<double> C1(qe);
+  auto lag_row = [&](int T, int i, double* out) {
+    const double c0 = cs * (T * dt), c1 = cs * ((T + 1) * dt);
+    const double* r1e = &re[(size_t)i * qe];
+    for (int e = 0; e < qe; ++e) {
+      C[e] = corner(r1e[e], r2i[i], c0, fr.n1, fr.n2);
+      C1[e] = corner(r1e[e], r2i[i], c1, fr.n1, fr.n2);
+    }
+    for (int j = 0; j < q; ++j) out[j] = sgn * (C1[j] - C1[j + 1]) - sgn * (C[j] - C[j + 1]);
+  };
+  auto lag_col = [&](int T, int j, double* out) {
+    const double c0 = cs * (T * dt), c1 = cs * ((T + 1) * dt);
+    for (int i = 0; i < p; ++i) {
+      const double* r1e = &re[(size_t)i * qe + j];
+      const double g1 = sgn * (corner(r1e[0], r2i[i], c1, fr.n1, fr.n2) - corner(r1e[1], r2i[i], c1, fr.n1, fr.n2));
+      const double g0 = sgn * (corner(r1e[0], r2i[i], c0, fr.n1, fr.n2) - corner(r1e[1], r2i[i], c0, fr.n1, fr.n2));
+      out[i] = g1 - g0;
+    }
+  };
+  for (int T = std::max(T_lo, T_part); T <= T_hi; ++T) {
+    // crosses to a quarter of the tolerance, then the SVD of their sum truncated
+    // to the rest: the two errors together stay within aca_tol
+    const int km = in_list3(T) ? kmax32 : kmax;
+    int k = aca_partial(
+        p, q, 0.25 * op.prm.aca_tol, 2 * km, [&](int i, double* o) { lag_row(T, i, o); },
+        [&](int j, double* o) { lag_col(T, j, o); }, U, W);
+    if (k == 0) continue;  // the whole block-lag is zero
+    if (k > 0) k = svd_truncate(U, W, p, q, k, 0.75 * op.prm.aca_tol);
+    if (k > 0 && k < km) {
+      LagFactor lf;
+      lf.T = T;
+      lf.rank = k;
+      lf.U = U;
+      lf.W = W;
+      lags.push_back(std::move(lf));
+      continue;
+    }
+    for (int i = 0; i < p; ++i) lag_row(T, i, &K[(size_t)i * q]);  // rank cap: whole block, as above
+    compress(T);
   }
   int toff = 0;
   if (op.prm.int_tail) {
@@ -803,6 +1078,7 @@ void build_host(const seas_fault_t* fin, int nf, const seas_params_t& prm, HostO
   if (prm.free_surface != 0 && prm.free_surface != 1)
     throw Error(SEAS_ERR_INVALID_ARG, "free_surface must be 0 or 1");
   if (prm.self_tail != 0 && prm.self_tail != 1) throw Error(SEAS_ERR_INVALID_ARG, "self_tail must be 0 or 1");
+  if (prm.aca_partial != 0 && prm.aca_partial != 1) throw Error(SEAS_ERR_INVALID_ARG, "aca_partial must be 0 or 1");
   if (prm.free_surface) {
     if (!std::isfinite(prm.surface_y)) throw Error(SEAS_ERR_INVALID_ARG, "surface_y must be finite");
     const double y0 = prm.surface_y;

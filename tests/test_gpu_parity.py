@@ -109,6 +109,29 @@ def test_two_fault_prescribed_aca_1e6_fp64_and_fp32():
     assert e32b < 1e-4
 
 
+FIVE60 = SI.five_fault_network(seed=3, n_elem=60)
+
+
+@pytest.mark.parametrize("dtype,S,tol", [("f64", 1, 1e-5), ("f32", 32, 1e-4)])
+def test_partial_aca_prescribed_against_oracle(dtype, S, tol):
+    # aca_partial = 1: admissible blocks at lags behind both wave fronts are built
+    # from rows and columns of the block (partial pivoting, truncated SVD); a prior
+    # history longer than every window makes the evaluation read all of those lags
+    kw = dict(aca_tol=1e-6, leaf=10, eta_H=2.0, factor_dtype=dtype, time_block=S)
+    V = SI.prescribed_slip_rate(FIVE60, 40, 7, lo_exp=-6, hi_exp=0)
+    full = P.Operator(FIVE60, SI.default_params(host_only=1, **kw))
+    prior = SI.prescribed_slip_rate(FIVE60, full.info["max_lag"] + 10, 8, lo_exp=-6, hi_exp=0)
+    ref = oracle_prescribed(("five60", 0), FIVE60, SI.default_params(compress=0, leaf=10, eta_H=2.0), V, prior)
+    f, op = gpu_prescribed(FIVE60, SI.default_params(aca_partial=1, **kw), V, prior=prior)
+    f0, _ = gpu_prescribed(FIVE60, SI.default_params(**kw), V, prior=prior)
+    e, e0 = rel_err(f, ref), rel_err(f0, ref)
+    print(f"[gpu] partial aca {dtype} S={S}: err {e:.3e} (full pivoting {e0:.3e}), stored "
+          f"{op.info['stored_entries']} vs {full.info['stored_entries']}")
+    assert op.info["stored_entries"] != full.info["stored_entries"]
+    assert not np.array_equal(f, f0)
+    assert e < tol
+
+
 # ----------------------------------------------------------------- ragged, saturated windows
 RAG = [SI.fault(0, 0, 5.0, 1300.0, 13), SI.fault(300.0, 900.0, 70.0, 2900.0, 29),
        SI.fault(-1500.0, 2200.0, 140.0, 2000.0, 40)]

@@ -194,6 +194,52 @@ def test_ensemble_row_slices_reconstruct_the_kernel():
         assert np.linalg.norm(R - K) / np.linalg.norm(K) < 3 * 2.0 ** -9, T
 
 
+def _first_lag_behind_fronts(geo, a, b, r0, r1, s0, s1, dt):
+    """Smallest T with cs T dt beyond every distance from a receiver midpoint of the
+    block to an edge of its source elements (both fronts of the primitive passed)."""
+    B = geo[b]
+    edges = B.c[None, :] + (-0.5 * B.L + np.arange(s0, s1 + 1) * B.dx)[:, None] * B.t[None, :]
+    d = np.linalg.norm(geo[a].mid[r0:r1, None, :] - edges[None, :, :], axis=2).max()
+    return int(np.floor(d / (SI.CS * dt))) + 1
+
+
+@pytest.mark.parametrize("dtype,S", [("f64", 1), ("f32", 32)])
+def test_partial_aca_behind_the_fronts(dtype, S):
+    """aca_partial = 1: admissible blocks at lags behind both wave fronts are built
+    from rows and columns (partial pivoting, then truncated SVD); every other
+    block-lag and the static tails are the same bits as with full pivoting, and
+    the new factors reproduce the dense kernel block by block within the tolerance."""
+    faults = SI.five_fault_network(seed=3, n_elem=100)
+    tol = 1e-6
+    kw = dict(compress=1, aca_tol=tol, eta_H=2.0, leaf=20, time_block=S, factor_dtype=dtype)
+    op0, op1 = _op(faults, **kw), _op(faults, aca_partial=1, **kw)
+    geo = geometry.discretize(faults)
+    dt = geometry.time_step(geo, SI.CS)
+    exact = 1e-12 if dtype == "f64" else 1e-6
+    behind = changed = same = 0
+    for (a, b), (t0, t1) in op1.windows().items():
+        blks = op1.blocks(a, b)
+        first = [_first_lag_behind_fronts(geo, a, b, r0, r1, s0, s1, dt) for (r0, r1, s0, s1, _) in blks]
+        for T in sorted({int(x) for x in np.linspace(max(t0, 1), t1, 8)}):
+            K = I.pair_kernel(geo, a, b, T, dt, SI.CS)
+            R0 = op0.lag_matrix(a, b, T, 100, 100)
+            R1 = op1.lag_matrix(a, b, T, 100, 100)
+            for (r0, r1, s0, s1, adm), f in zip(blks, first):
+                sl = np.s_[r0:r1, s0:s1]
+                if not adm or T <= f - 2:
+                    assert np.array_equal(R1[sl], R0[sl]), (a, b, T, r0, s0)
+                    same += 1
+                elif T >= f + 1:
+                    nrm = np.linalg.norm(K[sl])
+                    assert np.linalg.norm(R1[sl] - K[sl]) <= (2 * tol + exact) * nrm, (a, b, T, r0, s0)
+                    behind += 1
+                    changed += not np.array_equal(R1[sl], R0[sl])
+        assert np.array_equal(op1.lag_matrix(a, b, -1, 100, 100), op0.lag_matrix(a, b, -1, 100, 100))
+    assert behind > 200 and same > 200
+    assert changed > behind // 2
+    assert op1.info["stored_entries"] < 1.01 * op0.info["stored_entries"]
+
+
 def test_16bit_rounding_matches_numpy():
     """The host conversions round to nearest even: FP16 against numpy's float16,
     BF16 against the top 16 bits of the FP32 pattern rounded to nearest even."""
@@ -240,6 +286,7 @@ def test_rejects_degenerate_input():
     dict(time_block=64, factor_dtype="f32"),
     dict(time_block=12, factor_dtype="f32"),
     dict(self_tail=2),
+    dict(aca_partial=2),
     dict(free_surface=2),
     dict(adaptive_dt=1, time_block=16),              # adaptive steps need unblocked evaluation
     dict(adaptive_dt=2),
