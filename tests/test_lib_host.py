@@ -203,19 +203,26 @@ def _first_lag_behind_fronts(geo, a, b, r0, r1, s0, s1, dt):
     return int(np.floor(d / (SI.CS * dt))) + 1
 
 
-@pytest.mark.parametrize("dtype,S", [("f64", 1), ("f32", 32)])
-def test_partial_aca_behind_the_fronts(dtype, S):
+@pytest.mark.parametrize("dtype,S,nv", [("f64", 1, 1), ("f32", 32, 1), ("bf16", 16, 1), ("f16", 1, 16)])
+def test_partial_aca_behind_the_fronts(dtype, S, nv):
     """aca_partial = 1: admissible blocks at lags behind both wave fronts are built
-    from rows and columns (partial pivoting, then truncated SVD); every other
-    block-lag and the static tails are the same bits as with full pivoting, and
-    the new factors reproduce the dense kernel block by block within the tolerance."""
+    from rows and columns (partial pivoting, then truncated SVD), and reproduce the
+    dense kernel block by block within the tolerance (plus the storage rounding).
+    With FP64 / FP32 storage every other block-lag and the static tails are the
+    same bits as with full pivoting; 16-bit items share one power-of-two scale over
+    their lags, so there the other block-lags are held to the rounding bound."""
     faults = SI.five_fault_network(seed=3, n_elem=100)
     tol = 1e-6
-    kw = dict(compress=1, aca_tol=tol, eta_H=2.0, leaf=20, time_block=S, factor_dtype=dtype)
+    kw = dict(compress=1, aca_tol=tol, eta_H=2.0, leaf=20, time_block=S, factor_dtype=dtype, n_variants=nv)
     op0, op1 = _op(faults, **kw), _op(faults, aca_partial=1, **kw)
     geo = geometry.discretize(faults)
     dt = geometry.time_step(geo, SI.CS)
+    wide = dtype in ("f64", "f32")
     exact = 1e-12 if dtype == "f64" else 1e-6
+    # 16-bit lags (three roundings of 2^-9 / 2^-12); lags below S, and for ensembles
+    # below 16, stay in FP32
+    rel16 = {"bf16": 2.0 ** -9, "f16": 2.0 ** -12}.get(dtype, 0.0) * 3
+    fp32_below = 16 if nv > 1 else S
     behind = changed = same = 0
     for (a, b), (t0, t1) in op1.windows().items():
         blks = op1.blocks(a, b)
@@ -224,17 +231,22 @@ def test_partial_aca_behind_the_fronts(dtype, S):
             K = I.pair_kernel(geo, a, b, T, dt, SI.CS)
             R0 = op0.lag_matrix(a, b, T, 100, 100)
             R1 = op1.lag_matrix(a, b, T, 100, 100)
+            rnd = exact if (wide or T < fp32_below) else rel16 + 2e-6
             for (r0, r1, s0, s1, adm), f in zip(blks, first):
                 sl = np.s_[r0:r1, s0:s1]
+                nrm = np.linalg.norm(K[sl])
                 if not adm or T <= f - 2:
-                    assert np.array_equal(R1[sl], R0[sl]), (a, b, T, r0, s0)
+                    if wide:
+                        assert np.array_equal(R1[sl], R0[sl]), (a, b, T, r0, s0)
+                    else:
+                        assert np.linalg.norm(R1[sl] - K[sl]) <= (2 * tol + rnd) * nrm, (a, b, T, r0, s0)
                     same += 1
                 elif T >= f + 1:
-                    nrm = np.linalg.norm(K[sl])
-                    assert np.linalg.norm(R1[sl] - K[sl]) <= (2 * tol + exact) * nrm, (a, b, T, r0, s0)
+                    assert np.linalg.norm(R1[sl] - K[sl]) <= (2 * tol + rnd) * nrm, (a, b, T, r0, s0)
                     behind += 1
                     changed += not np.array_equal(R1[sl], R0[sl])
-        assert np.array_equal(op1.lag_matrix(a, b, -1, 100, 100), op0.lag_matrix(a, b, -1, 100, 100))
+        if wide:
+            assert np.array_equal(op1.lag_matrix(a, b, -1, 100, 100), op0.lag_matrix(a, b, -1, 100, 100))
     assert behind > 200 and same > 200
     assert changed > behind // 2
     assert op1.info["stored_entries"] < 1.01 * op0.info["stored_entries"]
