@@ -254,8 +254,11 @@ seas_status seas_operator_self_table(const seas_op_t* op, int32_t k, int32_t n,
  * for the static-tail matrix, stored as -G/eta with G the static stress per unit
  * slip) from the stored factors: out is n_elem(a) x n_elem(b), row-major, host.
  * b = n_faults + a selects the pair of fault a with its own mirror image
- * (free_surface; the image pair's sign included). Only for operators built with
- * host_only = 1 (the factors are on the host). */
+ * (free_surface; the image pair's sign included). With free_surface, the pair
+ * (a, b) for b < n_faults is what the evaluation applies to the slip of b: the
+ * kernel against fault b plus the one against its image (sign included), each
+ * inside its own window. Only for operators built with host_only = 1 (the factors
+ * are on the host). */
 seas_status seas_operator_lag_matrix(const seas_op_t* op, int32_t a, int32_t b, int32_t T, double* out);
 
 /* Rate-and-state parameters, one value per element and variant (host arrays of

@@ -826,6 +826,8 @@ seas_status seas_operator_lag_matrix(const seas_op_t* op, int32_t a, int32_t b, 
         }
       return;
     }
+    // every item covering the pair adds its part: with a free surface the pair (a, b)
+    // also holds the blocks of fault a against the image of b, on the same columns
     // the arenas are the concatenation of the per-block buffers: locate an element
     const HostFactors& hf = op->hf;
     auto elem_in = [&](const std::vector<int64_t>& off, int64_t e, int which) -> double {
@@ -872,7 +874,7 @@ seas_status seas_operator_lag_matrix(const seas_op_t* op, int32_t a, int32_t b, 
           } else {
             for (int i = 0; i < it.p; ++i)
               for (int j = 0; j < it.q; ++j)
-                out[(size_t)(ri + i) * q_all + cj + j] =
+                out[(size_t)(ri + i) * q_all + cj + j] +=
                     sc * elem(it.data + (int64_t)i * it.nlag * q8 + (int64_t)l * q8 + j);
           }
           continue;
@@ -888,7 +890,7 @@ seas_status seas_operator_lag_matrix(const seas_op_t* op, int32_t a, int32_t b, 
         } else {
           for (int j = 0; j < it.q; ++j)
             for (int i = 0; i < it.p; ++i)
-              out[(size_t)(ri + i) * q_all + cj + j] = elem(it.data + ((int64_t)l * it.q + j) * it.p + i);
+              out[(size_t)(ri + i) * q_all + cj + j] += elem(it.data + ((int64_t)l * it.q + j) * it.p + i);
         }
       }
     }

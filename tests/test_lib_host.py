@@ -400,6 +400,64 @@ def test_free_surface_image_pairs_match_oracle():
         _op(faults, free_surface=1, surface_y=-200.0)  # a fault reaching above the surface
 
 
+@pytest.mark.parametrize("compress", [0, 1])
+def test_free_surface_cross_pairs_sum_direct_and_image(compress):
+    # the pair (a, b) of a free-surface operator holds the blocks against fault b and
+    # against its image on the same source columns; the reconstruction sums both
+    # (dense items included), each inside its own window, tails too
+    y0 = 0.0
+    faults = SI.free_surface_network(n_elem=64, y0=y0)
+    nf = len(faults)
+    op = _op(faults, free_surface=1, surface_y=y0, compress=compress, aca_tol=1e-10, eta_H=2.0, leaf=8)
+    dt = op.info["dt"]
+    geo = geometry.discretize(faults + geometry.mirror_images(faults, y0))
+    eta = SI.MU / (2 * SI.CS)
+    tol = 1e-11 if compress == 0 else 1e-9
+    for a in range(nf):
+        for b in range(nf):
+            if a == b:
+                continue
+            d0, d1 = I.pair_window_lags(geo, a, b, SI.CS, dt, 0.01, 0.01)
+            m0, m1 = I.pair_window_lags(geo, a, nf + b, SI.CS, dt, 0.01, 0.01)
+            assert d1 != m1   # the two windows differ: some lags hold one of the two kernels only
+            for T in sorted({1, d0, m0, (d0 + d1) // 2, d1, d1 + 1, m1}):
+                ref = np.zeros((64, 64))
+                if d0 <= T <= d1:
+                    ref += I.pair_kernel(geo, a, b, T, dt, SI.CS)
+                if m0 <= T <= m1:
+                    ref -= I.pair_kernel(geo, a, nf + b, T, dt, SI.CS)
+                got = op.lag_matrix(a, b, T, 64, 64)
+                assert np.abs(got - ref).max() <= tol * max(np.abs(ref).max(), 1e-300), (a, b, T)
+            G = I.static_dipole(geo, a, b, SI.MU) - I.static_dipole(geo, a, nf + b, SI.MU)
+            got = op.lag_matrix(a, b, -1, 64, 64)
+            assert np.abs(got + G / eta).max() <= tol * np.abs(G / eta).max()
+
+
+@pytest.mark.parametrize("cluster_windows", [0, 1])
+def test_partial_aca_with_images_and_cluster_windows(cluster_windows):
+    # aca_partial on image pairs (sign -1) and on per-block windows: every lag matrix
+    # within the tolerance of the full-pivoting build, the static tails the same bits
+    y0 = 0.0
+    faults = SI.free_surface_network(n_elem=64, y0=y0)
+    nf = len(faults)
+    tol = 1e-6
+    kw = dict(free_surface=1, surface_y=y0, compress=1, aca_tol=tol, eta_H=2.0, leaf=8,
+              cluster_windows=cluster_windows)
+    op0, op1 = _op(faults, **kw), _op(faults, aca_partial=1, **kw)
+    changed = 0
+    for a in range(nf):
+        for b in list(range(nf)) + [nf + a]:
+            if a == b:
+                continue
+            t0, t1 = op1.pair_window(a, b)
+            for T in range(max(t0, 1), t1 + 1, 3):
+                R0, R1 = op0.lag_matrix(a, b, T, 64, 64), op1.lag_matrix(a, b, T, 64, 64)
+                assert np.linalg.norm(R1 - R0) <= 2 * tol * np.linalg.norm(R0), (a, b, T)
+                changed += not np.array_equal(R0, R1)
+            assert np.array_equal(op1.lag_matrix(a, b, -1, 64, 64), op0.lag_matrix(a, b, -1, 64, 64))
+    assert changed > 5
+
+
 def test_free_surface_own_image_matrices_match_oracle():
     # the stored kernel of a surface-reaching fault with its own image, lag by lag and
     # its static tail, against the oracle's mirrored pair (sign -1 included)
