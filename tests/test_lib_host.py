@@ -475,3 +475,41 @@ def test_free_surface_own_image_matrices_match_oracle():
     tail = op.lag_matrix(0, 1, -1, 24, 24)
     G = -I.static_dipole(geo, 0, 1, SI.MU)
     assert np.allclose(tail, -G / (SI.MU / (2 * SI.CS)), rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("dtype,S,nv,compress,partial", [
+    ("f64", 1, 1, 0, 0), ("f64", 8, 1, 1, 1), ("f32", 32, 1, 0, 0), ("f32", 32, 1, 1, 1), ("f32", 16, 1, 1, 0),
+    ("bf16", 16, 1, 1, 1), ("f16", 16, 1, 0, 0), ("bf16", 1, 16, 1, 0), ("f16", 1, 32, 1, 1)])
+def test_option_matrix_against_oracle_with_images(dtype, S, nv, compress, partial):
+    # storage types, time blocks, ensembles and both ACA forms on a free-surface
+    # network: every pair's lag matrices (direct kernel plus the image's, each inside
+    # its window) against the oracle, to the tolerance plus the storage rounding
+    y0 = 0.0
+    faults = SI.free_surface_network(n_elem=48, y0=y0)
+    nf = len(faults)
+    tol = 1e-7
+    op = _op(faults, factor_dtype=dtype, time_block=S, n_variants=nv, compress=compress, aca_partial=partial,
+             aca_tol=tol, eta_H=2.0, leaf=8, free_surface=1, surface_y=y0)
+    dt = op.info["dt"]
+    geo = geometry.discretize(faults + geometry.mirror_images(faults, y0))
+    rounding = {"f64": 1e-11, "f32": 1e-6}.get(dtype, 1e-6 + 3 * {"bf16": 2.0 ** -9, "f16": 2.0 ** -12}.get(dtype, 0))
+    bound = 2 * tol * compress + rounding
+    checked = 0
+    for a in range(nf):
+        for b in range(nf):
+            if a == b:
+                continue
+            wins = [(b, 1.0) + I.pair_window_lags(geo, a, b, SI.CS, dt, 0.01, 0.01),
+                    (nf + b, -1.0) + I.pair_window_lags(geo, a, nf + b, SI.CS, dt, 0.01, 0.01)]
+            hi = max(w[3] for w in wins)
+            for T in sorted({S - 1, S, S + 1, 2 * S, hi - 1, hi} | set(range(1, hi + 1, max(1, hi // 12)))):
+                if T < 1 or T > hi:
+                    continue
+                ref = np.zeros((48, 48))
+                for (bb, sg, t0, t1) in wins:
+                    if t0 <= T <= t1:
+                        ref += sg * I.pair_kernel(geo, a, bb, T, dt, SI.CS)
+                got = op.lag_matrix(a, b, T, 48, 48)
+                assert np.linalg.norm(got - ref) <= bound * np.linalg.norm(ref), (a, b, T)
+                checked += 1
+    assert checked >= 30
