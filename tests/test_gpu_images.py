@@ -4,7 +4,8 @@ Two faults below the line y = 0: a vertical one reaching it (its own image acts
 on it from lag 0, through the lag-0 coupling) and a buried dipping one. Against
 the FP64 oracle with the same images: the prescribed-history stress (FP64, the
 uncompressed and the ACA operator, time blocks 1 and 8; FP32 factors on the
-time-blocked segment kernel; cluster-level windows) and a SEAS trajectory. The
+time-blocked segment kernel, also with partial ACA; BF16 / FP16 factors on the
+16-bit segment kernel; cluster-level windows) and a SEAS trajectory. The
 surface also changes the answer (the images are not negligible).
 
 beta = 0.45: with beta = 1/2 the receiver next to the surface sits exactly
@@ -68,6 +69,13 @@ CASES = [
     ("f32_seg_S16", 1e-5, dict(factor_dtype="f32", aca_tol=1e-10, time_block=16)),
     ("f32_seg_S32", 1e-5, dict(factor_dtype="f32", aca_tol=1e-10, time_block=32)),
     ("f64_cluster", 3e-10, dict(factor_dtype="f64", aca_tol=1e-13, time_block=8, cluster_windows=1, leaf=8)),
+    # 16-bit factors: three roundings of 2^-9 (BF16) or 2^-12 (FP16) per lag matrix,
+    # with room for the cancellation of the sums
+    # (leaf 8: admissible blocks, whose far lags the 16-bit segment kernel applies;
+    # with one leaf per fault every block is near-field and stays in FP32)
+    ("bf16_seg_S16", 1e-2, dict(factor_dtype="bf16", aca_tol=1e-10, time_block=16, leaf=8)),
+    ("f16_seg_S16", 1.5e-3, dict(factor_dtype="f16", aca_tol=1e-10, time_block=16, leaf=8)),
+    ("f32_seg_S32_partial_aca", 1e-5, dict(factor_dtype="f32", aca_tol=1e-10, time_block=32, leaf=8, aca_partial=1)),
 ]
 
 
@@ -76,8 +84,11 @@ def test_prescribed_with_free_surface(name, tol, kw):
     p = SI.default_params(free_surface=1, surface_y=0.0, beta=0.45, **kw)
     V = SI.prescribed_slip_rate(FAULTS, 120, 4)
     f, op = _prescribed(p, V)
-    if name.startswith("f32_seg"):
+    if "_seg_" in name:
         assert op.info["n_segments"] > 0 and op.info["time_block"] == kw["time_block"]
+    if kw.get("aca_partial"):
+        full = P.Operator(FAULTS, dict(p, aca_partial=0, host_only=1))
+        assert op.info["stored_entries"] != full.info["stored_entries"]
     ref = OS.prescribed(OS.Problem(FAULTS, p), V)
     e = rel_err(f, ref)
     print(f"[gpu] free surface {name}: {e:.2e}", flush=True)
