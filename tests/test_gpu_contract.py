@@ -93,8 +93,10 @@ def test_newton_failure_holds_last_good_step(S):
 
 def test_failed_variant_is_held_and_the_others_step_on():
     nv = 16
-    p = SI.default_params(factor_dtype="bf16", aca_tol=1e-6, time_block=1, n_variants=nv)
+    # leaf 8: admissible blocks, so the 16-bit segment kernel runs beside the FP32 list
+    p = SI.default_params(factor_dtype="bf16", aca_tol=1e-6, time_block=1, n_variants=nv, leaf=8)
     op = P.Operator(FAULTS, p)
+    assert op.info["far_entries"] > op.info["far_entries_f32"]
     N = op.N
     s = _stream()
     fric, ini = _setup()

@@ -48,7 +48,7 @@ def _faults():
 CASES = [
     ("f32", 16, dict(factor_dtype="f32", aca_tol=1e-8, time_block=16)),
     ("f32_S32", 32, dict(factor_dtype="f32", aca_tol=1e-8, time_block=32)),
-    ("f16", 16, dict(factor_dtype="f16", aca_tol=1e-8, time_block=16)),
+    ("f16", 16, dict(factor_dtype="f16", aca_tol=1e-8, time_block=16, leaf=10)),  # both 16-bit and FP32 far lists
     ("f64", 16, dict(factor_dtype="f64", aca_tol=1e-12, time_block=16)),
 ]
 
@@ -63,6 +63,7 @@ def test_lookahead_is_bitwise_neutral(name, S, kw):
     assert inf["far_entries"] - inf["far_entries_first"] > 0
     if name == "f16":
         assert inf["far_entries_f32"] > 0 and inf["far_entries_first_f32"] > 0
+        assert inf["far_entries"] > inf["far_entries_f32"]
     fric = SI.rate_state_fields(faults)
     ini = SI.near_nucleation_state(faults, fric, seed=4, V_init=1e-6, bump_amp=0.1)
     s = _stream()

@@ -122,6 +122,11 @@ def test_ragged_network_16bit_with_prior_history(dtype):
 E2 = SI.two_fault_prescribed_faults(n_elem=64, dx=200.0)
 
 
+def _n16(op):
+    """Far entries stored in 16 bits (the rest are FP32: near-field blocks and early lags)."""
+    return op.info["far_entries"] - op.info["far_entries_f32"]
+
+
 def _ensemble_V(nv, steps, seed0=0):
     return np.stack([SI.prescribed_slip_rate(E2, steps, seed0 + v) for v in range(nv)], axis=1)
 
@@ -130,8 +135,10 @@ def _ensemble_V(nv, steps, seed0=0):
 def test_ensemble_prescribed_matches_oracle_per_variant(dtype, nv):
     steps = 160
     V = _ensemble_V(nv, steps)
-    p = SI.default_params(factor_dtype=dtype, aca_tol=1e-6, time_block=1, n_variants=nv)
+    # leaf 8: admissible blocks, whose lags >= 16 the 16-bit segment kernel applies
+    p = SI.default_params(factor_dtype=dtype, aca_tol=1e-6, time_block=1, n_variants=nv, leaf=8)
     f, op = gpu_prescribed(E2, p, V)
+    assert _n16(op) > 0
     worst = 0.0
     for v in range(0, nv, max(1, nv // 8)):
         ref = oracle_prescribed(("e2", v), E2, SI.default_params(compress=0), V[:, v, :])
@@ -148,8 +155,9 @@ def test_ensemble_variants_do_not_mix(dtype):
     column of a product is formed on its own, with its own history scale)."""
     nv, steps = 16, 96
     V = _ensemble_V(nv, steps)
-    p = SI.default_params(factor_dtype=dtype, aca_tol=1e-6, time_block=1, n_variants=nv)
-    f, _ = gpu_prescribed(E2, p, V)
+    p = SI.default_params(factor_dtype=dtype, aca_tol=1e-6, time_block=1, n_variants=nv, leaf=8)
+    f, op = gpu_prescribed(E2, p, V)
+    assert _n16(op) > 0
     perm = np.random.default_rng(5).permutation(nv)
     fp, _ = gpu_prescribed(E2, p, V[:, perm, :])
     assert np.array_equal(fp, f[:, perm, :])
@@ -170,8 +178,9 @@ def test_fp16_ensemble_variant_beside_a_rupture():
     loud = quiet.copy()
     loud[:, 1:, :] = np.stack([SI.prescribed_slip_rate(E2, steps, 50 + v, lo_exp=-1, hi_exp=1)
                                for v in range(nv - 1)], axis=1)
-    p = SI.default_params(factor_dtype="f16", aca_tol=1e-6, time_block=1, n_variants=nv)
-    fq, _ = gpu_prescribed(E2, p, quiet)
+    p = SI.default_params(factor_dtype="f16", aca_tol=1e-6, time_block=1, n_variants=nv, leaf=8)
+    fq, op = gpu_prescribed(E2, p, quiet)
+    assert _n16(op) > 0
     fl, _ = gpu_prescribed(E2, p, loud)
     assert np.array_equal(fl[:, 0, :], fq[:, 0, :])
     ref = oracle_prescribed(("e2q", 0), E2, SI.default_params(compress=0), quiet[:, 0, :])
@@ -199,8 +208,9 @@ def test_ensemble_seas_matches_oracle_per_variant(dtype):
         inis.append(SI.near_nucleation_state(faults, fr, seed=0, V_init=1e-6, bump_amp=0.1))
     cat = lambda key, src: np.concatenate([d[key] for d in src])
     fric = {k: cat(k, frs) for k in ("a", "b", "Dc", "sigma_n", "V0", "f0")}
-    p = SI.default_params(factor_dtype=dtype, aca_tol=1e-6, time_block=1, n_variants=nv, compress=0)
+    p = SI.default_params(factor_dtype=dtype, aca_tol=1e-6, time_block=1, n_variants=nv, compress=0, leaf=8)
     op = P.Operator(faults, p)
+    assert _n16(op) > 0
     s = _stream()
     st = P.State(op, fric, cat("V", inis), cat("theta", inis), cat("tau0", inis), cat("tau0_rate", inis), stream=s)
     print(f"[gpu] ensemble seas {dtype} nv={nv} N={N} steps={steps}", flush=True)

@@ -54,7 +54,10 @@ FAULTS = SI.two_fault_prescribed_faults(n_elem=24, dx=50.0)
 
 @pytest.mark.parametrize("dtype", ["bf16", "f16"])
 def test_reset_slot_evolves_like_a_fresh_state(dtype):
-    op = P.Operator(FAULTS, SI.default_params(factor_dtype=dtype, aca_tol=1e-6, time_block=1, n_variants=16))
+    # leaf 8: admissible blocks, so the 16-bit segment kernel (per-variant history
+    # scales) runs beside the FP32 list
+    op = P.Operator(FAULTS, SI.default_params(factor_dtype=dtype, aca_tol=1e-6, time_block=1, n_variants=16, leaf=8))
+    assert op.info["far_entries"] > op.info["far_entries_f32"]
     s = _stream()
     req = _window(FAULTS, 7)
     quiet = _window(FAULTS, 0, quiet=True)
@@ -79,8 +82,9 @@ def test_reset_slot_evolves_like_a_fresh_state(dtype):
 
 def test_server_results_alone_and_in_the_mix():
     geo = [FAULTS, SI.two_fault_prescribed_faults(n_elem=32, dx=50.0)]
-    ops = [P.Operator(g, SI.default_params(factor_dtype="bf16", aca_tol=1e-6, time_block=1, n_variants=16))
+    ops = [P.Operator(g, SI.default_params(factor_dtype="bf16", aca_tol=1e-6, time_block=1, n_variants=16, leaf=8))
            for g in geo]
+    assert all(o.info["far_entries"] > o.info["far_entries_f32"] for o in ops)
     idle = [_window(g, 0, quiet=True) for g in geo]
     rng = np.random.default_rng(11)
     reqs = []
