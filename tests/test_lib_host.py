@@ -513,3 +513,38 @@ def test_option_matrix_against_oracle_with_images(dtype, S, nv, compress, partia
                 assert np.linalg.norm(got - ref) <= bound * np.linalg.norm(ref), (a, b, T)
                 checked += 1
     assert checked >= 30
+
+
+@pytest.mark.parametrize("S,dtype", [(1, "f64"), (8, "f64"), (32, "f32")])
+def test_entry_counts_of_an_uncompressed_operator(S, dtype):
+    # the counts behind the bench's algorithmic bytes, tallied from the oracle: with
+    # compress = 0 every block-lag holding a nonzero kernel entry stores p q values,
+    # every block one static tail of p q; far entries are the lags >= S (at S = 1
+    # every stored entry, tails included), block-start entries the lags S..2S-1
+    faults = SI.five_fault_network(seed=2, n_elem=40)
+    geo = geometry.discretize(faults)
+    op = _op(faults, compress=0, eta_H=2.0, leaf=10, time_block=S, factor_dtype=dtype)
+    info = op.info
+    dt = info["dt"]
+    parts = HP.partition(geo, 2.0, 10)
+    stored = far = first = dense = 0
+    nf = len(faults)
+    for a in range(nf):
+        for b in range(nf):
+            if a == b:
+                continue
+            t0, t1 = I.pair_window_lags(geo, a, b, SI.CS, dt, 0.01, 0.01)
+            dense += (t1 - t0 + 1) * 40 * 40
+            for T in range(max(t0, 1), t1 + 1):
+                K = I.pair_kernel(geo, a, b, T, dt, SI.CS)
+                for (r0, r1, s0, s1, _) in parts[(a, b)]:
+                    if np.any(K[r0:r1, s0:s1] != 0):
+                        n = (r1 - r0) * (s1 - s0)
+                        stored += n
+                        far += n if (S == 1 or T >= S) else 0
+                        first += n if (S > 1 and S <= T < 2 * S) else 0
+            tails = sum((r1 - r0) * (s1 - s0) for (r0, r1, s0, s1, _) in parts[(a, b)])
+            stored += tails
+            far += tails if S == 1 else 0
+    assert (info["stored_entries"], info["far_entries"], info["far_entries_first"], info["dense_entries"]) == \
+        (stored, far, first, dense)
