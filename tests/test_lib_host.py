@@ -515,19 +515,22 @@ def test_option_matrix_against_oracle_with_images(dtype, S, nv, compress, partia
     assert checked >= 30
 
 
-@pytest.mark.parametrize("S,dtype", [(1, "f64"), (8, "f64"), (32, "f32")])
-def test_entry_counts_of_an_uncompressed_operator(S, dtype):
+@pytest.mark.parametrize("S,dtype,nv", [(1, "f64", 1), (8, "f64", 1), (32, "f32", 1), (16, "bf16", 1), (1, "f16", 16)])
+def test_entry_counts_of_an_uncompressed_operator(S, dtype, nv):
     # the counts behind the bench's algorithmic bytes, tallied from the oracle: with
     # compress = 0 every block-lag holding a nonzero kernel entry stores p q values,
     # every block one static tail of p q; far entries are the lags >= S (at S = 1
-    # every stored entry, tails included), block-start entries the lags S..2S-1
+    # every stored entry, tails included), block-start entries the lags S..2S-1.
+    # FP32 part of 16-bit builds: one variant, the far lags of near-field blocks;
+    # ensembles, near-field blocks, lags below 16 and the tails
     faults = SI.five_fault_network(seed=2, n_elem=40)
     geo = geometry.discretize(faults)
-    op = _op(faults, compress=0, eta_H=2.0, leaf=10, time_block=S, factor_dtype=dtype)
+    op = _op(faults, compress=0, eta_H=2.0, leaf=10, time_block=S, factor_dtype=dtype, n_variants=nv)
     info = op.info
     dt = info["dt"]
     parts = HP.partition(geo, 2.0, 10)
-    stored = far = first = dense = 0
+    stored = far = first = dense = f32 = 0
+    x16 = dtype in ("bf16", "f16")
     nf = len(faults)
     for a in range(nf):
         for b in range(nf):
@@ -537,14 +540,22 @@ def test_entry_counts_of_an_uncompressed_operator(S, dtype):
             dense += (t1 - t0 + 1) * 40 * 40
             for T in range(max(t0, 1), t1 + 1):
                 K = I.pair_kernel(geo, a, b, T, dt, SI.CS)
-                for (r0, r1, s0, s1, _) in parts[(a, b)]:
+                for (r0, r1, s0, s1, adm) in parts[(a, b)]:
                     if np.any(K[r0:r1, s0:s1] != 0):
                         n = (r1 - r0) * (s1 - s0)
                         stored += n
                         far += n if (S == 1 or T >= S) else 0
                         first += n if (S > 1 and S <= T < 2 * S) else 0
+                        if x16 and nv == 1 and T >= S and not adm:
+                            f32 += n
+                        if x16 and nv > 1 and (not adm or T < 16):
+                            f32 += n
             tails = sum((r1 - r0) * (s1 - s0) for (r0, r1, s0, s1, _) in parts[(a, b)])
             stored += tails
             far += tails if S == 1 else 0
+            f32 += tails if (x16 and nv > 1) else 0
     assert (info["stored_entries"], info["far_entries"], info["far_entries_first"], info["dense_entries"]) == \
         (stored, far, first, dense)
+    if x16:
+        assert 0 < info["far_entries_f32"] < info["far_entries"]
+        assert info["far_entries_f32"] == f32
