@@ -559,3 +559,41 @@ def test_entry_counts_of_an_uncompressed_operator(S, dtype, nv):
     if x16:
         assert 0 < info["far_entries_f32"] < info["far_entries"]
         assert info["far_entries_f32"] == f32
+
+
+@pytest.mark.parametrize("eta_w,q_w,mode_cap", [(2.5, 5, 0), (1.0, 0, 20), (1.5, 40, 64)])
+def test_self_window_options_match_oracle(eta_w, q_w, mode_cap):
+    # the self windows W_n under other window factors, modulation integers and mode
+    # caps: the library's tables against the oracle's, and the entry count they add up to
+    faults = SI.two_fault_prescribed_faults(n_elem=96, dx=100.0)
+    op = _op(faults, eta_w=eta_w, q_w=q_w, mode_cap=mode_cap)
+    dt = op.info["dt"]
+    total = 0
+    for k, f in enumerate(faults):
+        st = S.SelfTerm(f["n_elem"], f["length"], SI.MU, SI.CS, dt, eta_w=eta_w, q_w=q_w, mode_cap=mode_cap)
+        nm = len(st.W)
+        assert nm == (f["n_elem"] if mode_cap == 0 else min(mode_cap, f["n_elem"]))
+        total += int(np.sum(st.W + 1))
+        for n in sorted({1, 2, nm // 2, nm}):
+            lt, ot = op.self_table(k, n), st.table(n - 1)
+            assert len(lt) == len(ot) == st.W[n - 1] + 1
+            assert np.abs(lt - ot).max() <= 1e-12 * np.abs(ot).max()
+        if nm < f["n_elem"]:
+            with pytest.raises(P.SeasError):
+                op.self_table(k, nm + 1)
+    assert op.info["self_entries"] == total
+
+
+def test_build_is_independent_of_the_thread_count():
+    # blocks are built in parallel and merged in a fixed order: one thread and eight
+    # give the same operator bit for bit
+    faults = SI.five_fault_network(seed=5, n_elem=60)
+    kw = dict(compress=1, aca_tol=1e-6, eta_H=2.0, leaf=10, time_block=32, factor_dtype="f32")
+    ops = [_op(faults, n_threads=t, **kw) for t in (1, 8)]
+    i0, i1 = ({k: v for k, v in o.info.items() if k != "build_seconds"} for o in ops)
+    assert i0 == i1
+    for (a, b), (t0, t1) in ops[0].windows().items():
+        for T in sorted({max(t0, 1), 31, 32, 64, (t0 + t1) // 2, t1, -1}):
+            if T != -1 and not (max(t0, 1) <= T <= t1):
+                continue
+            assert np.array_equal(ops[0].lag_matrix(a, b, T, 60, 60), ops[1].lag_matrix(a, b, T, 60, 60)), (a, b, T)
