@@ -65,7 +65,7 @@ def _prescribed(p, V):
 
 CASES = [
     ("f64_dense_S1", 3e-10, dict(factor_dtype="f64", compress=0, time_block=1)),
-    ("f64_aca_S8", 3e-10, dict(factor_dtype="f64", aca_tol=1e-13, time_block=8)),
+    ("f64_aca_S8", 3e-10, dict(factor_dtype="f64", aca_tol=1e-13, time_block=8, leaf=8)),  # blocks compressed
     ("f32_seg_S16", 1e-5, dict(factor_dtype="f32", aca_tol=1e-10, time_block=16)),
     ("f32_seg_S32", 1e-5, dict(factor_dtype="f32", aca_tol=1e-10, time_block=32)),
     ("f64_cluster", 3e-10, dict(factor_dtype="f64", aca_tol=1e-13, time_block=8, cluster_windows=1, leaf=8)),
@@ -86,6 +86,9 @@ def test_prescribed_with_free_surface(name, tol, kw):
     f, op = _prescribed(p, V)
     if "_seg_" in name:
         assert op.info["n_segments"] > 0 and op.info["time_block"] == kw["time_block"]
+    if name == "f64_aca_S8":
+        dense = P.Operator(FAULTS, dict(p, compress=0, host_only=1))
+        assert op.info["stored_entries"] < dense.info["stored_entries"]
     if kw.get("aca_partial"):
         full = P.Operator(FAULTS, dict(p, aca_partial=0, host_only=1))
         assert op.info["stored_entries"] != full.info["stored_entries"]
