@@ -597,3 +597,48 @@ def test_build_is_independent_of_the_thread_count():
             if T != -1 and not (max(t0, 1) <= T <= t1):
                 continue
             assert np.array_equal(ops[0].lag_matrix(a, b, T, 60, 60), ops[1].lag_matrix(a, b, T, 60, 60)), (a, b, T)
+
+
+def test_cluster_windows_on_image_pairs_match_oracle():
+    # per-block upper lags of the pairs with mirror images (free surface), and the pair
+    # (a, b) as the evaluation applies it: the direct and the image kernel, each entry
+    # cut at its own block's upper lag. Receivers of a surface-reaching fault sit at
+    # (m + 1/2) dx from the element edges of its own image, the fronts at beta T dx:
+    # beta = 0.4373 keeps every lag off them (beta = 1/2 or 0.45 = 9/20 puts whole
+    # lags on a front, where the square root of the primitive magnifies rounding and
+    # library and oracle differ by ~1e-8)
+    y0 = 0.0
+    faults = SI.free_surface_network(n_elem=40, y0=y0)
+    nf = len(faults)
+    op = _op(faults, compress=0, eta_H=1.5, leaf=6, free_surface=1, surface_y=y0, cluster_windows=1, beta=0.4373)
+    geo = geometry.discretize(faults + geometry.mirror_images(faults, y0))
+    dt = op.info["dt"]
+    blocks = HP.partition(geo, 1.5, 6)
+    shortened = checked = 0
+    for a in range(nf):
+        cut = {}
+        for bb in [c for c in range(nf) if c != a] + [nf + c for c in range(nf)]:
+            t0, t1 = op.pair_window(a, bb)
+            te_all = op.block_windows(a, bb)
+            Te = np.full((40, 40), -1)
+            for blk, te in zip(blocks[(a, bb)], te_all):
+                assert te == min(t1, I.block_window_end(geo, a, bb, blk, SI.CS, dt, 0.01)), (a, bb, blk)
+                shortened += te < t1
+                Te[blk[0]:blk[1], blk[2]:blk[3]] = te
+            cut[bb] = (t0, Te)
+
+        def kernel(bb, T, sg):
+            t0, Te = cut[bb]
+            return sg * np.where(T <= Te, I.pair_kernel(geo, a, bb, T, dt, SI.CS), 0.0) if T >= t0 else 0.0
+
+        for b in list(range(nf)) + [nf + a]:
+            if b == a:
+                continue
+            terms = [(nf + a, -1.0)] if b == nf + a else [(b, 1.0), (nf + b, -1.0)]
+            hi = max(cut[bb][1].max() for bb, _ in terms)
+            for T in range(1, hi + 1, 3):
+                K = sum(kernel(bb, T, sg) for bb, sg in terms) + np.zeros((40, 40))
+                R = op.lag_matrix(a, b, T, 40, 40)
+                assert np.linalg.norm(R - K) <= 1e-11 * max(np.linalg.norm(K), 1e-300), (a, b, T)
+                checked += 1
+    assert shortened > 0 and checked > 50
