@@ -332,17 +332,22 @@ def test_host_only_operator_refuses_evaluation():
 
 
 @pytest.mark.slow
-def test_wide_cluster_is_split_into_column_slices():
+@pytest.mark.parametrize("dtype,S,partial", [("f64", 16, 0), ("f32", 32, 0), ("f32", 32, 1)])
+def test_wide_cluster_is_split_into_column_slices(dtype, S, partial):
     # two parallel 400-element faults whose root clusters are admissible: with
     # S = 16 the 400-wide source cluster exceeds the kernel's history buffer and is
-    # packed as column slices, each compressed on its own
+    # packed as column slices, each compressed on its own (with aca_partial, each
+    # slice from the first lag behind both fronts of its own columns)
     faults = [SI.fault(0, 0, 0, 400.0, 400), SI.fault(0, 100.0, 0, 400.0, 400)]
-    op = _op(faults, compress=1, aca_tol=1e-6, eta_H=0.2, leaf=50, time_block=16)
+    kw = dict(compress=1, aca_tol=1e-6, eta_H=0.2, leaf=50, time_block=S, factor_dtype=dtype)
+    op = _op(faults, aca_partial=partial, **kw)
     assert op.blocks(0, 1) == [(0, 400, 0, 400, True)]
+    if partial:
+        assert op.info["stored_entries"] != _op(faults, **kw).info["stored_entries"]
     geo = geometry.discretize(faults)
     dt = geometry.time_step(geo, SI.CS)
     t0, t1 = op.windows()[(0, 1)]
-    for T in (t0 + 5, t0 + 40, (t0 + t1) // 2):
+    for T in (t0 + 5, t0 + 40, (t0 + t1) // 2, t1 - 30, t1 - 8, t1):
         K = I.pair_kernel(geo, 0, 1, T, dt, SI.CS)
         R = op.lag_matrix(0, 1, T, 400, 400)
         assert np.linalg.norm(K) > 0
