@@ -647,3 +647,24 @@ def test_cluster_windows_on_image_pairs_match_oracle():
                 assert np.linalg.norm(R - K) <= 1e-11 * max(np.linalg.norm(K), 1e-300), (a, b, T)
                 checked += 1
     assert shortened > 0 and checked > 50
+
+
+@pytest.mark.parametrize("kw", [dict(factor_dtype="f64"), dict(factor_dtype="f32", time_block=32, aca_partial=1),
+                                dict(factor_dtype="bf16", time_block=16, leaf=8),
+                                dict(factor_dtype="f16", n_variants=16, leaf=8),
+                                dict(factor_dtype="f64", cluster_windows=1, leaf=8)])
+def test_dropping_the_static_tail_changes_nothing_else(kw):
+    # int_tail = 0 removes the static-tail matrices and nothing else: every lag matrix
+    # (direct and image pairs) is the same bits as with the tail, the tails are zero
+    y0 = 0.0
+    faults = SI.free_surface_network(n_elem=40, y0=y0)
+    base = dict(free_surface=1, surface_y=y0, beta=0.4373, aca_tol=1e-8, **kw)
+    with_tail, without = _op(faults, int_tail=1, **base), _op(faults, int_tail=0, **base)
+    for a in range(2):
+        for b in (1 - a, 2 + a):
+            t0, t1 = with_tail.pair_window(a, b)
+            for T in range(max(t0, 1), t1 + 1, 7):
+                assert np.array_equal(with_tail.lag_matrix(a, b, T, 40, 40), without.lag_matrix(a, b, T, 40, 40))
+            assert not without.lag_matrix(a, b, -1, 40, 40).any()
+            assert with_tail.lag_matrix(a, b, -1, 40, 40).any()
+    assert without.info["stored_entries"] < with_tail.info["stored_entries"]
